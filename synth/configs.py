@@ -1,0 +1,152 @@
+"""The five synthetic workloads and their reduced-size variants.
+
+Each configuration is a plain dict that both the HIP path and the CPU oracle read:
+
+  N, precision ("f64" | "f32"), potential (dict, or a list of dicts when batched),
+  model_sizes (batched only), layout (see ``synth.targets``), prior (dict),
+  dt, eps, mu, tau, steps, seeds.
+
+``make_inputs(cfg)`` draws the initial particle model and the noisy target and
+returns a dict of float64 numpy arrays: ics [6, N], w [N], Y [J], sigma [J].
+Weights start at 1/N (per model when batched), as in paper section 2.1.
+"""
+import numpy as np
+
+from . import galaxy, targets
+from .galaxy import seed_for
+
+DEG = np.pi / 180.0
+
+
+def _log_edges(lo, hi, n):
+    return np.geomspace(lo, hi, n + 1)
+
+
+def layout_cfg1():
+    """30 log shells in r over [0.05, 20] (mass) + 20 log annuli in R over [0.1, 10]
+    (second LOS moment); line of sight along z."""
+    return {"incl": 0.0, "binnings": [
+        {"kind": "shell", "edges": _log_edges(0.05, 20.0, 30), "moments": (0,)},
+        {"kind": "annulus", "edges": _log_edges(0.1, 10.0, 20), "moments": (2,)},
+    ]}
+
+
+def layout_cfg2():
+    """64x64 sky pixels over [-5,5]^2 (mass) + 20x20 kinematic bins over [-2,2]^2
+    (first and second LOS moments), inclination 60 degrees."""
+    return {"incl": 60.0 * DEG, "binnings": [
+        {"kind": "grid", "nx": 64, "ny": 64, "x0": -5.0, "x1": 5.0, "y0": -5.0, "y1": 5.0,
+         "moments": (0,)},
+        {"kind": "grid", "nx": 20, "ny": 20, "x0": -2.0, "x1": 2.0, "y0": -2.0, "y1": 2.0,
+         "moments": (1, 2)},
+    ]}
+
+
+def layout_cfg3():
+    lay = layout_cfg2()
+    lay["binnings"].append({"kind": "shell", "edges": _log_edges(0.05, 10.0, 50), "moments": (0,)})
+    return lay
+
+
+LOG_POT = {"kind": "log", "v0": 1.0, "Rc": 0.1, "q": 0.8}
+HERN_POT = {"kind": "hernquist", "G": 1.0, "M": 1.0, "a": 1.0}
+
+
+def cfg1(N=20000, steps=2000):
+    return {"name": "hernquist_fp64_N%d" % N, "index": 1, "N": N, "precision": "f64",
+            "potential": dict(HERN_POT), "layout": layout_cfg1(),
+            "prior": {"kind": "hist", "axes": ("E", "L/Lc"), "shape": (20, 20), "period": 1},
+            "dt": 0.01, "eps": 1e-3, "mu": 1e-2, "tau": 0.5, "steps": steps,
+            "target": {"kind": "hernquist_om", "ra": 1.0, "noise": 0.05}}
+
+
+def cfg2(N=1 << 20, steps=5000, target_n=1 << 23):
+    return {"name": "log_fp32_N%d" % N, "index": 2, "N": N, "precision": "f32",
+            "potential": dict(LOG_POT), "layout": layout_cfg2(),
+            "prior": {"kind": "hist", "axes": ("E", "Lz/Lc"), "shape": (32, 32), "period": 1},
+            "dt": 0.005, "eps": EPS_CFG2, "mu": 5e-3, "tau": 0.5, "steps": steps,
+            "target": {"kind": "log_rotating", "n": target_n, "rot_frac": 0.8, "noise": 0.03}}
+
+
+def cfg3(N=1 << 23, steps=2000, target_n=1 << 23):
+    c = cfg2(N, steps, target_n)
+    c.update({"name": "multipole_fp32_N%d" % N, "index": 3, "layout": layout_cfg3(),
+              "potential": {"kind": "multipole", "G": 1.0, "lmax": 8, "nodes": 200,
+                            "rmin": 1e-3, "rmax": 100.0, "Mtot": LOG_MASS_R10},
+              "eps": EPS_CFG3})
+    return c
+
+
+def cfg4(n_models=64, nmin=100_000, nmax=2_000_000, steps=3000):
+    rng = np.random.default_rng(seed_for(4, 3))
+    sizes = rng.integers(nmin, nmax + 1, n_models)
+    ratio = np.linspace(0.0, 10.0, 8)
+    rs = np.linspace(1.0, 10.0, 8)
+    pots = []
+    for m in range(n_models):
+        pots.append({"kind": "hernquist_nfw", "G": 1.0, "M": 1.0, "a": 1.0,
+                     "Mh": float(ratio[(m // 8) % 8]), "rs": float(rs[m % 8])})
+    return {"name": "batched_hnfw_%dmodels" % n_models, "index": 4, "N": int(sizes.sum()),
+            "model_sizes": sizes.astype(np.int64), "precision": "f32", "potential": pots,
+            "layout": layout_cfg1(),
+            "prior": {"kind": "hist", "axes": ("E", "L/Lc"), "shape": (20, 20), "period": 1},
+            "dt": 0.01, "eps": 1e-3, "mu": 1e-2, "tau": 0.5, "steps": steps,
+            "target": {"kind": "hernquist_om", "ra": 1.0, "noise": 0.05, "seed_cfg": 1}}
+
+
+def cfg5(N=1 << 22, steps=5000, target_n=1 << 23):
+    c = cfg2(N, steps, target_n)
+    c.update({"name": "mlp_prior_fp32_N%d" % N, "index": 5,
+              "prior": {"kind": "mlp", "axes": ("E", "L/Lc", "Lz/L"), "shape": (32, 32, 8),
+                        "period": 100, "hidden": 64, "subset": 1 << 20, "batch": 8192,
+                        "lr": 1e-3, "beta1": 0.9, "beta2": 0.999, "adam_eps": 1e-8,
+                        "fallback": 0.5},
+              "eps": EPS_CFG2})
+    return c
+
+
+# Values fixed once from the initial state so that eps*dt*max_i |G_i(0)| <= 0.1;
+# written by tests/golden/derive_eps.py, which calls only the oracle.
+EPS_CFG2 = 1.8e-6
+EPS_CFG3 = 1.85e-6
+# Mass of the truncated (r <= 10) logarithmic-potential density: the self-consistent
+# form weights its particles by w_i * Mtot (galaxy.log_mass_within_sphere()).
+LOG_MASS_R10 = 9.999142073415042
+
+
+def make_inputs(cfg, dtype=np.float64):
+    """Initial particle model, weights 1/N (per model), noisy target."""
+    idx = cfg["index"]
+    seed = seed_for(idx)
+    pot = cfg["potential"]
+    if "model_sizes" in cfg:
+        parts, ws = [], []
+        for m, (n, p) in enumerate(zip(cfg["model_sizes"], pot)):
+            parts.append(galaxy.hernquist_nfw_ics(int(n), seed + 7 * m, p["G"], p["M"], p["a"],
+                                                  p["Mh"], p["rs"]))
+            ws.append(np.full(int(n), 1.0 / int(n)))
+        ics = np.concatenate(parts, axis=1)
+        w = np.concatenate(ws)
+    elif pot["kind"] == "hernquist":
+        ics = galaxy.hernquist_isotropic_ics(cfg["N"], seed, pot["G"], pot["M"], pot["a"])
+        w = np.full(cfg["N"], 1.0 / cfg["N"])
+    else:
+        lp = LOG_POT
+        ics = galaxy.log_isotropic_ics(cfg["N"], seed, lp["v0"], lp["Rc"], lp["q"])
+        w = np.full(cfg["N"], 1.0 / cfg["N"])
+    Y, sigma = make_target(cfg)
+    return {"ics": ics.astype(dtype), "w": w.astype(dtype), "Y": Y, "sigma": sigma}
+
+
+def make_target(cfg):
+    t = cfg["target"]
+    lay = cfg["layout"]
+    sidx = t.get("seed_cfg", cfg["index"])
+    if t["kind"] == "hernquist_om":
+        Yt, Mb = targets.hernquist_om_target(lay, ra=t["ra"])
+    else:
+        lp = LOG_POT
+        real = galaxy.log_isotropic_ics(t["n"], seed_for(sidx, 5), lp["v0"], lp["Rc"], lp["q"])
+        real = galaxy.make_rotating(real, t["rot_frac"], seed_for(sidx, 6))
+        Yt, Mb = targets.observe_realisation(lay, real, 1.0 / t["n"])
+    return targets.add_noise(lay, Yt, Mb, t["noise"], seed_for(sidx, 1))

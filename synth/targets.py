@@ -1,0 +1,208 @@
+"""Target observables Y_j with errors sigma_j for the synthetic galaxies.
+
+The paper (section 2) fits observables of a target galaxy that come with
+observational errors; the data types are photometry and line-of-sight
+kinematics (section 1).  Here a target is either
+
+* analytic: Hernquist shell masses and projected second LOS moments of an
+  Osipkov-Merritt (r_a = 1) Hernquist model from the spherical Jeans equation, or
+* a realisation: an independent particle model observed on the sky plane
+  (surface density, first and second LOS moments),
+
+and then perturbed once by Gaussian noise of relative size f.
+
+A "layout" is a dict: ``incl`` (radians) and a list ``binnings``; each binning is
+one of ``{"kind": "shell", "edges": ...}``, ``{"kind": "annulus", "edges": ...}`` or
+``{"kind": "grid", "nx", "ny", "x0", "x1", "y0", "y1"}`` and carries ``moments``, a
+tuple drawn from (0, 1, 2): mass, sum of w*v_los, sum of w*v_los^2.  Observable j
+runs over binnings in order, then over the listed moments, then over bins.
+"""
+import numpy as np
+
+from . import galaxy
+
+
+def layout_size(layout):
+    J = 0
+    for b in layout["binnings"]:
+        J += len(b["moments"]) * binning_nbins(b)
+    return J
+
+
+def binning_nbins(b):
+    if b["kind"] in ("shell", "annulus"):
+        return len(b["edges"]) - 1
+    return b["nx"] * b["ny"]
+
+
+def observable_kinds(layout):
+    """Per observable: (moment, binning index, bin index)."""
+    out = []
+    for ib, b in enumerate(layout["binnings"]):
+        nb = binning_nbins(b)
+        for m in b["moments"]:
+            for k in range(nb):
+                out.append((m, ib, k))
+    return out
+
+
+# ------------------------------------------------------------ analytic Hernquist OM
+def hernquist_projected_mass(R, M=1.0, a=1.0):
+    """M_p(R) = M s^2 (X(s) - 1)/(1 - s^2), s = R/a (Hernquist 1990, eq. 37)."""
+    s = np.asarray(R, dtype=float) / a
+    out = np.empty_like(s)
+    lo = s < 1.0
+    hi = s > 1.0
+    X = np.empty_like(s)
+    X[lo] = np.arccosh(1.0 / s[lo]) / np.sqrt(1.0 - s[lo] ** 2)
+    X[hi] = np.arccos(1.0 / s[hi]) / np.sqrt(s[hi] ** 2 - 1.0)
+    one = ~(lo | hi)
+    X[one] = 1.0
+    out[lo | hi] = M * s[lo | hi] ** 2 * (X[lo | hi] - 1.0) / (1.0 - s[lo | hi] ** 2)
+    out[one] = M / 3.0
+    return out
+
+
+def om_rho_sigr2_table(ra, G=1.0, M=1.0, a=1.0):
+    """rho sigma_r^2 of a Hernquist model with Osipkov-Merritt anisotropy
+    beta = r^2/(r^2 + ra^2) from the spherical Jeans equation:
+    rho sigma_r^2 (r) = (1 + r^2/ra^2)^-1 int_r^inf (1 + r'^2/ra^2) rho G M(r')/r'^2 dr'.
+    ra = inf gives the isotropic model.  Returns (ln r grid, rho sigma_r^2)."""
+    lr = np.linspace(np.log(1e-7), np.log(1e7), 56001)
+    r = np.exp(lr)
+    fac = 1.0 + (r / ra) ** 2 if np.isfinite(ra) else np.ones_like(r)
+    integrand = fac * galaxy.hernquist_density(r, M, a) * G * galaxy.hernquist_mass(r, M, a) / r ** 2 * r
+    seg = 0.5 * (integrand[1:] + integrand[:-1]) * np.diff(lr)
+    tail = np.concatenate([np.cumsum(seg[::-1])[::-1], [0.0]])
+    return lr, tail / fac
+
+
+def om_projected_sigma2_sigma(R, ra, G=1.0, M=1.0, a=1.0, nu=6000):
+    """Sigma(R) sigma_p^2(R) = 2 int_R^inf (1 - beta R^2/r^2) rho sigma_r^2 r dr / sqrt(r^2 - R^2),
+    with r = R cosh(u) to remove the end-point singularity."""
+    lr, P = om_rho_sigr2_table(ra, G, M, a)
+    lP = np.log(np.maximum(P, 1e-300))
+    R = np.atleast_1d(np.asarray(R, dtype=float))
+    out = np.empty_like(R)
+    for i, Ri in enumerate(R):
+        umax = np.arccosh(1e7 / Ri)
+        u = np.linspace(0.0, umax, nu)
+        r = Ri * np.cosh(u)
+        beta = r * r / (r * r + ra * ra) if np.isfinite(ra) else np.zeros_like(r)
+        Pr = np.exp(np.interp(np.log(r), lr, lP))
+        f = (1.0 - beta * Ri * Ri / (r * r)) * Pr * Ri * np.cosh(u)
+        out[i] = 2.0 * np.trapezoid(f, u)
+    return out
+
+
+def hernquist_om_annulus_moment2(edges, ra, G=1.0, M=1.0, a=1.0, per_bin=161):
+    """Y2_b = int_{R_b}^{R_b+1} 2 pi R Sigma sigma_p^2 dR (Simpson in ln R)."""
+    out = np.empty(len(edges) - 1)
+    for b in range(len(edges) - 1):
+        lR = np.linspace(np.log(edges[b]), np.log(edges[b + 1]), per_bin)
+        R = np.exp(lR)
+        g = om_projected_sigma2_sigma(R, ra, G, M, a)
+        f = 2 * np.pi * R * R * g
+        h = lR[1] - lR[0]
+        out[b] = h / 3.0 * (f[0] + f[-1] + 4 * f[1:-1:2].sum() + 2 * f[2:-1:2].sum())
+    return out
+
+
+def hernquist_om_target(layout, ra=1.0, G=1.0, M=1.0, a=1.0):
+    """True (noise-free) observables of the OM Hernquist target for a layout made of
+    shells (moment 0) and annuli (moment 0 or 2; the mean LOS velocity is zero)."""
+    Y = []
+    Mb_list = []
+    for b in layout["binnings"]:
+        e = np.asarray(b["edges"], dtype=float)
+        if b["kind"] == "shell":
+            mass = np.diff(galaxy.hernquist_mass(e, M, a))
+            proj = None
+        elif b["kind"] == "annulus":
+            mass = np.diff(hernquist_projected_mass(e, M, a))
+            proj = hernquist_om_annulus_moment2(e, ra, G, M, a)
+        else:
+            raise ValueError("analytic target supports shells and annuli only")
+        for m in b["moments"]:
+            if m == 0:
+                Y.append(mass)
+            elif m == 1:
+                Y.append(np.zeros_like(mass))
+            else:
+                if proj is None:
+                    raise ValueError("second moment needs a projected binning")
+                Y.append(proj)
+            Mb_list.append(mass)
+    return np.concatenate(Y), np.concatenate(Mb_list)
+
+
+# ----------------------------------------------------------------- realisations
+def observe_realisation(layout, ics, mass):
+    """Observe a particle realisation of the target galaxy (equal masses) on the
+    layout's bins.  Returns (Y_true, M_b) where M_b is the binned mass that goes with
+    each observable (used to size kinematic errors)."""
+    x, y, z, vx, vy, vz = ics
+    inc = layout["incl"]
+    X = x
+    Ysky = y * np.cos(inc) - z * np.sin(inc)
+    vlos = vy * np.sin(inc) + vz * np.cos(inc)
+    out, mb = [], []
+    for b in layout["binnings"]:
+        if b["kind"] == "grid":
+            ix = np.floor((X - b["x0"]) / (b["x1"] - b["x0"]) * b["nx"]).astype(np.int64)
+            iy = np.floor((Ysky - b["y0"]) / (b["y1"] - b["y0"]) * b["ny"]).astype(np.int64)
+            ok = (ix >= 0) & (ix < b["nx"]) & (iy >= 0) & (iy < b["ny"])
+            idx = (iy * b["nx"] + ix)[ok]
+            nb = b["nx"] * b["ny"]
+        else:
+            rad = np.sqrt(x * x + y * y + z * z) if b["kind"] == "shell" else np.sqrt(X * X + Ysky * Ysky)
+            e = np.asarray(b["edges"])
+            k = np.searchsorted(e, rad, side="right") - 1
+            ok = (k >= 0) & (k < len(e) - 1)
+            idx = k[ok]
+            nb = len(e) - 1
+        vv = vlos[ok]
+        mass_b = np.bincount(idx, minlength=nb) * mass
+        for m in b["moments"]:
+            w = mass * vv ** m
+            out.append(np.bincount(idx, weights=w, minlength=nb))
+            mb.append(mass_b)
+    return np.concatenate(out), np.concatenate(mb)
+
+
+# ------------------------------------------------------------------------ noise
+def add_noise(layout, Y_true, M_b, f, seed):
+    """One fixed Gaussian noise draw.  Mass-type observables: sigma = f |Y|;
+    first moments: sigma = f sqrt(M_b Y2) (f on the rms LOS velocity);
+    second moments: sigma = 2 f Y2 (f on the dispersion).  Zero errors (empty bins)
+    are raised to the smallest positive error of the same group."""
+    rng = np.random.default_rng(seed)
+    kinds = observable_kinds(layout)
+    moment = np.array([k[0] for k in kinds])
+    sigma = np.empty_like(Y_true)
+    # second moment of each first-moment bin: look it up in the same binning
+    start = 0
+    for b in layout["binnings"]:
+        nb = binning_nbins(b)
+        y2 = None
+        for mi, m in enumerate(b["moments"]):
+            if m == 2:
+                y2 = Y_true[start + mi * nb: start + (mi + 1) * nb]
+        for mi, m in enumerate(b["moments"]):
+            sl = slice(start + mi * nb, start + (mi + 1) * nb)
+            if m == 0:
+                sigma[sl] = f * np.abs(Y_true[sl])
+            elif m == 1:
+                if y2 is None:
+                    raise ValueError("first moment needs the second moment in the same binning")
+                sigma[sl] = f * np.sqrt(np.maximum(M_b[sl] * y2, 0.0))
+            else:
+                sigma[sl] = 2.0 * f * np.abs(Y_true[sl])
+            s = sigma[sl]
+            pos = s[s > 0]
+            floor = pos.min() if pos.size else 1.0
+            sigma[sl] = np.where(s > 0, s, floor)
+        start += len(b["moments"]) * nb
+    g = rng.normal(0.0, 1.0, Y_true.size)
+    del moment
+    return Y_true + sigma * g, sigma

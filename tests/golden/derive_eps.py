@@ -1,0 +1,35 @@
+"""Derive the weight-adaptation rate eps of the log-potential workloads.
+
+Reading of the update law: eps is set once from the initial state so that
+eps * dt * max_i |G_i(0)| = 0.1, where G_i = dF/dw_i with the priors held fixed.
+G_i(0) is read off one oracle step with a negligible rate (w1 = w0 exp(e dt G)).
+Calls only the oracle and the input generators; prints the values recorded in
+synth/configs.py (EPS_CFG2, EPS_CFG3).
+
+    python tests/golden/derive_eps.py
+"""
+import os
+import sys
+
+import numpy as np
+
+sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__)))))
+import oracle  # noqa: E402
+from synth import configs  # noqa: E402
+
+
+def max_abs_G(cfg):
+    inp = configs.make_inputs(cfg)
+    c = dict(cfg, eps=1e-12, update="exp", frozen=True)
+    m = oracle.Model(c, inp["ics"], inp["w"], inp["Y"], inp["sigma"])
+    w0 = m.w.copy()
+    m.run(1)
+    G = np.log(m.w / w0) / (c["eps"] * c["dt"])
+    return float(np.max(np.abs(G)))
+
+
+if __name__ == "__main__":
+    for name, cfg in [("EPS_CFG2", configs.cfg2(N=1 << 20)), ("EPS_CFG3", configs.cfg3(N=1 << 20))]:
+        g = max_abs_G(cfg)
+        eps = 0.1 / (cfg["dt"] * g)
+        print("%s = %.3e   # max|G(0)| = %.4e" % (name, float("%.2e" % eps), g))
