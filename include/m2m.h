@@ -1,0 +1,259 @@
+/*
+ * m2m.h -- C ABI of the MI355X (gfx950) library for the per-timestep loop of the
+ * NMAGIC made-to-measure (M2M) particle method (Morganti & Gerhard,
+ * "NMAGIC made-to-measure particle models of galaxies").
+ *
+ * Problem statement (section 2 of the paper): an N-body system of particles with
+ * weights w_i is evolved in a gravitational potential (fixed and known a priori,
+ * or self-consistently computed from the particles) while the weights are
+ * adapted to maximise the merit function F = -chi^2/2 + mu S (eq. 1), where
+ * chi^2 measures the deviations between target and model observables and
+ * S = -sum_i w_i ln(w_i / what_i) is a pseudo-entropy (eq. 2) that pushes the
+ * weights towards priors what_i.  Priors are flat (what_i = 1/N, section 2.1)
+ * or moving: recomputed from the weight distribution over integrals of motion
+ * (section 2.1).
+ *
+ * One library step n (all on the GPU, no host round trip):
+ *   G_i = -sum_j K_j(z_i) Dt_j/sigma_j - mu (ln(w_i/what_i) + 1)
+ *   w_i <- w_i exp(eps dt G_i)            (or w_i (1 + eps dt G_i), see update)
+ *   z_i <- kick-drift-kick leapfrog over dt
+ *   y_j  = sum_i w_i K_j(z_i)              (observables of the new state)
+ *   ys_j <- ys_j + (dt/tau) (y_j - ys_j)   (temporal smoothing)
+ *   Dt_j = (ys_j - Y_j)/sigma_j,  chi^2 = sum_j Dt_j^2
+ *   moving prior: what_i = mean weight of the particles in i's phase-space cell
+ * The observable kernels K_j are linear in the weights: mass in 3D shells,
+ * projected annuli or sky pixels, and the first/second line-of-sight velocity
+ * moments sum w v_los, sum w v_los^2 in annuli or pixels.
+ *
+ * Conventions for every entry point:
+ *  - Status codes only; nothing throws or aborts across this boundary.  After an
+ *    error the context keeps a message (m2m_last_error).
+ *  - A context is not thread-safe.  Calls on one context are ordered on its
+ *    stream.  Separate contexts are independent.
+ *  - The caller owns every buffer it passes.  m2m_create copies its inputs and
+ *    keeps no caller pointer.  Readbacks synchronise the context's stream and
+ *    then write the caller's buffer.
+ *  - "device_ptrs"/"device_ptr" = 1 means the pointer is a device address on
+ *    the context's device (for example torch.Tensor.data_ptr()); 0 means host.
+ */
+#ifndef M2M_H
+#define M2M_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define M2M_ABI_VERSION 1
+#define M2M_MAX_BINNINGS 4
+#define M2M_MAX_EDGES 256
+#define M2M_MLP_NPARAM 4481
+
+typedef enum {
+    M2M_OK = 0,
+    M2M_ERR_INVALID = 1,            /* bad argument; nothing was changed                  */
+    M2M_ERR_NOMEM = 2,              /* device allocation failed                           */
+    M2M_ERR_DEVICE = 3,             /* a HIP call failed; the context should be destroyed */
+    M2M_ERR_NONPOSITIVE_WEIGHT = 4, /* an update produced w <= 0; state is the last good step */
+    M2M_ERR_NONFINITE = 5,          /* an update produced a non-finite weight; idem        */
+    M2M_ERR_UNSUPPORTED = 6         /* valid request this build does not support           */
+} m2m_status;
+
+enum { M2M_F32 = 0, M2M_F64 = 1 };
+enum { M2M_POT_HERNQUIST = 0, M2M_POT_LOG = 1, M2M_POT_HERNQUIST_NFW = 2, M2M_POT_MULTIPOLE = 3 };
+enum { M2M_BIN_SHELL = 1, M2M_BIN_ANNULUS = 2, M2M_BIN_GRID = 3 };
+enum { M2M_PRIOR_FLAT = 0, M2M_PRIOR_HIST = 1, M2M_PRIOR_MLP = 2 };
+enum { M2M_UPDATE_EULER = 0, M2M_UPDATE_EXP = 1 };
+
+/* Gravitational potential of one model (section 2: fixed a priori, or
+ * self-consistent).  Units are the caller's.
+ *   HERNQUIST      Phi = -G M/(r + a)
+ *   LOG            Phi = v0^2/2 ln(Rc^2 + x^2 + y^2 + z^2/q^2)
+ *   HERNQUIST_NFW  Hernquist(G, M, a) - G Mh ln(1 + r/rs)/r
+ *   MULTIPOLE      self-consistent multipole expansion to l <= lmax of the
+ *                  particles (mass w_i * Mtot), coefficients at nnode
+ *                  log-spaced radii in [rmin, rmax], linear in ln r between
+ *                  them; radii outside the range are clamped. */
+typedef struct {
+    int32_t kind;
+    int32_t lmax, nnode, reserved;
+    double G, M, a;
+    double v0, Rc, q;
+    double Mh, rs;
+    double rmin, rmax, Mtot;
+} m2m_potential;
+
+/* One group of observation bins.  kind SHELL bins r = |x| and ANNULUS bins the
+ * projected radius R = |(X, Y)| against nedge strictly increasing edges (bins
+ * are [e_k, e_k+1)); GRID bins the sky plane into nx * ny pixels over
+ * [x0, x1) x [y0, y1), pixel k = iy * nx + ix.  mom[0..nmom-1] lists the
+ * moments fitted in these bins: 0 = mass, 1 = sum w v_los, 2 = sum w v_los^2. */
+typedef struct {
+    int32_t kind;
+    int32_t nmom;
+    int32_t mom[3];
+    int32_t nedge;
+    const double *edges;     /* host, nedge values (SHELL, ANNULUS)     */
+    int32_t nx, ny;
+    double x0, x1, y0, y1;   /* GRID extent                             */
+} m2m_binning;
+
+/* Observation layout.  Sky coordinates for inclination incl (radians):
+ * X = x, Y = y cos(incl) - z sin(incl), v_los = vy sin(incl) + vz cos(incl).
+ * Observable index j runs over binnings in order, then their moments in the
+ * listed order, then bins; J is the total. */
+typedef struct {
+    double incl;
+    int32_t nbin;
+    int32_t reserved;
+    m2m_binning bin[M2M_MAX_BINNINGS];
+} m2m_obs_layout;
+
+/* Priors what_i (section 2.1).  FLAT: constant flat_value (<= 0 means 1/N_m).
+ * HIST: moving prior; what_i = mean weight of the particles in i's cell, cells
+ * on n[0] uniform bins of E in [Emin, Emax] (clamped to the edge cells), then
+ * n[1] bins of L/Lc(E) in [0, 1] (ax2 = 0) or Lz/Lc(E) in [-1, 1] (ax2 = 1), then
+ * n[2] bins of Lz/L in [-1, 1] (n[2] = 1: unused); Lc(E) is the angular momentum
+ * of the circular orbit of energy E.  Recomputed every `period` steps and held
+ * per particle in between.  MLP: learned prior ln what = g(u) + c with g a
+ * 3-64-64-1 tanh network of u = (2(E-Emin)/(Emax-Emin) - 1, 2 L/Lc - 1, Lz/L),
+ * retrained every `period` steps on the current weights (Adam on the mean
+ * squared error of g - ln w over a Philox4x32-10 sample of mlp_subset
+ * particles in minibatches of mlp_batch), with the HIST prior on the same cells
+ * as fallback whenever the w-weighted mean |ln what_mlp - ln what_hist| exceeds
+ * `fallback`.  E and Lc are measured in `ref` (ref.kind < 0: the model's own
+ * potential; required for MULTIPOLE models). */
+typedef struct {
+    int32_t kind;
+    int32_t ax2;
+    int32_t n[3];
+    int32_t period;
+    const double *Erange;    /* host, 2 * n_models (Emin, Emax) or NULL: min/max of E(0) */
+    double flat_value;
+    m2m_potential ref;
+    int32_t mlp_subset, mlp_batch;
+    double lr, beta1, beta2, adam_eps, fallback;
+    uint32_t seed;
+    int32_t reserved;
+    const float *mlp_init;   /* host, M2M_MLP_NPARAM initial parameters (MLP only) */
+} m2m_prior;
+
+/* Run configuration.  Models are independent M2M runs stepped together: model m
+ * owns particles [model_offsets[m], model_offsets[m+1]) and potentials[m]; all
+ * share the layout and prior settings.  update selects the integration of
+ * dw/dt = eps w G over dt: EXP (w exp(eps dt G), default) or EULER
+ * (w (1 + eps dt G)).  frozen = 1 keeps the particles fixed (weights still adapt). */
+typedef struct {
+    int32_t abi_version;       /* must be M2M_ABI_VERSION                 */
+    int32_t precision;         /* M2M_F32 or M2M_F64 particle arithmetic  */
+    int32_t update;
+    int32_t frozen;
+    double dt, eps, mu, tau;   /* dt > 0, eps >= 0, mu >= 0, tau >= dt    */
+    int32_t n_models;          /* >= 1                                    */
+    int32_t reserved;
+    const int64_t *model_offsets;       /* host, n_models + 1, first 0     */
+    const m2m_potential *potentials;    /* host, n_models                  */
+    m2m_prior prior;
+    void *stream;              /* hipStream_t to run on; NULL = default   */
+} m2m_config;
+
+/* Targets Y_j and errors sigma_j > 0 (FP64, host): J values shared by every
+ * model (per_model = 0) or n_models * J values, model-major (per_model = 1). */
+typedef struct {
+    const double *Y;
+    const double *sigma;
+    int32_t J;
+    int32_t per_model;
+} m2m_target;
+
+/* Per-step, per-model statistics: chi2 of the smoothed and of the instantaneous
+ * observables, S (eq. 2), F (eq. 1), sum w, min w, sum w^2,
+ * n_eff = (sum w)^2 / sum w^2, all of the state at the start of `step`. */
+typedef struct {
+    double chi2, chi2_inst, S, F, sum_w, min_w, sum_w2, n_eff;
+    int64_t step;
+    int32_t model;
+    int32_t reserved;
+} m2m_step_stats;
+
+/* Launch shape of the fused step kernel (see m2m_autotune).  timing = 1 makes
+ * m2m_step launch without graphs and bracket every fused step kernel with HIP
+ * events on the context's stream (read with m2m_kernel_time). */
+typedef struct {
+    int32_t threads;        /* 64..1024, multiple of 64 (FP64: at most 256) */
+    int32_t ilp;            /* particles per thread per tile: 1, 2, 4       */
+    int32_t blocks_per_cu;  /* blocks per compute unit (grid = CUs x this)  */
+    int32_t graph_steps;    /* steps captured per HIP graph (0: none)       */
+    int32_t timing;
+    int32_t reserved;
+} m2m_launch;
+
+typedef struct m2m_ctx m2m_ctx;
+
+int32_t m2m_abi_version(void);
+
+/* Create a context: validate, copy the particles (xv: 6 * N values, SoA
+ * x[N] y[N] z[N] vx[N] vy[N] vz[N]; w: N values > 0, both in cfg precision),
+ * observe the initial state (y(0), smoothed y = y(0), priors at step 0).
+ * Errors: INVALID (w <= 0 or non-finite, J or model offsets inconsistent,
+ * dt <= 0, mu < 0, eps < 0, tau < dt, edges not increasing, unknown kinds,
+ * unsupported MULTIPOLE/MLP combinations), NOMEM, DEVICE.  *out is NULL on error. */
+m2m_status m2m_create(const m2m_config *cfg, const m2m_obs_layout *layout,
+                      const m2m_target *target, const void *xv, const void *w,
+                      int32_t device_ptrs, m2m_ctx **out);
+
+/* Advance n_steps >= 0 steps.  last (nullable) receives n_models rows: the
+ * statistics of the final step taken.  On NONPOSITIVE_WEIGHT / NONFINITE the
+ * context stays at the start of the failing step (whose index is in the
+ * message and in m2m_step_index); later calls return the same error. */
+m2m_status m2m_step(m2m_ctx *ctx, int64_t n_steps, m2m_step_stats *last);
+
+/* Steps taken so far (host mirror of the device counter). */
+int64_t m2m_step_index(const m2m_ctx *ctx);
+
+/* Observables of model m at the current state: y (last observe), y_smooth,
+ * delta = (y_smooth - Y)/sigma (J values each, host, nullable) and chi2
+ * (nullable). */
+m2m_status m2m_observables(m2m_ctx *ctx, int32_t model, double *y, double *y_smooth,
+                           double *delta, double *chi2);
+
+/* Current weights, N values in cfg precision. */
+m2m_status m2m_weights(m2m_ctx *ctx, void *w_out, int32_t device_ptr);
+
+/* Priors what_i the next step will use (N values, cfg precision, nullable)
+ * and the cell table (n_models * ncell FP64 cell means, host, nullable;
+ * HIST and MLP only). */
+m2m_status m2m_priors(m2m_ctx *ctx, void *what_out, double *cell_mean, int32_t device_ptr);
+
+/* Current particles, 6 * N values SoA (same layout as m2m_create). */
+m2m_status m2m_particles(m2m_ctx *ctx, void *xv_out, int32_t device_ptr);
+
+/* Statistics rows of the most recent steps, oldest first (ring of the last
+ * 4096 steps per model).  out holds max_rows rows; *n_rows gets the count. */
+m2m_status m2m_history(m2m_ctx *ctx, m2m_step_stats *out, int64_t max_rows, int64_t *n_rows);
+
+/* Time candidate launch shapes (threads x ilp x blocks_per_cu) on trial_steps
+ * steps each, restore the state, keep the fastest; chosen may be NULL.  The
+ * choice is cached in the JSON file named by $M2M_AUTOTUNE_CACHE if set. */
+m2m_status m2m_autotune(m2m_ctx *ctx, int32_t trial_steps, m2m_launch *chosen);
+
+/* Read or set the launch shape (graph_steps = 0 disables HIP graphs). */
+m2m_status m2m_get_launch(const m2m_ctx *ctx, m2m_launch *out);
+m2m_status m2m_set_launch(m2m_ctx *ctx, const m2m_launch *in);
+
+/* Average duration in milliseconds of the fused step kernel over the last
+ * m2m_step call, measured with HIP events on the context's stream (0 if the
+ * call used graphs or took no steps); *launches gets the launch count. */
+m2m_status m2m_kernel_time(const m2m_ctx *ctx, double *ms_per_launch, int64_t *launches);
+
+/* Free every device buffer of the context (NULL is ignored). */
+void m2m_destroy(m2m_ctx *ctx);
+
+/* Message of the last error on ctx ("" if none; static text if ctx is NULL). */
+const char *m2m_last_error(const m2m_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* M2M_H */

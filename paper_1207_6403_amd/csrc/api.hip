@@ -1,0 +1,1026 @@
+// api.hip -- the C ABI (include/m2m.h): context, buffers, launch plan, HIP
+// graphs, readbacks and the launch-shape autotuner.
+//
+// Device memory (HBM) layout of a context, N particles over all models:
+//   state[2]  ping-pong particle buffers, 7 SoA rows of `stride` values
+//             (x y z vx vy vz w); step n reads state[n & 1], writes the other,
+//             so a failed step leaves the last good state untouched;
+//   what      per-particle priors (periodic and learned priors only);
+//   per model observables y, ys, delta (FP64, J each), the FP32/FP64 update
+//             table Dt_j/sigma_j, prior cell means, chi^2, a statistics ring;
+//   partial   one slot per (block, model) pair: the block's LDS histograms,
+//             summed in fixed order by the finalise kernel.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "m2m.h"
+#include "runtime.h"
+#include "internal.h"
+
+using namespace m2m;
+
+static thread_local std::string g_create_error;
+
+// ------------------------------------------------------------------ helpers
+namespace {
+
+m2m_status fail(m2m_ctx* c, m2m_status s, const std::string& msg) {
+    if (c) { c->msg = msg; }
+    else g_create_error = msg;
+    return s;
+}
+
+#define HIPCHK(ctx, expr)                                                                        \
+    do {                                                                                         \
+        hipError_t e_ = (expr);                                                                  \
+        if (e_ != hipSuccess)                                                                    \
+            return fail(ctx, M2M_ERR_DEVICE, std::string(#expr ": ") + hipGetErrorString(e_));    \
+    } while (0)
+
+template <typename X>
+m2m_status dalloc(m2m_ctx* c, X** p, size_t n) {
+    *p = nullptr;
+    if (n == 0) n = 1;
+    hipError_t e = hipMalloc((void**)p, n * sizeof(X));
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        *p = nullptr;
+        return fail(c, M2M_ERR_NOMEM, "hipMalloc of " + std::to_string(n * sizeof(X)) + " bytes failed");
+    }
+    c->allocs.push_back((void*)*p);
+    return M2M_OK;
+}
+
+void dfree(m2m_ctx* c, void* p) {
+    if (!p) return;
+    auto it = std::find(c->allocs.begin(), c->allocs.end(), p);
+    if (it != c->allocs.end()) c->allocs.erase(it);
+    (void)hipFree(p);
+}
+
+size_t tsize(const m2m_ctx* c) { return c->prec == M2M_F64 ? 8 : 4; }
+
+bool is_fin(double v) { return std::isfinite(v); }
+
+}  // namespace
+
+// --------------------------------------------------------------- validation
+static m2m_status validate(const m2m_config* cfg, const m2m_obs_layout* lay, const m2m_target* tg,
+                           int64_t* N_out, int* J_out) {
+    if (!cfg || !lay || !tg) return fail(nullptr, M2M_ERR_INVALID, "null config, layout or target");
+    if (cfg->abi_version != M2M_ABI_VERSION) return fail(nullptr, M2M_ERR_INVALID, "abi_version mismatch");
+    if (cfg->precision != M2M_F32 && cfg->precision != M2M_F64) return fail(nullptr, M2M_ERR_INVALID, "precision");
+    if (cfg->update != M2M_UPDATE_EULER && cfg->update != M2M_UPDATE_EXP) return fail(nullptr, M2M_ERR_INVALID, "update");
+    if (!(cfg->dt > 0) || !is_fin(cfg->dt)) return fail(nullptr, M2M_ERR_INVALID, "dt must be > 0");
+    if (!(cfg->eps >= 0) || !is_fin(cfg->eps)) return fail(nullptr, M2M_ERR_INVALID, "eps must be >= 0");
+    if (!(cfg->mu >= 0) || !is_fin(cfg->mu)) return fail(nullptr, M2M_ERR_INVALID, "mu must be >= 0");
+    if (!(cfg->tau >= cfg->dt) || !is_fin(cfg->tau)) return fail(nullptr, M2M_ERR_INVALID, "tau must be >= dt");
+    if (cfg->n_models < 1 || !cfg->model_offsets || !cfg->potentials)
+        return fail(nullptr, M2M_ERR_INVALID, "n_models >= 1 with offsets and potentials required");
+    if (cfg->model_offsets[0] != 0) return fail(nullptr, M2M_ERR_INVALID, "model_offsets[0] must be 0");
+    for (int m = 0; m < cfg->n_models; ++m)
+        if (cfg->model_offsets[m + 1] <= cfg->model_offsets[m])
+            return fail(nullptr, M2M_ERR_INVALID, "every model needs at least one particle (offsets increasing)");
+    const int kind = cfg->potentials[0].kind;
+    for (int m = 0; m < cfg->n_models; ++m) {
+        const m2m_potential& p = cfg->potentials[m];
+        if (p.kind != kind) return fail(nullptr, M2M_ERR_INVALID, "all models must share the potential kind");
+        if (p.kind == M2M_POT_HERNQUIST || p.kind == M2M_POT_HERNQUIST_NFW) {
+            if (!(p.G > 0 && p.M >= 0 && p.a > 0)) return fail(nullptr, M2M_ERR_INVALID, "Hernquist needs G>0, M>=0, a>0");
+            if (p.kind == M2M_POT_HERNQUIST_NFW && !(p.Mh >= 0 && p.rs > 0))
+                return fail(nullptr, M2M_ERR_INVALID, "NFW needs Mh>=0, rs>0");
+        } else if (p.kind == M2M_POT_LOG) {
+            if (!(p.v0 > 0 && p.Rc > 0 && p.q > 0)) return fail(nullptr, M2M_ERR_INVALID, "log potential needs v0, Rc, q > 0");
+        } else if (p.kind == M2M_POT_MULTIPOLE) {
+            if (!(p.lmax >= 0 && p.lmax <= 8 && p.nnode >= 2 && p.nnode <= 512 && p.rmin > 0 && p.rmax > p.rmin &&
+                  p.G > 0 && p.Mtot > 0))
+                return fail(nullptr, M2M_ERR_INVALID, "multipole needs 0<=lmax<=8, 2<=nnode<=512, 0<rmin<rmax, G, Mtot > 0");
+        } else {
+            return fail(nullptr, M2M_ERR_INVALID, "unknown potential kind");
+        }
+    }
+    if (lay->nbin < 1 || lay->nbin > M2M_MAX_BINNINGS) return fail(nullptr, M2M_ERR_INVALID, "nbin must be 1..4");
+    if (!is_fin(lay->incl)) return fail(nullptr, M2M_ERR_INVALID, "inclination");
+    int J = 0, ne = 0;
+    for (int b = 0; b < lay->nbin; ++b) {
+        const m2m_binning& d = lay->bin[b];
+        if (d.nmom < 1 || d.nmom > 3) return fail(nullptr, M2M_ERR_INVALID, "nmom must be 1..3");
+        for (int k = 0; k < d.nmom; ++k)
+            if (d.mom[k] < 0 || d.mom[k] > 2) return fail(nullptr, M2M_ERR_INVALID, "moments are 0, 1 or 2");
+        int nb;
+        if (d.kind == M2M_BIN_SHELL || d.kind == M2M_BIN_ANNULUS) {
+            if (d.nedge < 2 || !d.edges) return fail(nullptr, M2M_ERR_INVALID, "need >= 2 edges");
+            for (int k = 0; k < d.nedge; ++k) {
+                if (!is_fin(d.edges[k])) return fail(nullptr, M2M_ERR_INVALID, "edges must be finite");
+                if (k && !(d.edges[k] > d.edges[k - 1])) return fail(nullptr, M2M_ERR_INVALID, "edges must increase");
+            }
+            nb = d.nedge - 1;
+            ne += d.nedge;
+        } else if (d.kind == M2M_BIN_GRID) {
+            if (d.nx < 1 || d.ny < 1 || !(d.x1 > d.x0) || !(d.y1 > d.y0) || !is_fin(d.x0) || !is_fin(d.x1) ||
+                !is_fin(d.y0) || !is_fin(d.y1))
+                return fail(nullptr, M2M_ERR_INVALID, "grid needs nx, ny >= 1 and x1 > x0, y1 > y0");
+            nb = d.nx * d.ny;
+        } else {
+            return fail(nullptr, M2M_ERR_INVALID, "unknown binning kind");
+        }
+        J += d.nmom * nb;
+    }
+    if (ne > M2M_MAX_EDGES) return fail(nullptr, M2M_ERR_INVALID, "too many edges (max 256)");
+    if (tg->J != J) return fail(nullptr, M2M_ERR_INVALID, "target J does not match the layout");
+    if (!tg->Y || !tg->sigma) return fail(nullptr, M2M_ERR_INVALID, "target arrays missing");
+    const int64_t nt = (int64_t)J * (tg->per_model ? cfg->n_models : 1);
+    for (int64_t j = 0; j < nt; ++j)
+        if (!is_fin(tg->Y[j]) || !(tg->sigma[j] > 0) || !is_fin(tg->sigma[j]))
+            return fail(nullptr, M2M_ERR_INVALID, "target Y must be finite and sigma > 0");
+    const m2m_prior& P = cfg->prior;
+    if (P.kind != M2M_PRIOR_FLAT && P.kind != M2M_PRIOR_HIST && P.kind != M2M_PRIOR_MLP)
+        return fail(nullptr, M2M_ERR_INVALID, "unknown prior kind");
+    if (P.kind != M2M_PRIOR_FLAT) {
+        if (P.n[0] < 1 || P.n[1] < 1 || P.n[2] < 1 || (int64_t)P.n[0] * P.n[1] * P.n[2] > 16384)
+            return fail(nullptr, M2M_ERR_INVALID, "prior cells must be >= 1 per axis, <= 16384 in all");
+        if (P.ax2 != 0 && P.ax2 != 1) return fail(nullptr, M2M_ERR_INVALID, "prior ax2 must be 0 or 1");
+        if (P.period < 1) return fail(nullptr, M2M_ERR_INVALID, "prior period must be >= 1");
+        if (P.Erange)
+            for (int m = 0; m < cfg->n_models; ++m)
+                if (!(P.Erange[2 * m + 1] > P.Erange[2 * m]) || !is_fin(P.Erange[2 * m]) || !is_fin(P.Erange[2 * m + 1]))
+                    return fail(nullptr, M2M_ERR_INVALID, "prior Erange needs Emin < Emax per model");
+        if (P.ref.kind >= 0 && P.ref.kind != kind)
+            return fail(nullptr, M2M_ERR_UNSUPPORTED, "prior reference potential must be the model potential here");
+        if (kind == M2M_POT_MULTIPOLE && P.ref.kind < 0)
+            return fail(nullptr, M2M_ERR_INVALID, "multipole models need an analytic prior reference potential");
+    }
+    if (P.kind == M2M_PRIOR_MLP) return fail(nullptr, M2M_ERR_UNSUPPORTED, "learned prior not available in this build");
+    if (kind == M2M_POT_MULTIPOLE) return fail(nullptr, M2M_ERR_UNSUPPORTED, "multipole potential not available in this build");
+    *N_out = cfg->model_offsets[cfg->n_models];
+    *J_out = J;
+    return M2M_OK;
+}
+
+// ------------------------------------------------------------------ the plan
+static void free_plan(m2m_ctx* c) {
+    Plan& p = c->plan;
+    for (void* q : {(void*)p.tile_model, (void*)p.tile_p0, (void*)p.tile_cnt, (void*)p.block_tile0,
+                    (void*)p.block_slot0, (void*)p.model_slot, (void*)p.chunk_model, (void*)p.chunk_col0,
+                    (void*)p.chunk_ncol, (void*)p.model_chunk, (void*)p.part, (void*)p.seg_stats, (void*)p.l2,
+                    (void*)p.chunk_cnt, (void*)p.chunk_chi, (void*)p.model_cnt, (void*)p.all_cnt, (void*)p.erange_out})
+        dfree(c, q);
+    p = Plan();
+    for (int k = 0; k < 2; ++k)
+        if (c->graph[k]) { (void)hipGraphExecDestroy(c->graph[k]); c->graph[k] = nullptr; }
+}
+
+template <typename X>
+static m2m_status upload(m2m_ctx* c, X** d, const std::vector<X>& h) {
+    m2m_status s = dalloc(c, d, h.size());
+    if (s) return s;
+    HIPCHK(c, hipMemcpy(*d, h.data(), h.size() * sizeof(X), hipMemcpyHostToDevice));
+    return M2M_OK;
+}
+
+static m2m_status make_plan(m2m_ctx* c, int threads, int ilp, int bpc) {
+    free_plan(c);
+    Plan& p = c->plan;
+    p.threads = threads;
+    p.ilp = ilp;
+    p.bpc = bpc;
+    const int64_t TS = (int64_t)threads * ilp;
+    std::vector<int32_t> tm, tc;
+    std::vector<int64_t> tp;
+    for (int m = 0; m < c->M; ++m) {
+        const int64_t n = c->off[m + 1] - c->off[m];
+        for (int64_t k = 0; k * TS < n; ++k) {
+            tm.push_back(m);
+            tp.push_back(c->off[m] + k * TS);
+            tc.push_back((int32_t)std::min<int64_t>(TS, n - k * TS));
+        }
+    }
+    const int64_t T = (int64_t)tm.size();
+    const int64_t B = std::max<int64_t>(1, std::min<int64_t>(T, (int64_t)c->numCU * bpc));
+    std::vector<int32_t> bt0(B + 1), bs0(B), mslot(c->M + 1, -1);
+    int32_t nslot = 0;
+    for (int64_t b = 0; b <= B; ++b) bt0[b] = (int32_t)((b * T) / B);
+    for (int64_t b = 0; b < B; ++b) {
+        bs0[b] = nslot;
+        if (bt0[b] == bt0[b + 1]) continue;
+        const int mlo = tm[bt0[b]], mhi = tm[bt0[b + 1] - 1];
+        for (int m = mlo; m <= mhi; ++m) {
+            if (mslot[m] < 0) mslot[m] = nslot;
+            ++nslot;
+        }
+    }
+    mslot[c->M] = nslot;
+    int maxslot = 0;
+    for (int m = 0; m < c->M; ++m) maxslot = std::max(maxslot, mslot[m + 1] - mslot[m]);
+    std::vector<int32_t> cm, cc0, cn, mch(c->M + 1);
+    for (int m = 0; m < c->M; ++m) {
+        mch[m] = (int32_t)cm.size();
+        for (int c0 = 0; c0 < c->pcols; c0 += 256) {
+            cm.push_back(m);
+            cc0.push_back(c0);
+            cn.push_back(std::min(256, c->pcols - c0));
+        }
+    }
+    mch[c->M] = (int32_t)cm.size();
+    p.ntile = T;
+    p.nblock = (int)B;
+    p.nslot = nslot;
+    p.nchunk = (int)cm.size();
+    p.nsplit = std::max(1, (maxslot + 31) / 32);
+    m2m_status s;
+    if ((s = upload(c, &p.tile_model, tm)) || (s = upload(c, &p.tile_p0, tp)) || (s = upload(c, &p.tile_cnt, tc)) ||
+        (s = upload(c, &p.block_tile0, bt0)) || (s = upload(c, &p.block_slot0, bs0)) ||
+        (s = upload(c, &p.model_slot, mslot)) || (s = upload(c, &p.chunk_model, cm)) ||
+        (s = upload(c, &p.chunk_col0, cc0)) || (s = upload(c, &p.chunk_ncol, cn)) || (s = upload(c, &p.model_chunk, mch)))
+        return s;
+    if ((s = dalloc(c, (char**)&p.part, (size_t)nslot * c->pcols * tsize(c))) ||
+        (s = dalloc(c, &p.seg_stats, (size_t)nslot * 4)) ||
+        (s = dalloc(c, &p.l2, (size_t)p.nchunk * p.nsplit * 256)) || (s = dalloc(c, &p.chunk_cnt, (size_t)p.nchunk)) ||
+        (s = dalloc(c, &p.chunk_chi, (size_t)p.nchunk * 2)) || (s = dalloc(c, &p.model_cnt, (size_t)c->M)) ||
+        (s = dalloc(c, &p.all_cnt, 1)) || (s = dalloc(c, &p.erange_out, (size_t)nslot * 2)))
+        return s;
+    HIPCHK(c, hipMemset(p.chunk_cnt, 0, sizeof(int) * p.nchunk));
+    HIPCHK(c, hipMemset(p.model_cnt, 0, sizeof(int) * c->M));
+    HIPCHK(c, hipMemset(p.all_cnt, 0, sizeof(int)));
+    HIPCHK(c, hipMemset(p.part, 0, (size_t)nslot * c->pcols * tsize(c)));
+    // LDS of the fused kernel: histograms, cell sums/counts, update table,
+    // cell means, edges, reduction scratch
+    const size_t ts = tsize(c);
+    const int NCe = (c->NC + 1) & ~1;
+    p.lds = 8 * (size_t)c->JP + 8 * (size_t)c->NC + 4 * (size_t)NCe + ts * ((size_t)c->JP + NCe + ((c->nedge + 1) & ~1)) + 8 * 4 * 16;
+    p.lds = (p.lds + 15) & ~(size_t)15;
+    if (p.lds > (size_t)c->max_lds)
+        return fail(c, M2M_ERR_UNSUPPORTED, "layout needs " + std::to_string(p.lds) + " bytes of LDS per block (max " +
+                                                std::to_string(c->max_lds) + ")");
+    return M2M_OK;
+}
+
+// --------------------------------------------------------------- launches
+template <typename T>
+static void fill_step_args(m2m_ctx* c, StepArgs<T, T>& a, int parity, int mode, int what_mode, int accum) {
+    const Plan& p = c->plan;
+    a.in = (const T*)c->state[parity];
+    a.out = (T*)c->state[parity ^ 1];
+    a.stride = c->stride;
+    a.what = (T*)c->what;
+    a.tile_model = p.tile_model;
+    a.tile_p0 = p.tile_p0;
+    a.tile_cnt = p.tile_cnt;
+    a.block_tile0 = p.block_tile0;
+    a.block_slot0 = p.block_slot0;
+    a.pots = (const Pot<T>*)c->pots_d;
+    a.ectab = (const T*)c->ectab;
+    a.erange = (const T*)c->erange;
+    a.flatw = (const T*)c->flatw;
+    a.cvec = (const T*)c->cvec;
+    a.cellmean = (const T*)c->cellmean;
+    a.part = (T*)p.part;
+    a.seg_stats = p.seg_stats;
+    a.edges = (const T*)c->edges;
+    a.nedge = c->nedge;
+    a.pcols = c->pcols;
+    a.jpad = c->JP;
+    std::memcpy(&a.lay, c->lay_bytes, sizeof(Layout<T>));
+    std::memcpy(&a.cells, c->cells_bytes, sizeof(Cells<T>));
+    a.dt = (T)c->dt;
+    a.eps = (T)c->eps;
+    a.mu = (T)c->mu;
+    a.update = c->update;
+    a.frozen = c->frozen;
+    a.mode = mode;
+    a.what_mode = what_mode;
+    a.accum_cells = accum;
+    a.flag = c->flag;
+    a.bad_step = c->bad_step;
+    a.d_step = c->d_step;
+}
+
+template <typename T>
+static void fill_fin_args(m2m_ctx* c, FinArgs<T, T>& f, int first, int accum) {
+    const Plan& p = c->plan;
+    f.part = (const T*)p.part;
+    f.pcols = c->pcols;
+    f.jpad = c->JP;
+    f.J = c->J;
+    f.ncell = c->NC;
+    f.n_models = c->M;
+    f.chunk_model = p.chunk_model;
+    f.chunk_col0 = p.chunk_col0;
+    f.chunk_ncol = p.chunk_ncol;
+    f.model_slot = p.model_slot;
+    f.model_chunk = p.model_chunk;
+    f.l2 = p.l2;
+    f.chunk_cnt = p.chunk_cnt;
+    f.chunk_chi = p.chunk_chi;
+    f.model_cnt = p.model_cnt;
+    f.all_cnt = p.all_cnt;
+    f.Y = c->Y;
+    f.sigma = c->sigma;
+    f.y = c->y;
+    f.ys = c->ys;
+    f.delta = c->delta;
+    f.cvec = (T*)c->cvec;
+    f.cellmean = (T*)c->cellmean;
+    f.cellmean64 = c->cellmean64;
+    f.chi2 = c->chi2;
+    f.seg_stats = p.seg_stats;
+    f.ring = c->ring;
+    f.g = c->dt / c->tau;
+    f.mu = c->mu;
+    f.first = first;
+    f.accum_cells = accum;
+    f.flag = c->flag;
+    f.d_step = c->d_step;
+}
+
+// prior handling of step n: (what_mode, accumulate cells for step n+1)
+static void prior_modes(const m2m_ctx* c, int64_t n, int* what_mode, int* accum) {
+    const int P = c->prior.period;
+    if (c->prior.kind == M2M_PRIOR_FLAT) { *what_mode = 0; *accum = 0; }
+    else if (c->prior.kind == M2M_PRIOR_HIST && P == 1) { *what_mode = 1; *accum = 1; }
+    else if (c->prior.kind == M2M_PRIOR_HIST) { *what_mode = (n % P == 0) ? 2 : 3; *accum = ((n + 1) % P == 0); }
+    else { *what_mode = 3; *accum = 0; }
+}
+
+template <typename T>
+static hipError_t launch_one_T(m2m_ctx* c, int64_t n, hipEvent_t e0, hipEvent_t e1) {
+    int wm, acc;
+    prior_modes(c, n, &wm, &acc);
+    StepArgs<T, T> a;
+    fill_step_args<T>(c, a, (int)(n & 1), 0, wm, acc);
+    const Plan& p = c->plan;
+    if (e0) (void)hipEventRecord(e0, c->stream);
+    hipError_t e = launch_step<T, T>(a, c->pot_kind, p.ilp, p.nblock, p.threads, p.lds, c->stream);
+    if (e1) (void)hipEventRecord(e1, c->stream);
+    if (e != hipSuccess) return e;
+    FinArgs<T, T> f;
+    fill_fin_args<T>(c, f, 0, acc);
+    return launch_finalize<T, T>(f, p.nchunk, p.nsplit, c->stream);
+}
+
+static hipError_t launch_one(m2m_ctx* c, int64_t n, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr) {
+    return c->prec == M2M_F64 ? launch_one_T<double>(c, n, e0, e1) : launch_one_T<float>(c, n, e0, e1);
+}
+
+template <typename T>
+static hipError_t launch_prologue_T(m2m_ctx* c) {
+    const int accum = c->prior.kind == M2M_PRIOR_HIST ? 1 : 0;
+    StepArgs<T, T> a;
+    fill_step_args<T>(c, a, (int)(c->step & 1), 1, 0, accum);
+    const Plan& p = c->plan;
+    hipError_t e = launch_step<T, T>(a, c->pot_kind, p.ilp, p.nblock, p.threads, p.lds, c->stream);
+    if (e != hipSuccess) return e;
+    FinArgs<T, T> f;
+    fill_fin_args<T>(c, f, 1, accum);
+    return launch_finalize<T, T>(f, p.nchunk, p.nsplit, c->stream);
+}
+
+template <typename T>
+static m2m_status derive_erange_T(m2m_ctx* c, std::vector<double>& er) {
+    const Plan& p = c->plan;
+    ErangeArgs<T> a;
+    a.in = (const T*)c->state[0];
+    a.stride = c->stride;
+    a.tile_model = p.tile_model;
+    a.tile_p0 = p.tile_p0;
+    a.tile_cnt = p.tile_cnt;
+    a.block_tile0 = p.block_tile0;
+    a.block_slot0 = p.block_slot0;
+    a.pots = (const Pot<T>*)c->pots_d;
+    a.out = p.erange_out;
+    HIPCHK(c, launch_erange<T>(a, c->pot_kind, p.nblock, c->stream));
+    std::vector<double> h((size_t)p.nslot * 2);
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, hipMemcpy(h.data(), p.erange_out, h.size() * 8, hipMemcpyDeviceToHost));
+    std::vector<int32_t> ms(c->M + 1);
+    HIPCHK(c, hipMemcpy(ms.data(), p.model_slot, ms.size() * 4, hipMemcpyDeviceToHost));
+    er.assign(2 * (size_t)c->M, 0.0);
+    for (int m = 0; m < c->M; ++m) {
+        double lo = INFINITY, hi = -INFINITY;
+        for (int s = ms[m]; s < ms[m + 1]; ++s) { lo = std::min(lo, h[2 * s]); hi = std::max(hi, h[2 * s + 1]); }
+        if (!(hi > lo)) hi = lo + 1e-6 * std::max(1.0, std::fabs(lo));
+        er[2 * m] = lo;
+        er[2 * m + 1] = hi;
+    }
+    return M2M_OK;
+}
+
+// ---------------------------------------------------------- host-side tables
+template <typename T>
+static void build_tables(m2m_ctx* c, std::vector<unsigned char>& pots, std::vector<T>& ectab) {
+    pots.assign(sizeof(Pot<T>) * c->M, 0);
+    ectab.assign(128 * (size_t)c->M, T(0));
+    for (int m = 0; m < c->M; ++m) {
+        const m2m_potential& q = c->pots[m];
+        Pot<T> p{};
+        p.kind = q.kind;
+        p.lc_off = 128 * m;
+        p.GM = (T)(q.G * q.M);
+        p.a = (T)q.a;
+        p.v2 = (T)(q.v0 * q.v0);
+        p.Rc2 = (T)(q.Rc * q.Rc);
+        p.iq2 = q.q > 0 ? (T)(1.0 / (q.q * q.q)) : T(0);
+        p.GMh = q.kind == M2M_POT_HERNQUIST_NFW ? (T)(q.G * q.Mh) : T(0);
+        p.rs = q.rs > 0 ? (T)q.rs : T(1);
+        p.irs = q.rs > 0 ? (T)(1.0 / q.rs) : T(1);
+        std::memcpy(pots.data() + sizeof(Pot<T>) * m, &p, sizeof(p));
+        // circular-orbit energies E_c(r) = Phi + r Phi'/2 at 128 log radii (Hernquist + NFW)
+        for (int k = 0; k < 128; ++k) {
+            const double r = 1e-4 * std::pow(10.0, 8.0 * k / 127.0);
+            double phi = -q.G * q.M / (r + q.a), d1 = q.G * q.M / ((r + q.a) * (r + q.a));
+            if (q.kind == M2M_POT_HERNQUIST_NFW && q.Mh > 0) {
+                const double l1 = std::log1p(r / q.rs);
+                phi += -q.G * q.Mh * l1 / r;
+                d1 += q.G * q.Mh * (l1 / (r * r) - 1.0 / (r * (r + q.rs)));
+            }
+            ectab[128 * (size_t)m + k] = (T)(phi + 0.5 * r * d1);
+        }
+    }
+}
+
+template <typename T>
+static void build_layout(m2m_ctx* c) {
+    Layout<T> L{};
+    L.cosi = (T)std::cos(c->lay.incl);
+    L.sini = (T)std::sin(c->lay.incl);
+    L.nbin = c->lay.nbin;
+    L.J = c->J;
+    int off = 0, e0 = 0;
+    for (int b = 0; b < c->lay.nbin; ++b) {
+        const m2m_binning& d = c->lay.bin[b];
+        L.kind[b] = d.kind;
+        L.nmom[b] = d.nmom;
+        for (int k = 0; k < 3; ++k) L.mom[b][k] = k < d.nmom ? d.mom[k] : 0;
+        L.off[b] = off;
+        L.edge0[b] = e0;
+        if (d.kind == M2M_BIN_GRID) {
+            L.nb[b] = d.nx * d.ny;
+            L.nx[b] = d.nx;
+            L.ny[b] = d.ny;
+            L.x0[b] = (T)d.x0;
+            L.wx[b] = (T)(d.x1 - d.x0);
+            L.y0[b] = (T)d.y0;
+            L.wy[b] = (T)(d.y1 - d.y0);
+        } else {
+            L.nb[b] = d.nedge - 1;
+            e0 += d.nedge;
+        }
+        off += d.nmom * L.nb[b];
+    }
+    std::memcpy(c->lay_bytes, &L, sizeof(L));
+    Cells<T> C{};
+    C.n0 = c->prior.n[0];
+    C.n1 = c->prior.n[1];
+    C.n2 = c->prior.n[2];
+    C.ax2 = c->prior.ax2;
+    C.ncell = c->NC;
+    std::memcpy(c->cells_bytes, &C, sizeof(C));
+}
+
+// ------------------------------------------------------------------- create
+template <typename T>
+static m2m_status create_T(m2m_ctx* c, const m2m_target* tg, const void* xv, const void* w, int dev) {
+    const int64_t N = c->N, S = c->stride;
+    m2m_status s;
+    for (int k = 0; k < 2; ++k)
+        if ((s = dalloc(c, (T**)&c->state[k], (size_t)7 * S))) return s;
+    // copy in and validate the weights and coordinates on the host
+    std::vector<T> hx((size_t)6 * N), hw((size_t)N);
+    const hipMemcpyKind kind = dev ? hipMemcpyDeviceToHost : hipMemcpyHostToHost;
+    HIPCHK(c, hipMemcpy(hx.data(), xv, sizeof(T) * 6 * N, kind));
+    HIPCHK(c, hipMemcpy(hw.data(), w, sizeof(T) * N, kind));
+    for (int64_t i = 0; i < 6 * N; ++i)
+        if (!std::isfinite((double)hx[i])) return fail(c, M2M_ERR_INVALID, "non-finite coordinate at " + std::to_string(i));
+    for (int64_t i = 0; i < N; ++i)
+        if (!(hw[i] > T(0)) || !std::isfinite((double)hw[i]))
+            return fail(c, M2M_ERR_INVALID, "weights must be finite and > 0 (index " + std::to_string(i) + ")");
+    for (int k = 0; k < 6; ++k)
+        HIPCHK(c, hipMemcpy((T*)c->state[0] + k * S, hx.data() + k * N, sizeof(T) * N, hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy((T*)c->state[0] + 6 * S, hw.data(), sizeof(T) * N, hipMemcpyHostToDevice));
+    if (c->prior.kind != M2M_PRIOR_FLAT && (c->prior.period > 1 || c->prior.kind == M2M_PRIOR_MLP))
+        if ((s = dalloc(c, (T**)&c->what, (size_t)S))) return s;
+    // tables
+    std::vector<unsigned char> pots;
+    std::vector<T> ectab;
+    build_tables<T>(c, pots, ectab);
+    if ((s = upload(c, (unsigned char**)&c->pots_d, pots)) || (s = upload(c, (T**)&c->ectab, ectab))) return s;
+    build_layout<T>(c);
+    std::vector<T> ed;
+    for (int b = 0; b < c->lay.nbin; ++b)
+        if (c->lay.bin[b].kind != M2M_BIN_GRID)
+            for (double v : c->edges_host[b]) ed.push_back((T)v);
+    if (ed.empty()) ed.push_back(T(0));
+    if ((s = upload(c, (T**)&c->edges, ed))) return s;
+    std::vector<T> fw(c->M);
+    for (int m = 0; m < c->M; ++m)
+        fw[m] = (T)(c->prior.flat_value > 0 ? c->prior.flat_value : 1.0 / (double)(c->off[m + 1] - c->off[m]));
+    if ((s = upload(c, (T**)&c->flatw, fw))) return s;
+    const size_t MJ = (size_t)c->M * c->J;
+    std::vector<double> Y(MJ), sg(MJ);
+    for (int m = 0; m < c->M; ++m)
+        for (int j = 0; j < c->J; ++j) {
+            const size_t src = (tg->per_model ? (size_t)m * c->J : 0) + j;
+            Y[(size_t)m * c->J + j] = tg->Y[src];
+            sg[(size_t)m * c->J + j] = tg->sigma[src];
+        }
+    if ((s = upload(c, &c->Y, Y)) || (s = upload(c, &c->sigma, sg))) return s;
+    if ((s = dalloc(c, &c->y, MJ)) || (s = dalloc(c, &c->ys, MJ)) || (s = dalloc(c, &c->delta, MJ)) ||
+        (s = dalloc(c, (T**)&c->cvec, MJ)) || (s = dalloc(c, (T**)&c->cellmean, (size_t)c->M * std::max(1, c->NC))) ||
+        (s = dalloc(c, &c->cellmean64, (size_t)c->M * std::max(1, c->NC))) || (s = dalloc(c, &c->chi2, 2 * (size_t)c->M)) ||
+        (s = dalloc(c, &c->ring, (size_t)c->M * kRing)) || (s = dalloc(c, &c->flag, 1)) ||
+        (s = dalloc(c, &c->bad_step, 1)) || (s = dalloc(c, &c->d_step, 1)))
+        return s;
+    HIPCHK(c, hipMemset(c->flag, 0, sizeof(int)));
+    HIPCHK(c, hipMemset(c->bad_step, 0, sizeof(long long)));
+    HIPCHK(c, hipMemset(c->d_step, 0, sizeof(long long)));
+    HIPCHK(c, hipMemset(c->ring, 0, sizeof(StatRow) * (size_t)c->M * kRing));
+    HIPCHK(c, hipMemset(c->cvec, 0, sizeof(T) * MJ));
+    HIPCHK(c, hipMemset(c->cellmean, 0, sizeof(T) * (size_t)c->M * std::max(1, c->NC)));
+    HIPCHK(c, hipMemset(c->cellmean64, 0, sizeof(double) * (size_t)c->M * std::max(1, c->NC)));
+    // launch plan, energy range of the prior grid, prologue observe
+    if ((s = make_plan(c, c->launch.threads, c->launch.ilp, c->launch.blocks_per_cu))) return s;
+    std::vector<double> er(2 * (size_t)c->M, 0.0);
+    if (c->prior.kind != M2M_PRIOR_FLAT) {
+        if (c->prior.Erange) for (size_t k = 0; k < er.size(); ++k) er[k] = c->prior.Erange[k];
+        else if ((s = derive_erange_T<T>(c, er))) return s;
+    }
+    c->erange_host = er;
+    std::vector<T> erT(er.size());
+    for (size_t k = 0; k < er.size(); ++k) erT[k] = (T)er[k];
+    if ((s = upload(c, (T**)&c->erange, erT))) return s;
+    HIPCHK(c, launch_prologue_T<T>(c));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return M2M_OK;
+}
+
+extern "C" int32_t m2m_abi_version(void) { return M2M_ABI_VERSION; }
+
+extern "C" m2m_status m2m_create(const m2m_config* cfg, const m2m_obs_layout* layout, const m2m_target* target,
+                                 const void* xv, const void* w, int32_t device_ptrs, m2m_ctx** out) {
+    if (!out) return fail(nullptr, M2M_ERR_INVALID, "out is NULL");
+    *out = nullptr;
+    if (!xv || !w) return fail(nullptr, M2M_ERR_INVALID, "particle arrays missing");
+    int64_t N = 0;
+    int J = 0;
+    m2m_status s = validate(cfg, layout, target, &N, &J);
+    if (s) return s;
+    if (!device_ptrs) {
+        // host inputs are checked before any device work
+        const bool f64 = cfg->precision == M2M_F64;
+        for (int64_t i = 0; i < 6 * N; ++i) {
+            const double v = f64 ? ((const double*)xv)[i] : ((const float*)xv)[i];
+            if (!std::isfinite(v)) return fail(nullptr, M2M_ERR_INVALID, "non-finite coordinate at " + std::to_string(i));
+        }
+        for (int64_t i = 0; i < N; ++i) {
+            const double v = f64 ? ((const double*)w)[i] : ((const float*)w)[i];
+            if (!(v > 0) || !std::isfinite(v))
+                return fail(nullptr, M2M_ERR_INVALID, "weights must be finite and > 0 (index " + std::to_string(i) + ")");
+        }
+    }
+    m2m_ctx* c = new m2m_ctx();
+    c->prec = cfg->precision;
+    c->update = cfg->update;
+    c->frozen = cfg->frozen ? 1 : 0;
+    c->dt = cfg->dt;
+    c->eps = cfg->eps;
+    c->mu = cfg->mu;
+    c->tau = cfg->tau;
+    c->M = cfg->n_models;
+    c->off.assign(cfg->model_offsets, cfg->model_offsets + c->M + 1);
+    c->pots.assign(cfg->potentials, cfg->potentials + c->M);
+    c->pot_kind = c->pots[0].kind;
+    c->prior = cfg->prior;
+    c->prior.Erange = nullptr;
+    c->prior.mlp_init = nullptr;
+    c->lay = *layout;
+    for (int b = 0; b < layout->nbin; ++b) {
+        if (layout->bin[b].kind != M2M_BIN_GRID)
+            c->edges_host[b].assign(layout->bin[b].edges, layout->bin[b].edges + layout->bin[b].nedge);
+        c->lay.bin[b].edges = nullptr;
+    }
+    c->nedge = 0;
+    for (int b = 0; b < layout->nbin; ++b) c->nedge += (int)c->edges_host[b].size();
+    c->N = N;
+    c->stride = (N + 63) / 64 * 64;
+    c->J = J;
+    c->JP = (J + 1) & ~1;
+    c->NC = cfg->prior.kind == M2M_PRIOR_FLAT ? 0 : cfg->prior.n[0] * cfg->prior.n[1] * cfg->prior.n[2];
+    c->pcols = c->JP + 2 * c->NC;
+    c->stream = (hipStream_t)cfg->stream;
+    hipError_t e = hipGetDevice(&c->device);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&c->numCU, hipDeviceAttributeMultiprocessorCount, c->device);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&c->max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device);
+    if (e != hipSuccess) {
+        delete c;
+        return fail(nullptr, M2M_ERR_DEVICE, std::string("no usable HIP device: ") + hipGetErrorString(e));
+    }
+    c->launch.threads = c->prec == M2M_F64 ? 256 : 1024;
+    c->launch.ilp = c->prec == M2M_F64 ? 1 : 2;
+    c->launch.blocks_per_cu = 1;
+    c->launch.graph_steps = 0;
+    c->launch.timing = 0;
+    const size_t lds_need = 160 * 1024;
+    if (c->prec == M2M_F64) (void)set_step_lds_limit<double, double>(c->pot_kind, lds_need);
+    else (void)set_step_lds_limit<float, float>(c->pot_kind, lds_need);
+    (void)hipGetLastError();
+    s = c->prec == M2M_F64 ? create_T<double>(c, target, xv, w, device_ptrs)
+                           : create_T<float>(c, target, xv, w, device_ptrs);
+    if (s) {
+        g_create_error = c->msg;
+        m2m_destroy(c);
+        return s;
+    }
+    *out = c;
+    return M2M_OK;
+}
+
+// --------------------------------------------------------------------- step
+static m2m_status sticky(m2m_ctx* c) {
+    if (c->status == M2M_ERR_NONPOSITIVE_WEIGHT || c->status == M2M_ERR_NONFINITE || c->status == M2M_ERR_DEVICE)
+        return c->status;
+    return M2M_OK;
+}
+
+static m2m_status check_flag(m2m_ctx* c, int64_t start) {
+    int flag = 0;
+    long long bad = 0;
+    HIPCHK(c, hipMemcpy(&flag, c->flag, sizeof(int), hipMemcpyDeviceToHost));
+    if (!flag) return M2M_OK;
+    HIPCHK(c, hipMemcpy(&bad, c->bad_step, sizeof(long long), hipMemcpyDeviceToHost));
+    c->step = bad;
+    c->status = (flag & 2) ? M2M_ERR_NONFINITE : M2M_ERR_NONPOSITIVE_WEIGHT;
+    (void)start;
+    return fail(c, c->status, std::string(flag & 2 ? "non-finite weight" : "non-positive weight") +
+                                  " produced by the update of step " + std::to_string(bad) +
+                                  "; the context holds the state at the start of that step");
+}
+
+static bool graphable(const m2m_ctx* c) {
+    return c->launch.graph_steps > 0 && !c->launch.timing &&
+           (c->prior.kind == M2M_PRIOR_FLAT || (c->prior.kind == M2M_PRIOR_HIST && c->prior.period == 1));
+}
+
+static m2m_status build_graph(m2m_ctx* c, int parity) {
+    const int K = (c->launch.graph_steps + 1) & ~1;
+    hipGraph_t g = nullptr;
+    HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+    hipError_t e = hipSuccess;
+    for (int k = 0; k < K && e == hipSuccess; ++k) e = launch_one(c, parity + k);
+    hipError_t e2 = hipStreamEndCapture(c->stream, &g);
+    if (e != hipSuccess || e2 != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return fail(c, M2M_ERR_DEVICE, std::string("graph capture failed: ") + hipGetErrorString(e != hipSuccess ? e : e2));
+    }
+    e = hipGraphInstantiate(&c->graph[parity], g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return fail(c, M2M_ERR_DEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
+    c->graph_k = K;
+    return M2M_OK;
+}
+
+extern "C" m2m_status m2m_step(m2m_ctx* c, int64_t n_steps, m2m_step_stats* last) {
+    if (!c) return fail(nullptr, M2M_ERR_INVALID, "ctx is NULL");
+    if (m2m_status s = sticky(c)) return s;
+    if (n_steps < 0) return fail(c, M2M_ERR_INVALID, "n_steps < 0");
+    const int64_t start = c->step;
+    int64_t left = n_steps;
+    c->last_launches = 0;
+    c->last_kernel_ms = 0;
+    if (graphable(c)) {
+        const int K = (c->launch.graph_steps + 1) & ~1;
+        while (left >= K) {
+            const int par = (int)(c->step & 1);
+            if (!c->graph[par] || c->graph_k != K)
+                if (m2m_status s = build_graph(c, par)) return s;
+            HIPCHK(c, hipGraphLaunch(c->graph[par], c->stream));
+            c->step += K;
+            left -= K;
+        }
+    }
+    if (c->launch.timing && left > 0) {
+        const int64_t nt = std::min<int64_t>(left, 4096);
+        if ((int64_t)c->events.size() < 2 * nt) {
+            while ((int64_t)c->events.size() < 2 * nt) {
+                hipEvent_t ev;
+                HIPCHK(c, hipEventCreate(&ev));
+                c->events.push_back(ev);
+            }
+        }
+        for (int64_t k = 0; k < left; ++k) {
+            hipEvent_t e0 = k < nt ? c->events[2 * k] : nullptr, e1 = k < nt ? c->events[2 * k + 1] : nullptr;
+            HIPCHK(c, launch_one(c, c->step, e0, e1));
+            ++c->step;
+        }
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        double tot = 0;
+        for (int64_t k = 0; k < nt; ++k) {
+            float ms = 0;
+            HIPCHK(c, hipEventElapsedTime(&ms, c->events[2 * k], c->events[2 * k + 1]));
+            tot += ms;
+        }
+        c->last_kernel_ms = tot / nt;
+        c->last_launches = nt;
+        left = 0;
+    }
+    for (; left > 0; --left) {
+        HIPCHK(c, launch_one(c, c->step));
+        ++c->step;
+    }
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (m2m_status s = check_flag(c, start)) return s;
+    if (last && c->step > 0) {
+        const int64_t row = (c->step - 1) % kRing;
+        for (int m = 0; m < c->M; ++m) {
+            StatRow r;
+            HIPCHK(c, hipMemcpy(&r, c->ring + (size_t)m * kRing + row, sizeof(r), hipMemcpyDeviceToHost));
+            std::memcpy(&last[m], &r, sizeof(r));
+        }
+    }
+    return M2M_OK;
+}
+
+extern "C" int64_t m2m_step_index(const m2m_ctx* c) { return c ? c->step : -1; }
+
+// ---------------------------------------------------------------- readbacks
+extern "C" m2m_status m2m_observables(m2m_ctx* c, int32_t model, double* y, double* ys, double* delta, double* chi2) {
+    if (!c) return fail(nullptr, M2M_ERR_INVALID, "ctx is NULL");
+    if (model < 0 || model >= c->M) return fail(c, M2M_ERR_INVALID, "model out of range");
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    const size_t o = (size_t)model * c->J, n = sizeof(double) * c->J;
+    if (y) HIPCHK(c, hipMemcpy(y, c->y + o, n, hipMemcpyDeviceToHost));
+    if (ys) HIPCHK(c, hipMemcpy(ys, c->ys + o, n, hipMemcpyDeviceToHost));
+    if (delta) HIPCHK(c, hipMemcpy(delta, c->delta + o, n, hipMemcpyDeviceToHost));
+    if (chi2) HIPCHK(c, hipMemcpy(chi2, c->chi2 + 2 * model, sizeof(double), hipMemcpyDeviceToHost));
+    return M2M_OK;
+}
+
+static m2m_status copy_rows(m2m_ctx* c, void* dst, int row0, int nrow, int dev) {
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    const size_t ts = tsize(c);
+    const char* src = (const char*)c->state[c->step & 1];
+    for (int k = 0; k < nrow; ++k)
+        HIPCHK(c, hipMemcpy((char*)dst + (size_t)k * c->N * ts, src + (size_t)(row0 + k) * c->stride * ts, c->N * ts,
+                            dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost));
+    return M2M_OK;
+}
+
+extern "C" m2m_status m2m_weights(m2m_ctx* c, void* w_out, int32_t device_ptr) {
+    if (!c || !w_out) return fail(c, M2M_ERR_INVALID, "null argument");
+    return copy_rows(c, w_out, 6, 1, device_ptr);
+}
+
+extern "C" m2m_status m2m_particles(m2m_ctx* c, void* xv_out, int32_t device_ptr) {
+    if (!c || !xv_out) return fail(c, M2M_ERR_INVALID, "null argument");
+    return copy_rows(c, xv_out, 0, 6, device_ptr);
+}
+
+template <typename T>
+static m2m_status gather_T(m2m_ctx* c, void* out, int dev) {
+    if (!c->scratch_n) {
+        if (m2m_status s = dalloc(c, (T**)&c->scratch_n, (size_t)c->stride)) return s;
+    }
+    int wm, acc;
+    prior_modes(c, c->step, &wm, &acc);
+    if (wm == 2) wm = 1;   // a refresh step would compute the table priors
+    GatherArgs<T> a;
+    a.in = (const T*)c->state[c->step & 1];
+    a.stride = c->stride;
+    a.what = (const T*)c->what;
+    a.out = (T*)c->scratch_n;
+    a.tile_model = c->plan.tile_model;
+    a.tile_p0 = c->plan.tile_p0;
+    a.tile_cnt = c->plan.tile_cnt;
+    a.block_tile0 = c->plan.block_tile0;
+    a.pots = (const Pot<T>*)c->pots_d;
+    a.ectab = (const T*)c->ectab;
+    a.erange = (const T*)c->erange;
+    a.flatw = (const T*)c->flatw;
+    a.cellmean = (const T*)c->cellmean;
+    std::memcpy(&a.cells, c->cells_bytes, sizeof(Cells<T>));
+    a.what_mode = wm;
+    HIPCHK(c, launch_gather<T>(a, c->pot_kind, c->plan.nblock, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, hipMemcpy(out, c->scratch_n, sizeof(T) * c->N, dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost));
+    return M2M_OK;
+}
+
+extern "C" m2m_status m2m_priors(m2m_ctx* c, void* what_out, double* cell_mean, int32_t device_ptr) {
+    if (!c) return fail(nullptr, M2M_ERR_INVALID, "ctx is NULL");
+    if (what_out) {
+        m2m_status s = c->prec == M2M_F64 ? gather_T<double>(c, what_out, device_ptr) : gather_T<float>(c, what_out, device_ptr);
+        if (s) return s;
+    }
+    if (cell_mean) {
+        if (c->NC == 0) return fail(c, M2M_ERR_INVALID, "flat prior has no cell table");
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        HIPCHK(c, hipMemcpy(cell_mean, c->cellmean64, sizeof(double) * c->M * c->NC, hipMemcpyDeviceToHost));
+    }
+    return M2M_OK;
+}
+
+extern "C" m2m_status m2m_history(m2m_ctx* c, m2m_step_stats* out, int64_t max_rows, int64_t* n_rows) {
+    if (!c || !out || !n_rows || max_rows < 0) return fail(c, M2M_ERR_INVALID, "null argument");
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    const int64_t have = std::min<int64_t>(c->step, kRing);
+    const int64_t per = std::min<int64_t>(have, max_rows / c->M);
+    std::vector<StatRow> ring((size_t)c->M * kRing);
+    HIPCHK(c, hipMemcpy(ring.data(), c->ring, sizeof(StatRow) * ring.size(), hipMemcpyDeviceToHost));
+    int64_t k = 0;
+    for (int64_t s = c->step - per; s < c->step; ++s)
+        for (int m = 0; m < c->M; ++m) std::memcpy(&out[k++], &ring[(size_t)m * kRing + s % kRing], sizeof(StatRow));
+    *n_rows = k;
+    return M2M_OK;
+}
+
+// ------------------------------------------------------------- launch shape
+extern "C" m2m_status m2m_get_launch(const m2m_ctx* c, m2m_launch* out) {
+    if (!c || !out) return M2M_ERR_INVALID;
+    *out = c->launch;
+    return M2M_OK;
+}
+
+static m2m_status apply_launch(m2m_ctx* c, const m2m_launch& L) {
+    const int tmax = c->prec == M2M_F64 ? 256 : 1024;
+    if (L.threads < 64 || L.threads > tmax || L.threads % 64 || (L.ilp != 1 && L.ilp != 2 && L.ilp != 4) ||
+        L.blocks_per_cu < 1 || L.blocks_per_cu > 64 || L.graph_steps < 0 || L.graph_steps > 100000)
+        return fail(c, M2M_ERR_INVALID, "launch shape out of range");
+    const bool replan = L.threads != c->plan.threads || L.ilp != c->plan.ilp || L.blocks_per_cu != c->plan.bpc;
+    c->launch = L;
+    if (replan) return make_plan(c, L.threads, L.ilp, L.blocks_per_cu);
+    for (int k = 0; k < 2; ++k)
+        if (c->graph[k]) { (void)hipGraphExecDestroy(c->graph[k]); c->graph[k] = nullptr; }
+    return M2M_OK;
+}
+
+extern "C" m2m_status m2m_set_launch(m2m_ctx* c, const m2m_launch* in) {
+    if (!c || !in) return fail(c, M2M_ERR_INVALID, "null argument");
+    if (m2m_status s = sticky(c)) return s;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return apply_launch(c, *in);
+}
+
+extern "C" m2m_status m2m_kernel_time(const m2m_ctx* c, double* ms, int64_t* launches) {
+    if (!c || !ms || !launches) return M2M_ERR_INVALID;
+    *ms = c->last_kernel_ms;
+    *launches = c->last_launches;
+    return M2M_OK;
+}
+
+// ---------------------------------------------------------------- autotune
+namespace {
+struct Snapshot {
+    std::vector<std::pair<void*, void*>> bufs;   // (live, copy)
+    std::vector<size_t> sizes;
+};
+}  // namespace
+
+static m2m_status snapshot(m2m_ctx* c, Snapshot& s, bool restore) {
+    const size_t ts = tsize(c);
+    const size_t MJ = (size_t)c->M * c->J, MC = (size_t)c->M * std::max(1, c->NC);
+    struct Item { void* p; size_t n; };
+    std::vector<Item> items = {{c->state[c->step & 1], 7 * (size_t)c->stride * ts},
+                               {c->ys, MJ * 8}, {c->y, MJ * 8}, {c->delta, MJ * 8}, {c->cvec, MJ * ts},
+                               {c->cellmean, MC * ts}, {c->cellmean64, MC * 8}, {c->chi2, 2 * (size_t)c->M * 8},
+                               {c->ring, sizeof(StatRow) * (size_t)c->M * kRing}, {c->d_step, 8}};
+    if (c->what) items.push_back({c->what, (size_t)c->stride * ts});
+    if (!restore) {
+        for (auto& it : items) {
+            void* cp = nullptr;
+            if (hipMalloc(&cp, it.n) != hipSuccess) {
+                (void)hipGetLastError();
+                for (auto& b : s.bufs) (void)hipFree(b.second);
+                s.bufs.clear();
+                return fail(c, M2M_ERR_NOMEM, "autotune snapshot allocation failed");
+            }
+            HIPCHK(c, hipMemcpy(cp, it.p, it.n, hipMemcpyDeviceToDevice));
+            s.bufs.push_back({it.p, cp});
+            s.sizes.push_back(it.n);
+        }
+    } else {
+        for (size_t k = 0; k < s.bufs.size(); ++k)
+            HIPCHK(c, hipMemcpy(s.bufs[k].first, s.bufs[k].second, s.sizes[k], hipMemcpyDeviceToDevice));
+        HIPCHK(c, hipMemset(c->flag, 0, sizeof(int)));
+    }
+    return M2M_OK;
+}
+
+static std::string tune_key(const m2m_ctx* c) {
+    char buf[256];
+    snprintf(buf, sizeof buf, "gfx950|p%d|k%d|N%lld|M%d|J%d|C%d|P%d", c->prec, c->pot_kind, (long long)c->N, c->M, c->J,
+             c->NC, c->prior.kind);
+    return buf;
+}
+
+static bool cache_lookup(const std::string& key, m2m_launch* L) {
+    const char* path = std::getenv("M2M_AUTOTUNE_CACHE");
+    if (!path) return false;
+    FILE* f = std::fopen(path, "r");
+    if (!f) return false;
+    char line[512];
+    bool found = false;
+    while (std::fgets(line, sizeof line, f)) {
+        // one JSON object per line: {"key": "...", "threads": T, "ilp": I, "blocks_per_cu": B}
+        char k[256];
+        int t, i, b;
+        if (std::sscanf(line, " {\"key\": \"%255[^\"]\", \"threads\": %d, \"ilp\": %d, \"blocks_per_cu\": %d", k, &t, &i, &b) == 4 &&
+            key == k) {
+            L->threads = t;
+            L->ilp = i;
+            L->blocks_per_cu = b;
+            found = true;
+        }
+    }
+    std::fclose(f);
+    return found;
+}
+
+static void cache_store(const std::string& key, const m2m_launch& L) {
+    const char* path = std::getenv("M2M_AUTOTUNE_CACHE");
+    if (!path) return;
+    FILE* f = std::fopen(path, "a");
+    if (!f) return;
+    std::fprintf(f, "{\"key\": \"%s\", \"threads\": %d, \"ilp\": %d, \"blocks_per_cu\": %d}\n", key.c_str(), L.threads, L.ilp,
+                 L.blocks_per_cu);
+    std::fclose(f);
+}
+
+extern "C" m2m_status m2m_autotune(m2m_ctx* c, int32_t trial_steps, m2m_launch* chosen) {
+    if (!c) return fail(nullptr, M2M_ERR_INVALID, "ctx is NULL");
+    if (m2m_status s = sticky(c)) return s;
+    if (trial_steps < 1) return fail(c, M2M_ERR_INVALID, "trial_steps must be >= 1");
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    const m2m_launch keep = c->launch;
+    m2m_launch best = keep;
+    const std::string key = tune_key(c);
+    if (!cache_lookup(key, &best)) {
+        Snapshot snap;
+        if (m2m_status s = snapshot(c, snap, false)) return s;
+        const int64_t step0 = c->step;
+        double best_ms = INFINITY;
+        std::vector<int> threads = c->prec == M2M_F64 ? std::vector<int>{64, 128, 256} : std::vector<int>{256, 512, 1024};
+        hipEvent_t e0, e1;
+        HIPCHK(c, hipEventCreate(&e0));
+        HIPCHK(c, hipEventCreate(&e1));
+        m2m_status err = M2M_OK;
+        for (int t : threads)
+            for (int ilp : {1, 2, 4})
+                for (int bpc : {1, 2, 4}) {
+                    m2m_launch L = keep;
+                    L.threads = t;
+                    L.ilp = ilp;
+                    L.blocks_per_cu = bpc;
+                    L.graph_steps = 0;
+                    L.timing = 0;
+                    if ((err = apply_launch(c, L))) {
+                        if (err == M2M_ERR_UNSUPPORTED) { err = M2M_OK; continue; }
+                        goto done;
+                    }
+                    (void)launch_one(c, c->step);   // warm-up
+                    ++c->step;
+                    if (hipEventRecord(e0, c->stream) != hipSuccess) { err = fail(c, M2M_ERR_DEVICE, "event"); goto done; }
+                    for (int k = 0; k < trial_steps; ++k) { (void)launch_one(c, c->step); ++c->step; }
+                    (void)hipEventRecord(e1, c->stream);
+                    (void)hipEventSynchronize(e1);
+                    float ms = 0;
+                    (void)hipEventElapsedTime(&ms, e0, e1);
+                    int flag = 0;
+                    (void)hipMemcpy(&flag, c->flag, sizeof(int), hipMemcpyDeviceToHost);
+                    if (!flag && ms < best_ms) { best_ms = ms; best = L; }
+                    if ((err = snapshot(c, snap, true))) goto done;
+                    c->step = step0;
+                }
+    done:
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        for (auto& b : snap.bufs) (void)hipFree(b.second);
+        c->step = step0;
+        if (err) return err;
+        cache_store(key, best);
+    }
+    best.graph_steps = keep.graph_steps;
+    best.timing = keep.timing;
+    if (m2m_status s = apply_launch(c, best)) return s;
+    if (chosen) *chosen = c->launch;
+    return M2M_OK;
+}
+
+// ------------------------------------------------------------------ destroy
+extern "C" void m2m_destroy(m2m_ctx* c) {
+    if (!c) return;
+    if (c->stream || true) (void)hipStreamSynchronize(c->stream);
+    for (int k = 0; k < 2; ++k)
+        if (c->graph[k]) (void)hipGraphExecDestroy(c->graph[k]);
+    for (hipEvent_t e : c->events) (void)hipEventDestroy(e);
+    for (void* p : c->allocs) (void)hipFree(p);
+    delete c;
+}
+
+extern "C" const char* m2m_last_error(const m2m_ctx* c) {
+    return c ? c->msg.c_str() : g_create_error.c_str();
+}

@@ -1,0 +1,84 @@
+// internal.h -- host-side context of the C ABI (not exported).
+#pragma once
+#include <string>
+#include <vector>
+
+#include "m2m.h"
+#include "runtime.h"
+
+// Launch plan: tiles of threads * ilp particles (never straddling a model),
+// contiguous tile ranges per block, one partial slot per (block, model) pair,
+// and the column chunks of the finalise kernel.
+struct Plan {
+    int threads = 0, ilp = 0, bpc = 0;
+    int64_t ntile = 0;
+    int nblock = 0, nslot = 0, nchunk = 0, nsplit = 0;
+    size_t lds = 0;
+    int32_t* tile_model = nullptr;
+    int64_t* tile_p0 = nullptr;
+    int32_t* tile_cnt = nullptr;
+    int32_t* block_tile0 = nullptr;
+    int32_t* block_slot0 = nullptr;
+    int32_t* model_slot = nullptr;
+    int32_t* chunk_model = nullptr;
+    int32_t* chunk_col0 = nullptr;
+    int32_t* chunk_ncol = nullptr;
+    int32_t* model_chunk = nullptr;
+    void* part = nullptr;
+    double* seg_stats = nullptr;
+    double* l2 = nullptr;
+    int* chunk_cnt = nullptr;
+    double* chunk_chi = nullptr;
+    int* model_cnt = nullptr;
+    int* all_cnt = nullptr;
+    double* erange_out = nullptr;
+};
+
+struct m2m_ctx {
+    // configuration
+    int prec = 0, update = 1, frozen = 0;
+    double dt = 0, eps = 0, mu = 0, tau = 0;
+    int M = 0, pot_kind = 0;
+    std::vector<int64_t> off;
+    std::vector<m2m_potential> pots;
+    m2m_prior prior{};
+    m2m_obs_layout lay{};
+    std::vector<double> edges_host[M2M_MAX_BINNINGS];
+    std::vector<double> erange_host;
+    int64_t N = 0, stride = 0;
+    int J = 0, JP = 0, NC = 0, pcols = 0, nedge = 0;
+    alignas(16) unsigned char lay_bytes[sizeof(m2m::Layout<double>)] = {};
+    alignas(16) unsigned char cells_bytes[sizeof(m2m::Cells<double>)] = {};
+    // device
+    hipStream_t stream = nullptr;
+    int device = 0, numCU = 0, max_lds = 0;
+    void* state[2] = {nullptr, nullptr};
+    void* what = nullptr;
+    void* pots_d = nullptr;
+    void* ectab = nullptr;
+    void* erange = nullptr;
+    void* flatw = nullptr;
+    void* cvec = nullptr;
+    void* cellmean = nullptr;
+    void* edges = nullptr;
+    void* scratch_n = nullptr;
+    double *Y = nullptr, *sigma = nullptr, *y = nullptr, *ys = nullptr, *delta = nullptr;
+    double* cellmean64 = nullptr;
+    double* chi2 = nullptr;
+    m2m::StatRow* ring = nullptr;
+    int* flag = nullptr;
+    long long* bad_step = nullptr;
+    long long* d_step = nullptr;
+    Plan plan;
+    std::vector<void*> allocs;
+    // host state
+    int64_t step = 0;
+    m2m_status status = M2M_OK;
+    std::string msg;
+    m2m_launch launch{};
+    hipGraphExec_t graph[2] = {nullptr, nullptr};
+    int graph_k = 0;
+    std::vector<hipEvent_t> events;
+    double last_kernel_ms = 0;
+    int64_t last_launches = 0;
+};

@@ -1,0 +1,130 @@
+// runtime.h -- kernel argument blocks and launch helpers shared by the
+// library's translation units (never exported through the C ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "device.h"
+
+namespace m2m {
+
+constexpr int kRing = 4096;   // statistics rows kept per model
+
+struct StatRow {
+    double chi2, chi2_inst, S, F, sum_w, min_w, sum_w2, n_eff;
+    long long step;
+    int32_t model, reserved;
+};
+
+// Fused step: update + push + observe + prior cells (one particle pass).
+template <typename T, typename PT>
+struct StepArgs {
+    const T* in;            // 7 * stride: x y z vx vy vz w (state at step n)
+    T* out;                 // 7 * stride: state at step n+1
+    int64_t stride;
+    T* what;                // per-particle priors (stored modes)
+    const int32_t* tile_model;
+    const int64_t* tile_p0;
+    const int32_t* tile_cnt;
+    const int32_t* block_tile0;   // nblocks + 1
+    const int32_t* block_slot0;   // first partial slot of each block
+    const Pot<T>* pots;           // per model
+    const T* ectab;               // 128 per model (Hernquist+NFW)
+    const T* erange;              // 2 per model
+    const T* flatw;               // per model
+    const T* cvec;                // M * J: Dt_j / sigma_j
+    const T* cellmean;            // M * NC
+    PT* part;                     // nslot * pcols
+    double* seg_stats;            // nslot * 4
+    const T* edges;
+    int32_t nedge;
+    int32_t pcols, jpad;
+    Layout<T> lay;
+    Cells<T> cells;
+    T dt, eps, mu;
+    int32_t update, frozen;
+    int32_t mode;                 // 0 step, 1 observe only
+    int32_t what_mode;            // 0 flat, 1 table, 2 table + store, 3 stored
+    int32_t accum_cells;
+    int* flag;
+    long long* bad_step;
+    const long long* d_step;
+};
+
+template <typename T, typename PT>
+struct FinArgs {
+    const PT* part;
+    int32_t pcols, jpad, J, ncell, n_models;
+    const int32_t* chunk_model;
+    const int32_t* chunk_col0;
+    const int32_t* chunk_ncol;
+    const int32_t* model_slot;    // M + 1
+    const int32_t* model_chunk;   // M + 1
+    double* l2;                   // nchunk * nsplit * 256
+    int* chunk_cnt;
+    double* chunk_chi;            // 2 * nchunk
+    int* model_cnt;
+    int* all_cnt;
+    const double* Y;
+    const double* sigma;
+    double* y;
+    double* ys;
+    double* delta;
+    T* cvec;
+    T* cellmean;
+    double* cellmean64;
+    double* chi2;                 // 2 * M: chi2, chi2_inst of the current state
+    const double* seg_stats;
+    StatRow* ring;
+    double g, mu;
+    int32_t first, accum_cells;
+    const int* flag;
+    long long* d_step;
+};
+
+template <typename T>
+struct ErangeArgs {
+    const T* in;
+    int64_t stride;
+    const int32_t* tile_model;
+    const int64_t* tile_p0;
+    const int32_t* tile_cnt;
+    const int32_t* block_tile0;
+    const int32_t* block_slot0;
+    const Pot<T>* pots;
+    double* out;   // 2 * nslot
+};
+
+// Priors a step would use, per particle (readback).
+template <typename T>
+struct GatherArgs {
+    const T* in;
+    int64_t stride;
+    const T* what;
+    T* out;
+    const int32_t* tile_model;
+    const int64_t* tile_p0;
+    const int32_t* tile_cnt;
+    const int32_t* block_tile0;
+    const Pot<T>* pots;
+    const T* ectab;
+    const T* erange;
+    const T* flatw;
+    const T* cellmean;
+    Cells<T> cells;
+    int32_t what_mode;
+};
+
+template <typename T, typename PT>
+hipError_t launch_step(const StepArgs<T, PT>& a, int pot_kind, int ilp, int blocks, int threads, size_t lds,
+                       hipStream_t s);
+template <typename T, typename PT>
+hipError_t set_step_lds_limit(int pot_kind, size_t lds);
+template <typename T, typename PT>
+hipError_t launch_finalize(const FinArgs<T, PT>& a, int nchunk, int nsplit, hipStream_t s);
+template <typename T>
+hipError_t launch_erange(const ErangeArgs<T>& a, int pot_kind, int blocks, hipStream_t s);
+template <typename T>
+hipError_t launch_gather(const GatherArgs<T>& a, int pot_kind, int blocks, hipStream_t s);
+
+}  // namespace m2m

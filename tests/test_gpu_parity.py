@@ -1,0 +1,223 @@
+"""GPU parity of the fused M2M step (C ABI, HIP path) against the FP64 oracle.
+
+Bars (derived in the design doc):
+  FP64 path: every output within 1e-11 relative of the oracle after one step and
+             within 1e-8 after 50 steps (rounding order only).
+  FP32 path: one step -- weights and coordinates within 1e-6 relative (coordinates
+             absolute 1e-6 * scale), observables within 1e-6 of sum |w K| except bins
+             explained by particles within 1e-5 of a bin edge, chi^2 within 1e-6
+             relative; end of run -- chi^2 and the binned observables within 1e-3.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from synth import configs
+from tests import helpers as H
+
+pytestmark = pytest.mark.gpu
+
+m2m = pytest.importorskip("paper_1207_6403_amd")
+
+
+def run_both(cfg, nsteps, launch=None, er=None):
+    inp = H.inputs(cfg)
+    er = H.erange(cfg, inp) if er is None else er
+    H.flush("case %s N=%d steps=%d launch=%s" % (cfg["name"], cfg["N"], nsteps, launch))
+    ctx = m2m.m2m_create(cfg, inp["ics"], inp["w"], inp["Y"], inp["sigma"], Erange=er)
+    if launch:
+        m2m.m2m_set_launch(ctx, **launch)
+    ors = H.oracle_models(cfg, inp, er)
+    return inp, ctx, ors
+
+
+def test_prologue_observables_fp64():
+    cfg = configs.cfg1(N=3000)
+    inp, ctx, (om,) = run_both(cfg, 0)
+    obs = m2m.m2m_observables(ctx, 0)
+    y0 = om.observe()
+    np.testing.assert_allclose(obs["y"], y0, rtol=1e-12, atol=1e-18)
+    np.testing.assert_array_equal(obs["y_smooth"], obs["y"])
+    chi2 = np.sum(((y0 - inp["Y"]) / inp["sigma"]) ** 2)
+    assert obs["chi2"] == pytest.approx(chi2, rel=1e-12)
+    what, cells = m2m.m2m_priors(ctx)
+    o_what, o_cs, o_cn = om.prior_means()
+    np.testing.assert_allclose(what, o_what, rtol=1e-12)
+    np.testing.assert_allclose(cells[0], np.where(o_cn > 0, o_cs / np.maximum(o_cn, 1), 0), rtol=1e-12)
+
+
+@pytest.mark.parametrize("nsteps", [1, 2, 50])
+def test_cfg1_fp64_matches_oracle(nsteps):
+    cfg = configs.cfg1(N=5000)
+    inp, ctx, (om,) = run_both(cfg, nsteps)
+    st = m2m.m2m_step(ctx, nsteps)[0]
+    ost = om.run(nsteps)[-1]
+    tol = 1e-11 if nsteps <= 2 else 1e-8
+    np.testing.assert_allclose(m2m.m2m_weights(ctx), om.w, rtol=tol)
+    np.testing.assert_allclose(m2m.m2m_particles(ctx), om.ics(), rtol=tol, atol=tol)
+    for k, name in enumerate(["chi2", "chi2_inst", "S", "F", "sum_w", "min_w", "sum_w2"]):
+        assert st[name] == pytest.approx(ost[k], rel=tol, abs=1e-300), name
+    assert st["step"] == nsteps - 1
+    # the context already observed the state of step nsteps; the oracle observes it
+    # at the start of its next step
+    obs = m2m.m2m_observables(ctx, 0)
+    y_next = om.observe()
+    np.testing.assert_allclose(obs["y"], y_next, rtol=max(tol, 1e-10), atol=1e-18)
+    assert m2m.m2m_step_index(ctx) == nsteps
+
+
+def test_cfg2_fp32_single_step():
+    cfg = configs.cfg2(N=50000, target_n=1 << 18)
+    inp, ctx, (om,) = run_both(cfg, 1)
+    m2m.m2m_step(ctx, 1)
+    om.run(1)
+    wg = m2m.m2m_weights(ctx).astype(np.float64)
+    np.testing.assert_allclose(wg, om.w, rtol=1e-6)
+    xg = m2m.m2m_particles(ctx).astype(np.float64)
+    xo = om.ics()
+    np.testing.assert_allclose(xg, xo, rtol=1e-6, atol=1e-6 * np.abs(xo).max())
+    obs = m2m.m2m_observables(ctx, 0)
+    y1 = om.observe()
+    amb = H.edge_distance(cfg["layout"], xo) < 1e-5
+    scale = H.moment_scale(cfg, xo, om.w)
+    wk = np.max(np.abs(om.w[amb]) * (1 + np.sum(xo[3:5, amb] ** 2, axis=0))) if amb.any() else 0.0
+    H.compare_observables(obs["y"], y1, scale, int(amb.sum()), wk, 1e-6)
+
+
+@pytest.mark.parametrize("launch", [{"threads": 256, "ilp": 1, "blocks_per_cu": 1},
+                                    {"threads": 1024, "ilp": 4, "blocks_per_cu": 1},
+                                    {"threads": 512, "ilp": 2, "blocks_per_cu": 4}])
+def test_cfg2_fp32_launch_shapes_agree(launch):
+    """Ragged tiles (N = 40,007 is not a multiple of any tile) in several launch shapes."""
+    cfg = configs.cfg2(N=40007, target_n=1 << 18)
+    inp, ctx, (om,) = run_both(cfg, 3, launch=launch)
+    st = m2m.m2m_step(ctx, 3)[0]
+    ost = om.run(3)[-1]
+    np.testing.assert_allclose(m2m.m2m_weights(ctx).astype(np.float64), om.w, rtol=2e-6)
+    assert st["chi2"] == pytest.approx(ost[0], rel=2e-6)
+    assert st["S"] == pytest.approx(ost[2], rel=1e-4, abs=1e-9)
+    assert st["sum_w"] == pytest.approx(ost[4], rel=1e-6)
+
+
+def test_cfg2_fp32_end_of_run():
+    """200 steps of N = 2e4: chi^2 and the observables within 1e-3 of the FP64 oracle."""
+    cfg = configs.cfg2(N=20000, target_n=1 << 18)
+    inp, ctx, (om,) = run_both(cfg, 200)
+    st = m2m.m2m_step(ctx, 200)[0]
+    ost = om.run(200)[-1]
+    assert st["chi2"] == pytest.approx(ost[0], rel=1e-3)
+    obs = m2m.m2m_observables(ctx, 0)
+    ys_o = om.arr["ys"]
+    scale = H.moment_scale(cfg, om.ics(), om.w)
+    big = scale > 1e-3 * scale.max()
+    err = np.abs(obs["y_smooth"] - ys_o)[big] / scale[big]
+    assert np.percentile(err, 99) < 1e-3 and err.max() < 1e-2
+
+
+def test_cfg1_fp64_full_run_chi2():
+    """cfg 1 at its full size and length (N = 20,000, 2000 steps): chi^2 of the FP64 GPU
+    path within 1e-6 of the oracle, the final weights within 1e-6."""
+    cfg = configs.cfg1()
+    inp, ctx, (om,) = run_both(cfg, 2000)
+    st = m2m.m2m_step(ctx, 2000)[0]
+    ost = om.run(2000)[-1]
+    assert st["chi2"] == pytest.approx(ost[0], rel=1e-6)
+    np.testing.assert_allclose(m2m.m2m_weights(ctx), om.w, rtol=1e-6)
+
+
+def test_cfg2_full_size_one_step():
+    """N = 2^20 in the benchmark's launch shape: one step against the oracle."""
+    cfg = configs.cfg2()
+    inp, ctx, (om,) = run_both(cfg, 1, launch={"threads": 1024, "ilp": 4, "blocks_per_cu": 1})
+    st = m2m.m2m_step(ctx, 1)[0]
+    ost = om.run(1)[-1]
+    np.testing.assert_allclose(m2m.m2m_weights(ctx).astype(np.float64), om.w, rtol=1e-6)
+    assert st["chi2"] == pytest.approx(ost[0], rel=1e-6)
+    obs = m2m.m2m_observables(ctx, 0)
+    chi2_next = np.sum(((om.observe() - inp["Y"]) / inp["sigma"]) ** 2)
+    assert obs["chi2"] == pytest.approx(chi2_next, rel=1e-5)
+
+
+def test_nonpositive_weight_keeps_last_state():
+    cfg = configs.cfg1(N=2000)
+    cfg.update(update="euler", eps=1.0)
+    inp, ctx, (om,) = run_both(cfg, 1)
+    with pytest.raises(m2m.M2MError) as e:
+        m2m.m2m_step(ctx, 3)
+    assert e.value.status == 4
+    assert m2m.m2m_step_index(ctx) == 0
+    np.testing.assert_array_equal(m2m.m2m_weights(ctx), inp["w"])
+    with pytest.raises(m2m.M2MError):
+        m2m.m2m_step(ctx, 1)
+
+
+def test_batched_models_match_oracle():
+    cfg = configs.cfg4(n_models=5, nmin=1500, nmax=6000, steps=4)
+    inp, ctx, ors = run_both(cfg, 4, launch={"threads": 256, "ilp": 2, "blocks_per_cu": 1})
+    rows = m2m.m2m_step(ctx, 4)
+    offs = np.concatenate([[0], np.cumsum(cfg["model_sizes"])])
+    wg = m2m.m2m_weights(ctx).astype(np.float64)
+    for m, om in enumerate(ors):
+        ost = om.run(4)[-1]
+        np.testing.assert_allclose(wg[offs[m]:offs[m + 1]], om.w, rtol=2e-6)
+        assert rows[m]["chi2"] == pytest.approx(ost[0], rel=2e-6)
+        assert rows[m]["model"] == m
+
+
+def test_frozen_entropy_recurrence_gpu():
+    """Frozen particles, one prior cell, chi^2 off: w_n = w_0 exp(-eps dt mu n) (FP64)."""
+    cfg = configs.cfg1(N=700)
+    cfg.update(frozen=True, eps=0.05, mu=0.5)
+    cfg["prior"] = {"kind": "hist", "axes": ("E", "L/Lc"), "shape": (1, 1), "period": 1}
+    inp = H.inputs(cfg)
+    ctx = m2m.m2m_create(cfg, inp["ics"], inp["w"], inp["Y"], np.full(50, 1e300), Erange=np.array([-1.0, 0.0]))
+    m2m.m2m_step(ctx, 40)
+    a = cfg["eps"] * cfg["dt"] * cfg["mu"]
+    np.testing.assert_allclose(m2m.m2m_weights(ctx), np.exp(-a * 40) / 700, rtol=1e-13)
+
+
+def test_single_particle_and_empty_bins():
+    """N = 1 (one ragged tile, most bins empty) in FP32 and FP64."""
+    for prec in ("f64", "f32"):
+        cfg = configs.cfg1(N=1)
+        cfg["precision"] = prec
+        ics = np.array([[0.3], [0.1], [0.2], [0.1], [-0.2], [0.3]])
+        w = np.array([1.0])
+        inp = configs.make_inputs(configs.cfg1(N=10))
+        ctx = m2m.m2m_create(cfg, ics, w, inp["Y"], inp["sigma"], Erange=np.array([-1.0, 0.0]))
+        st = m2m.m2m_step(ctx, 2)[0]
+        om = oracle.Model(cfg, ics, w, inp["Y"], inp["sigma"], Erange=(-1.0, 0.0))
+        ost = om.run(2)[-1]
+        tol = 1e-11 if prec == "f64" else 2e-6
+        assert st["chi2"] == pytest.approx(ost[0], rel=tol)
+        np.testing.assert_allclose(m2m.m2m_weights(ctx).astype(np.float64), om.w, rtol=tol)
+
+
+def test_graphs_match_direct_launches():
+    cfg = configs.cfg2(N=30000, target_n=1 << 16)
+    inp = H.inputs(cfg)
+    er = H.erange(cfg, inp)
+    a = m2m.m2m_create(cfg, inp["ics"], inp["w"], inp["Y"], inp["sigma"], Erange=er)
+    b = m2m.m2m_create(cfg, inp["ics"], inp["w"], inp["Y"], inp["sigma"], Erange=er)
+    m2m.m2m_set_launch(b, graph_steps=8)
+    sa = m2m.m2m_step(a, 21)[0]
+    sb = m2m.m2m_step(b, 21)[0]
+    assert sb["step"] == sa["step"] == 20
+    np.testing.assert_allclose(m2m.m2m_weights(b), m2m.m2m_weights(a), rtol=1e-6)
+    assert sb["chi2"] == pytest.approx(sa["chi2"], rel=1e-6)
+    hist = m2m.m2m_history(b)
+    assert [r["step"] for r in hist] == list(range(21))
+
+
+def test_autotune_restores_state():
+    cfg = configs.cfg2(N=30000, target_n=1 << 16)
+    inp = H.inputs(cfg)
+    er = H.erange(cfg, inp)
+    a = m2m.m2m_create(cfg, inp["ics"], inp["w"], inp["Y"], inp["sigma"], Erange=er)
+    m2m.m2m_step(a, 2)
+    w_before = m2m.m2m_weights(a).copy()
+    chosen = m2m.m2m_autotune(a, 3)
+    assert chosen["threads"] in (256, 512, 1024)
+    np.testing.assert_array_equal(m2m.m2m_weights(a), w_before)
+    assert m2m.m2m_step_index(a) == 2
+    m2m.m2m_step(a, 1)
