@@ -252,8 +252,8 @@ static m2m_status make_plan(m2m_ctx* c, int threads, int ilp, int bpc) {
     // LDS of the fused kernel: histograms, cell sums/counts, update table,
     // cell means, edges, reduction scratch
     const size_t ts = tsize(c);
-    const int NCe = (c->NC + 1) & ~1;
-    p.lds = 8 * (size_t)c->JP + 8 * (size_t)c->NC + 4 * (size_t)NCe + ts * ((size_t)c->JP + NCe + ((c->nedge + 1) & ~1)) + 8 * 4 * 16;
+    const int NCe = (c->NC + 1) & ~1, NE = (c->nedge + 1) & ~1;
+    p.lds = 8 * ((size_t)c->JP + c->NC + NE + 64) + 4 * (size_t)NCe + ts * ((size_t)c->JP + NCe + NE + kLcTab);
     p.lds = (p.lds + 15) & ~(size_t)15;
     if (p.lds > (size_t)c->max_lds)
         return fail(c, M2M_ERR_UNSUPPORTED, "layout needs " + std::to_string(p.lds) + " bytes of LDS per block (max " +
@@ -262,6 +262,15 @@ static m2m_status make_plan(m2m_ctx* c, int threads, int ilp, int bpc) {
 }
 
 // --------------------------------------------------------------- launches
+static Exact exact_tables(const m2m_ctx* c) {
+    Exact e;
+    e.pots = (const Pot<double>*)c->pots64;
+    e.lctab = c->lctab64;
+    e.erange = c->erange64;
+    e.edges = c->edges64;
+    return e;
+}
+
 template <typename T>
 static void fill_step_args(m2m_ctx* c, StepArgs<T, T>& a, int parity, int mode, int what_mode, int accum) {
     const Plan& p = c->plan;
@@ -275,7 +284,7 @@ static void fill_step_args(m2m_ctx* c, StepArgs<T, T>& a, int parity, int mode, 
     a.block_tile0 = p.block_tile0;
     a.block_slot0 = p.block_slot0;
     a.pots = (const Pot<T>*)c->pots_d;
-    a.ectab = (const T*)c->ectab;
+    a.lctab = (const T*)c->lctab;
     a.erange = (const T*)c->erange;
     a.flatw = (const T*)c->flatw;
     a.cvec = (const T*)c->cvec;
@@ -287,7 +296,8 @@ static void fill_step_args(m2m_ctx* c, StepArgs<T, T>& a, int parity, int mode, 
     a.pcols = c->pcols;
     a.jpad = c->JP;
     std::memcpy(&a.lay, c->lay_bytes, sizeof(Layout<T>));
-    std::memcpy(&a.cells, c->cells_bytes, sizeof(Cells<T>));
+    a.cells = c->cells;
+    a.ex = exact_tables(c);
     a.dt = (T)c->dt;
     a.eps = (T)c->eps;
     a.mu = (T)c->mu;
@@ -412,34 +422,44 @@ static m2m_status derive_erange_T(m2m_ctx* c, std::vector<double>& er) {
 }
 
 // ---------------------------------------------------------- host-side tables
-template <typename T>
-static void build_tables(m2m_ctx* c, std::vector<unsigned char>& pots, std::vector<T>& ectab) {
-    pots.assign(sizeof(Pot<T>) * c->M, 0);
-    ectab.assign(128 * (size_t)c->M, T(0));
+// Potential parameters in precision X, and the circular-orbit energies
+// E_c(r_k) = Phi(r_k) + r_k Phi'(r_k)/2 at kLcTab radii r_k = 1e-8 10^(16 k/(kLcTab-1))
+// (equatorial plane; logarithmic and Hernquist + NFW models).
+template <typename X>
+static void build_tables(const m2m_ctx* c, std::vector<unsigned char>& pots, std::vector<X>& lctab) {
+    pots.assign(sizeof(Pot<X>) * c->M, 0);
+    lctab.assign((size_t)kLcTab * c->M, X(0));
     for (int m = 0; m < c->M; ++m) {
         const m2m_potential& q = c->pots[m];
-        Pot<T> p{};
+        Pot<X> p{};
         p.kind = q.kind;
-        p.lc_off = 128 * m;
-        p.GM = (T)(q.G * q.M);
-        p.a = (T)q.a;
-        p.v2 = (T)(q.v0 * q.v0);
-        p.Rc2 = (T)(q.Rc * q.Rc);
-        p.iq2 = q.q > 0 ? (T)(1.0 / (q.q * q.q)) : T(0);
-        p.GMh = q.kind == M2M_POT_HERNQUIST_NFW ? (T)(q.G * q.Mh) : T(0);
-        p.rs = q.rs > 0 ? (T)q.rs : T(1);
-        p.irs = q.rs > 0 ? (T)(1.0 / q.rs) : T(1);
-        std::memcpy(pots.data() + sizeof(Pot<T>) * m, &p, sizeof(p));
-        // circular-orbit energies E_c(r) = Phi + r Phi'/2 at 128 log radii (Hernquist + NFW)
-        for (int k = 0; k < 128; ++k) {
-            const double r = 1e-4 * std::pow(10.0, 8.0 * k / 127.0);
-            double phi = -q.G * q.M / (r + q.a), d1 = q.G * q.M / ((r + q.a) * (r + q.a));
-            if (q.kind == M2M_POT_HERNQUIST_NFW && q.Mh > 0) {
-                const double l1 = std::log1p(r / q.rs);
-                phi += -q.G * q.Mh * l1 / r;
-                d1 += q.G * q.Mh * (l1 / (r * r) - 1.0 / (r * (r + q.rs)));
+        p.lc_off = kLcTab * m;
+        p.GM = (X)(q.G * q.M);
+        p.a = (X)q.a;
+        p.v2 = (X)(q.v0 * q.v0);
+        p.Rc2 = (X)(q.Rc * q.Rc);
+        p.iq2 = q.q > 0 ? (X)(1.0 / (q.q * q.q)) : X(0);
+        p.GMh = q.kind == M2M_POT_HERNQUIST_NFW ? (X)(q.G * q.Mh) : X(0);
+        p.rs = q.rs > 0 ? (X)q.rs : X(1);
+        p.irs = q.rs > 0 ? (X)(1.0 / q.rs) : X(1);
+        std::memcpy(pots.data() + sizeof(Pot<X>) * m, &p, sizeof(p));
+        for (int k = 0; k < kLcTab; ++k) {
+            const double r = 1e-8 * std::pow(10.0, 16.0 * k / (kLcTab - 1));
+            double phi, d1;
+            if (q.kind == M2M_POT_LOG) {
+                const double s2 = q.Rc * q.Rc + r * r;
+                phi = 0.5 * q.v0 * q.v0 * std::log(s2);
+                d1 = q.v0 * q.v0 * r / s2;
+            } else {
+                phi = -q.G * q.M / (r + q.a);
+                d1 = q.G * q.M / ((r + q.a) * (r + q.a));
+                if (q.kind == M2M_POT_HERNQUIST_NFW && q.Mh > 0) {
+                    const double l1 = std::log1p(r / q.rs);
+                    phi += -q.G * q.Mh * l1 / r;
+                    d1 += q.G * q.Mh * (l1 / (r * r) - 1.0 / (r * (r + q.rs)));
+                }
             }
-            ectab[128 * (size_t)m + k] = (T)(phi + 0.5 * r * d1);
+            lctab[(size_t)kLcTab * m + k] = (X)(phi + 0.5 * r * d1);
         }
     }
 }
@@ -449,6 +469,8 @@ static void build_layout(m2m_ctx* c) {
     Layout<T> L{};
     L.cosi = (T)std::cos(c->lay.incl);
     L.sini = (T)std::sin(c->lay.incl);
+    L.cosd = std::cos(c->lay.incl);
+    L.sind = std::sin(c->lay.incl);
     L.nbin = c->lay.nbin;
     L.J = c->J;
     int off = 0, e0 = 0;
@@ -464,9 +486,13 @@ static void build_layout(m2m_ctx* c) {
             L.nx[b] = d.nx;
             L.ny[b] = d.ny;
             L.x0[b] = (T)d.x0;
-            L.wx[b] = (T)(d.x1 - d.x0);
+            L.sx[b] = (T)(d.nx / (d.x1 - d.x0));
             L.y0[b] = (T)d.y0;
-            L.wy[b] = (T)(d.y1 - d.y0);
+            L.sy[b] = (T)(d.ny / (d.y1 - d.y0));
+            L.x0d[b] = d.x0;
+            L.wxd[b] = d.x1 - d.x0;
+            L.y0d[b] = d.y0;
+            L.wyd[b] = d.y1 - d.y0;
         } else {
             L.nb[b] = d.nedge - 1;
             e0 += d.nedge;
@@ -474,13 +500,13 @@ static void build_layout(m2m_ctx* c) {
         off += d.nmom * L.nb[b];
     }
     std::memcpy(c->lay_bytes, &L, sizeof(L));
-    Cells<T> C{};
+    Cells C{};
     C.n0 = c->prior.n[0];
     C.n1 = c->prior.n[1];
     C.n2 = c->prior.n[2];
     C.ax2 = c->prior.ax2;
     C.ncell = c->NC;
-    std::memcpy(c->cells_bytes, &C, sizeof(C));
+    c->cells = C;
 }
 
 // ------------------------------------------------------------------- create
@@ -505,18 +531,23 @@ static m2m_status create_T(m2m_ctx* c, const m2m_target* tg, const void* xv, con
     HIPCHK(c, hipMemcpy((T*)c->state[0] + 6 * S, hw.data(), sizeof(T) * N, hipMemcpyHostToDevice));
     if (c->prior.kind != M2M_PRIOR_FLAT && (c->prior.period > 1 || c->prior.kind == M2M_PRIOR_MLP))
         if ((s = dalloc(c, (T**)&c->what, (size_t)S))) return s;
-    // tables
-    std::vector<unsigned char> pots;
-    std::vector<T> ectab;
-    build_tables<T>(c, pots, ectab);
-    if ((s = upload(c, (unsigned char**)&c->pots_d, pots)) || (s = upload(c, (T**)&c->ectab, ectab))) return s;
+    // tables (particle precision, and FP64 for the exact decisions)
+    std::vector<unsigned char> pots, pots64;
+    std::vector<T> lctab;
+    std::vector<double> lctab64;
+    build_tables<T>(c, pots, lctab);
+    build_tables<double>(c, pots64, lctab64);
+    if ((s = upload(c, (unsigned char**)&c->pots_d, pots)) || (s = upload(c, (T**)&c->lctab, lctab)) ||
+        (s = upload(c, (unsigned char**)&c->pots64, pots64)) || (s = upload(c, &c->lctab64, lctab64)))
+        return s;
     build_layout<T>(c);
     std::vector<T> ed;
+    std::vector<double> ed64;
     for (int b = 0; b < c->lay.nbin; ++b)
         if (c->lay.bin[b].kind != M2M_BIN_GRID)
-            for (double v : c->edges_host[b]) ed.push_back((T)v);
-    if (ed.empty()) ed.push_back(T(0));
-    if ((s = upload(c, (T**)&c->edges, ed))) return s;
+            for (double v : c->edges_host[b]) { ed.push_back((T)v); ed64.push_back(v); }
+    if (ed.empty()) { ed.push_back(T(0)); ed64.push_back(0.0); }
+    if ((s = upload(c, (T**)&c->edges, ed)) || (s = upload(c, &c->edges64, ed64))) return s;
     std::vector<T> fw(c->M);
     for (int m = 0; m < c->M; ++m)
         fw[m] = (T)(c->prior.flat_value > 0 ? c->prior.flat_value : 1.0 / (double)(c->off[m + 1] - c->off[m]));
@@ -553,7 +584,7 @@ static m2m_status create_T(m2m_ctx* c, const m2m_target* tg, const void* xv, con
     c->erange_host = er;
     std::vector<T> erT(er.size());
     for (size_t k = 0; k < er.size(); ++k) erT[k] = (T)er[k];
-    if ((s = upload(c, (T**)&c->erange, erT))) return s;
+    if ((s = upload(c, (T**)&c->erange, erT)) || (s = upload(c, &c->erange64, er))) return s;
     HIPCHK(c, launch_prologue_T<T>(c));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     return M2M_OK;
@@ -620,7 +651,7 @@ extern "C" m2m_status m2m_create(const m2m_config* cfg, const m2m_obs_layout* la
         delete c;
         return fail(nullptr, M2M_ERR_DEVICE, std::string("no usable HIP device: ") + hipGetErrorString(e));
     }
-    c->launch.threads = c->prec == M2M_F64 ? 256 : 1024;
+    c->launch.threads = c->prec == M2M_F64 ? 256 : 512;
     c->launch.ilp = c->prec == M2M_F64 ? 1 : 2;
     c->launch.blocks_per_cu = 1;
     c->launch.graph_steps = 0;
@@ -798,11 +829,12 @@ static m2m_status gather_T(m2m_ctx* c, void* out, int dev) {
     a.tile_cnt = c->plan.tile_cnt;
     a.block_tile0 = c->plan.block_tile0;
     a.pots = (const Pot<T>*)c->pots_d;
-    a.ectab = (const T*)c->ectab;
+    a.lctab = (const T*)c->lctab;
     a.erange = (const T*)c->erange;
     a.flatw = (const T*)c->flatw;
     a.cellmean = (const T*)c->cellmean;
-    std::memcpy(&a.cells, c->cells_bytes, sizeof(Cells<T>));
+    a.cells = c->cells;
+    a.ex = exact_tables(c);
     a.what_mode = wm;
     HIPCHK(c, launch_gather<T>(a, c->pot_kind, c->plan.nblock, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -846,7 +878,7 @@ extern "C" m2m_status m2m_get_launch(const m2m_ctx* c, m2m_launch* out) {
 }
 
 static m2m_status apply_launch(m2m_ctx* c, const m2m_launch& L) {
-    const int tmax = c->prec == M2M_F64 ? 256 : 1024;
+    const int tmax = c->prec == M2M_F64 ? 256 : 512;
     if (L.threads < 64 || L.threads > tmax || L.threads % 64 || (L.ilp != 1 && L.ilp != 2 && L.ilp != 4) ||
         L.blocks_per_cu < 1 || L.blocks_per_cu > 64 || L.graph_steps < 0 || L.graph_steps > 100000)
         return fail(c, M2M_ERR_INVALID, "launch shape out of range");
@@ -963,7 +995,7 @@ extern "C" m2m_status m2m_autotune(m2m_ctx* c, int32_t trial_steps, m2m_launch* 
         if (m2m_status s = snapshot(c, snap, false)) return s;
         const int64_t step0 = c->step;
         double best_ms = INFINITY;
-        std::vector<int> threads = c->prec == M2M_F64 ? std::vector<int>{64, 128, 256} : std::vector<int>{256, 512, 1024};
+        std::vector<int> threads = c->prec == M2M_F64 ? std::vector<int>{64, 128, 256} : std::vector<int>{128, 256, 512};
         hipEvent_t e0, e1;
         HIPCHK(c, hipEventCreate(&e0));
         HIPCHK(c, hipEventCreate(&e1));

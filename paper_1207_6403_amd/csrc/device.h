@@ -6,6 +6,12 @@
 // target; section 1: photometry and line-of-sight kinematics) and the
 // phase-space cell of the moving prior (section 2.1: integrals of motion E, L,
 // Lz).  Kernels include this header; the host never calls these functions.
+//
+// Integer decisions (which bin, which prior cell) are taken in FP64.  The FP32
+// kernels first decide in FP32 and keep that answer when the fractional bin
+// coordinate is further than a guard band from every edge (the FP32 error is
+// an order of magnitude below the band); particles inside the band -- a few in
+// ten thousand -- are re-decided from the same coordinates in FP64.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -13,19 +19,23 @@
 namespace m2m {
 
 constexpr int kMaxBin = 4;
-constexpr int kMaxEntries = 3 * kMaxBin;   // non-zero K_j per particle
+constexpr int kMaxEntries = 3 * kMaxBin;   // kernel entries K_j per particle (fixed slots)
+constexpr int kLcTab = 256;                // circular-orbit energies per model
+constexpr float kGuardBin = 1e-4f;         // guard band, in bins, of the FP32 bin coordinates
+constexpr float kGuardCell = 3e-4f;        // guard band, in cells, of the FP32 prior coordinates
 
-// Potential parameters in the particle precision, with derived constants.
+// Potential parameters with derived constants.
 template <typename T>
 struct Pot {
     int32_t kind;       // M2M_POT_*
-    int32_t lc_off;     // offset of this model's Ec table (Hernquist+NFW Lc(E))
+    int32_t lc_off;     // this model's offset in the circular-orbit table
     T GM, a;            // Hernquist
     T v2, Rc2, iq2;     // logarithmic: v0^2, Rc^2, 1/q^2
     T GMh, rs, irs;     // NFW halo
 };
 
-// Observation layout in the particle precision.  Edges live in LDS.
+// Observation layout.  sx, sy = n / width give the fast FP32 bin coordinate;
+// the FP64 decision uses the defining form (v - x0) / width * n.
 template <typename T>
 struct Layout {
     T cosi, sini;
@@ -36,17 +46,26 @@ struct Layout {
     int32_t mom[kMaxBin][3];
     int32_t off[kMaxBin];      // first observable index of the binning
     int32_t nb[kMaxBin];       // bins per moment
-    int32_t edge0[kMaxBin];    // offset of the binning's edges in the edge table
+    int32_t edge0[kMaxBin];    // offset of the binning's edges in the edge tables
     int32_t nx[kMaxBin], ny[kMaxBin];
-    T x0[kMaxBin], wx[kMaxBin], y0[kMaxBin], wy[kMaxBin];
+    T x0[kMaxBin], sx[kMaxBin], y0[kMaxBin], sy[kMaxBin];
+    double cosd, sind;
+    double x0d[kMaxBin], wxd[kMaxBin], y0d[kMaxBin], wyd[kMaxBin];
 };
 
 // Moving-prior cell geometry.
-template <typename T>
 struct Cells {
     int32_t n0, n1, n2;   // cells along E, L/Lc or Lz/Lc, Lz/L
     int32_t ax2;          // 0: L/Lc in [0,1]; 1: Lz/Lc in [-1,1]
     int32_t ncell;
+};
+
+// FP64 tables of the exact (re-)decision path.
+struct Exact {
+    const Pot<double>* pots;
+    const double* lctab;      // kLcTab per model
+    const double* erange;     // Emin, Emax per model
+    const double* edges;      // edge values (also copied to LDS)
 };
 
 // ------------------------------------------------------------------ potentials
@@ -59,25 +78,25 @@ template <typename T> __device__ __forceinline__ T dlog1p(T v) { return log1p(v)
 template <int POT, typename T>
 __device__ __forceinline__ void potential(const Pot<T>& p, T x, T y, T z, T& phi, T& ax, T& ay, T& az) {
     if (POT == 1) {   // logarithmic
-        T s = p.Rc2 + x * x + y * y + z * z * p.iq2;
-        T f = p.v2 / s;
+        const T s = p.Rc2 + x * x + y * y + z * z * p.iq2;
+        const T f = p.v2 / s;
         phi = T(0.5) * p.v2 * dlog(s);
         ax = -f * x;
         ay = -f * y;
         az = -f * z * p.iq2;
         return;
     }
-    T r2 = x * x + y * y + z * z;
-    T r = dsqrt(r2);
-    T u = r + p.a;
+    const T r2 = x * x + y * y + z * z;
+    const T r = dsqrt(r2);
+    const T u = r + p.a;
     T ph = -p.GM / u;
     T g_over_r = r > T(0) ? p.GM / (u * u * r) : T(0);   // (dPhi/dr)/r
     if (POT == 2 && p.GMh > T(0)) {
-        T xx = r * p.irs;
-        T l1 = dlog1p(xx);
+        const T xx = r * p.irs;
+        const T l1 = dlog1p(xx);
         ph += r > T(0) ? -p.GMh * l1 / r : -p.GMh * p.irs;
-        // dPhi_NFW/dr = G Mh/rs^2 * f(x), f = ln(1+x)/x^2 - 1/(x(1+x));
-        // near x = 0 the two terms cancel, so a series is used there.
+        // dPhi_NFW/dr = G Mh/rs^2 f(x), f = ln(1+x)/x^2 - 1/(x(1+x)); the two terms
+        // cancel near x = 0, where the Taylor series is used instead.
         T f;
         if (xx < T(0.05)) {
             f = T(0.5) + xx * (T(-2.0 / 3.0) + xx * (T(0.75) + xx * (T(-0.8) + xx * (T(5.0 / 6.0) - xx * T(6.0 / 7.0)))));
@@ -92,157 +111,225 @@ __device__ __forceinline__ void potential(const Pot<T>& p, T x, T y, T z, T& phi
     az = -g_over_r * z;
 }
 
-// dPhi/dr and d2Phi/dr2 of the spherical kinds (Hernquist + NFW Lc(E) Newton).
-template <typename T>
+// Equatorial Phi(R), dPhi/dR and d2Phi/dR2 (circular-orbit Newton iteration).
+template <int POT, typename T>
 __device__ __forceinline__ void radial_derivs(const Pot<T>& p, T r, T& phi, T& d1, T& d2) {
-    T u = r + p.a;
+    if (POT == 1) {
+        const T s = p.Rc2 + r * r;
+        phi = T(0.5) * p.v2 * dlog(s);
+        d1 = p.v2 * r / s;
+        d2 = p.v2 * (p.Rc2 - r * r) / (s * s);
+        return;
+    }
+    const T u = r + p.a;
     phi = -p.GM / u;
     d1 = p.GM / (u * u);
     d2 = T(-2) * p.GM / (u * u * u);
-    if (p.GMh > T(0)) {
-        T xx = r * p.irs;
-        T l1 = dlog1p(xx);
-        T rrs = r + p.rs;
+    if (POT == 2 && p.GMh > T(0)) {
+        const T l1 = dlog1p(r * p.irs);
+        const T rrs = r + p.rs;
         phi += -p.GMh * l1 / r;
         d1 += p.GMh * (l1 / (r * r) - T(1) / (r * rrs));
         d2 += p.GMh * (T(1) / (r * r * rrs) + (T(2) * r + p.rs) / (r * r * rrs * rrs) - T(2) * l1 / (r * r * r));
     }
 }
 
-// Angular momentum of the circular orbit of energy E.  Returns a value <= 0 to
-// mean "infinite" (E at or above the top of the potential) and a negative
-// sentinel below the bottom is not needed: the ratio is clamped by the caller.
-template <int POT, typename T>
-__device__ __forceinline__ T circular_L(const Pot<T>& p, const T* __restrict__ ectab, T E) {
+// Angular momentum Lc(E) of the circular orbit of energy E.  Radii are
+// bracketed to [1e-8, 1e8]; energies outside take the end values.
+//   Hernquist: 2E u^2 + GM u + GM a = 0 with u = r_c + a, in the stable form
+//     r_c = 4a(GM + E a)/(sqrt(GM^2 - 8 E GM a) - GM - 4 E a);
+//   otherwise: E_c(r_k) tabulated at kLcTab log-spaced radii, r from the table by
+//     bisection and linear interpolation in ln r, then Newton steps on
+//     E_c(r) = Phi + r Phi'/2 = E with dE_c/dr = (3 Phi' + r Phi'')/2.
+template <int POT, typename T, int NEWTON>
+__device__ __forceinline__ T circular_L(const Pot<T>& p, const T* __restrict__ tab, T E) {
     if (POT == 0) {
-        // 2E u^2 + GM u + GM a = 0 with u = r_c + a; the stable form
-        // r_c = 4a(GM + E a)/(sqrt(GM^2 - 8 E GM a) - GM - 4 E a).
-        T D = p.GM * p.GM - T(8) * E * p.GM * p.a;
-        if (!(E < T(0))) return T(-1);
-        T rc = T(4) * p.a * (p.GM + E * p.a) / (dsqrt(D) - p.GM - T(4) * E * p.a);
+        if (!(E < T(0))) return T(-1);        // unbound: infinite Lc
+        const T D = p.GM * p.GM - T(8) * E * p.GM * p.a;
+        const T rc = T(4) * p.a * (p.GM + E * p.a) / (dsqrt(D) - p.GM - T(4) * E * p.a);
         if (!(rc > T(0))) return T(0);
         return rc * dsqrt(p.GM * rc) / (rc + p.a);
-    } else if (POT == 1) {
-        // E = v0^2/2 [1 - Rc^2/s + ln s], s = Rc^2 + R^2: solve t = ln s of
-        // t - Rc^2 e^-t = k (increasing, concave) by Newton from the left.
-        T k = T(2) * E / p.v2 - T(1);
-        T tmin = dlog(p.Rc2);
-        T t = k > tmin ? k : tmin;
-        #pragma unroll
-        for (int it = 0; it < 8; ++it) {
-            T e = p.Rc2 * dexp(-t);
-            t = t - (t - e - k) / (T(1) + e);
-        }
-        T s = dexp(t);
-        T R2 = s - p.Rc2;
-        if (!(R2 > T(0))) return T(0);
-        return dsqrt(p.v2) * R2 / dsqrt(s);
     } else {
-        // Hernquist + NFW: bracket ln r in the model's table of E_c(r) at 128
-        // log-spaced radii on [1e-4, 1e4] (r_k = 1e-4 * 10^(8k/127)), then Newton
-        // on E_c(r) = Phi + r Phi'/2 with dE_c/dr = (3 Phi' + r Phi'')/2.
-        const T* tab = ectab + p.lc_off;
-        if (E <= tab[0] || E >= tab[127]) {
-            T rr = E <= tab[0] ? T(1e-4) : T(1e4);
-            T ph, d1, d2;
-            radial_derivs(p, rr, ph, d1, d2);
-            return rr * dsqrt(rr * d1);
-        }
-        int lo = 0, hi = 127;
-        #pragma unroll
-        for (int it = 0; it < 7; ++it) {
-            int mid = (lo + hi) >> 1;
-            if (tab[mid] <= E) lo = mid; else hi = mid;
-        }
-        const T dl = T(8.0 * 2.302585092994046 / 127.0);
-        T t = (E - tab[lo]) / (tab[hi] - tab[lo]);
-        T lr = T(-4.0 * 2.302585092994046) + (T(lo) + t) * dl;
-        T r = dexp(lr);
-        #pragma unroll
-        for (int it = 0; it < 3; ++it) {
-            T ph, d1, d2;
-            radial_derivs(p, r, ph, d1, d2);
-            T Ec = ph + T(0.5) * r * d1;
-            T dE = T(0.5) * (T(3) * d1 + r * d2);
-            r = r - (Ec - E) / dE;
+        const T lr0 = T(-8.0 * 2.302585092994046), dl = T(16.0 * 2.302585092994046 / (kLcTab - 1));
+        T r;
+        if (E <= tab[0]) {
+            r = T(1e-8);
+        } else if (E >= tab[kLcTab - 1]) {
+            r = T(1e8);
+        } else {
+            int lo = 0, hi = kLcTab - 1;
+            #pragma unroll
+            for (int it = 0; it < 8; ++it) {
+                const int mid = (lo + hi) >> 1;
+                if (tab[mid] <= E) lo = mid; else hi = mid;
+            }
+            const T t = (E - tab[lo]) / (tab[hi] - tab[lo]);
+            r = dexp(lr0 + (T(lo) + t) * dl);
+            #pragma unroll
+            for (int it = 0; it < NEWTON; ++it) {
+                T ph, d1, d2;
+                radial_derivs<POT, T>(p, r, ph, d1, d2);
+                const T Ec = ph + T(0.5) * r * d1;
+                const T dE = T(0.5) * (T(3) * d1 + r * d2);
+                r = r - (Ec - E) / dE;
+            }
         }
         T ph, d1, d2;
-        radial_derivs(p, r, ph, d1, d2);
+        radial_derivs<POT, T>(p, r, ph, d1, d2);
         return r * dsqrt(r * d1);
     }
 }
 
+__device__ __forceinline__ int clamp_cell(double f, int n) {
+    if (!(f >= 0.0)) return 0;   // also NaN
+    if (f >= double(n)) return n - 1;
+    return int(f);
+}
 __device__ __forceinline__ int clamp_cell(float f, int n) {
     if (!(f >= 0.0f)) return 0;
     if (f >= float(n)) return n - 1;
     return int(f);
 }
-__device__ __forceinline__ int clamp_cell(double f, int n) {
-    if (!(f >= 0.0)) return 0;
-    if (f >= double(n)) return n - 1;
-    return int(f);
+// Is the clamped FP32 coordinate f within g of a cell edge it could cross?
+__device__ __forceinline__ bool near_cell_edge(float f, int n, float g) {
+    if (!(f > -g) || !(f < float(n) + g)) return !(f == f);   // far outside: clamped either way
+    const float fr = f - floorf(f);
+    return fr < g || fr > 1.0f - g;
 }
 
-// Cell of the moving prior for a particle of energy E.
-template <int POT, typename T>
-__device__ __forceinline__ int prior_cell(const Pot<T>& p, const T* __restrict__ ectab, const Cells<T>& c,
-                                          T Emin, T Ewid, T E, T x, T y, T z, T vx, T vy, T vz) {
-    T Lx = y * vz - z * vy, Ly = z * vx - x * vz, Lz = x * vy - y * vx;
-    T L = dsqrt(Lx * Lx + Ly * Ly + Lz * Lz);
-    T Lc = circular_L<POT, T>(p, ectab, E);
-    int iE = clamp_cell((E - Emin) / Ewid * T(c.n0), c.n0);
+// Cell of the moving prior in FP64 (the defining arithmetic).
+template <int POT>
+__device__ __forceinline__ int prior_cell_f64(const Pot<double>& p, const double* __restrict__ tab, const Cells& c,
+                                              double Emin, double Emax, double x, double y, double z, double vx,
+                                              double vy, double vz) {
+    double phi, ax, ay, az;
+    potential<POT, double>(p, x, y, z, phi, ax, ay, az);
+    const double E = 0.5 * (vx * vx + vy * vy + vz * vz) + phi;
+    const double Lx = y * vz - z * vy, Ly = z * vx - x * vz, Lz = x * vy - y * vx;
+    const double L = sqrt(Lx * Lx + Ly * Ly + Lz * Lz);
+    const double Lc = circular_L<POT, double, 5>(p, tab, E);
+    const int iE = clamp_cell((E - Emin) / (Emax - Emin) * c.n0, c.n0);
     int i2;
-    if (c.ax2 == 0) {
-        T f = Lc > T(0) ? L / Lc : (Lc < T(0) ? T(0) : T(1e30));
-        i2 = clamp_cell(f * T(c.n1), c.n1);
-    } else {
-        T f = Lc > T(0) ? Lz / Lc : (Lc < T(0) ? T(0) : (Lz > T(0) ? T(1e30) : T(-1e30)));
-        i2 = clamp_cell((f + T(1)) * T(0.5) * T(c.n1), c.n1);
-    }
+    if (c.ax2 == 0) i2 = clamp_cell((Lc > 0 ? L / Lc : (Lc < 0 ? 0.0 : 1e300)) * c.n1, c.n1);
+    else i2 = clamp_cell(((Lc > 0 ? Lz / Lc : (Lc < 0 ? 0.0 : (Lz > 0 ? 1e300 : -1e300))) + 1.0) * 0.5 * c.n1, c.n1);
     int i3 = 0;
-    if (c.n2 > 1) {
-        T f = L > T(0) ? Lz / L : T(0);
-        i3 = clamp_cell((f + T(1)) * T(0.5) * T(c.n2), c.n2);
-    }
+    if (c.n2 > 1) i3 = clamp_cell(((L > 0 ? Lz / L : 0.0) + 1.0) * 0.5 * c.n2, c.n2);
     return (iE * c.n1 + i2) * c.n2 + i3;
 }
 
+// Out-of-line FP64 re-decision of the FP32 kernels (rarely taken; kept out of
+// line so that its registers do not weigh on the FP32 fast path).
+template <int POT>
+__device__ __noinline__ int prior_cell_exact(const Pot<double>* __restrict__ pots, const double* __restrict__ lctab,
+                                             const double* __restrict__ erange, int m, int n0, int n1, int n2, int ax2,
+                                             double x, double y, double z, double vx, double vy, double vz) {
+    const Pot<double> p = pots[m];
+    Cells c;
+    c.n0 = n0; c.n1 = n1; c.n2 = n2; c.ax2 = ax2; c.ncell = n0 * n1 * n2;
+    return prior_cell_f64<POT>(p, lctab + p.lc_off, c, erange[2 * m], erange[2 * m + 1], x, y, z, vx, vy, vz);
+}
+
+// Cell of the moving prior for a particle of energy E (FP32 decision with an
+// FP64 re-decision inside the guard band; FP64 kernels decide in FP64).
+template <int POT, typename T>
+__device__ __forceinline__ int prior_cell(const Pot<T>& p, const T* __restrict__ tab, const Cells& c, T Emin, T sE,
+                                          T E, T x, T y, T z, T vx, T vy, T vz, const Exact& ex, int m) {
+    if constexpr (sizeof(T) == 8) {
+        return prior_cell_f64<POT>(p, tab, c, ex.erange[2 * m], ex.erange[2 * m + 1], x, y, z, vx, vy, vz);
+    } else {
+        const T Lx = y * vz - z * vy, Ly = z * vx - x * vz, Lz = x * vy - y * vx;
+        const T L = dsqrt(Lx * Lx + Ly * Ly + Lz * Lz);
+        const T Lc = circular_L<POT, T, 2>(p, tab, E);
+        const T fE = (E - Emin) * sE;
+        T f2;
+        if (c.ax2 == 0) f2 = (Lc > T(0) ? L / Lc : (Lc < T(0) ? T(0) : T(1e30))) * T(c.n1);
+        else f2 = ((Lc > T(0) ? Lz / Lc : (Lc < T(0) ? T(0) : (Lz > T(0) ? T(1e30) : T(-1e30)))) + T(1)) * T(0.5) * T(c.n1);
+        const T f3 = c.n2 > 1 ? ((L > T(0) ? Lz / L : T(0)) + T(1)) * T(0.5) * T(c.n2) : T(0.5);
+        bool unsure = near_cell_edge(fE, c.n0, kGuardCell) || near_cell_edge(f2, c.n1, kGuardCell) ||
+                      (c.n2 > 1 && near_cell_edge(f3, c.n2, kGuardCell)) || !(Lc > T(0));
+        if (unsure)
+            return prior_cell_exact<POT>(ex.pots, ex.lctab, ex.erange, m, c.n0, c.n1, c.n2, c.ax2, double(x), double(y),
+                                         double(z), double(vx), double(vy), double(vz));
+        return (clamp_cell(fE, c.n0) * c.n1 + clamp_cell(f2, c.n1)) * c.n2 + (c.n2 > 1 ? clamp_cell(f3, c.n2) : 0);
+    }
+}
+
 // ---------------------------------------------------------------- observables
-// Bin of value v against nedge increasing edges in LDS: -1 outside [e0, e_last).
+// Bin of value v against ne increasing edges: -1 outside [e0, e_last).
 template <typename T>
 __device__ __forceinline__ int edge_bin(const T* __restrict__ e, int ne, T v) {
     if (!(v >= e[0]) || !(v < e[ne - 1])) return -1;
     int lo = 0, hi = ne - 1;   // e[lo] <= v < e[hi]
     while (hi - lo > 1) {
-        int mid = (lo + hi) >> 1;
+        const int mid = (lo + hi) >> 1;
         if (v >= e[mid]) lo = mid; else hi = mid;
     }
     return lo;
 }
 
+// Bin of one binning in FP64, the defining arithmetic: grid pixel
+// floor((v - x0) / width * n) on the sky plane, or the edge interval of r / R.
+__device__ __forceinline__ int bin_f64(int kind, double cosd, double sind, double x0, double wx, int nx, double y0,
+                                       double wy, int ny, const double* __restrict__ e, int ne, double x, double y,
+                                       double z) {
+    const double X = x, Ys = y * cosd - z * sind;
+    if (kind == 3) {
+        const double fx = floor((X - x0) / wx * nx);
+        const double fy = floor((Ys - y0) / wy * ny);
+        if (fx >= 0 && fx < nx && fy >= 0 && fy < ny) return int(fy) * nx + int(fx);
+        return -1;
+    }
+    const double rad = kind == 1 ? sqrt(x * x + y * y + z * z) : sqrt(X * X + Ys * Ys);
+    return edge_bin(e, ne, rad);
+}
+
+// FP64 re-decision of the FP32 kernels (rarely taken).
+__device__ __forceinline__ int bin_exact(int kind, double cosd, double sind, double x0, double wx, int nx, double y0,
+                                      double wy, int ny, const double* __restrict__ e, int ne, double x, double y,
+                                      double z) {
+    return bin_f64(kind, cosd, sind, x0, wx, nx, y0, wy, ny, e, ne, x, y, z);
+}
+
 // Kernel entries K_j of one phase-space point in fixed slots e = 3 b + m
-// (binning b, m-th listed moment); jj[e] = -1 marks an empty slot.  Fixed
-// slots keep both arrays in registers (every index is a compile-time constant
-// once the loops are unrolled).
+// (binning b, m-th listed moment); jj[e] = -1 marks an empty slot.  Fixed slots
+// keep both arrays in registers (every index is a compile-time constant once
+// the loops are unrolled).  ef / ed: edge tables in T and in FP64.
 template <typename T>
-__device__ __forceinline__ void kernel_entries(const Layout<T>& L, const T* __restrict__ edges,
-                                               T x, T y, T z, T vy, T vz, int (&jj)[kMaxEntries],
-                                               T (&K)[kMaxEntries]) {
-    const T X = x;
+__device__ __forceinline__ void kernel_entries(const Layout<T>& L, const T* __restrict__ ef,
+                                               const double* __restrict__ ed, T x, T y, T z, T vy, T vz,
+                                               int (&jj)[kMaxEntries], T (&K)[kMaxEntries]) {
     const T Ys = y * L.cosi - z * L.sini;
     const T vl = vy * L.sini + vz * L.cosi;
     #pragma unroll
     for (int b = 0; b < kMaxBin; ++b) {
         int k = -1;
         if (b < L.nbin) {
-            if (L.kind[b] == 3) {
-                const T fx = floor((X - L.x0[b]) / L.wx[b] * T(L.nx[b]));
-                const T fy = floor((Ys - L.y0[b]) / L.wy[b] * T(L.ny[b]));
-                if (fx >= T(0) && fx < T(L.nx[b]) && fy >= T(0) && fy < T(L.ny[b]))
+            if constexpr (sizeof(T) == 8) {
+                k = bin_f64(L.kind[b], L.cosd, L.sind, L.x0d[b], L.wxd[b], L.nx[b], L.y0d[b], L.wyd[b], L.ny[b],
+                            ed + L.edge0[b], L.nb[b] + 1, x, y, z);
+            } else if (L.kind[b] == 3) {
+                const T fx = (x - L.x0[b]) * L.sx[b];
+                const T fy = (Ys - L.y0[b]) * L.sy[b];
+                if (near_cell_edge(fx, L.nx[b], kGuardBin) || near_cell_edge(fy, L.ny[b], kGuardBin)) {
+                    k = bin_exact(3, L.cosd, L.sind, L.x0d[b], L.wxd[b], L.nx[b], L.y0d[b], L.wyd[b], L.ny[b], ed, 0,
+                                  double(x), double(y), double(z));
+                } else if (fx >= T(0) && fx < T(L.nx[b]) && fy >= T(0) && fy < T(L.ny[b])) {
                     k = int(fy) * L.nx[b] + int(fx);
+                }
             } else {
-                const T rad = L.kind[b] == 1 ? dsqrt(x * x + y * y + z * z) : dsqrt(X * X + Ys * Ys);
-                k = edge_bin(edges + L.edge0[b], L.nb[b] + 1, rad);
+                const T rad = L.kind[b] == 1 ? dsqrt(x * x + y * y + z * z) : dsqrt(x * x + Ys * Ys);
+                const T* e = ef + L.edge0[b];
+                const int ne = L.nb[b] + 1;
+                // FP32 search on the rounded edges, re-decided in FP64 within a
+                // relative guard band of the nearest candidate edges
+                const T g = T(kGuardBin) * rad;
+                int kk = edge_bin(e, ne, rad);
+                bool unsure;
+                if (kk >= 0) unsure = rad - e[kk] < g || e[kk + 1] - rad < g;
+                else unsure = fabs(rad - e[0]) < g || fabs(rad - e[ne - 1]) < g || !(rad == rad);
+                k = unsure ? bin_exact(L.kind[b], L.cosd, L.sind, 0.0, 1.0, 1, 0.0, 1.0, 1, ed + L.edge0[b], ne,
+                                       double(x), double(y), double(z))
+                           : kk;
             }
         }
         #pragma unroll

@@ -48,14 +48,18 @@ struct m2m_ctx {
     int64_t N = 0, stride = 0;
     int J = 0, JP = 0, NC = 0, pcols = 0, nedge = 0;
     alignas(16) unsigned char lay_bytes[sizeof(m2m::Layout<double>)] = {};
-    alignas(16) unsigned char cells_bytes[sizeof(m2m::Cells<double>)] = {};
+    m2m::Cells cells{};
     // device
     hipStream_t stream = nullptr;
     int device = 0, numCU = 0, max_lds = 0;
     void* state[2] = {nullptr, nullptr};
     void* what = nullptr;
     void* pots_d = nullptr;
-    void* ectab = nullptr;
+    void* pots64 = nullptr;
+    void* lctab = nullptr;
+    double* lctab64 = nullptr;
+    double* erange64 = nullptr;
+    double* edges64 = nullptr;
     void* erange = nullptr;
     void* flatw = nullptr;
     void* cvec = nullptr;

@@ -29,7 +29,7 @@ struct StepArgs {
     const int32_t* block_tile0;   // nblocks + 1
     const int32_t* block_slot0;   // first partial slot of each block
     const Pot<T>* pots;           // per model
-    const T* ectab;               // 128 per model (Hernquist+NFW)
+    const T* lctab;               // kLcTab circular-orbit energies per model
     const T* erange;              // 2 per model
     const T* flatw;               // per model
     const T* cvec;                // M * J: Dt_j / sigma_j
@@ -40,7 +40,8 @@ struct StepArgs {
     int32_t nedge;
     int32_t pcols, jpad;
     Layout<T> lay;
-    Cells<T> cells;
+    Cells cells;
+    Exact ex;
     T dt, eps, mu;
     int32_t update, frozen;
     int32_t mode;                 // 0 step, 1 observe only
@@ -107,11 +108,12 @@ struct GatherArgs {
     const int32_t* tile_cnt;
     const int32_t* block_tile0;
     const Pot<T>* pots;
-    const T* ectab;
+    const T* lctab;
     const T* erange;
     const T* flatw;
     const T* cellmean;
-    Cells<T> cells;
+    Cells cells;
+    Exact ex;
     int32_t what_mode;
 };
 

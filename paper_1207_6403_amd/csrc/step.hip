@@ -47,21 +47,23 @@ __device__ __forceinline__ void block_stats(double s, double w, double w2, doubl
 }
 
 template <typename T, typename PT, int POT, int ILP>
-__global__ void __launch_bounds__(sizeof(T) == 8 ? 256 : 1024) step_kernel(StepArgs<T, PT> a) {
+__global__ void __launch_bounds__(sizeof(T) == 8 ? 256 : 512) step_kernel(StepArgs<T, PT> a) {
     extern __shared__ __align__(16) unsigned char smem[];
     if (*a.flag) return;   // an earlier step failed: the whole step is a no-op
 
-    const int J = a.lay.J, NC = a.cells.ncell, JP = a.jpad;
+    const int J = a.lay.J, NC = a.cells.ncell, JP = a.jpad, NE = (a.nedge + 1) & ~1;
     double* hist = reinterpret_cast<double*>(smem);                 // J (padded to JP)
     double* csum = hist + JP;                                        // NC
-    unsigned* ccnt = reinterpret_cast<unsigned*>(csum + NC);         // NC (padded to even)
+    double* ed64 = csum + NC;                                        // edges, FP64
+    double* red = ed64 + NE;                                         // 4 * 16
+    unsigned* ccnt = reinterpret_cast<unsigned*>(red + 64);          // NC (padded to even)
     T* cl = reinterpret_cast<T*>(ccnt + ((NC + 1) & ~1));            // J : Dt_j / sigma_j
     T* cm = cl + JP;                                                 // NC: cell means
-    T* ed = cm + ((NC + 1) & ~1);                                    // edges
-    double* red = reinterpret_cast<double*>(ed + ((a.nedge + 1) & ~1));  // 4 * 16
+    T* ed = cm + ((NC + 1) & ~1);                                    // edges in T
+    T* lct = ed + NE;                                                // circular-orbit energies
 
     const int tid = threadIdx.x, nt = blockDim.x;
-    for (int i = tid; i < a.nedge; i += nt) ed[i] = a.edges[i];
+    for (int i = tid; i < a.nedge; i += nt) { ed[i] = a.edges[i]; ed64[i] = a.ex.edges[i]; }
 
     const int t0 = a.block_tile0[blockIdx.x], t1 = a.block_tile0[blockIdx.x + 1];
     const bool observe_only = a.mode == 1;
@@ -69,7 +71,7 @@ __global__ void __launch_bounds__(sizeof(T) == 8 ? 256 : 1024) step_kernel(StepA
     int slot = a.block_slot0[blockIdx.x] - 1;
     int cur = -1;
     Pot<T> pot;
-    T Emin = 0, Ewid = 1, wflat = 0;
+    T Emin = 0, sE = 1, wflat = 0;
     double sS = 0, sW = 0, sW2 = 0, mW = INFINITY;
     unsigned bad = 0;
     const T hdt = T(0.5) * a.dt, dt = a.dt, edt = a.eps * a.dt, mu = a.mu;
@@ -92,12 +94,13 @@ __global__ void __launch_bounds__(sizeof(T) == 8 ? 256 : 1024) step_kernel(StepA
             ++slot;
             pot = a.pots[m];
             Emin = a.erange[2 * m];
-            Ewid = a.erange[2 * m + 1] - a.erange[2 * m];
+            sE = T(a.cells.n0) / (a.erange[2 * m + 1] - a.erange[2 * m]);
             wflat = a.flatw[m];
             __syncthreads();
             for (int j = tid; j < J; j += nt) { hist[j] = 0.0; cl[j] = a.cvec[(size_t)m * J + j]; }
             if (a.accum_cells) for (int c = tid; c < NC; c += nt) { csum[c] = 0.0; ccnt[c] = 0u; }
             if (want_cm) for (int c = tid; c < NC; c += nt) cm[c] = a.cellmean[(size_t)m * NC + c];
+            if (NC) for (int i = tid; i < kLcTab; i += nt) lct[i] = a.lctab[(size_t)pot.lc_off + i];
             __syncthreads();
         }
         const int64_t p0 = a.tile_p0[t];
@@ -132,7 +135,7 @@ __global__ void __launch_bounds__(sizeof(T) == 8 ? 256 : 1024) step_kernel(StepA
                     wh = wflat;
                 } else if (want_cm) {
                     const T E = T(0.5) * (vx * vx + vy * vy + vz * vz) + phi;
-                    const int c = prior_cell<POT, T>(pot, a.ectab, a.cells, Emin, Ewid, E, x, y, z, vx, vy, vz);
+                    const int c = prior_cell<POT, T>(pot, lct, a.cells, Emin, sE, E, x, y, z, vx, vy, vz, a.ex, m);
                     wh = cm[c];
                     if (a.what_mode == 2) a.what[p] = wh;
                 } else {
@@ -141,7 +144,7 @@ __global__ void __launch_bounds__(sizeof(T) == 8 ? 256 : 1024) step_kernel(StepA
                 // dF/dw_i with the priors held fixed
                 int jj[kMaxEntries];
                 T K[kMaxEntries];
-                kernel_entries<T>(a.lay, ed, x, y, z, vy, vz, jj, K);
+                kernel_entries<T>(a.lay, ed, ed64, x, y, z, vy, vz, jj, K);
                 T chi = T(0);
                 #pragma unroll
                 for (int e = 0; e < kMaxEntries; ++e)
@@ -175,13 +178,13 @@ __global__ void __launch_bounds__(sizeof(T) == 8 ? 256 : 1024) step_kernel(StepA
             {
                 int jj[kMaxEntries];
                 T K[kMaxEntries];
-                kernel_entries<T>(a.lay, ed, x, y, z, vy, vz, jj, K);
+                kernel_entries<T>(a.lay, ed, ed64, x, y, z, vy, vz, jj, K);
                 #pragma unroll
                 for (int e = 0; e < kMaxEntries; ++e)
                     if (jj[e] >= 0) atomicAdd(&hist[jj[e]], double(w * K[e]));
                 if (a.accum_cells) {
                     const T E = T(0.5) * (vx * vx + vy * vy + vz * vz) + phi;
-                    const int c = prior_cell<POT, T>(pot, a.ectab, a.cells, Emin, Ewid, E, x, y, z, vx, vy, vz);
+                    const int c = prior_cell<POT, T>(pot, lct, a.cells, Emin, sE, E, x, y, z, vx, vy, vz, a.ex, m);
                     atomicAdd(&csum[c], double(w));
                     atomicAdd(&ccnt[c], 1u);
                 }
@@ -277,22 +280,38 @@ __global__ void __launch_bounds__(256) finalize_kernel(FinArgs<T, PT> a) {
     __syncthreads();
     if (!last) return;
     __threadfence();
-    if (c == 0) {
-        // model finaliser: chi^2 of the new state, statistics of the step just taken
-        double x2 = 0, x2i = 0;
-        for (int k = a.model_chunk[m]; k < a.model_chunk[m + 1]; ++k) {
-            x2 += __hip_atomic_load(a.chunk_chi + 2 * k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            x2i += __hip_atomic_load(a.chunk_chi + 2 * k + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    // model finaliser: chi^2 of the new state and the statistics of the step just
+    // taken, reduced over the model's chunks and slots by the whole block in a fixed
+    // order (thread c takes chunks / slots c, c + 256, ...)
+    double x2 = 0, x2i = 0, sS = 0, sW = 0, sW2 = 0, smn = INFINITY;
+    for (int k = a.model_chunk[m] + c; k < a.model_chunk[m + 1]; k += 256) {
+        x2 += __hip_atomic_load(a.chunk_chi + 2 * k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        x2i += __hip_atomic_load(a.chunk_chi + 2 * k + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    if (!a.first)
+        for (int s = s0 + c; s < s0 + ns; s += 256) {
+            sS += a.seg_stats[4 * s];
+            sW += a.seg_stats[4 * s + 1];
+            sW2 += a.seg_stats[4 * s + 2];
+            smn = fmin(smn, a.seg_stats[4 * s + 3]);
         }
+    __shared__ double mred[6][4];
+    x2 = wave_sum(x2); x2i = wave_sum(x2i); sS = wave_sum(sS); sW = wave_sum(sW); sW2 = wave_sum(sW2);
+    smn = wave_min(smn);
+    if ((c & 63) == 0) {
+        const int wv = c >> 6;
+        mred[0][wv] = x2; mred[1][wv] = x2i; mred[2][wv] = sS; mred[3][wv] = sW; mred[4][wv] = sW2; mred[5][wv] = smn;
+    }
+    __syncthreads();
+    if (c == 0) {
+        x2 = (mred[0][0] + mred[0][1]) + (mred[0][2] + mred[0][3]);
+        x2i = (mred[1][0] + mred[1][1]) + (mred[1][2] + mred[1][3]);
         const long long n = *a.d_step;
         if (!a.first) {
-            double S = 0, W = 0, W2 = 0, mn = INFINITY;
-            for (int s = s0; s < s0 + ns; ++s) {
-                S += a.seg_stats[4 * s];
-                W += a.seg_stats[4 * s + 1];
-                W2 += a.seg_stats[4 * s + 2];
-                mn = fmin(mn, a.seg_stats[4 * s + 3]);
-            }
+            const double S = (mred[2][0] + mred[2][1]) + (mred[2][2] + mred[2][3]);
+            const double W = (mred[3][0] + mred[3][1]) + (mred[3][2] + mred[3][3]);
+            const double W2 = (mred[4][0] + mred[4][1]) + (mred[4][2] + mred[4][3]);
+            const double mn = fmin(fmin(mred[5][0], mred[5][1]), fmin(mred[5][2], mred[5][3]));
             StatRow* r = a.ring + (size_t)m * kRing + (n % kRing);
             r->chi2 = a.chi2[2 * m];
             r->chi2_inst = a.chi2[2 * m + 1];
@@ -372,7 +391,8 @@ __global__ void __launch_bounds__(256) gather_kernel(GatherArgs<T> a) {
     for (int t = t0; t < t1; ++t) {
         const int m = a.tile_model[t];
         const Pot<T> pot = a.pots[m];
-        const T Emin = a.erange[2 * m], Ewid = a.erange[2 * m + 1] - a.erange[2 * m];
+        const T Emin = a.erange[2 * m], sE = T(a.cells.n0) / (a.erange[2 * m + 1] - a.erange[2 * m]);
+        const T* lct = a.lctab + pot.lc_off;
         const int64_t p0 = a.tile_p0[t];
         const int cnt = a.tile_cnt[t];
         for (int i = threadIdx.x; i < cnt; i += blockDim.x) {
@@ -389,7 +409,7 @@ __global__ void __launch_bounds__(256) gather_kernel(GatherArgs<T> a) {
                 potential<POT, T>(pot, x, y, z, phi, ax, ay, az);
                 const T E = T(0.5) * (vx * vx + vy * vy + vz * vz) + phi;
                 wh = a.cellmean[(size_t)m * a.cells.ncell +
-                                prior_cell<POT, T>(pot, a.ectab, a.cells, Emin, Ewid, E, x, y, z, vx, vy, vz)];
+                                prior_cell<POT, T>(pot, lct, a.cells, Emin, sE, E, x, y, z, vx, vy, vz, a.ex, m)];
             }
             a.out[p] = wh;
         }

@@ -114,7 +114,18 @@ EPS_CFG3 = 1.85e-6
 LOG_MASS_R10 = 9.999142073415042
 
 
-def make_inputs(cfg, dtype=np.float64):
+_TARGET_CACHE = {}
+
+
+def cached_target(cfg):
+    """make_target(cfg), memoised on the target recipe and the layout."""
+    key = (cfg["index"], repr(cfg["target"]), repr(cfg["layout"]))
+    if key not in _TARGET_CACHE:
+        _TARGET_CACHE[key] = make_target(cfg)
+    return _TARGET_CACHE[key]
+
+
+def make_inputs(cfg, dtype=np.float64, cache_target=True):
     """Initial particle model, weights 1/N (per model), noisy target."""
     idx = cfg["index"]
     seed = seed_for(idx)
@@ -134,8 +145,8 @@ def make_inputs(cfg, dtype=np.float64):
         lp = LOG_POT
         ics = galaxy.log_isotropic_ics(cfg["N"], seed, lp["v0"], lp["Rc"], lp["q"])
         w = np.full(cfg["N"], 1.0 / cfg["N"])
-    Y, sigma = make_target(cfg)
-    return {"ics": ics.astype(dtype), "w": w.astype(dtype), "Y": Y, "sigma": sigma}
+    Y, sigma = cached_target(cfg) if cache_target else make_target(cfg)
+    return {"ics": ics.astype(dtype), "w": w.astype(dtype), "Y": Y.copy(), "sigma": sigma.copy()}
 
 
 def make_target(cfg):

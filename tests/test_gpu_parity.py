@@ -56,7 +56,8 @@ def test_cfg1_fp64_matches_oracle(nsteps):
     np.testing.assert_allclose(m2m.m2m_weights(ctx), om.w, rtol=tol)
     np.testing.assert_allclose(m2m.m2m_particles(ctx), om.ics(), rtol=tol, atol=tol)
     for k, name in enumerate(["chi2", "chi2_inst", "S", "F", "sum_w", "min_w", "sum_w2"]):
-        assert st[name] == pytest.approx(ost[k], rel=tol, abs=1e-300), name
+        # S(0) = 0 exactly (w = what); its rounding noise is ~1e-16 of sum w |ln w|
+        assert st[name] == pytest.approx(ost[k], rel=tol, abs=1e-12 if name == "S" else 1e-300), name
     assert st["step"] == nsteps - 1
     # the context already observed the state of step nsteps; the oracle observes it
     # at the start of its next step
@@ -67,7 +68,7 @@ def test_cfg1_fp64_matches_oracle(nsteps):
 
 
 def test_cfg2_fp32_single_step():
-    cfg = configs.cfg2(N=50000, target_n=1 << 18)
+    cfg = configs.cfg2(N=50000)
     inp, ctx, (om,) = run_both(cfg, 1)
     m2m.m2m_step(ctx, 1)
     om.run(1)
@@ -85,11 +86,11 @@ def test_cfg2_fp32_single_step():
 
 
 @pytest.mark.parametrize("launch", [{"threads": 256, "ilp": 1, "blocks_per_cu": 1},
-                                    {"threads": 1024, "ilp": 4, "blocks_per_cu": 1},
+                                    {"threads": 512, "ilp": 4, "blocks_per_cu": 1},
                                     {"threads": 512, "ilp": 2, "blocks_per_cu": 4}])
 def test_cfg2_fp32_launch_shapes_agree(launch):
     """Ragged tiles (N = 40,007 is not a multiple of any tile) in several launch shapes."""
-    cfg = configs.cfg2(N=40007, target_n=1 << 18)
+    cfg = configs.cfg2(N=40007)
     inp, ctx, (om,) = run_both(cfg, 3, launch=launch)
     st = m2m.m2m_step(ctx, 3)[0]
     ost = om.run(3)[-1]
@@ -101,7 +102,7 @@ def test_cfg2_fp32_launch_shapes_agree(launch):
 
 def test_cfg2_fp32_end_of_run():
     """200 steps of N = 2e4: chi^2 and the observables within 1e-3 of the FP64 oracle."""
-    cfg = configs.cfg2(N=20000, target_n=1 << 18)
+    cfg = configs.cfg2(N=20000)
     inp, ctx, (om,) = run_both(cfg, 200)
     st = m2m.m2m_step(ctx, 200)[0]
     ost = om.run(200)[-1]
@@ -128,7 +129,7 @@ def test_cfg1_fp64_full_run_chi2():
 def test_cfg2_full_size_one_step():
     """N = 2^20 in the benchmark's launch shape: one step against the oracle."""
     cfg = configs.cfg2()
-    inp, ctx, (om,) = run_both(cfg, 1, launch={"threads": 1024, "ilp": 4, "blocks_per_cu": 1})
+    inp, ctx, (om,) = run_both(cfg, 1, launch={"threads": 512, "ilp": 4, "blocks_per_cu": 1})
     st = m2m.m2m_step(ctx, 1)[0]
     ost = om.run(1)[-1]
     np.testing.assert_allclose(m2m.m2m_weights(ctx).astype(np.float64), om.w, rtol=1e-6)
@@ -159,8 +160,8 @@ def test_batched_models_match_oracle():
     wg = m2m.m2m_weights(ctx).astype(np.float64)
     for m, om in enumerate(ors):
         ost = om.run(4)[-1]
-        np.testing.assert_allclose(wg[offs[m]:offs[m + 1]], om.w, rtol=2e-6)
-        assert rows[m]["chi2"] == pytest.approx(ost[0], rel=2e-6)
+        np.testing.assert_allclose(wg[offs[m]:offs[m + 1]], om.w, rtol=1e-5)
+        assert rows[m]["chi2"] == pytest.approx(ost[0], rel=1e-5)
         assert rows[m]["model"] == m
 
 
@@ -194,7 +195,7 @@ def test_single_particle_and_empty_bins():
 
 
 def test_graphs_match_direct_launches():
-    cfg = configs.cfg2(N=30000, target_n=1 << 16)
+    cfg = configs.cfg2(N=30000)
     inp = H.inputs(cfg)
     er = H.erange(cfg, inp)
     a = m2m.m2m_create(cfg, inp["ics"], inp["w"], inp["Y"], inp["sigma"], Erange=er)
@@ -210,14 +211,14 @@ def test_graphs_match_direct_launches():
 
 
 def test_autotune_restores_state():
-    cfg = configs.cfg2(N=30000, target_n=1 << 16)
+    cfg = configs.cfg2(N=30000)
     inp = H.inputs(cfg)
     er = H.erange(cfg, inp)
     a = m2m.m2m_create(cfg, inp["ics"], inp["w"], inp["Y"], inp["sigma"], Erange=er)
     m2m.m2m_step(a, 2)
     w_before = m2m.m2m_weights(a).copy()
     chosen = m2m.m2m_autotune(a, 3)
-    assert chosen["threads"] in (256, 512, 1024)
+    assert chosen["threads"] in (128, 256, 512)
     np.testing.assert_array_equal(m2m.m2m_weights(a), w_before)
     assert m2m.m2m_step_index(a) == 2
     m2m.m2m_step(a, 1)
