@@ -53,6 +53,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=24)
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--graph-steps", type=int, default=100)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -77,11 +78,16 @@ def main():
     if not args.no_autotune:
         launch = m2m.m2m_autotune(ctx, 20)
         log("autotuned launch: %s" % launch)
-    m2m.m2m_set_launch(ctx, timing=0, graph_steps=0)
+    # HIP graphs of G steps with an event pair captured around every fused step
+    # kernel; the warmup builds the graph, the timed region only replays it
+    G = args.graph_steps
+    if G:
+        assert args.steps % G == 0 and args.warmup % G == 0 and args.warmup >= G, \
+            "--steps and --warmup must be multiples of --graph-steps"
+    m2m.m2m_set_launch(ctx, timing=1, graph_steps=G)
     log("warmup %d steps" % args.warmup)
     m2m.m2m_step(ctx, args.warmup)
     torch.cuda.synchronize()
-    m2m.m2m_set_launch(ctx, timing=1)
     log("timing %d steps" % args.steps)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
