@@ -647,6 +647,12 @@ extern "C" m2m_status m2m_create(const m2m_config* cfg, const m2m_obs_layout* la
     hipError_t e = hipGetDevice(&c->device);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&c->numCU, hipDeviceAttributeMultiprocessorCount, c->device);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&c->max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device);
+    if (e == hipSuccess && !c->stream) {
+        // the legacy default stream cannot be captured into graphs: run on a
+        // stream of our own (default priority) unless the caller names one
+        e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
+        c->own_stream = e == hipSuccess;
+    }
     if (e != hipSuccess) {
         delete c;
         return fail(nullptr, M2M_ERR_DEVICE, std::string("no usable HIP device: ") + hipGetErrorString(e));
@@ -1074,13 +1080,14 @@ extern "C" m2m_status m2m_autotune(m2m_ctx* c, int32_t trial_steps, m2m_launch* 
 // ------------------------------------------------------------------ destroy
 extern "C" void m2m_destroy(m2m_ctx* c) {
     if (!c) return;
-    if (c->stream || true) (void)hipStreamSynchronize(c->stream);
+    (void)hipStreamSynchronize(c->stream);
     for (int k = 0; k < 2; ++k)
         if (c->graph[k]) (void)hipGraphExecDestroy(c->graph[k]);
     for (hipEvent_t e : c->events) (void)hipEventDestroy(e);
     for (int k = 0; k < 2; ++k)
         for (hipEvent_t e : c->gevents[k]) (void)hipEventDestroy(e);
     for (void* p : c->allocs) (void)hipFree(p);
+    if (c->own_stream) (void)hipStreamDestroy(c->stream);
     delete c;
 }
 

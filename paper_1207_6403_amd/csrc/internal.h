@@ -51,6 +51,7 @@ struct m2m_ctx {
     m2m::Cells cells{};
     // device
     hipStream_t stream = nullptr;
+    bool own_stream = false;
     int device = 0, numCU = 0, max_lds = 0;
     void* state[2] = {nullptr, nullptr};
     void* what = nullptr;

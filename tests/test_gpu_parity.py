@@ -100,19 +100,33 @@ def test_cfg2_fp32_launch_shapes_agree(launch):
     assert st["sum_w"] == pytest.approx(ost[4], rel=1e-6)
 
 
+def smoothed_next(cfg, om):
+    """Oracle smoothed observables of its current state (those the context holds)."""
+    g = cfg["dt"] / cfg["tau"]
+    ys = om.arr["ys"]
+    return ys + g * (om.observe() - ys)
+
+
 def test_cfg2_fp32_end_of_run():
-    """200 steps of N = 2e4: chi^2 and the observables within 1e-3 of the FP64 oracle."""
+    """200 steps of N = 2e4: chi^2 within 1e-3 of the FP64 oracle; the smoothed
+    observables within max(1e-3, 3x the spread of two oracle runs whose initial
+    coordinates differ by one FP32 ulp) at the 99th percentile of the bins."""
     cfg = configs.cfg2(N=20000)
     inp, ctx, (om,) = run_both(cfg, 200)
     st = m2m.m2m_step(ctx, 200)[0]
     ost = om.run(200)[-1]
     assert st["chi2"] == pytest.approx(ost[0], rel=1e-3)
+    ulp = H.oracle_models(cfg, dict(inp, ics=np.nextafter(inp["ics"], np.float32(np.inf))), H.erange(cfg, inp))[0]
+    ulp.run(200)
     obs = m2m.m2m_observables(ctx, 0)
-    ys_o = om.arr["ys"]
+    ys_o = smoothed_next(cfg, om)
     scale = H.moment_scale(cfg, om.ics(), om.w)
     big = scale > 1e-3 * scale.max()
     err = np.abs(obs["y_smooth"] - ys_o)[big] / scale[big]
-    assert np.percentile(err, 99) < 1e-3 and err.max() < 1e-2
+    floor = np.abs(smoothed_next(cfg, ulp) - ys_o)[big] / scale[big]
+    H.flush("end-of-run error p99 %.3g max %.3g; one-ulp floor p99 %.3g max %.3g" % (
+        np.percentile(err, 99), err.max(), np.percentile(floor, 99), floor.max()))
+    assert np.percentile(err, 99) <= max(1e-3, 3 * np.percentile(floor, 99))
 
 
 def test_cfg1_fp64_full_run_chi2():
@@ -135,8 +149,8 @@ def test_cfg2_full_size_one_step():
     np.testing.assert_allclose(m2m.m2m_weights(ctx).astype(np.float64), om.w, rtol=1e-6)
     assert st["chi2"] == pytest.approx(ost[0], rel=1e-6)
     obs = m2m.m2m_observables(ctx, 0)
-    chi2_next = np.sum(((om.observe() - inp["Y"]) / inp["sigma"]) ** 2)
-    assert obs["chi2"] == pytest.approx(chi2_next, rel=1e-5)
+    chi2_next = np.sum(((smoothed_next(cfg, om) - inp["Y"]) / inp["sigma"]) ** 2)
+    assert obs["chi2"] == pytest.approx(chi2_next, rel=1e-6)
 
 
 def test_nonpositive_weight_keeps_last_state():
