@@ -698,30 +698,22 @@ static m2m_status check_flag(m2m_ctx* c, int64_t start) {
                                   "; the context holds the state at the start of that step");
 }
 
+// HIP graphs are used when the step sequence is the same every step (flat prior
+// or a moving prior refreshed every step) and no per-kernel timing is asked for
+// (event records inside a graph cannot be timed).
 static bool graphable(const m2m_ctx* c) {
-    return c->launch.graph_steps > 0 &&
+    return c->launch.graph_steps > 0 && !c->launch.timing &&
            (c->prior.kind == M2M_PRIOR_FLAT || (c->prior.kind == M2M_PRIOR_HIST && c->prior.period == 1));
 }
 
 // Capture K steps (K even, so a replay ends on the buffer parity it started on).
-// With timing on, every fused kernel of the graph is bracketed by captured event
-// records (one pair per step, read after the replay).
 static m2m_status build_graph(m2m_ctx* c, int parity) {
     const int K = (c->launch.graph_steps + 1) & ~1;
-    const bool timing = c->launch.timing != 0;
     if (c->graph[parity]) { (void)hipGraphExecDestroy(c->graph[parity]); c->graph[parity] = nullptr; }
-    if (timing)
-        while ((int)c->gevents[parity].size() < 2 * K) {
-            hipEvent_t ev;
-            HIPCHK(c, hipEventCreate(&ev));
-            c->gevents[parity].push_back(ev);
-        }
     hipGraph_t g = nullptr;
     HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
     hipError_t e = hipSuccess;
-    for (int k = 0; k < K && e == hipSuccess; ++k)
-        e = timing ? launch_one(c, parity + k, c->gevents[parity][2 * k], c->gevents[parity][2 * k + 1])
-                   : launch_one(c, parity + k);
+    for (int k = 0; k < K && e == hipSuccess; ++k) e = launch_one(c, parity + k);
     hipError_t e2 = hipStreamEndCapture(c->stream, &g);
     if (e != hipSuccess || e2 != hipSuccess) {
         if (g) (void)hipGraphDestroy(g);
@@ -731,7 +723,6 @@ static m2m_status build_graph(m2m_ctx* c, int parity) {
     (void)hipGraphDestroy(g);
     if (e != hipSuccess) return fail(c, M2M_ERR_DEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
     c->graph_k[parity] = K;
-    c->graph_timing[parity] = timing;
     return M2M_OK;
 }
 
@@ -743,31 +734,16 @@ extern "C" m2m_status m2m_step(m2m_ctx* c, int64_t n_steps, m2m_step_stats* last
     int64_t left = n_steps;
     c->last_launches = 0;
     c->last_kernel_ms = 0;
-    int timed_graph = -1;
     if (graphable(c)) {
         const int K = (c->launch.graph_steps + 1) & ~1;
         while (left >= K) {
             const int par = (int)(c->step & 1);
-            if (!c->graph[par] || c->graph_k[par] != K || c->graph_timing[par] != (c->launch.timing != 0))
+            if (!c->graph[par] || c->graph_k[par] != K)
                 if (m2m_status s = build_graph(c, par)) return s;
             HIPCHK(c, hipGraphLaunch(c->graph[par], c->stream));
-            if (c->launch.timing) timed_graph = par;
             c->step += K;
             left -= K;
         }
-    }
-    if (timed_graph >= 0) {
-        // kernel durations of the last replay (its events are the ones still set)
-        HIPCHK(c, hipStreamSynchronize(c->stream));
-        const int K = c->graph_k[timed_graph];
-        double tot = 0;
-        for (int k = 0; k < K; ++k) {
-            float ms = 0;
-            HIPCHK(c, hipEventElapsedTime(&ms, c->gevents[timed_graph][2 * k], c->gevents[timed_graph][2 * k + 1]));
-            tot += ms;
-        }
-        c->last_kernel_ms = tot / K;
-        c->last_launches = K;
     }
     if (c->launch.timing && left > 0) {
         const int64_t nt = std::min<int64_t>(left, 4096);
@@ -1084,8 +1060,6 @@ extern "C" void m2m_destroy(m2m_ctx* c) {
     for (int k = 0; k < 2; ++k)
         if (c->graph[k]) (void)hipGraphExecDestroy(c->graph[k]);
     for (hipEvent_t e : c->events) (void)hipEventDestroy(e);
-    for (int k = 0; k < 2; ++k)
-        for (hipEvent_t e : c->gevents[k]) (void)hipEventDestroy(e);
     for (void* p : c->allocs) (void)hipFree(p);
     if (c->own_stream) (void)hipStreamDestroy(c->stream);
     delete c;

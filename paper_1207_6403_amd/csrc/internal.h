@@ -83,8 +83,6 @@ struct m2m_ctx {
     m2m_launch launch{};
     hipGraphExec_t graph[2] = {nullptr, nullptr};
     int graph_k[2] = {0, 0};
-    bool graph_timing[2] = {false, false};
-    std::vector<hipEvent_t> gevents[2];
     std::vector<hipEvent_t> events;
     double last_kernel_ms = 0;
     int64_t last_launches = 0;
