@@ -232,7 +232,11 @@ static m2m_status make_plan(m2m_ctx* c, int threads, int ilp, int bpc) {
     p.nblock = (int)B;
     p.nslot = nslot;
     p.nchunk = (int)cm.size();
-    p.nsplit = std::max(1, (maxslot + 31) / 32);
+    p.nsplit = std::max(1, (maxslot + kSlotsPerSplit - 1) / kSlotsPerSplit);
+    if (p.nsplit > kMaxSplit)
+        return fail(c, M2M_ERR_UNSUPPORTED, "launch shape gives " + std::to_string(maxslot) +
+                                                " partial slots for one model (max " +
+                                                std::to_string(kSlotsPerSplit * kMaxSplit) + ")");
     m2m_status s;
     if ((s = upload(c, &p.tile_model, tm)) || (s = upload(c, &p.tile_p0, tp)) || (s = upload(c, &p.tile_cnt, tc)) ||
         (s = upload(c, &p.block_tile0, bt0)) || (s = upload(c, &p.block_slot0, bs0)) ||
@@ -894,8 +898,19 @@ static m2m_status apply_launch(m2m_ctx* c, const m2m_launch& L) {
         L.blocks_per_cu < 1 || L.blocks_per_cu > 64 || L.graph_steps < 0 || L.graph_steps > 100000)
         return fail(c, M2M_ERR_INVALID, "launch shape out of range");
     const bool replan = L.threads != c->plan.threads || L.ilp != c->plan.ilp || L.blocks_per_cu != c->plan.bpc;
+    const m2m_launch prev = c->launch;
     c->launch = L;
-    if (replan) return make_plan(c, L.threads, L.ilp, L.blocks_per_cu);
+    if (replan) {
+        m2m_status s = make_plan(c, L.threads, L.ilp, L.blocks_per_cu);
+        if (s) {
+            // keep the context usable: go back to the previous shape
+            const std::string why = c->msg;
+            c->launch = prev;
+            if (make_plan(c, prev.threads, prev.ilp, prev.blocks_per_cu) != M2M_OK) return s;
+            c->msg = why;
+        }
+        return s;
+    }
     for (int k = 0; k < 2; ++k)
         if (c->graph[k]) { (void)hipGraphExecDestroy(c->graph[k]); c->graph[k] = nullptr; }
     return M2M_OK;

@@ -8,7 +8,9 @@
 
 namespace m2m {
 
-constexpr int kRing = 4096;   // statistics rows kept per model
+constexpr int kRing = 4096;          // statistics rows kept per model
+constexpr int kSlotsPerSplit = 32;   // partial slots summed by one finalise block
+constexpr int kMaxSplit = 32;        // finalise blocks per column chunk (<= 1024 slots)
 
 struct StatRow {
     double chi2, chi2_inst, S, F, sum_w, min_w, sum_w2, n_eff;

@@ -217,17 +217,16 @@ __global__ void __launch_bounds__(256) finalize_kernel(FinArgs<T, PT> a) {
     const bool live = c < ncol && (col0 + c < J || (col0 + c >= a.jpad && a.accum_cells));
     // level 1: this split's slots, fixed order
     if (live) {
-        double acc0 = 0, acc1 = 0, acc2 = 0, acc3 = 0;
+        // at most kSlotsPerSplit slots: issue every load before the first add so the
+        // whole column is in flight at once
         const PT* src = a.part + col0 + c;
-        int s = sa;
-        for (; s + 3 < sb; s += 4) {
-            acc0 += double(src[(size_t)s * a.pcols]);
-            acc1 += double(src[(size_t)(s + 1) * a.pcols]);
-            acc2 += double(src[(size_t)(s + 2) * a.pcols]);
-            acc3 += double(src[(size_t)(s + 3) * a.pcols]);
-        }
-        for (; s < sb; ++s) acc0 += double(src[(size_t)s * a.pcols]);
-        a.l2[((size_t)chunk * S + split) * 256 + c] = (acc0 + acc1) + (acc2 + acc3);
+        PT v[kSlotsPerSplit];
+        #pragma unroll
+        for (int k = 0; k < kSlotsPerSplit; ++k) v[k] = sa + k < sb ? src[(size_t)(sa + k) * a.pcols] : PT(0);
+        double acc = 0;
+        #pragma unroll
+        for (int k = 0; k < kSlotsPerSplit; ++k) acc += double(v[k]);
+        a.l2[((size_t)chunk * S + split) * 256 + c] = acc;
     }
     __threadfence();
     __syncthreads();
@@ -237,8 +236,16 @@ __global__ void __launch_bounds__(256) finalize_kernel(FinArgs<T, PT> a) {
     __threadfence();
     // level 2: the chunk's column totals
     double v = 0;
-    if (live)
-        for (int s = 0; s < S; ++s) v += __hip_atomic_load(a.l2 + ((size_t)chunk * S + s) * 256 + c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (live) {
+        double pv[kMaxSplit];
+        #pragma unroll
+        for (int s = 0; s < kMaxSplit; ++s)
+            pv[s] = s < S ? __hip_atomic_load(a.l2 + ((size_t)chunk * S + s) * 256 + c, __ATOMIC_RELAXED,
+                                              __HIP_MEMORY_SCOPE_AGENT)
+                          : 0.0;
+        #pragma unroll
+        for (int s = 0; s < kMaxSplit; ++s) v += pv[s];
+    }
     tot[c] = v;
     __syncthreads();
     double chi = 0, chii = 0;
