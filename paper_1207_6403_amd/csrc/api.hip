@@ -167,9 +167,8 @@ static m2m_status validate(const m2m_config* cfg, const m2m_obs_layout* lay, con
 static void free_plan(m2m_ctx* c) {
     Plan& p = c->plan;
     for (void* q : {(void*)p.tile_model, (void*)p.tile_p0, (void*)p.tile_cnt, (void*)p.block_tile0,
-                    (void*)p.block_slot0, (void*)p.model_slot, (void*)p.chunk_model, (void*)p.chunk_col0,
-                    (void*)p.chunk_ncol, (void*)p.model_chunk, (void*)p.part, (void*)p.seg_stats, (void*)p.l2,
-                    (void*)p.chunk_cnt, (void*)p.chunk_chi, (void*)p.model_cnt, (void*)p.all_cnt, (void*)p.erange_out})
+                    (void*)p.block_slot0, (void*)p.model_slot, (void*)p.part, (void*)p.seg_stats,
+                    (void*)p.erange_out})
         dfree(c, q);
     p = Plan();
     for (int k = 0; k < 2; ++k)
@@ -216,48 +215,24 @@ static m2m_status make_plan(m2m_ctx* c, int threads, int ilp, int bpc) {
         }
     }
     mslot[c->M] = nslot;
-    int maxslot = 0;
-    for (int m = 0; m < c->M; ++m) maxslot = std::max(maxslot, mslot[m + 1] - mslot[m]);
-    std::vector<int32_t> cm, cc0, cn, mch(c->M + 1);
-    for (int m = 0; m < c->M; ++m) {
-        mch[m] = (int32_t)cm.size();
-        for (int c0 = 0; c0 < c->pcols; c0 += 256) {
-            cm.push_back(m);
-            cc0.push_back(c0);
-            cn.push_back(std::min(256, c->pcols - c0));
-        }
-    }
-    mch[c->M] = (int32_t)cm.size();
     p.ntile = T;
     p.nblock = (int)B;
     p.nslot = nslot;
-    p.nchunk = (int)cm.size();
-    p.nsplit = std::max(1, (maxslot + kSlotsPerSplit - 1) / kSlotsPerSplit);
-    if (p.nsplit > kMaxSplit)
-        return fail(c, M2M_ERR_UNSUPPORTED, "launch shape gives " + std::to_string(maxslot) +
-                                                " partial slots for one model (max " +
-                                                std::to_string(kSlotsPerSplit * kMaxSplit) + ")");
     m2m_status s;
     if ((s = upload(c, &p.tile_model, tm)) || (s = upload(c, &p.tile_p0, tp)) || (s = upload(c, &p.tile_cnt, tc)) ||
         (s = upload(c, &p.block_tile0, bt0)) || (s = upload(c, &p.block_slot0, bs0)) ||
-        (s = upload(c, &p.model_slot, mslot)) || (s = upload(c, &p.chunk_model, cm)) ||
-        (s = upload(c, &p.chunk_col0, cc0)) || (s = upload(c, &p.chunk_ncol, cn)) || (s = upload(c, &p.model_chunk, mch)))
+        (s = upload(c, &p.model_slot, mslot)))
         return s;
     if ((s = dalloc(c, (char**)&p.part, (size_t)nslot * c->pcols * tsize(c))) ||
-        (s = dalloc(c, &p.seg_stats, (size_t)nslot * 4)) ||
-        (s = dalloc(c, &p.l2, (size_t)p.nchunk * p.nsplit * 256)) || (s = dalloc(c, &p.chunk_cnt, (size_t)p.nchunk)) ||
-        (s = dalloc(c, &p.chunk_chi, (size_t)p.nchunk * 2)) || (s = dalloc(c, &p.model_cnt, (size_t)c->M)) ||
-        (s = dalloc(c, &p.all_cnt, 1)) || (s = dalloc(c, &p.erange_out, (size_t)nslot * 2)))
+        (s = dalloc(c, &p.seg_stats, (size_t)nslot * 4)) || (s = dalloc(c, &p.erange_out, (size_t)nslot * 2)))
         return s;
-    HIPCHK(c, hipMemset(p.chunk_cnt, 0, sizeof(int) * p.nchunk));
-    HIPCHK(c, hipMemset(p.model_cnt, 0, sizeof(int) * c->M));
-    HIPCHK(c, hipMemset(p.all_cnt, 0, sizeof(int)));
     HIPCHK(c, hipMemset(p.part, 0, (size_t)nslot * c->pcols * tsize(c)));
     // LDS of the fused kernel: histograms, cell sums/counts, update table,
     // cell means, edges, reduction scratch
     const size_t ts = tsize(c);
     const int NCe = (c->NC + 1) & ~1, NE = (c->nedge + 1) & ~1;
-    p.lds = 8 * ((size_t)c->JP + c->NC + NE + 64) + 4 * (size_t)NCe + ts * ((size_t)c->JP + NCe + NE + kLcTab);
+    const int NET = (ts == 4 && c->NC) ? kLcE : 0;
+    p.lds = 8 * ((size_t)c->JP + c->NC + NE + 64 + NET) + 4 * (size_t)NCe + ts * ((size_t)c->JP + NCe + NE + kLcTab);
     p.lds = (p.lds + 15) & ~(size_t)15;
     if (p.lds > (size_t)c->max_lds)
         return fail(c, M2M_ERR_UNSUPPORTED, "layout needs " + std::to_string(p.lds) + " bytes of LDS per block (max " +
@@ -289,6 +264,7 @@ static void fill_step_args(m2m_ctx* c, StepArgs<T, T>& a, int parity, int mode, 
     a.block_slot0 = p.block_slot0;
     a.pots = (const Pot<T>*)c->pots_d;
     a.lctab = (const T*)c->lctab;
+    a.lcetab = (const float*)c->lcetab;
     a.erange = (const T*)c->erange;
     a.flatw = (const T*)c->flatw;
     a.cvec = (const T*)c->cvec;
@@ -316,7 +292,7 @@ static void fill_step_args(m2m_ctx* c, StepArgs<T, T>& a, int parity, int mode, 
 }
 
 template <typename T>
-static void fill_fin_args(m2m_ctx* c, FinArgs<T, T>& f, int first, int accum) {
+static void fill_fin_args(m2m_ctx* c, FinArgs<T, T>& f, int first, int accum, int parity) {
     const Plan& p = c->plan;
     f.part = (const T*)p.part;
     f.pcols = c->pcols;
@@ -324,16 +300,14 @@ static void fill_fin_args(m2m_ctx* c, FinArgs<T, T>& f, int first, int accum) {
     f.J = c->J;
     f.ncell = c->NC;
     f.n_models = c->M;
-    f.chunk_model = p.chunk_model;
-    f.chunk_col0 = p.chunk_col0;
-    f.chunk_ncol = p.chunk_ncol;
+    f.chunk_model = c->chunk_model;
+    f.chunk_col0 = c->chunk_col0;
+    f.chunk_ncol = c->chunk_ncol;
     f.model_slot = p.model_slot;
-    f.model_chunk = p.model_chunk;
-    f.l2 = p.l2;
-    f.chunk_cnt = p.chunk_cnt;
-    f.chunk_chi = p.chunk_chi;
-    f.model_cnt = p.model_cnt;
-    f.all_cnt = p.all_cnt;
+    f.model_chunk = c->model_chunk;
+    f.nchunk = c->nchunk;
+    f.parity = parity;
+    f.chunk_chi = c->chunk_chi;
     f.Y = c->Y;
     f.sigma = c->sigma;
     f.y = c->y;
@@ -342,7 +316,6 @@ static void fill_fin_args(m2m_ctx* c, FinArgs<T, T>& f, int first, int accum) {
     f.cvec = (T*)c->cvec;
     f.cellmean = (T*)c->cellmean;
     f.cellmean64 = c->cellmean64;
-    f.chi2 = c->chi2;
     f.seg_stats = p.seg_stats;
     f.ring = c->ring;
     f.g = c->dt / c->tau;
@@ -374,8 +347,8 @@ static hipError_t launch_one_T(m2m_ctx* c, int64_t n, hipEvent_t e0, hipEvent_t 
     if (e1) (void)hipEventRecord(e1, c->stream);
     if (e != hipSuccess) return e;
     FinArgs<T, T> f;
-    fill_fin_args<T>(c, f, 0, acc);
-    return launch_finalize<T, T>(f, p.nchunk, p.nsplit, c->stream);
+    fill_fin_args<T>(c, f, 0, acc, (int)(n & 1));
+    return launch_finalize<T, T>(f, c->stream);
 }
 
 static hipError_t launch_one(m2m_ctx* c, int64_t n, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr) {
@@ -391,8 +364,9 @@ static hipError_t launch_prologue_T(m2m_ctx* c) {
     hipError_t e = launch_step<T, T>(a, c->pot_kind, p.ilp, p.nblock, p.threads, p.lds, c->stream);
     if (e != hipSuccess) return e;
     FinArgs<T, T> f;
-    fill_fin_args<T>(c, f, 1, accum);
-    return launch_finalize<T, T>(f, p.nchunk, p.nsplit, c->stream);
+    // the prologue's chi^2 shares are those of "step -1"
+    fill_fin_args<T>(c, f, 1, accum, 1);
+    return launch_finalize<T, T>(f, c->stream);
 }
 
 template <typename T>
@@ -513,6 +487,87 @@ static void build_layout(m2m_ctx* c) {
     c->cells = C;
 }
 
+// Equatorial circular orbit of radius r (host, FP64): energy and angular momentum.
+static void host_circular(const m2m_potential& q, double r, double* Ec, double* Lc) {
+    double phi, d1;
+    if (q.kind == M2M_POT_LOG) {
+        const double s2 = q.Rc * q.Rc + r * r;
+        phi = 0.5 * q.v0 * q.v0 * std::log(s2);
+        d1 = q.v0 * q.v0 * r / s2;
+    } else {
+        phi = -q.G * q.M / (r + q.a);
+        d1 = q.G * q.M / ((r + q.a) * (r + q.a));
+        if (q.kind == M2M_POT_HERNQUIST_NFW && q.Mh > 0) {
+            const double l1 = std::log1p(r / q.rs);
+            phi += -q.G * q.Mh * l1 / r;
+            d1 += q.G * q.Mh * (l1 / (r * r) - 1.0 / (r * (r + q.rs)));
+        }
+    }
+    *Ec = phi + 0.5 * r * d1;
+    *Lc = r * std::sqrt(std::max(0.0, r * d1));
+}
+
+// Lc(E) by bisection in ln r on [1e-8, 1e8] (end values outside the bracket).
+static double host_lc(const m2m_potential& q, double E) {
+    double lo = std::log(1e-8), hi = std::log(1e8), Ec, Lc;
+    host_circular(q, std::exp(lo), &Ec, &Lc);
+    if (E <= Ec) return Lc;
+    host_circular(q, std::exp(hi), &Ec, &Lc);
+    if (E >= Ec) return Lc;
+    for (int it = 0; it < 200 && hi - lo > 1e-15; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        host_circular(q, std::exp(mid), &Ec, &Lc);
+        if (Ec < E) lo = mid; else hi = mid;
+    }
+    host_circular(q, std::exp(0.5 * (lo + hi)), &Ec, &Lc);
+    return Lc;
+}
+
+// Uniform-E table of Lc(E) for the FP32 kernels: kLcE pairs (Lc(E_k), bound) per
+// model over [Emin - W/4, Emax + W/4] (W = Emax - Emin; kept below E = 0 for the
+// bound-orbit potentials).  bound is a relative error bound of the FP32 linear
+// interpolation on [E_k, E_k+1]: 4x the largest deviation from the FP64 value at
+// three interior points, plus the FP32 rounding of the table, of the index and of
+// the interpolation.
+template <typename T>
+static m2m_status build_lc_etab(m2m_ctx* c, const std::vector<double>& er) {
+    std::vector<float> tab(2 * (size_t)kLcE * c->M, 0.0f);
+    std::vector<unsigned char> pots(sizeof(Pot<T>) * c->M);
+    HIPCHK(c, hipMemcpy(pots.data(), c->pots_d, pots.size(), hipMemcpyDeviceToHost));
+    for (int m = 0; m < c->M && c->prior.kind != M2M_PRIOR_FLAT; ++m) {
+        const m2m_potential& q = c->pots[m];
+        const double W = er[2 * m + 1] - er[2 * m];
+        double lo = er[2 * m] - 0.25 * W, hi = er[2 * m + 1] + 0.25 * W;
+        if (q.kind != M2M_POT_LOG && hi >= 0.0) hi = -1e-3 * std::fabs(er[2 * m]);
+        if (!(hi > lo)) hi = lo + 1e-6;
+        const double h = (hi - lo) / (kLcE - 1);
+        std::vector<double> L(kLcE);
+        for (int k = 0; k < kLcE; ++k) L[k] = host_lc(q, lo + k * h);
+        for (int k = 0; k < kLcE; ++k) {
+            double err = 1.0;
+            if (k + 1 < kLcE && L[k] > 0 && L[k + 1] > 0) {
+                double dev = 0;
+                for (double f : {0.25, 0.5, 0.75}) {
+                    const double ex = host_lc(q, lo + (k + f) * h);
+                    if (!(ex > 0)) { dev = 1.0; break; }
+                    dev = std::max(dev, std::fabs(L[k] + f * (L[k + 1] - L[k]) - ex) / ex);
+                }
+                const double slope = std::fabs(L[k + 1] - L[k]) / std::min(L[k], L[k + 1]);
+                err = std::min(1.0, 4.0 * dev + 5e-4 * slope + 1e-6);
+            }
+            tab[2 * ((size_t)m * kLcE + k)] = (float)L[k];
+            tab[2 * ((size_t)m * kLcE + k) + 1] = (float)err;
+        }
+        Pot<T> p;
+        std::memcpy(&p, pots.data() + sizeof(Pot<T>) * m, sizeof(p));
+        p.lcE0 = (T)lo;
+        p.lcEinv = (T)(1.0 / h);
+        std::memcpy(pots.data() + sizeof(Pot<T>) * m, &p, sizeof(p));
+    }
+    HIPCHK(c, hipMemcpy(c->pots_d, pots.data(), pots.size(), hipMemcpyHostToDevice));
+    return upload(c, (float**)&c->lcetab, tab);
+}
+
 // ------------------------------------------------------------------- create
 template <typename T>
 static m2m_status create_T(m2m_ctx* c, const m2m_target* tg, const void* xv, const void* w, int dev) {
@@ -567,10 +622,31 @@ static m2m_status create_T(m2m_ctx* c, const m2m_target* tg, const void* xv, con
     if ((s = upload(c, &c->Y, Y)) || (s = upload(c, &c->sigma, sg))) return s;
     if ((s = dalloc(c, &c->y, MJ)) || (s = dalloc(c, &c->ys, MJ)) || (s = dalloc(c, &c->delta, MJ)) ||
         (s = dalloc(c, (T**)&c->cvec, MJ)) || (s = dalloc(c, (T**)&c->cellmean, (size_t)c->M * std::max(1, c->NC))) ||
-        (s = dalloc(c, &c->cellmean64, (size_t)c->M * std::max(1, c->NC))) || (s = dalloc(c, &c->chi2, 2 * (size_t)c->M)) ||
+        (s = dalloc(c, &c->cellmean64, (size_t)c->M * std::max(1, c->NC))) ||
         (s = dalloc(c, &c->ring, (size_t)c->M * kRing)) || (s = dalloc(c, &c->flag, 1)) ||
         (s = dalloc(c, &c->bad_step, 1)) || (s = dalloc(c, &c->d_step, 1)))
         return s;
+    // finalise column chunks (independent of the launch shape): kFinCols columns
+    // of one model each; chi^2 shares double-buffered by step parity
+    {
+        std::vector<int32_t> cm, cc0, cn, mch(c->M + 1);
+        for (int m = 0; m < c->M; ++m) {
+            mch[m] = (int32_t)cm.size();
+            for (int c0 = 0; c0 < c->pcols; c0 += kFinCols) {
+                cm.push_back(m);
+                cc0.push_back(c0);
+                cn.push_back(std::min(kFinCols, c->pcols - c0));
+            }
+        }
+        mch[c->M] = (int32_t)cm.size();
+        c->nchunk = (int)cm.size();
+        c->model_chunk_host = mch;
+        if ((s = upload(c, &c->chunk_model, cm)) || (s = upload(c, &c->chunk_col0, cc0)) ||
+            (s = upload(c, &c->chunk_ncol, cn)) || (s = upload(c, &c->model_chunk, mch)) ||
+            (s = dalloc(c, &c->chunk_chi, 4 * (size_t)c->nchunk)))
+            return s;
+        HIPCHK(c, hipMemset(c->chunk_chi, 0, sizeof(double) * 4 * c->nchunk));
+    }
     HIPCHK(c, hipMemset(c->flag, 0, sizeof(int)));
     HIPCHK(c, hipMemset(c->bad_step, 0, sizeof(long long)));
     HIPCHK(c, hipMemset(c->d_step, 0, sizeof(long long)));
@@ -589,6 +665,7 @@ static m2m_status create_T(m2m_ctx* c, const m2m_target* tg, const void* xv, con
     std::vector<T> erT(er.size());
     for (size_t k = 0; k < er.size(); ++k) erT[k] = (T)er[k];
     if ((s = upload(c, (T**)&c->erange, erT)) || (s = upload(c, &c->erange64, er))) return s;
+    if ((s = build_lc_etab<T>(c, er))) return s;
     HIPCHK(c, launch_prologue_T<T>(c));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     return M2M_OK;
@@ -802,7 +879,16 @@ extern "C" m2m_status m2m_observables(m2m_ctx* c, int32_t model, double* y, doub
     if (y) HIPCHK(c, hipMemcpy(y, c->y + o, n, hipMemcpyDeviceToHost));
     if (ys) HIPCHK(c, hipMemcpy(ys, c->ys + o, n, hipMemcpyDeviceToHost));
     if (delta) HIPCHK(c, hipMemcpy(delta, c->delta + o, n, hipMemcpyDeviceToHost));
-    if (chi2) HIPCHK(c, hipMemcpy(chi2, c->chi2 + 2 * model, sizeof(double), hipMemcpyDeviceToHost));
+    if (chi2) {
+        // chi^2 of the current state: the model's shares from the last finalise
+        const int par = (int)((c->step + 1) & 1);
+        std::vector<double> sh(2 * (size_t)c->nchunk);
+        HIPCHK(c, hipMemcpy(sh.data(), c->chunk_chi + 2 * (size_t)par * c->nchunk, sizeof(double) * sh.size(),
+                            hipMemcpyDeviceToHost));
+        double x2 = 0;
+        for (int k = c->model_chunk_host[model]; k < c->model_chunk_host[model + 1]; ++k) x2 += sh[2 * k];
+        *chi2 = x2;
+    }
     return M2M_OK;
 }
 
@@ -845,6 +931,7 @@ static m2m_status gather_T(m2m_ctx* c, void* out, int dev) {
     a.block_tile0 = c->plan.block_tile0;
     a.pots = (const Pot<T>*)c->pots_d;
     a.lctab = (const T*)c->lctab;
+    a.lcetab = (const float*)c->lcetab;
     a.erange = (const T*)c->erange;
     a.flatw = (const T*)c->flatw;
     a.cellmean = (const T*)c->cellmean;
@@ -944,7 +1031,7 @@ static m2m_status snapshot(m2m_ctx* c, Snapshot& s, bool restore) {
     struct Item { void* p; size_t n; };
     std::vector<Item> items = {{c->state[c->step & 1], 7 * (size_t)c->stride * ts},
                                {c->ys, MJ * 8}, {c->y, MJ * 8}, {c->delta, MJ * 8}, {c->cvec, MJ * ts},
-                               {c->cellmean, MC * ts}, {c->cellmean64, MC * 8}, {c->chi2, 2 * (size_t)c->M * 8},
+                               {c->cellmean, MC * ts}, {c->cellmean64, MC * 8}, {c->chunk_chi, 4 * (size_t)c->nchunk * 8},
                                {c->ring, sizeof(StatRow) * (size_t)c->M * kRing}, {c->d_step, 8}};
     if (c->what) items.push_back({c->what, (size_t)c->stride * ts});
     if (!restore) {

@@ -20,7 +20,8 @@ namespace m2m {
 
 constexpr int kMaxBin = 4;
 constexpr int kMaxEntries = 3 * kMaxBin;   // kernel entries K_j per particle (fixed slots)
-constexpr int kLcTab = 256;                // circular-orbit energies per model
+constexpr int kLcTab = 256;                // circular-orbit energies per model (FP64 path)
+constexpr int kLcE = 1024;                 // uniform-E Lc(E) table per model (FP32 path)
 constexpr float kGuardBin = 1e-4f;         // guard band, in bins, of the FP32 bin coordinates
 constexpr float kGuardCell = 3e-4f;        // guard band, in cells, of the FP32 prior coordinates
 
@@ -32,6 +33,7 @@ struct Pot {
     T GM, a;            // Hernquist
     T v2, Rc2, iq2;     // logarithmic: v0^2, Rc^2, 1/q^2
     T GMh, rs, irs;     // NFW halo
+    T lcE0, lcEinv;     // uniform-E Lc table: first energy, 1 / spacing
 };
 
 // Observation layout.  sx, sy = n / width give the fast FP32 bin coordinate;
@@ -73,14 +75,20 @@ template <typename T> __device__ __forceinline__ T dsqrt(T v) { return sqrt(v); 
 template <typename T> __device__ __forceinline__ T dlog(T v) { return log(v); }
 template <typename T> __device__ __forceinline__ T dexp(T v) { return exp(v); }
 template <typename T> __device__ __forceinline__ T dlog1p(T v) { return log1p(v); }
+// Fast forms for quantities that only feed guarded decisions or the orbit
+// integration (a few ulp in FP32; exact IEEE forms in FP64).
+__device__ __forceinline__ float qdiv(float a, float b) { return __fdividef(a, b); }
+__device__ __forceinline__ double qdiv(double a, double b) { return a / b; }
+__device__ __forceinline__ float qlog(float v) { return __logf(v); }
+__device__ __forceinline__ double qlog(double v) { return log(v); }
 
 // Phi(x) and a = -grad Phi.  POT is the compile-time potential kind.
 template <int POT, typename T>
 __device__ __forceinline__ void potential(const Pot<T>& p, T x, T y, T z, T& phi, T& ax, T& ay, T& az) {
     if (POT == 1) {   // logarithmic
         const T s = p.Rc2 + x * x + y * y + z * z * p.iq2;
-        const T f = p.v2 / s;
-        phi = T(0.5) * p.v2 * dlog(s);
+        const T f = qdiv(p.v2, s);
+        phi = T(0.5) * p.v2 * qlog(s);
         ax = -f * x;
         ay = -f * y;
         az = -f * z * p.iq2;
@@ -89,8 +97,8 @@ __device__ __forceinline__ void potential(const Pot<T>& p, T x, T y, T z, T& phi
     const T r2 = x * x + y * y + z * z;
     const T r = dsqrt(r2);
     const T u = r + p.a;
-    T ph = -p.GM / u;
-    T g_over_r = r > T(0) ? p.GM / (u * u * r) : T(0);   // (dPhi/dr)/r
+    T ph = -qdiv(p.GM, u);
+    T g_over_r = r > T(0) ? qdiv(p.GM, u * u * r) : T(0);   // (dPhi/dr)/r
     if (POT == 2 && p.GMh > T(0)) {
         const T xx = r * p.irs;
         const T l1 = dlog1p(xx);
@@ -229,24 +237,48 @@ __device__ __noinline__ int prior_cell_exact(const Pot<double>* __restrict__ pot
     return prior_cell_f64<POT>(p, lctab + p.lc_off, c, erange[2 * m], erange[2 * m + 1], x, y, z, vx, vy, vz);
 }
 
+// Lc(E) of an FP32 kernel from the model's uniform-E table in LDS: pairs
+// (Lc(E_k), bound) at E_k = E0 + k / invh, k < kLcE; bound is the relative error
+// of linear interpolation on [E_k, E_k+1] (measured on the host in FP64, with a
+// safety factor).  Returns false outside the table.
+__device__ __forceinline__ bool lc_from_table(const float2* __restrict__ et, float E0, float invh, float E, float& Lc,
+                                              float& err) {
+    const float t = (E - E0) * invh;
+    if (!(t >= 0.0f) || !(t < float(kLcE - 1))) return false;
+    const int k = int(t);
+    const float f = t - float(k);
+    const float2 a = et[k], b = et[k + 1];
+    Lc = a.x + f * (b.x - a.x);
+    err = a.y;
+    return true;
+}
+
 // Cell of the moving prior for a particle of energy E (FP32 decision with an
 // FP64 re-decision inside the guard band; FP64 kernels decide in FP64).
 template <int POT, typename T>
-__device__ __forceinline__ int prior_cell(const Pot<T>& p, const T* __restrict__ tab, const Cells& c, T Emin, T sE,
-                                          T E, T x, T y, T z, T vx, T vy, T vz, const Exact& ex, int m) {
+__device__ __forceinline__ int prior_cell(const Pot<T>& p, const T* __restrict__ tab, const float2* __restrict__ et,
+                                          const Cells& c, T Emin, T sE, T E, T x, T y, T z, T vx, T vy, T vz,
+                                          const Exact& ex, int m) {
     if constexpr (sizeof(T) == 8) {
+        (void)et;
         return prior_cell_f64<POT>(p, tab, c, ex.erange[2 * m], ex.erange[2 * m + 1], x, y, z, vx, vy, vz);
     } else {
         const T Lx = y * vz - z * vy, Ly = z * vx - x * vz, Lz = x * vy - y * vx;
         const T L = dsqrt(Lx * Lx + Ly * Ly + Lz * Lz);
-        const T Lc = circular_L<POT, T, 2>(p, tab, E);
+        T Lc, err = T(2e-6);
+        bool ok = true;
+        if (POT == 0) Lc = circular_L<POT, T, 2>(p, tab, E);
+        else ok = lc_from_table(et, p.lcE0, p.lcEinv, E, Lc, err);
         const T fE = (E - Emin) * sE;
         T f2;
-        if (c.ax2 == 0) f2 = (Lc > T(0) ? L / Lc : (Lc < T(0) ? T(0) : T(1e30))) * T(c.n1);
-        else f2 = ((Lc > T(0) ? Lz / Lc : (Lc < T(0) ? T(0) : (Lz > T(0) ? T(1e30) : T(-1e30)))) + T(1)) * T(0.5) * T(c.n1);
-        const T f3 = c.n2 > 1 ? ((L > T(0) ? Lz / L : T(0)) + T(1)) * T(0.5) * T(c.n2) : T(0.5);
-        bool unsure = near_cell_edge(fE, c.n0, kGuardCell) || near_cell_edge(f2, c.n1, kGuardCell) ||
-                      (c.n2 > 1 && near_cell_edge(f3, c.n2, kGuardCell)) || !(Lc > T(0));
+        const T iLc = Lc > T(0) ? qdiv(T(1), Lc) : T(0);
+        if (c.ax2 == 0) f2 = (Lc > T(0) ? L * iLc : (Lc < T(0) ? T(0) : T(1e30))) * T(c.n1);
+        else f2 = ((Lc > T(0) ? Lz * iLc : (Lc < T(0) ? T(0) : (Lz > T(0) ? T(1e30) : T(-1e30)))) + T(1)) * T(0.5) * T(c.n1);
+        const T f3 = c.n2 > 1 ? ((L > T(0) ? qdiv(Lz, L) : T(0)) + T(1)) * T(0.5) * T(c.n2) : T(0.5);
+        // a relative error err of Lc moves f2 by at most (|f2| + n1) err
+        const T g2 = T(kGuardCell) + (fabsf(f2) + T(c.n1)) * err;
+        bool unsure = !ok || !(Lc > T(0)) || near_cell_edge(fE, c.n0, kGuardCell) || near_cell_edge(f2, c.n1, g2) ||
+                      (c.n2 > 1 && near_cell_edge(f3, c.n2, kGuardCell));
         if (unsure)
             return prior_cell_exact<POT>(ex.pots, ex.lctab, ex.erange, m, c.n0, c.n1, c.n2, c.ax2, double(x), double(y),
                                          double(z), double(vx), double(vy), double(vz));

@@ -1,0 +1,161 @@
+// finalize.hip -- per-step reduction of the fused kernel's partial histograms.
+//
+// After step kernel n every (block, model) pair has written its LDS histograms
+// to one partial slot.  finalize_kernel sums the slots of each column in a
+// fixed order and applies, per observable j (paper section 2 and eq. 1):
+//   y_j(n+1), ys_j <- ys_j + (dt/tau) (y_j - ys_j) (ys = y at the first
+//   observe), Dt_j = (ys_j - Y_j)/sigma_j, the update table Dt_j/sigma_j and the
+//   chunk's share of chi^2 = sum Dt_j^2;
+// and per prior cell (section 2.1) the mean weight sum/count.
+// Blocks never wait for each other: column blocks write per-chunk chi^2 shares
+// (double-buffered by step parity), and one extra block assembles the
+// statistics row of step n from the previous finalise's chi^2 shares and step
+// kernel n's per-slot sums, then advances the device step counter.
+#include "runtime.h"
+
+namespace m2m {
+
+template <typename T>
+__device__ __forceinline__ T fwave_sum(T v) {
+    #pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+template <typename T, typename PT>
+__global__ void __launch_bounds__(256) finalize_kernel(FinArgs<T, PT> a) {
+    __shared__ double part[kFinGroups][kFinCols + 1];
+    __shared__ double tot[kFinCols];
+    __shared__ double red[4][8];
+    if (*a.flag) return;   // the step failed: leave every output as it was
+    const int tid = threadIdx.x;
+    double* chi_out = a.chunk_chi + (size_t)(a.parity) * 2 * a.nchunk;
+    const double* chi_prev = a.chunk_chi + (size_t)(a.parity ^ 1) * 2 * a.nchunk;
+
+    if ((int)blockIdx.x < a.nchunk) {
+        // ------------------------------------------------ column block
+        const int chunk = blockIdx.x;
+        const int m = a.chunk_model[chunk];
+        const int col0 = a.chunk_col0[chunk];
+        const int ncol = a.chunk_ncol[chunk];
+        const int s0 = a.model_slot[m], ns = a.model_slot[m + 1] - s0;
+        const int g = tid / kFinCols, c = tid % kFinCols;
+        const int col = col0 + c;
+        const bool live = c < ncol && (col < a.J || (col >= a.jpad && a.accum_cells));
+        const int per = (ns + kFinGroups - 1) / kFinGroups;
+        const int sa = s0 + g * per, sb = min(s0 + ns, sa + per);
+        double acc = 0;
+        if (live) {
+            const PT* src = a.part + col;
+            for (int r = sa; r < sb; r += kSlotsPerSplit) {
+                // a whole round of slots in flight before the first add
+                PT v[kSlotsPerSplit];
+                #pragma unroll
+                for (int k = 0; k < kSlotsPerSplit; ++k) v[k] = r + k < sb ? src[(size_t)(r + k) * a.pcols] : PT(0);
+                #pragma unroll
+                for (int k = 0; k < kSlotsPerSplit; ++k) acc += double(v[k]);
+            }
+        }
+        part[g][c] = acc;
+        __syncthreads();
+        double chi = 0, chii = 0;
+        if (g == 0) {
+            double v = 0;
+            #pragma unroll
+            for (int k = 0; k < kFinGroups; ++k) v += part[k][c];
+            tot[c] = v;
+        }
+        __syncthreads();
+        if (g == 0 && live) {
+            const double v = tot[c];
+            if (col < a.J) {
+                const size_t j = (size_t)m * a.J + col;
+                const double ys = a.first ? v : a.ys[j] + a.g * (v - a.ys[j]);
+                const double d = (ys - a.Y[j]) / a.sigma[j];
+                const double di = (v - a.Y[j]) / a.sigma[j];
+                a.y[j] = v;
+                a.ys[j] = ys;
+                a.delta[j] = d;
+                a.cvec[j] = T(d / a.sigma[j]);
+                chi = d * d;
+                chii = di * di;
+            } else if (((col - a.jpad) & 1) == 0) {
+                // (sum, count) pairs never straddle a chunk: chunks start at
+                // multiples of kFinCols and the cell region at an even column
+                const int cell = (col - a.jpad) >> 1;
+                const double cnt = tot[c + 1];
+                const double mean = cnt > 0 ? v / cnt : 0.0;
+                a.cellmean[(size_t)m * a.ncell + cell] = T(mean);
+                a.cellmean64[(size_t)m * a.ncell + cell] = mean;
+            }
+        }
+        if (tid < 64) {
+            chi = fwave_sum(chi);
+            chii = fwave_sum(chii);
+            if (tid == 0) {
+                chi_out[2 * chunk] = chi;
+                chi_out[2 * chunk + 1] = chii;
+            }
+        }
+        return;
+    }
+
+    // ---------------------------------------------------- statistics block
+    if (a.first) return;
+    const long long n = *a.d_step;
+    for (int m = 0; m < a.n_models; ++m) {
+        double x2 = 0, x2i = 0, S = 0, W = 0, W2 = 0, mn = INFINITY;
+        for (int k = a.model_chunk[m] + tid; k < a.model_chunk[m + 1]; k += 256) {
+            x2 += chi_prev[2 * k];
+            x2i += chi_prev[2 * k + 1];
+        }
+        for (int s = a.model_slot[m] + tid; s < a.model_slot[m + 1]; s += 256) {
+            S += a.seg_stats[4 * s];
+            W += a.seg_stats[4 * s + 1];
+            W2 += a.seg_stats[4 * s + 2];
+            mn = fmin(mn, a.seg_stats[4 * s + 3]);
+        }
+        x2 = fwave_sum(x2); x2i = fwave_sum(x2i); S = fwave_sum(S); W = fwave_sum(W); W2 = fwave_sum(W2);
+        #pragma unroll
+        for (int o = 32; o > 0; o >>= 1) mn = fmin(mn, __shfl_xor(mn, o, 64));
+        __shared__ double sred[6][4];
+        if ((tid & 63) == 0) {
+            const int w = tid >> 6;
+            sred[0][w] = x2; sred[1][w] = x2i; sred[2][w] = S; sred[3][w] = W; sred[4][w] = W2; sred[5][w] = mn;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            const double X2 = (sred[0][0] + sred[0][1]) + (sred[0][2] + sred[0][3]);
+            const double X2i = (sred[1][0] + sred[1][1]) + (sred[1][2] + sred[1][3]);
+            const double Ss = (sred[2][0] + sred[2][1]) + (sred[2][2] + sred[2][3]);
+            const double Ws = (sred[3][0] + sred[3][1]) + (sred[3][2] + sred[3][3]);
+            const double W2s = (sred[4][0] + sred[4][1]) + (sred[4][2] + sred[4][3]);
+            const double mns = fmin(fmin(sred[5][0], sred[5][1]), fmin(sred[5][2], sred[5][3]));
+            StatRow* r = a.ring + (size_t)m * kRing + (n % kRing);
+            r->chi2 = X2;
+            r->chi2_inst = X2i;
+            r->S = Ss;
+            r->F = -0.5 * X2 + a.mu * Ss;
+            r->sum_w = Ws;
+            r->min_w = mns;
+            r->sum_w2 = W2s;
+            r->n_eff = Ws * Ws / W2s;
+            r->step = n;
+            r->model = m;
+        }
+        __syncthreads();
+    }
+    if (tid == 0) *a.d_step = n + 1;
+    (void)red;
+}
+
+template <typename T, typename PT>
+hipError_t launch_finalize(const FinArgs<T, PT>& a, hipStream_t s) {
+    hipLaunchKernelGGL((finalize_kernel<T, PT>), dim3(a.nchunk + 1), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+template hipError_t launch_finalize<float, float>(const FinArgs<float, float>&, hipStream_t);
+template hipError_t launch_finalize<double, double>(const FinArgs<double, double>&, hipStream_t);
+
+}  // namespace m2m

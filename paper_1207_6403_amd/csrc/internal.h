@@ -12,7 +12,7 @@
 struct Plan {
     int threads = 0, ilp = 0, bpc = 0;
     int64_t ntile = 0;
-    int nblock = 0, nslot = 0, nchunk = 0, nsplit = 0;
+    int nblock = 0, nslot = 0;
     size_t lds = 0;
     int32_t* tile_model = nullptr;
     int64_t* tile_p0 = nullptr;
@@ -20,17 +20,8 @@ struct Plan {
     int32_t* block_tile0 = nullptr;
     int32_t* block_slot0 = nullptr;
     int32_t* model_slot = nullptr;
-    int32_t* chunk_model = nullptr;
-    int32_t* chunk_col0 = nullptr;
-    int32_t* chunk_ncol = nullptr;
-    int32_t* model_chunk = nullptr;
     void* part = nullptr;
     double* seg_stats = nullptr;
-    double* l2 = nullptr;
-    int* chunk_cnt = nullptr;
-    double* chunk_chi = nullptr;
-    int* model_cnt = nullptr;
-    int* all_cnt = nullptr;
     double* erange_out = nullptr;
 };
 
@@ -58,6 +49,7 @@ struct m2m_ctx {
     void* pots_d = nullptr;
     void* pots64 = nullptr;
     void* lctab = nullptr;
+    void* lcetab = nullptr;
     double* lctab64 = nullptr;
     double* erange64 = nullptr;
     double* edges64 = nullptr;
@@ -69,7 +61,14 @@ struct m2m_ctx {
     void* scratch_n = nullptr;
     double *Y = nullptr, *sigma = nullptr, *y = nullptr, *ys = nullptr, *delta = nullptr;
     double* cellmean64 = nullptr;
-    double* chi2 = nullptr;
+    // finalise column chunks (launch-shape independent) and chi^2 shares
+    int nchunk = 0;
+    int32_t* chunk_model = nullptr;
+    int32_t* chunk_col0 = nullptr;
+    int32_t* chunk_ncol = nullptr;
+    int32_t* model_chunk = nullptr;
+    std::vector<int32_t> model_chunk_host;
+    double* chunk_chi = nullptr;
     m2m::StatRow* ring = nullptr;
     int* flag = nullptr;
     long long* bad_step = nullptr;

@@ -9,8 +9,9 @@
 namespace m2m {
 
 constexpr int kRing = 4096;          // statistics rows kept per model
-constexpr int kSlotsPerSplit = 32;   // partial slots summed by one finalise block
-constexpr int kMaxSplit = 32;        // finalise blocks per column chunk (<= 1024 slots)
+constexpr int kSlotsPerSplit = 32;   // partial slots in flight per finalise thread
+constexpr int kFinCols = 32;         // columns per finalise block
+constexpr int kFinGroups = 8;        // slot groups per column (256 threads)
 
 struct StatRow {
     double chi2, chi2_inst, S, F, sum_w, min_w, sum_w2, n_eff;
@@ -32,6 +33,7 @@ struct StepArgs {
     const int32_t* block_slot0;   // first partial slot of each block
     const Pot<T>* pots;           // per model
     const T* lctab;               // kLcTab circular-orbit energies per model
+    const float* lcetab;          // kLcE (Lc, error bound) pairs per model (FP32 path)
     const T* erange;              // 2 per model
     const T* flatw;               // per model
     const T* cvec;                // M * J: Dt_j / sigma_j
@@ -63,11 +65,9 @@ struct FinArgs {
     const int32_t* chunk_ncol;
     const int32_t* model_slot;    // M + 1
     const int32_t* model_chunk;   // M + 1
-    double* l2;                   // nchunk * nsplit * 256
-    int* chunk_cnt;
-    double* chunk_chi;            // 2 * nchunk
-    int* model_cnt;
-    int* all_cnt;
+    int32_t nchunk;
+    int32_t parity;               // chi^2 shares go to chunk_chi[parity]
+    double* chunk_chi;            // 2 (parity) * 2 * nchunk: chi2, chi2_inst shares
     const double* Y;
     const double* sigma;
     double* y;
@@ -76,7 +76,6 @@ struct FinArgs {
     T* cvec;
     T* cellmean;
     double* cellmean64;
-    double* chi2;                 // 2 * M: chi2, chi2_inst of the current state
     const double* seg_stats;
     StatRow* ring;
     double g, mu;
@@ -111,6 +110,7 @@ struct GatherArgs {
     const int32_t* block_tile0;
     const Pot<T>* pots;
     const T* lctab;
+    const float* lcetab;
     const T* erange;
     const T* flatw;
     const T* cellmean;
@@ -125,7 +125,7 @@ hipError_t launch_step(const StepArgs<T, PT>& a, int pot_kind, int ilp, int bloc
 template <typename T, typename PT>
 hipError_t set_step_lds_limit(int pot_kind, size_t lds);
 template <typename T, typename PT>
-hipError_t launch_finalize(const FinArgs<T, PT>& a, int nchunk, int nsplit, hipStream_t s);
+hipError_t launch_finalize(const FinArgs<T, PT>& a, hipStream_t s);
 template <typename T>
 hipError_t launch_erange(const ErangeArgs<T>& a, int pot_kind, int blocks, hipStream_t s);
 template <typename T>

@@ -10,11 +10,7 @@
 // When a block moves to another model (batched form) or finishes, it writes
 // its LDS histograms to its own partial slot (no atomics, deterministic).
 //
-// finalize_kernel then sums the partial slots column by column (split over
-// blocks, fixed order), applies the temporal smoothing, deviations, chi^2 and
-// the prior cell means, and -- in the last block of each model, chosen by an
-// atomic arrival counter (no block ever waits) -- writes the statistics row and
-// advances the step counter.
+// finalize.hip then sums the partial slots column by column in a fixed order.
 #include "runtime.h"
 
 namespace m2m {
@@ -56,7 +52,9 @@ __global__ void __launch_bounds__(sizeof(T) == 8 ? 256 : 512) step_kernel(StepAr
     double* csum = hist + JP;                                        // NC
     double* ed64 = csum + NC;                                        // edges, FP64
     double* red = ed64 + NE;                                         // 4 * 16
-    unsigned* ccnt = reinterpret_cast<unsigned*>(red + 64);          // NC (padded to even)
+    const int NET = (sizeof(T) == 4 && NC) ? kLcE : 0;
+    float2* et = reinterpret_cast<float2*>(red + 64);                // uniform-E Lc table (FP32)
+    unsigned* ccnt = reinterpret_cast<unsigned*>(et + NET);          // NC (padded to even)
     T* cl = reinterpret_cast<T*>(ccnt + ((NC + 1) & ~1));            // J : Dt_j / sigma_j
     T* cm = cl + JP;                                                 // NC: cell means
     T* ed = cm + ((NC + 1) & ~1);                                    // edges in T
@@ -101,6 +99,8 @@ __global__ void __launch_bounds__(sizeof(T) == 8 ? 256 : 512) step_kernel(StepAr
             if (a.accum_cells) for (int c = tid; c < NC; c += nt) { csum[c] = 0.0; ccnt[c] = 0u; }
             if (want_cm) for (int c = tid; c < NC; c += nt) cm[c] = a.cellmean[(size_t)m * NC + c];
             if (NC) for (int i = tid; i < kLcTab; i += nt) lct[i] = a.lctab[(size_t)pot.lc_off + i];
+            for (int i = tid; i < NET; i += nt)
+                et[i] = make_float2(a.lcetab[2 * ((size_t)m * kLcE + i)], a.lcetab[2 * ((size_t)m * kLcE + i) + 1]);
             __syncthreads();
         }
         const int64_t p0 = a.tile_p0[t];
@@ -135,7 +135,7 @@ __global__ void __launch_bounds__(sizeof(T) == 8 ? 256 : 512) step_kernel(StepAr
                     wh = wflat;
                 } else if (want_cm) {
                     const T E = T(0.5) * (vx * vx + vy * vy + vz * vz) + phi;
-                    const int c = prior_cell<POT, T>(pot, lct, a.cells, Emin, sE, E, x, y, z, vx, vy, vz, a.ex, m);
+                    const int c = prior_cell<POT, T>(pot, lct, et, a.cells, Emin, sE, E, x, y, z, vx, vy, vz, a.ex, m);
                     wh = cm[c];
                     if (a.what_mode == 2) a.what[p] = wh;
                 } else {
@@ -184,7 +184,7 @@ __global__ void __launch_bounds__(sizeof(T) == 8 ? 256 : 512) step_kernel(StepAr
                     if (jj[e] >= 0) atomicAdd(&hist[jj[e]], double(w * K[e]));
                 if (a.accum_cells) {
                     const T E = T(0.5) * (vx * vx + vy * vy + vz * vz) + phi;
-                    const int c = prior_cell<POT, T>(pot, lct, a.cells, Emin, sE, E, x, y, z, vx, vy, vz, a.ex, m);
+                    const int c = prior_cell<POT, T>(pot, lct, et, a.cells, Emin, sE, E, x, y, z, vx, vy, vz, a.ex, m);
                     atomicAdd(&csum[c], double(w));
                     atomicAdd(&ccnt[c], 1u);
                 }
@@ -194,155 +194,6 @@ __global__ void __launch_bounds__(sizeof(T) == 8 ? 256 : 512) step_kernel(StepAr
     if (bad) {
         __hip_atomic_fetch_or(a.flag, (int)bad, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         *a.bad_step = *a.d_step;
-    }
-}
-
-// ------------------------------------------------------------------ finalize
-template <typename T, typename PT>
-__global__ void __launch_bounds__(256) finalize_kernel(FinArgs<T, PT> a) {
-    __shared__ double tot[256];
-    __shared__ double red[8];
-    __shared__ int last;
-    if (*a.flag) return;
-    const int chunk = blockIdx.x, split = blockIdx.y, S = gridDim.y;
-    const int m = a.chunk_model[chunk];
-    const int col0 = a.chunk_col0[chunk];
-    const int ncol = a.chunk_ncol[chunk];
-    const int s0 = a.model_slot[m], ns = a.model_slot[m + 1] - s0;
-    const int per = (ns + S - 1) / S;
-    const int sa = s0 + split * per, sb = min(s0 + ns, sa + per);
-    const int c = threadIdx.x;
-    const int J = a.J;
-    // column kinds: observables [0, J), padding [J, jpad), cell (sum, count) pairs after
-    const bool live = c < ncol && (col0 + c < J || (col0 + c >= a.jpad && a.accum_cells));
-    // level 1: this split's slots, fixed order
-    if (live) {
-        // at most kSlotsPerSplit slots: issue every load before the first add so the
-        // whole column is in flight at once
-        const PT* src = a.part + col0 + c;
-        PT v[kSlotsPerSplit];
-        #pragma unroll
-        for (int k = 0; k < kSlotsPerSplit; ++k) v[k] = sa + k < sb ? src[(size_t)(sa + k) * a.pcols] : PT(0);
-        double acc = 0;
-        #pragma unroll
-        for (int k = 0; k < kSlotsPerSplit; ++k) acc += double(v[k]);
-        a.l2[((size_t)chunk * S + split) * 256 + c] = acc;
-    }
-    __threadfence();
-    __syncthreads();
-    if (c == 0) last = __hip_atomic_fetch_add(a.chunk_cnt + chunk, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) == S - 1;
-    __syncthreads();
-    if (!last) return;
-    __threadfence();
-    // level 2: the chunk's column totals
-    double v = 0;
-    if (live) {
-        double pv[kMaxSplit];
-        #pragma unroll
-        for (int s = 0; s < kMaxSplit; ++s)
-            pv[s] = s < S ? __hip_atomic_load(a.l2 + ((size_t)chunk * S + s) * 256 + c, __ATOMIC_RELAXED,
-                                              __HIP_MEMORY_SCOPE_AGENT)
-                          : 0.0;
-        #pragma unroll
-        for (int s = 0; s < kMaxSplit; ++s) v += pv[s];
-    }
-    tot[c] = v;
-    __syncthreads();
-    double chi = 0, chii = 0;
-    if (live) {
-        const int col = col0 + c;
-        if (col < J) {
-            const size_t j = (size_t)m * J + col;
-            const double y = v;
-            const double ys = a.first ? y : a.ys[j] + a.g * (y - a.ys[j]);
-            const double d = (ys - a.Y[j]) / a.sigma[j];
-            const double di = (y - a.Y[j]) / a.sigma[j];
-            a.y[j] = y;
-            a.ys[j] = ys;
-            a.delta[j] = d;
-            a.cvec[j] = T(d / a.sigma[j]);
-            chi = d * d;
-            chii = di * di;
-        } else if (((col - a.jpad) & 1) == 0) {
-            const int cell = (col - a.jpad) >> 1;
-            const double cnt = tot[c + 1];
-            const double mean = cnt > 0 ? v / cnt : 0.0;
-            a.cellmean[(size_t)m * a.ncell + cell] = T(mean);
-            a.cellmean64[(size_t)m * a.ncell + cell] = mean;
-        }
-    }
-    chi = wave_sum(chi);
-    chii = wave_sum(chii);
-    if ((c & 63) == 0) { red[2 * (c >> 6)] = chi; red[2 * (c >> 6) + 1] = chii; }
-    __syncthreads();
-    if (c == 0) {
-        a.chunk_chi[2 * chunk] = (red[0] + red[2]) + (red[4] + red[6]);
-        a.chunk_chi[2 * chunk + 1] = (red[1] + red[3]) + (red[5] + red[7]);
-        a.chunk_cnt[chunk] = 0;
-    }
-    __threadfence();
-    __syncthreads();
-    if (c == 0) last = __hip_atomic_fetch_add(a.model_cnt + m, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) ==
-                       a.model_chunk[m + 1] - a.model_chunk[m] - 1;
-    __syncthreads();
-    if (!last) return;
-    __threadfence();
-    // model finaliser: chi^2 of the new state and the statistics of the step just
-    // taken, reduced over the model's chunks and slots by the whole block in a fixed
-    // order (thread c takes chunks / slots c, c + 256, ...)
-    double x2 = 0, x2i = 0, sS = 0, sW = 0, sW2 = 0, smn = INFINITY;
-    for (int k = a.model_chunk[m] + c; k < a.model_chunk[m + 1]; k += 256) {
-        x2 += __hip_atomic_load(a.chunk_chi + 2 * k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        x2i += __hip_atomic_load(a.chunk_chi + 2 * k + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-    if (!a.first)
-        for (int s = s0 + c; s < s0 + ns; s += 256) {
-            sS += a.seg_stats[4 * s];
-            sW += a.seg_stats[4 * s + 1];
-            sW2 += a.seg_stats[4 * s + 2];
-            smn = fmin(smn, a.seg_stats[4 * s + 3]);
-        }
-    __shared__ double mred[6][4];
-    x2 = wave_sum(x2); x2i = wave_sum(x2i); sS = wave_sum(sS); sW = wave_sum(sW); sW2 = wave_sum(sW2);
-    smn = wave_min(smn);
-    if ((c & 63) == 0) {
-        const int wv = c >> 6;
-        mred[0][wv] = x2; mred[1][wv] = x2i; mred[2][wv] = sS; mred[3][wv] = sW; mred[4][wv] = sW2; mred[5][wv] = smn;
-    }
-    __syncthreads();
-    if (c == 0) {
-        x2 = (mred[0][0] + mred[0][1]) + (mred[0][2] + mred[0][3]);
-        x2i = (mred[1][0] + mred[1][1]) + (mred[1][2] + mred[1][3]);
-        const long long n = *a.d_step;
-        if (!a.first) {
-            const double S = (mred[2][0] + mred[2][1]) + (mred[2][2] + mred[2][3]);
-            const double W = (mred[3][0] + mred[3][1]) + (mred[3][2] + mred[3][3]);
-            const double W2 = (mred[4][0] + mred[4][1]) + (mred[4][2] + mred[4][3]);
-            const double mn = fmin(fmin(mred[5][0], mred[5][1]), fmin(mred[5][2], mred[5][3]));
-            StatRow* r = a.ring + (size_t)m * kRing + (n % kRing);
-            r->chi2 = a.chi2[2 * m];
-            r->chi2_inst = a.chi2[2 * m + 1];
-            r->S = S;
-            r->F = -0.5 * a.chi2[2 * m] + a.mu * S;
-            r->sum_w = W;
-            r->min_w = mn;
-            r->sum_w2 = W2;
-            r->n_eff = W * W / W2;
-            r->step = n;
-            r->model = m;
-        }
-        a.chi2[2 * m] = x2;
-        a.chi2[2 * m + 1] = x2i;
-        a.model_cnt[m] = 0;
-    }
-    __threadfence();
-    __syncthreads();
-    if (c == 0) {
-        const bool all = __hip_atomic_fetch_add(a.all_cnt, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) == a.n_models - 1;
-        if (all) {
-            if (!a.first) *a.d_step = *a.d_step + 1;
-            *a.all_cnt = 0;
-        }
     }
 }
 
@@ -416,7 +267,8 @@ __global__ void __launch_bounds__(256) gather_kernel(GatherArgs<T> a) {
                 potential<POT, T>(pot, x, y, z, phi, ax, ay, az);
                 const T E = T(0.5) * (vx * vx + vy * vy + vz * vz) + phi;
                 wh = a.cellmean[(size_t)m * a.cells.ncell +
-                                prior_cell<POT, T>(pot, lct, a.cells, Emin, sE, E, x, y, z, vx, vy, vz, a.ex, m)];
+                                prior_cell<POT, T>(pot, lct, (const float2*)a.lcetab + (size_t)m * kLcE, a.cells,
+                                                   Emin, sE, E, x, y, z, vx, vy, vz, a.ex, m)];
             }
             a.out[p] = wh;
         }
@@ -471,11 +323,6 @@ hipError_t set_step_lds_limit(int pot_kind, size_t lds) {
     return hipSuccess;
 }
 
-template <typename T, typename PT>
-hipError_t launch_finalize(const FinArgs<T, PT>& a, int nchunk, int nsplit, hipStream_t s) {
-    hipLaunchKernelGGL((finalize_kernel<T, PT>), dim3(nchunk, nsplit), dim3(256), 0, s, a);
-    return hipGetLastError();
-}
 
 template <typename T>
 hipError_t launch_erange(const ErangeArgs<T>& a, int pot_kind, int blocks, hipStream_t s) {
@@ -491,8 +338,6 @@ template hipError_t launch_step<float, float>(const StepArgs<float, float>&, int
 template hipError_t launch_step<double, double>(const StepArgs<double, double>&, int, int, int, int, size_t, hipStream_t);
 template hipError_t set_step_lds_limit<float, float>(int, size_t);
 template hipError_t set_step_lds_limit<double, double>(int, size_t);
-template hipError_t launch_finalize<float, float>(const FinArgs<float, float>&, int, int, hipStream_t);
-template hipError_t launch_finalize<double, double>(const FinArgs<double, double>&, int, int, hipStream_t);
 template hipError_t launch_erange<float>(const ErangeArgs<float>&, int, int, hipStream_t);
 template hipError_t launch_erange<double>(const ErangeArgs<double>&, int, int, hipStream_t);
 
