@@ -181,8 +181,8 @@ typedef struct {
  * m2m_step launch without graphs and bracket every fused step kernel with HIP
  * events on the context's stream (read with m2m_kernel_time). */
 typedef struct {
-    int32_t threads;        /* 64..512, multiple of 64 (FP64: at most 256) */
-    int32_t ilp;            /* particles per thread per tile: 1, 2, 4       */
+    int32_t threads;        /* 64..1024, multiple of 64 (FP64: at most 256) */
+    int32_t ilp;            /* particles per thread per tile: 1 or 2        */
     int32_t blocks_per_cu;  /* blocks per compute unit (grid = CUs x this)  */
     int32_t graph_steps;    /* steps captured per HIP graph (0: none)       */
     int32_t timing;

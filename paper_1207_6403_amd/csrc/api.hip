@@ -3,8 +3,10 @@
 //
 // Device memory (HBM) layout of a context, N particles over all models:
 //   state[2]  ping-pong particle buffers, 7 SoA rows of `stride` values
-//             (x y z vx vy vz w); step n reads state[n & 1], writes the other,
-//             so a failed step leaves the last good state untouched;
+//             (x y z vx vy vz w) then nbin + 1 rows of `stride` uint16 tags
+//             (the bin of each binning and the prior cell of the particle);
+//             step n reads state[n & 1], writes the other, so a failed step
+//             leaves the last good state untouched;
 //   what      per-particle priors (periodic and learned priors only);
 //   per model observables y, ys, delta (FP64, J each), the FP32/FP64 update
 //             table Dt_j/sigma_j, prior cell means, chi^2, a statistics ring;
@@ -130,6 +132,7 @@ static m2m_status validate(const m2m_config* cfg, const m2m_obs_layout* lay, con
         } else {
             return fail(nullptr, M2M_ERR_INVALID, "unknown binning kind");
         }
+        if (nb > 65534) return fail(nullptr, M2M_ERR_UNSUPPORTED, "at most 65534 bins per binning");
         J += d.nmom * nb;
     }
     if (ne > M2M_MAX_EDGES) return fail(nullptr, M2M_ERR_INVALID, "too many edges (max 256)");
@@ -228,7 +231,7 @@ static m2m_status make_plan(m2m_ctx* c, int threads, int ilp, int bpc) {
         return s;
     HIPCHK(c, hipMemset(p.part, 0, (size_t)nslot * c->pcols * tsize(c)));
     // LDS of the fused kernel: histograms, cell sums/counts, update table,
-    // cell means, edges, reduction scratch
+    // cell means, edges, reduction scratch, Lc table
     const size_t ts = tsize(c);
     const int NCe = (c->NC + 1) & ~1, NE = (c->nedge + 1) & ~1;
     const int NET = (ts == 4 && c->NC) ? kLcE : 0;
@@ -241,13 +244,39 @@ static m2m_status make_plan(m2m_ctx* c, int threads, int ilp, int bpc) {
 }
 
 // --------------------------------------------------------------- launches
-static Exact exact_tables(const m2m_ctx* c) {
-    Exact e;
+static const Exact* exact_tables(const m2m_ctx* c) { return (const Exact*)c->exact_d; }
+
+template <typename T>
+static Layout<T> layout_of(const m2m_ctx* c);
+
+// FP64 constants and table pointers of the exact decisions, uploaded once.
+static m2m_status upload_exact(m2m_ctx* c) {
+    Exact e{};
     e.pots = (const Pot<double>*)c->pots64;
     e.lctab = c->lctab64;
     e.erange = c->erange64;
     e.edges = c->edges64;
-    return e;
+    e.rce = (const float*)c->rcetab;
+    e.lay = layout_of<float>(c);
+    e.cells = c->cells;
+    e.cosd = std::cos(c->lay.incl);
+    e.sind = std::sin(c->lay.incl);
+    for (int b = 0; b < c->lay.nbin; ++b) {
+        const m2m_binning& d = c->lay.bin[b];
+        if (d.kind != M2M_BIN_GRID) continue;
+        e.x0d[b] = d.x0;
+        e.wxd[b] = d.x1 - d.x0;
+        e.y0d[b] = d.y0;
+        e.wyd[b] = d.y1 - d.y0;
+    }
+    std::vector<unsigned char> h(sizeof(Exact));
+    std::memcpy(h.data(), &e, sizeof(e));
+    return upload(c, (unsigned char**)&c->exact_d, h);
+}
+
+// Tag rows of state buffer k.
+static uint16_t* tags(const m2m_ctx* c, int k) {
+    return (uint16_t*)((char*)c->state[k] + (size_t)7 * c->stride * tsize(c));
 }
 
 template <typename T>
@@ -281,11 +310,9 @@ static void fill_step_args(m2m_ctx* c, StepArgs<T, T>& a, int parity, int mode, 
     a.dt = (T)c->dt;
     a.eps = (T)c->eps;
     a.mu = (T)c->mu;
-    a.update = c->update;
-    a.frozen = c->frozen;
-    a.mode = mode;
-    a.what_mode = what_mode;
-    a.accum_cells = accum;
+    a.flags = (mode == 1 ? kObserve : 0u) | ((uint32_t)what_mode << kWhatShift) | (accum ? kAccum : 0u) |
+              (c->update == 1 ? kExpLaw : 0u) | (c->frozen ? kFrozen : 0u);
+    a.cellrow = c->lay.nbin;
     a.flag = c->flag;
     a.bad_step = c->bad_step;
     a.d_step = c->d_step;
@@ -343,7 +370,7 @@ static hipError_t launch_one_T(m2m_ctx* c, int64_t n, hipEvent_t e0, hipEvent_t 
     fill_step_args<T>(c, a, (int)(n & 1), 0, wm, acc);
     const Plan& p = c->plan;
     if (e0) (void)hipEventRecord(e0, c->stream);
-    hipError_t e = launch_step<T, T>(a, c->pot_kind, p.ilp, p.nblock, p.threads, p.lds, c->stream);
+    hipError_t e = launch_step<T, T>(a, c->pot_kind, c->lay.nbin, p.ilp, p.nblock, p.threads, p.lds, c->stream);
     if (e1) (void)hipEventRecord(e1, c->stream);
     if (e != hipSuccess) return e;
     FinArgs<T, T> f;
@@ -360,8 +387,9 @@ static hipError_t launch_prologue_T(m2m_ctx* c) {
     const int accum = c->prior.kind == M2M_PRIOR_HIST ? 1 : 0;
     StepArgs<T, T> a;
     fill_step_args<T>(c, a, (int)(c->step & 1), 1, 0, accum);
+    a.out = (T*)c->state[c->step & 1];   // observing only: the tags of the current state are written
     const Plan& p = c->plan;
-    hipError_t e = launch_step<T, T>(a, c->pot_kind, p.ilp, p.nblock, p.threads, p.lds, c->stream);
+    hipError_t e = launch_step<T, T>(a, c->pot_kind, c->lay.nbin, p.ilp, p.nblock, p.threads, p.lds, c->stream);
     if (e != hipSuccess) return e;
     FinArgs<T, T> f;
     // the prologue's chi^2 shares are those of "step -1"
@@ -443,12 +471,10 @@ static void build_tables(const m2m_ctx* c, std::vector<unsigned char>& pots, std
 }
 
 template <typename T>
-static void build_layout(m2m_ctx* c) {
+static Layout<T> layout_of(const m2m_ctx* c) {
     Layout<T> L{};
     L.cosi = (T)std::cos(c->lay.incl);
     L.sini = (T)std::sin(c->lay.incl);
-    L.cosd = std::cos(c->lay.incl);
-    L.sind = std::sin(c->lay.incl);
     L.nbin = c->lay.nbin;
     L.J = c->J;
     int off = 0, e0 = 0;
@@ -456,7 +482,8 @@ static void build_layout(m2m_ctx* c) {
         const m2m_binning& d = c->lay.bin[b];
         L.kind[b] = d.kind;
         L.nmom[b] = d.nmom;
-        for (int k = 0; k < 3; ++k) L.mom[b][k] = k < d.nmom ? d.mom[k] : 0;
+        L.mom[b] = 0;
+        for (int k = 0; k < d.nmom; ++k) L.mom[b] |= d.mom[k] << (2 * k);
         L.off[b] = off;
         L.edge0[b] = e0;
         if (d.kind == M2M_BIN_GRID) {
@@ -467,16 +494,18 @@ static void build_layout(m2m_ctx* c) {
             L.sx[b] = (T)(d.nx / (d.x1 - d.x0));
             L.y0[b] = (T)d.y0;
             L.sy[b] = (T)(d.ny / (d.y1 - d.y0));
-            L.x0d[b] = d.x0;
-            L.wxd[b] = d.x1 - d.x0;
-            L.y0d[b] = d.y0;
-            L.wyd[b] = d.y1 - d.y0;
         } else {
             L.nb[b] = d.nedge - 1;
             e0 += d.nedge;
         }
         off += d.nmom * L.nb[b];
     }
+    return L;
+}
+
+template <typename T>
+static void build_layout(m2m_ctx* c) {
+    const Layout<T> L = layout_of<T>(c);
     std::memcpy(c->lay_bytes, &L, sizeof(L));
     Cells C{};
     C.n0 = c->prior.n[0];
@@ -507,31 +536,38 @@ static void host_circular(const m2m_potential& q, double r, double* Ec, double* 
     *Lc = r * std::sqrt(std::max(0.0, r * d1));
 }
 
-// Lc(E) by bisection in ln r on [1e-8, 1e8] (end values outside the bracket).
-static double host_lc(const m2m_potential& q, double E) {
+// Lc(E) by bisection in ln r on [1e-8, 1e8] (end values outside the bracket);
+// the circular radius goes to *rc when rc is given.
+static double host_lc(const m2m_potential& q, double E, double* rc = nullptr) {
     double lo = std::log(1e-8), hi = std::log(1e8), Ec, Lc;
     host_circular(q, std::exp(lo), &Ec, &Lc);
+    if (rc) *rc = 1e-8;
     if (E <= Ec) return Lc;
     host_circular(q, std::exp(hi), &Ec, &Lc);
+    if (rc) *rc = 1e8;
     if (E >= Ec) return Lc;
     for (int it = 0; it < 200 && hi - lo > 1e-15; ++it) {
         const double mid = 0.5 * (lo + hi);
         host_circular(q, std::exp(mid), &Ec, &Lc);
         if (Ec < E) lo = mid; else hi = mid;
     }
+    if (rc) *rc = std::exp(0.5 * (lo + hi));
     host_circular(q, std::exp(0.5 * (lo + hi)), &Ec, &Lc);
     return Lc;
 }
 
-// Uniform-E table of Lc(E) for the FP32 kernels: kLcE pairs (Lc(E_k), bound) per
-// model over [Emin - W/4, Emax + W/4] (W = Emax - Emin; kept below E = 0 for the
-// bound-orbit potentials).  bound is a relative error bound of the FP32 linear
-// interpolation on [E_k, E_k+1]: 4x the largest deviation from the FP64 value at
-// three interior points, plus the FP32 rounding of the table, of the index and of
-// the interpolation.
+// Uniform-E table of Lc(E) for the FP32 kernels: kLcE pairs (ln Lc(E_k), bound)
+// per model over [Emin - W/4, Emax + W/4] (W = Emax - Emin; kept below E = 0 for
+// the bound-orbit potentials).  bound is a relative error bound of Lc from the
+// FP32 linear interpolation of ln Lc on [E_k, E_k+1]: 4x the largest deviation
+// from the FP64 value at three interior points, plus the effect of the FP32
+// rounding of the index (2e-4 of the interval's change of ln Lc), of the energy
+// (8e-7 times the largest |E| of the table, a few FP32 ulp) and of the table,
+// interpolation and exponential (1e-6).  Beside it, ln r_c(E_k): the seeds of
+// the FP64 Newton iteration that re-takes a cell decision left open.
 template <typename T>
 static m2m_status build_lc_etab(m2m_ctx* c, const std::vector<double>& er) {
-    std::vector<float> tab(2 * (size_t)kLcE * c->M, 0.0f);
+    std::vector<float> tab(2 * (size_t)kLcE * c->M, 0.0f), rce((size_t)kLcE * c->M, 0.0f);
     std::vector<unsigned char> pots(sizeof(Pot<T>) * c->M);
     HIPCHK(c, hipMemcpy(pots.data(), c->pots_d, pots.size(), hipMemcpyDeviceToHost));
     for (int m = 0; m < c->M && c->prior.kind != M2M_PRIOR_FLAT; ++m) {
@@ -541,21 +577,28 @@ static m2m_status build_lc_etab(m2m_ctx* c, const std::vector<double>& er) {
         if (q.kind != M2M_POT_LOG && hi >= 0.0) hi = -1e-3 * std::fabs(er[2 * m]);
         if (!(hi > lo)) hi = lo + 1e-6;
         const double h = (hi - lo) / (kLcE - 1);
+        const double eE = 8e-7 * std::max(2.0, std::max(std::fabs(lo), std::fabs(hi)));
         std::vector<double> L(kLcE);
-        for (int k = 0; k < kLcE; ++k) L[k] = host_lc(q, lo + k * h);
+        for (int k = 0; k < kLcE; ++k) {
+            double rc;
+            L[k] = host_lc(q, lo + k * h, &rc);
+            rce[(size_t)m * kLcE + k] = (float)std::log(rc);
+        }
         for (int k = 0; k < kLcE; ++k) {
             double err = 1.0;
             if (k + 1 < kLcE && L[k] > 0 && L[k + 1] > 0) {
+                const double l0 = std::log(L[k]), l1 = std::log(L[k + 1]);
                 double dev = 0;
                 for (double f : {0.25, 0.5, 0.75}) {
                     const double ex = host_lc(q, lo + (k + f) * h);
                     if (!(ex > 0)) { dev = 1.0; break; }
-                    dev = std::max(dev, std::fabs(L[k] + f * (L[k + 1] - L[k]) - ex) / ex);
+                    dev = std::max(dev, std::fabs(std::exp(l0 + f * (l1 - l0)) - ex) / ex);
                 }
-                const double slope = std::fabs(L[k + 1] - L[k]) / std::min(L[k], L[k + 1]);
-                err = std::min(1.0, 4.0 * dev + 5e-4 * slope + 1e-6);
+                // FP32 index error: ulp(E - E0) * invh + ulp(t) < 1e-4 of an interval;
+                // FP32 energy error: eE (a few ulp of the largest |E|) times d ln Lc / dE
+                err = std::min(1.0, 4.0 * dev + 2e-4 * std::fabs(l1 - l0) + eE * std::fabs(l1 - l0) / h + 1e-6);
             }
-            tab[2 * ((size_t)m * kLcE + k)] = (float)L[k];
+            tab[2 * ((size_t)m * kLcE + k)] = L[k] > 0 ? (float)std::log(L[k]) : -1e30f;
             tab[2 * ((size_t)m * kLcE + k) + 1] = (float)err;
         }
         Pot<T> p;
@@ -565,16 +608,27 @@ static m2m_status build_lc_etab(m2m_ctx* c, const std::vector<double>& er) {
         std::memcpy(pots.data() + sizeof(Pot<T>) * m, &p, sizeof(p));
     }
     HIPCHK(c, hipMemcpy(c->pots_d, pots.data(), pots.size(), hipMemcpyHostToDevice));
-    return upload(c, (float**)&c->lcetab, tab);
+    m2m_status s = upload(c, (float**)&c->lcetab, tab);
+    return s ? s : upload(c, (float**)&c->rcetab, rce);
 }
 
 // ------------------------------------------------------------------- create
+// Bytes of one state buffer: 7 value rows and nbin + 1 tag rows.
+static size_t state_bytes(const m2m_ctx* c) {
+    return (size_t)c->stride * (7 * tsize(c) + sizeof(uint16_t) * (c->lay.nbin + 1));
+}
+
 template <typename T>
 static m2m_status create_T(m2m_ctx* c, const m2m_target* tg, const void* xv, const void* w, int dev) {
     const int64_t N = c->N, S = c->stride;
     m2m_status s;
-    for (int k = 0; k < 2; ++k)
-        if ((s = dalloc(c, (T**)&c->state[k], (size_t)7 * S))) return s;
+    if (state_bytes(c) >= ((size_t)1 << 32))
+        return fail(c, M2M_ERR_UNSUPPORTED, "state buffer of " + std::to_string(state_bytes(c)) +
+                                                " bytes: at most 4 GiB per context (split the particles)");
+    for (int k = 0; k < 2; ++k) {
+        if ((s = dalloc(c, (char**)&c->state[k], state_bytes(c)))) return s;
+        HIPCHK(c, hipMemset(tags(c, k), 0xFF, state_bytes(c) - (size_t)7 * S * sizeof(T)));
+    }
     // copy in and validate the weights and coordinates on the host
     std::vector<T> hx((size_t)6 * N), hw((size_t)N);
     const hipMemcpyKind kind = dev ? hipMemcpyDeviceToHost : hipMemcpyHostToHost;
@@ -665,7 +719,7 @@ static m2m_status create_T(m2m_ctx* c, const m2m_target* tg, const void* xv, con
     std::vector<T> erT(er.size());
     for (size_t k = 0; k < er.size(); ++k) erT[k] = (T)er[k];
     if ((s = upload(c, (T**)&c->erange, erT)) || (s = upload(c, &c->erange64, er))) return s;
-    if ((s = build_lc_etab<T>(c, er))) return s;
+    if ((s = build_lc_etab<T>(c, er)) || (s = upload_exact(c))) return s;
     HIPCHK(c, launch_prologue_T<T>(c));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     return M2M_OK;
@@ -738,8 +792,8 @@ extern "C" m2m_status m2m_create(const m2m_config* cfg, const m2m_obs_layout* la
         delete c;
         return fail(nullptr, M2M_ERR_DEVICE, std::string("no usable HIP device: ") + hipGetErrorString(e));
     }
-    c->launch.threads = c->prec == M2M_F64 ? 256 : 512;
-    c->launch.ilp = c->prec == M2M_F64 ? 1 : 2;
+    c->launch.threads = c->prec == M2M_F64 ? 256 : 1024;
+    c->launch.ilp = 1;
     c->launch.blocks_per_cu = 1;
     c->launch.graph_steps = 0;
     c->launch.timing = 0;
@@ -922,6 +976,7 @@ static m2m_status gather_T(m2m_ctx* c, void* out, int dev) {
     if (wm == 2) wm = 1;   // a refresh step would compute the table priors
     GatherArgs<T> a;
     a.in = (const T*)c->state[c->step & 1];
+    a.tin = tags(c, (int)(c->step & 1));
     a.stride = c->stride;
     a.what = (const T*)c->what;
     a.out = (T*)c->scratch_n;
@@ -938,6 +993,7 @@ static m2m_status gather_T(m2m_ctx* c, void* out, int dev) {
     a.cells = c->cells;
     a.ex = exact_tables(c);
     a.what_mode = wm;
+    a.cellrow = c->lay.nbin;
     HIPCHK(c, launch_gather<T>(a, c->pot_kind, c->plan.nblock, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     HIPCHK(c, hipMemcpy(out, c->scratch_n, sizeof(T) * c->N, dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost));
@@ -980,8 +1036,8 @@ extern "C" m2m_status m2m_get_launch(const m2m_ctx* c, m2m_launch* out) {
 }
 
 static m2m_status apply_launch(m2m_ctx* c, const m2m_launch& L) {
-    const int tmax = c->prec == M2M_F64 ? 256 : 512;
-    if (L.threads < 64 || L.threads > tmax || L.threads % 64 || (L.ilp != 1 && L.ilp != 2 && L.ilp != 4) ||
+    const int tmax = c->prec == M2M_F64 ? 256 : 1024;
+    if (L.threads < 64 || L.threads > tmax || L.threads % 64 || (L.ilp != 1 && L.ilp != 2) ||
         L.blocks_per_cu < 1 || L.blocks_per_cu > 64 || L.graph_steps < 0 || L.graph_steps > 100000)
         return fail(c, M2M_ERR_INVALID, "launch shape out of range");
     const bool replan = L.threads != c->plan.threads || L.ilp != c->plan.ilp || L.blocks_per_cu != c->plan.bpc;
@@ -1029,7 +1085,7 @@ static m2m_status snapshot(m2m_ctx* c, Snapshot& s, bool restore) {
     const size_t ts = tsize(c);
     const size_t MJ = (size_t)c->M * c->J, MC = (size_t)c->M * std::max(1, c->NC);
     struct Item { void* p; size_t n; };
-    std::vector<Item> items = {{c->state[c->step & 1], 7 * (size_t)c->stride * ts},
+    std::vector<Item> items = {{c->state[c->step & 1], state_bytes(c)},
                                {c->ys, MJ * 8}, {c->y, MJ * 8}, {c->delta, MJ * 8}, {c->cvec, MJ * ts},
                                {c->cellmean, MC * ts}, {c->cellmean64, MC * 8}, {c->chunk_chi, 4 * (size_t)c->nchunk * 8},
                                {c->ring, sizeof(StatRow) * (size_t)c->M * kRing}, {c->d_step, 8}};
@@ -1108,13 +1164,13 @@ extern "C" m2m_status m2m_autotune(m2m_ctx* c, int32_t trial_steps, m2m_launch* 
         if (m2m_status s = snapshot(c, snap, false)) return s;
         const int64_t step0 = c->step;
         double best_ms = INFINITY;
-        std::vector<int> threads = c->prec == M2M_F64 ? std::vector<int>{64, 128, 256} : std::vector<int>{128, 256, 512};
+        std::vector<int> threads = c->prec == M2M_F64 ? std::vector<int>{64, 128, 256} : std::vector<int>{256, 512, 1024};
         hipEvent_t e0, e1;
         HIPCHK(c, hipEventCreate(&e0));
         HIPCHK(c, hipEventCreate(&e1));
         m2m_status err = M2M_OK;
         for (int t : threads)
-            for (int ilp : {1, 2, 4})
+            for (int ilp : {1, 2})
                 for (int bpc : {1, 2, 4}) {
                     m2m_launch L = keep;
                     L.threads = t;

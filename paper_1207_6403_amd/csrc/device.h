@@ -10,8 +10,8 @@
 // Integer decisions (which bin, which prior cell) are taken in FP64.  The FP32
 // kernels first decide in FP32 and keep that answer when the fractional bin
 // coordinate is further than a guard band from every edge (the FP32 error is
-// an order of magnitude below the band); particles inside the band -- a few in
-// ten thousand -- are re-decided from the same coordinates in FP64.
+// an order of magnitude below the band); a decision inside the band -- a few in
+// ten thousand -- is re-taken from the same coordinates in FP64.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -21,9 +21,9 @@ namespace m2m {
 constexpr int kMaxBin = 4;
 constexpr int kMaxEntries = 3 * kMaxBin;   // kernel entries K_j per particle (fixed slots)
 constexpr int kLcTab = 256;                // circular-orbit energies per model (FP64 path)
-constexpr int kLcE = 1024;                 // uniform-E Lc(E) table per model (FP32 path)
+constexpr int kLcE = 2048;                 // uniform-E Lc(E) table per model (FP32 path)
 constexpr float kGuardBin = 1e-4f;         // guard band, in bins, of the FP32 bin coordinates
-constexpr float kGuardCell = 3e-4f;        // guard band, in cells, of the FP32 prior coordinates
+constexpr float kGuardCell = 1e-4f;        // guard band, in cells, of the FP32 prior coordinates
 
 // Potential parameters with derived constants.
 template <typename T>
@@ -36,8 +36,10 @@ struct Pot {
     T lcE0, lcEinv;     // uniform-E Lc table: first energy, 1 / spacing
 };
 
-// Observation layout.  sx, sy = n / width give the fast FP32 bin coordinate;
-// the FP64 decision uses the defining form (v - x0) / width * n.
+// Observation layout (kept small: it lives in scalar registers).  sx, sy =
+// n / width give the fast FP32 bin coordinate; mom packs the listed moments in
+// 2-bit fields.  The FP64 decision uses the defining form (v - x0) / width * n
+// with the constants in Exact.
 template <typename T>
 struct Layout {
     T cosi, sini;
@@ -45,14 +47,12 @@ struct Layout {
     int32_t J;
     int32_t kind[kMaxBin];
     int32_t nmom[kMaxBin];
-    int32_t mom[kMaxBin][3];
+    int32_t mom[kMaxBin];      // moment m of binning b: (mom[b] >> 2m) & 3
     int32_t off[kMaxBin];      // first observable index of the binning
     int32_t nb[kMaxBin];       // bins per moment
     int32_t edge0[kMaxBin];    // offset of the binning's edges in the edge tables
     int32_t nx[kMaxBin], ny[kMaxBin];
     T x0[kMaxBin], sx[kMaxBin], y0[kMaxBin], sy[kMaxBin];
-    double cosd, sind;
-    double x0d[kMaxBin], wxd[kMaxBin], y0d[kMaxBin], wyd[kMaxBin];
 };
 
 // Moving-prior cell geometry.
@@ -62,13 +62,29 @@ struct Cells {
     int32_t ncell;
 };
 
-// FP64 tables of the exact (re-)decision path.
+// FP64 tables and constants of the exact (re-)decision path, in device
+// memory (read only when a decision is re-taken, or by the FP64 kernels).
 struct Exact {
+    Layout<float> lay;        // the layout as the FP32 kernels see it
+    Cells cells;
     const Pot<double>* pots;
     const double* lctab;      // kLcTab per model
     const double* erange;     // Emin, Emax per model
-    const double* edges;      // edge values (also copied to LDS)
+    const double* edges;      // edge values
+    const float* rce;         // kLcE values ln r_c(E_k) per model: Newton seeds (FP32 path)
+    double cosd, sind;
+    double x0d[kMaxBin], wxd[kMaxBin], y0d[kMaxBin], wyd[kMaxBin];
 };
+
+// x unchanged, but opaque to the optimiser: conditions derived from a uniform
+// value are then evaluated where they are used (a few scalar instructions)
+// instead of being hoisted to the kernel entry and held in scalar registers
+// across the whole particle loop.
+template <typename X>
+__device__ __forceinline__ X opaque(X x) {
+    asm volatile("" : "+s"(x));
+    return x;
+}
 
 // ------------------------------------------------------------------ potentials
 template <typename T> __device__ __forceinline__ T dsqrt(T v) { return sqrt(v); }
@@ -205,17 +221,12 @@ __device__ __forceinline__ bool near_cell_edge(float f, int n, float g) {
     return fr < g || fr > 1.0f - g;
 }
 
-// Cell of the moving prior in FP64 (the defining arithmetic).
-template <int POT>
-__device__ __forceinline__ int prior_cell_f64(const Pot<double>& p, const double* __restrict__ tab, const Cells& c,
-                                              double Emin, double Emax, double x, double y, double z, double vx,
-                                              double vy, double vz) {
-    double phi, ax, ay, az;
-    potential<POT, double>(p, x, y, z, phi, ax, ay, az);
-    const double E = 0.5 * (vx * vx + vy * vy + vz * vz) + phi;
-    const double Lx = y * vz - z * vy, Ly = z * vx - x * vz, Lz = x * vy - y * vx;
-    const double L = sqrt(Lx * Lx + Ly * Ly + Lz * Lz);
-    const double Lc = circular_L<POT, double, 5>(p, tab, E);
+// Cell index from E, L, Lz and Lc(E) in FP64 (the defining arithmetic): E
+// uniform over [Emin, Emax], then L/Lc in [0, 1] or Lz/Lc in [-1, 1], then
+// optionally Lz/L in [-1, 1]; coordinates outside a range take the edge cell.
+// Lc < 0 marks an unbound energy (infinite Lc), Lc = 0 a degenerate one.
+__device__ __forceinline__ int cell_index(const Cells& c, double Emin, double Emax, double E, double L, double Lz,
+                                          double Lc) {
     const int iE = clamp_cell((E - Emin) / (Emax - Emin) * c.n0, c.n0);
     int i2;
     if (c.ax2 == 0) i2 = clamp_cell((Lc > 0 ? L / Lc : (Lc < 0 ? 0.0 : 1e300)) * c.n1, c.n1);
@@ -225,22 +236,59 @@ __device__ __forceinline__ int prior_cell_f64(const Pot<double>& p, const double
     return (iE * c.n1 + i2) * c.n2 + i3;
 }
 
-// Out-of-line FP64 re-decision of the FP32 kernels (rarely taken; kept out of
-// line so that its registers do not weigh on the FP32 fast path).
+// Cell of the moving prior in FP64, Lc(E) from the circular-orbit table.
 template <int POT>
-__device__ __noinline__ int prior_cell_exact(const Pot<double>* __restrict__ pots, const double* __restrict__ lctab,
-                                             const double* __restrict__ erange, int m, int n0, int n1, int n2, int ax2,
-                                             double x, double y, double z, double vx, double vy, double vz) {
-    const Pot<double> p = pots[m];
-    Cells c;
-    c.n0 = n0; c.n1 = n1; c.n2 = n2; c.ax2 = ax2; c.ncell = n0 * n1 * n2;
-    return prior_cell_f64<POT>(p, lctab + p.lc_off, c, erange[2 * m], erange[2 * m + 1], x, y, z, vx, vy, vz);
+__device__ __forceinline__ int prior_cell_f64(const Pot<double>& p, const double* __restrict__ tab, const Cells& c,
+                                              double Emin, double Emax, double x, double y, double z, double vx,
+                                              double vy, double vz) {
+    double phi, ax, ay, az;
+    potential<POT, double>(p, x, y, z, phi, ax, ay, az);
+    const double E = 0.5 * (vx * vx + vy * vy + vz * vz) + phi;
+    const double Lx = y * vz - z * vy, Ly = z * vx - x * vz, Lz = x * vy - y * vx;
+    const double L = sqrt(Lx * Lx + Ly * Ly + Lz * Lz);
+    return cell_index(c, Emin, Emax, E, L, Lz, circular_L<POT, double, 5>(p, tab, E));
+}
+
+// Cell of the moving prior in FP64 for a decision the FP32 path left open.
+// Lc(E) from Newton steps on E_c(r) = E seeded by the tabulated ln r_c(E)
+// (uniform in E from E0 with 1/spacing invh; the seed is good to about 1e-6, so
+// three steps reach FP64 precision), the Hernquist closed form, or the
+// circular-orbit table (gtab, device memory) outside the seed table.
+template <int POT>
+__device__ __forceinline__ int prior_cell_seeded(const Pot<double>& p, const double* __restrict__ gtab,
+                                              const float* __restrict__ rce, double E0, double invh, const Cells& c,
+                                              double Emin, double Emax, double x, double y, double z, double vx,
+                                              double vy, double vz) {
+    double phi, ax, ay, az;
+    potential<POT, double>(p, x, y, z, phi, ax, ay, az);
+    const double E = 0.5 * (vx * vx + vy * vy + vz * vz) + phi;
+    const double Lx = y * vz - z * vy, Ly = z * vx - x * vz, Lz = x * vy - y * vx;
+    const double L = sqrt(Lx * Lx + Ly * Ly + Lz * Lz);
+    double Lc;
+    const double t = (E - E0) * invh;
+    if (POT == 0 || !(t >= 0.0) || !(t < double(kLcE - 1))) {
+        Lc = circular_L<POT, double, 5>(p, gtab, E);
+    } else {
+        const int k = int(t);
+        double r = exp(double(rce[k]) + (t - k) * double(rce[k + 1] - rce[k]));
+        #pragma unroll
+        for (int it = 0; it < 3; ++it) {
+            double ph, d1, d2;
+            radial_derivs<POT, double>(p, r, ph, d1, d2);
+            r = r - (ph + 0.5 * r * d1 - E) / (0.5 * (3.0 * d1 + r * d2));
+        }
+        double ph, d1, d2;
+        radial_derivs<POT, double>(p, r, ph, d1, d2);
+        Lc = r * sqrt(r * d1);
+    }
+    return cell_index(c, Emin, Emax, E, L, Lz, Lc);
 }
 
 // Lc(E) of an FP32 kernel from the model's uniform-E table in LDS: pairs
-// (Lc(E_k), bound) at E_k = E0 + k / invh, k < kLcE; bound is the relative error
-// of linear interpolation on [E_k, E_k+1] (measured on the host in FP64, with a
-// safety factor).  Returns false outside the table.
+// (ln Lc(E_k), bound) at E_k = E0 + k / invh, k < kLcE; ln Lc is interpolated
+// linearly and bound is the relative error of the resulting Lc on [E_k, E_k+1]
+// (measured on the host in FP64, with a safety factor).  Returns false outside
+// the table.
 __device__ __forceinline__ bool lc_from_table(const float2* __restrict__ et, float E0, float invh, float E, float& Lc,
                                               float& err) {
     const float t = (E - E0) * invh;
@@ -248,42 +296,46 @@ __device__ __forceinline__ bool lc_from_table(const float2* __restrict__ et, flo
     const int k = int(t);
     const float f = t - float(k);
     const float2 a = et[k], b = et[k + 1];
-    Lc = a.x + f * (b.x - a.x);
+    Lc = __expf(a.x + f * (b.x - a.x));
     err = a.y;
     return true;
 }
 
-// Cell of the moving prior for a particle of energy E (FP32 decision with an
-// FP64 re-decision inside the guard band; FP64 kernels decide in FP64).
-template <int POT, typename T>
-__device__ __forceinline__ int prior_cell(const Pot<T>& p, const T* __restrict__ tab, const float2* __restrict__ et,
-                                          const Cells& c, T Emin, T sE, T E, T x, T y, T z, T vx, T vy, T vz,
-                                          const Exact& ex, int m) {
-    if constexpr (sizeof(T) == 8) {
-        (void)et;
-        return prior_cell_f64<POT>(p, tab, c, ex.erange[2 * m], ex.erange[2 * m + 1], x, y, z, vx, vy, vz);
-    } else {
-        const T Lx = y * vz - z * vy, Ly = z * vx - x * vz, Lz = x * vy - y * vx;
-        const T L = dsqrt(Lx * Lx + Ly * Ly + Lz * Lz);
-        T Lc, err = T(2e-6);
-        bool ok = true;
-        if (POT == 0) Lc = circular_L<POT, T, 2>(p, tab, E);
-        else ok = lc_from_table(et, p.lcE0, p.lcEinv, E, Lc, err);
-        const T fE = (E - Emin) * sE;
-        T f2;
-        const T iLc = Lc > T(0) ? qdiv(T(1), Lc) : T(0);
-        if (c.ax2 == 0) f2 = (Lc > T(0) ? L * iLc : (Lc < T(0) ? T(0) : T(1e30))) * T(c.n1);
-        else f2 = ((Lc > T(0) ? Lz * iLc : (Lc < T(0) ? T(0) : (Lz > T(0) ? T(1e30) : T(-1e30)))) + T(1)) * T(0.5) * T(c.n1);
-        const T f3 = c.n2 > 1 ? ((L > T(0) ? qdiv(Lz, L) : T(0)) + T(1)) * T(0.5) * T(c.n2) : T(0.5);
-        // a relative error err of Lc moves f2 by at most (|f2| + n1) err
-        const T g2 = T(kGuardCell) + (fabsf(f2) + T(c.n1)) * err;
-        bool unsure = !ok || !(Lc > T(0)) || near_cell_edge(fE, c.n0, kGuardCell) || near_cell_edge(f2, c.n1, g2) ||
-                      (c.n2 > 1 && near_cell_edge(f3, c.n2, kGuardCell));
-        if (unsure)
-            return prior_cell_exact<POT>(ex.pots, ex.lctab, ex.erange, m, c.n0, c.n1, c.n2, c.ax2, double(x), double(y),
-                                         double(z), double(vx), double(vy), double(vz));
-        return (clamp_cell(fE, c.n0) * c.n1 + clamp_cell(f2, c.n1)) * c.n2 + (c.n2 > 1 ? clamp_cell(f3, c.n2) : 0);
+// Cell of the moving prior from FP32 values, or false when a coordinate lies
+// within the guard band of a cell edge (or outside the Lc table): the caller
+// then re-decides in FP64 with prior_cell_f64.
+template <int POT>
+__device__ __forceinline__ bool cell_fast(const Pot<float>& p, const float2* __restrict__ et, const Cells& c,
+                                          float Emin, float sE, float E, float x, float y, float z, float vx, float vy,
+                                          float vz, int& cell) {
+    const float Lx = y * vz - z * vy, Ly = z * vx - x * vz, Lz = x * vy - y * vx;
+    const float L = sqrtf(Lx * Lx + Ly * Ly + Lz * Lz);
+    float Lc, err = 2e-6f;
+    if (POT == 0) {
+        // Hernquist closed form (see circular_L)
+        if (!(E < 0.0f)) return false;
+        const float D = p.GM * p.GM - 8.0f * E * p.GM * p.a;
+        const float rc = 4.0f * p.a * (p.GM + E * p.a) / (sqrtf(D) - p.GM - 4.0f * E * p.a);
+        if (!(rc > 0.0f)) return false;
+        Lc = rc * sqrtf(p.GM * rc) / (rc + p.a);
+        err = 1e-5f;
+    } else if (!lc_from_table(et, p.lcE0, p.lcEinv, E, Lc, err)) {
+        return false;
     }
+    if (!(Lc > 0.0f)) return false;
+    const int n0 = opaque(c.n0), n1 = opaque(c.n1), n2 = opaque(c.n2), ax2 = opaque(c.ax2);
+    const float fE = (E - Emin) * sE;
+    const float iLc = qdiv(1.0f, Lc);
+    const float f2 = ax2 == 0 ? L * iLc * float(n1) : (Lz * iLc + 1.0f) * 0.5f * float(n1);
+    const float f3 = n2 > 1 ? ((L > 0.0f ? qdiv(Lz, L) : 0.0f) + 1.0f) * 0.5f * float(n2) : 0.5f;
+    // a relative error err of Lc moves f2 by at most |f2| err (L/Lc axis) or
+    // |f2 - n1/2| err (Lz/Lc axis)
+    const float g2 = kGuardCell + (ax2 == 0 ? fabsf(f2) : fabsf(f2 - 0.5f * float(n1))) * err;
+    if (near_cell_edge(fE, n0, kGuardCell) || near_cell_edge(f2, n1, g2) ||
+        (n2 > 1 && near_cell_edge(f3, n2, kGuardCell)))
+        return false;
+    cell = (clamp_cell(fE, n0) * n1 + clamp_cell(f2, n1)) * n2 + (n2 > 1 ? clamp_cell(f3, n2) : 0);
+    return true;
 }
 
 // ---------------------------------------------------------------- observables
@@ -315,63 +367,32 @@ __device__ __forceinline__ int bin_f64(int kind, double cosd, double sind, doubl
     return edge_bin(e, ne, rad);
 }
 
-// FP64 re-decision of the FP32 kernels (rarely taken).
-__device__ __forceinline__ int bin_exact(int kind, double cosd, double sind, double x0, double wx, int nx, double y0,
-                                      double wy, int ny, const double* __restrict__ e, int ne, double x, double y,
-                                      double z) {
-    return bin_f64(kind, cosd, sind, x0, wx, nx, y0, wy, ny, e, ne, x, y, z);
+// Bin of binning b in FP32, -1 outside; sure = false when the coordinate lies
+// within the guard band of an edge (the caller re-decides with bin_f64).
+__device__ __forceinline__ int bin_fast(const Layout<float>& L, int b, const float* __restrict__ ef, float x, float y,
+                                        float z, float Ys, bool& sure) {
+    const int kind = opaque(L.kind[b]);
+    if (kind == 3) {
+        const float fx = (x - L.x0[b]) * L.sx[b];
+        const float fy = (Ys - L.y0[b]) * L.sy[b];
+        sure = !near_cell_edge(fx, L.nx[b], kGuardBin) && !near_cell_edge(fy, L.ny[b], kGuardBin);
+        if (fx >= 0.0f && fx < float(L.nx[b]) && fy >= 0.0f && fy < float(L.ny[b])) return int(fy) * L.nx[b] + int(fx);
+        return -1;
+    }
+    const float rad = kind == 1 ? __builtin_sqrtf(x * x + y * y + z * z) : __builtin_sqrtf(x * x + Ys * Ys);
+    const float* e = ef + L.edge0[b];
+    const int ne = L.nb[b] + 1;
+    const float g = kGuardBin * rad;
+    const int k = edge_bin(e, ne, rad);
+    if (k >= 0) sure = !(rad - e[k] < g) && !(e[k + 1] - rad < g);
+    else sure = !(fabsf(rad - e[0]) < g) && !(fabsf(rad - e[ne - 1]) < g) && rad == rad;
+    return k;
 }
 
-// Kernel entries K_j of one phase-space point in fixed slots e = 3 b + m
-// (binning b, m-th listed moment); jj[e] = -1 marks an empty slot.  Fixed slots
-// keep both arrays in registers (every index is a compile-time constant once
-// the loops are unrolled).  ef / ed: edge tables in T and in FP64.
+// Kernel value of moment code mo (0: 1, 1: v_los, 2: v_los^2).
 template <typename T>
-__device__ __forceinline__ void kernel_entries(const Layout<T>& L, const T* __restrict__ ef,
-                                               const double* __restrict__ ed, T x, T y, T z, T vy, T vz,
-                                               int (&jj)[kMaxEntries], T (&K)[kMaxEntries]) {
-    const T Ys = y * L.cosi - z * L.sini;
-    const T vl = vy * L.sini + vz * L.cosi;
-    #pragma unroll
-    for (int b = 0; b < kMaxBin; ++b) {
-        int k = -1;
-        if (b < L.nbin) {
-            if constexpr (sizeof(T) == 8) {
-                k = bin_f64(L.kind[b], L.cosd, L.sind, L.x0d[b], L.wxd[b], L.nx[b], L.y0d[b], L.wyd[b], L.ny[b],
-                            ed + L.edge0[b], L.nb[b] + 1, x, y, z);
-            } else if (L.kind[b] == 3) {
-                const T fx = (x - L.x0[b]) * L.sx[b];
-                const T fy = (Ys - L.y0[b]) * L.sy[b];
-                if (near_cell_edge(fx, L.nx[b], kGuardBin) || near_cell_edge(fy, L.ny[b], kGuardBin)) {
-                    k = bin_exact(3, L.cosd, L.sind, L.x0d[b], L.wxd[b], L.nx[b], L.y0d[b], L.wyd[b], L.ny[b], ed, 0,
-                                  double(x), double(y), double(z));
-                } else if (fx >= T(0) && fx < T(L.nx[b]) && fy >= T(0) && fy < T(L.ny[b])) {
-                    k = int(fy) * L.nx[b] + int(fx);
-                }
-            } else {
-                const T rad = L.kind[b] == 1 ? dsqrt(x * x + y * y + z * z) : dsqrt(x * x + Ys * Ys);
-                const T* e = ef + L.edge0[b];
-                const int ne = L.nb[b] + 1;
-                // FP32 search on the rounded edges, re-decided in FP64 within a
-                // relative guard band of the nearest candidate edges
-                const T g = T(kGuardBin) * rad;
-                int kk = edge_bin(e, ne, rad);
-                bool unsure;
-                if (kk >= 0) unsure = rad - e[kk] < g || e[kk + 1] - rad < g;
-                else unsure = fabs(rad - e[0]) < g || fabs(rad - e[ne - 1]) < g || !(rad == rad);
-                k = unsure ? bin_exact(L.kind[b], L.cosd, L.sind, 0.0, 1.0, 1, 0.0, 1.0, 1, ed + L.edge0[b], ne,
-                                       double(x), double(y), double(z))
-                           : kk;
-            }
-        }
-        #pragma unroll
-        for (int m = 0; m < 3; ++m) {
-            const bool on = k >= 0 && m < L.nmom[b];
-            const int mo = L.mom[b][m];
-            jj[3 * b + m] = on ? L.off[b] + m * L.nb[b] + k : -1;
-            K[3 * b + m] = mo == 0 ? T(1) : (mo == 1 ? vl : vl * vl);
-        }
-    }
+__device__ __forceinline__ T moment_value(int mo, T vl) {
+    return mo == 0 ? T(1) : (mo == 1 ? vl : vl * vl);
 }
 
 }  // namespace m2m

@@ -50,6 +50,8 @@ struct m2m_ctx {
     void* pots64 = nullptr;
     void* lctab = nullptr;
     void* lcetab = nullptr;
+    void* rcetab = nullptr;
+    void* exact_d = nullptr;
     double* lctab64 = nullptr;
     double* erange64 = nullptr;
     double* edges64 = nullptr;

@@ -22,8 +22,10 @@ struct StatRow {
 // Fused step: update + push + observe + prior cells (one particle pass).
 template <typename T, typename PT>
 struct StepArgs {
-    const T* in;            // 7 * stride: x y z vx vy vz w (state at step n)
-    T* out;                 // 7 * stride: state at step n+1
+    // State buffers: 7 value rows (x y z vx vy vz w) then tag rows (bin of each
+    // binning, prior cell), `stride` entries each; less than 4 GiB in all.
+    const T* in;            // state at step n
+    T* out;                 // state at step n+1 (the state at step n when observing only)
     int64_t stride;
     T* what;                // per-particle priors (stored modes)
     const int32_t* tile_model;
@@ -45,16 +47,26 @@ struct StepArgs {
     int32_t pcols, jpad;
     Layout<T> lay;
     Cells cells;
-    Exact ex;
+    const Exact* ex;              // FP64 constants and tables (device memory)
     T dt, eps, mu;
-    int32_t update, frozen;
-    int32_t mode;                 // 0 step, 1 observe only
-    int32_t what_mode;            // 0 flat, 1 table, 2 table + store, 3 stored
-    int32_t accum_cells;
+    uint32_t flags;               // kObserve | kWhat* | kAccum | kExpLaw | kFrozen
+    int32_t cellrow;              // tag row of the prior cell
     int* flag;
     long long* bad_step;
     const long long* d_step;
 };
+
+// Step flags.  kWhat: where the prior of the update comes from -- 0 flat,
+// 1 cell-mean table, 2 table and store it per particle, 3 the stored priors.
+constexpr uint32_t kObserve = 1u;     // observe only: no update, no push
+constexpr uint32_t kWhatShift = 1u;   // 2 bits
+constexpr uint32_t kAccum = 8u;       // decide (and store) the prior cell of the new state
+constexpr uint32_t kExpLaw = 16u;     // w <- w exp(eps dt G), else w (1 + eps dt G)
+constexpr uint32_t kFrozen = 32u;     // particles do not move
+
+// Tags: per particle and binning, the bin the particle fell in (kNoBin when
+// none), and its prior cell; rows of `stride` uint16 after the 7 value rows.
+constexpr uint16_t kNoBin = 0xFFFF;
 
 template <typename T, typename PT>
 struct FinArgs {
@@ -101,6 +113,7 @@ struct ErangeArgs {
 template <typename T>
 struct GatherArgs {
     const T* in;
+    const uint16_t* tin;
     int64_t stride;
     const T* what;
     T* out;
@@ -115,12 +128,13 @@ struct GatherArgs {
     const T* flatw;
     const T* cellmean;
     Cells cells;
-    Exact ex;
+    const Exact* ex;              // FP64 constants and tables (device memory)
     int32_t what_mode;
+    int32_t cellrow;
 };
 
 template <typename T, typename PT>
-hipError_t launch_step(const StepArgs<T, PT>& a, int pot_kind, int ilp, int blocks, int threads, size_t lds,
+hipError_t launch_step(const StepArgs<T, PT>& a, int pot_kind, int nbin, int ilp, int blocks, int threads, size_t lds,
                        hipStream_t s);
 template <typename T, typename PT>
 hipError_t set_step_lds_limit(int pot_kind, size_t lds);

@@ -1,16 +1,19 @@
-// step.hip -- fused M2M step kernel and the per-step reduction/finalise kernel.
+// step.hip -- fused M2M step kernel (plus the energy-range and prior readback
+// kernels).
 //
 // One launch of step_kernel performs, for every particle of every model (the
 // per-timestep loop of the made-to-measure method, section 2 of the paper):
-//   weight update with the current deviations and priors (maximising
-//   F = -chi^2/2 + mu S, eq. 1 and 2), kick-drift-kick push in the analytic
+//   the weight update with the current deviations and priors (maximising
+//   F = -chi^2/2 + mu S, eq. 1 and 2), the kick-drift-kick push in the analytic
 //   potential, and the scatter of w * K_j of the new state into LDS-privatised
 //   observable histograms, plus the moving-prior cell sums (section 2.1).
+// The bins and the prior cell of a particle are decided once, for the new
+// state, and stored as 16-bit tags beside the state: the next step's update
+// reads them instead of deciding again.
 // Each block owns a contiguous range of tiles; a tile never straddles models.
 // When a block moves to another model (batched form) or finishes, it writes
-// its LDS histograms to its own partial slot (no atomics, deterministic).
-//
-// finalize.hip then sums the partial slots column by column in a fixed order.
+// its LDS histograms to its own partial slot (no atomics, deterministic
+// placement); finalize.hip sums the slots.
 #include "runtime.h"
 
 namespace m2m {
@@ -42,37 +45,248 @@ __device__ __forceinline__ void block_stats(double s, double w, double w2, doubl
     __syncthreads();
 }
 
-template <typename T, typename PT, int POT, int ILP>
-__global__ void __launch_bounds__(sizeof(T) == 8 ? 256 : 512) step_kernel(StepArgs<T, PT> a) {
+// Per-block working set of one model (LDS tables and model constants).
+template <typename T>
+struct Blk {
+    double* hist;       // observable histogram (FP64)
+    double* csum;       // prior cell weight sums
+    unsigned* ccnt;     // prior cell counts
+    const T* cl;        // update table Dt_j / sigma_j
+    const T* cm;        // prior cell means
+    const T* ed;        // edges in T
+    const double* ed64; // edges in FP64
+    const float2* et;   // uniform-E Lc table (FP32 kernels)
+    const T* lct;       // circular-orbit energies (FP64 kernels)
+    Pot<T> pot;
+    T Emin, sE, wflat;
+    int m;
+};
+
+// Statistics of the weights entering the step, accumulated per thread.
+struct Acc {
+    double S = 0, W = 0, W2 = 0, mn = INFINITY;
+    unsigned bad = 0;
+};
+
+// Value at byte offset off from base.  Every row of a state buffer (values,
+// then tags) is addressed from the buffer's base with a 32-bit byte offset
+// (state buffers are smaller than 4 GiB), so one scalar base serves all rows.
+template <typename X>
+__device__ __forceinline__ X ld_at(const void* base, uint32_t off) {
+    return *reinterpret_cast<const X*>(reinterpret_cast<const char*>(base) + off);
+}
+template <typename X>
+__device__ __forceinline__ void st_at(void* base, uint32_t off, X v) {
+    *reinterpret_cast<X*>(reinterpret_cast<char*>(base) + off) = v;
+}
+
+// Scatter w * K_j of one particle's bin k of binning b (moments of v_los = vl).
+template <typename T>
+__device__ __forceinline__ void scatter_bin(const Layout<T>& L, double* hist, int b, int k, T wn, T vl) {
+    const int base = L.off[b] + k;
+    const int nmom = opaque(L.nmom[b]), mom = opaque(L.mom[b]);
+    #pragma unroll
+    for (int mm = 0; mm < 3; ++mm) {
+        if (mm >= nmom) break;
+        atomicAdd(&hist[base + mm * L.nb[b]], double(wn * moment_value<T>((mom >> (2 * mm)) & 3, vl)));
+    }
+}
+
+// One particle's step: update the weight with the bins and cell of the current
+// state (its tags), push, decide the bins and cell of the new state, store, and
+// scatter into the histograms.  With kObserve the particle is neither updated
+// nor moved: its current bins and cell are decided and stored.
+// FP32 kernels decide in FP32; a decision inside its guard band is left open
+// and flagged in the returned mask (bit b: binning b, bit NB: the cell), to be
+// re-taken in FP64 by fixup(); FP64 kernels decide in FP64 and return 0.
+template <int POT, int NB, typename T, typename PT>
+__device__ __forceinline__ unsigned particle_step(const StepArgs<T, PT>& a, const Blk<T>& B, Acc& acc, int64_t p,
+                                                  T x, T y, T z, T vx, T vy, T vz, T w,
+                                                  const uint16_t (&tg)[kMaxBin + 1]) {
+    const Layout<T>& L = a.lay;
+    const uint32_t fl = opaque(a.flags);
+    const uint32_t rb = opaque(uint32_t(a.stride * sizeof(T)));   // bytes per value row
+    const uint32_t o = uint32_t(p) * uint32_t(sizeof(T));
+    const uint32_t ot = 7 * rb + uint32_t(p) * 2u;                 // tag of row 0
+    const int nbin = opaque(L.nbin);
+    T wn = w, phi = T(0);
+    bool have_phi = false;
+    if (!(fl & kObserve)) {
+        // dF/dw_i with the kernel entries of the stored bins (eq. 1 and 2)
+        const T vl = vy * L.sini + vz * L.cosi;
+        T chi = T(0);
+        #pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            if (b >= nbin) break;
+            const int k = tg[b];
+            if (k == kNoBin) continue;
+            const int base = L.off[b] + k;
+            const int nmom = opaque(L.nmom[b]), mom = opaque(L.mom[b]);
+            #pragma unroll
+            for (int mm = 0; mm < 3; ++mm) {
+                if (mm >= nmom) break;
+                chi += moment_value<T>((mom >> (2 * mm)) & 3, vl) * B.cl[base + mm * L.nb[b]];
+            }
+        }
+        const uint32_t wm = (fl >> kWhatShift) & 3u;
+        const T wh = wm == 0 ? B.wflat : (wm == 3 ? a.what[p] : B.cm[tg[kMaxBin]]);
+        const T lr = dlog(w / wh);
+        const T G = -chi - a.mu * (lr + T(1));
+        const T edt = a.eps * a.dt;
+        wn = (fl & kExpLaw) ? w * dexp(edt * G) : w * (T(1) + edt * G);
+        acc.S -= double(w) * double(lr);
+        acc.W += double(w);
+        acc.W2 += double(w) * double(w);
+        acc.mn = fmin(acc.mn, double(w));
+        if (!(wn == wn) || wn == T(INFINITY) || wn == T(-INFINITY)) acc.bad |= 2u;   // non-finite
+        else if (!(wn > T(0))) acc.bad |= 1u;                                        // w <= 0
+        if (wm == 2) a.what[p] = wh;   // a refresh step stores the prior it used
+        if (!(fl & kFrozen)) {
+            // kick-drift-kick
+            T ax, ay, az;
+            potential<POT, T>(B.pot, x, y, z, phi, ax, ay, az);
+            const T hdt = T(0.5) * a.dt;
+            vx += hdt * ax; vy += hdt * ay; vz += hdt * az;
+            x += a.dt * vx; y += a.dt * vy; z += a.dt * vz;
+            potential<POT, T>(B.pot, x, y, z, phi, ax, ay, az);
+            vx += hdt * ax; vy += hdt * ay; vz += hdt * az;
+            have_phi = true;
+        }
+        st_at(a.out, o, x);
+        st_at(a.out, o + rb, y);
+        st_at(a.out, o + 2 * rb, z);
+        st_at(a.out, o + 3 * rb, vx);
+        st_at(a.out, o + 4 * rb, vy);
+        st_at(a.out, o + 5 * rb, vz);
+        st_at(a.out, o + 6 * rb, wn);
+    }
+    // bins and cell of the new state
+    unsigned open = 0;
+    const T vl = vy * L.sini + vz * L.cosi;
+    const float Ys = float(y * L.cosi - z * L.sini);
+    #pragma unroll
+    for (int b = 0; b < NB; ++b) {
+        if (b >= nbin) break;
+        int k;
+        if constexpr (sizeof(T) == 4) {
+            bool sure;
+            k = bin_fast(L, b, B.ed, x, y, z, Ys, sure);
+            if (!sure) { open |= 1u << b; continue; }
+        } else {
+            const Exact* ex = a.ex;
+            k = bin_f64(L.kind[b], ex->cosd, ex->sind, ex->x0d[b], ex->wxd[b], L.nx[b], ex->y0d[b], ex->wyd[b], L.ny[b],
+                        B.ed64 + L.edge0[b], L.nb[b] + 1, x, y, z);
+        }
+        st_at<uint16_t>(a.out, ot + b * (rb / uint32_t(sizeof(T)) * 2u), k < 0 ? kNoBin : (uint16_t)k);
+        if (k >= 0) scatter_bin(L, B.hist, b, k, wn, vl);
+    }
+    if (fl & kAccum) {
+        if (!have_phi) {
+            T ax, ay, az;
+            potential<POT, T>(B.pot, x, y, z, phi, ax, ay, az);
+        }
+        int cell;
+        if constexpr (sizeof(T) == 4) {
+            const float E = 0.5f * (vx * vx + vy * vy + vz * vz) + phi;
+            if (!cell_fast<POT>(B.pot, B.et, a.cells, B.Emin, B.sE, E, x, y, z, vx, vy, vz, cell))
+                return open | (1u << NB);
+        } else {
+            cell = prior_cell_f64<POT>(B.pot, B.lct, a.cells, a.ex->erange[2 * B.m], a.ex->erange[2 * B.m + 1], x, y, z,
+                                       vx, vy, vz);
+        }
+        st_at<uint16_t>(a.out, ot + a.cellrow * (rb / uint32_t(sizeof(T)) * 2u), (uint16_t)cell);
+        atomicAdd(&B.csum[cell], double(wn));
+        atomicAdd(&B.ccnt[cell], 1u);
+    }
+    return open;
+}
+
+// Address-space-qualified pointers for the out-of-line fix-up: its arguments
+// keep their memory kinds, so neither side falls back to flat addressing.
+using cExact = const __attribute__((address_space(4))) Exact;
+using gF32 = const __attribute__((address_space(1))) float;
+using gU16 = __attribute__((address_space(1))) uint16_t;
+using lF64 = __attribute__((address_space(3))) double;
+using lU32 = __attribute__((address_space(3))) unsigned;
+
+// The decisions particle_step left open (mask `open`), taken in FP64 from the
+// FP32 coordinates of the new state (read back from the particle's own stores,
+// or from the input when observing only), then stored and scattered.  Out of
+// line: it runs for a few particles in ten thousand, and inlined its FP64
+// working set would raise the register use of the whole kernel.
+template <int POT, int NB>
+__device__ __noinline__ void fixup(cExact* ex, int m, unsigned open, int64_t p, int64_t stride, int cellrow,
+                                   gF32* src, gU16* tout, lF64* hist, lF64* csum, lU32* ccnt, float lcE0,
+                                   float lcEinv) {
+    const float x = src[p], y = src[stride + p], z = src[2 * stride + p];
+    const float vx = src[3 * stride + p], vy = src[4 * stride + p], vz = src[5 * stride + p];
+    const float wn = src[6 * stride + p];
+    const float vl = vy * ex->lay.sini + vz * ex->lay.cosi;
+    #pragma unroll
+    for (int b = 0; b < NB; ++b) {
+        if (!(open & (1u << b))) continue;
+        const int k = bin_f64(ex->lay.kind[b], ex->cosd, ex->sind, ex->x0d[b], ex->wxd[b], ex->lay.nx[b], ex->y0d[b],
+                              ex->wyd[b], ex->lay.ny[b], ex->edges + ex->lay.edge0[b], ex->lay.nb[b] + 1, double(x),
+                              double(y), double(z));
+        tout[b * stride + p] = k < 0 ? kNoBin : (uint16_t)k;
+        if (k < 0) continue;
+        const int base = ex->lay.off[b] + k;
+        for (int mm = 0; mm < ex->lay.nmom[b]; ++mm)
+            __hip_atomic_fetch_add(&hist[base + mm * ex->lay.nb[b]],
+                                   double(wn * moment_value<float>((ex->lay.mom[b] >> (2 * mm)) & 3, vl)),
+                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    }
+    if (open & (1u << NB)) {
+        const Pot<double> pd = ex->pots[m];
+        Cells cells;
+        cells.n0 = ex->cells.n0;
+        cells.n1 = ex->cells.n1;
+        cells.n2 = ex->cells.n2;
+        cells.ax2 = ex->cells.ax2;
+        cells.ncell = ex->cells.ncell;
+        const int cell = prior_cell_seeded<POT>(pd, ex->lctab + pd.lc_off, ex->rce + (size_t)m * kLcE, double(lcE0),
+                                                double(lcEinv), cells, ex->erange[2 * m], ex->erange[2 * m + 1],
+                                                double(x), double(y), double(z), double(vx), double(vy), double(vz));
+        tout[cellrow * stride + p] = (uint16_t)cell;
+        __hip_atomic_fetch_add(&csum[cell], double(wn), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        __hip_atomic_fetch_add(&ccnt[cell], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    }
+}
+
+template <typename T, typename PT, int POT, int NB, int ILP>
+__global__ void __launch_bounds__(sizeof(T) == 8 ? 256 : 1024) step_kernel(StepArgs<T, PT> a) {
     extern __shared__ __align__(16) unsigned char smem[];
     if (*a.flag) return;   // an earlier step failed: the whole step is a no-op
 
+    constexpr bool F32 = sizeof(T) == 4;
     const int J = a.lay.J, NC = a.cells.ncell, JP = a.jpad, NE = (a.nedge + 1) & ~1;
+    const int nt = blockDim.x, tid = threadIdx.x;
     double* hist = reinterpret_cast<double*>(smem);                 // J (padded to JP)
     double* csum = hist + JP;                                        // NC
     double* ed64 = csum + NC;                                        // edges, FP64
     double* red = ed64 + NE;                                         // 4 * 16
-    const int NET = (sizeof(T) == 4 && NC) ? kLcE : 0;
+    const int NET = (F32 && NC) ? kLcE : 0;
     float2* et = reinterpret_cast<float2*>(red + 64);                // uniform-E Lc table (FP32)
     unsigned* ccnt = reinterpret_cast<unsigned*>(et + NET);          // NC (padded to even)
     T* cl = reinterpret_cast<T*>(ccnt + ((NC + 1) & ~1));            // J : Dt_j / sigma_j
     T* cm = cl + JP;                                                 // NC: cell means
     T* ed = cm + ((NC + 1) & ~1);                                    // edges in T
-    T* lct = ed + NE;                                                // circular-orbit energies
+    T* lct = ed + NE;                                                // circular-orbit energies (FP64)
 
-    const int tid = threadIdx.x, nt = blockDim.x;
-    for (int i = tid; i < a.nedge; i += nt) { ed[i] = a.edges[i]; ed64[i] = a.ex.edges[i]; }
+    for (int i = tid; i < a.nedge; i += nt) { ed[i] = a.edges[i]; ed64[i] = a.ex->edges[i]; }
 
     const int t0 = a.block_tile0[blockIdx.x], t1 = a.block_tile0[blockIdx.x + 1];
-    const bool observe_only = a.mode == 1;
-    const bool want_cm = a.what_mode == 1 || a.what_mode == 2;
+    const uint32_t fl = a.flags;
+    const uint32_t wm = (fl >> kWhatShift) & 3u;
+    const bool want_cm = wm == 1 || wm == 2;
+    const bool accum = fl & kAccum;
+    const bool stepping = !(fl & kObserve);
     int slot = a.block_slot0[blockIdx.x] - 1;
     int cur = -1;
-    Pot<T> pot;
-    T Emin = 0, sE = 1, wflat = 0;
-    double sS = 0, sW = 0, sW2 = 0, mW = INFINITY;
-    unsigned bad = 0;
-    const T hdt = T(0.5) * a.dt, dt = a.dt, edt = a.eps * a.dt, mu = a.mu;
+    Blk<T> B;
+    B.hist = hist; B.csum = csum; B.ccnt = ccnt; B.cl = cl; B.cm = cm; B.ed = ed; B.ed64 = ed64; B.et = et;
+    B.lct = lct;
+    Acc acc;
 
     for (int t = t0; t <= t1; ++t) {
         const int m = t < t1 ? a.tile_model[t] : -2;
@@ -82,23 +296,25 @@ __global__ void __launch_bounds__(sizeof(T) == 8 ? 256 : 512) step_kernel(StepAr
                 __syncthreads();
                 PT* dst = a.part + (size_t)slot * a.pcols;
                 for (int j = tid; j < J; j += nt) dst[j] = PT(hist[j]);
-                if (a.accum_cells)
+                if (accum)
                     for (int c = tid; c < NC; c += nt) { dst[JP + 2 * c] = PT(csum[c]); dst[JP + 2 * c + 1] = PT(ccnt[c]); }
-                block_stats(sS, sW, sW2, mW, red, a.seg_stats + 4 * (size_t)slot);
-                sS = sW = sW2 = 0; mW = INFINITY;
+                block_stats(acc.S, acc.W, acc.W2, acc.mn, red, a.seg_stats + 4 * (size_t)slot);
+                acc.S = acc.W = acc.W2 = 0;
+                acc.mn = INFINITY;
             }
             if (m < 0) break;
             cur = m;
             ++slot;
-            pot = a.pots[m];
-            Emin = a.erange[2 * m];
-            sE = T(a.cells.n0) / (a.erange[2 * m + 1] - a.erange[2 * m]);
-            wflat = a.flatw[m];
+            B.m = m;
+            B.pot = a.pots[m];
+            B.Emin = a.erange[2 * m];
+            B.sE = T(a.cells.n0) / (a.erange[2 * m + 1] - a.erange[2 * m]);
+            B.wflat = a.flatw[m];
             __syncthreads();
             for (int j = tid; j < J; j += nt) { hist[j] = 0.0; cl[j] = a.cvec[(size_t)m * J + j]; }
-            if (a.accum_cells) for (int c = tid; c < NC; c += nt) { csum[c] = 0.0; ccnt[c] = 0u; }
+            if (accum) for (int c = tid; c < NC; c += nt) { csum[c] = 0.0; ccnt[c] = 0u; }
             if (want_cm) for (int c = tid; c < NC; c += nt) cm[c] = a.cellmean[(size_t)m * NC + c];
-            if (NC) for (int i = tid; i < kLcTab; i += nt) lct[i] = a.lctab[(size_t)pot.lc_off + i];
+            if (NC && !F32) for (int i = tid; i < kLcTab; i += nt) lct[i] = a.lctab[(size_t)B.pot.lc_off + i];
             for (int i = tid; i < NET; i += nt)
                 et[i] = make_float2(a.lcetab[2 * ((size_t)m * kLcE + i)], a.lcetab[2 * ((size_t)m * kLcE + i) + 1]);
             __syncthreads();
@@ -106,93 +322,46 @@ __global__ void __launch_bounds__(sizeof(T) == 8 ? 256 : 512) step_kernel(StepAr
         const int64_t p0 = a.tile_p0[t];
         const int cnt = a.tile_cnt[t];
         T px[ILP], py[ILP], pz[ILP], qx[ILP], qy[ILP], qz[ILP], pw[ILP];
+        uint16_t tg[ILP][kMaxBin + 1];
         #pragma unroll
         for (int k = 0; k < ILP; ++k) {
             const int i = k * nt + tid;
             if (i < cnt) {
                 const int64_t p = p0 + i;
-                px[k] = a.in[p];
-                py[k] = a.in[a.stride + p];
-                pz[k] = a.in[2 * a.stride + p];
-                qx[k] = a.in[3 * a.stride + p];
-                qy[k] = a.in[4 * a.stride + p];
-                qz[k] = a.in[5 * a.stride + p];
-                pw[k] = a.in[6 * a.stride + p];
+                const uint32_t rb = opaque(uint32_t(a.stride * sizeof(T))), tr = uint32_t(a.stride * 2);
+                const uint32_t o = uint32_t(p) * uint32_t(sizeof(T)), ot = 7 * rb + uint32_t(p) * 2u;
+                px[k] = ld_at<T>(a.in, o);
+                py[k] = ld_at<T>(a.in, o + rb);
+                pz[k] = ld_at<T>(a.in, o + 2 * rb);
+                qx[k] = ld_at<T>(a.in, o + 3 * rb);
+                qy[k] = ld_at<T>(a.in, o + 4 * rb);
+                qz[k] = ld_at<T>(a.in, o + 5 * rb);
+                pw[k] = ld_at<T>(a.in, o + 6 * rb);
+                #pragma unroll
+                for (int b = 0; b < kMaxBin; ++b)
+                    tg[k][b] = (stepping && b < NB && b < a.lay.nbin) ? ld_at<uint16_t>(a.in, ot + b * tr) : kNoBin;
+                tg[k][kMaxBin] = (stepping && want_cm) ? ld_at<uint16_t>(a.in, ot + a.cellrow * tr) : 0;
             }
         }
+        unsigned open[ILP];
         #pragma unroll
         for (int k = 0; k < ILP; ++k) {
             const int i = k * nt + tid;
-            if (i >= cnt) continue;
-            const int64_t p = p0 + i;
-            T x = px[k], y = py[k], z = pz[k], vx = qx[k], vy = qy[k], vz = qz[k], w = pw[k];
-            T phi, ax, ay, az;
-            potential<POT, T>(pot, x, y, z, phi, ax, ay, az);
-            if (!observe_only) {
-                // priors what_i at z_n
-                T wh;
-                if (a.what_mode == 0) {
-                    wh = wflat;
-                } else if (want_cm) {
-                    const T E = T(0.5) * (vx * vx + vy * vy + vz * vz) + phi;
-                    const int c = prior_cell<POT, T>(pot, lct, et, a.cells, Emin, sE, E, x, y, z, vx, vy, vz, a.ex, m);
-                    wh = cm[c];
-                    if (a.what_mode == 2) a.what[p] = wh;
-                } else {
-                    wh = a.what[p];
-                }
-                // dF/dw_i with the priors held fixed
-                int jj[kMaxEntries];
-                T K[kMaxEntries];
-                kernel_entries<T>(a.lay, ed, ed64, x, y, z, vy, vz, jj, K);
-                T chi = T(0);
-                #pragma unroll
-                for (int e = 0; e < kMaxEntries; ++e)
-                    if (jj[e] >= 0) chi += K[e] * cl[jj[e]];
-                const T lr = dlog(w / wh);
-                const T G = -chi - mu * (lr + T(1));
-                sS -= double(w) * double(lr);
-                sW += double(w);
-                sW2 += double(w) * double(w);
-                mW = fmin(mW, double(w));
-                const T wn = a.update == 1 ? w * dexp(edt * G) : w * (T(1) + edt * G);
-                if (!(wn == wn) || wn == T(INFINITY) || wn == T(-INFINITY)) bad |= 2u;   // non-finite
-                else if (!(wn > T(0))) bad |= 1u;                                        // w <= 0
-                w = wn;
-                // kick-drift-kick
-                if (!a.frozen) {
-                    vx += hdt * ax; vy += hdt * ay; vz += hdt * az;
-                    x += dt * vx; y += dt * vy; z += dt * vz;
-                    potential<POT, T>(pot, x, y, z, phi, ax, ay, az);
-                    vx += hdt * ax; vy += hdt * ay; vz += hdt * az;
-                }
-                a.out[p] = x;
-                a.out[a.stride + p] = y;
-                a.out[2 * a.stride + p] = z;
-                a.out[3 * a.stride + p] = vx;
-                a.out[4 * a.stride + p] = vy;
-                a.out[5 * a.stride + p] = vz;
-                a.out[6 * a.stride + p] = w;
-            }
-            // observables and prior cells of the new state
-            {
-                int jj[kMaxEntries];
-                T K[kMaxEntries];
-                kernel_entries<T>(a.lay, ed, ed64, x, y, z, vy, vz, jj, K);
-                #pragma unroll
-                for (int e = 0; e < kMaxEntries; ++e)
-                    if (jj[e] >= 0) atomicAdd(&hist[jj[e]], double(w * K[e]));
-                if (a.accum_cells) {
-                    const T E = T(0.5) * (vx * vx + vy * vy + vz * vz) + phi;
-                    const int c = prior_cell<POT, T>(pot, lct, et, a.cells, Emin, sE, E, x, y, z, vx, vy, vz, a.ex, m);
-                    atomicAdd(&csum[c], double(w));
-                    atomicAdd(&ccnt[c], 1u);
-                }
-            }
+            open[k] = i < cnt ? particle_step<POT, NB>(a, B, acc, p0 + i, px[k], py[k], pz[k], qx[k], qy[k], qz[k],
+                                                        pw[k], tg[k])
+                              : 0u;
+        }
+        if constexpr (F32) {
+            #pragma unroll
+            for (int k = 0; k < ILP; ++k)
+                if (open[k])
+                    fixup<POT, NB>((cExact*)a.ex, B.m, open[k], p0 + k * nt + tid, a.stride, a.cellrow,
+                                   (gF32*)a.out, (gU16*)((char*)a.out + 7 * a.stride * sizeof(T)), (lF64*)hist,
+                                   (lF64*)csum, (lU32*)ccnt, B.pot.lcE0, B.pot.lcEinv);
         }
     }
-    if (bad) {
-        __hip_atomic_fetch_or(a.flag, (int)bad, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (acc.bad) {
+        __hip_atomic_fetch_or(a.flag, (int)acc.bad, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         *a.bad_step = *a.d_step;
     }
 }
@@ -243,33 +412,21 @@ __global__ void __launch_bounds__(256) erange_kernel(ErangeArgs<T> a) {
 }
 
 // ------------------------------------------ priors of the current state (readback)
-template <typename T, int POT>
+// The prior cell of every particle is its stored tag (decided when the state
+// was made).
+template <typename T>
 __global__ void __launch_bounds__(256) gather_kernel(GatherArgs<T> a) {
     const int t0 = a.block_tile0[blockIdx.x], t1 = a.block_tile0[blockIdx.x + 1];
     for (int t = t0; t < t1; ++t) {
         const int m = a.tile_model[t];
-        const Pot<T> pot = a.pots[m];
-        const T Emin = a.erange[2 * m], sE = T(a.cells.n0) / (a.erange[2 * m + 1] - a.erange[2 * m]);
-        const T* lct = a.lctab + pot.lc_off;
         const int64_t p0 = a.tile_p0[t];
         const int cnt = a.tile_cnt[t];
         for (int i = threadIdx.x; i < cnt; i += blockDim.x) {
             const int64_t p = p0 + i;
             T wh;
-            if (a.what_mode == 0) {
-                wh = a.flatw[m];
-            } else if (a.what_mode == 3) {
-                wh = a.what[p];
-            } else {
-                T x = a.in[p], y = a.in[a.stride + p], z = a.in[2 * a.stride + p];
-                T vx = a.in[3 * a.stride + p], vy = a.in[4 * a.stride + p], vz = a.in[5 * a.stride + p];
-                T phi, ax, ay, az;
-                potential<POT, T>(pot, x, y, z, phi, ax, ay, az);
-                const T E = T(0.5) * (vx * vx + vy * vy + vz * vz) + phi;
-                wh = a.cellmean[(size_t)m * a.cells.ncell +
-                                prior_cell<POT, T>(pot, lct, (const float2*)a.lcetab + (size_t)m * kLcE, a.cells,
-                                                   Emin, sE, E, x, y, z, vx, vy, vz, a.ex, m)];
-            }
+            if (a.what_mode == 0) wh = a.flatw[m];
+            else if (a.what_mode == 3) wh = a.what[p];
+            else wh = a.cellmean[(size_t)m * a.cells.ncell + a.tin[a.cellrow * a.stride + p]];
             a.out[p] = wh;
         }
     }
@@ -278,44 +435,44 @@ __global__ void __launch_bounds__(256) gather_kernel(GatherArgs<T> a) {
 // ------------------------------------------------------------------ launchers
 template <typename T>
 hipError_t launch_gather(const GatherArgs<T>& a, int pot_kind, int blocks, hipStream_t s) {
-    switch (pot_kind) {
-        case 0: hipLaunchKernelGGL((gather_kernel<T, 0>), dim3(blocks), dim3(256), 0, s, a); break;
-        case 1: hipLaunchKernelGGL((gather_kernel<T, 1>), dim3(blocks), dim3(256), 0, s, a); break;
-        default: hipLaunchKernelGGL((gather_kernel<T, 2>), dim3(blocks), dim3(256), 0, s, a); break;
-    }
+    (void)pot_kind;
+    hipLaunchKernelGGL((gather_kernel<T>), dim3(blocks), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 template hipError_t launch_gather<float>(const GatherArgs<float>&, int, int, hipStream_t);
 template hipError_t launch_gather<double>(const GatherArgs<double>&, int, int, hipStream_t);
 
-template <typename T, typename PT, int POT>
-static hipError_t launch_step_pot(const StepArgs<T, PT>& a, int ilp, int blocks, int threads, size_t lds,
-                                  hipStream_t s) {
-    switch (ilp) {
-        case 1: hipLaunchKernelGGL((step_kernel<T, PT, POT, 1>), dim3(blocks), dim3(threads), lds, s, a); break;
-        case 2: hipLaunchKernelGGL((step_kernel<T, PT, POT, 2>), dim3(blocks), dim3(threads), lds, s, a); break;
-        default: hipLaunchKernelGGL((step_kernel<T, PT, POT, 4>), dim3(blocks), dim3(threads), lds, s, a); break;
-    }
+template <typename T, typename PT, int POT, int NB>
+static hipError_t launch_step_nb(const StepArgs<T, PT>& a, int ilp, int blocks, int threads, size_t lds,
+                                 hipStream_t s) {
+    if (ilp == 1) hipLaunchKernelGGL((step_kernel<T, PT, POT, NB, 1>), dim3(blocks), dim3(threads), lds, s, a);
+    else hipLaunchKernelGGL((step_kernel<T, PT, POT, NB, 2>), dim3(blocks), dim3(threads), lds, s, a);
     return hipGetLastError();
 }
 
-template <typename T, typename PT>
-hipError_t launch_step(const StepArgs<T, PT>& a, int pot_kind, int ilp, int blocks, int threads, size_t lds,
-                       hipStream_t s) {
-    switch (pot_kind) {
-        case 0: return launch_step_pot<T, PT, 0>(a, ilp, blocks, threads, lds, s);
-        case 1: return launch_step_pot<T, PT, 1>(a, ilp, blocks, threads, lds, s);
-        default: return launch_step_pot<T, PT, 2>(a, ilp, blocks, threads, lds, s);
-    }
+// Binnings are compiled for at most NB = 2 or 4 (fewer live constants when the
+// layout has one or two).
+template <typename T, typename PT, int POT>
+static hipError_t launch_step_pot(const StepArgs<T, PT>& a, int nbin, int ilp, int blocks, int threads, size_t lds,
+                                  hipStream_t s) {
+    if (nbin <= 2) return launch_step_nb<T, PT, POT, 2>(a, ilp, blocks, threads, lds, s);
+    return launch_step_nb<T, PT, POT, 4>(a, ilp, blocks, threads, lds, s);
 }
 
 template <typename T, typename PT>
-hipError_t set_step_lds_limit(int pot_kind, size_t lds) {
-    const void* fns[] = {
-        (const void*)step_kernel<T, PT, 0, 1>, (const void*)step_kernel<T, PT, 0, 2>, (const void*)step_kernel<T, PT, 0, 4>,
-        (const void*)step_kernel<T, PT, 1, 1>, (const void*)step_kernel<T, PT, 1, 2>, (const void*)step_kernel<T, PT, 1, 4>,
-        (const void*)step_kernel<T, PT, 2, 1>, (const void*)step_kernel<T, PT, 2, 2>, (const void*)step_kernel<T, PT, 2, 4>};
-    (void)pot_kind;
+hipError_t launch_step(const StepArgs<T, PT>& a, int pot_kind, int nbin, int ilp, int blocks, int threads, size_t lds,
+                       hipStream_t s) {
+    switch (pot_kind) {
+        case 0: return launch_step_pot<T, PT, 0>(a, nbin, ilp, blocks, threads, lds, s);
+        case 1: return launch_step_pot<T, PT, 1>(a, nbin, ilp, blocks, threads, lds, s);
+        default: return launch_step_pot<T, PT, 2>(a, nbin, ilp, blocks, threads, lds, s);
+    }
+}
+
+template <typename T, typename PT, int POT>
+static hipError_t set_lds_pot(size_t lds) {
+    const void* fns[] = {(const void*)step_kernel<T, PT, POT, 2, 1>, (const void*)step_kernel<T, PT, POT, 2, 2>,
+                         (const void*)step_kernel<T, PT, POT, 4, 1>, (const void*)step_kernel<T, PT, POT, 4, 2>};
     for (const void* f : fns) {
         hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
@@ -323,6 +480,14 @@ hipError_t set_step_lds_limit(int pot_kind, size_t lds) {
     return hipSuccess;
 }
 
+template <typename T, typename PT>
+hipError_t set_step_lds_limit(int pot_kind, size_t lds) {
+    switch (pot_kind) {
+        case 0: return set_lds_pot<T, PT, 0>(lds);
+        case 1: return set_lds_pot<T, PT, 1>(lds);
+        default: return set_lds_pot<T, PT, 2>(lds);
+    }
+}
 
 template <typename T>
 hipError_t launch_erange(const ErangeArgs<T>& a, int pot_kind, int blocks, hipStream_t s) {
@@ -334,8 +499,8 @@ hipError_t launch_erange(const ErangeArgs<T>& a, int pot_kind, int blocks, hipSt
     return hipGetLastError();
 }
 
-template hipError_t launch_step<float, float>(const StepArgs<float, float>&, int, int, int, int, size_t, hipStream_t);
-template hipError_t launch_step<double, double>(const StepArgs<double, double>&, int, int, int, int, size_t, hipStream_t);
+template hipError_t launch_step<float, float>(const StepArgs<float, float>&, int, int, int, int, int, size_t, hipStream_t);
+template hipError_t launch_step<double, double>(const StepArgs<double, double>&, int, int, int, int, int, size_t, hipStream_t);
 template hipError_t set_step_lds_limit<float, float>(int, size_t);
 template hipError_t set_step_lds_limit<double, double>(int, size_t);
 template hipError_t launch_erange<float>(const ErangeArgs<float>&, int, int, hipStream_t);
