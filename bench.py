@@ -12,6 +12,7 @@ particles resident in HBM; each fused step kernel is bracketed by HIP events on
 the context's stream, which gives the roofline figure.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--n N] [--no-cpu-baseline]
+    python bench.py --copy-calibration MIB   # plain device copy, for HBM counter scaling
 """
 import argparse
 import json
@@ -54,6 +55,9 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=24)
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--graph-steps", type=int, default=100)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only copy MIB MiB device to device 10 times (the reference for the "
+                         "FETCH_SIZE / WRITE_SIZE counters) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -61,6 +65,16 @@ def main():
         sys.exit(2)
 
     import torch
+
+    if args.copy_calibration:
+        n = args.copy_calibration * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(10):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_per_launch": 4 * n, "launches": 10}))
+        return
 
     import paper_1207_6403_amd as m2m
     from synth import configs

@@ -171,7 +171,7 @@ static void free_plan(m2m_ctx* c) {
     Plan& p = c->plan;
     for (void* q : {(void*)p.tile_model, (void*)p.tile_p0, (void*)p.tile_cnt, (void*)p.block_tile0,
                     (void*)p.block_slot0, (void*)p.model_slot, (void*)p.part, (void*)p.seg_stats,
-                    (void*)p.erange_out})
+                    (void*)p.erange_out, (void*)p.chunk_desc})
         dfree(c, q);
     p = Plan();
     for (int k = 0; k < 2; ++k)
@@ -226,6 +226,17 @@ static m2m_status make_plan(m2m_ctx* c, int threads, int ilp, int bpc) {
         (s = upload(c, &p.block_tile0, bt0)) || (s = upload(c, &p.block_slot0, bs0)) ||
         (s = upload(c, &p.model_slot, mslot)))
         return s;
+    // finalise chunk descriptors: model, first column, columns, first slot, slots
+    std::vector<int32_t> desc(8 * (size_t)c->nchunk, 0);
+    for (int k = 0; k < c->nchunk; ++k) {
+        const int m = c->chunk_model_host[k];
+        desc[8 * k] = m;
+        desc[8 * k + 1] = c->chunk_col0_host[k];
+        desc[8 * k + 2] = c->chunk_ncol_host[k];
+        desc[8 * k + 3] = mslot[m];
+        desc[8 * k + 4] = mslot[m + 1] - mslot[m];
+    }
+    if ((s = upload(c, &p.chunk_desc, desc))) return s;
     if ((s = dalloc(c, (char**)&p.part, (size_t)nslot * c->pcols * tsize(c))) ||
         (s = dalloc(c, &p.seg_stats, (size_t)nslot * 4)) || (s = dalloc(c, &p.erange_out, (size_t)nslot * 2)))
         return s;
@@ -327,9 +338,7 @@ static void fill_fin_args(m2m_ctx* c, FinArgs<T, T>& f, int first, int accum, in
     f.J = c->J;
     f.ncell = c->NC;
     f.n_models = c->M;
-    f.chunk_model = c->chunk_model;
-    f.chunk_col0 = c->chunk_col0;
-    f.chunk_ncol = c->chunk_ncol;
+    f.chunk_desc = p.chunk_desc;
     f.model_slot = p.model_slot;
     f.model_chunk = c->model_chunk;
     f.nchunk = c->nchunk;
@@ -370,7 +379,7 @@ static hipError_t launch_one_T(m2m_ctx* c, int64_t n, hipEvent_t e0, hipEvent_t 
     fill_step_args<T>(c, a, (int)(n & 1), 0, wm, acc);
     const Plan& p = c->plan;
     if (e0) (void)hipEventRecord(e0, c->stream);
-    hipError_t e = launch_step<T, T>(a, c->pot_kind, c->lay.nbin, p.ilp, p.nblock, p.threads, p.lds, c->stream);
+    hipError_t e = launch_step<T, T>(a, c->pot_kind, c->sig, c->lay.nbin, p.ilp, p.nblock, p.threads, p.lds, c->stream);
     if (e1) (void)hipEventRecord(e1, c->stream);
     if (e != hipSuccess) return e;
     FinArgs<T, T> f;
@@ -389,7 +398,7 @@ static hipError_t launch_prologue_T(m2m_ctx* c) {
     fill_step_args<T>(c, a, (int)(c->step & 1), 1, 0, accum);
     a.out = (T*)c->state[c->step & 1];   // observing only: the tags of the current state are written
     const Plan& p = c->plan;
-    hipError_t e = launch_step<T, T>(a, c->pot_kind, c->lay.nbin, p.ilp, p.nblock, p.threads, p.lds, c->stream);
+    hipError_t e = launch_step<T, T>(a, c->pot_kind, c->sig, c->lay.nbin, p.ilp, p.nblock, p.threads, p.lds, c->stream);
     if (e != hipSuccess) return e;
     FinArgs<T, T> f;
     // the prologue's chi^2 shares are those of "step -1"
@@ -480,33 +489,47 @@ static Layout<T> layout_of(const m2m_ctx* c) {
     int off = 0, e0 = 0;
     for (int b = 0; b < c->lay.nbin; ++b) {
         const m2m_binning& d = c->lay.bin[b];
-        L.kind[b] = d.kind;
-        L.nmom[b] = d.nmom;
-        L.mom[b] = 0;
-        for (int k = 0; k < d.nmom; ++k) L.mom[b] |= d.mom[k] << (2 * k);
-        L.off[b] = off;
-        L.edge0[b] = e0;
+        BinDesc<T>& B = L.b[b];
+        B.kind = d.kind;
+        B.nmom = d.nmom;
+        B.mom = 0;
+        for (int k = 0; k < d.nmom; ++k) B.mom |= d.mom[k] << (2 * k);
+        B.off = off;
+        B.edge0 = e0;
         if (d.kind == M2M_BIN_GRID) {
-            L.nb[b] = d.nx * d.ny;
-            L.nx[b] = d.nx;
-            L.ny[b] = d.ny;
-            L.x0[b] = (T)d.x0;
-            L.sx[b] = (T)(d.nx / (d.x1 - d.x0));
-            L.y0[b] = (T)d.y0;
-            L.sy[b] = (T)(d.ny / (d.y1 - d.y0));
+            B.nb = d.nx * d.ny;
+            B.nx = d.nx;
+            B.ny = d.ny;
+            B.x0 = (T)d.x0;
+            B.sx = (T)(d.nx / (d.x1 - d.x0));
+            B.y0 = (T)d.y0;
+            B.sy = (T)(d.ny / (d.y1 - d.y0));
         } else {
-            L.nb[b] = d.nedge - 1;
+            B.nb = d.nedge - 1;
             e0 += d.nedge;
         }
-        off += d.nmom * L.nb[b];
+        off += d.nmom * B.nb;
     }
     return L;
+}
+
+// Structure signature of the layout (selects kernels compiled for it).
+static uint64_t signature_of(const m2m_ctx* c) {
+    uint64_t code[kMaxBin] = {0, 0, 0, 0};
+    for (int b = 0; b < c->lay.nbin; ++b) {
+        const m2m_binning& d = c->lay.bin[b];
+        int mom = 0;
+        for (int k = 0; k < d.nmom; ++k) mom |= d.mom[k] << (2 * k);
+        code[b] = bin_code(d.kind, d.nmom, mom);
+    }
+    return layout_sig(c->lay.nbin, code[0], code[1], code[2], code[3]);
 }
 
 template <typename T>
 static void build_layout(m2m_ctx* c) {
     const Layout<T> L = layout_of<T>(c);
     std::memcpy(c->lay_bytes, &L, sizeof(L));
+    c->sig = signature_of(c);
     Cells C{};
     C.n0 = c->prior.n[0];
     C.n1 = c->prior.n[1];
@@ -695,9 +718,10 @@ static m2m_status create_T(m2m_ctx* c, const m2m_target* tg, const void* xv, con
         mch[c->M] = (int32_t)cm.size();
         c->nchunk = (int)cm.size();
         c->model_chunk_host = mch;
-        if ((s = upload(c, &c->chunk_model, cm)) || (s = upload(c, &c->chunk_col0, cc0)) ||
-            (s = upload(c, &c->chunk_ncol, cn)) || (s = upload(c, &c->model_chunk, mch)) ||
-            (s = dalloc(c, &c->chunk_chi, 4 * (size_t)c->nchunk)))
+        c->chunk_model_host = cm;
+        c->chunk_col0_host = cc0;
+        c->chunk_ncol_host = cn;
+        if ((s = upload(c, &c->model_chunk, mch)) || (s = dalloc(c, &c->chunk_chi, 4 * (size_t)c->nchunk)))
             return s;
         HIPCHK(c, hipMemset(c->chunk_chi, 0, sizeof(double) * 4 * c->nchunk));
     }

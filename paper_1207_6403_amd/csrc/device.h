@@ -36,23 +36,69 @@ struct Pot {
     T lcE0, lcEinv;     // uniform-E Lc table: first energy, 1 / spacing
 };
 
-// Observation layout (kept small: it lives in scalar registers).  sx, sy =
-// n / width give the fast FP32 bin coordinate; mom packs the listed moments in
-// 2-bit fields.  The FP64 decision uses the defining form (v - x0) / width * n
-// with the constants in Exact.
+// x unchanged, but opaque to the optimiser: conditions derived from a uniform
+// value are then evaluated where they are used (a few scalar instructions)
+// instead of being hoisted to the kernel entry and held in scalar registers
+// across the whole particle loop.
+template <typename X>
+__device__ __forceinline__ X opaque(X x) {
+    asm volatile("" : "+s"(x));
+    return x;
+}
+
+// One binning of the observation layout.  Grids: sx, sy = n / width give the
+// fast FP32 bin coordinate (the FP64 decision uses the defining form
+// (v - x0) / width * n with the constants in Exact); shells and annuli: nb + 1
+// edges from edge0 of the edge tables.  mom packs the listed moments in 2-bit
+// fields: moment m is (mom >> 2m) & 3.
+template <typename T>
+struct BinDesc {
+    int32_t kind, nmom, mom, off;   // off: first observable index of the binning
+    int32_t nb, edge0, nx, ny;      // nb: bins per moment
+    T x0, sx, y0, sy;
+};
+
 template <typename T>
 struct Layout {
     T cosi, sini;
     int32_t nbin;
     int32_t J;
-    int32_t kind[kMaxBin];
-    int32_t nmom[kMaxBin];
-    int32_t mom[kMaxBin];      // moment m of binning b: (mom[b] >> 2m) & 3
-    int32_t off[kMaxBin];      // first observable index of the binning
-    int32_t nb[kMaxBin];       // bins per moment
-    int32_t edge0[kMaxBin];    // offset of the binning's edges in the edge tables
-    int32_t nx[kMaxBin], ny[kMaxBin];
-    T x0[kMaxBin], sx[kMaxBin], y0[kMaxBin], sy[kMaxBin];
+    BinDesc<T> b[kMaxBin];
+};
+
+// Compile-time signature of a layout's structure: nbin in the low 4 bits, then
+// 10 bits per binning (kind, nmom, mom).  Kernels compiled for a signature
+// take these from the signature instead of the layout (0: from the layout).
+constexpr uint64_t bin_code(int kind, int nmom, int mom) { return uint64_t(kind | nmom << 2 | mom << 4); }
+constexpr uint64_t layout_sig(int nbin, uint64_t c0, uint64_t c1 = 0, uint64_t c2 = 0, uint64_t c3 = 0) {
+    return uint64_t(nbin) | c0 << 4 | c1 << 14 | c2 << 24 | c3 << 34;
+}
+// The layouts with compiled kernels: sky pixels (mass) with a kinematic grid
+// (first and second LOS moments); 3D shells (mass) with projected annuli
+// (second LOS moment).
+constexpr uint64_t kSigPixKin = layout_sig(2, bin_code(3, 1, 0), bin_code(3, 2, 1 | 2 << 2));
+constexpr uint64_t kSigShellAnn = layout_sig(2, bin_code(1, 1, 0), bin_code(2, 1, 2));
+
+// Structure of the layout seen by a kernel compiled for signature SIG.
+template <uint64_t SIG, typename T>
+struct LayoutView {
+    const Layout<T>& L;
+    __device__ __forceinline__ int nbin() const {
+        if constexpr (SIG != 0) return int(SIG & 15);
+        else return opaque(L.nbin);
+    }
+    __device__ __forceinline__ int kind(int b) const {
+        if constexpr (SIG != 0) return int((SIG >> (4 + 10 * b)) & 3);
+        else return opaque(L.b[b].kind);
+    }
+    __device__ __forceinline__ int nmom(int b) const {
+        if constexpr (SIG != 0) return int((SIG >> (6 + 10 * b)) & 3);
+        else return opaque(L.b[b].nmom);
+    }
+    __device__ __forceinline__ int mom(int b) const {
+        if constexpr (SIG != 0) return int((SIG >> (8 + 10 * b)) & 63);
+        else return opaque(L.b[b].mom);
+    }
 };
 
 // Moving-prior cell geometry.
@@ -75,16 +121,6 @@ struct Exact {
     double cosd, sind;
     double x0d[kMaxBin], wxd[kMaxBin], y0d[kMaxBin], wyd[kMaxBin];
 };
-
-// x unchanged, but opaque to the optimiser: conditions derived from a uniform
-// value are then evaluated where they are used (a few scalar instructions)
-// instead of being hoisted to the kernel entry and held in scalar registers
-// across the whole particle loop.
-template <typename X>
-__device__ __forceinline__ X opaque(X x) {
-    asm volatile("" : "+s"(x));
-    return x;
-}
 
 // ------------------------------------------------------------------ potentials
 template <typename T> __device__ __forceinline__ T dsqrt(T v) { return sqrt(v); }
@@ -367,21 +403,21 @@ __device__ __forceinline__ int bin_f64(int kind, double cosd, double sind, doubl
     return edge_bin(e, ne, rad);
 }
 
-// Bin of binning b in FP32, -1 outside; sure = false when the coordinate lies
-// within the guard band of an edge (the caller re-decides with bin_f64).
-__device__ __forceinline__ int bin_fast(const Layout<float>& L, int b, const float* __restrict__ ef, float x, float y,
-                                        float z, float Ys, bool& sure) {
-    const int kind = opaque(L.kind[b]);
+// Bin of binning b (kind `kind`) in FP32, -1 outside; sure = false when the
+// coordinate lies within the guard band of an edge (the caller re-decides with
+// bin_f64).
+__device__ __forceinline__ int bin_fast(const BinDesc<float>& d, int kind, const float* __restrict__ ef, float x,
+                                        float y, float z, float Ys, bool& sure) {
     if (kind == 3) {
-        const float fx = (x - L.x0[b]) * L.sx[b];
-        const float fy = (Ys - L.y0[b]) * L.sy[b];
-        sure = !near_cell_edge(fx, L.nx[b], kGuardBin) && !near_cell_edge(fy, L.ny[b], kGuardBin);
-        if (fx >= 0.0f && fx < float(L.nx[b]) && fy >= 0.0f && fy < float(L.ny[b])) return int(fy) * L.nx[b] + int(fx);
+        const float fx = (x - d.x0) * d.sx;
+        const float fy = (Ys - d.y0) * d.sy;
+        sure = !near_cell_edge(fx, d.nx, kGuardBin) && !near_cell_edge(fy, d.ny, kGuardBin);
+        if (fx >= 0.0f && fx < float(d.nx) && fy >= 0.0f && fy < float(d.ny)) return int(fy) * d.nx + int(fx);
         return -1;
     }
     const float rad = kind == 1 ? __builtin_sqrtf(x * x + y * y + z * z) : __builtin_sqrtf(x * x + Ys * Ys);
-    const float* e = ef + L.edge0[b];
-    const int ne = L.nb[b] + 1;
+    const float* e = ef + d.edge0;
+    const int ne = d.nb + 1;
     const float g = kGuardBin * rad;
     const int k = edge_bin(e, ne, rad);
     if (k >= 0) sure = !(rad - e[k] < g) && !(e[k + 1] - rad < g);

@@ -26,8 +26,9 @@ template <typename T, typename PT>
 __global__ void __launch_bounds__(256) finalize_kernel(FinArgs<T, PT> a) {
     __shared__ double part[kFinGroups][kFinCols + 1];
     __shared__ double tot[kFinCols];
-    __shared__ double red[4][8];
-    if (*a.flag) return;   // the step failed: leave every output as it was
+    // the step failed: leave every output as it was (checked before the first
+    // store, so that the loads below need not wait for the flag)
+    const int failed = *a.flag;
     const int tid = threadIdx.x;
     double* chi_out = a.chunk_chi + (size_t)(a.parity) * 2 * a.nchunk;
     const double* chi_prev = a.chunk_chi + (size_t)(a.parity ^ 1) * 2 * a.nchunk;
@@ -35,13 +36,15 @@ __global__ void __launch_bounds__(256) finalize_kernel(FinArgs<T, PT> a) {
     if ((int)blockIdx.x < a.nchunk) {
         // ------------------------------------------------ column block
         const int chunk = blockIdx.x;
-        const int m = a.chunk_model[chunk];
-        const int col0 = a.chunk_col0[chunk];
-        const int ncol = a.chunk_ncol[chunk];
-        const int s0 = a.model_slot[m], ns = a.model_slot[m + 1] - s0;
+        const int* d = a.chunk_desc + 8 * chunk;
+        const int m = d[0], col0 = d[1], ncol = d[2], s0 = d[3], ns = d[4];
         const int g = tid / kFinCols, c = tid % kFinCols;
         const int col = col0 + c;
         const bool live = c < ncol && (col < a.J || (col >= a.jpad && a.accum_cells));
+        // the column's target, error and smoothed value, fetched while the slots load
+        const bool obs = g == 0 && live && col < a.J;
+        const size_t j = (size_t)m * a.J + col;
+        const double Yj = obs ? a.Y[j] : 0.0, sj = obs ? a.sigma[j] : 1.0, ysj = obs && !a.first ? a.ys[j] : 0.0;
         const int per = (ns + kFinGroups - 1) / kFinGroups;
         const int sa = s0 + g * per, sb = min(s0 + ns, sa + per);
         double acc = 0;
@@ -56,6 +59,7 @@ __global__ void __launch_bounds__(256) finalize_kernel(FinArgs<T, PT> a) {
                 for (int k = 0; k < kSlotsPerSplit; ++k) acc += double(v[k]);
             }
         }
+        if (failed) return;
         part[g][c] = acc;
         __syncthreads();
         double chi = 0, chii = 0;
@@ -69,15 +73,14 @@ __global__ void __launch_bounds__(256) finalize_kernel(FinArgs<T, PT> a) {
         if (g == 0 && live) {
             const double v = tot[c];
             if (col < a.J) {
-                const size_t j = (size_t)m * a.J + col;
-                const double ys = a.first ? v : a.ys[j] + a.g * (v - a.ys[j]);
-                const double d = (ys - a.Y[j]) / a.sigma[j];
-                const double di = (v - a.Y[j]) / a.sigma[j];
+                const double ys = a.first ? v : ysj + a.g * (v - ysj);
+                const double dl = (ys - Yj) / sj;
+                const double di = (v - Yj) / sj;
                 a.y[j] = v;
                 a.ys[j] = ys;
-                a.delta[j] = d;
-                a.cvec[j] = T(d / a.sigma[j]);
-                chi = d * d;
+                a.delta[j] = dl;
+                a.cvec[j] = T(dl / sj);
+                chi = dl * dl;
                 chii = di * di;
             } else if (((col - a.jpad) & 1) == 0) {
                 // (sum, count) pairs never straddle a chunk: chunks start at
@@ -101,7 +104,7 @@ __global__ void __launch_bounds__(256) finalize_kernel(FinArgs<T, PT> a) {
     }
 
     // ---------------------------------------------------- statistics block
-    if (a.first) return;
+    if (a.first || failed) return;
     const long long n = *a.d_step;
     for (int m = 0; m < a.n_models; ++m) {
         double x2 = 0, x2i = 0, S = 0, W = 0, W2 = 0, mn = INFINITY;
@@ -146,7 +149,6 @@ __global__ void __launch_bounds__(256) finalize_kernel(FinArgs<T, PT> a) {
         __syncthreads();
     }
     if (tid == 0) *a.d_step = n + 1;
-    (void)red;
 }
 
 template <typename T, typename PT>

@@ -20,6 +20,7 @@ struct Plan {
     int32_t* block_tile0 = nullptr;
     int32_t* block_slot0 = nullptr;
     int32_t* model_slot = nullptr;
+    int32_t* chunk_desc = nullptr;   // 8 per finalise chunk: model, col0, ncol, slot0, nslot
     void* part = nullptr;
     double* seg_stats = nullptr;
     double* erange_out = nullptr;
@@ -39,6 +40,7 @@ struct m2m_ctx {
     int64_t N = 0, stride = 0;
     int J = 0, JP = 0, NC = 0, pcols = 0, nedge = 0;
     alignas(16) unsigned char lay_bytes[sizeof(m2m::Layout<double>)] = {};
+    uint64_t sig = 0;   // layout structure signature
     m2m::Cells cells{};
     // device
     hipStream_t stream = nullptr;
@@ -65,9 +67,7 @@ struct m2m_ctx {
     double* cellmean64 = nullptr;
     // finalise column chunks (launch-shape independent) and chi^2 shares
     int nchunk = 0;
-    int32_t* chunk_model = nullptr;
-    int32_t* chunk_col0 = nullptr;
-    int32_t* chunk_ncol = nullptr;
+    std::vector<int32_t> chunk_model_host, chunk_col0_host, chunk_ncol_host;
     int32_t* model_chunk = nullptr;
     std::vector<int32_t> model_chunk_host;
     double* chunk_chi = nullptr;

@@ -72,9 +72,7 @@ template <typename T, typename PT>
 struct FinArgs {
     const PT* part;
     int32_t pcols, jpad, J, ncell, n_models;
-    const int32_t* chunk_model;
-    const int32_t* chunk_col0;
-    const int32_t* chunk_ncol;
+    const int32_t* chunk_desc;    // 8 per chunk: model, col0, ncol, slot0, nslot
     const int32_t* model_slot;    // M + 1
     const int32_t* model_chunk;   // M + 1
     int32_t nchunk;
@@ -134,8 +132,8 @@ struct GatherArgs {
 };
 
 template <typename T, typename PT>
-hipError_t launch_step(const StepArgs<T, PT>& a, int pot_kind, int nbin, int ilp, int blocks, int threads, size_t lds,
-                       hipStream_t s);
+hipError_t launch_step(const StepArgs<T, PT>& a, int pot_kind, uint64_t sig, int nbin, int ilp, int blocks,
+                       int threads, size_t lds, hipStream_t s);
 template <typename T, typename PT>
 hipError_t set_step_lds_limit(int pot_kind, size_t lds);
 template <typename T, typename PT>

@@ -81,14 +81,15 @@ __device__ __forceinline__ void st_at(void* base, uint32_t off, X v) {
 }
 
 // Scatter w * K_j of one particle's bin k of binning b (moments of v_los = vl).
-template <typename T>
-__device__ __forceinline__ void scatter_bin(const Layout<T>& L, double* hist, int b, int k, T wn, T vl) {
-    const int base = L.off[b] + k;
-    const int nmom = opaque(L.nmom[b]), mom = opaque(L.mom[b]);
+template <uint64_t SIG, typename T>
+__device__ __forceinline__ void scatter_bin(const LayoutView<SIG, T>& V, double* hist, int b, int k, T wn, T vl) {
+    const BinDesc<T>& d = V.L.b[b];
+    const int base = d.off + k;
+    const int nmom = V.nmom(b), mom = V.mom(b);
     #pragma unroll
     for (int mm = 0; mm < 3; ++mm) {
         if (mm >= nmom) break;
-        atomicAdd(&hist[base + mm * L.nb[b]], double(wn * moment_value<T>((mom >> (2 * mm)) & 3, vl)));
+        atomicAdd(&hist[base + mm * d.nb], double(wn * moment_value<T>((mom >> (2 * mm)) & 3, vl)));
     }
 }
 
@@ -99,16 +100,17 @@ __device__ __forceinline__ void scatter_bin(const Layout<T>& L, double* hist, in
 // FP32 kernels decide in FP32; a decision inside its guard band is left open
 // and flagged in the returned mask (bit b: binning b, bit NB: the cell), to be
 // re-taken in FP64 by fixup(); FP64 kernels decide in FP64 and return 0.
-template <int POT, int NB, typename T, typename PT>
+template <int POT, int NB, uint64_t SIG, typename T, typename PT>
 __device__ __forceinline__ unsigned particle_step(const StepArgs<T, PT>& a, const Blk<T>& B, Acc& acc, int64_t p,
                                                   T x, T y, T z, T vx, T vy, T vz, T w,
                                                   const uint16_t (&tg)[kMaxBin + 1]) {
     const Layout<T>& L = a.lay;
+    const LayoutView<SIG, T> V{L};
     const uint32_t fl = opaque(a.flags);
     const uint32_t rb = opaque(uint32_t(a.stride * sizeof(T)));   // bytes per value row
     const uint32_t o = uint32_t(p) * uint32_t(sizeof(T));
     const uint32_t ot = 7 * rb + uint32_t(p) * 2u;                 // tag of row 0
-    const int nbin = opaque(L.nbin);
+    const int nbin = V.nbin();
     T wn = w, phi = T(0);
     bool have_phi = false;
     if (!(fl & kObserve)) {
@@ -120,12 +122,12 @@ __device__ __forceinline__ unsigned particle_step(const StepArgs<T, PT>& a, cons
             if (b >= nbin) break;
             const int k = tg[b];
             if (k == kNoBin) continue;
-            const int base = L.off[b] + k;
-            const int nmom = opaque(L.nmom[b]), mom = opaque(L.mom[b]);
+            const int base = L.b[b].off + k;
+            const int nmom = V.nmom(b), mom = V.mom(b);
             #pragma unroll
             for (int mm = 0; mm < 3; ++mm) {
                 if (mm >= nmom) break;
-                chi += moment_value<T>((mom >> (2 * mm)) & 3, vl) * B.cl[base + mm * L.nb[b]];
+                chi += moment_value<T>((mom >> (2 * mm)) & 3, vl) * B.cl[base + mm * L.b[b].nb];
             }
         }
         const uint32_t wm = (fl >> kWhatShift) & 3u;
@@ -170,15 +172,16 @@ __device__ __forceinline__ unsigned particle_step(const StepArgs<T, PT>& a, cons
         int k;
         if constexpr (sizeof(T) == 4) {
             bool sure;
-            k = bin_fast(L, b, B.ed, x, y, z, Ys, sure);
+            k = bin_fast(L.b[b], V.kind(b), B.ed, x, y, z, Ys, sure);
             if (!sure) { open |= 1u << b; continue; }
         } else {
             const Exact* ex = a.ex;
-            k = bin_f64(L.kind[b], ex->cosd, ex->sind, ex->x0d[b], ex->wxd[b], L.nx[b], ex->y0d[b], ex->wyd[b], L.ny[b],
-                        B.ed64 + L.edge0[b], L.nb[b] + 1, x, y, z);
+            const BinDesc<T>& d = L.b[b];
+            k = bin_f64(V.kind(b), ex->cosd, ex->sind, ex->x0d[b], ex->wxd[b], d.nx, ex->y0d[b], ex->wyd[b], d.ny,
+                        B.ed64 + d.edge0, d.nb + 1, x, y, z);
         }
         st_at<uint16_t>(a.out, ot + b * (rb / uint32_t(sizeof(T)) * 2u), k < 0 ? kNoBin : (uint16_t)k);
-        if (k >= 0) scatter_bin(L, B.hist, b, k, wn, vl);
+        if (k >= 0) scatter_bin(V, B.hist, b, k, wn, vl);
     }
     if (fl & kAccum) {
         if (!have_phi) {
@@ -225,15 +228,14 @@ __device__ __noinline__ void fixup(cExact* ex, int m, unsigned open, int64_t p, 
     #pragma unroll
     for (int b = 0; b < NB; ++b) {
         if (!(open & (1u << b))) continue;
-        const int k = bin_f64(ex->lay.kind[b], ex->cosd, ex->sind, ex->x0d[b], ex->wxd[b], ex->lay.nx[b], ex->y0d[b],
-                              ex->wyd[b], ex->lay.ny[b], ex->edges + ex->lay.edge0[b], ex->lay.nb[b] + 1, double(x),
-                              double(y), double(z));
+        const int kind = ex->lay.b[b].kind, nx = ex->lay.b[b].nx, ny = ex->lay.b[b].ny, nb = ex->lay.b[b].nb;
+        const int k = bin_f64(kind, ex->cosd, ex->sind, ex->x0d[b], ex->wxd[b], nx, ex->y0d[b], ex->wyd[b], ny,
+                              ex->edges + ex->lay.b[b].edge0, nb + 1, double(x), double(y), double(z));
         tout[b * stride + p] = k < 0 ? kNoBin : (uint16_t)k;
         if (k < 0) continue;
-        const int base = ex->lay.off[b] + k;
-        for (int mm = 0; mm < ex->lay.nmom[b]; ++mm)
-            __hip_atomic_fetch_add(&hist[base + mm * ex->lay.nb[b]],
-                                   double(wn * moment_value<float>((ex->lay.mom[b] >> (2 * mm)) & 3, vl)),
+        const int base = ex->lay.b[b].off + k, mom = ex->lay.b[b].mom;
+        for (int mm = 0; mm < ex->lay.b[b].nmom; ++mm)
+            __hip_atomic_fetch_add(&hist[base + mm * nb], double(wn * moment_value<float>((mom >> (2 * mm)) & 3, vl)),
                                    __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     }
     if (open & (1u << NB)) {
@@ -253,10 +255,12 @@ __device__ __noinline__ void fixup(cExact* ex, int m, unsigned open, int64_t p, 
     }
 }
 
-template <typename T, typename PT, int POT, int NB, int ILP>
+template <typename T, typename PT, int POT, int NB, uint64_t SIG, int ILP>
 __global__ void __launch_bounds__(sizeof(T) == 8 ? 256 : 1024) step_kernel(StepArgs<T, PT> a) {
     extern __shared__ __align__(16) unsigned char smem[];
-    if (*a.flag) return;   // an earlier step failed: the whole step is a no-op
+    // an earlier step failed: the whole step is a no-op (the flag is checked
+    // before the first store; the table loads need not wait for it)
+    const int failed = *a.flag;
 
     constexpr bool F32 = sizeof(T) == 4;
     const int J = a.lay.J, NC = a.cells.ncell, JP = a.jpad, NE = (a.nedge + 1) & ~1;
@@ -287,6 +291,41 @@ __global__ void __launch_bounds__(sizeof(T) == 8 ? 256 : 1024) step_kernel(StepA
     B.hist = hist; B.csum = csum; B.ccnt = ccnt; B.cl = cl; B.cm = cm; B.ed = ed; B.ed64 = ed64; B.et = et;
     B.lct = lct;
     Acc acc;
+    if (failed) return;
+
+    // the particles of a tile (values and the tags of the current state); the
+    // next tile's are loaded while this one is processed
+    struct Regs {
+        T x[ILP], y[ILP], z[ILP], vx[ILP], vy[ILP], vz[ILP], w[ILP];
+        uint16_t tg[ILP][kMaxBin + 1];
+    };
+    auto load_tile = [&](int t, Regs& R) {
+        const int64_t p0 = a.tile_p0[t];
+        const int cnt = a.tile_cnt[t];
+        #pragma unroll
+        for (int k = 0; k < ILP; ++k) {
+            const int i = k * nt + tid;
+            if (i < cnt) {
+                const int64_t p = p0 + i;
+                const uint32_t rb = opaque(uint32_t(a.stride * sizeof(T))), tr = uint32_t(a.stride * 2);
+                const uint32_t o = uint32_t(p) * uint32_t(sizeof(T)), ot = 7 * rb + uint32_t(p) * 2u;
+                R.x[k] = ld_at<T>(a.in, o);
+                R.y[k] = ld_at<T>(a.in, o + rb);
+                R.z[k] = ld_at<T>(a.in, o + 2 * rb);
+                R.vx[k] = ld_at<T>(a.in, o + 3 * rb);
+                R.vy[k] = ld_at<T>(a.in, o + 4 * rb);
+                R.vz[k] = ld_at<T>(a.in, o + 5 * rb);
+                R.w[k] = ld_at<T>(a.in, o + 6 * rb);
+                #pragma unroll
+                for (int b = 0; b < kMaxBin; ++b)
+                    R.tg[k][b] = (stepping && b < NB && b < LayoutView<SIG, T>{a.lay}.nbin()) ? ld_at<uint16_t>(a.in, ot + b * tr)
+                                                                                   : kNoBin;
+                R.tg[k][kMaxBin] = (stepping && want_cm) ? ld_at<uint16_t>(a.in, ot + a.cellrow * tr) : 0;
+            }
+        }
+    };
+    Regs cur_r, next_r;
+    if (t0 < t1) load_tile(t0, cur_r);
 
     for (int t = t0; t <= t1; ++t) {
         const int m = t < t1 ? a.tile_model[t] : -2;
@@ -319,36 +358,15 @@ __global__ void __launch_bounds__(sizeof(T) == 8 ? 256 : 1024) step_kernel(StepA
                 et[i] = make_float2(a.lcetab[2 * ((size_t)m * kLcE + i)], a.lcetab[2 * ((size_t)m * kLcE + i) + 1]);
             __syncthreads();
         }
+        if (t + 1 < t1) load_tile(t + 1, next_r);
         const int64_t p0 = a.tile_p0[t];
         const int cnt = a.tile_cnt[t];
-        T px[ILP], py[ILP], pz[ILP], qx[ILP], qy[ILP], qz[ILP], pw[ILP];
-        uint16_t tg[ILP][kMaxBin + 1];
-        #pragma unroll
-        for (int k = 0; k < ILP; ++k) {
-            const int i = k * nt + tid;
-            if (i < cnt) {
-                const int64_t p = p0 + i;
-                const uint32_t rb = opaque(uint32_t(a.stride * sizeof(T))), tr = uint32_t(a.stride * 2);
-                const uint32_t o = uint32_t(p) * uint32_t(sizeof(T)), ot = 7 * rb + uint32_t(p) * 2u;
-                px[k] = ld_at<T>(a.in, o);
-                py[k] = ld_at<T>(a.in, o + rb);
-                pz[k] = ld_at<T>(a.in, o + 2 * rb);
-                qx[k] = ld_at<T>(a.in, o + 3 * rb);
-                qy[k] = ld_at<T>(a.in, o + 4 * rb);
-                qz[k] = ld_at<T>(a.in, o + 5 * rb);
-                pw[k] = ld_at<T>(a.in, o + 6 * rb);
-                #pragma unroll
-                for (int b = 0; b < kMaxBin; ++b)
-                    tg[k][b] = (stepping && b < NB && b < a.lay.nbin) ? ld_at<uint16_t>(a.in, ot + b * tr) : kNoBin;
-                tg[k][kMaxBin] = (stepping && want_cm) ? ld_at<uint16_t>(a.in, ot + a.cellrow * tr) : 0;
-            }
-        }
         unsigned open[ILP];
         #pragma unroll
         for (int k = 0; k < ILP; ++k) {
             const int i = k * nt + tid;
-            open[k] = i < cnt ? particle_step<POT, NB>(a, B, acc, p0 + i, px[k], py[k], pz[k], qx[k], qy[k], qz[k],
-                                                        pw[k], tg[k])
+            open[k] = i < cnt ? particle_step<POT, NB, SIG>(a, B, acc, p0 + i, cur_r.x[k], cur_r.y[k], cur_r.z[k],
+                                                        cur_r.vx[k], cur_r.vy[k], cur_r.vz[k], cur_r.w[k], cur_r.tg[k])
                               : 0u;
         }
         if constexpr (F32) {
@@ -359,6 +377,7 @@ __global__ void __launch_bounds__(sizeof(T) == 8 ? 256 : 1024) step_kernel(StepA
                                    (gF32*)a.out, (gU16*)((char*)a.out + 7 * a.stride * sizeof(T)), (lF64*)hist,
                                    (lF64*)csum, (lU32*)ccnt, B.pot.lcE0, B.pot.lcEinv);
         }
+        cur_r = next_r;
     }
     if (acc.bad) {
         __hip_atomic_fetch_or(a.flag, (int)acc.bad, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -442,42 +461,54 @@ hipError_t launch_gather(const GatherArgs<T>& a, int pot_kind, int blocks, hipSt
 template hipError_t launch_gather<float>(const GatherArgs<float>&, int, int, hipStream_t);
 template hipError_t launch_gather<double>(const GatherArgs<double>&, int, int, hipStream_t);
 
-template <typename T, typename PT, int POT, int NB>
-static hipError_t launch_step_nb(const StepArgs<T, PT>& a, int ilp, int blocks, int threads, size_t lds,
-                                 hipStream_t s) {
-    if (ilp == 1) hipLaunchKernelGGL((step_kernel<T, PT, POT, NB, 1>), dim3(blocks), dim3(threads), lds, s, a);
-    else hipLaunchKernelGGL((step_kernel<T, PT, POT, NB, 2>), dim3(blocks), dim3(threads), lds, s, a);
+template <typename T, typename PT, int POT, int NB, uint64_t SIG>
+static hipError_t launch_k(const StepArgs<T, PT>& a, int ilp, int blocks, int threads, size_t lds, hipStream_t s) {
+    if (ilp == 1) hipLaunchKernelGGL((step_kernel<T, PT, POT, NB, SIG, 1>), dim3(blocks), dim3(threads), lds, s, a);
+    else hipLaunchKernelGGL((step_kernel<T, PT, POT, NB, SIG, 2>), dim3(blocks), dim3(threads), lds, s, a);
     return hipGetLastError();
 }
 
-// Binnings are compiled for at most NB = 2 or 4 (fewer live constants when the
-// layout has one or two).
+// FP32 layouts with a compiled signature get their own kernels; every other
+// layout runs the kernels compiled for at most NB = 2 or 4 binnings.
 template <typename T, typename PT, int POT>
-static hipError_t launch_step_pot(const StepArgs<T, PT>& a, int nbin, int ilp, int blocks, int threads, size_t lds,
-                                  hipStream_t s) {
-    if (nbin <= 2) return launch_step_nb<T, PT, POT, 2>(a, ilp, blocks, threads, lds, s);
-    return launch_step_nb<T, PT, POT, 4>(a, ilp, blocks, threads, lds, s);
+static hipError_t launch_step_pot(const StepArgs<T, PT>& a, uint64_t sig, int nbin, int ilp, int blocks, int threads,
+                                  size_t lds, hipStream_t s) {
+    if constexpr (sizeof(T) == 4 && POT == 1)
+        if (sig == kSigPixKin) return launch_k<T, PT, POT, 2, kSigPixKin>(a, ilp, blocks, threads, lds, s);
+    if constexpr (sizeof(T) == 4 && POT != 1)
+        if (sig == kSigShellAnn) return launch_k<T, PT, POT, 2, kSigShellAnn>(a, ilp, blocks, threads, lds, s);
+    if (nbin <= 2) return launch_k<T, PT, POT, 2, 0>(a, ilp, blocks, threads, lds, s);
+    return launch_k<T, PT, POT, 4, 0>(a, ilp, blocks, threads, lds, s);
 }
 
 template <typename T, typename PT>
-hipError_t launch_step(const StepArgs<T, PT>& a, int pot_kind, int nbin, int ilp, int blocks, int threads, size_t lds,
-                       hipStream_t s) {
+hipError_t launch_step(const StepArgs<T, PT>& a, int pot_kind, uint64_t sig, int nbin, int ilp, int blocks,
+                       int threads, size_t lds, hipStream_t s) {
     switch (pot_kind) {
-        case 0: return launch_step_pot<T, PT, 0>(a, nbin, ilp, blocks, threads, lds, s);
-        case 1: return launch_step_pot<T, PT, 1>(a, nbin, ilp, blocks, threads, lds, s);
-        default: return launch_step_pot<T, PT, 2>(a, nbin, ilp, blocks, threads, lds, s);
+        case 0: return launch_step_pot<T, PT, 0>(a, sig, nbin, ilp, blocks, threads, lds, s);
+        case 1: return launch_step_pot<T, PT, 1>(a, sig, nbin, ilp, blocks, threads, lds, s);
+        default: return launch_step_pot<T, PT, 2>(a, sig, nbin, ilp, blocks, threads, lds, s);
     }
 }
 
-template <typename T, typename PT, int POT>
-static hipError_t set_lds_pot(size_t lds) {
-    const void* fns[] = {(const void*)step_kernel<T, PT, POT, 2, 1>, (const void*)step_kernel<T, PT, POT, 2, 2>,
-                         (const void*)step_kernel<T, PT, POT, 4, 1>, (const void*)step_kernel<T, PT, POT, 4, 2>};
-    for (const void* f : fns) {
+template <typename T, typename PT, int POT, int NB, uint64_t SIG>
+static hipError_t set_lds_k(size_t lds) {
+    for (const void* f : {(const void*)step_kernel<T, PT, POT, NB, SIG, 1>, (const void*)step_kernel<T, PT, POT, NB, SIG, 2>}) {
         hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
+}
+
+template <typename T, typename PT, int POT>
+static hipError_t set_lds_pot(size_t lds) {
+    hipError_t e = set_lds_k<T, PT, POT, 2, 0>(lds);
+    if (e == hipSuccess) e = set_lds_k<T, PT, POT, 4, 0>(lds);
+    if constexpr (sizeof(T) == 4 && POT == 1)
+        if (e == hipSuccess) e = set_lds_k<T, PT, POT, 2, kSigPixKin>(lds);
+    if constexpr (sizeof(T) == 4 && POT != 1)
+        if (e == hipSuccess) e = set_lds_k<T, PT, POT, 2, kSigShellAnn>(lds);
+    return e;
 }
 
 template <typename T, typename PT>
@@ -499,8 +530,10 @@ hipError_t launch_erange(const ErangeArgs<T>& a, int pot_kind, int blocks, hipSt
     return hipGetLastError();
 }
 
-template hipError_t launch_step<float, float>(const StepArgs<float, float>&, int, int, int, int, int, size_t, hipStream_t);
-template hipError_t launch_step<double, double>(const StepArgs<double, double>&, int, int, int, int, int, size_t, hipStream_t);
+template hipError_t launch_step<float, float>(const StepArgs<float, float>&, int, uint64_t, int, int, int, int, size_t,
+                                             hipStream_t);
+template hipError_t launch_step<double, double>(const StepArgs<double, double>&, int, uint64_t, int, int, int, int,
+                                               size_t, hipStream_t);
 template hipError_t set_step_lds_limit<float, float>(int, size_t);
 template hipError_t set_step_lds_limit<double, double>(int, size_t);
 template hipError_t launch_erange<float>(const ErangeArgs<float>&, int, int, hipStream_t);
