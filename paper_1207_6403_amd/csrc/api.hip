@@ -171,7 +171,7 @@ static void free_plan(m2m_ctx* c) {
     Plan& p = c->plan;
     for (void* q : {(void*)p.tile_model, (void*)p.tile_p0, (void*)p.tile_cnt, (void*)p.block_tile0,
                     (void*)p.block_slot0, (void*)p.model_slot, (void*)p.part, (void*)p.seg_stats,
-                    (void*)p.erange_out, (void*)p.chunk_desc})
+                    (void*)p.erange_out, (void*)p.chunk_desc, (void*)p.slot_base, (void*)p.slot_stride})
         dfree(c, q);
     p = Plan();
     for (int k = 0; k < 2; ++k)
@@ -226,21 +226,43 @@ static m2m_status make_plan(m2m_ctx* c, int threads, int ilp, int bpc) {
         (s = upload(c, &p.block_tile0, bt0)) || (s = upload(c, &p.block_slot0, bs0)) ||
         (s = upload(c, &p.model_slot, mslot)))
         return s;
-    // finalise chunk descriptors: model, first column, columns, first slot, slots
+    // partial slots, chunk-major: for model m, chunk k (kFinCols columns) of all
+    // the model's slots is one contiguous block, so each finalise block reads
+    // one contiguous range
+    const int cpm = c->nchunk / c->M;   // chunks per model
+    std::vector<int64_t> mbase(c->M + 1, 0), sbase(nslot);
+    std::vector<int32_t> sstride(nslot);
+    for (int m = 0; m < c->M; ++m) {
+        const int ns = mslot[m + 1] - mslot[m];
+        mbase[m + 1] = mbase[m] + (int64_t)cpm * ns * kFinCols;
+        for (int q = mslot[m]; q < mslot[m + 1]; ++q) {
+            sbase[q] = mbase[m] + (int64_t)(q - mslot[m]) * kFinCols;
+            sstride[q] = ns * kFinCols;
+        }
+    }
+    // finalise chunk descriptors: model, first column, columns, first slot,
+    // slots, start of the chunk's block of partials (low, high 32 bits)
     std::vector<int32_t> desc(8 * (size_t)c->nchunk, 0);
     for (int k = 0; k < c->nchunk; ++k) {
         const int m = c->chunk_model_host[k];
+        const int ns = mslot[m + 1] - mslot[m];
+        const int64_t base = mbase[m] + (int64_t)(c->chunk_col0_host[k] / kFinCols) * ns * kFinCols;
         desc[8 * k] = m;
         desc[8 * k + 1] = c->chunk_col0_host[k];
         desc[8 * k + 2] = c->chunk_ncol_host[k];
         desc[8 * k + 3] = mslot[m];
-        desc[8 * k + 4] = mslot[m + 1] - mslot[m];
+        desc[8 * k + 4] = ns;
+        desc[8 * k + 5] = (int32_t)(base & 0xffffffff);
+        desc[8 * k + 6] = (int32_t)(base >> 32);
     }
-    if ((s = upload(c, &p.chunk_desc, desc))) return s;
-    if ((s = dalloc(c, (char**)&p.part, (size_t)nslot * c->pcols * tsize(c))) ||
-        (s = dalloc(c, &p.seg_stats, (size_t)nslot * 4)) || (s = dalloc(c, &p.erange_out, (size_t)nslot * 2)))
+    const size_t npart = (size_t)mbase[c->M];
+    if ((s = upload(c, &p.chunk_desc, desc)) || (s = upload(c, &p.slot_base, sbase)) ||
+        (s = upload(c, &p.slot_stride, sstride)))
         return s;
-    HIPCHK(c, hipMemset(p.part, 0, (size_t)nslot * c->pcols * tsize(c)));
+    if ((s = dalloc(c, (char**)&p.part, npart * tsize(c))) || (s = dalloc(c, &p.seg_stats, (size_t)nslot * 4)) ||
+        (s = dalloc(c, &p.erange_out, (size_t)nslot * 2)))
+        return s;
+    HIPCHK(c, hipMemset(p.part, 0, npart * tsize(c)));
     // LDS of the fused kernel: histograms, cell sums/counts, update table,
     // cell means, edges, reduction scratch, Lc table
     const size_t ts = tsize(c);
@@ -310,6 +332,8 @@ static void fill_step_args(m2m_ctx* c, StepArgs<T, T>& a, int parity, int mode, 
     a.cvec = (const T*)c->cvec;
     a.cellmean = (const T*)c->cellmean;
     a.part = (T*)p.part;
+    a.slot_base = p.slot_base;
+    a.slot_stride = p.slot_stride;
     a.seg_stats = p.seg_stats;
     a.edges = (const T*)c->edges;
     a.nedge = c->nedge;
@@ -701,7 +725,7 @@ static m2m_status create_T(m2m_ctx* c, const m2m_target* tg, const void* xv, con
         (s = dalloc(c, (T**)&c->cvec, MJ)) || (s = dalloc(c, (T**)&c->cellmean, (size_t)c->M * std::max(1, c->NC))) ||
         (s = dalloc(c, &c->cellmean64, (size_t)c->M * std::max(1, c->NC))) ||
         (s = dalloc(c, &c->ring, (size_t)c->M * kRing)) || (s = dalloc(c, &c->flag, 1)) ||
-        (s = dalloc(c, &c->bad_step, 1)) || (s = dalloc(c, &c->d_step, 1)))
+        (s = dalloc(c, &c->bad_step, 1)) || (s = dalloc(c, &c->d_step, 2)))
         return s;
     // finalise column chunks (independent of the launch shape): kFinCols columns
     // of one model each; chi^2 shares double-buffered by step parity
@@ -727,7 +751,7 @@ static m2m_status create_T(m2m_ctx* c, const m2m_target* tg, const void* xv, con
     }
     HIPCHK(c, hipMemset(c->flag, 0, sizeof(int)));
     HIPCHK(c, hipMemset(c->bad_step, 0, sizeof(long long)));
-    HIPCHK(c, hipMemset(c->d_step, 0, sizeof(long long)));
+    HIPCHK(c, hipMemset(c->d_step, 0, 2 * sizeof(long long)));
     HIPCHK(c, hipMemset(c->ring, 0, sizeof(StatRow) * (size_t)c->M * kRing));
     HIPCHK(c, hipMemset(c->cvec, 0, sizeof(T) * MJ));
     HIPCHK(c, hipMemset(c->cellmean, 0, sizeof(T) * (size_t)c->M * std::max(1, c->NC)));
@@ -1112,7 +1136,7 @@ static m2m_status snapshot(m2m_ctx* c, Snapshot& s, bool restore) {
     std::vector<Item> items = {{c->state[c->step & 1], state_bytes(c)},
                                {c->ys, MJ * 8}, {c->y, MJ * 8}, {c->delta, MJ * 8}, {c->cvec, MJ * ts},
                                {c->cellmean, MC * ts}, {c->cellmean64, MC * 8}, {c->chunk_chi, 4 * (size_t)c->nchunk * 8},
-                               {c->ring, sizeof(StatRow) * (size_t)c->M * kRing}, {c->d_step, 8}};
+                               {c->ring, sizeof(StatRow) * (size_t)c->M * kRing}, {c->d_step, 16}};
     if (c->what) items.push_back({c->what, (size_t)c->stride * ts});
     if (!restore) {
         for (auto& it : items) {

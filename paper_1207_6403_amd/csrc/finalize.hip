@@ -8,9 +8,10 @@
 //   chunk's share of chi^2 = sum Dt_j^2;
 // and per prior cell (section 2.1) the mean weight sum/count.
 // Blocks never wait for each other: column blocks write per-chunk chi^2 shares
-// (double-buffered by step parity), and one extra block assembles the
-// statistics row of step n from the previous finalise's chi^2 shares and step
-// kernel n's per-slot sums, then advances the device step counter.
+// (double-buffered by step parity), and one extra block per model assembles
+// the model's statistics row of step n from the previous finalise's chi^2
+// shares and step kernel n's per-slot sums; the last of them advances the
+// device step counter.
 #include "runtime.h"
 
 namespace m2m {
@@ -37,7 +38,8 @@ __global__ void __launch_bounds__(256) finalize_kernel(FinArgs<T, PT> a) {
         // ------------------------------------------------ column block
         const int chunk = blockIdx.x;
         const int* d = a.chunk_desc + 8 * chunk;
-        const int m = d[0], col0 = d[1], ncol = d[2], s0 = d[3], ns = d[4];
+        const int m = d[0], col0 = d[1], ncol = d[2], ns = d[4];
+        const int64_t base = (int64_t)(uint32_t)d[5] | ((int64_t)d[6] << 32);
         const int g = tid / kFinCols, c = tid % kFinCols;
         const int col = col0 + c;
         const bool live = c < ncol && (col < a.J || (col >= a.jpad && a.accum_cells));
@@ -45,16 +47,22 @@ __global__ void __launch_bounds__(256) finalize_kernel(FinArgs<T, PT> a) {
         const bool obs = g == 0 && live && col < a.J;
         const size_t j = (size_t)m * a.J + col;
         const double Yj = obs ? a.Y[j] : 0.0, sj = obs ? a.sigma[j] : 1.0, ysj = obs && !a.first ? a.ys[j] : 0.0;
-        const int per = (ns + kFinGroups - 1) / kFinGroups;
-        const int sa = s0 + g * per, sb = min(s0 + ns, sa + per);
         double acc = 0;
         if (live) {
-            const PT* src = a.part + col;
-            for (int r = sa; r < sb; r += kSlotsPerSplit) {
+            // slot r of the chunk at src[r * kFinCols]; group g takes r = g + kFinGroups k,
+            // so that a wave reads consecutive slot rows
+            const PT* src = a.part + base + c;
+            for (int r0 = g; r0 < ns; r0 += kFinGroups * kSlotsPerSplit) {
                 // a whole round of slots in flight before the first add
                 PT v[kSlotsPerSplit];
+                // unconditional loads (rows past the end re-read the last row and
+                // are dropped), so that no load waits for the one before it
                 #pragma unroll
-                for (int k = 0; k < kSlotsPerSplit; ++k) v[k] = r + k < sb ? src[(size_t)(r + k) * a.pcols] : PT(0);
+                for (int k = 0; k < kSlotsPerSplit; ++k) {
+                    const int r = r0 + kFinGroups * k;
+                    const PT t = src[(size_t)min(r, ns - 1) * kFinCols];
+                    v[k] = r < ns ? t : PT(0);
+                }
                 #pragma unroll
                 for (int k = 0; k < kSlotsPerSplit; ++k) acc += double(v[k]);
             }
@@ -103,57 +111,65 @@ __global__ void __launch_bounds__(256) finalize_kernel(FinArgs<T, PT> a) {
         return;
     }
 
-    // ---------------------------------------------------- statistics block
+    // ------------------------------------------- statistics block of model m
+    // (one per model; every load of the row is issued before the first wait)
     if (a.first || failed) return;
-    const long long n = *a.d_step;
-    for (int m = 0; m < a.n_models; ++m) {
-        double x2 = 0, x2i = 0, S = 0, W = 0, W2 = 0, mn = INFINITY;
-        for (int k = a.model_chunk[m] + tid; k < a.model_chunk[m + 1]; k += 256) {
-            x2 += chi_prev[2 * k];
-            x2i += chi_prev[2 * k + 1];
-        }
-        for (int s = a.model_slot[m] + tid; s < a.model_slot[m + 1]; s += 256) {
-            S += a.seg_stats[4 * s];
-            W += a.seg_stats[4 * s + 1];
-            W2 += a.seg_stats[4 * s + 2];
-            mn = fmin(mn, a.seg_stats[4 * s + 3]);
-        }
-        x2 = fwave_sum(x2); x2i = fwave_sum(x2i); S = fwave_sum(S); W = fwave_sum(W); W2 = fwave_sum(W2);
-        #pragma unroll
-        for (int o = 32; o > 0; o >>= 1) mn = fmin(mn, __shfl_xor(mn, o, 64));
-        __shared__ double sred[6][4];
-        if ((tid & 63) == 0) {
-            const int w = tid >> 6;
-            sred[0][w] = x2; sred[1][w] = x2i; sred[2][w] = S; sred[3][w] = W; sred[4][w] = W2; sred[5][w] = mn;
-        }
-        __syncthreads();
-        if (tid == 0) {
-            const double X2 = (sred[0][0] + sred[0][1]) + (sred[0][2] + sred[0][3]);
-            const double X2i = (sred[1][0] + sred[1][1]) + (sred[1][2] + sred[1][3]);
-            const double Ss = (sred[2][0] + sred[2][1]) + (sred[2][2] + sred[2][3]);
-            const double Ws = (sred[3][0] + sred[3][1]) + (sred[3][2] + sred[3][3]);
-            const double W2s = (sred[4][0] + sred[4][1]) + (sred[4][2] + sred[4][3]);
-            const double mns = fmin(fmin(sred[5][0], sred[5][1]), fmin(sred[5][2], sred[5][3]));
-            StatRow* r = a.ring + (size_t)m * kRing + (n % kRing);
-            r->chi2 = X2;
-            r->chi2_inst = X2i;
-            r->S = Ss;
-            r->F = -0.5 * X2 + a.mu * Ss;
-            r->sum_w = Ws;
-            r->min_w = mns;
-            r->sum_w2 = W2s;
-            r->n_eff = Ws * Ws / W2s;
-            r->step = n;
-            r->model = m;
-        }
-        __syncthreads();
+    const int m = blockIdx.x - a.nchunk;
+    const long long n = a.d_step[0];
+    const int c0 = a.model_chunk[m], c1 = a.model_chunk[m + 1];
+    const int q0 = a.model_slot[m], q1 = a.model_slot[m + 1];
+    double x2 = 0, x2i = 0, S = 0, W = 0, W2 = 0, mn = INFINITY;
+    for (int k = c0 + tid; k < c1; k += 256) {
+        x2 += chi_prev[2 * k];
+        x2i += chi_prev[2 * k + 1];
     }
-    if (tid == 0) *a.d_step = n + 1;
+    for (int q = q0 + tid; q < q1; q += 256) {
+        S += a.seg_stats[4 * q];
+        W += a.seg_stats[4 * q + 1];
+        W2 += a.seg_stats[4 * q + 2];
+        mn = fmin(mn, a.seg_stats[4 * q + 3]);
+    }
+    x2 = fwave_sum(x2); x2i = fwave_sum(x2i); S = fwave_sum(S); W = fwave_sum(W); W2 = fwave_sum(W2);
+    #pragma unroll
+    for (int o = 32; o > 0; o >>= 1) mn = fmin(mn, __shfl_xor(mn, o, 64));
+    __shared__ double sred[6][4];
+    if ((tid & 63) == 0) {
+        const int w = tid >> 6;
+        sred[0][w] = x2; sred[1][w] = x2i; sred[2][w] = S; sred[3][w] = W; sred[4][w] = W2; sred[5][w] = mn;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        const double X2 = (sred[0][0] + sred[0][1]) + (sred[0][2] + sred[0][3]);
+        const double X2i = (sred[1][0] + sred[1][1]) + (sred[1][2] + sred[1][3]);
+        const double Ss = (sred[2][0] + sred[2][1]) + (sred[2][2] + sred[2][3]);
+        const double Ws = (sred[3][0] + sred[3][1]) + (sred[3][2] + sred[3][3]);
+        const double W2s = (sred[4][0] + sred[4][1]) + (sred[4][2] + sred[4][3]);
+        const double mns = fmin(fmin(sred[5][0], sred[5][1]), fmin(sred[5][2], sred[5][3]));
+        StatRow* r = a.ring + (size_t)m * kRing + (n % kRing);
+        r->chi2 = X2;
+        r->chi2_inst = X2i;
+        r->S = Ss;
+        r->F = -0.5 * X2 + a.mu * Ss;
+        r->sum_w = Ws;
+        r->min_w = mns;
+        r->sum_w2 = W2s;
+        r->n_eff = Ws * Ws / W2s;
+        r->step = n;
+        r->model = m;
+        // the last statistics block to finish (every block has read the step
+        // counter before its ticket) advances the counter and resets the tickets
+        const unsigned long long ticket = __hip_atomic_fetch_add(
+            reinterpret_cast<unsigned long long*>(a.d_step + 1), 1ull, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        if (ticket == (unsigned long long)(a.n_models - 1)) {
+            a.d_step[1] = 0;
+            a.d_step[0] = n + 1;
+        }
+    }
 }
 
 template <typename T, typename PT>
 hipError_t launch_finalize(const FinArgs<T, PT>& a, hipStream_t s) {
-    hipLaunchKernelGGL((finalize_kernel<T, PT>), dim3(a.nchunk + 1), dim3(256), 0, s, a);
+    hipLaunchKernelGGL((finalize_kernel<T, PT>), dim3(a.nchunk + a.n_models), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

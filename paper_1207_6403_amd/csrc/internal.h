@@ -20,7 +20,9 @@ struct Plan {
     int32_t* block_tile0 = nullptr;
     int32_t* block_slot0 = nullptr;
     int32_t* model_slot = nullptr;
-    int32_t* chunk_desc = nullptr;   // 8 per finalise chunk: model, col0, ncol, slot0, nslot
+    int32_t* chunk_desc = nullptr;   // 8 per finalise chunk: model, col0, ncol, slot0, nslot, base
+    int64_t* slot_base = nullptr;    // per slot: index of its first column in `part`
+    int32_t* slot_stride = nullptr;  // per slot: distance between its chunks
     void* part = nullptr;
     double* seg_stats = nullptr;
     double* erange_out = nullptr;

@@ -40,7 +40,9 @@ struct StepArgs {
     const T* flatw;               // per model
     const T* cvec;                // M * J: Dt_j / sigma_j
     const T* cellmean;            // M * NC
-    PT* part;                     // nslot * pcols
+    PT* part;                     // partial slots, chunk-major per model
+    const int64_t* slot_base;     // column j of slot q: part[slot_base[q] + (j / kFinCols) *
+    const int32_t* slot_stride;   //   slot_stride[q] + j % kFinCols]
     double* seg_stats;            // nslot * 4
     const T* edges;
     int32_t nedge;
@@ -72,7 +74,7 @@ template <typename T, typename PT>
 struct FinArgs {
     const PT* part;
     int32_t pcols, jpad, J, ncell, n_models;
-    const int32_t* chunk_desc;    // 8 per chunk: model, col0, ncol, slot0, nslot
+    const int32_t* chunk_desc;    // 8 per chunk: model, col0, ncol, slot0, nslot, base (2 x 32 bits)
     const int32_t* model_slot;    // M + 1
     const int32_t* model_chunk;   // M + 1
     int32_t nchunk;
@@ -91,7 +93,7 @@ struct FinArgs {
     double g, mu;
     int32_t first, accum_cells;
     const int* flag;
-    long long* d_step;
+    long long* d_step;            // [0] step counter, [1] statistics-block tickets
 };
 
 template <typename T>

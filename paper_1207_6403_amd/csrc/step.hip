@@ -14,6 +14,8 @@
 // When a block moves to another model (batched form) or finishes, it writes
 // its LDS histograms to its own partial slot (no atomics, deterministic
 // placement); finalize.hip sums the slots.
+#include <type_traits>
+
 #include "runtime.h"
 
 namespace m2m {
@@ -68,6 +70,25 @@ struct Acc {
     unsigned bad = 0;
 };
 
+// Element i of a table that no kernel writes while it runs, read through the
+// constant address space: uniform indices then become scalar loads, which do
+// not wait behind the vector stores of the particle loop.
+template <typename X>
+__device__ __forceinline__ X ro(const X* p, int64_t i) {
+    if constexpr (std::is_arithmetic<X>::value) {
+        return ((const __attribute__((address_space(4))) X*)p)[i];
+    } else {
+        // a struct, word by word
+        static_assert(sizeof(X) % 4 == 0, "whole words");
+        X v;
+        const __attribute__((address_space(4))) uint32_t* s = (const __attribute__((address_space(4))) uint32_t*)(p + i);
+        uint32_t* d = reinterpret_cast<uint32_t*>(&v);
+        #pragma unroll
+        for (unsigned k = 0; k < sizeof(X) / 4; ++k) d[k] = s[k];
+        return v;
+    }
+}
+
 // Value at byte offset off from base.  Every row of a state buffer (values,
 // then tags) is addressed from the buffer's base with a 32-bit byte offset
 // (state buffers are smaller than 4 GiB), so one scalar base serves all rows.
@@ -102,7 +123,7 @@ __device__ __forceinline__ void scatter_bin(const LayoutView<SIG, T>& V, double*
 // re-taken in FP64 by fixup(); FP64 kernels decide in FP64 and return 0.
 template <int POT, int NB, uint64_t SIG, typename T, typename PT>
 __device__ __forceinline__ unsigned particle_step(const StepArgs<T, PT>& a, const Blk<T>& B, Acc& acc, int64_t p,
-                                                  T x, T y, T z, T vx, T vy, T vz, T w,
+                                                  T x, T y, T z, T vx, T vy, T vz, T w, T what_p,
                                                   const uint16_t (&tg)[kMaxBin + 1]) {
     const Layout<T>& L = a.lay;
     const LayoutView<SIG, T> V{L};
@@ -131,7 +152,7 @@ __device__ __forceinline__ unsigned particle_step(const StepArgs<T, PT>& a, cons
             }
         }
         const uint32_t wm = (fl >> kWhatShift) & 3u;
-        const T wh = wm == 0 ? B.wflat : (wm == 3 ? a.what[p] : B.cm[tg[kMaxBin]]);
+        const T wh = wm == 0 ? B.wflat : (wm == 3 ? what_p : B.cm[tg[kMaxBin]]);
         const T lr = dlog(w / wh);
         const T G = -chi - a.mu * (lr + T(1));
         const T edt = a.eps * a.dt;
@@ -279,13 +300,13 @@ __global__ void __launch_bounds__(sizeof(T) == 8 ? 256 : 1024) step_kernel(StepA
 
     for (int i = tid; i < a.nedge; i += nt) { ed[i] = a.edges[i]; ed64[i] = a.ex->edges[i]; }
 
-    const int t0 = a.block_tile0[blockIdx.x], t1 = a.block_tile0[blockIdx.x + 1];
+    const int t0 = ro(a.block_tile0, blockIdx.x), t1 = ro(a.block_tile0, blockIdx.x + 1);
     const uint32_t fl = a.flags;
     const uint32_t wm = (fl >> kWhatShift) & 3u;
     const bool want_cm = wm == 1 || wm == 2;
     const bool accum = fl & kAccum;
     const bool stepping = !(fl & kObserve);
-    int slot = a.block_slot0[blockIdx.x] - 1;
+    int slot = ro(a.block_slot0, blockIdx.x) - 1;
     int cur = -1;
     Blk<T> B;
     B.hist = hist; B.csum = csum; B.ccnt = ccnt; B.cl = cl; B.cm = cm; B.ed = ed; B.ed64 = ed64; B.et = et;
@@ -296,12 +317,12 @@ __global__ void __launch_bounds__(sizeof(T) == 8 ? 256 : 1024) step_kernel(StepA
     // the particles of a tile (values and the tags of the current state); the
     // next tile's are loaded while this one is processed
     struct Regs {
-        T x[ILP], y[ILP], z[ILP], vx[ILP], vy[ILP], vz[ILP], w[ILP];
+        T x[ILP], y[ILP], z[ILP], vx[ILP], vy[ILP], vz[ILP], w[ILP], wh[ILP];
         uint16_t tg[ILP][kMaxBin + 1];
     };
     auto load_tile = [&](int t, Regs& R) {
-        const int64_t p0 = a.tile_p0[t];
-        const int cnt = a.tile_cnt[t];
+        const int64_t p0 = ro(a.tile_p0, t);
+        const int cnt = ro(a.tile_cnt, t);
         #pragma unroll
         for (int k = 0; k < ILP; ++k) {
             const int i = k * nt + tid;
@@ -316,6 +337,7 @@ __global__ void __launch_bounds__(sizeof(T) == 8 ? 256 : 1024) step_kernel(StepA
                 R.vy[k] = ld_at<T>(a.in, o + 4 * rb);
                 R.vz[k] = ld_at<T>(a.in, o + 5 * rb);
                 R.w[k] = ld_at<T>(a.in, o + 6 * rb);
+                R.wh[k] = (stepping && wm == 3) ? a.what[p] : T(1);
                 #pragma unroll
                 for (int b = 0; b < kMaxBin; ++b)
                     R.tg[k][b] = (stepping && b < NB && b < LayoutView<SIG, T>{a.lay}.nbin()) ? ld_at<uint16_t>(a.in, ot + b * tr)
@@ -324,19 +346,36 @@ __global__ void __launch_bounds__(sizeof(T) == 8 ? 256 : 1024) step_kernel(StepA
             }
         }
     };
-    Regs cur_r, next_r;
-    if (t0 < t1) load_tile(t0, cur_r);
+    Regs next_r;
+    if (t0 < t1) load_tile(t0, next_r);
+    unsigned open[ILP];   // decisions left open in the previous tile
+    int64_t p_open = 0;   // its first particle
+    #pragma unroll
+    for (int k = 0; k < ILP; ++k) open[k] = 0u;
 
     for (int t = t0; t <= t1; ++t) {
-        const int m = t < t1 ? a.tile_model[t] : -2;
+        if constexpr (F32) {
+            // the previous tile's open decisions (out of line, and before this
+            // tile's loads are issued, so that waiting for those loads never
+            // waits for the unknown memory operations of a call)
+            #pragma unroll
+            for (int k = 0; k < ILP; ++k)
+                if (open[k])
+                    fixup<POT, NB>((cExact*)a.ex, B.m, open[k], p_open + k * nt + tid, a.stride, a.cellrow,
+                                   (gF32*)a.out, (gU16*)((char*)a.out + 7 * a.stride * sizeof(T)), (lF64*)hist,
+                                   (lF64*)csum, (lU32*)ccnt, B.pot.lcE0, B.pot.lcEinv);
+        }
+        const int m = t < t1 ? ro(a.tile_model, t) : -2;
         if (m != cur) {
             if (cur >= 0) {
                 // flush the finished model's histograms to its partial slot
                 __syncthreads();
-                PT* dst = a.part + (size_t)slot * a.pcols;
-                for (int j = tid; j < J; j += nt) dst[j] = PT(hist[j]);
+                PT* dst = a.part + ro(a.slot_base, slot);
+                const int64_t cs = ro(a.slot_stride, slot);
+                auto at = [&](int j) -> PT& { return dst[(j / kFinCols) * cs + j % kFinCols]; };
+                for (int j = tid; j < J; j += nt) at(j) = PT(hist[j]);
                 if (accum)
-                    for (int c = tid; c < NC; c += nt) { dst[JP + 2 * c] = PT(csum[c]); dst[JP + 2 * c + 1] = PT(ccnt[c]); }
+                    for (int c = tid; c < NC; c += nt) { at(JP + 2 * c) = PT(csum[c]); at(JP + 2 * c + 1) = PT(ccnt[c]); }
                 block_stats(acc.S, acc.W, acc.W2, acc.mn, red, a.seg_stats + 4 * (size_t)slot);
                 acc.S = acc.W = acc.W2 = 0;
                 acc.mn = INFINITY;
@@ -345,10 +384,10 @@ __global__ void __launch_bounds__(sizeof(T) == 8 ? 256 : 1024) step_kernel(StepA
             cur = m;
             ++slot;
             B.m = m;
-            B.pot = a.pots[m];
-            B.Emin = a.erange[2 * m];
-            B.sE = T(a.cells.n0) / (a.erange[2 * m + 1] - a.erange[2 * m]);
-            B.wflat = a.flatw[m];
+            B.pot = ro(a.pots, m);
+            B.Emin = ro(a.erange, 2 * m);
+            B.sE = T(a.cells.n0) / (ro(a.erange, 2 * m + 1) - ro(a.erange, 2 * m));
+            B.wflat = ro(a.flatw, m);
             __syncthreads();
             for (int j = tid; j < J; j += nt) { hist[j] = 0.0; cl[j] = a.cvec[(size_t)m * J + j]; }
             if (accum) for (int c = tid; c < NC; c += nt) { csum[c] = 0.0; ccnt[c] = 0u; }
@@ -358,26 +397,21 @@ __global__ void __launch_bounds__(sizeof(T) == 8 ? 256 : 1024) step_kernel(StepA
                 et[i] = make_float2(a.lcetab[2 * ((size_t)m * kLcE + i)], a.lcetab[2 * ((size_t)m * kLcE + i) + 1]);
             __syncthreads();
         }
+        // this tile's particles (their loads were issued one tile ago), then the
+        // next tile's loads
+        const Regs cur_r = next_r;
         if (t + 1 < t1) load_tile(t + 1, next_r);
-        const int64_t p0 = a.tile_p0[t];
-        const int cnt = a.tile_cnt[t];
-        unsigned open[ILP];
+        const int64_t p0 = ro(a.tile_p0, t);
+        const int cnt = ro(a.tile_cnt, t);
         #pragma unroll
         for (int k = 0; k < ILP; ++k) {
             const int i = k * nt + tid;
             open[k] = i < cnt ? particle_step<POT, NB, SIG>(a, B, acc, p0 + i, cur_r.x[k], cur_r.y[k], cur_r.z[k],
-                                                        cur_r.vx[k], cur_r.vy[k], cur_r.vz[k], cur_r.w[k], cur_r.tg[k])
+                                                        cur_r.vx[k], cur_r.vy[k], cur_r.vz[k], cur_r.w[k], cur_r.wh[k],
+                                                        cur_r.tg[k])
                               : 0u;
         }
-        if constexpr (F32) {
-            #pragma unroll
-            for (int k = 0; k < ILP; ++k)
-                if (open[k])
-                    fixup<POT, NB>((cExact*)a.ex, B.m, open[k], p0 + k * nt + tid, a.stride, a.cellrow,
-                                   (gF32*)a.out, (gU16*)((char*)a.out + 7 * a.stride * sizeof(T)), (lF64*)hist,
-                                   (lF64*)csum, (lU32*)ccnt, B.pot.lcE0, B.pot.lcEinv);
-        }
-        cur_r = next_r;
+        p_open = p0;
     }
     if (acc.bad) {
         __hip_atomic_fetch_or(a.flag, (int)acc.bad, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
