@@ -15,6 +15,7 @@ the context's stream, which gives the roofline figure.
     python bench.py --copy-calibration MIB   # plain device copy, for HBM counter scaling
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -27,6 +28,33 @@ sys.path.insert(0, ROOT)
 
 BYTES_PER_PARTICLE_STEP = 56      # read x y z vx vy vz w (7 x 4 B), write the same
 HBM_PEAK_GBS = 8000.0
+
+
+def kernel_sources_sha256():
+    """Digest of the sources the fused step kernel is compiled from."""
+    h = hashlib.sha256()
+    for f in ("step.hip", "device.h", "runtime.h"):
+        with open(os.path.join(ROOT, "paper_1207_6403_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(n):
+    """HBM bytes per launch of the fused kernel from the committed counter summary
+    (FETCH_SIZE + WRITE_SIZE, scaled by the same counters on a plain copy), or None
+    when the kernel sources have changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "step_kernel_logpot_N1M_traffic.txt")
+    if n != 1 << 20 or not os.path.exists(path):
+        return None
+    kv = {}
+    with open(path) as fh:
+        for line in fh:
+            if ":" in line and not line.startswith(" "):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+    if kv.get("kernel_sources_sha256") != kernel_sources_sha256():
+        return None
+    return float(kv["hbm_bytes_per_launch"])
 
 
 def log(msg):
@@ -53,7 +81,8 @@ def main():
     ap.add_argument("--n", type=int, default=1 << 20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=24)
-    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--autotune", action="store_true",
+                    help="time the candidate launch shapes first (the default shape is the tuned one)")
     ap.add_argument("--graph-steps", type=int, default=100)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device to device 10 times (the reference for the "
@@ -89,39 +118,40 @@ def main():
     w = torch.from_numpy(np.ascontiguousarray(inp["w"])).to(dev)
     ctx = m2m.m2m_create(cfg, xv, w, inp["Y"], inp["sigma"], device_ptrs=True)
     launch = m2m.m2m_get_launch(ctx)
-    if not args.no_autotune:
+    if args.autotune:
         launch = m2m.m2m_autotune(ctx, 20)
         log("autotuned launch: %s" % launch)
-    # timed region: every fused step kernel bracketed by HIP events on the
-    # context's stream (direct launches: event records inside a HIP graph cannot
-    # be timed)
-    m2m.m2m_set_launch(ctx, timing=1, graph_steps=0)
     log("warmup %d steps" % args.warmup)
     m2m.m2m_step(ctx, args.warmup)
     torch.cuda.synchronize()
-    log("timing %d steps" % args.steps)
+
+    # timed region 1 (the throughput): K steps as the library runs them, from
+    # HIP graphs of G steps each (both step parities' graphs built beforehand)
+    G = args.graph_steps
+    m2m.m2m_set_launch(ctx, timing=0, graph_steps=G)
+    if G:
+        m2m.m2m_step(ctx, 2 * G)
     torch.cuda.synchronize()
+    log("timing %d steps (graphs of %d)" % (args.steps, G))
     t0 = time.perf_counter()
     last = m2m.m2m_step(ctx, args.steps)[0]
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    k_ms, k_n = m2m.m2m_kernel_time(ctx)
-    # the same steps replayed from HIP graphs of G steps (no per-kernel events)
-    graph_value = None
-    G = args.graph_steps
-    if G:
-        steps_g = max(G, args.steps // G * G)
-        m2m.m2m_set_launch(ctx, timing=0, graph_steps=G)
-        m2m.m2m_step(ctx, 2 * G)   # builds both parities' graphs
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        m2m.m2m_step(ctx, steps_g)
-        torch.cuda.synchronize()
-        graph_value = cfg["N"] * steps_g / (time.perf_counter() - t1)
-        log("graph replay: %.3g particle-steps/s" % graph_value)
     value = cfg["N"] * args.steps / wall
+
+    # timed region 2 (the roofline): the same K steps launched one by one, each
+    # fused step kernel bracketed by HIP events on the context's stream
+    m2m.m2m_set_launch(ctx, timing=1, graph_steps=0)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    m2m.m2m_step(ctx, args.steps)
+    torch.cuda.synchronize()
+    wall_ev = time.perf_counter() - t1
+    k_ms, k_n = m2m.m2m_kernel_time(ctx)
     achieved = BYTES_PER_PARTICLE_STEP * cfg["N"] / (k_ms * 1e-3) / 1e9
-    log("wall %.3f s, %.2f us/step, fused kernel %.2f us (%d launches)" % (wall, wall / args.steps * 1e6, k_ms * 1e3, k_n))
+    log("graphs: %.2f us/step (%.3g particle-steps/s); one by one: %.2f us/step, fused kernel %.2f us (%d launches)"
+        % (wall / args.steps * 1e6, value, wall_ev / args.steps * 1e6, k_ms * 1e3, k_n))
+    traffic = measured_traffic(cfg["N"])
 
     # chi^2 relative error against the oracle: one step from the initial state
     er = None
@@ -156,10 +186,13 @@ def main():
                                "32x32 (E, Lz/Lc) moving prior every step, dt=0.005" % cfg["N"],
                    "N": cfg["N"], "J": 4896, "prior_cells": 1024, "launch": launch},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "step_kernel<float,float,1,ILP>", "kernel_us": k_ms * 1e3,
-                     "bytes_per_launch": BYTES_PER_PARTICLE_STEP * cfg["N"]},
-        "graph_replay_value": graph_value,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "step_kernel (fused update + push + observe + prior cells)",
+                     "kernel_us": k_ms * 1e3, "bytes_per_launch": BYTES_PER_PARTICLE_STEP * cfg["N"],
+                     "timing": "HIP events around each of %d one-by-one launches" % k_n},
+        "timing": {"value": "%d steps replayed from HIP graphs of %d steps" % (args.steps, G),
+                   "one_by_one_value": cfg["N"] * args.steps / wall_ev,
+                   "one_by_one_ms_per_step": wall_ev / args.steps * 1e3},
         "chi2_rel_err_vs_oracle": chi2_err,
         "chi2_final": last["chi2"],
         "cpu_baseline": cpu,
