@@ -73,12 +73,48 @@ def cpu_baseline(cfg, inp, er, nsteps):
             "kind": "oracle", "sample": "N=%d particles x %d steps of the same workload (%.1f s)" % (cfg["N"], nsteps, dt)}, st
 
 
+def batched_checks(m2m, cfg, inp, xv, w, launch, cpu_steps, sample=(0, 31, 63)):
+    """Batched workload: chi^2 of sampled models after two steps of the full 64-model run
+    against the oracle run on each of those models alone, and the oracle's rate on the
+    first sampled model (a bounded sample of the workload)."""
+    import oracle
+    offs = np.concatenate([[0], np.cumsum(cfg["model_sizes"])])
+    ics64 = inp["ics"].astype(np.float64)
+    er = []
+    for m in range(len(cfg["model_sizes"])):
+        er += list(oracle.energy_range(cfg, ics64, slice(offs[m], offs[m + 1]), model=m))
+    ctx2 = m2m.m2m_create(cfg, xv, w, inp["Y"], inp["sigma"], Erange=np.array(er), device_ptrs=True)
+    m2m.m2m_set_launch(ctx2, threads=launch["threads"], ilp=launch["ilp"], blocks_per_cu=launch["blocks_per_cu"])
+    m2m.m2m_step(ctx2, 2)
+    hist = m2m.m2m_history(ctx2)
+    m2m.m2m_destroy(ctx2)
+    errs, cpu = [], None
+    for m in sample:
+        sl = slice(offs[m], offs[m + 1])
+        om = oracle.Model(cfg, ics64[:, sl].copy(), inp["w"][sl].astype(np.float64), inp["Y"], inp["sigma"],
+                          Erange=tuple(er[2 * m:2 * m + 2]), model=m)
+        t0 = time.perf_counter()
+        rows = om.run(cpu_steps if cpu is None else 2)
+        dt = time.perf_counter() - t0
+        if cpu is None:
+            cpu = {"value": (offs[m + 1] - offs[m]) * cpu_steps / dt, "unit": "particle-steps/s",
+                   "cores": oracle.threads(), "kind": "oracle",
+                   "sample": "model %d alone (N=%d) x %d steps (%.1f s)" % (m, offs[m + 1] - offs[m], cpu_steps, dt)}
+        g = [r for r in hist if r["model"] == m and r["step"] == 1][0]
+        errs.append(abs(g["chi2"] - rows[1][0]) / rows[1][0])
+        log("model %d: chi2 step 1 GPU %.10g oracle %.10g" % (m, g["chi2"], rows[1][0]))
+    return cpu, max(errs)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--n", type=int, default=1 << 20)
+    ap.add_argument("--workload", choices=("logpot", "batched"), default="logpot",
+                    help="logpot: the 2^20-particle log-potential model (the headline); batched: 64 "
+                         "Hernquist+NFW models, sum N_m ~ 67M, one launch per step for all models")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=24)
     ap.add_argument("--autotune", action="store_true",
@@ -108,8 +144,9 @@ def main():
     import paper_1207_6403_amd as m2m
     from synth import configs
 
-    cfg = configs.cfg2(N=args.n)
-    log("generating inputs (N=%d)" % args.n)
+    batched = args.workload == "batched"
+    cfg = configs.cfg4() if batched else configs.cfg2(N=args.n)
+    log("generating inputs (N=%d)" % cfg["N"])
     inp = configs.make_inputs(cfg, dtype=np.float32)
     # prior energy grid: [min E(0), max E(0)] in the model potential, from the synthetic model
     from synth import galaxy  # noqa: F401
@@ -151,13 +188,15 @@ def main():
     achieved = BYTES_PER_PARTICLE_STEP * cfg["N"] / (k_ms * 1e-3) / 1e9
     log("graphs: %.2f us/step (%.3g particle-steps/s); one by one: %.2f us/step, fused kernel %.2f us (%d launches)"
         % (wall / args.steps * 1e6, value, wall_ev / args.steps * 1e6, k_ms * 1e3, k_n))
-    traffic = measured_traffic(cfg["N"])
+    traffic = None if batched else measured_traffic(cfg["N"])
 
     # chi^2 relative error against the oracle: one step from the initial state
     er = None
     chi2_err = None
     cpu = None
-    if not args.no_cpu_baseline:
+    if batched and not args.no_cpu_baseline:
+        cpu, chi2_err = batched_checks(m2m, cfg, inp, xv, w, launch, args.cpu_steps)
+    elif not args.no_cpu_baseline:
         import oracle
         er = oracle.energy_range(cfg, inp["ics"].astype(np.float64))
         ctx2 = m2m.m2m_create(cfg, xv, w, inp["Y"], inp["sigma"], Erange=np.array(er), device_ptrs=True)
@@ -168,6 +207,17 @@ def main():
         chi2_err = abs(g1["chi2"] - ost[1][0]) / ost[1][0]
         m2m.m2m_destroy(ctx2)
 
+    if batched:
+        workload = ("64 Hernquist+NFW models (halo mass ratio x scale radius grid), sum N_m=%d FP32 particles, "
+                    "30 shells + 20 annuli (LOS second moment) per model, (E, L/Lc) 20x20 moving prior per "
+                    "model every step, dt=0.01, one launch per step for all models" % cfg["N"])
+        config = {"workload": workload, "N": cfg["N"], "models": len(cfg["model_sizes"]), "J": 50,
+                  "prior_cells": 400, "launch": launch}
+    else:
+        workload = ("log-potential M2M at scale: N=%d FP32 particles, J=4896 observables (64x64 sky pixels "
+                    "+ 20x20 kinematic bins x 2 LOS moments), 32x32 (E, Lz/Lc) moving prior every step, "
+                    "dt=0.005" % cfg["N"])
+        config = {"workload": workload, "N": cfg["N"], "J": 4896, "prior_cells": 1024, "launch": launch}
     out = {
         "metric": "particle-steps/sec at 1M particles (push+observe+update); chi2 rel. err vs oracle",
         "value": value,
@@ -181,10 +231,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "log-potential M2M at scale: N=%d FP32 particles, J=4896 observables "
-                               "(64x64 sky pixels + 20x20 kinematic bins x 2 LOS moments), "
-                               "32x32 (E, Lz/Lc) moving prior every step, dt=0.005" % cfg["N"],
-                   "N": cfg["N"], "J": 4896, "prior_cells": 1024, "launch": launch},
+        "config": config,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "step_kernel (fused update + push + observe + prior cells)",

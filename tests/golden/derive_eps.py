@@ -3,8 +3,9 @@
 Reading of the update law: eps is set once from the initial state so that
 eps * dt * max_i |G_i(0)| = 0.1, where G_i = dF/dw_i with the priors held fixed.
 G_i(0) is read off one oracle step with a negligible rate (w1 = w0 exp(e dt G)).
-Calls only the oracle and the input generators; prints the values recorded in
-synth/configs.py (EPS_CFG2, EPS_CFG3).
+The batched workload shares one rate over its 64 models: the maximum is taken over
+all of them at their full sizes.  Calls only the oracle and the input generators;
+prints the values recorded in synth/configs.py (EPS_CFG2, EPS_CFG3, EPS_CFG4).
 
     python tests/golden/derive_eps.py
 """
@@ -28,8 +29,28 @@ def max_abs_G(cfg):
     return float(np.max(np.abs(G)))
 
 
+def max_abs_G_batched(cfg):
+    inp = configs.make_inputs(cfg)
+    offs = np.concatenate([[0], np.cumsum(cfg["model_sizes"])])
+    c = dict(cfg, eps=1e-12, update="exp", frozen=True)
+    g = 0.0
+    for k in range(len(cfg["model_sizes"])):
+        sl = slice(offs[k], offs[k + 1])
+        m = oracle.Model(c, inp["ics"][:, sl].copy(), inp["w"][sl].copy(), inp["Y"], inp["sigma"], model=k)
+        w0 = m.w.copy()
+        m.run(1)
+        g = max(g, float(np.max(np.abs(np.log(m.w / w0) / (c["eps"] * c["dt"])))))
+    return g
+
+
 if __name__ == "__main__":
-    for name, cfg in [("EPS_CFG2", configs.cfg2(N=1 << 20)), ("EPS_CFG3", configs.cfg3(N=1 << 20))]:
-        g = max_abs_G(cfg)
+    which = sys.argv[1:] or ["EPS_CFG2", "EPS_CFG3", "EPS_CFG4"]
+    cases = {"EPS_CFG2": lambda: max_abs_G(configs.cfg2(N=1 << 20)),
+             "EPS_CFG3": lambda: max_abs_G(configs.cfg3(N=1 << 20)),
+             "EPS_CFG4": lambda: max_abs_G_batched(configs.cfg4())}
+    dts = {"EPS_CFG2": configs.cfg2(N=16)["dt"], "EPS_CFG3": configs.cfg3(N=16)["dt"], "EPS_CFG4": 0.01}
+    for name in which:
+        g = cases[name]()
+        cfg = {"dt": dts[name]}
         eps = 0.1 / (cfg["dt"] * g)
         print("%s = %.3e   # max|G(0)| = %.4e" % (name, float("%.2e" % eps), g))

@@ -168,6 +168,7 @@ def test_nonpositive_weight_keeps_last_state():
 
 def test_batched_models_match_oracle():
     cfg = configs.cfg4(n_models=5, nmin=1500, nmax=6000, steps=4)
+    cfg["eps"] = 1e-3   # small models: the cfg-1 rate keeps the weights positive and moves them visibly
     inp, ctx, ors = run_both(cfg, 4, launch={"threads": 256, "ilp": 2, "blocks_per_cu": 1})
     rows = m2m.m2m_step(ctx, 4)
     offs = np.concatenate([[0], np.cumsum(cfg["model_sizes"])])
@@ -177,6 +178,51 @@ def test_batched_models_match_oracle():
         np.testing.assert_allclose(wg[offs[m]:offs[m + 1]], om.w, rtol=1e-5)
         assert rows[m]["chi2"] == pytest.approx(ost[0], rel=1e-5)
         assert rows[m]["model"] == m
+
+
+@pytest.mark.parametrize("prec,period,nsteps,tol", [("f64", 3, 7, 1e-11), ("f32", 4, 9, 5e-6)])
+def test_periodic_hist_prior(prec, period, nsteps, tol):
+    """Histogram prior refreshed every P > 1 steps (priors stored per particle between
+    refreshes): weights, chi^2 and S against the oracle across several refreshes."""
+    cfg = configs.cfg1(N=3000) if prec == "f64" else configs.cfg2(N=30000)
+    cfg["prior"] = dict(cfg["prior"], period=period)
+    inp, ctx, (om,) = run_both(cfg, nsteps)
+    m2m.m2m_step(ctx, nsteps)
+    orows = om.run(nsteps)
+    np.testing.assert_allclose(m2m.m2m_weights(ctx).astype(np.float64), om.w, rtol=tol)
+    hist = m2m.m2m_history(ctx)
+    assert [r["step"] for r in hist] == list(range(nsteps))
+    for r, o in zip(hist, orows):
+        assert r["chi2"] == pytest.approx(o[0], rel=tol)
+        # S is a sum of terms of both signs (S(0) = 0): compare it on the scale of sum w |ln w|
+        assert r["S"] == pytest.approx(o[2], abs=tol * 30.0 * o[4])
+
+
+def test_batched_full_size_sampled_models():
+    """The 64-model batch at its full size (sum N_m ~ 67M, one launch per step, the
+    benchmark's launch shape): chi^2 and weights of sampled models after two steps
+    against the oracle run on each of those models alone."""
+    cfg = configs.cfg4()
+    H.flush("case batched 64 models N=%d: generating inputs" % cfg["N"])
+    inp = configs.make_inputs(cfg, dtype=np.float32)
+    er = H.erange(cfg, inp)
+    offs = np.concatenate([[0], np.cumsum(cfg["model_sizes"])])
+    H.flush("case batched 64 models N=%d: create + 2 steps" % cfg["N"])
+    ctx = m2m.m2m_create(cfg, inp["ics"], inp["w"], inp["Y"], inp["sigma"], Erange=er)
+    m2m.m2m_step(ctx, 2)
+    hist = m2m.m2m_history(ctx)
+    wg = m2m.m2m_weights(ctx)
+    assert len(hist) == 2 * 64
+    for m in (0, 17, 63):
+        sl = slice(offs[m], offs[m + 1])
+        om = oracle.Model(cfg, inp["ics"][:, sl].astype(np.float64), inp["w"][sl].astype(np.float64), inp["Y"],
+                          inp["sigma"], Erange=tuple(er[2 * m:2 * m + 2]), model=m)
+        rows = om.run(2)
+        for n in (0, 1):
+            g = [r for r in hist if r["model"] == m and r["step"] == n][0]
+            assert g["chi2"] == pytest.approx(rows[n][0], rel=2e-6), (m, n)
+            assert g["sum_w"] == pytest.approx(rows[n][4], rel=1e-6), (m, n)
+        np.testing.assert_allclose(wg[sl].astype(np.float64), om.w, rtol=2e-6)
 
 
 def test_frozen_entropy_recurrence_gpu():
