@@ -395,54 +395,80 @@ void or_mp_coeffs(const or_pot *p, int64_t N, const double *x, const double *y, 
     free(SA); free(SB);
 }
 
-/* Phi and acceleration from coefficient values Ar, Br (already at radius r):
- * dPhi/dr uses -(l+1) r^-(l+2) A + l r^(l-1) B (the dA/dr, dB/dr terms cancel). */
+/* Phi and acceleration from coefficient values Ar, Br (already at radius r),
+ * with A and B held fixed (the dA/dr and dB/dr terms cancel in the exact
+ * expansion).  Written with the solid harmonics R_lm = r^l P_l^m(ct) e^(i m ph),
+ *   Phi = -G sum_lm c_lm [Re R_lm (Ac r^-(2l+1) + Bc) + Im R_lm (As r^-(2l+1) + Bs)],
+ * so that the gradient has no coordinate singularity on the polar axis:
+ *   d/dz R_lm = (l+m) R_(l-1)m,  (d/dx + i d/dy) R_lm = R_(l-1)(m+1),
+ *   (d/dx - i d/dy) R_lm = -(l+m)(l+m-1) R_(l-1)(m-1)  (m >= 1; for m = 0 it is the
+ *   complex conjugate of (d/dx + i d/dy) R_l0, R_l0 being real),
+ * identities of the associated Legendre functions with the Condon-Shortley phase.
+ * R_lm follows from P_m^m = (-1)^m (2m-1)!! st^m and the recurrence in l. */
 static void mp_field(int lmax, double G, double x, double y, double z,
                      const double *Ar, const double *Br,
                      double *phi, double *ax, double *ay, double *az) {
-    double r = sqrt(x * x + y * y + z * z);
-    /* on the polar axis the spherical components are singular: step off it by a
-       relative 1e-9 (changes the field far below the FP64 checks that use it) */
-    if (x * x + y * y < 1e-24 * r * r) x = 1e-9 * r;
-    double Rxy = sqrt(x * x + y * y);
-    double ct = z / r, st = Rxy / r;
-    double ph = atan2(y, x), cp = cos(ph), sp = sin(ph);
-    double P[(OR_MAXL + 2) * (OR_MAXL + 2)];
-    legendre(lmax + 1, ct, P);
-    int L1 = lmax + 2;
-    double Phi = 0.0, dr = 0.0, dth = 0.0, dph = 0.0;
-    for (int l = 0; l <= lmax; ++l) {
-        double rl = pow(r, l), rinv = pow(r, -(l + 1));
-        for (int m = 0; m <= l; ++m) {
-            double c = (m == 0 ? 1.0 : 2.0) * factorial(l - m) / factorial(l + m);
-            double p = P[l * L1 + m];
-            /* dP_l^m(cos t)/dt = (l ct P_l^m - (l+m) P_(l-1)^m)/st */
-            double pl1 = l >= 1 ? P[(l - 1) * L1 + m] : 0.0;
-            if (m > l - 1) pl1 = 0.0;
-            double dp = (l * ct * p - (l + m) * pl1) / st;
-            double cm = cos(m * ph), sm = sin(m * ph);
-            int jc = lm_index(l, m, 0);
-            double radc = Ar[jc] * rinv + Br[jc] * rl;
-            double draddr_c = -(l + 1) * Ar[jc] * rinv / r + (l > 0 ? l * Br[jc] * rl / r : 0.0);
-            double rads = 0.0, draddr_s = 0.0;
-            if (m > 0) {
-                int js = lm_index(l, m, 1);
-                rads = Ar[js] * rinv + Br[js] * rl;
-                draddr_s = -(l + 1) * Ar[js] * rinv / r + (l > 0 ? l * Br[js] * rl / r : 0.0);
-            }
-            double ang = cm * radc + sm * rads;
-            Phi += c * p * ang;
-            dr += c * p * (cm * draddr_c + sm * draddr_s);
-            dth += c * dp * ang;
-            dph += c * p * m * (-sm * radc + cm * rads);
+    const int L1 = OR_MAXL + 1;
+    double Rre[(OR_MAXL + 1) * (OR_MAXL + 1)], Rim[(OR_MAXL + 1) * (OR_MAXL + 1)];
+    double r2 = x * x + y * y + z * z;
+    double r = sqrt(r2);
+    /* R[l*L1+m] */
+    Rre[0] = 1.0; Rim[0] = 0.0;
+    for (int m = 0; m <= lmax; ++m) {
+        if (m > 0) {
+            double pr = Rre[(m - 1) * L1 + m - 1], pi = Rim[(m - 1) * L1 + m - 1];
+            double f = -(2.0 * m - 1.0);
+            Rre[m * L1 + m] = f * (x * pr - y * pi);
+            Rim[m * L1 + m] = f * (x * pi + y * pr);
+        }
+        if (m + 1 <= lmax) {
+            Rre[(m + 1) * L1 + m] = (2.0 * m + 1.0) * z * Rre[m * L1 + m];
+            Rim[(m + 1) * L1 + m] = (2.0 * m + 1.0) * z * Rim[m * L1 + m];
+        }
+        for (int l = m + 2; l <= lmax; ++l) {
+            Rre[l * L1 + m] = ((2.0 * l - 1.0) * z * Rre[(l - 1) * L1 + m] - (l + m - 1.0) * r2 * Rre[(l - 2) * L1 + m]) / (l - m);
+            Rim[l * L1 + m] = ((2.0 * l - 1.0) * z * Rim[(l - 1) * L1 + m] - (l + m - 1.0) * r2 * Rim[(l - 2) * L1 + m]) / (l - m);
         }
     }
-    Phi *= -G; dr *= -G; dth *= -G; dph *= -G;
-    double ar = -dr, at = -dth / r, ap = -dph / (r * st);
-    *phi = Phi;
-    *ax = ar * st * cp + at * ct * cp - ap * sp;
-    *ay = ar * st * sp + at * ct * sp + ap * cp;
-    *az = ar * ct - at * st;
+    double U = 0.0, gx = 0.0, gy = 0.0, gz = 0.0;
+    for (int l = 0; l <= lmax; ++l) {
+        double p = pow(r, -(2.0 * l + 1.0));          /* r^-(2l+1) */
+        double q = (2.0 * l + 1.0) * p / r2;           /* -d(r^-(2l+1))/dx = q x */
+        for (int m = 0; m <= l; ++m) {
+            double c = (m == 0 ? 1.0 : 2.0) * factorial(l - m) / factorial(l + m);
+            int jc = lm_index(l, m, 0);
+            double Ac = Ar[jc], Bc = Br[jc], As = 0.0, Bs = 0.0;
+            if (m > 0) { int js = lm_index(l, m, 1); As = Ar[js]; Bs = Br[js]; }
+            double re = Rre[l * L1 + m], im = Rim[l * L1 + m];
+            double ac = Ac * p + Bc, as = As * p + Bs;
+            U += c * (re * ac + im * as);
+            /* gradient of R_lm: components (dre, dim) for x, y, z */
+            double dxr = 0, dxi = 0, dyr = 0, dyi = 0, dzr = 0, dzi = 0;
+            if (l >= 1) {
+                double upr = 0, upi = 0;   /* R_(l-1)(m+1) */
+                if (m + 1 <= l - 1) { upr = Rre[(l - 1) * L1 + m + 1]; upi = Rim[(l - 1) * L1 + m + 1]; }
+                if (m == 0) {
+                    dxr = upr; dyr = upi;   /* d/dx R_l0 = Re(d+ R), d/dy R_l0 = Im(d+ R) */
+                } else {
+                    double f = -(double)(l + m) * (l + m - 1.0);
+                    double dnr = 0, dni = 0;   /* f R_(l-1)(m-1) */
+                    if (m - 1 <= l - 1) { dnr = f * Rre[(l - 1) * L1 + m - 1]; dni = f * Rim[(l - 1) * L1 + m - 1]; }
+                    /* d/dx = (d+ + d-)/2, d/dy = (d+ - d-)/(2i) */
+                    dxr = 0.5 * (upr + dnr); dxi = 0.5 * (upi + dni);
+                    dyr = 0.5 * (upi - dni); dyi = -0.5 * (upr - dnr);
+                }
+                if (m <= l - 1) { dzr = (l + m) * Rre[(l - 1) * L1 + m]; dzi = (l + m) * Rim[(l - 1) * L1 + m]; }
+            }
+            double t = re * Ac + im * As;
+            gx += c * (dxr * ac + dxi * as - q * x * t);
+            gy += c * (dyr * ac + dyi * as - q * y * t);
+            gz += c * (dzr * ac + dzi * as - q * z * t);
+        }
+    }
+    *phi = -G * U;
+    *ax = G * gx;
+    *ay = G * gy;
+    *az = G * gz;
 }
 
 /* Evaluate the node-interpolated expansion at one point (radius clamped). */

@@ -78,6 +78,23 @@ def test_exact_expansion_force_is_minus_gradient():
         done += 1
 
 
+@pytest.mark.parametrize("pt", [(0.0, 0.0, 0.7), (0.0, 0.0, -1.3), (1e-7, 0.0, 0.9)])
+def test_force_on_the_polar_axis_is_minus_gradient(pt):
+    """On (and next to) the z axis the spherical angles are singular but the force is
+    not: central differences of Phi in x, y, z give it."""
+    pos, w = cloud(100)
+    pt = np.array(pt)
+    _, ax, ay, az = oracle.mp_exact(MP, pos, w, pt)
+    h = 1e-5
+    g = np.zeros(3)
+    for k in range(3):
+        e = np.zeros(3)
+        e[k] = h
+        g[k] = (oracle.mp_exact(MP, pos, w, pt + e)[0] - oracle.mp_exact(MP, pos, w, pt - e)[0]) / (2 * h)
+    scale = np.abs(g).max()
+    np.testing.assert_allclose([ax, ay, az], -g, rtol=0, atol=1e-6 * scale)
+
+
 def test_node_tables_equal_exact_at_node_radii():
     pos, w = cloud(100)
     A, B = oracle.mp_coeffs(MP, pos, w)
