@@ -74,7 +74,11 @@ enum { M2M_UPDATE_EULER = 0, M2M_UPDATE_EXP = 1 };
  *   MULTIPOLE      self-consistent multipole expansion to l <= lmax of the
  *                  particles (mass w_i * Mtot), coefficients at nnode
  *                  log-spaced radii in [rmin, rmax], linear in ln r between
- *                  them; radii outside the range are clamped. */
+ *                  them; radii outside the range are clamped.  Rebuilt every
+ *                  step between the drift and the second kick.  One model per
+ *                  context; FP32 contexts hold the node table in LDS, so
+ *                  nnode is limited by it (720 bytes per node of the 160 KB:
+ *                  at most 226 nodes; UNSUPPORTED beyond). */
 typedef struct {
     int32_t kind;
     int32_t lmax, nnode, reserved;
@@ -232,6 +236,16 @@ m2m_status m2m_particles(m2m_ctx *ctx, void *xv_out, int32_t device_ptr);
 /* Statistics rows of the most recent steps, oldest first (ring of the last
  * 4096 steps per model).  out holds max_rows rows; *n_rows gets the count. */
 m2m_status m2m_history(m2m_ctx *ctx, m2m_step_stats *out, int64_t max_rows, int64_t *n_rows);
+
+/* Node coefficients of a MULTIPOLE model (sections 1 and 2: the potential
+ * computed from the particles), as used by the first kick of the next step:
+ * A and B, nnode * (lmax+1)^2 FP64 values each (host; node k at k*(lmax+1)^2,
+ * coefficient (l, m >= 0, cos) at l*l + 2m - 1 for m > 0, l*l for m = 0, the
+ * sin part one after the cos part).  A(r_k) sums m_i r_i^l P_l^m e^(i m phi_i)
+ * over the particles below node radius r_k, B(r_k) m_i r_i^-(l+1) P_l^m e^(i m
+ * phi_i) over the rest.  FP32 contexts sum per-block FP32 partials in FP64.
+ * INVALID when the model is not a multipole. */
+m2m_status m2m_multipole_tables(m2m_ctx *ctx, double *A, double *B);
 
 /* Time candidate launch shapes (threads x ilp x blocks_per_cu) on trial_steps
  * steps each, restore the state, keep the fastest; chosen may be NULL.  The

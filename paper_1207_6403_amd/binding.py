@@ -104,6 +104,7 @@ def lib():
         L.m2m_priors.argtypes = [CTX, VP, C.POINTER(C.c_double), C.c_int32]
         L.m2m_particles.argtypes = [CTX, VP, C.c_int32]
         L.m2m_history.argtypes = [CTX, C.POINTER(m2m_step_stats), C.c_int64, C.POINTER(C.c_int64)]
+        L.m2m_multipole_tables.argtypes = [CTX, C.POINTER(C.c_double), C.POINTER(C.c_double)]
         L.m2m_autotune.argtypes = [CTX, C.c_int32, C.POINTER(m2m_launch)]
         L.m2m_get_launch.argtypes = [CTX, C.POINTER(m2m_launch)]
         L.m2m_set_launch.argtypes = [CTX, C.POINTER(m2m_launch)]
@@ -113,7 +114,7 @@ def lib():
         L.m2m_last_error.argtypes = [CTX]
         L.m2m_last_error.restype = C.c_char_p
         for f in ("m2m_create", "m2m_step", "m2m_observables", "m2m_weights", "m2m_priors", "m2m_particles",
-                  "m2m_history", "m2m_autotune", "m2m_get_launch", "m2m_set_launch", "m2m_kernel_time"):
+                  "m2m_history", "m2m_multipole_tables", "m2m_autotune", "m2m_get_launch", "m2m_set_launch", "m2m_kernel_time"):
             getattr(L, f).restype = C.c_int
         if L.m2m_abi_version() != ABI_VERSION:
             raise ImportError("libm2m_hip.so ABI %d, binding expects %d" % (L.m2m_abi_version(), ABI_VERSION))
@@ -256,6 +257,8 @@ def m2m_create(cfg, xv, w, Y, sigma, Erange=None, device_ptrs=False, stream=None
     c.n_models = M
     c.model_offsets = offs.ctypes.data_as(C.POINTER(C.c_int64))
     c.potentials = parr
+    if prior_ref is None:
+        prior_ref = cfg["prior"].get("ref_potential")
     c.prior = pack_prior(cfg["prior"], M, keep, Erange, prior_ref)
     c.stream = stream
     lay = pack_layout(cfg["layout"], keep)
@@ -338,6 +341,15 @@ def m2m_history(ctx, max_rows=None):
     n = C.c_int64()
     _check(lib().m2m_history(ctx.ptr, rows, max_rows, C.byref(n)), ctx)
     return [_stats_dict(rows[k]) for k in range(n.value)]
+
+
+def m2m_multipole_tables(ctx, nnode, lmax):
+    """Node coefficient tables (A, B) of a multipole model, each [nnode, (lmax+1)^2]."""
+    nlm = (lmax + 1) * (lmax + 1)
+    A = np.empty((nnode, nlm))
+    B = np.empty((nnode, nlm))
+    _check(lib().m2m_multipole_tables(ctx.ptr, _dp(A), _dp(B)), ctx)
+    return A, B
 
 
 def _launch_dict(L):

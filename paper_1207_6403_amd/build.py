@@ -17,7 +17,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libm2m_hip.so")
 BUILD = os.path.join(ROOT, "_build")
 
-SOURCES = ["step.hip", "finalize.hip", "api.hip"]
+SOURCES = ["step.hip", "multipole.hip", "finalize.hip", "api.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
@@ -45,7 +45,7 @@ def build(verbose=False):
     # development tree only).
     chk = os.path.join(HERE, "isa_check.py")
     if os.path.exists(chk):
-        subprocess.check_call([sys.executable, chk, LIB])
+        subprocess.check_call([sys.executable, chk] + objs)
     if verbose:
         print("built", LIB)
     return LIB

@@ -73,6 +73,23 @@ bool is_fin(double v) { return std::isfinite(v); }
 }  // namespace
 
 // --------------------------------------------------------------- validation
+static m2m_status check_potential(const m2m_potential& p) {
+    if (p.kind == M2M_POT_HERNQUIST || p.kind == M2M_POT_HERNQUIST_NFW) {
+        if (!(p.G > 0 && p.M >= 0 && p.a > 0)) return fail(nullptr, M2M_ERR_INVALID, "Hernquist needs G>0, M>=0, a>0");
+        if (p.kind == M2M_POT_HERNQUIST_NFW && !(p.Mh >= 0 && p.rs > 0))
+            return fail(nullptr, M2M_ERR_INVALID, "NFW needs Mh>=0, rs>0");
+    } else if (p.kind == M2M_POT_LOG) {
+        if (!(p.v0 > 0 && p.Rc > 0 && p.q > 0)) return fail(nullptr, M2M_ERR_INVALID, "log potential needs v0, Rc, q > 0");
+    } else if (p.kind == M2M_POT_MULTIPOLE) {
+        if (!(p.lmax >= 0 && p.lmax <= 8 && p.nnode >= 2 && p.nnode <= 512 && p.rmin > 0 && p.rmax > p.rmin &&
+              p.G > 0 && p.Mtot > 0))
+            return fail(nullptr, M2M_ERR_INVALID, "multipole needs 0<=lmax<=8, 2<=nnode<=512, 0<rmin<rmax, G, Mtot > 0");
+    } else {
+        return fail(nullptr, M2M_ERR_INVALID, "unknown potential kind");
+    }
+    return M2M_OK;
+}
+
 static m2m_status validate(const m2m_config* cfg, const m2m_obs_layout* lay, const m2m_target* tg,
                            int64_t* N_out, int* J_out) {
     if (!cfg || !lay || !tg) return fail(nullptr, M2M_ERR_INVALID, "null config, layout or target");
@@ -93,19 +110,8 @@ static m2m_status validate(const m2m_config* cfg, const m2m_obs_layout* lay, con
     for (int m = 0; m < cfg->n_models; ++m) {
         const m2m_potential& p = cfg->potentials[m];
         if (p.kind != kind) return fail(nullptr, M2M_ERR_INVALID, "all models must share the potential kind");
-        if (p.kind == M2M_POT_HERNQUIST || p.kind == M2M_POT_HERNQUIST_NFW) {
-            if (!(p.G > 0 && p.M >= 0 && p.a > 0)) return fail(nullptr, M2M_ERR_INVALID, "Hernquist needs G>0, M>=0, a>0");
-            if (p.kind == M2M_POT_HERNQUIST_NFW && !(p.Mh >= 0 && p.rs > 0))
-                return fail(nullptr, M2M_ERR_INVALID, "NFW needs Mh>=0, rs>0");
-        } else if (p.kind == M2M_POT_LOG) {
-            if (!(p.v0 > 0 && p.Rc > 0 && p.q > 0)) return fail(nullptr, M2M_ERR_INVALID, "log potential needs v0, Rc, q > 0");
-        } else if (p.kind == M2M_POT_MULTIPOLE) {
-            if (!(p.lmax >= 0 && p.lmax <= 8 && p.nnode >= 2 && p.nnode <= 512 && p.rmin > 0 && p.rmax > p.rmin &&
-                  p.G > 0 && p.Mtot > 0))
-                return fail(nullptr, M2M_ERR_INVALID, "multipole needs 0<=lmax<=8, 2<=nnode<=512, 0<rmin<rmax, G, Mtot > 0");
-        } else {
-            return fail(nullptr, M2M_ERR_INVALID, "unknown potential kind");
-        }
+        const m2m_status ps = check_potential(p);
+        if (ps) return ps;
     }
     if (lay->nbin < 1 || lay->nbin > M2M_MAX_BINNINGS) return fail(nullptr, M2M_ERR_INVALID, "nbin must be 1..4");
     if (!is_fin(lay->incl)) return fail(nullptr, M2M_ERR_INVALID, "inclination");
@@ -154,13 +160,18 @@ static m2m_status validate(const m2m_config* cfg, const m2m_obs_layout* lay, con
             for (int m = 0; m < cfg->n_models; ++m)
                 if (!(P.Erange[2 * m + 1] > P.Erange[2 * m]) || !is_fin(P.Erange[2 * m]) || !is_fin(P.Erange[2 * m + 1]))
                     return fail(nullptr, M2M_ERR_INVALID, "prior Erange needs Emin < Emax per model");
-        if (P.ref.kind >= 0 && P.ref.kind != kind)
+        if (kind == M2M_POT_MULTIPOLE) {
+            if (P.ref.kind < 0 || P.ref.kind == M2M_POT_MULTIPOLE)
+                return fail(nullptr, M2M_ERR_INVALID, "multipole models need an analytic prior reference potential");
+            const m2m_status rs = check_potential(P.ref);
+            if (rs) return rs;
+        } else if (P.ref.kind >= 0 && P.ref.kind != kind) {
             return fail(nullptr, M2M_ERR_UNSUPPORTED, "prior reference potential must be the model potential here");
-        if (kind == M2M_POT_MULTIPOLE && P.ref.kind < 0)
-            return fail(nullptr, M2M_ERR_INVALID, "multipole models need an analytic prior reference potential");
+        }
     }
     if (P.kind == M2M_PRIOR_MLP) return fail(nullptr, M2M_ERR_UNSUPPORTED, "learned prior not available in this build");
-    if (kind == M2M_POT_MULTIPOLE) return fail(nullptr, M2M_ERR_UNSUPPORTED, "multipole potential not available in this build");
+    if (kind == M2M_POT_MULTIPOLE && cfg->n_models != 1)
+        return fail(nullptr, M2M_ERR_UNSUPPORTED, "a multipole model runs alone in its context");
     *N_out = cfg->model_offsets[cfg->n_models];
     *J_out = J;
     return M2M_OK;
@@ -273,6 +284,21 @@ static m2m_status make_plan(m2m_ctx* c, int threads, int ilp, int bpc) {
     if (p.lds > (size_t)c->max_lds)
         return fail(c, M2M_ERR_UNSUPPORTED, "layout needs " + std::to_string(p.lds) + " bytes of LDS per block (max " +
                                                 std::to_string(c->max_lds) + ")");
+    if (c->mp) {
+        // multipole kernels: FP32 kernels keep the node table in LDS (update and
+        // drift, second kick)
+        const int nn = c->mp_pot.nnode;
+        const bool f32 = ts == 4;
+        MpLds& L = c->mp_lds;
+        L.kick_drift = 512 + (f32 ? 4 * (size_t)nn * kMpRowF : 0);
+        L.coeff = 0;
+        L.kick = f32 ? 4 * (size_t)nn * kMpRowF : 0;
+        const size_t need = std::max(L.kick_drift, L.kick);
+        if (need > (size_t)c->max_lds)
+            return fail(c, M2M_ERR_UNSUPPORTED, "multipole with " + std::to_string(nn) + " nodes needs " +
+                                                    std::to_string(need) + " bytes of LDS per block (max " +
+                                                    std::to_string(c->max_lds) + ")");
+    }
     return M2M_OK;
 }
 
@@ -395,6 +421,50 @@ static void prior_modes(const m2m_ctx* c, int64_t n, int* what_mode, int* accum)
     else { *what_mode = 3; *accum = 0; }
 }
 
+// Multipole kernel arguments; src is the state buffer the coefficient and
+// second-kick kernels work on.
+template <typename T>
+static void fill_mp_args(const m2m_ctx* c, MpArgs<T>& mp, const void* src) {
+    const m2m_potential& q = c->mp_pot;
+    const Plan& p = c->plan;
+    const double lr0 = std::log(q.rmin), dl = (std::log(q.rmax) - lr0) / (q.nnode - 1);
+    mp.lmax = q.lmax;
+    mp.nn = q.nnode;
+    mp.nlm = (q.lmax + 1) * (q.lmax + 1);
+    mp.nblock = p.nblock;
+    mp.lr0 = (T)lr0;
+    mp.idl = (T)(1.0 / dl);
+    mp.rmin = (T)q.rmin;
+    mp.rmax = (T)q.rmax;
+    mp.G = (T)q.G;
+    mp.Mtot = (T)q.Mtot;
+    mp.hdt = (T)(0.5 * c->dt);
+    mp.lr0d = lr0;
+    mp.dld = dl;
+    mp.tab = (const T*)c->mp_tab;
+    mp.tab_out = (T*)c->mp_tab;
+    mp.rk = c->mp_rk;
+    mp.n = c->N;
+    mp.G_sort = c->mp_G;
+    mp.R = c->mp_R;
+    mp.maxchunk = c->mp_maxchunk;
+    mp.key = c->mp_key;
+    mp.counts = c->mp_counts;
+    mp.offs = c->mp_offs;
+    mp.total = c->mp_total;
+    mp.sorted = c->mp_sorted;
+    mp.part = c->mp_part;
+    mp.S = c->mp_S;
+    mp.A64 = c->mp_A64;
+    mp.B64 = c->mp_B64;
+    mp.src = (const T*)src;
+    mp.stride = c->stride;
+    mp.block_tile0 = p.block_tile0;
+    mp.tile_p0 = p.tile_p0;
+    mp.tile_cnt = p.tile_cnt;
+    mp.flag = c->flag;
+}
+
 template <typename T>
 static hipError_t launch_one_T(m2m_ctx* c, int64_t n, hipEvent_t e0, hipEvent_t e1) {
     int wm, acc;
@@ -403,7 +473,22 @@ static hipError_t launch_one_T(m2m_ctx* c, int64_t n, hipEvent_t e0, hipEvent_t 
     fill_step_args<T>(c, a, (int)(n & 1), 0, wm, acc);
     const Plan& p = c->plan;
     if (e0) (void)hipEventRecord(e0, c->stream);
-    hipError_t e = launch_step<T, T>(a, c->pot_kind, c->sig, c->lay.nbin, p.ilp, p.nblock, p.threads, p.lds, c->stream);
+    hipError_t e;
+    if (c->mp) {
+        // self-consistent model: update, kicks and drift with the coefficient
+        // rebuild between them, then the fused kernel observes the new state
+        MpArgs<T> mp;
+        fill_mp_args<T>(c, mp, a.out);
+        e = launch_mp_step<T, T>(a, mp, c->sig, c->lay.nbin, p.nblock, c->mp_lds, c->stream);
+        if (e == hipSuccess) {
+            StepArgs<T, T> o;
+            fill_step_args<T>(c, o, (int)((n + 1) & 1), 1, 0, acc);
+            o.out = (T*)c->state[(n + 1) & 1];
+            e = launch_step<T, T>(o, c->pot_kind, c->sig, c->lay.nbin, p.ilp, p.nblock, p.threads, p.lds, c->stream);
+        }
+    } else {
+        e = launch_step<T, T>(a, c->pot_kind, c->sig, c->lay.nbin, p.ilp, p.nblock, p.threads, p.lds, c->stream);
+    }
     if (e1) (void)hipEventRecord(e1, c->stream);
     if (e != hipSuccess) return e;
     FinArgs<T, T> f;
@@ -756,6 +841,34 @@ static m2m_status create_T(m2m_ctx* c, const m2m_target* tg, const void* xv, con
     HIPCHK(c, hipMemset(c->cvec, 0, sizeof(T) * MJ));
     HIPCHK(c, hipMemset(c->cellmean, 0, sizeof(T) * (size_t)c->M * std::max(1, c->NC)));
     HIPCHK(c, hipMemset(c->cellmean64, 0, sizeof(double) * (size_t)c->M * std::max(1, c->NC)));
+    if (c->mp) {
+        // node radii (FP64, the interval decisions), node table, interval sums,
+        // readback tables
+        const m2m_potential& q = c->mp_pot;
+        const int nn = q.nnode, nlm = (q.lmax + 1) * (q.lmax + 1);
+        const double lr0 = std::log(q.rmin), dl = (std::log(q.rmax) - lr0) / (nn - 1);
+        std::vector<double> rk(nn);
+        for (int k = 0; k < nn; ++k) rk[k] = std::exp(lr0 + k * dl);
+        const size_t ntab = (size_t)nn * (sizeof(T) == 4 ? kMpRowF : kMpW);
+        if ((s = upload(c, &c->mp_rk, rk)) || (s = dalloc(c, (T**)&c->mp_tab, ntab)) ||
+            (s = dalloc(c, &c->mp_S, (size_t)(nn + 1) * kMpW)) || (s = dalloc(c, &c->mp_A64, (size_t)nn * nlm)) ||
+            (s = dalloc(c, &c->mp_B64, (size_t)nn * nlm)))
+            return s;
+        HIPCHK(c, hipMemset(c->mp_tab, 0, sizeof(T) * ntab));
+        HIPCHK(c, hipMemset(c->mp_S, 0, sizeof(double) * (nn + 1) * kMpW));
+        if (sizeof(T) == 4) {
+            // counting sort by interval: G blocks of R particles (G <= 1024)
+            c->mp_G = (int)std::min<int64_t>(1024, (N + kMpSortThreads - 1) / kMpSortThreads);
+            c->mp_R = ((N + c->mp_G - 1) / c->mp_G + kMpSortThreads - 1) / kMpSortThreads * kMpSortThreads;
+            c->mp_maxchunk = (int)((N + kMpChunk - 1) / kMpChunk + nn + 1);
+            const size_t nk = (size_t)(nn + 1) * c->mp_G;
+            if ((s = dalloc(c, &c->mp_key, (size_t)N)) || (s = dalloc(c, &c->mp_counts, nk)) ||
+                (s = dalloc(c, &c->mp_offs, nk)) || (s = dalloc(c, &c->mp_total, (size_t)nn + 1)) ||
+                (s = dalloc(c, &c->mp_sorted, (size_t)N)) ||
+                (s = dalloc(c, &c->mp_part, (size_t)c->mp_maxchunk * kMpW)))
+                return s;
+        }
+    }
     // launch plan, energy range of the prior grid, prologue observe
     if ((s = make_plan(c, c->launch.threads, c->launch.ilp, c->launch.blocks_per_cu))) return s;
     std::vector<double> er(2 * (size_t)c->M, 0.0);
@@ -768,6 +881,12 @@ static m2m_status create_T(m2m_ctx* c, const m2m_target* tg, const void* xv, con
     for (size_t k = 0; k < er.size(); ++k) erT[k] = (T)er[k];
     if ((s = upload(c, (T**)&c->erange, erT)) || (s = upload(c, &c->erange64, er))) return s;
     if ((s = build_lc_etab<T>(c, er)) || (s = upload_exact(c))) return s;
+    if (c->mp) {
+        // coefficients of the initial state (used by the first kick of step 0)
+        MpArgs<T> mp;
+        fill_mp_args<T>(c, mp, c->state[0]);
+        HIPCHK(c, launch_mp_build<T>(mp, c->plan.nblock, c->mp_lds, c->stream, false));
+    }
     HIPCHK(c, launch_prologue_T<T>(c));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     return M2M_OK;
@@ -808,6 +927,19 @@ extern "C" m2m_status m2m_create(const m2m_config* cfg, const m2m_obs_layout* la
     c->M = cfg->n_models;
     c->off.assign(cfg->model_offsets, cfg->model_offsets + c->M + 1);
     c->pots.assign(cfg->potentials, cfg->potentials + c->M);
+    if (c->pots[0].kind == M2M_POT_MULTIPOLE) {
+        // the self-consistent model: energies of the prior cells are measured in
+        // the analytic reference potential (a flat prior needs none)
+        c->mp = true;
+        c->mp_pot = c->pots[0];
+        if (cfg->prior.ref.kind >= 0) {
+            c->pots[0] = cfg->prior.ref;
+        } else {
+            c->pots[0] = m2m_potential{};
+            c->pots[0].kind = M2M_POT_HERNQUIST;
+            c->pots[0].G = c->pots[0].M = c->pots[0].a = 1.0;
+        }
+    }
     c->pot_kind = c->pots[0].kind;
     c->prior = cfg->prior;
     c->prior.Erange = nullptr;
@@ -846,8 +978,13 @@ extern "C" m2m_status m2m_create(const m2m_config* cfg, const m2m_obs_layout* la
     c->launch.graph_steps = 0;
     c->launch.timing = 0;
     const size_t lds_need = 160 * 1024;
-    if (c->prec == M2M_F64) (void)set_step_lds_limit<double, double>(c->pot_kind, lds_need);
-    else (void)set_step_lds_limit<float, float>(c->pot_kind, lds_need);
+    if (c->prec == M2M_F64) {
+        (void)set_step_lds_limit<double, double>(c->pot_kind, lds_need);
+        if (c->mp) (void)set_mp_lds_limit<double, double>(lds_need);
+    } else {
+        (void)set_step_lds_limit<float, float>(c->pot_kind, lds_need);
+        if (c->mp) (void)set_mp_lds_limit<float, float>(lds_need);
+    }
     (void)hipGetLastError();
     s = c->prec == M2M_F64 ? create_T<double>(c, target, xv, w, device_ptrs)
                            : create_T<float>(c, target, xv, w, device_ptrs);
@@ -1076,6 +1213,18 @@ extern "C" m2m_status m2m_history(m2m_ctx* c, m2m_step_stats* out, int64_t max_r
     return M2M_OK;
 }
 
+// --------------------------------------------------------- multipole tables
+extern "C" m2m_status m2m_multipole_tables(m2m_ctx* c, double* A, double* B) {
+    if (!c || !A || !B) return fail(c, M2M_ERR_INVALID, "null argument");
+    if (!c->mp) return fail(c, M2M_ERR_INVALID, "the context's model has no multipole potential");
+    if (c->status == M2M_ERR_DEVICE) return c->status;
+    const size_t n = (size_t)c->mp_pot.nnode * (c->mp_pot.lmax + 1) * (c->mp_pot.lmax + 1);
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, hipMemcpy(A, c->mp_A64, n * sizeof(double), hipMemcpyDeviceToHost));
+    HIPCHK(c, hipMemcpy(B, c->mp_B64, n * sizeof(double), hipMemcpyDeviceToHost));
+    return M2M_OK;
+}
+
 // ------------------------------------------------------------- launch shape
 extern "C" m2m_status m2m_get_launch(const m2m_ctx* c, m2m_launch* out) {
     if (!c || !out) return M2M_ERR_INVALID;
@@ -1138,6 +1287,12 @@ static m2m_status snapshot(m2m_ctx* c, Snapshot& s, bool restore) {
                                {c->cellmean, MC * ts}, {c->cellmean64, MC * 8}, {c->chunk_chi, 4 * (size_t)c->nchunk * 8},
                                {c->ring, sizeof(StatRow) * (size_t)c->M * kRing}, {c->d_step, 16}};
     if (c->what) items.push_back({c->what, (size_t)c->stride * ts});
+    if (c->mp) {
+        const size_t nn = c->mp_pot.nnode, nlm = (size_t)(c->mp_pot.lmax + 1) * (c->mp_pot.lmax + 1);
+        items.push_back({c->mp_tab, nn * (ts == 4 ? kMpRowF : kMpW) * ts});
+        items.push_back({c->mp_A64, nn * nlm * 8});
+        items.push_back({c->mp_B64, nn * nlm * 8});
+    }
     if (!restore) {
         for (auto& it : items) {
             void* cp = nullptr;

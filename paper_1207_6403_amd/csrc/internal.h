@@ -43,6 +43,26 @@ struct m2m_ctx {
     int J = 0, JP = 0, NC = 0, pcols = 0, nedge = 0;
     alignas(16) unsigned char lay_bytes[sizeof(m2m::Layout<double>)] = {};
     uint64_t sig = 0;   // layout structure signature
+    // self-consistent multipole (one model): its parameters, node radii, node
+    // tables, interval sums, readback tables
+    bool mp = false;
+    m2m_potential mp_pot{};
+    void* mp_tab = nullptr;
+    double* mp_rk = nullptr;
+    double* mp_S = nullptr;
+    double* mp_A64 = nullptr;
+    double* mp_B64 = nullptr;
+    // FP32 coefficient build: interval keys, counts and offsets, sorted copy, chunk partials
+    uint16_t* mp_key = nullptr;
+    uint32_t* mp_counts = nullptr;
+    uint32_t* mp_offs = nullptr;
+    uint32_t* mp_total = nullptr;
+    float4* mp_sorted = nullptr;
+    float* mp_part = nullptr;
+    int mp_G = 0;
+    int64_t mp_R = 0;
+    int mp_maxchunk = 0;
+    m2m::MpLds mp_lds{};
     m2m::Cells cells{};
     // device
     hipStream_t stream = nullptr;

@@ -1,0 +1,146 @@
+// particle.h -- per-particle pieces shared by the step kernels (step.hip) and
+// the self-consistent multipole kernels (multipole.hip): block reductions, the
+// per-block working set, state-buffer addressing, and the weight update.
+#pragma once
+#include <type_traits>
+
+#include "runtime.h"
+
+namespace m2m {
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+    #pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+template <typename T>
+__device__ __forceinline__ T wave_min(T v) {
+    #pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+// Block-wide sum / min of four per-thread statistics into out[0..3] (thread 0).
+__device__ __forceinline__ void block_stats(double s, double w, double w2, double mn, double* red, double* out) {
+    s = wave_sum(s); w = wave_sum(w); w2 = wave_sum(w2); mn = wave_min(mn);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    if (lane == 0) { red[4 * wid] = s; red[4 * wid + 1] = w; red[4 * wid + 2] = w2; red[4 * wid + 3] = mn; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double a = 0, b = 0, c = 0, d = INFINITY;
+        for (int i = 0; i < nw; ++i) { a += red[4 * i]; b += red[4 * i + 1]; c += red[4 * i + 2]; d = fmin(d, red[4 * i + 3]); }
+        out[0] = a; out[1] = b; out[2] = c; out[3] = d;
+    }
+    __syncthreads();
+}
+
+// Per-block working set of one model (LDS tables and model constants).
+template <typename T>
+struct Blk {
+    double* hist;       // observable histogram (FP64)
+    double* csum;       // prior cell weight sums
+    unsigned* ccnt;     // prior cell counts
+    const T* cl;        // update table Dt_j / sigma_j
+    const T* cm;        // prior cell means
+    const T* ed;        // edges in T
+    const double* ed64; // edges in FP64
+    const float2* et;   // uniform-E Lc table (FP32 kernels)
+    const T* lct;       // circular-orbit energies (FP64 kernels)
+    Pot<T> pot;
+    T Emin, sE, wflat;
+    int m;
+};
+
+// Statistics of the weights entering the step, accumulated per thread.
+struct Acc {
+    double S = 0, W = 0, W2 = 0, mn = INFINITY;
+    unsigned bad = 0;
+};
+
+// Element i of a table that no kernel writes while it runs, read through the
+// constant address space: uniform indices then become scalar loads, which do
+// not wait behind the vector stores of the particle loop.
+template <typename X>
+__device__ __forceinline__ X ro(const X* p, int64_t i) {
+    if constexpr (std::is_arithmetic<X>::value) {
+        return ((const __attribute__((address_space(4))) X*)p)[i];
+    } else {
+        // a struct, word by word
+        static_assert(sizeof(X) % 4 == 0, "whole words");
+        X v;
+        const __attribute__((address_space(4))) uint32_t* s = (const __attribute__((address_space(4))) uint32_t*)(p + i);
+        uint32_t* d = reinterpret_cast<uint32_t*>(&v);
+        #pragma unroll
+        for (unsigned k = 0; k < sizeof(X) / 4; ++k) d[k] = s[k];
+        return v;
+    }
+}
+
+// Value at byte offset off from base.  Every row of a state buffer (values,
+// then tags) is addressed from the buffer's base with a 32-bit byte offset
+// (state buffers are smaller than 4 GiB), so one scalar base serves all rows.
+template <typename X>
+__device__ __forceinline__ X ld_at(const void* base, uint32_t off) {
+    return *reinterpret_cast<const X*>(reinterpret_cast<const char*>(base) + off);
+}
+template <typename X>
+__device__ __forceinline__ void st_at(void* base, uint32_t off, X v) {
+    *reinterpret_cast<X*>(reinterpret_cast<char*>(base) + off) = v;
+}
+
+// Scatter w * K_j of one particle's bin k of binning b (moments of v_los = vl).
+template <uint64_t SIG, typename T>
+__device__ __forceinline__ void scatter_bin(const LayoutView<SIG, T>& V, double* hist, int b, int k, T wn, T vl) {
+    const BinDesc<T>& d = V.L.b[b];
+    const int base = d.off + k;
+    const int nmom = V.nmom(b), mom = V.mom(b);
+    #pragma unroll
+    for (int mm = 0; mm < 3; ++mm) {
+        if (mm >= nmom) break;
+        atomicAdd(&hist[base + mm * d.nb], double(wn * moment_value<T>((mom >> (2 * mm)) & 3, vl)));
+    }
+}
+
+// w(n+1) of one particle (section 2: dw/dt = eps w dF/dw with F of eq. 1 and S
+// of eq. 2, the priors held fixed; exp law w exp(eps dt G) or Euler w (1 + eps
+// dt G)), from the kernel entries of its stored bins and the update table;
+// accumulates the statistics of w(n) and stores the prior a refresh step used.
+template <int NB, uint64_t SIG, typename T, typename PT>
+__device__ __forceinline__ T weight_update(const StepArgs<T, PT>& a, const Blk<T>& B, Acc& acc, int64_t p, T vy, T vz,
+                                           T w, T what_p, const uint16_t (&tg)[kMaxBin + 1], uint32_t fl) {
+    const Layout<T>& L = a.lay;
+    const LayoutView<SIG, T> V{L};
+    const int nbin = V.nbin();
+    const T vl = vy * L.sini + vz * L.cosi;
+    T chi = T(0);
+    #pragma unroll
+    for (int b = 0; b < NB; ++b) {
+        if (b >= nbin) break;
+        const int k = tg[b];
+        if (k == kNoBin) continue;
+        const int base = L.b[b].off + k;
+        const int nmom = V.nmom(b), mom = V.mom(b);
+        #pragma unroll
+        for (int mm = 0; mm < 3; ++mm) {
+            if (mm >= nmom) break;
+            chi += moment_value<T>((mom >> (2 * mm)) & 3, vl) * B.cl[base + mm * L.b[b].nb];
+        }
+    }
+    const uint32_t wm = (fl >> kWhatShift) & 3u;
+    const T wh = wm == 0 ? B.wflat : (wm == 3 ? what_p : B.cm[tg[kMaxBin]]);
+    const T lr = dlog(w / wh);
+    const T G = -chi - a.mu * (lr + T(1));
+    const T edt = a.eps * a.dt;
+    const T wn = (fl & kExpLaw) ? w * dexp(edt * G) : w * (T(1) + edt * G);
+    acc.S -= double(w) * double(lr);
+    acc.W += double(w);
+    acc.W2 += double(w) * double(w);
+    acc.mn = fmin(acc.mn, double(w));
+    if (!(wn == wn) || wn == T(INFINITY) || wn == T(-INFINITY)) acc.bad |= 2u;   // non-finite
+    else if (!(wn > T(0))) acc.bad |= 1u;                                        // w <= 0
+    if (wm == 2) a.what[p] = wh;   // a refresh step stores the prior it used
+    return wn;
+}
+
+}  // namespace m2m

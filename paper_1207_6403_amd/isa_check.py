@@ -1,6 +1,7 @@
-"""Development-tree check of the built gfx950 code object: fail the build if the
+"""Development-tree check of the built gfx950 code objects: fail the build if the
 compiler emitted any scalar-cache write (scalar stores, scalar atomics, scalar
-cache write-back or discard).  Reads only code built here from source."""
+cache write-back or discard).  Takes the object files of the build (one device
+code bundle each).  Reads only code built here from source."""
 import os
 import re
 import subprocess
@@ -13,10 +14,14 @@ BAD = re.compile(r"\b(s_store_\w+|s_buffer_store\w*|s_atomic_\w+|s_buffer_atomic
 
 
 def check(lib):
+    heads = subprocess.run([os.path.join(LLVM, "llvm-objdump"), "-h", lib], stdout=subprocess.PIPE, text=True,
+                           check=True).stdout
+    if ".hip_fatbin" not in heads:
+        return 0   # host code only
     with tempfile.TemporaryDirectory() as d:
         fat = os.path.join(d, "fatbin")
         subprocess.check_call([os.path.join(LLVM, "llvm-objcopy"), "--dump-section", ".hip_fatbin=" + fat, lib,
-                               os.path.join(d, "copy.so")])
+                               os.path.join(d, "copy.o")])
         co = os.path.join(d, "gfx950.co")
         subprocess.check_call([os.path.join(LLVM, "clang-offload-bundler"), "--unbundle", "--type=o",
                                "--targets=hipv4-amdgcn-amd-amdhsa--gfx950", "--input=" + fat, "--output=" + co])
@@ -32,4 +37,5 @@ def check(lib):
 
 
 if __name__ == "__main__":
-    print("isa_check ok: %d instructions" % check(sys.argv[1]))
+    print("isa_check ok: %s instructions" % ", ".join(
+        "%s %d" % (os.path.basename(f), check(f)) for f in sys.argv[1:]))

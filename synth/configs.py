@@ -74,6 +74,8 @@ def cfg3(N=1 << 23, steps=2000, target_n=1 << 23):
               "potential": {"kind": "multipole", "G": 1.0, "lmax": 8, "nodes": 200,
                             "rmin": 1e-3, "rmax": 100.0, "Mtot": LOG_MASS_R10},
               "eps": EPS_CFG3})
+    # prior cells measured in the analytic potential the particles were drawn from
+    c["prior"] = dict(c["prior"], ref_potential=dict(LOG_POT))
     return c
 
 
