@@ -225,9 +225,9 @@ m2m_status m2m_observables(m2m_ctx *ctx, int32_t model, double *y, double *y_smo
 /* Current weights, N values in cfg precision. */
 m2m_status m2m_weights(m2m_ctx *ctx, void *w_out, int32_t device_ptr);
 
-/* Priors what_i the next step will use (N values, cfg precision, nullable)
- * and the cell table (n_models * ncell FP64 cell means, host, nullable;
- * HIST and MLP only). */
+/* Priors what_i the next step will use (N values, cfg precision, nullable;
+ * MLP: those of the last refresh) and the cell table (n_models * ncell FP64
+ * cell means, host, nullable; HIST and MLP only). */
 m2m_status m2m_priors(m2m_ctx *ctx, void *what_out, double *cell_mean, int32_t device_ptr);
 
 /* Current particles, 6 * N values SoA (same layout as m2m_create). */
@@ -246,6 +246,19 @@ m2m_status m2m_history(m2m_ctx *ctx, m2m_step_stats *out, int64_t max_rows, int6
  * phi_i) over the rest.  FP32 contexts sum per-block FP32 partials in FP64.
  * INVALID when the model is not a multipole. */
 m2m_status m2m_multipole_tables(m2m_ctx *ctx, double *A, double *B);
+
+/* State of an MLP prior (section 2.1: priors over integrals of motion that
+ * follow the weight distribution; here learned): theta gets the
+ * M2M_MLP_NPARAM FP32 parameters as of the last refresh (W1[64][3], b1[64],
+ * W2[64][64], b2[64], W3[64], b3), judge the w-weighted mean |ln what_mlp -
+ * ln what_hist| of the last refresh, used_fallback whether it exceeded the
+ * threshold (the histogram prior then applies until the next refresh),
+ * refreshes the count so far.  Every output is a host pointer and nullable.
+ * A refresh runs before the update of every step n with n % period == 0, on
+ * that step's state.  INVALID when the prior is not MLP.  The learned prior
+ * runs in FP32 contexts of one model (m2m_create: UNSUPPORTED otherwise);
+ * mlp_batch must be a multiple of 64 and divide mlp_subset. */
+m2m_status m2m_mlp_state(m2m_ctx *ctx, float *theta, double *judge, int32_t *used_fallback, int64_t *refreshes);
 
 /* Time candidate launch shapes (threads x ilp x blocks_per_cu) on trial_steps
  * steps each, restore the state, keep the fastest; chosen may be NULL.  The

@@ -93,6 +93,7 @@ def lib():
         L.or_cell.argtypes = [C.POINTER(Prior)] + [C.c_double] * 6
         L.or_cells.argtypes = [C.POINTER(Prior), C.c_int64] + [DP] * 6 + [C.POINTER(C.c_int32)]
         L.or_prior_means.argtypes = [C.POINTER(Prior), C.c_int64] + [DP] * 10
+        L.or_integrals.argtypes = [C.POINTER(Prior), C.c_int64] + [DP] * 10
         L.or_legendre.argtypes = [C.c_int, C.c_double, DP]
         L.or_mp_coeffs.argtypes = [C.POINTER(Pot), C.c_int64, DP, DP, DP, DP, DP, DP]
         L.or_mp_eval.argtypes = [C.POINTER(Pot), DP, DP, C.c_double, C.c_double, C.c_double, DP, DP, DP, DP]
@@ -289,6 +290,15 @@ class Model:
         out = np.zeros(self.c.N, dtype=np.int32)
         lib().or_cells(C.byref(self.c.prior), self.c.N, _dp(a["x"]), _dp(a["y"]), _dp(a["z"]),
                        _dp(a["vx"]), _dp(a["vy"]), _dp(a["vz"]), out.ctypes.data_as(C.POINTER(C.c_int32)))
+        return out
+
+    def integrals(self):
+        """E, |L|, Lz, Lc(E) of every particle in the prior's reference potential."""
+        a = self.arr
+        N = self.c.N
+        out = [np.empty(N) for _ in range(4)]
+        lib().or_integrals(C.byref(self.c.prior), N, _dp(a["x"]), _dp(a["y"]), _dp(a["z"]),
+                           _dp(a["vx"]), _dp(a["vy"]), _dp(a["vz"]), *[_dp(o) for o in out])
         return out
 
     def prior_means(self):

@@ -264,6 +264,23 @@ int or_cell(const or_prior *P, double x, double y, double z,
 
 int64_t or_ncell(const or_prior *P) { return (int64_t)P->n[0] * P->n[1] * P->n[2]; }
 
+/* The integrals of motion the priors are computed over (section 2.1): E, |L|,
+ * Lz and Lc(E), in the prior's reference potential, for every particle. */
+void or_integrals(const or_prior *P, int64_t N, const double *x, const double *y, const double *z,
+                  const double *vx, const double *vy, const double *vz,
+                  double *E, double *L, double *Lz, double *Lc) {
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < N; ++i) {
+        double phi, ax, ay, az;
+        or_potential(&P->ref, x[i], y[i], z[i], &phi, &ax, &ay, &az);
+        E[i] = 0.5 * (vx[i] * vx[i] + vy[i] * vy[i] + vz[i] * vz[i]) + phi;
+        double Lx = y[i] * vz[i] - z[i] * vy[i], Ly = z[i] * vx[i] - x[i] * vz[i];
+        Lz[i] = x[i] * vy[i] - y[i] * vx[i];
+        L[i] = sqrt(Lx * Lx + Ly * Ly + Lz[i] * Lz[i]);
+        Lc[i] = or_circular_L(&P->ref, E[i]);
+    }
+}
+
 /* Cell index of every particle. */
 void or_cells(const or_prior *P, int64_t N, const double *x, const double *y, const double *z,
               const double *vx, const double *vy, const double *vz, int32_t *cell) {

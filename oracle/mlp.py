@@ -86,3 +86,61 @@ def priors(theta, u, w):
 def judge(w, what_mlp, what_hist):
     """w-weighted mean |ln what_mlp - ln what_hist| (fallback test)."""
     return float(np.sum(w * np.abs(np.log(what_mlp) - np.log(what_hist))) / np.sum(w))
+
+
+class LearnedPrior:
+    """The learned moving prior of one model over a run (reading of section 2.1):
+    every `period` steps, at refresh q = n / period, before the step's update,
+      1. a sample of `subset` particle indices, Philox4x32-10 counter (k/4, q, 0, 0)
+         under key (seed, 0), index = (word * N) >> 32 (the oracle's subset());
+      2. Adam on the sample in consecutive minibatches of `batch`, with the
+         moments and the step count carried over from earlier refreshes, on the
+         mean squared error of g(u_i) - ln w_i at the current weights;
+      3. what_i = s exp(g(u_i)) over all particles, sum what = sum w;
+      4. the judge against the histogram prior on the same cells (the mean weight
+         of each particle's cell): above `fallback` the histogram prior is used.
+    The priors are held until the next refresh."""
+
+    def __init__(self, theta0, lr, beta1, beta2, eps, seed, subset, batch, fallback):
+        self.theta = np.asarray(theta0, dtype=np.float64).copy()
+        self.m = np.zeros_like(self.theta)
+        self.v = np.zeros_like(self.theta)
+        self.t = 0
+        self.lr, self.beta1, self.beta2, self.eps = lr, beta1, beta2, eps
+        self.seed, self.subset, self.batch, self.fallback = seed, subset, batch, fallback
+        self.last_judge = None
+        self.used_fallback = None
+
+    def refresh(self, q, idx, u, w, what_hist):
+        """One refresh: idx the sample (subset indices), u [N, 3] features, w the
+        weights, what_hist the histogram prior; returns the priors."""
+        tgt = np.log(w)
+        for b0 in range(0, self.subset, self.batch):
+            sl = idx[b0:b0 + self.batch]
+            _, g = loss_grad(self.theta, u[sl], tgt[sl])
+            self.t += 1
+            self.theta, self.m, self.v = adam(self.theta, g, self.m, self.v, self.t, self.lr, self.beta1,
+                                              self.beta2, self.eps)
+        what = priors(self.theta, u, w)
+        self.last_judge = judge(w, what, what_hist)
+        self.used_fallback = self.last_judge > self.fallback
+        return what_hist.copy() if self.used_fallback else what
+
+
+def run(model, lp, prior_cfg, nsteps, subset_fn):
+    """Run an oracle model (oracle.Model) nsteps with the learned prior lp:
+    refreshes at the steps n with n % period == 0.  subset_fn(seed, q, count, N)
+    gives the sample indices.  Returns the per-step statistics rows."""
+    P = int(prior_cfg.get("period", 1))
+    Emin, Emax = model.Erange
+    rows = []
+    for _ in range(nsteps):
+        n = model.step_index
+        if n % P == 0:
+            E, L, Lz, Lc = model.integrals()
+            u = features(E, L, Lz, Lc, Emin, Emax)
+            what_hist = model.prior_means()[0]
+            idx = subset_fn(lp.seed, n // P, lp.subset, u.shape[0])
+            model.set_what(lp.refresh(n // P, idx, u, model.w, what_hist))
+        rows.append(model.run(1)[0])
+    return np.array(rows)

@@ -105,6 +105,8 @@ def lib():
         L.m2m_particles.argtypes = [CTX, VP, C.c_int32]
         L.m2m_history.argtypes = [CTX, C.POINTER(m2m_step_stats), C.c_int64, C.POINTER(C.c_int64)]
         L.m2m_multipole_tables.argtypes = [CTX, C.POINTER(C.c_double), C.POINTER(C.c_double)]
+        L.m2m_mlp_state.argtypes = [CTX, C.POINTER(C.c_float), C.POINTER(C.c_double), C.POINTER(C.c_int32),
+                                    C.POINTER(C.c_int64)]
         L.m2m_autotune.argtypes = [CTX, C.c_int32, C.POINTER(m2m_launch)]
         L.m2m_get_launch.argtypes = [CTX, C.POINTER(m2m_launch)]
         L.m2m_set_launch.argtypes = [CTX, C.POINTER(m2m_launch)]
@@ -114,7 +116,7 @@ def lib():
         L.m2m_last_error.argtypes = [CTX]
         L.m2m_last_error.restype = C.c_char_p
         for f in ("m2m_create", "m2m_step", "m2m_observables", "m2m_weights", "m2m_priors", "m2m_particles",
-                  "m2m_history", "m2m_multipole_tables", "m2m_autotune", "m2m_get_launch", "m2m_set_launch", "m2m_kernel_time"):
+                  "m2m_history", "m2m_multipole_tables", "m2m_mlp_state", "m2m_autotune", "m2m_get_launch", "m2m_set_launch", "m2m_kernel_time"):
             getattr(L, f).restype = C.c_int
         if L.m2m_abi_version() != ABI_VERSION:
             raise ImportError("libm2m_hip.so ABI %d, binding expects %d" % (L.m2m_abi_version(), ABI_VERSION))
@@ -350,6 +352,18 @@ def m2m_multipole_tables(ctx, nnode, lmax):
     B = np.empty((nnode, nlm))
     _check(lib().m2m_multipole_tables(ctx.ptr, _dp(A), _dp(B)), ctx)
     return A, B
+
+
+def m2m_mlp_state(ctx):
+    """Learned prior: parameters (float32 [4481]), last judge value, whether the
+    histogram fallback applies, refreshes so far."""
+    th = np.empty(MLP_NPARAM, dtype=np.float32)
+    j = C.c_double()
+    fb = C.c_int32()
+    nr = C.c_int64()
+    _check(lib().m2m_mlp_state(ctx.ptr, th.ctypes.data_as(C.POINTER(C.c_float)), C.byref(j), C.byref(fb),
+                               C.byref(nr)), ctx)
+    return {"theta": th, "judge": j.value, "used_fallback": bool(fb.value), "refreshes": nr.value}
 
 
 def _launch_dict(L):

@@ -169,7 +169,21 @@ static m2m_status validate(const m2m_config* cfg, const m2m_obs_layout* lay, con
             return fail(nullptr, M2M_ERR_UNSUPPORTED, "prior reference potential must be the model potential here");
         }
     }
-    if (P.kind == M2M_PRIOR_MLP) return fail(nullptr, M2M_ERR_UNSUPPORTED, "learned prior not available in this build");
+    if (P.kind == M2M_PRIOR_MLP) {
+        if (!P.mlp_init) return fail(nullptr, M2M_ERR_INVALID, "learned prior needs mlp_init");
+        if (P.mlp_batch < kMlpTrainThreads || P.mlp_batch % kMlpTrainThreads || P.mlp_subset < P.mlp_batch ||
+            P.mlp_subset % P.mlp_batch)
+            return fail(nullptr, M2M_ERR_INVALID, "mlp_batch must be a multiple of 64 and divide mlp_subset");
+        if (!(P.lr > 0) || !(P.beta1 >= 0 && P.beta1 < 1) || !(P.beta2 >= 0 && P.beta2 < 1) || !(P.adam_eps >= 0) ||
+            !(P.fallback >= 0))
+            return fail(nullptr, M2M_ERR_INVALID, "learned prior needs lr > 0, 0 <= beta < 1, adam_eps >= 0, fallback >= 0");
+        for (int k = 0; k < M2M_MLP_NPARAM; ++k)
+            if (!is_fin(P.mlp_init[k])) return fail(nullptr, M2M_ERR_INVALID, "mlp_init must be finite");
+        if (cfg->n_models != 1) return fail(nullptr, M2M_ERR_UNSUPPORTED, "the learned prior runs on one model per context");
+        if (cfg->precision != M2M_F32) return fail(nullptr, M2M_ERR_UNSUPPORTED, "the learned prior runs in FP32 contexts");
+        if (cfg->model_offsets[1] >= ((int64_t)1 << 32))
+            return fail(nullptr, M2M_ERR_UNSUPPORTED, "the learned prior samples at most 2^32 particles");
+    }
     if (kind == M2M_POT_MULTIPOLE && cfg->n_models != 1)
         return fail(nullptr, M2M_ERR_UNSUPPORTED, "a multipole model runs alone in its context");
     *N_out = cfg->model_offsets[cfg->n_models];
@@ -277,9 +291,10 @@ static m2m_status make_plan(m2m_ctx* c, int threads, int ilp, int bpc) {
     // LDS of the fused kernel: histograms, cell sums/counts, update table,
     // cell means, edges, reduction scratch, Lc table
     const size_t ts = tsize(c);
-    const int NCe = (c->NC + 1) & ~1, NE = (c->nedge + 1) & ~1;
-    const int NET = (ts == 4 && c->NC) ? kLcE : 0;
-    p.lds = 8 * ((size_t)c->JP + c->NC + NE + 64 + NET) + 4 * (size_t)NCe + ts * ((size_t)c->JP + NCe + NE + kLcTab);
+    const int NCk = c->cells_apart ? 0 : c->NC;   // cells the fused kernel holds
+    const int NCe = (NCk + 1) & ~1, NE = (c->nedge + 1) & ~1;
+    const int NET = (ts == 4 && NCk) ? kLcE : 0;
+    p.lds = 8 * ((size_t)c->JP + NCk + NE + 64 + NET) + 4 * (size_t)NCe + ts * ((size_t)c->JP + NCe + NE + kLcTab);
     p.lds = (p.lds + 15) & ~(size_t)15;
     if (p.lds > (size_t)c->max_lds)
         return fail(c, M2M_ERR_UNSUPPORTED, "layout needs " + std::to_string(p.lds) + " bytes of LDS per block (max " +
@@ -371,6 +386,11 @@ static void fill_step_args(m2m_ctx* c, StepArgs<T, T>& a, int parity, int mode, 
     a.dt = (T)c->dt;
     a.eps = (T)c->eps;
     a.mu = (T)c->mu;
+    if (c->cells_apart) {
+        // the cells are accumulated by their own kernel (launch_cells_after)
+        a.cells.ncell = 0;
+        accum = 0;
+    }
     a.flags = (mode == 1 ? kObserve : 0u) | ((uint32_t)what_mode << kWhatShift) | (accum ? kAccum : 0u) |
               (c->update == 1 ? kExpLaw : 0u) | (c->frozen ? kFrozen : 0u);
     a.cellrow = c->lay.nbin;
@@ -418,7 +438,7 @@ static void prior_modes(const m2m_ctx* c, int64_t n, int* what_mode, int* accum)
     if (c->prior.kind == M2M_PRIOR_FLAT) { *what_mode = 0; *accum = 0; }
     else if (c->prior.kind == M2M_PRIOR_HIST && P == 1) { *what_mode = 1; *accum = 1; }
     else if (c->prior.kind == M2M_PRIOR_HIST) { *what_mode = (n % P == 0) ? 2 : 3; *accum = ((n + 1) % P == 0); }
-    else { *what_mode = 3; *accum = 0; }
+    else { *what_mode = 3; *accum = ((n + 1) % P == 0); }   // learned: refreshed before step n when n % P == 0
 }
 
 // Multipole kernel arguments; src is the state buffer the coefficient and
@@ -465,6 +485,54 @@ static void fill_mp_args(const m2m_ctx* c, MpArgs<T>& mp, const void* src) {
     mp.flag = c->flag;
 }
 
+// When the cells are kept apart: the cells of the state in buffer k, after the
+// fused kernel has observed it.
+template <typename T>
+static hipError_t launch_cells_after(m2m_ctx* c, int k) {
+    if constexpr (sizeof(T) == 4) {
+        StepArgs<float, float> a;
+        fill_step_args<float>(c, a, k ^ 1, 1, 0, 1);
+        a.out = (float*)c->state[k];
+        a.cells = c->cells;
+        return launch_cells(a, c->pot_kind, c->plan.nblock, c->cells_lds, c->stream);
+    }
+    return hipSuccess;
+}
+
+// Learned-prior kernel arguments for the refresh before step n (state n).
+static void fill_mlp_args(const m2m_ctx* c, MlpArgs& a, int64_t n) {
+    const m2m_prior& P = c->prior;
+    a.state = (const float*)c->state[n & 1];
+    a.stride = c->stride;
+    a.n = c->N;
+    a.ex = exact_tables(c);
+    a.lcE0 = c->lce_host[0];
+    a.lcEinv = c->lce_host[1];
+    a.Emin = c->erange_host[0];
+    a.Emax = c->erange_host[1];
+    a.seed = P.seed;
+    a.q = (uint32_t)(n / P.period);
+    a.subset = P.mlp_subset;
+    a.batch = P.mlp_batch;
+    a.sub = c->mlp_sub;
+    a.theta = c->mlp_theta;
+    a.adam_m = c->mlp_m;
+    a.adam_v = c->mlp_v;
+    a.gpart = c->mlp_gpart;
+    a.lr = (float)P.lr;
+    a.beta1 = (float)P.beta1;
+    a.beta2 = (float)P.beta2;
+    a.adam_eps = (float)P.adam_eps;
+    a.fallback = P.fallback;
+    a.what = (float*)c->what;
+    a.cellmean = (const float*)c->cellmean;
+    a.cellrow = c->lay.nbin;
+    a.nblk = c->mlp_nblk;
+    a.red = c->mlp_red;
+    a.stats = c->mlp_stats;
+    a.flag = c->flag;
+}
+
 template <typename T>
 static hipError_t launch_one_T(m2m_ctx* c, int64_t n, hipEvent_t e0, hipEvent_t e1) {
     int wm, acc;
@@ -472,6 +540,16 @@ static hipError_t launch_one_T(m2m_ctx* c, int64_t n, hipEvent_t e0, hipEvent_t 
     StepArgs<T, T> a;
     fill_step_args<T>(c, a, (int)(n & 1), 0, wm, acc);
     const Plan& p = c->plan;
+    if constexpr (sizeof(T) == 4) {
+        if (c->prior.kind == M2M_PRIOR_MLP && n % c->prior.period == 0) {
+            // learned prior: refresh on state n before its update
+            MlpArgs m;
+            fill_mlp_args(c, m, n);
+            const hipError_t e = launch_mlp_refresh(m, c->pot_kind, (int)c->mlp_t, c->stream);
+            if (e != hipSuccess) return e;
+            c->mlp_t += c->prior.mlp_subset / c->prior.mlp_batch;
+        }
+    }
     if (e0) (void)hipEventRecord(e0, c->stream);
     hipError_t e;
     if (c->mp) {
@@ -491,6 +569,7 @@ static hipError_t launch_one_T(m2m_ctx* c, int64_t n, hipEvent_t e0, hipEvent_t 
     }
     if (e1) (void)hipEventRecord(e1, c->stream);
     if (e != hipSuccess) return e;
+    if (c->cells_apart && acc && (e = launch_cells_after<T>(c, (int)((n + 1) & 1))) != hipSuccess) return e;
     FinArgs<T, T> f;
     fill_fin_args<T>(c, f, 0, acc, (int)(n & 1));
     return launch_finalize<T, T>(f, c->stream);
@@ -502,13 +581,14 @@ static hipError_t launch_one(m2m_ctx* c, int64_t n, hipEvent_t e0 = nullptr, hip
 
 template <typename T>
 static hipError_t launch_prologue_T(m2m_ctx* c) {
-    const int accum = c->prior.kind == M2M_PRIOR_HIST ? 1 : 0;
+    const int accum = c->prior.kind != M2M_PRIOR_FLAT ? 1 : 0;
     StepArgs<T, T> a;
     fill_step_args<T>(c, a, (int)(c->step & 1), 1, 0, accum);
     a.out = (T*)c->state[c->step & 1];   // observing only: the tags of the current state are written
     const Plan& p = c->plan;
     hipError_t e = launch_step<T, T>(a, c->pot_kind, c->sig, c->lay.nbin, p.ilp, p.nblock, p.threads, p.lds, c->stream);
     if (e != hipSuccess) return e;
+    if (c->cells_apart && accum && (e = launch_cells_after<T>(c, (int)(c->step & 1))) != hipSuccess) return e;
     FinArgs<T, T> f;
     // the prologue's chi^2 shares are those of "step -1"
     fill_fin_args<T>(c, f, 1, accum, 1);
@@ -700,6 +780,7 @@ static double host_lc(const m2m_potential& q, double E, double* rc = nullptr) {
 template <typename T>
 static m2m_status build_lc_etab(m2m_ctx* c, const std::vector<double>& er) {
     std::vector<float> tab(2 * (size_t)kLcE * c->M, 0.0f), rce((size_t)kLcE * c->M, 0.0f);
+    c->lce_host.assign(2 * (size_t)c->M, 0.0f);
     std::vector<unsigned char> pots(sizeof(Pot<T>) * c->M);
     HIPCHK(c, hipMemcpy(pots.data(), c->pots_d, pots.size(), hipMemcpyDeviceToHost));
     for (int m = 0; m < c->M && c->prior.kind != M2M_PRIOR_FLAT; ++m) {
@@ -737,6 +818,8 @@ static m2m_status build_lc_etab(m2m_ctx* c, const std::vector<double>& er) {
         std::memcpy(&p, pots.data() + sizeof(Pot<T>) * m, sizeof(p));
         p.lcE0 = (T)lo;
         p.lcEinv = (T)(1.0 / h);
+        c->lce_host[2 * m] = (float)lo;
+        c->lce_host[2 * m + 1] = (float)(1.0 / h);
         std::memcpy(pots.data() + sizeof(Pot<T>) * m, &p, sizeof(p));
     }
     HIPCHK(c, hipMemcpy(c->pots_d, pots.data(), pots.size(), hipMemcpyHostToDevice));
@@ -776,6 +859,18 @@ static m2m_status create_T(m2m_ctx* c, const m2m_target* tg, const void* xv, con
     HIPCHK(c, hipMemcpy((T*)c->state[0] + 6 * S, hw.data(), sizeof(T) * N, hipMemcpyHostToDevice));
     if (c->prior.kind != M2M_PRIOR_FLAT && (c->prior.period > 1 || c->prior.kind == M2M_PRIOR_MLP))
         if ((s = dalloc(c, (T**)&c->what, (size_t)S))) return s;
+    if (c->prior.kind == M2M_PRIOR_MLP) {
+        const m2m_prior& P = c->prior;
+        c->mlp_nblk = (int)std::min<int64_t>(kMlpMaxInferBlocks, (N + kMlpInferThreads - 1) / kMlpInferThreads);
+        if ((s = upload(c, &c->mlp_theta, c->mlp_init_host)) || (s = dalloc(c, &c->mlp_m, (size_t)kMlpNP)) ||
+            (s = dalloc(c, &c->mlp_v, (size_t)kMlpNP)) || (s = dalloc(c, &c->mlp_sub, (size_t)P.mlp_subset)) ||
+            (s = dalloc(c, &c->mlp_gpart, (size_t)(P.mlp_batch / kMlpTrainThreads) * kMlpNP)) ||
+            (s = dalloc(c, &c->mlp_red, 2 * (size_t)c->mlp_nblk)) || (s = dalloc(c, &c->mlp_stats, 8)))
+            return s;
+        HIPCHK(c, hipMemset(c->mlp_m, 0, sizeof(float) * kMlpNP));
+        HIPCHK(c, hipMemset(c->mlp_v, 0, sizeof(float) * kMlpNP));
+        HIPCHK(c, hipMemset(c->mlp_stats, 0, sizeof(double) * 8));
+    }
     // tables (particle precision, and FP64 for the exact decisions)
     std::vector<unsigned char> pots, pots64;
     std::vector<T> lctab;
@@ -943,6 +1038,7 @@ extern "C" m2m_status m2m_create(const m2m_config* cfg, const m2m_obs_layout* la
     c->pot_kind = c->pots[0].kind;
     c->prior = cfg->prior;
     c->prior.Erange = nullptr;
+    if (cfg->prior.kind == M2M_PRIOR_MLP) c->mlp_init_host.assign(cfg->prior.mlp_init, cfg->prior.mlp_init + M2M_MLP_NPARAM);
     c->prior.mlp_init = nullptr;
     c->lay = *layout;
     for (int b = 0; b < layout->nbin; ++b) {
@@ -978,6 +1074,19 @@ extern "C" m2m_status m2m_create(const m2m_config* cfg, const m2m_obs_layout* la
     c->launch.graph_steps = 0;
     c->launch.timing = 0;
     const size_t lds_need = 160 * 1024;
+    if (c->prior.kind == M2M_PRIOR_MLP) {
+        // the learned prior's judge grid is accumulated by the cell kernel
+        const int NCe = (c->NC + 1) & ~1;
+        c->cells_apart = true;
+        c->cells_lds = 8 * (size_t)c->NC + 8 * (size_t)kLcE + 4 * (size_t)NCe;
+        if (c->cells_lds > (size_t)c->max_lds) {
+            const std::string why = "prior grid of " + std::to_string(c->NC) + " cells needs " +
+                                    std::to_string(c->cells_lds) + " bytes of LDS (max " + std::to_string(c->max_lds) + ")";
+            m2m_destroy(c);
+            return fail(nullptr, M2M_ERR_UNSUPPORTED, why);
+        }
+        (void)set_cells_lds_limit(lds_need);
+    }
     if (c->prec == M2M_F64) {
         (void)set_step_lds_limit<double, double>(c->pot_kind, lds_need);
         if (c->mp) (void)set_mp_lds_limit<double, double>(lds_need);
@@ -1225,6 +1334,22 @@ extern "C" m2m_status m2m_multipole_tables(m2m_ctx* c, double* A, double* B) {
     return M2M_OK;
 }
 
+// ------------------------------------------------------------ learned prior
+extern "C" m2m_status m2m_mlp_state(m2m_ctx* c, float* theta, double* judge, int32_t* used_fallback,
+                                    int64_t* refreshes) {
+    if (!c) return fail(nullptr, M2M_ERR_INVALID, "ctx is NULL");
+    if (c->prior.kind != M2M_PRIOR_MLP) return fail(c, M2M_ERR_INVALID, "the context has no learned prior");
+    if (c->status == M2M_ERR_DEVICE) return c->status;
+    double st[8];
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, hipMemcpy(st, c->mlp_stats, sizeof(st), hipMemcpyDeviceToHost));
+    if (theta) HIPCHK(c, hipMemcpy(theta, c->mlp_theta, sizeof(float) * kMlpNP, hipMemcpyDeviceToHost));
+    if (judge) *judge = st[4];
+    if (used_fallback) *used_fallback = st[5] != 0.0;
+    if (refreshes) *refreshes = (int64_t)st[6];
+    return M2M_OK;
+}
+
 // ------------------------------------------------------------- launch shape
 extern "C" m2m_status m2m_get_launch(const m2m_ctx* c, m2m_launch* out) {
     if (!c || !out) return M2M_ERR_INVALID;
@@ -1287,6 +1412,12 @@ static m2m_status snapshot(m2m_ctx* c, Snapshot& s, bool restore) {
                                {c->cellmean, MC * ts}, {c->cellmean64, MC * 8}, {c->chunk_chi, 4 * (size_t)c->nchunk * 8},
                                {c->ring, sizeof(StatRow) * (size_t)c->M * kRing}, {c->d_step, 16}};
     if (c->what) items.push_back({c->what, (size_t)c->stride * ts});
+    if (c->mlp_theta) {
+        items.push_back({c->mlp_theta, sizeof(float) * kMlpNP});
+        items.push_back({c->mlp_m, sizeof(float) * kMlpNP});
+        items.push_back({c->mlp_v, sizeof(float) * kMlpNP});
+        items.push_back({c->mlp_stats, sizeof(double) * 8});
+    }
     if (c->mp) {
         const size_t nn = c->mp_pot.nnode, nlm = (size_t)(c->mp_pot.lmax + 1) * (c->mp_pot.lmax + 1);
         items.push_back({c->mp_tab, nn * (ts == 4 ? kMpRowF : kMpW) * ts});
@@ -1365,7 +1496,7 @@ extern "C" m2m_status m2m_autotune(m2m_ctx* c, int32_t trial_steps, m2m_launch* 
     if (!cache_lookup(key, &best)) {
         Snapshot snap;
         if (m2m_status s = snapshot(c, snap, false)) return s;
-        const int64_t step0 = c->step;
+        const int64_t step0 = c->step, mlp_t0 = c->mlp_t;
         double best_ms = INFINITY;
         std::vector<int> threads = c->prec == M2M_F64 ? std::vector<int>{64, 128, 256} : std::vector<int>{256, 512, 1024};
         hipEvent_t e0, e1;
@@ -1398,12 +1529,14 @@ extern "C" m2m_status m2m_autotune(m2m_ctx* c, int32_t trial_steps, m2m_launch* 
                     if (!flag && ms < best_ms) { best_ms = ms; best = L; }
                     if ((err = snapshot(c, snap, true))) goto done;
                     c->step = step0;
+                    c->mlp_t = mlp_t0;
                 }
     done:
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
         for (auto& b : snap.bufs) (void)hipFree(b.second);
         c->step = step0;
+        c->mlp_t = mlp_t0;
         if (err) return err;
         cache_store(key, best);
     }

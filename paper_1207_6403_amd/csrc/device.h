@@ -285,22 +285,22 @@ __device__ __forceinline__ int prior_cell_f64(const Pot<double>& p, const double
     return cell_index(c, Emin, Emax, E, L, Lz, circular_L<POT, double, 5>(p, tab, E));
 }
 
-// Cell of the moving prior in FP64 for a decision the FP32 path left open.
-// Lc(E) from Newton steps on E_c(r) = E seeded by the tabulated ln r_c(E)
+// E, |L|, Lz and Lc(E) in FP64, the integrals of motion the priors are computed
+// over.  Lc(E) from Newton steps on E_c(r) = E seeded by the tabulated ln r_c(E)
 // (uniform in E from E0 with 1/spacing invh; the seed is good to about 1e-6, so
 // three steps reach FP64 precision), the Hernquist closed form, or the
 // circular-orbit table (gtab, device memory) outside the seed table.
 template <int POT>
-__device__ __forceinline__ int prior_cell_seeded(const Pot<double>& p, const double* __restrict__ gtab,
-                                              const float* __restrict__ rce, double E0, double invh, const Cells& c,
-                                              double Emin, double Emax, double x, double y, double z, double vx,
-                                              double vy, double vz) {
+__device__ __forceinline__ void integrals_seeded(const Pot<double>& p, const double* __restrict__ gtab,
+                                                 const float* __restrict__ rce, double E0, double invh, double x,
+                                                 double y, double z, double vx, double vy, double vz, double& E,
+                                                 double& L, double& Lz, double& Lc) {
     double phi, ax, ay, az;
     potential<POT, double>(p, x, y, z, phi, ax, ay, az);
-    const double E = 0.5 * (vx * vx + vy * vy + vz * vz) + phi;
-    const double Lx = y * vz - z * vy, Ly = z * vx - x * vz, Lz = x * vy - y * vx;
-    const double L = sqrt(Lx * Lx + Ly * Ly + Lz * Lz);
-    double Lc;
+    E = 0.5 * (vx * vx + vy * vy + vz * vz) + phi;
+    const double Lx = y * vz - z * vy, Ly = z * vx - x * vz;
+    Lz = x * vy - y * vx;
+    L = sqrt(Lx * Lx + Ly * Ly + Lz * Lz);
     const double t = (E - E0) * invh;
     if (POT == 0 || !(t >= 0.0) || !(t < double(kLcE - 1))) {
         Lc = circular_L<POT, double, 5>(p, gtab, E);
@@ -317,6 +317,16 @@ __device__ __forceinline__ int prior_cell_seeded(const Pot<double>& p, const dou
         radial_derivs<POT, double>(p, r, ph, d1, d2);
         Lc = r * sqrt(r * d1);
     }
+}
+
+// Cell of the moving prior in FP64 for a decision the FP32 path left open.
+template <int POT>
+__device__ __forceinline__ int prior_cell_seeded(const Pot<double>& p, const double* __restrict__ gtab,
+                                              const float* __restrict__ rce, double E0, double invh, const Cells& c,
+                                              double Emin, double Emax, double x, double y, double z, double vx,
+                                              double vy, double vz) {
+    double E, L, Lz, Lc;
+    integrals_seeded<POT>(p, gtab, rce, E0, invh, x, y, z, vx, vy, vz, E, L, Lz, Lc);
     return cell_index(c, Emin, Emax, E, L, Lz, Lc);
 }
 

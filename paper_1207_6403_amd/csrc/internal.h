@@ -39,6 +39,7 @@ struct m2m_ctx {
     m2m_obs_layout lay{};
     std::vector<double> edges_host[M2M_MAX_BINNINGS];
     std::vector<double> erange_host;
+    std::vector<float> lce_host;   // per model: origin and inverse spacing of the uniform-E tables
     int64_t N = 0, stride = 0;
     int J = 0, JP = 0, NC = 0, pcols = 0, nedge = 0;
     alignas(16) unsigned char lay_bytes[sizeof(m2m::Layout<double>)] = {};
@@ -63,6 +64,22 @@ struct m2m_ctx {
     int64_t mp_R = 0;
     int mp_maxchunk = 0;
     m2m::MpLds mp_lds{};
+    // learned prior (FP32, one model): parameters and Adam moments, samples,
+    // partial gradients, inference partials and statistics, Adam steps taken
+    std::vector<float> mlp_init_host;
+    float* mlp_theta = nullptr;
+    float* mlp_m = nullptr;
+    float* mlp_v = nullptr;
+    float4* mlp_sub = nullptr;
+    float* mlp_gpart = nullptr;
+    double* mlp_red = nullptr;
+    double* mlp_stats = nullptr;
+    int mlp_nblk = 0;
+    int64_t mlp_t = 0;
+    // prior cells accumulated by a kernel of their own (the fused kernel then
+    // observes without them): its LDS bytes
+    bool cells_apart = false;
+    size_t cells_lds = 0;
     m2m::Cells cells{};
     // device
     hipStream_t stream = nullptr;

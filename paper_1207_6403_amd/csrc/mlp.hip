@@ -1,0 +1,332 @@
+// mlp.hip -- the learned moving prior (section 2.1: priors that follow the
+// structure of the weight distribution over integrals of motion, here a smooth
+// function of them fitted to the weights).
+//
+// Every `period` steps, before the step's update, one refresh runs
+//   mlp_subset    a Philox4x32-10 sample of the particles: features
+//                 u = (2 (E - Emin)/(Emax - Emin) - 1, 2 L/Lc(E) - 1, Lz/L) (FP64
+//                 integrals, FP32 features) and the target ln w
+//   mlp_train     per minibatch: forward and backward of each sample, the
+//                 block's gradient sums (64 samples per block)
+//   mlp_adam      the minibatch gradient (block sums in block order) and one Adam
+//                 step (Kingma & Ba 2015, Algorithm 1)
+//   mlp_infer     g(u) of every particle, per-block maxima
+//   mlp_norm      e = exp(g - max g), per-block sums of e and w
+//   mlp_judge     what = e sum w / sum e, per-block sums of w |ln what - ln what_hist|
+//   mlp_select    the histogram prior instead when the w-weighted mean exceeds
+//                 the fallback threshold
+// with single-block reductions of the per-block partials in between, in block
+// order (deterministic).
+#include "runtime.h"
+
+namespace m2m {
+
+// ------------------------------------------------------------ Philox4x32-10
+// Salmon, Moraes, Dror & Shaw (2011): ten rounds of two 32x32 -> 64-bit
+// multiplications on a 4-word counter under a 2-word key bumped by the Weyl
+// constants between rounds.
+__device__ __forceinline__ void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
+    #pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c[0], p1 = (uint64_t)0xCD9E8D57u * c[2];
+        const uint32_t hi0 = uint32_t(p0 >> 32), lo0 = uint32_t(p0), hi1 = uint32_t(p1 >> 32), lo1 = uint32_t(p1);
+        const uint32_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+        c[0] = n0; c[1] = lo1; c[2] = n2; c[3] = lo0;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+}
+
+// Features of the particle at row offset p of the state (FP64 integrals of the
+// FP32 coordinates), and its weight.
+template <int POT>
+__device__ __forceinline__ void mlp_features(const MlpArgs& a, int64_t p, float& u0, float& u1, float& u2, float& w) {
+    const float* s = a.state;
+    const int64_t S = a.stride;
+    const double x = s[p], y = s[S + p], z = s[2 * S + p], vx = s[3 * S + p], vy = s[4 * S + p], vz = s[5 * S + p];
+    w = s[6 * S + p];
+    const Exact* ex = a.ex;
+    double E, L, Lz, Lc;
+    integrals_seeded<POT>(ex->pots[0], ex->lctab, ex->rce, double(a.lcE0), double(a.lcEinv), x, y, z, vx, vy, vz, E, L,
+                          Lz, Lc);
+    u0 = float(2.0 * (E - a.Emin) / (a.Emax - a.Emin) - 1.0);
+    u1 = float(Lc > 0.0 ? 2.0 * L / Lc - 1.0 : -1.0);
+    u2 = float(L > 0.0 ? Lz / L : 0.0);
+}
+
+template <int POT>
+__global__ void __launch_bounds__(256) mlp_subset_kernel(MlpArgs a) {
+    if (*a.flag) return;
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= a.subset) return;
+    uint32_t c[4] = {uint32_t(k >> 2), a.q, 0u, 0u};
+    philox4x32_10(c, a.seed, 0u);
+    const uint32_t word = c[k & 3];
+    const int64_t p = int64_t(((uint64_t)word * (uint64_t)a.n) >> 32);
+    float u0, u1, u2, w;
+    mlp_features<POT>(a, p, u0, u1, u2, w);
+    a.sub[k] = make_float4(u0, u1, u2, logf(w));
+}
+
+// tanh(x) = 1 - 2 / (exp(2x) + 1), with the hardware exp and reciprocal: an
+// absolute error of a few 1e-7 over the whole line (+-1 in the limits), which
+// is what the units' sums see.
+__device__ __forceinline__ float unit_tanh(float x) {
+    return 1.0f - 2.0f * __builtin_amdgcn_rcpf(__expf(2.0f * x) + 1.0f);
+}
+
+// Forward pass of one sample with the parameters th in LDS: the first hidden
+// layer h1 (registers), the second layer's units one by one (to h2, an LDS row,
+// when given) and the output g.
+__device__ __forceinline__ float mlp_forward(const float* th, float u0, float u1, float u2, float (&h1)[kMlpH],
+                                             float* h2) {
+    #pragma unroll
+    for (int o = 0; o < kMlpH; ++o)
+        h1[o] = unit_tanh(th[kMlpB1 + o] + th[kMlpW1 + 3 * o] * u0 + th[kMlpW1 + 3 * o + 1] * u1 + th[kMlpW1 + 3 * o + 2] * u2);
+    float g = th[kMlpB3];
+    #pragma unroll 2
+    for (int o = 0; o < kMlpH; ++o) {
+        const float4* row = reinterpret_cast<const float4*>(th + kMlpW2 + kMlpH * o);
+        float acc = th[kMlpB2 + o];
+        #pragma unroll
+        for (int i = 0; i < kMlpH / 4; ++i) {
+            const float4 r = row[i];
+            acc += r.x * h1[4 * i] + r.y * h1[4 * i + 1] + r.z * h1[4 * i + 2] + r.w * h1[4 * i + 3];
+        }
+        const float t = unit_tanh(acc);
+        if (h2) h2[o] = t;
+        g += th[kMlpW3 + o] * t;
+    }
+    return g;
+}
+
+// Minibatch b: samples b*batch + blockIdx.x*64 + threadIdx.x.  Each thread runs
+// its sample forward and backward (loss (g - t)^2 averaged over the minibatch);
+// the block then sums the 64 samples' gradient terms: thread o takes row o of
+// W2 (and W1, b1, b2, W3), thread 0 also b3.
+__global__ void __launch_bounds__(kMlpTrainThreads) mlp_train_kernel(MlpArgs a, int b) {
+    __shared__ __align__(16) float th[kMlpNP + 3];
+    __shared__ float H1[kMlpTrainThreads][kMlpH + 1], H2[kMlpTrainThreads][kMlpH + 1];
+    __shared__ float D2[kMlpTrainThreads][kMlpH + 1], D1[kMlpTrainThreads][kMlpH + 1];
+    __shared__ float U[kMlpTrainThreads][4];
+    if (*a.flag) return;
+    const int tid = threadIdx.x;
+    for (int i = tid; i < kMlpNP; i += kMlpTrainThreads) th[i] = a.theta[i];
+    __syncthreads();
+    const float4 smp = a.sub[(size_t)b * a.batch + (size_t)blockIdx.x * kMlpTrainThreads + tid];
+    float h1[kMlpH];
+    const float g = mlp_forward(th, smp.x, smp.y, smp.z, h1, &H2[tid][0]);
+    const float dg = 2.0f * (g - smp.w) / float(a.batch);
+    // backward: d2 = dg W3 (1 - h2^2), d1 = (W2^T d2) (1 - h1^2)
+    float d1[kMlpH];
+    #pragma unroll
+    for (int i = 0; i < kMlpH; ++i) d1[i] = 0.0f;
+    #pragma unroll 2
+    for (int o = 0; o < kMlpH; ++o) {
+        const float h2o = H2[tid][o];
+        const float d2 = dg * th[kMlpW3 + o] * (1.0f - h2o * h2o);
+        D2[tid][o] = d2;
+        const float4* row = reinterpret_cast<const float4*>(th + kMlpW2 + kMlpH * o);
+        #pragma unroll
+        for (int i = 0; i < kMlpH / 4; ++i) {
+            const float4 r = row[i];
+            d1[4 * i] += r.x * d2;
+            d1[4 * i + 1] += r.y * d2;
+            d1[4 * i + 2] += r.z * d2;
+            d1[4 * i + 3] += r.w * d2;
+        }
+    }
+    #pragma unroll
+    for (int i = 0; i < kMlpH; ++i) {
+        H1[tid][i] = h1[i];
+        D1[tid][i] = d1[i] * (1.0f - h1[i] * h1[i]);
+    }
+    U[tid][0] = smp.x; U[tid][1] = smp.y; U[tid][2] = smp.z; U[tid][3] = dg;
+    __syncthreads();
+    // sums over the block's samples (in sample order)
+    const int o = tid;
+    float gw2[kMlpH];
+    #pragma unroll
+    for (int i = 0; i < kMlpH; ++i) gw2[i] = 0.0f;
+    float gb2 = 0.0f, gw3 = 0.0f, gb1 = 0.0f, gw10 = 0.0f, gw11 = 0.0f, gw12 = 0.0f, gb3 = 0.0f;
+    for (int s = 0; s < kMlpTrainThreads; ++s) {
+        const float d2 = D2[s][o], d1o = D1[s][o];
+        #pragma unroll
+        for (int i = 0; i < kMlpH; ++i) gw2[i] += d2 * H1[s][i];
+        gb2 += d2;
+        gw3 += U[s][3] * H2[s][o];
+        gb1 += d1o;
+        gw10 += d1o * U[s][0];
+        gw11 += d1o * U[s][1];
+        gw12 += d1o * U[s][2];
+        gb3 += U[s][3];
+    }
+    float* dst = a.gpart + (size_t)blockIdx.x * kMlpNP;
+    #pragma unroll
+    for (int i = 0; i < kMlpH; ++i) dst[kMlpW2 + kMlpH * o + i] = gw2[i];
+    dst[kMlpB2 + o] = gb2;
+    dst[kMlpW3 + o] = gw3;
+    dst[kMlpB1 + o] = gb1;
+    dst[kMlpW1 + 3 * o] = gw10;
+    dst[kMlpW1 + 3 * o + 1] = gw11;
+    dst[kMlpW1 + 3 * o + 2] = gw12;
+    if (o == 0) dst[kMlpB3] = gb3;
+}
+
+// One Adam step on the minibatch gradient (the blocks' sums added in block order
+// in FP64); c1 = 1 - beta1^t, c2 = 1 - beta2^t.
+__global__ void __launch_bounds__(256) mlp_adam_kernel(MlpArgs a, int nblk, float c1, float c2) {
+    if (*a.flag) return;
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= kMlpNP) return;
+    double gs = 0.0;
+    for (int k = 0; k < nblk; ++k) gs += double(a.gpart[(size_t)k * kMlpNP + j]);
+    const float g = float(gs);
+    const float m = a.beta1 * a.adam_m[j] + (1.0f - a.beta1) * g;
+    const float v = a.beta2 * a.adam_v[j] + (1.0f - a.beta2) * g * g;
+    a.adam_m[j] = m;
+    a.adam_v[j] = v;
+    a.theta[j] -= a.lr * (m / c1) / (sqrtf(v / c2) + a.adam_eps);
+}
+
+// Block partials of the inference passes: thread values reduced in a fixed tree.
+__device__ __forceinline__ double block_reduce(double v, bool is_max, double* sh) {
+    const int tid = threadIdx.x;
+    #pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const double u = __shfl_xor(v, o, 64);
+        v = is_max ? fmax(v, u) : v + u;
+    }
+    if ((tid & 63) == 0) sh[tid >> 6] = v;
+    __syncthreads();
+    double r = sh[0];
+    for (int k = 1; k < int(blockDim.x >> 6); ++k) r = is_max ? fmax(r, sh[k]) : r + sh[k];
+    __syncthreads();
+    return r;
+}
+
+template <int POT>
+__global__ void __launch_bounds__(kMlpInferThreads, 2) mlp_infer_kernel(MlpArgs a) {
+    __shared__ __align__(16) float th[kMlpNP + 3];
+    __shared__ double sh[kMlpInferThreads / 64];
+    if (*a.flag) return;
+    const int tid = threadIdx.x;
+    for (int i = tid; i < kMlpNP; i += blockDim.x) th[i] = a.theta[i];
+    __syncthreads();
+    double gmax = -INFINITY;
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + tid; p < a.n; p += (int64_t)gridDim.x * blockDim.x) {
+        float u0, u1, u2, w;
+        mlp_features<POT>(a, p, u0, u1, u2, w);
+        float h1[kMlpH];
+        // (the parameters are read from LDS for every particle rather than held
+        // in registers across the loop, which would leave one wave per SIMD)
+        const float g = mlp_forward(th + opaque(0u), u0, u1, u2, h1, nullptr);
+        a.what[p] = g;
+        gmax = fmax(gmax, double(g));
+    }
+    gmax = block_reduce(gmax, true, sh);
+    if (tid == 0) a.red[2 * blockIdx.x] = gmax;
+}
+
+__global__ void __launch_bounds__(kMlpInferThreads) mlp_norm_kernel(MlpArgs a) {
+    __shared__ double sh[kMlpInferThreads / 64];
+    if (*a.flag) return;
+    const float gmax = float(a.stats[0]);
+    const float* wrow = a.state + 6 * a.stride;
+    double se = 0.0, sw = 0.0;
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < a.n; p += (int64_t)gridDim.x * blockDim.x) {
+        const float e = expf(a.what[p] - gmax);
+        a.what[p] = e;
+        se += double(e);
+        sw += double(wrow[p]);
+    }
+    se = block_reduce(se, false, sh);
+    sw = block_reduce(sw, false, sh);
+    if (threadIdx.x == 0) {
+        a.red[2 * blockIdx.x] = sw;
+        a.red[2 * blockIdx.x + 1] = se;
+    }
+}
+
+__global__ void __launch_bounds__(kMlpInferThreads) mlp_judge_kernel(MlpArgs a) {
+    __shared__ double sh[kMlpInferThreads / 64];
+    if (*a.flag) return;
+    const float scale = float(a.stats[1] / a.stats[2]);
+    const float* wrow = a.state + 6 * a.stride;
+    const uint16_t* cell = reinterpret_cast<const uint16_t*>(a.state + 7 * a.stride) + (size_t)a.cellrow * a.stride;
+    double sj = 0.0;
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < a.n; p += (int64_t)gridDim.x * blockDim.x) {
+        const float what = a.what[p] * scale;
+        a.what[p] = what;
+        const float hist = a.cellmean[cell[p]];
+        sj += double(wrow[p]) * fabs(log(double(what)) - log(double(hist)));
+    }
+    sj = block_reduce(sj, false, sh);
+    if (threadIdx.x == 0) a.red[2 * blockIdx.x] = sj;
+}
+
+__global__ void __launch_bounds__(kMlpInferThreads) mlp_select_kernel(MlpArgs a) {
+    if (*a.flag || a.stats[5] == 0.0) return;
+    const uint16_t* cell = reinterpret_cast<const uint16_t*>(a.state + 7 * a.stride) + (size_t)a.cellrow * a.stride;
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < a.n; p += (int64_t)gridDim.x * blockDim.x)
+        a.what[p] = a.cellmean[cell[p]];
+}
+
+// Reductions of the per-block partials (one block, block order):
+//   0: stats[0] = max g;  1: stats[1] = sum w, stats[2] = sum e;
+//   2: stats[3] = sum w |ln what - ln what_hist|, stats[4] = its w-weighted mean,
+//      stats[5] = 1 when that exceeds the fallback threshold, stats[6] += 1.
+__global__ void __launch_bounds__(64) mlp_reduce_kernel(MlpArgs a, int mode) {
+    if (*a.flag) return;
+    if (threadIdx.x != 0) return;
+    if (mode == 0) {
+        double m = -INFINITY;
+        for (int k = 0; k < a.nblk; ++k) m = fmax(m, a.red[2 * k]);
+        a.stats[0] = m;
+    } else if (mode == 1) {
+        double sw = 0.0, se = 0.0;
+        for (int k = 0; k < a.nblk; ++k) { sw += a.red[2 * k]; se += a.red[2 * k + 1]; }
+        a.stats[1] = sw;
+        a.stats[2] = se;
+    } else {
+        double sj = 0.0;
+        for (int k = 0; k < a.nblk; ++k) sj += a.red[2 * k];
+        a.stats[3] = sj;
+        a.stats[4] = sj / a.stats[1];
+        a.stats[5] = a.stats[4] > a.fallback ? 1.0 : 0.0;
+        a.stats[6] += 1.0;
+    }
+}
+
+template <int POT>
+static hipError_t refresh_pot(const MlpArgs& a, int t0, hipStream_t s) {
+    hipError_t e;
+    hipLaunchKernelGGL((mlp_subset_kernel<POT>), dim3((a.subset + 255) / 256), dim3(256), 0, s, a);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    const int nb = a.subset / a.batch, nblk = a.batch / kMlpTrainThreads;
+    for (int b = 0; b < nb; ++b) {
+        const int t = t0 + b + 1;
+        const float c1 = float(1.0 - std::pow(double(a.beta1), t)), c2 = float(1.0 - std::pow(double(a.beta2), t));
+        hipLaunchKernelGGL(mlp_train_kernel, dim3(nblk), dim3(kMlpTrainThreads), 0, s, a, b);
+        hipLaunchKernelGGL(mlp_adam_kernel, dim3((kMlpNP + 255) / 256), dim3(256), 0, s, a, nblk, c1, c2);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL((mlp_infer_kernel<POT>), dim3(a.nblk), dim3(kMlpInferThreads), 0, s, a);
+    hipLaunchKernelGGL(mlp_reduce_kernel, dim3(1), dim3(64), 0, s, a, 0);
+    hipLaunchKernelGGL(mlp_norm_kernel, dim3(a.nblk), dim3(kMlpInferThreads), 0, s, a);
+    hipLaunchKernelGGL(mlp_reduce_kernel, dim3(1), dim3(64), 0, s, a, 1);
+    hipLaunchKernelGGL(mlp_judge_kernel, dim3(a.nblk), dim3(kMlpInferThreads), 0, s, a);
+    hipLaunchKernelGGL(mlp_reduce_kernel, dim3(1), dim3(64), 0, s, a, 2);
+    hipLaunchKernelGGL(mlp_select_kernel, dim3(a.nblk), dim3(kMlpInferThreads), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_refresh(const MlpArgs& a, int pot_kind, int t0, hipStream_t s) {
+    switch (pot_kind) {
+        case 0: return refresh_pot<0>(a, t0, s);
+        case 1: return refresh_pot<1>(a, t0, s);
+        default: return refresh_pot<2>(a, t0, s);
+    }
+}
+
+}  // namespace m2m

@@ -186,6 +186,49 @@ struct MpLds {
     size_t kick_drift, coeff, kick;
 };
 
+// Learned prior (FP32 contexts, one model): network 3 -> 64 -> 64 -> 1 with tanh
+// hidden units, parameters W1[64][3], b1[64], W2[64][64], b2[64], W3[64], b3.
+constexpr int kMlpH = 64;
+constexpr int kMlpNP = kMlpH * 3 + kMlpH + kMlpH * kMlpH + kMlpH + kMlpH + 1;   // 4481
+constexpr int kMlpW1 = 0, kMlpB1 = kMlpW1 + kMlpH * 3, kMlpW2 = kMlpB1 + kMlpH, kMlpB2 = kMlpW2 + kMlpH * kMlpH,
+              kMlpW3 = kMlpB2 + kMlpH, kMlpB3 = kMlpW3 + kMlpH;
+constexpr int kMlpTrainThreads = 64;   // samples per training block
+constexpr int kMlpInferThreads = 256;
+constexpr int kMlpMaxInferBlocks = 2048;
+
+struct MlpArgs {
+    const float* state;        // state buffer of the refresh step (rows x y z vx vy vz w, then tags)
+    int64_t stride, n;
+    const Exact* ex;           // FP64 potential, circular-orbit and seed tables
+    float lcE0, lcEinv;        // origin and inverse spacing of the seed table
+    double Emin, Emax;         // the prior's energy range
+    uint32_t seed, q;          // sample generator key word and refresh index
+    int32_t subset, batch;
+    float4* sub;               // subset: (u0, u1, u2, ln w) per sample
+    float* theta;              // kMlpNP parameters
+    float* adam_m;
+    float* adam_v;
+    float* gpart;              // (batch / kMlpTrainThreads) x kMlpNP partial gradients
+    float lr, beta1, beta2, adam_eps;
+    double fallback;
+    float* what;               // n priors
+    const float* cellmean;     // histogram prior cell means
+    int32_t cellrow;           // tag row of the prior cell
+    int32_t nblk;              // blocks of the inference passes (<= kMlpMaxInferBlocks)
+    double* red;               // nblk x 2 per-block partials
+    double* stats;             // gmax, sum w, sum e, judge numerator, judge, fallback used, refreshes
+    const int* flag;
+};
+
+// Prior cells of the state a.out (tags, and cell sums and counts into the cell
+// columns of the partial slots) when the fused kernel observes without them.
+hipError_t launch_cells(const StepArgs<float, float>& a, int pot_kind, int blocks, size_t lds, hipStream_t s);
+hipError_t set_cells_lds_limit(size_t lds);
+
+// One refresh of the learned prior: sample, nbatch Adam steps from step t0 + 1
+// on, priors of every particle, judge and fallback.
+hipError_t launch_mlp_refresh(const MlpArgs& a, int pot_kind, int t0, hipStream_t s);
+
 template <typename T, typename PT>
 hipError_t launch_step(const StepArgs<T, PT>& a, int pot_kind, uint64_t sig, int nbin, int ilp, int blocks,
                        int threads, size_t lds, hipStream_t s);

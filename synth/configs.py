@@ -96,13 +96,23 @@ def cfg4(n_models=64, nmin=100_000, nmax=2_000_000, steps=3000):
             "target": {"kind": "hernquist_om", "ra": 1.0, "noise": 0.05, "seed_cfg": 1}}
 
 
+def mlp_init(seed):
+    """Initial parameters of the 3-64-64-1 prior network (FP32): weights normal
+    with variance 1/fan-in, biases zero; W1[64,3], b1, W2[64,64], b2, W3[1,64], b3."""
+    rng = np.random.default_rng(seed)
+    parts = [rng.normal(0.0, 1.0 / np.sqrt(3.0), (64, 3)), np.zeros(64), rng.normal(0.0, 1.0 / 8.0, (64, 64)),
+             np.zeros(64), rng.normal(0.0, 1.0 / 8.0, (1, 64)), np.zeros(1)]
+    return np.concatenate([p.ravel() for p in parts]).astype(np.float32)
+
+
 def cfg5(N=1 << 22, steps=5000, target_n=1 << 23):
     c = cfg2(N, steps, target_n)
+    seed = seed_for(5, 2)
     c.update({"name": "mlp_prior_fp32_N%d" % N, "index": 5,
               "prior": {"kind": "mlp", "axes": ("E", "L/Lc", "Lz/L"), "shape": (32, 32, 8),
                         "period": 100, "hidden": 64, "subset": 1 << 20, "batch": 8192,
                         "lr": 1e-3, "beta1": 0.9, "beta2": 0.999, "adam_eps": 1e-8,
-                        "fallback": 0.5},
+                        "fallback": 0.5, "seed": seed, "mlp_init": mlp_init(seed)},
               "eps": EPS_CFG2})
     return c
 

@@ -219,3 +219,85 @@ def test_subset_indices_in_range_and_uniform():
     assert idx.min() >= 0 and idx.max() < 1000
     counts = np.bincount(idx, minlength=1000)
     assert counts.std() < 3 * np.sqrt(65.536)
+
+
+# ---------------------------------------------------- learned prior: refreshes
+def small_mlp_model(N=3000, **prior):
+    from synth import configs
+    cfg = configs.cfg5(N=N, target_n=1 << 14)
+    cfg["prior"].update(prior)
+    inp = configs.make_inputs(cfg)
+    m = oracle.Model(cfg, inp["ics"], inp["w"], inp["Y"], inp["sigma"])
+    pr = cfg["prior"]
+    lp = mlp.LearnedPrior(pr["mlp_init"], pr["lr"], pr["beta1"], pr["beta2"], pr["adam_eps"], pr["seed"],
+                          pr["subset"], pr["batch"], pr["fallback"])
+    return cfg, m, lp
+
+
+def test_circular_orbit_has_L_equal_Lc():
+    """Integrals of a circular orbit in the equatorial plane of the logarithmic
+    potential: L = Lc(E) (the feature 2 L/Lc - 1 = 1) and Lz = L."""
+    from synth import configs
+    cfg, m, _ = small_mlp_model(N=8)
+    lp = configs.LOG_POT
+    R = np.array([0.05, 0.3, 1.0, 4.0])
+    vc = lp["v0"] * R / np.sqrt(lp["Rc"] ** 2 + R * R)
+    ics = np.zeros((6, R.size))
+    ics[0], ics[4] = R, vc
+    mc = oracle.Model(cfg, ics, np.full(R.size, 0.25), np.zeros(m.J), np.ones(m.J), Erange=m.Erange)
+    E, L, Lz, Lc = mc.integrals()
+    np.testing.assert_allclose(L, Lc, rtol=1e-10)
+    np.testing.assert_allclose(Lz, L, rtol=1e-14)
+    np.testing.assert_allclose(E, 0.5 * vc ** 2 + 0.5 * lp["v0"] ** 2 * np.log(lp["Rc"] ** 2 + R * R), rtol=1e-14)
+
+
+def test_refresh_with_zero_threshold_gives_the_histogram_prior():
+    cfg, m, lp = small_mlp_model(subset=512, batch=128, fallback=0.0)
+    E, L, Lz, Lc = m.integrals()
+    u = mlp.features(E, L, Lz, Lc, *m.Erange)
+    hist = m.prior_means()[0]
+    what = lp.refresh(0, oracle.subset(lp.seed, 0, lp.subset, u.shape[0]), u, m.w, hist)
+    assert lp.used_fallback and lp.last_judge > 0
+    np.testing.assert_array_equal(what, hist)
+
+
+def test_refresh_counts_adam_steps_and_normalises():
+    cfg, m, lp = small_mlp_model(subset=512, batch=128, fallback=1e9)
+    E, L, Lz, Lc = m.integrals()
+    u = mlp.features(E, L, Lz, Lc, *m.Erange)
+    hist = m.prior_means()[0]
+    th0 = lp.theta.copy()
+    what = lp.refresh(0, oracle.subset(lp.seed, 0, lp.subset, u.shape[0]), u, m.w, hist)
+    assert lp.t == 4 and not lp.used_fallback
+    assert np.sum(what) == pytest.approx(np.sum(m.w), rel=1e-12)
+    # Adam's step bound (Kingma & Ba, section 2.1): |step| <= lr (1 - b1)/sqrt(1 - b2)
+    # when 1 - b1 > sqrt(1 - b2)
+    assert np.max(np.abs(lp.theta - th0)) <= 4 * lp.lr * (1 - lp.beta1) / np.sqrt(1 - lp.beta2)
+    lp.refresh(1, oracle.subset(lp.seed, 1, lp.subset, u.shape[0]), u, m.w, hist)
+    assert lp.t == 8
+
+
+def test_first_adam_step_moves_each_parameter_by_lr():
+    """One minibatch per refresh: the first Adam step is lr g / (|g| + eps) per parameter."""
+    cfg, m, lp = small_mlp_model(subset=256, batch=256, fallback=1e9)
+    E, L, Lz, Lc = m.integrals()
+    u = mlp.features(E, L, Lz, Lc, *m.Erange)
+    idx = oracle.subset(lp.seed, 0, lp.subset, u.shape[0])
+    _, g = mlp.loss_grad(lp.theta, u[idx], np.log(m.w[idx]))
+    th0 = lp.theta.copy()
+    lp.refresh(0, idx, u, m.w, m.prior_means()[0])
+    np.testing.assert_allclose(th0 - lp.theta, lp.lr * g / (np.abs(g) + lp.eps), rtol=1e-9, atol=1e-15)
+
+
+def test_refresh_training_lowers_the_loss():
+    """Training on the refresh's own sample lowers the loss on it."""
+    cfg, m, lp = small_mlp_model(N=4000, subset=4096, batch=256, fallback=1e9)
+    E, L, Lz, Lc = m.integrals()
+    u = mlp.features(E, L, Lz, Lc, *m.Erange)
+    rng = np.random.default_rng(3)
+    w = m.w * np.exp(0.3 * u[:, 0] - 0.2 * u[:, 1] + 0.05 * rng.normal(size=u.shape[0]))
+    idx = oracle.subset(lp.seed, 0, lp.subset, u.shape[0])
+    before = mlp.loss(lp.theta, u[idx], np.log(w[idx]))
+    for q in range(4):
+        lp.refresh(q, idx, u, w, m.prior_means()[0])
+    assert mlp.loss(lp.theta, u[idx], np.log(w[idx])) < 0.5 * before
