@@ -1,17 +1,24 @@
-"""Benchmark: particle-steps per second of the fused M2M step on one MI355X.
+"""Benchmark: particle-steps per second of the M2M step on one MI355X.
 
-Workload: the plain method at scale -- N = 2^20 particles in the axisymmetric
-logarithmic potential (v0 = 1, Rc = 0.1, q = 0.8), FP32 particle arithmetic,
-64x64 sky pixels plus 20x20 kinematic bins (first and second LOS moments,
-J = 4896 observables), moving (E, Lz/Lc) prior on 32x32 cells refreshed every
-step, dt = 0.005.  One step = weight update + leapfrog push + observe + smoothing,
-deviations, chi^2 and prior cell means, all on the GPU.
+Workloads (--workload):
+  logpot     the headline: the plain method at scale -- N = 2^20 particles in the
+             axisymmetric logarithmic potential (v0 = 1, Rc = 0.1, q = 0.8), FP32,
+             64x64 sky pixels plus 20x20 kinematic bins (first and second LOS
+             moments, J = 4896), moving (E, Lz/Lc) prior on 32x32 cells every step,
+             dt = 0.005;
+  batched    64 Hernquist+NFW models, sum N_m ~ 7e7, one launch per step;
+  multipole  2^23 particles in their own multipole potential (lmax 8, 200 nodes),
+             the logpot observables plus 50 density shells;
+  mlp        2^22 particles with the learned prior (refreshed every 100 steps on a
+             2^20 sample, judged against a 32x32x8 histogram prior).
+One step = weight update + push + observe + smoothing, deviations, chi^2 and
+prior, all on the GPU.
 
-Prints one JSON line (see the keys below).  The timed region starts with the
-particles resident in HBM; each fused step kernel is bracketed by HIP events on
-the context's stream, which gives the roofline figure.
+Prints one JSON line.  The timed region starts with the particles resident in
+HBM; the dominant kernel is bracketed by HIP events on the context's stream in a
+second timed region, which gives the roofline figure.
 
-    python bench.py [--steps K] [--warmup W] [--gpus 1] [--n N] [--no-cpu-baseline]
+    python bench.py [--workload W] [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
     python bench.py --copy-calibration MIB   # plain device copy, for HBM counter scaling
 """
 import argparse
@@ -28,12 +35,25 @@ sys.path.insert(0, ROOT)
 
 BYTES_PER_PARTICLE_STEP = 56      # read x y z vx vy vz w (7 x 4 B), write the same
 HBM_PEAK_GBS = 8000.0
+FP32_PEAK_TFLOPS = 157.3           # MI355X vector FP32 (published; packed FP32 counts twice)
+
+
+def mp_flops_per_particle(lmax=8):
+    """Algorithmic FP32 operations (an FMA counts 2) of the multipole
+    update/kick/drift kernel per particle: per (l, m >= 0) term 12 to interpolate
+    the four node coefficients (a + t (b - a) each), 11 for the potential, 45 for
+    the gradient (6 for the two radial combinations, 12 for the solid-harmonic
+    derivatives, 15 to accumulate three components, 12 for the radial term) and 8
+    for the harmonic recurrence; per degree l 4 for the radial powers; 50 for the
+    set-up of the expansion point, the weight update, the kick and the drift."""
+    terms = (lmax + 1) * (lmax + 2) // 2
+    return terms * (12 + 11 + 45 + 8) + (lmax + 1) * 4 + 50
 
 
 def kernel_sources_sha256():
     """Digest of the sources the fused step kernel is compiled from."""
     h = hashlib.sha256()
-    for f in ("step.hip", "device.h", "runtime.h"):
+    for f in ("step.hip", "particle.h", "device.h", "runtime.h"):
         with open(os.path.join(ROOT, "paper_1207_6403_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
@@ -62,12 +82,20 @@ def log(msg):
 
 
 def cpu_baseline(cfg, inp, er, nsteps):
-    """The FP64 oracle, as it is, on the host cores: a bounded sample of the workload."""
+    """The FP64 oracle, as it is, on the host cores: a bounded sample of the workload
+    (the learned prior through the oracle's refresh schedule)."""
     import oracle
+    from oracle import mlp
     m = oracle.Model(cfg, inp["ics"].astype(np.float64), inp["w"].astype(np.float64), inp["Y"], inp["sigma"],
                      Erange=tuple(er))
     t0 = time.perf_counter()
-    st = m.run(nsteps)
+    if cfg["prior"]["kind"] == "mlp":
+        pr = cfg["prior"]
+        lp = mlp.LearnedPrior(pr["mlp_init"], pr["lr"], pr["beta1"], pr["beta2"], pr["adam_eps"], pr["seed"],
+                              pr["subset"], pr["batch"], pr["fallback"])
+        st = mlp.run(m, lp, pr, nsteps, oracle.subset)
+    else:
+        st = m.run(nsteps)
     dt = time.perf_counter() - t0
     return {"value": cfg["N"] * nsteps / dt, "unit": "particle-steps/s", "cores": oracle.threads(),
             "kind": "oracle", "sample": "N=%d particles x %d steps of the same workload (%.1f s)" % (cfg["N"], nsteps, dt)}, st
@@ -106,17 +134,32 @@ def batched_checks(m2m, cfg, inp, xv, w, launch, cpu_steps, sample=(0, 31, 63)):
     return cpu, max(errs)
 
 
+WORKLOADS = {
+    "logpot": ("log-potential M2M at scale: N=%d FP32 particles, J=4896 observables (64x64 sky pixels "
+               "+ 20x20 kinematic bins x 2 LOS moments), 32x32 (E, Lz/Lc) moving prior every step, dt=0.005"),
+    "batched": ("64 Hernquist+NFW models (halo mass ratio x scale radius grid), sum N_m=%d FP32 particles, "
+                "30 shells + 20 annuli (LOS second moment) per model, (E, L/Lc) 20x20 moving prior per "
+                "model every step, dt=0.01, one launch per step for all models"),
+    "multipole": ("self-consistent multipole model: N=%d FP32 particles, lmax=8 at 200 log-spaced nodes "
+                  "rebuilt every step, J=4896 + 50 density shells, 32x32 (E, Lz/Lc) prior in the analytic "
+                  "log potential every step, dt=0.005"),
+    "mlp": ("learned prior: N=%d FP32 particles in the log potential, 3-64-64-1 network retrained every 100 "
+            "steps on a 2^20 sample (128 Adam minibatches of 8192), judged against a 32x32x8 (E, L/Lc, Lz/L) "
+            "histogram prior, J=4896, dt=0.005"),
+}
+DEFAULT_CPU_STEPS = {"logpot": 24, "batched": 24, "multipole": 2, "mlp": 2}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=100)
-    ap.add_argument("--n", type=int, default=1 << 20)
-    ap.add_argument("--workload", choices=("logpot", "batched"), default="logpot",
-                    help="logpot: the 2^20-particle log-potential model (the headline); batched: 64 "
-                         "Hernquist+NFW models, sum N_m ~ 67M, one launch per step for all models")
+    ap.add_argument("--n", type=int, default=1 << 20, help="particles of the logpot workload")
+    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="logpot",
+                    help="logpot (the headline), batched, multipole or mlp")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-steps", type=int, default=24)
+    ap.add_argument("--cpu-steps", type=int, default=0, help="oracle steps of the CPU baseline (0: per workload)")
     ap.add_argument("--autotune", action="store_true",
                     help="time the candidate launch shapes first (the default shape is the tuned one)")
     ap.add_argument("--graph-steps", type=int, default=100)
@@ -144,12 +187,13 @@ def main():
     import paper_1207_6403_amd as m2m
     from synth import configs
 
-    batched = args.workload == "batched"
-    cfg = configs.cfg4() if batched else configs.cfg2(N=args.n)
+    wl = args.workload
+    batched = wl == "batched"
+    cfg = {"logpot": lambda: configs.cfg2(N=args.n), "batched": configs.cfg4, "multipole": configs.cfg3,
+           "mlp": configs.cfg5}[wl]()
+    cpu_steps = args.cpu_steps or DEFAULT_CPU_STEPS[wl]
     log("generating inputs (N=%d)" % cfg["N"])
     inp = configs.make_inputs(cfg, dtype=np.float32)
-    # prior energy grid: [min E(0), max E(0)] in the model potential, from the synthetic model
-    from synth import galaxy  # noqa: F401
     dev = torch.device("cuda:0")
     xv = torch.from_numpy(np.ascontiguousarray(inp["ics"])).to(dev)
     w = torch.from_numpy(np.ascontiguousarray(inp["w"])).to(dev)
@@ -163,7 +207,8 @@ def main():
     torch.cuda.synchronize()
 
     # timed region 1 (the throughput): K steps as the library runs them, from
-    # HIP graphs of G steps each (both step parities' graphs built beforehand)
+    # HIP graphs of G steps each where the step sequence allows (both step
+    # parities' graphs built beforehand)
     G = args.graph_steps
     m2m.m2m_set_launch(ctx, timing=0, graph_steps=G)
     if G:
@@ -176,8 +221,8 @@ def main():
     wall = time.perf_counter() - t0
     value = cfg["N"] * args.steps / wall
 
-    # timed region 2 (the roofline): the same K steps launched one by one, each
-    # fused step kernel bracketed by HIP events on the context's stream
+    # timed region 2 (the roofline): the same K steps launched one by one, the
+    # dominant kernel bracketed by HIP events on the context's stream
     m2m.m2m_set_launch(ctx, timing=1, graph_steps=0)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
@@ -185,39 +230,47 @@ def main():
     torch.cuda.synchronize()
     wall_ev = time.perf_counter() - t1
     k_ms, k_n = m2m.m2m_kernel_time(ctx)
-    achieved = BYTES_PER_PARTICLE_STEP * cfg["N"] / (k_ms * 1e-3) / 1e9
-    log("graphs: %.2f us/step (%.3g particle-steps/s); one by one: %.2f us/step, fused kernel %.2f us (%d launches)"
+    if wl == "multipole":
+        flops = mp_flops_per_particle() * cfg["N"]
+        achieved = flops / (k_ms * 1e-3) / 1e12
+        roof = {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / FP32_PEAK_TFLOPS, "traffic": None,
+                "kernel": "mp_kick_drift_kernel (weight update, first kick from the node tables in LDS, drift)",
+                "kernel_us": k_ms * 1e3, "flops_per_launch": flops}
+    else:
+        bpp = BYTES_PER_PARTICLE_STEP + (4 if wl == "mlp" else 0)   # the learned prior is read per particle
+        achieved = bpp * cfg["N"] / (k_ms * 1e-3) / 1e9
+        roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(cfg["N"]) if wl == "logpot" else None,
+                "kernel": "step_kernel (fused update + push + observe + prior cells)",
+                "kernel_us": k_ms * 1e3, "bytes_per_launch": bpp * cfg["N"]}
+    roof["timing"] = "HIP events around each of %d one-by-one launches" % k_n
+    log("throughput: %.2f us/step (%.3g particle-steps/s); one by one: %.2f us/step, dominant kernel %.2f us (%d launches)"
         % (wall / args.steps * 1e6, value, wall_ev / args.steps * 1e6, k_ms * 1e3, k_n))
-    traffic = None if batched else measured_traffic(cfg["N"])
 
-    # chi^2 relative error against the oracle: one step from the initial state
-    er = None
+    # chi^2 relative error against the oracle after two steps from the initial state
     chi2_err = None
     cpu = None
     if batched and not args.no_cpu_baseline:
-        cpu, chi2_err = batched_checks(m2m, cfg, inp, xv, w, launch, args.cpu_steps)
+        cpu, chi2_err = batched_checks(m2m, cfg, inp, xv, w, launch, cpu_steps)
     elif not args.no_cpu_baseline:
         import oracle
         er = oracle.energy_range(cfg, inp["ics"].astype(np.float64))
         ctx2 = m2m.m2m_create(cfg, xv, w, inp["Y"], inp["sigma"], Erange=np.array(er), device_ptrs=True)
         m2m.m2m_set_launch(ctx2, threads=launch["threads"], ilp=launch["ilp"], blocks_per_cu=launch["blocks_per_cu"])
         g1 = m2m.m2m_step(ctx2, 2)[0]
-        log("cpu baseline: %d oracle steps of N=%d" % (args.cpu_steps, cfg["N"]))
-        cpu, ost = cpu_baseline(cfg, inp, er, args.cpu_steps)
-        chi2_err = abs(g1["chi2"] - ost[1][0]) / ost[1][0]
         m2m.m2m_destroy(ctx2)
+        log("cpu baseline: %d oracle steps of N=%d" % (max(cpu_steps, 2), cfg["N"]))
+        cpu, ost = cpu_baseline(cfg, inp, er, max(cpu_steps, 2))
+        chi2_err = abs(g1["chi2"] - ost[1][0]) / ost[1][0]
 
+    config = {"workload": WORKLOADS[wl] % cfg["N"], "N": cfg["N"], "launch": launch}
     if batched:
-        workload = ("64 Hernquist+NFW models (halo mass ratio x scale radius grid), sum N_m=%d FP32 particles, "
-                    "30 shells + 20 annuli (LOS second moment) per model, (E, L/Lc) 20x20 moving prior per "
-                    "model every step, dt=0.01, one launch per step for all models" % cfg["N"])
-        config = {"workload": workload, "N": cfg["N"], "models": len(cfg["model_sizes"]), "J": 50,
-                  "prior_cells": 400, "launch": launch}
+        config.update(models=len(cfg["model_sizes"]), J=50, prior_cells=400)
     else:
-        workload = ("log-potential M2M at scale: N=%d FP32 particles, J=4896 observables (64x64 sky pixels "
-                    "+ 20x20 kinematic bins x 2 LOS moments), 32x32 (E, Lz/Lc) moving prior every step, "
-                    "dt=0.005" % cfg["N"])
-        config = {"workload": workload, "N": cfg["N"], "J": 4896, "prior_cells": 1024, "launch": launch}
+        config.update(J=4946 if wl == "multipole" else 4896,
+                      prior_cells=8192 if wl == "mlp" else 1024)
+    graphs = G and (cfg["prior"]["kind"] == "flat" or cfg["prior"].get("period", 1) == 1)
     out = {
         "metric": "particle-steps/sec at 1M particles (push+observe+update); chi2 rel. err vs oracle",
         "value": value,
@@ -232,12 +285,9 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": config,
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "step_kernel (fused update + push + observe + prior cells)",
-                     "kernel_us": k_ms * 1e3, "bytes_per_launch": BYTES_PER_PARTICLE_STEP * cfg["N"],
-                     "timing": "HIP events around each of %d one-by-one launches" % k_n},
-        "timing": {"value": "%d steps replayed from HIP graphs of %d steps" % (args.steps, G),
+        "roofline": roof,
+        "timing": {"value": ("%d steps replayed from HIP graphs of %d steps" % (args.steps, G)) if graphs
+                   else "%d steps launched one by one (the step sequence changes between refreshes)" % args.steps,
                    "one_by_one_value": cfg["N"] * args.steps / wall_ev,
                    "one_by_one_ms_per_step": wall_ev / args.steps * 1e3},
         "chi2_rel_err_vs_oracle": chi2_err,

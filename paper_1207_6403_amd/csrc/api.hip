@@ -555,9 +555,13 @@ static hipError_t launch_one_T(m2m_ctx* c, int64_t n, hipEvent_t e0, hipEvent_t 
     if (c->mp) {
         // self-consistent model: update, kicks and drift with the coefficient
         // rebuild between them, then the fused kernel observes the new state
+        // (the timing events bracket the update/kick/drift kernel)
         MpArgs<T> mp;
         fill_mp_args<T>(c, mp, a.out);
         e = launch_mp_step<T, T>(a, mp, c->sig, c->lay.nbin, p.nblock, c->mp_lds, c->stream);
+        if (e1) (void)hipEventRecord(e1, c->stream);
+        e1 = nullptr;
+        if (e == hipSuccess && !c->frozen) e = launch_mp_build<T>(mp, p.nblock, c->mp_lds, c->stream, true);
         if (e == hipSuccess) {
             StepArgs<T, T> o;
             fill_step_args<T>(c, o, (int)((n + 1) & 1), 1, 0, acc);

@@ -7,6 +7,7 @@
 // counts per cell into the cell columns of the same partial slots, with the
 // same block-to-slot assignment.
 #include "particle.h"
+#include "forms.h"
 
 namespace m2m {
 

@@ -4,7 +4,7 @@
 #include <vector>
 
 #include "m2m.h"
-#include "runtime.h"
+#include "forms.h"
 
 // Launch plan: tiles of threads * ilp particles (never straddling a model),
 // contiguous tile ranges per block, one partial slot per (block, model) pair,

@@ -17,7 +17,7 @@
 //                 the fallback threshold
 // with single-block reductions of the per-block partials in between, in block
 // order (deterministic).
-#include "runtime.h"
+#include "forms.h"
 
 namespace m2m {
 

@@ -18,6 +18,7 @@
 //   mp_kick         second half kick
 // then the fused step kernel observing the new state, and the finalise kernel.
 #include "particle.h"
+#include "forms.h"
 
 namespace m2m {
 
@@ -676,12 +677,9 @@ static hipError_t launch_kd(const StepArgs<T, PT>& a, const MpArgs<T>& mp, int b
 template <typename T, typename PT>
 hipError_t launch_mp_step(const StepArgs<T, PT>& a, const MpArgs<T>& mp, uint64_t sig, int nbin, int blocks,
                           const MpLds& lds, hipStream_t s) {
-    hipError_t e;
-    if (nbin <= 2) e = launch_kd<T, PT, 2, 0>(a, mp, blocks, lds.kick_drift, s);
-    else e = launch_kd<T, PT, 4, 0>(a, mp, blocks, lds.kick_drift, s);
     (void)sig;
-    if (e != hipSuccess || (a.flags & kFrozen)) return e;
-    return launch_mp_build(mp, blocks, lds, s, true);
+    if (nbin <= 2) return launch_kd<T, PT, 2, 0>(a, mp, blocks, lds.kick_drift, s);
+    return launch_kd<T, PT, 4, 0>(a, mp, blocks, lds.kick_drift, s);
 }
 
 template <typename T>
