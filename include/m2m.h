@@ -258,7 +258,7 @@ m2m_status m2m_multipole_tables(m2m_ctx *ctx, double *A, double *B);
  * A refresh runs before the update of every step n with n % period == 0, on
  * that step's state.  INVALID when the prior is not MLP.  The learned prior
  * runs in FP32 contexts of one model (m2m_create: UNSUPPORTED otherwise);
- * mlp_batch must be a multiple of 64 and divide mlp_subset. */
+ * mlp_batch must be a multiple of 32 and divide mlp_subset. */
 m2m_status m2m_mlp_state(m2m_ctx *ctx, float *theta, double *judge, int32_t *used_fallback, int64_t *refreshes);
 
 /* Time candidate launch shapes (threads x ilp x blocks_per_cu) on trial_steps

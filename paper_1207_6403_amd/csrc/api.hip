@@ -171,9 +171,9 @@ static m2m_status validate(const m2m_config* cfg, const m2m_obs_layout* lay, con
     }
     if (P.kind == M2M_PRIOR_MLP) {
         if (!P.mlp_init) return fail(nullptr, M2M_ERR_INVALID, "learned prior needs mlp_init");
-        if (P.mlp_batch < kMlpTrainThreads || P.mlp_batch % kMlpTrainThreads || P.mlp_subset < P.mlp_batch ||
+        if (P.mlp_batch < kMlpSamples || P.mlp_batch % kMlpSamples || P.mlp_subset < P.mlp_batch ||
             P.mlp_subset % P.mlp_batch)
-            return fail(nullptr, M2M_ERR_INVALID, "mlp_batch must be a multiple of 64 and divide mlp_subset");
+            return fail(nullptr, M2M_ERR_INVALID, "mlp_batch must be a multiple of 32 and divide mlp_subset");
         if (!(P.lr > 0) || !(P.beta1 >= 0 && P.beta1 < 1) || !(P.beta2 >= 0 && P.beta2 < 1) || !(P.adam_eps >= 0) ||
             !(P.fallback >= 0))
             return fail(nullptr, M2M_ERR_INVALID, "learned prior needs lr > 0, 0 <= beta < 1, adam_eps >= 0, fallback >= 0");
@@ -868,7 +868,7 @@ static m2m_status create_T(m2m_ctx* c, const m2m_target* tg, const void* xv, con
         c->mlp_nblk = (int)std::min<int64_t>(kMlpMaxInferBlocks, (N + kMlpInferThreads - 1) / kMlpInferThreads);
         if ((s = upload(c, &c->mlp_theta, c->mlp_init_host)) || (s = dalloc(c, &c->mlp_m, (size_t)kMlpNP)) ||
             (s = dalloc(c, &c->mlp_v, (size_t)kMlpNP)) || (s = dalloc(c, &c->mlp_sub, (size_t)P.mlp_subset)) ||
-            (s = dalloc(c, &c->mlp_gpart, (size_t)(P.mlp_batch / kMlpTrainThreads) * kMlpNP)) ||
+            (s = dalloc(c, &c->mlp_gpart, (size_t)(P.mlp_batch / kMlpSamples) * kMlpNP)) ||
             (s = dalloc(c, &c->mlp_red, 2 * (size_t)c->mlp_nblk)) || (s = dalloc(c, &c->mlp_stats, 8)))
             return s;
         HIPCHK(c, hipMemset(c->mlp_m, 0, sizeof(float) * kMlpNP));

@@ -65,7 +65,9 @@ constexpr int kMlpH = 64;
 constexpr int kMlpNP = kMlpH * 3 + kMlpH + kMlpH * kMlpH + kMlpH + kMlpH + 1;   // 4481
 constexpr int kMlpW1 = 0, kMlpB1 = kMlpW1 + kMlpH * 3, kMlpW2 = kMlpB1 + kMlpH, kMlpB2 = kMlpW2 + kMlpH * kMlpH,
               kMlpW3 = kMlpB2 + kMlpH, kMlpB3 = kMlpW3 + kMlpH;
-constexpr int kMlpTrainThreads = 64;   // samples per training block
+constexpr int kMlpSamples = 32;        // samples per training block
+constexpr int kMlpTPS = 8;             // threads per sample
+constexpr int kMlpTrainThreads = kMlpSamples * kMlpTPS;
 constexpr int kMlpInferThreads = 256;
 constexpr int kMlpMaxInferBlocks = 2048;
 
@@ -81,7 +83,7 @@ struct MlpArgs {
     float* theta;              // kMlpNP parameters
     float* adam_m;
     float* adam_v;
-    float* gpart;              // (batch / kMlpTrainThreads) x kMlpNP partial gradients
+    float* gpart;              // (batch / kMlpSamples) x kMlpNP partial gradients
     float lr, beta1, beta2, adam_eps;
     double fallback;
     float* what;               // n priors

@@ -6,8 +6,9 @@
 //   mlp_subset    a Philox4x32-10 sample of the particles: features
 //                 u = (2 (E - Emin)/(Emax - Emin) - 1, 2 L/Lc(E) - 1, Lz/L) (FP64
 //                 integrals, FP32 features) and the target ln w
-//   mlp_train     per minibatch: forward and backward of each sample, the
-//                 block's gradient sums (64 samples per block)
+//   mlp_train     per minibatch: forward and backward of each sample (eight
+//                 threads per sample), the block's gradient sums (32 samples
+//                 per block)
 //   mlp_adam      the minibatch gradient (block sums in block order) and one Adam
 //                 step (Kingma & Ba 2015, Algorithm 1)
 //   mlp_infer     g(u) of every particle, per-block maxima
@@ -100,88 +101,154 @@ __device__ __forceinline__ float mlp_forward(const float* th, float u0, float u1
     return g;
 }
 
-// Minibatch b: samples b*batch + blockIdx.x*64 + threadIdx.x.  Each thread runs
-// its sample forward and backward (loss (g - t)^2 averaged over the minibatch);
-// the block then sums the 64 samples' gradient terms: thread o takes row o of
-// W2 (and W1, b1, b2, W3), thread 0 also b3.
+// Minibatch b, block of kMlpSamples samples (b*batch + blockIdx.x*kMlpSamples on),
+// kMlpTPS threads per sample: thread t takes sample s = t / kMlpTPS and the units
+// q*8 .. q*8+7 (q = t % kMlpTPS) of each layer; activations and deltas are shared
+// in LDS.  Loss (g - t)^2 averaged over the minibatch.  The block's gradient sums
+// over its samples (in sample order) go to its partial row.  W2 is held in LDS
+// with rows padded to kW2Row floats, so that the eight rows a wave reads at once
+// fall in different banks.
+constexpr int kW2Row = kMlpH + 4;
+constexpr int kThW2 = kMlpB1 + kMlpH;                    // W2 in the LDS copy
+constexpr int kThB2 = kThW2 + kMlpH * kW2Row;
+constexpr int kThW3 = kThB2 + kMlpH, kThB3 = kThW3 + kMlpH, kThN = kThB3 + 4;
+constexpr int kActRow = kMlpH + 1;
+
 __global__ void __launch_bounds__(kMlpTrainThreads) mlp_train_kernel(MlpArgs a, int b) {
-    __shared__ __align__(16) float th[kMlpNP + 3];
-    __shared__ float H1[kMlpTrainThreads][kMlpH + 1], H2[kMlpTrainThreads][kMlpH + 1];
-    __shared__ float D2[kMlpTrainThreads][kMlpH + 1], D1[kMlpTrainThreads][kMlpH + 1];
-    __shared__ float U[kMlpTrainThreads][4];
+    __shared__ __align__(16) float th[kThN];
+    __shared__ float H1[kMlpSamples][kActRow], H2[kMlpSamples][kActRow];
+    __shared__ float D2[kMlpSamples][kActRow], D1[kMlpSamples][kActRow];
+    __shared__ float U[kMlpSamples][4];
     if (*a.flag) return;
-    const int tid = threadIdx.x;
-    for (int i = tid; i < kMlpNP; i += kMlpTrainThreads) th[i] = a.theta[i];
+    const int tid = threadIdx.x, s = tid / kMlpTPS, q = tid % kMlpTPS;
+    constexpr int UPT = kMlpH / kMlpTPS;   // units per thread
+    for (int i = tid; i < kMlpNP; i += kMlpTrainThreads) {
+        const float v = a.theta[i];
+        int d;
+        if (i < kMlpW2) d = i;
+        else if (i < kMlpB2) d = kThW2 + ((i - kMlpW2) / kMlpH) * kW2Row + (i - kMlpW2) % kMlpH;
+        else d = kThB2 + (i - kMlpB2);
+        th[d] = v;
+    }
+    const float4 smp = a.sub[(size_t)b * a.batch + (size_t)blockIdx.x * kMlpSamples + s];
     __syncthreads();
-    const float4 smp = a.sub[(size_t)b * a.batch + (size_t)blockIdx.x * kMlpTrainThreads + tid];
-    float h1[kMlpH];
-    const float g = mlp_forward(th, smp.x, smp.y, smp.z, h1, &H2[tid][0]);
-    const float dg = 2.0f * (g - smp.w) / float(a.batch);
-    // backward: d2 = dg W3 (1 - h2^2), d1 = (W2^T d2) (1 - h1^2)
-    float d1[kMlpH];
+    // layer 1
     #pragma unroll
-    for (int i = 0; i < kMlpH; ++i) d1[i] = 0.0f;
-    #pragma unroll 2
-    for (int o = 0; o < kMlpH; ++o) {
-        const float h2o = H2[tid][o];
-        const float d2 = dg * th[kMlpW3 + o] * (1.0f - h2o * h2o);
-        D2[tid][o] = d2;
-        const float4* row = reinterpret_cast<const float4*>(th + kMlpW2 + kMlpH * o);
+    for (int k = 0; k < UPT; ++k) {
+        const int o = q * UPT + k;
+        H1[s][o] = unit_tanh(th[kMlpB1 + o] + th[kMlpW1 + 3 * o] * smp.x + th[kMlpW1 + 3 * o + 1] * smp.y +
+                             th[kMlpW1 + 3 * o + 2] * smp.z);
+    }
+    __syncthreads();
+    // layer 2 and the output
+    float acc[UPT];
+    #pragma unroll
+    for (int k = 0; k < UPT; ++k) acc[k] = th[kThB2 + q * UPT + k];
+    for (int i = 0; i < kMlpH; i += 4) {
+        const float h0 = H1[s][i], h1 = H1[s][i + 1], h2 = H1[s][i + 2], h3 = H1[s][i + 3];
         #pragma unroll
-        for (int i = 0; i < kMlpH / 4; ++i) {
-            const float4 r = row[i];
-            d1[4 * i] += r.x * d2;
-            d1[4 * i + 1] += r.y * d2;
-            d1[4 * i + 2] += r.z * d2;
-            d1[4 * i + 3] += r.w * d2;
+        for (int k = 0; k < UPT; ++k) {
+            const float4 r = *reinterpret_cast<const float4*>(&th[kThW2 + (q * UPT + k) * kW2Row + i]);
+            acc[k] += r.x * h0 + r.y * h1 + r.z * h2 + r.w * h3;
         }
     }
+    float gp = 0.0f;
     #pragma unroll
-    for (int i = 0; i < kMlpH; ++i) {
-        H1[tid][i] = h1[i];
-        D1[tid][i] = d1[i] * (1.0f - h1[i] * h1[i]);
+    for (int k = 0; k < UPT; ++k) {
+        acc[k] = unit_tanh(acc[k]);
+        gp += th[kThW3 + q * UPT + k] * acc[k];
     }
-    U[tid][0] = smp.x; U[tid][1] = smp.y; U[tid][2] = smp.z; U[tid][3] = dg;
+    #pragma unroll
+    for (int o = kMlpTPS / 2; o > 0; o >>= 1) gp += __shfl_xor(gp, o, 64);   // the sample's kMlpTPS threads, in a fixed tree
+    const float g = th[kThB3] + gp;
+    const float dg = 2.0f * (g - smp.w) / float(a.batch);
+    #pragma unroll
+    for (int k = 0; k < UPT; ++k) {
+        const int o = q * UPT + k;
+        H2[s][o] = acc[k];
+        D2[s][o] = dg * th[kThW3 + o] * (1.0f - acc[k] * acc[k]);
+    }
+    if (q == 0) { U[s][0] = smp.x; U[s][1] = smp.y; U[s][2] = smp.z; U[s][3] = dg; }
     __syncthreads();
-    // sums over the block's samples (in sample order)
-    const int o = tid;
-    float gw2[kMlpH];
+    // back to layer 1: d1 = (W2^T d2) (1 - h1^2)
+    float d1[UPT];
     #pragma unroll
-    for (int i = 0; i < kMlpH; ++i) gw2[i] = 0.0f;
-    float gb2 = 0.0f, gw3 = 0.0f, gb1 = 0.0f, gw10 = 0.0f, gw11 = 0.0f, gw12 = 0.0f, gb3 = 0.0f;
-    for (int s = 0; s < kMlpTrainThreads; ++s) {
-        const float d2 = D2[s][o], d1o = D1[s][o];
+    for (int k = 0; k < UPT; ++k) d1[k] = 0.0f;
+    for (int o = 0; o < kMlpH; ++o) {
+        const float d2 = D2[s][o];
         #pragma unroll
-        for (int i = 0; i < kMlpH; ++i) gw2[i] += d2 * H1[s][i];
-        gb2 += d2;
-        gw3 += U[s][3] * H2[s][o];
-        gb1 += d1o;
-        gw10 += d1o * U[s][0];
-        gw11 += d1o * U[s][1];
-        gw12 += d1o * U[s][2];
-        gb3 += U[s][3];
+        for (int k = 0; k < UPT; ++k) d1[k] += th[kThW2 + o * kW2Row + q * UPT + k] * d2;
     }
-    float* dst = a.gpart + (size_t)blockIdx.x * kMlpNP;
     #pragma unroll
-    for (int i = 0; i < kMlpH; ++i) dst[kMlpW2 + kMlpH * o + i] = gw2[i];
-    dst[kMlpB2 + o] = gb2;
-    dst[kMlpW3 + o] = gw3;
-    dst[kMlpB1 + o] = gb1;
-    dst[kMlpW1 + 3 * o] = gw10;
-    dst[kMlpW1 + 3 * o + 1] = gw11;
-    dst[kMlpW1 + 3 * o + 2] = gw12;
-    if (o == 0) dst[kMlpB3] = gb3;
+    for (int k = 0; k < UPT; ++k) {
+        const int i = q * UPT + k;
+        const float h = H1[s][i];
+        D1[s][i] = d1[k] * (1.0f - h * h);
+    }
+    __syncthreads();
+    // sums over the block's samples: thread t takes W2 row o = t / 4, columns
+    // 16 (t % 4) .. +15; threads t < 64 also row t of b2, W3, b1, W1, thread 0 b3
+    float* dst = a.gpart + (size_t)blockIdx.x * kMlpNP;
+    {
+        const int o = tid >> 2, i0 = 16 * (tid & 3);
+        float gw[16];
+        #pragma unroll
+        for (int j = 0; j < 16; ++j) gw[j] = 0.0f;
+        for (int ss = 0; ss < kMlpSamples; ++ss) {
+            const float d2 = D2[ss][o];
+            #pragma unroll
+            for (int j = 0; j < 16; ++j) gw[j] += d2 * H1[ss][i0 + j];
+        }
+        #pragma unroll
+        for (int j = 0; j < 16; ++j) dst[kMlpW2 + kMlpH * o + i0 + j] = gw[j];
+    }
+    if (tid < kMlpH) {
+        const int o = tid;
+        float gb2 = 0.0f, gw3 = 0.0f, gb1 = 0.0f, gw10 = 0.0f, gw11 = 0.0f, gw12 = 0.0f;
+        for (int ss = 0; ss < kMlpSamples; ++ss) {
+            const float d2 = D2[ss][o], d1o = D1[ss][o];
+            gb2 += d2;
+            gw3 += U[ss][3] * H2[ss][o];
+            gb1 += d1o;
+            gw10 += d1o * U[ss][0];
+            gw11 += d1o * U[ss][1];
+            gw12 += d1o * U[ss][2];
+        }
+        dst[kMlpB2 + o] = gb2;
+        dst[kMlpW3 + o] = gw3;
+        dst[kMlpB1 + o] = gb1;
+        dst[kMlpW1 + 3 * o] = gw10;
+        dst[kMlpW1 + 3 * o + 1] = gw11;
+        dst[kMlpW1 + 3 * o + 2] = gw12;
+        if (o == 0) {
+            float gb3 = 0.0f;
+            for (int ss = 0; ss < kMlpSamples; ++ss) gb3 += U[ss][3];
+            dst[kMlpB3] = gb3;
+        }
+    }
 }
 
-// One Adam step on the minibatch gradient (the blocks' sums added in block order
-// in FP64); c1 = 1 - beta1^t, c2 = 1 - beta2^t.
+// One Adam step on the minibatch gradient; c1 = 1 - beta1^t, c2 = 1 - beta2^t.
+// Block: 64 parameters (lanes); wave w adds the blocks' partial rows w, w + 4, ...
+// in order (FP64), then the four wave sums are added in wave order.
 __global__ void __launch_bounds__(256) mlp_adam_kernel(MlpArgs a, int nblk, float c1, float c2) {
+    __shared__ double part[4][64];
     if (*a.flag) return;
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= kMlpNP) return;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int j = blockIdx.x * 64 + lane;
+    const int jj = min(j, kMlpNP - 1);
     double gs = 0.0;
-    for (int k = 0; k < nblk; ++k) gs += double(a.gpart[(size_t)k * kMlpNP + j]);
-    const float g = float(gs);
+    for (int k0 = w; k0 < nblk; k0 += 4 * 8) {
+        float v[8];
+        #pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = a.gpart[(size_t)min(k0 + 4 * u, nblk - 1) * kMlpNP + jj];
+        #pragma unroll
+        for (int u = 0; u < 8; ++u) gs += k0 + 4 * u < nblk ? double(v[u]) : 0.0;
+    }
+    part[w][lane] = gs;
+    __syncthreads();
+    if (w != 0 || j >= kMlpNP) return;
+    const float g = float(((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane]);
     const float m = a.beta1 * a.adam_m[j] + (1.0f - a.beta1) * g;
     const float v = a.beta2 * a.adam_v[j] + (1.0f - a.beta2) * g * g;
     a.adam_m[j] = m;
@@ -272,27 +339,40 @@ __global__ void __launch_bounds__(kMlpInferThreads) mlp_select_kernel(MlpArgs a)
         a.what[p] = a.cellmean[cell[p]];
 }
 
-// Reductions of the per-block partials (one block, block order):
+// Reductions of the per-block partials (one block; thread t takes partials t,
+// t + 256, ... in order, then a fixed tree):
 //   0: stats[0] = max g;  1: stats[1] = sum w, stats[2] = sum e;
 //   2: stats[3] = sum w |ln what - ln what_hist|, stats[4] = its w-weighted mean,
 //      stats[5] = 1 when that exceeds the fallback threshold, stats[6] += 1.
-__global__ void __launch_bounds__(64) mlp_reduce_kernel(MlpArgs a, int mode) {
+__global__ void __launch_bounds__(256) mlp_reduce_kernel(MlpArgs a, int mode) {
+    __shared__ double sh[2][256];
     if (*a.flag) return;
-    if (threadIdx.x != 0) return;
+    const int tid = threadIdx.x;
+    const bool is_max = mode == 0;
+    double u = is_max ? -INFINITY : 0.0, v = 0.0;
+    for (int k = tid; k < a.nblk; k += 256) {
+        if (is_max) u = fmax(u, a.red[2 * k]);
+        else { u += a.red[2 * k]; v += a.red[2 * k + 1]; }
+    }
+    sh[0][tid] = u;
+    sh[1][tid] = v;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (tid < o) {
+            sh[0][tid] = is_max ? fmax(sh[0][tid], sh[0][tid + o]) : sh[0][tid] + sh[0][tid + o];
+            sh[1][tid] += sh[1][tid + o];
+        }
+        __syncthreads();
+    }
+    if (tid != 0) return;
     if (mode == 0) {
-        double m = -INFINITY;
-        for (int k = 0; k < a.nblk; ++k) m = fmax(m, a.red[2 * k]);
-        a.stats[0] = m;
+        a.stats[0] = sh[0][0];
     } else if (mode == 1) {
-        double sw = 0.0, se = 0.0;
-        for (int k = 0; k < a.nblk; ++k) { sw += a.red[2 * k]; se += a.red[2 * k + 1]; }
-        a.stats[1] = sw;
-        a.stats[2] = se;
+        a.stats[1] = sh[0][0];
+        a.stats[2] = sh[1][0];
     } else {
-        double sj = 0.0;
-        for (int k = 0; k < a.nblk; ++k) sj += a.red[2 * k];
-        a.stats[3] = sj;
-        a.stats[4] = sj / a.stats[1];
+        a.stats[3] = sh[0][0];
+        a.stats[4] = sh[0][0] / a.stats[1];
         a.stats[5] = a.stats[4] > a.fallback ? 1.0 : 0.0;
         a.stats[6] += 1.0;
     }
@@ -303,20 +383,20 @@ static hipError_t refresh_pot(const MlpArgs& a, int t0, hipStream_t s) {
     hipError_t e;
     hipLaunchKernelGGL((mlp_subset_kernel<POT>), dim3((a.subset + 255) / 256), dim3(256), 0, s, a);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    const int nb = a.subset / a.batch, nblk = a.batch / kMlpTrainThreads;
+    const int nb = a.subset / a.batch, nblk = a.batch / kMlpSamples;
     for (int b = 0; b < nb; ++b) {
         const int t = t0 + b + 1;
         const float c1 = float(1.0 - std::pow(double(a.beta1), t)), c2 = float(1.0 - std::pow(double(a.beta2), t));
         hipLaunchKernelGGL(mlp_train_kernel, dim3(nblk), dim3(kMlpTrainThreads), 0, s, a, b);
-        hipLaunchKernelGGL(mlp_adam_kernel, dim3((kMlpNP + 255) / 256), dim3(256), 0, s, a, nblk, c1, c2);
+        hipLaunchKernelGGL(mlp_adam_kernel, dim3((kMlpNP + 63) / 64), dim3(256), 0, s, a, nblk, c1, c2);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     hipLaunchKernelGGL((mlp_infer_kernel<POT>), dim3(a.nblk), dim3(kMlpInferThreads), 0, s, a);
-    hipLaunchKernelGGL(mlp_reduce_kernel, dim3(1), dim3(64), 0, s, a, 0);
+    hipLaunchKernelGGL(mlp_reduce_kernel, dim3(1), dim3(256), 0, s, a, 0);
     hipLaunchKernelGGL(mlp_norm_kernel, dim3(a.nblk), dim3(kMlpInferThreads), 0, s, a);
-    hipLaunchKernelGGL(mlp_reduce_kernel, dim3(1), dim3(64), 0, s, a, 1);
+    hipLaunchKernelGGL(mlp_reduce_kernel, dim3(1), dim3(256), 0, s, a, 1);
     hipLaunchKernelGGL(mlp_judge_kernel, dim3(a.nblk), dim3(kMlpInferThreads), 0, s, a);
-    hipLaunchKernelGGL(mlp_reduce_kernel, dim3(1), dim3(64), 0, s, a, 2);
+    hipLaunchKernelGGL(mlp_reduce_kernel, dim3(1), dim3(256), 0, s, a, 2);
     hipLaunchKernelGGL(mlp_select_kernel, dim3(a.nblk), dim3(kMlpInferThreads), 0, s, a);
     return hipGetLastError();
 }
