@@ -261,6 +261,17 @@ m2m_status m2m_multipole_tables(m2m_ctx *ctx, double *A, double *B);
  * mlp_batch must be a multiple of 32 and divide mlp_subset. */
 m2m_status m2m_mlp_state(m2m_ctx *ctx, float *theta, double *judge, int32_t *used_fallback, int64_t *refreshes);
 
+/* Loss and gradient of the MLP prior's training objective (the mean over n
+ * samples of (g(u) - t)^2) at parameters theta, computed by the same GPU
+ * kernels as a refresh's minibatches (FP32; the blocks' sums added in FP64).
+ * theta: host, M2M_MLP_NPARAM values in the layout of m2m_mlp_state; samples:
+ * host, n rows of (u0, u1, u2, t); n a positive multiple of 32.  grad (host,
+ * M2M_MLP_NPARAM) gets the gradient, loss (host, nullable) the mean.  The
+ * context's parameters and state are not touched; device scratch is allocated
+ * for the call.  INVALID when the prior is not MLP. */
+m2m_status m2m_mlp_loss_grad(m2m_ctx *ctx, const float *theta, const float *samples, int32_t n, float *grad,
+                             double *loss);
+
 /* Time candidate launch shapes (threads x ilp x blocks_per_cu) on trial_steps
  * steps each, restore the state, keep the fastest; chosen may be NULL.  The
  * choice is cached in the JSON file named by $M2M_AUTOTUNE_CACHE if set. */

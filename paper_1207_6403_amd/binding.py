@@ -107,6 +107,8 @@ def lib():
         L.m2m_multipole_tables.argtypes = [CTX, C.POINTER(C.c_double), C.POINTER(C.c_double)]
         L.m2m_mlp_state.argtypes = [CTX, C.POINTER(C.c_float), C.POINTER(C.c_double), C.POINTER(C.c_int32),
                                     C.POINTER(C.c_int64)]
+        L.m2m_mlp_loss_grad.argtypes = [CTX, C.POINTER(C.c_float), C.POINTER(C.c_float), C.c_int32,
+                                        C.POINTER(C.c_float), C.POINTER(C.c_double)]
         L.m2m_autotune.argtypes = [CTX, C.c_int32, C.POINTER(m2m_launch)]
         L.m2m_get_launch.argtypes = [CTX, C.POINTER(m2m_launch)]
         L.m2m_set_launch.argtypes = [CTX, C.POINTER(m2m_launch)]
@@ -116,7 +118,7 @@ def lib():
         L.m2m_last_error.argtypes = [CTX]
         L.m2m_last_error.restype = C.c_char_p
         for f in ("m2m_create", "m2m_step", "m2m_observables", "m2m_weights", "m2m_priors", "m2m_particles",
-                  "m2m_history", "m2m_multipole_tables", "m2m_mlp_state", "m2m_autotune", "m2m_get_launch", "m2m_set_launch", "m2m_kernel_time"):
+                  "m2m_history", "m2m_multipole_tables", "m2m_mlp_state", "m2m_mlp_loss_grad", "m2m_autotune", "m2m_get_launch", "m2m_set_launch", "m2m_kernel_time"):
             getattr(L, f).restype = C.c_int
         if L.m2m_abi_version() != ABI_VERSION:
             raise ImportError("libm2m_hip.so ABI %d, binding expects %d" % (L.m2m_abi_version(), ABI_VERSION))
@@ -364,6 +366,20 @@ def m2m_mlp_state(ctx):
     _check(lib().m2m_mlp_state(ctx.ptr, th.ctypes.data_as(C.POINTER(C.c_float)), C.byref(j), C.byref(fb),
                                C.byref(nr)), ctx)
     return {"theta": th, "judge": j.value, "used_fallback": bool(fb.value), "refreshes": nr.value}
+
+
+def m2m_mlp_loss_grad(ctx, theta, samples):
+    """Loss and gradient (float32 [4481]) of the MLP prior's objective over samples
+    [n, 4] = (u0, u1, u2, target) at parameters theta, on the GPU."""
+    th = np.ascontiguousarray(theta, dtype=np.float32)
+    sm = np.ascontiguousarray(samples, dtype=np.float32)
+    assert th.size == MLP_NPARAM and sm.ndim == 2 and sm.shape[1] == 4
+    g = np.empty(MLP_NPARAM, dtype=np.float32)
+    loss = C.c_double()
+    fp = C.POINTER(C.c_float)
+    _check(lib().m2m_mlp_loss_grad(ctx.ptr, th.ctypes.data_as(fp), sm.ctypes.data_as(fp), sm.shape[0],
+                                   g.ctypes.data_as(fp), C.byref(loss)), ctx)
+    return loss.value, g
 
 
 def _launch_dict(L):

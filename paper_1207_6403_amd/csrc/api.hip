@@ -530,13 +530,49 @@ static void fill_mlp_args(const m2m_ctx* c, MlpArgs& a, int64_t n) {
     a.nblk = c->mlp_nblk;
     a.red = c->mlp_red;
     a.stats = c->mlp_stats;
+    a.loss = nullptr;
     a.flag = c->flag;
+}
+
+// Priors what_i of the particles in state buffer k from their cell tags and the
+// cell means (or per particle, flat or held), into out.
+template <typename T>
+static GatherArgs<T> gather_args(m2m_ctx* c, int k, int what_mode, T* out) {
+    GatherArgs<T> a;
+    a.in = (const T*)c->state[k];
+    a.tin = tags(c, k);
+    a.stride = c->stride;
+    a.what = (const T*)c->what;
+    a.out = out;
+    a.tile_model = c->plan.tile_model;
+    a.tile_p0 = c->plan.tile_p0;
+    a.tile_cnt = c->plan.tile_cnt;
+    a.block_tile0 = c->plan.block_tile0;
+    a.pots = (const Pot<T>*)c->pots_d;
+    a.lctab = (const T*)c->lctab;
+    a.lcetab = (const float*)c->lcetab;
+    a.erange = (const T*)c->erange;
+    a.flatw = (const T*)c->flatw;
+    a.cellmean = (const T*)c->cellmean;
+    a.cells = c->cells;
+    a.ex = exact_tables(c);
+    a.what_mode = what_mode;
+    a.cellrow = c->lay.nbin;
+    return a;
 }
 
 template <typename T>
 static hipError_t launch_one_T(m2m_ctx* c, int64_t n, hipEvent_t e0, hipEvent_t e1) {
     int wm, acc;
     prior_modes(c, n, &wm, &acc);
+    if (c->cells_apart && (wm == 1 || wm == 2)) {
+        // the fused kernel holds no cell means: gather the priors first and step
+        // with them as held priors
+        const hipError_t e = launch_gather<T>(gather_args<T>(c, (int)(n & 1), 1, (T*)c->what), c->pot_kind,
+                                              c->plan.nblock, c->stream);
+        if (e != hipSuccess) return e;
+        wm = 3;
+    }
     StepArgs<T, T> a;
     fill_step_args<T>(c, a, (int)(n & 1), 0, wm, acc);
     const Plan& p = c->plan;
@@ -861,7 +897,7 @@ static m2m_status create_T(m2m_ctx* c, const m2m_target* tg, const void* xv, con
     for (int k = 0; k < 6; ++k)
         HIPCHK(c, hipMemcpy((T*)c->state[0] + k * S, hx.data() + k * N, sizeof(T) * N, hipMemcpyHostToDevice));
     HIPCHK(c, hipMemcpy((T*)c->state[0] + 6 * S, hw.data(), sizeof(T) * N, hipMemcpyHostToDevice));
-    if (c->prior.kind != M2M_PRIOR_FLAT && (c->prior.period > 1 || c->prior.kind == M2M_PRIOR_MLP))
+    if (c->prior.kind != M2M_PRIOR_FLAT && (c->prior.period > 1 || c->prior.kind == M2M_PRIOR_MLP || c->cells_apart))
         if ((s = dalloc(c, (T**)&c->what, (size_t)S))) return s;
     if (c->prior.kind == M2M_PRIOR_MLP) {
         const m2m_prior& P = c->prior;
@@ -1078,10 +1114,18 @@ extern "C" m2m_status m2m_create(const m2m_config* cfg, const m2m_obs_layout* la
     c->launch.graph_steps = 0;
     c->launch.timing = 0;
     const size_t lds_need = 160 * 1024;
-    if (c->prior.kind == M2M_PRIOR_MLP) {
-        // the learned prior's judge grid is accumulated by the cell kernel
+    {
+        // LDS of the fused kernel with the prior cells (as make_plan computes it)
+        const int NCe = (c->NC + 1) & ~1, NE = (c->nedge + 1) & ~1;
+        const size_t fused = 8 * ((size_t)c->JP + c->NC + NE + 64 + (c->NC ? kLcE : 0)) + 4 * (size_t)NCe +
+                             4 * ((size_t)c->JP + NCe + NE + kLcTab);
+        // the learned prior's judge grid, and FP32 histogram priors too large for
+        // the fused kernel, are accumulated by the cell kernel
+        c->cells_apart = c->prec == M2M_F32 && (c->prior.kind == M2M_PRIOR_MLP ||
+                                                (c->prior.kind == M2M_PRIOR_HIST && fused > (size_t)c->max_lds));
+    }
+    if (c->cells_apart) {
         const int NCe = (c->NC + 1) & ~1;
-        c->cells_apart = true;
         c->cells_lds = 8 * (size_t)c->NC + 8 * (size_t)kLcE + 4 * (size_t)NCe;
         if (c->cells_lds > (size_t)c->max_lds) {
             const std::string why = "prior grid of " + std::to_string(c->NC) + " cells needs " +
@@ -1272,27 +1316,8 @@ static m2m_status gather_T(m2m_ctx* c, void* out, int dev) {
     int wm, acc;
     prior_modes(c, c->step, &wm, &acc);
     if (wm == 2) wm = 1;   // a refresh step would compute the table priors
-    GatherArgs<T> a;
-    a.in = (const T*)c->state[c->step & 1];
-    a.tin = tags(c, (int)(c->step & 1));
-    a.stride = c->stride;
-    a.what = (const T*)c->what;
-    a.out = (T*)c->scratch_n;
-    a.tile_model = c->plan.tile_model;
-    a.tile_p0 = c->plan.tile_p0;
-    a.tile_cnt = c->plan.tile_cnt;
-    a.block_tile0 = c->plan.block_tile0;
-    a.pots = (const Pot<T>*)c->pots_d;
-    a.lctab = (const T*)c->lctab;
-    a.lcetab = (const float*)c->lcetab;
-    a.erange = (const T*)c->erange;
-    a.flatw = (const T*)c->flatw;
-    a.cellmean = (const T*)c->cellmean;
-    a.cells = c->cells;
-    a.ex = exact_tables(c);
-    a.what_mode = wm;
-    a.cellrow = c->lay.nbin;
-    HIPCHK(c, launch_gather<T>(a, c->pot_kind, c->plan.nblock, c->stream));
+    HIPCHK(c, launch_gather<T>(gather_args<T>(c, (int)(c->step & 1), wm, (T*)c->scratch_n), c->pot_kind,
+                               c->plan.nblock, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     HIPCHK(c, hipMemcpy(out, c->scratch_n, sizeof(T) * c->N, dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost));
     return M2M_OK;
@@ -1351,6 +1376,48 @@ extern "C" m2m_status m2m_mlp_state(m2m_ctx* c, float* theta, double* judge, int
     if (judge) *judge = st[4];
     if (used_fallback) *used_fallback = st[5] != 0.0;
     if (refreshes) *refreshes = (int64_t)st[6];
+    return M2M_OK;
+}
+
+extern "C" m2m_status m2m_mlp_loss_grad(m2m_ctx* c, const float* theta, const float* samples, int32_t n, float* grad,
+                                        double* loss) {
+    if (!c) return fail(nullptr, M2M_ERR_INVALID, "ctx is NULL");
+    if (c->prior.kind != M2M_PRIOR_MLP) return fail(c, M2M_ERR_INVALID, "the context has no learned prior");
+    if (!theta || !samples || !grad) return fail(c, M2M_ERR_INVALID, "null argument");
+    if (n < kMlpSamples || n % kMlpSamples) return fail(c, M2M_ERR_INVALID, "n must be a positive multiple of 32");
+    if (m2m_status s = sticky(c)) return s;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    // scratch of this call only: parameters, samples, partial rows, gradient, loss terms
+    const size_t nblk = (size_t)n / kMlpSamples;
+    float *th = nullptr, *gp = nullptr, *gr = nullptr, *ls = nullptr;
+    float4* sm = nullptr;
+    m2m_status s;
+    if ((s = dalloc(c, &th, (size_t)kMlpNP)) || (s = dalloc(c, &sm, (size_t)n)) || (s = dalloc(c, &gp, nblk * kMlpNP)) ||
+        (s = dalloc(c, &gr, (size_t)kMlpNP)) || (s = dalloc(c, &ls, (size_t)n))) {
+        for (void* q : {(void*)th, (void*)sm, (void*)gp, (void*)gr, (void*)ls}) dfree(c, q);
+        return s;
+    }
+    MlpArgs a{};
+    fill_mlp_args(c, a, c->step);
+    a.theta = th;
+    a.sub = sm;
+    a.gpart = gp;
+    a.batch = n;
+    a.loss = ls;
+    std::vector<float> hl((size_t)n);
+    hipError_t e = hipMemcpy(th, theta, sizeof(float) * kMlpNP, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(sm, samples, sizeof(float) * 4 * (size_t)n, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = launch_mlp_grad(a, gr, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e == hipSuccess) e = hipMemcpy(grad, gr, sizeof(float) * kMlpNP, hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(hl.data(), ls, sizeof(float) * (size_t)n, hipMemcpyDeviceToHost);
+    for (void* q : {(void*)th, (void*)sm, (void*)gp, (void*)gr, (void*)ls}) dfree(c, q);
+    HIPCHK(c, e);
+    if (loss) {
+        double t = 0.0;
+        for (float v : hl) t += v;
+        *loss = t;
+    }
     return M2M_OK;
 }
 

@@ -92,6 +92,7 @@ struct MlpArgs {
     int32_t nblk;              // blocks of the inference passes (<= kMlpMaxInferBlocks)
     double* red;               // nblk x 2 per-block partials
     double* stats;             // gmax, sum w, sum e, judge numerator, judge, fallback used, refreshes
+    float* loss;               // per sample (g - t)^2 / batch, or null
     const int* flag;
 };
 
@@ -103,6 +104,10 @@ hipError_t set_cells_lds_limit(size_t lds);
 // One refresh of the learned prior: sample, nbatch Adam steps from step t0 + 1
 // on, priors of every particle, judge and fallback.
 hipError_t launch_mlp_refresh(const MlpArgs& a, int pot_kind, int t0, hipStream_t s);
+// Loss terms and gradient of the mean squared error over the a.batch samples in
+// a.sub at the parameters a.theta (the training kernels of a refresh, without
+// the Adam step): grad gets kMlpNP values.
+hipError_t launch_mlp_grad(const MlpArgs& a, float* grad, hipStream_t s);
 
 // Weight update, first kick and drift of a multipole step (the coefficients of
 // the new state and the second kick follow with launch_mp_build).

@@ -162,6 +162,7 @@ __global__ void __launch_bounds__(kMlpTrainThreads) mlp_train_kernel(MlpArgs a, 
     for (int o = kMlpTPS / 2; o > 0; o >>= 1) gp += __shfl_xor(gp, o, 64);   // the sample's kMlpTPS threads, in a fixed tree
     const float g = th[kThB3] + gp;
     const float dg = 2.0f * (g - smp.w) / float(a.batch);
+    if (a.loss && q == 0) a.loss[(size_t)blockIdx.x * kMlpSamples + s] = (g - smp.w) * (g - smp.w) / float(a.batch);
     #pragma unroll
     for (int k = 0; k < UPT; ++k) {
         const int o = q * UPT + k;
@@ -254,6 +255,25 @@ __global__ void __launch_bounds__(256) mlp_adam_kernel(MlpArgs a, int nblk, floa
     a.adam_m[j] = m;
     a.adam_v[j] = v;
     a.theta[j] -= a.lr * (m / c1) / (sqrtf(v / c2) + a.adam_eps);
+}
+
+// The minibatch gradient alone (the blocks' rows added as in mlp_adam_kernel).
+__global__ void __launch_bounds__(256) mlp_grad_sum_kernel(MlpArgs a, int nblk, float* grad) {
+    __shared__ double part[4][64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int j = blockIdx.x * 64 + lane;
+    const int jj = min(j, kMlpNP - 1);
+    double gs = 0.0;
+    for (int k0 = w; k0 < nblk; k0 += 4 * 8) {
+        float v[8];
+        #pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = a.gpart[(size_t)min(k0 + 4 * u, nblk - 1) * kMlpNP + jj];
+        #pragma unroll
+        for (int u = 0; u < 8; ++u) gs += k0 + 4 * u < nblk ? double(v[u]) : 0.0;
+    }
+    part[w][lane] = gs;
+    __syncthreads();
+    if (w == 0 && j < kMlpNP) grad[j] = float(((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane]);
 }
 
 // Block partials of the inference passes: thread values reduced in a fixed tree.
@@ -398,6 +418,13 @@ static hipError_t refresh_pot(const MlpArgs& a, int t0, hipStream_t s) {
     hipLaunchKernelGGL(mlp_judge_kernel, dim3(a.nblk), dim3(kMlpInferThreads), 0, s, a);
     hipLaunchKernelGGL(mlp_reduce_kernel, dim3(1), dim3(256), 0, s, a, 2);
     hipLaunchKernelGGL(mlp_select_kernel, dim3(a.nblk), dim3(kMlpInferThreads), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_grad(const MlpArgs& a, float* grad, hipStream_t s) {
+    const int nblk = a.batch / kMlpSamples;
+    hipLaunchKernelGGL(mlp_train_kernel, dim3(nblk), dim3(kMlpTrainThreads), 0, s, a, 0);
+    hipLaunchKernelGGL(mlp_grad_sum_kernel, dim3((kMlpNP + 63) / 64), dim3(256), 0, s, a, nblk, grad);
     return hipGetLastError();
 }
 

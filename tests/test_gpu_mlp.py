@@ -108,3 +108,73 @@ def test_full_size_refresh():
     mlp.run(om, lp, cfg["prior"], 1, oracle.subset)
     compare(ctx, om, lp, what_rtol=3e-4)
     np.testing.assert_allclose(m2m.m2m_weights(ctx).astype(np.float64), om.w, rtol=2e-6)
+
+
+def test_gradient_matches_oracle():
+    """The training kernels' loss and gradient at identical parameters and samples
+    against the FP64 backpropagation (itself pinned to finite differences): the
+    gradient within 1e-5 relative L2 (FP32), the loss within 1e-6."""
+    cfg, ctx, om, lp = setup(4096, 512, 128, 4)
+    rng = np.random.default_rng(11)
+    n = 4096
+    u = rng.uniform(-1.0, 1.0, (n, 3))
+    t = 0.7 * u[:, 0] - 0.4 * u[:, 1] * u[:, 2] + 0.1 * rng.normal(size=n) - 14.0
+    theta = cfg["prior"]["mlp_init"].astype(np.float32)
+    samples = np.column_stack([u, t]).astype(np.float32)
+    loss_g, grad_g = m2m.m2m_mlp_loss_grad(ctx, theta, samples)
+    loss_o, grad_o = mlp.loss_grad(theta.astype(np.float64), samples[:, :3].astype(np.float64),
+                                   samples[:, 3].astype(np.float64))
+    rel = np.linalg.norm(grad_g - grad_o) / np.linalg.norm(grad_o)
+    H.flush("gradient: rel L2 %.3g, loss GPU %.10g oracle %.10g" % (rel, loss_g, loss_o))
+    assert rel <= 1e-5
+    assert loss_g == pytest.approx(loss_o, rel=1e-6)
+
+
+def nn_log_roughness(cfg, ics, vals, Erange, Y, sigma):
+    """Mean |ln v_i - ln v_j| over each particle i and its nearest neighbour j in the
+    space of the prior's features (E, L/Lc, Lz/L), from the oracle's integrals."""
+    from scipy.spatial import cKDTree
+    m = oracle.Model(dict(cfg, prior=dict(cfg["prior"], kind="hist")), ics.astype(np.float64),
+                     np.ones(ics.shape[1]), Y, sigma, Erange=tuple(Erange))
+    E, L, Lz, Lc = m.integrals()
+    u = mlp.features(E, L, Lz, Lc, Erange[0], Erange[1])
+    _, j = cKDTree(u).query(u, k=2)
+    lv = np.log(np.asarray(vals, dtype=np.float64))
+    return float(np.mean(np.abs(lv - lv[j[:, 1]])))
+
+
+def test_learned_prior_gain_over_histogram_prior():
+    """What the trained network gains over the histogram prior it stands in for, at
+    equal mu (1e5: at the workload's mu = 5e-3 the entropy term is ~1e7 times
+    smaller than the chi^2 force and no prior changes the run): 2^18 particles,
+    2000 steps, refreshes every 25 steps on a 2^15 sample.  The learned prior is a
+    smooth function of the integrals, the histogram prior a noisy piecewise
+    constant: the learned prior must be at least twice as smooth (nearest
+    neighbours in feature space) at chi^2 within 5% of the histogram prior's, with
+    its fallback on.  (It does not lower chi^2 here: the entry records that too.)"""
+    base = configs.cfg5(N=1 << 18, target_n=1 << 20)
+    base["prior"].update(subset=1 << 15, batch=1024, period=25)
+    base["eps"] = 0.1 / (base["dt"] * derive_eps.max_abs_G(base))
+    base["mu"] = 1e5
+    inp = H.inputs(base)
+    er = H.erange(base, inp)
+    out = {}
+    for name, pr in (("hist", dict(base["prior"], kind="hist")), ("mlp", dict(base["prior"]))):
+        cfg = dict(base, prior=pr)
+        H.flush("case %s prior, N=%d mu=%g" % (name, cfg["N"], cfg["mu"]))
+        ctx = m2m.m2m_create(cfg, inp["ics"], inp["w"], inp["Y"], inp["sigma"], Erange=er)
+        st = m2m.m2m_step(ctx, 2000)[0]
+        x = m2m.m2m_particles(ctx)
+        what = m2m.m2m_priors(ctx)[0]
+        out[name] = (st["chi2"], nn_log_roughness(cfg, x, what, er, inp["Y"], inp["sigma"]),
+                     nn_log_roughness(cfg, x, m2m.m2m_weights(ctx), er, inp["Y"], inp["sigma"]), st["n_eff"])
+        if name == "mlp":
+            out["mlp_state"] = m2m.m2m_mlp_state(ctx)
+    (c_h, rp_h, rw_h, ne_h), (c_m, rp_m, rw_m, ne_m) = out["hist"], out["mlp"]
+    H.flush("hist: chi2 %.6g prior roughness %.4f weight roughness %.4f n_eff %.4g" % (c_h, rp_h, rw_h, ne_h))
+    H.flush("mlp:  chi2 %.6g prior roughness %.4f weight roughness %.4f n_eff %.4g (judge %.3f, fallback %s)" % (
+        c_m, rp_m, rw_m, ne_m, out["mlp_state"]["judge"], out["mlp_state"]["used_fallback"]))
+    assert not out["mlp_state"]["used_fallback"]
+    assert rp_m <= 0.5 * rp_h
+    assert c_m <= 1.05 * c_h
+    assert ne_m >= 0.9 * ne_h

@@ -198,6 +198,27 @@ def test_periodic_hist_prior(prec, period, nsteps, tol):
         assert r["S"] == pytest.approx(o[2], abs=tol * 30.0 * o[4])
 
 
+@pytest.mark.parametrize("period,nsteps", [(1, 4), (3, 7)])
+def test_large_hist_prior_cells_apart(period, nsteps):
+    """A 32x32x8 (E, L/Lc, Lz/L) histogram prior next to the 4896 observables (more
+    than the fused kernel's LDS holds): the cells are summed by their own kernel and
+    the priors gathered before each step.  Weights, chi^2 and the priors against the
+    oracle at the FP32 bar of the periodic prior."""
+    cfg = configs.cfg2(N=30000)
+    cfg["prior"] = {"kind": "hist", "axes": ("E", "L/Lc", "Lz/L"), "shape": (32, 32, 8), "period": period}
+    inp, ctx, (om,) = run_both(cfg, nsteps)
+    m2m.m2m_step(ctx, nsteps)
+    orows = om.run(nsteps)
+    np.testing.assert_allclose(m2m.m2m_weights(ctx).astype(np.float64), om.w, rtol=5e-6)
+    for r, o in zip(m2m.m2m_history(ctx), orows):
+        assert r["chi2"] == pytest.approx(o[0], rel=5e-6)
+    # priors of the next step: the oracle's cell means of the current state
+    what, cells = m2m.m2m_priors(ctx)
+    if (nsteps % period) == 0:
+        o_what = om.prior_means()[0]
+        np.testing.assert_allclose(what.astype(np.float64), o_what, rtol=5e-6)
+
+
 def test_batched_full_size_sampled_models():
     """The 64-model batch at its full size (sum N_m ~ 67M, one launch per step, the
     benchmark's launch shape): chi^2 and weights of sampled models after two steps
