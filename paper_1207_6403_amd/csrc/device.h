@@ -129,10 +129,14 @@ template <typename T> __device__ __forceinline__ T dexp(T v) { return exp(v); }
 template <typename T> __device__ __forceinline__ T dlog1p(T v) { return log1p(v); }
 // Fast forms for quantities that only feed guarded decisions or the orbit
 // integration (a few ulp in FP32; exact IEEE forms in FP64).
-__device__ __forceinline__ float qdiv(float a, float b) { return __fdividef(a, b); }
+// (a times the hardware reciprocal, 1 ulp: __fdividef still expands to the IEEE
+// division sequence here)
+__device__ __forceinline__ float qdiv(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
 __device__ __forceinline__ double qdiv(double a, double b) { return a / b; }
 __device__ __forceinline__ float qlog(float v) { return __logf(v); }
 __device__ __forceinline__ double qlog(double v) { return log(v); }
+__device__ __forceinline__ float qexp(float v) { return __expf(v); }
+__device__ __forceinline__ double qexp(double v) { return exp(v); }
 
 // Phi(x) and a = -grad Phi.  POT is the compile-time potential kind.
 template <int POT, typename T>

@@ -129,10 +129,12 @@ __device__ __forceinline__ T weight_update(const StepArgs<T, PT>& a, const Blk<T
     }
     const uint32_t wm = (fl >> kWhatShift) & 3u;
     const T wh = wm == 0 ? B.wflat : (wm == 3 ? what_p : B.cm[tg[kMaxBin]]);
-    const T lr = dlog(w / wh);
+    // (FP32: the hardware log, exp and reciprocal, a few ulp each; the FP64
+    // kernels use the exact forms)
+    const T lr = qlog(qdiv(w, wh));
     const T G = -chi - a.mu * (lr + T(1));
     const T edt = a.eps * a.dt;
-    const T wn = (fl & kExpLaw) ? w * dexp(edt * G) : w * (T(1) + edt * G);
+    const T wn = (fl & kExpLaw) ? w * qexp(edt * G) : w * (T(1) + edt * G);
     acc.S -= double(w) * double(lr);
     acc.W += double(w);
     acc.W2 += double(w) * double(w);
