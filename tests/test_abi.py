@@ -83,3 +83,68 @@ def test_target_size_mismatch_rejected():
     with pytest.raises(b.M2MError) as e:
         b.m2m_create(cfg, inp["ics"], inp["w"], inp["Y"][:-1], inp["sigma"][:-1])
     assert e.value.status == 1
+
+
+def _small_mlp():
+    cfg = configs.cfg5(N=256, target_n=1 << 12)
+    cfg["prior"].update(subset=256, batch=64, period=4)
+    inp = configs.make_inputs(cfg)
+    return cfg, inp
+
+
+@pytest.mark.parametrize("mutate,status,msg", [
+    (lambda c: c["prior"].update(batch=48), 1, "multiple of 32"),
+    (lambda c: c["prior"].update(subset=200), 1, "divide mlp_subset"),
+    (lambda c: c["prior"].update(lr=0.0), 1, "lr > 0"),
+    (lambda c: c["prior"].update(beta2=1.0), 1, "beta"),
+    (lambda c: c["prior"].__setitem__("mlp_init", np.full(4481, np.nan, dtype=np.float32)), 1, "finite"),
+    (lambda c: c.update(precision="f64"), 6, "FP32"),
+])
+def test_learned_prior_configuration_checked_without_device(mutate, status, msg):
+    """The learned prior's configuration is validated before any device work."""
+    cfg, inp = _small_mlp()
+    mutate(cfg)
+    ics = inp["ics"] if cfg["precision"] == "f64" else inp["ics"].astype(np.float32)
+    w = inp["w"] if cfg["precision"] == "f64" else inp["w"].astype(np.float32)
+    with pytest.raises(b.M2MError) as e:
+        b.m2m_create(cfg, ics, w, inp["Y"], inp["sigma"], Erange=np.array([-1.0, 0.0]))
+    assert e.value.status == status
+    assert msg in str(e.value)
+
+
+def test_learned_prior_needs_its_initial_parameters():
+    cfg, inp = _small_mlp()
+    del cfg["prior"]["mlp_init"]
+    with pytest.raises(b.M2MError) as e:
+        b.m2m_create(cfg, inp["ics"].astype(np.float32), inp["w"].astype(np.float32), inp["Y"], inp["sigma"],
+                     Erange=np.array([-1.0, 0.0]))
+    assert e.value.status == 1 and "mlp_init" in str(e.value)
+
+
+@pytest.mark.parametrize("mutate,status,msg", [
+    (lambda c: c["potential"].update(lmax=9), 1, "lmax"),
+    (lambda c: c["potential"].update(nodes=1), 1, "nnode"),
+    (lambda c: c["potential"].update(rmin=0.0), 1, "rmin"),
+    (lambda c: c["prior"].pop("ref_potential"), 1, "reference potential"),
+    (lambda c: c["prior"].update(ref_potential=dict(c["potential"])), 1, "reference potential"),
+])
+def test_multipole_configuration_checked_without_device(mutate, status, msg):
+    """Multipole parameters and the analytic reference its prior cells need."""
+    cfg = configs.cfg3(N=128, target_n=1 << 12)
+    inp = configs.make_inputs(cfg, dtype=np.float32)
+    mutate(cfg)
+    with pytest.raises(b.M2MError) as e:
+        b.m2m_create(cfg, inp["ics"], inp["w"], inp["Y"], inp["sigma"], Erange=np.array([-1.0, 0.0]))
+    assert e.value.status == status
+    assert msg in str(e.value)
+
+
+def test_multipole_models_run_alone():
+    """A multipole model shares its context with no other model."""
+    cfg = configs.cfg3(N=128, target_n=1 << 12)
+    inp = configs.make_inputs(cfg, dtype=np.float32)
+    cfg["potential"] = [dict(cfg["potential"]), dict(cfg["potential"])]
+    cfg["model_sizes"] = np.array([64, 64])
+    with pytest.raises(b.M2MError) as e:
+        b.m2m_create(cfg, inp["ics"], inp["w"], np.tile(inp["Y"], 1), inp["sigma"], Erange=np.array([-1.0, 0.0, -1.0, 0.0]))
+    assert e.value.status == 6 and "alone" in str(e.value)
