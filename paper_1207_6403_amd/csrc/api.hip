@@ -284,7 +284,10 @@ static m2m_status make_plan(m2m_ctx* c, int threads, int ilp, int bpc) {
     if ((s = upload(c, &p.chunk_desc, desc)) || (s = upload(c, &p.slot_base, sbase)) ||
         (s = upload(c, &p.slot_stride, sstride)))
         return s;
-    if ((s = dalloc(c, (char**)&p.part, npart * tsize(c))) || (s = dalloc(c, &p.seg_stats, (size_t)nslot * 4)) ||
+    // per-wave statistics rows, the identity where no wave writes
+    std::vector<double> st0((size_t)nslot * kStatWaves * 4, 0.0);
+    for (size_t r = 0; r < (size_t)nslot * kStatWaves; ++r) st0[4 * r + 3] = INFINITY;
+    if ((s = dalloc(c, (char**)&p.part, npart * tsize(c))) || (s = upload(c, &p.seg_stats, st0)) ||
         (s = dalloc(c, &p.erange_out, (size_t)nslot * 2)))
         return s;
     HIPCHK(c, hipMemset(p.part, 0, npart * tsize(c)));
@@ -293,8 +296,8 @@ static m2m_status make_plan(m2m_ctx* c, int threads, int ilp, int bpc) {
     const size_t ts = tsize(c);
     const int NCk = c->cells_apart ? 0 : c->NC;   // cells the fused kernel holds
     const int NCe = (NCk + 1) & ~1, NE = (c->nedge + 1) & ~1;
-    const int NET = (ts == 4 && NCk) ? kLcE : 0;
-    p.lds = 8 * ((size_t)c->JP + NCk + NE + 64 + NET) + 4 * (size_t)NCe + ts * ((size_t)c->JP + NCe + NE + kLcTab);
+    p.lds = 8 * ((size_t)c->JP + kTrash + NCk + kTrash + NE + 64) + 4 * ((size_t)NCe + kTrash) +
+            ts * ((size_t)c->JP + 2 + NCe + NE + kLcTab);
     p.lds = (p.lds + 15) & ~(size_t)15;
     if (p.lds > (size_t)c->max_lds)
         return fail(c, M2M_ERR_UNSUPPORTED, "layout needs " + std::to_string(p.lds) + " bytes of LDS per block (max " +
@@ -1117,8 +1120,8 @@ extern "C" m2m_status m2m_create(const m2m_config* cfg, const m2m_obs_layout* la
     {
         // LDS of the fused kernel with the prior cells (as make_plan computes it)
         const int NCe = (c->NC + 1) & ~1, NE = (c->nedge + 1) & ~1;
-        const size_t fused = 8 * ((size_t)c->JP + c->NC + NE + 64 + (c->NC ? kLcE : 0)) + 4 * (size_t)NCe +
-                             4 * ((size_t)c->JP + NCe + NE + kLcTab);
+        const size_t fused = 8 * ((size_t)c->JP + kTrash + c->NC + kTrash + NE + 64) +
+                             4 * ((size_t)NCe + kTrash) + 4 * ((size_t)c->JP + 2 + NCe + NE + kLcTab);
         // the learned prior's judge grid, and FP32 histogram priors too large for
         // the fused kernel, are accumulated by the cell kernel
         c->cells_apart = c->prec == M2M_F32 && (c->prior.kind == M2M_PRIOR_MLP ||

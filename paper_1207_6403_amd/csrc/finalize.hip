@@ -123,7 +123,7 @@ __global__ void __launch_bounds__(256) finalize_kernel(FinArgs<T, PT> a) {
         x2 += chi_prev[2 * k];
         x2i += chi_prev[2 * k + 1];
     }
-    for (int q = q0 + tid; q < q1; q += 256) {
+    for (int q = q0 * kStatWaves + tid; q < q1 * kStatWaves; q += 256) {   // per-wave rows of the slots
         S += a.seg_stats[4 * q];
         W += a.seg_stats[4 * q + 1];
         W2 += a.seg_stats[4 * q + 2];

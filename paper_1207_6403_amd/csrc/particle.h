@@ -21,18 +21,14 @@ __device__ __forceinline__ T wave_min(T v) {
     return v;
 }
 
-// Block-wide sum / min of four per-thread statistics into out[0..3] (thread 0).
-__device__ __forceinline__ void block_stats(double s, double w, double w2, double mn, double* red, double* out) {
+// Wave sum / min of four per-thread statistics into the wave's row of out
+// (out[4 w .. 4 w + 3] for wave w of the block): no block barrier.
+__device__ __forceinline__ void wave_stats(double s, double w, double w2, double mn, double* out) {
     s = wave_sum(s); w = wave_sum(w); w2 = wave_sum(w2); mn = wave_min(mn);
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    if (lane == 0) { red[4 * wid] = s; red[4 * wid + 1] = w; red[4 * wid + 2] = w2; red[4 * wid + 3] = mn; }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double a = 0, b = 0, c = 0, d = INFINITY;
-        for (int i = 0; i < nw; ++i) { a += red[4 * i]; b += red[4 * i + 1]; c += red[4 * i + 2]; d = fmin(d, red[4 * i + 3]); }
-        out[0] = a; out[1] = b; out[2] = c; out[3] = d;
+    if ((threadIdx.x & 63) == 0) {
+        double* o = out + 4 * (threadIdx.x >> 6);
+        o[0] = s; o[1] = w; o[2] = w2; o[3] = mn;
     }
-    __syncthreads();
 }
 
 // Per-block working set of one model (LDS tables and model constants).
@@ -89,16 +85,18 @@ __device__ __forceinline__ void st_at(void* base, uint32_t off, X v) {
     *reinterpret_cast<X*>(reinterpret_cast<char*>(base) + off) = v;
 }
 
-// Scatter w * K_j of one particle's bin k of binning b (moments of v_los = vl).
+// Scatter w * K_j of one particle's bin k of binning b (moments of v_los = vl);
+// when take is false the terms go to the lane's trash slot instead.
 template <uint64_t SIG, typename T>
-__device__ __forceinline__ void scatter_bin(const LayoutView<SIG, T>& V, double* hist, int b, int k, T wn, T vl) {
+__device__ __forceinline__ void scatter_bin(const LayoutView<SIG, T>& V, double* hist, int b, int k, bool take,
+                                            int trash, T wn, T vl) {
     const BinDesc<T>& d = V.L.b[b];
     const int base = d.off + k;
     const int nmom = V.nmom(b), mom = V.mom(b);
     #pragma unroll
     for (int mm = 0; mm < 3; ++mm) {
         if (mm >= nmom) break;
-        atomicAdd(&hist[base + mm * d.nb], double(wn * moment_value<T>((mom >> (2 * mm)) & 3, vl)));
+        atomicAdd(&hist[take ? base + mm * d.nb : trash], double(wn * moment_value<T>((mom >> (2 * mm)) & 3, vl)));
     }
 }
 
@@ -106,9 +104,11 @@ __device__ __forceinline__ void scatter_bin(const LayoutView<SIG, T>& V, double*
 // of eq. 2, the priors held fixed; exp law w exp(eps dt G) or Euler w (1 + eps
 // dt G)), from the kernel entries of its stored bins and the update table;
 // accumulates the statistics of w(n) and stores the prior a refresh step used.
-template <int NB, uint64_t SIG, typename T, typename PT>
+// ZSLOT >= 0: B.cl[ZSLOT] is zero, and bins without a particle read it instead
+// of branching (the fused kernel's LDS table); ZSLOT < 0: they are skipped.
+template <int NB, uint64_t SIG, int ZSLOT = -1, typename T, typename PT>
 __device__ __forceinline__ T weight_update(const StepArgs<T, PT>& a, const Blk<T>& B, Acc& acc, int64_t p, T vy, T vz,
-                                           T w, T what_p, const uint16_t (&tg)[kMaxBin + 1], uint32_t fl) {
+                                           T w, T what_p, const uint16_t (&tg)[kMaxBin + 1], uint32_t fl, int zslot = 0) {
     const Layout<T>& L = a.lay;
     const LayoutView<SIG, T> V{L};
     const int nbin = V.nbin();
@@ -118,13 +118,16 @@ __device__ __forceinline__ T weight_update(const StepArgs<T, PT>& a, const Blk<T
     for (int b = 0; b < NB; ++b) {
         if (b >= nbin) break;
         const int k = tg[b];
-        if (k == kNoBin) continue;
+        if constexpr (ZSLOT < 0) {
+            if (k == kNoBin) continue;
+        }
         const int base = L.b[b].off + k;
         const int nmom = V.nmom(b), mom = V.mom(b);
         #pragma unroll
         for (int mm = 0; mm < 3; ++mm) {
             if (mm >= nmom) break;
-            chi += moment_value<T>((mom >> (2 * mm)) & 3, vl) * B.cl[base + mm * L.b[b].nb];
+            const int j = (ZSLOT >= 0 && k == kNoBin) ? zslot : base + mm * L.b[b].nb;
+            chi += moment_value<T>((mom >> (2 * mm)) & 3, vl) * B.cl[j];
         }
     }
     const uint32_t wm = (fl >> kWhatShift) & 3u;

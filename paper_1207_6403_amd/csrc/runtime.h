@@ -9,6 +9,14 @@
 namespace m2m {
 
 constexpr int kRing = 4096;          // statistics rows kept per model
+// Per-lane trash slots after the fused kernel's LDS histograms and cell sums:
+// scatters of particles outside every bin, or whose decision the FP64 fix-up
+// takes later, land there instead of branching around the atomic.
+constexpr int kTrash = 64;
+// Weight statistics are written per wave: kStatWaves rows of (S, sum w, sum w^2,
+// min w) per partial slot (a block has at most 16 waves; rows of absent waves
+// hold the identity).
+constexpr int kStatWaves = 16;
 constexpr int kSlotsPerSplit = 32;   // partial slots in flight per finalise thread
 constexpr int kFinCols = 32;         // columns per finalise block
 constexpr int kFinGroups = 8;        // slot groups per column (256 threads)

@@ -39,7 +39,7 @@ __device__ __forceinline__ unsigned particle_step(const StepArgs<T, PT>& a, cons
     T wn = w, phi = T(0);
     bool have_phi = false;
     if (!(fl & kObserve)) {
-        wn = weight_update<NB, SIG>(a, B, acc, p, vy, vz, w, what_p, tg, fl);
+        wn = weight_update<NB, SIG, 0>(a, B, acc, p, vy, vz, w, what_p, tg, fl, a.jpad);
         if (!(fl & kFrozen)) {
             // kick-drift-kick
             T ax, ay, az;
@@ -63,40 +63,50 @@ __device__ __forceinline__ unsigned particle_step(const StepArgs<T, PT>& a, cons
     unsigned open = 0;
     const T vl = vy * L.sini + vz * L.cosi;
     const float Ys = float(y * L.cosi - z * L.sini);
+    // (no branches: a decision left open stores a provisional tag, which the
+    // fix-up overwrites, and scatters to the lane's trash slot, as does a
+    // particle outside the binning)
+    const int lane = threadIdx.x & 63;
     #pragma unroll
     for (int b = 0; b < NB; ++b) {
         if (b >= nbin) break;
         int k;
+        bool take;
         if constexpr (sizeof(T) == 4) {
             bool sure;
             k = bin_fast(L.b[b], V.kind(b), B.ed, x, y, z, Ys, sure);
-            if (!sure) { open |= 1u << b; continue; }
+            open |= sure ? 0u : 1u << b;
+            take = sure && k >= 0;
         } else {
             const Exact* ex = a.ex;
             const BinDesc<T>& d = L.b[b];
             k = bin_f64(V.kind(b), ex->cosd, ex->sind, ex->x0d[b], ex->wxd[b], d.nx, ex->y0d[b], ex->wyd[b], d.ny,
                         B.ed64 + d.edge0, d.nb + 1, x, y, z);
+            take = k >= 0;
         }
         st_at<uint16_t>(a.out, ot + b * (rb / uint32_t(sizeof(T)) * 2u), k < 0 ? kNoBin : (uint16_t)k);
-        if (k >= 0) scatter_bin(V, B.hist, b, k, wn, vl);
+        scatter_bin(V, B.hist, b, k, take, a.jpad + lane, wn, vl);
     }
     if (fl & kAccum) {
         if (!have_phi) {
             T ax, ay, az;
             potential<POT, T>(B.pot, x, y, z, phi, ax, ay, az);
         }
-        int cell;
+        int cell = 0;
+        bool sure = true;
         if constexpr (sizeof(T) == 4) {
             const float E = 0.5f * (vx * vx + vy * vy + vz * vz) + phi;
-            if (!cell_fast<POT>(B.pot, B.et, a.cells, B.Emin, B.sE, E, x, y, z, vx, vy, vz, cell))
-                return open | (1u << NB);
+            sure = cell_fast<POT>(B.pot, B.et, a.cells, B.Emin, B.sE, E, x, y, z, vx, vy, vz, cell);
+            open |= sure ? 0u : 1u << NB;
+            if (!sure) cell = 0;
         } else {
             cell = prior_cell_f64<POT>(B.pot, B.lct, a.cells, a.ex->erange[2 * B.m], a.ex->erange[2 * B.m + 1], x, y, z,
                                        vx, vy, vz);
         }
         st_at<uint16_t>(a.out, ot + a.cellrow * (rb / uint32_t(sizeof(T)) * 2u), (uint16_t)cell);
-        atomicAdd(&B.csum[cell], double(wn));
-        atomicAdd(&B.ccnt[cell], 1u);
+        const int ci = sure ? cell : a.cells.ncell + lane;
+        atomicAdd(&B.csum[ci], double(wn));
+        atomicAdd(&B.ccnt[ci], 1u);
     }
     return open;
 }
@@ -162,15 +172,13 @@ __global__ void __launch_bounds__(sizeof(T) == 8 ? 256 : 1024) step_kernel(StepA
     constexpr bool F32 = sizeof(T) == 4;
     const int J = a.lay.J, NC = a.cells.ncell, JP = a.jpad, NE = (a.nedge + 1) & ~1;
     const int nt = blockDim.x, tid = threadIdx.x;
-    double* hist = reinterpret_cast<double*>(smem);                 // J (padded to JP)
-    double* csum = hist + JP;                                        // NC
-    double* ed64 = csum + NC;                                        // edges, FP64
+    double* hist = reinterpret_cast<double*>(smem);                 // J (padded to JP), then kTrash
+    double* csum = hist + JP + kTrash;                               // NC, then kTrash
+    double* ed64 = csum + NC + kTrash;                               // edges, FP64
     double* red = ed64 + NE;                                         // 4 * 16
-    const int NET = (F32 && NC) ? kLcE : 0;
-    float2* et = reinterpret_cast<float2*>(red + 64);                // uniform-E Lc table (FP32)
-    unsigned* ccnt = reinterpret_cast<unsigned*>(et + NET);          // NC (padded to even)
-    T* cl = reinterpret_cast<T*>(ccnt + ((NC + 1) & ~1));            // J : Dt_j / sigma_j
-    T* cm = cl + JP;                                                 // NC: cell means
+    unsigned* ccnt = reinterpret_cast<unsigned*>(red + 64);          // NC (padded to even), then kTrash
+    T* cl = reinterpret_cast<T*>(ccnt + ((NC + 1) & ~1) + kTrash);   // J : Dt_j / sigma_j, zero to JP + 2
+    T* cm = cl + JP + 2;                                             // NC: cell means
     T* ed = cm + ((NC + 1) & ~1);                                    // edges in T
     T* lct = ed + NE;                                                // circular-orbit energies (FP64)
 
@@ -185,7 +193,7 @@ __global__ void __launch_bounds__(sizeof(T) == 8 ? 256 : 1024) step_kernel(StepA
     int slot = ro(a.block_slot0, blockIdx.x) - 1;
     int cur = -1;
     Blk<T> B;
-    B.hist = hist; B.csum = csum; B.ccnt = ccnt; B.cl = cl; B.cm = cm; B.ed = ed; B.ed64 = ed64; B.et = et;
+    B.hist = hist; B.csum = csum; B.ccnt = ccnt; B.cl = cl; B.cm = cm; B.ed = ed; B.ed64 = ed64;
     B.lct = lct;
     Acc acc;
     if (failed) return;
@@ -253,7 +261,7 @@ __global__ void __launch_bounds__(sizeof(T) == 8 ? 256 : 1024) step_kernel(StepA
                 if (accum)
                     for (int c = tid; c < NC; c += nt) { at(JP + 2 * c) = PT(csum[c]); at(JP + 2 * c + 1) = PT(ccnt[c]); }
                 // (observing only, the statistics belong to the kernel that updated the weights)
-                if (stepping) block_stats(acc.S, acc.W, acc.W2, acc.mn, red, a.seg_stats + 4 * (size_t)slot);
+                if (stepping) wave_stats(acc.S, acc.W, acc.W2, acc.mn, a.seg_stats + 4 * kStatWaves * (size_t)slot);
                 acc.S = acc.W = acc.W2 = 0;
                 acc.mn = INFINITY;
             }
@@ -267,11 +275,13 @@ __global__ void __launch_bounds__(sizeof(T) == 8 ? 256 : 1024) step_kernel(StepA
             B.wflat = ro(a.flatw, m);
             __syncthreads();
             for (int j = tid; j < J; j += nt) { hist[j] = 0.0; cl[j] = a.cvec[(size_t)m * J + j]; }
+            if (tid < JP + 2 - J) cl[J + tid] = T(0);   // the entries bins without a particle read
             if (accum) for (int c = tid; c < NC; c += nt) { csum[c] = 0.0; ccnt[c] = 0u; }
             if (want_cm) for (int c = tid; c < NC; c += nt) cm[c] = a.cellmean[(size_t)m * NC + c];
             if (NC && !F32) for (int i = tid; i < kLcTab; i += nt) lct[i] = a.lctab[(size_t)B.pot.lc_off + i];
-            for (int i = tid; i < NET; i += nt)
-                et[i] = make_float2(a.lcetab[2 * ((size_t)m * kLcE + i)], a.lcetab[2 * ((size_t)m * kLcE + i) + 1]);
+            // the uniform-E Lc table of the model, read from global memory (L1/L2):
+            // in LDS it would leave room for one block per CU only
+            B.et = reinterpret_cast<const float2*>(a.lcetab) + (size_t)m * kLcE;
             __syncthreads();
         }
         // this tile's particles (their loads were issued one tile ago), then the
