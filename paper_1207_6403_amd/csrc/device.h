@@ -358,8 +358,13 @@ template <int POT>
 __device__ __forceinline__ bool cell_fast(const Pot<float>& p, const float2* __restrict__ et, const Cells& c,
                                           float Emin, float sE, float E, float x, float y, float z, float vx, float vy,
                                           float vz, int& cell) {
-    const float Lx = y * vz - z * vy, Ly = z * vx - x * vz, Lz = x * vy - y * vx;
-    const float L = sqrtf(Lx * Lx + Ly * Ly + Lz * Lz);
+    const int n0 = opaque(c.n0), n1 = opaque(c.n1), n2 = opaque(c.n2), ax2 = opaque(c.ax2);
+    const float Lz = x * vy - y * vx;
+    float L = 0.0f;
+    if (ax2 == 0 || n2 > 1) {   // |L| only for the L/Lc and Lz/L axes
+        const float Lx = y * vz - z * vy, Ly = z * vx - x * vz;
+        L = sqrtf(Lx * Lx + Ly * Ly + Lz * Lz);
+    }
     float Lc, err = 2e-6f;
     if (POT == 0) {
         // Hernquist closed form (see circular_L)
@@ -373,7 +378,6 @@ __device__ __forceinline__ bool cell_fast(const Pot<float>& p, const float2* __r
         return false;
     }
     if (!(Lc > 0.0f)) return false;
-    const int n0 = opaque(c.n0), n1 = opaque(c.n1), n2 = opaque(c.n2), ax2 = opaque(c.ax2);
     const float fE = (E - Emin) * sE;
     const float iLc = qdiv(1.0f, Lc);
     const float f2 = ax2 == 0 ? L * iLc * float(n1) : (Lz * iLc + 1.0f) * 0.5f * float(n1);

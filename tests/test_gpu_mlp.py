@@ -178,3 +178,24 @@ def test_learned_prior_gain_over_histogram_prior():
     assert rp_m <= 0.5 * rp_h
     assert c_m <= 1.05 * c_h
     assert ne_m >= 0.9 * ne_h
+
+
+def test_learned_prior_on_a_multipole_model():
+    """The learned prior of a self-consistent multipole model (features in the
+    analytic reference potential): one refresh and two steps against the oracle."""
+    cfg = configs.cfg3(N=12007, target_n=1 << 16)
+    c5 = configs.cfg5(N=16)
+    cfg["prior"] = dict(c5["prior"], subset=2048, batch=256, period=2, fallback=1e9,
+                        ref_potential=dict(configs.LOG_POT))
+    cfg["eps"] = 0.1 / (cfg["dt"] * derive_eps.max_abs_G(cfg))
+    inp = H.inputs(cfg)
+    er = H.erange(cfg, inp)
+    ctx = m2m.m2m_create(cfg, inp["ics"], inp["w"], inp["Y"], inp["sigma"], Erange=er)
+    (om,) = H.oracle_models(cfg, inp, er)
+    pr = cfg["prior"]
+    lp = mlp.LearnedPrior(pr["mlp_init"], pr["lr"], pr["beta1"], pr["beta2"], pr["adam_eps"], pr["seed"],
+                          pr["subset"], pr["batch"], pr["fallback"])
+    m2m.m2m_step(ctx, 2)
+    mlp.run(om, lp, pr, 2, oracle.subset)
+    compare(ctx, om, lp)
+    np.testing.assert_allclose(m2m.m2m_weights(ctx).astype(np.float64), om.w, rtol=1e-5)

@@ -223,3 +223,20 @@ def test_full_size_one_step():
     np.testing.assert_allclose(xg, xo, rtol=2e-6, atol=2e-6 * np.abs(xo).max())
     assert st["chi2"] == pytest.approx(ost[0], rel=1e-6)
     check_tables(ctx, cfg["potential"], om, xo, om.w, 2e-5, ics_gpu=xg)
+
+
+@pytest.mark.parametrize("precision,lmax,nodes,period", [("f64", 4, 50, 1), ("f32", 4, 50, 3), ("f32", 8, 120, 2)])
+def test_other_expansions_and_prior_periods(precision, lmax, nodes, period):
+    """Other truncations and node counts (the terms above lmax stay zero in the
+    tables), and a histogram prior refreshed every P steps: weights and tables
+    after three steps against the oracle."""
+    cfg = small(20011, precision)
+    cfg["potential"] = dict(cfg["potential"], lmax=lmax, nodes=nodes)
+    cfg["prior"] = dict(cfg["prior"], period=period)
+    inp, ctx, om = start(cfg)
+    m2m.m2m_step(ctx, 3)
+    om.run(3)
+    f64 = precision == "f64"
+    np.testing.assert_allclose(m2m.m2m_weights(ctx).astype(np.float64), om.w, rtol=1e-10 if f64 else 1e-5)
+    xg = m2m.m2m_particles(ctx).astype(np.float64)
+    check_tables(ctx, cfg["potential"], om, om.ics(), om.w, 1e-11 if f64 else 4e-5, ics_gpu=xg)
