@@ -133,7 +133,9 @@ typedef struct {
     int32_t ax2;
     int32_t n[3];
     int32_t period;
-    const double *Erange;    /* host, 2 * n_models (Emin, Emax) or NULL: min/max of E(0) */
+    const double *Erange;    /* host, 2 * n_models (Emin, Emax), copied at creation;
+                                or NULL: per model, min and max of E(0) over its
+                                particles, computed in FP64 from the stored values */
     double flat_value;
     m2m_potential ref;
     int32_t mlp_subset, mlp_batch;
@@ -233,6 +235,19 @@ m2m_status m2m_priors(m2m_ctx *ctx, void *what_out, double *cell_mean, int32_t d
 
 /* Current particles, 6 * N values SoA (same layout as m2m_create). */
 m2m_status m2m_particles(m2m_ctx *ctx, void *xv_out, int32_t device_ptr);
+
+/* Decisions stored with the current state (section 2: the observables are
+ * kernel sums over bins of the particles' coordinates; section 2.1: the moving
+ * prior averages over cells of the integrals of motion).  out receives
+ * (nbin + 1) * N uint16 values, row-major: row b < nbin holds each particle's
+ * bin within binning b (grid pixel iy * nx + ix, or shell/annulus index; 0xFFFF
+ * outside the binning), row nbin its prior cell ((iE * n1 + i2) * n2 + i3).
+ * The cell row is defined when the moving prior took the cells of the current
+ * state: always for a period of 1, else when the step index is a multiple of
+ * the period; otherwise (and for a flat prior) its contents are unspecified.
+ * Host or device memory (device_ptr), owned by the caller; synchronises the
+ * context's stream.  M2M_ERR_INVALID for a null argument. */
+m2m_status m2m_tags(m2m_ctx *ctx, uint16_t *out, int32_t device_ptr);
 
 /* Statistics rows of the most recent steps, oldest first (ring of the last
  * 4096 steps per model).  out holds max_rows rows; *n_rows gets the count. */

@@ -91,6 +91,7 @@ def lib():
         L.or_kernel.argtypes = [C.POINTER(Layout)] + [C.c_double] * 6 + [C.POINTER(C.c_int32), DP]
         L.or_kernel.restype = C.c_int
         L.or_cell.argtypes = [C.POINTER(Prior)] + [C.c_double] * 6
+        L.or_bins.argtypes = [C.POINTER(Layout), C.c_int64, DP, DP, DP, C.POINTER(C.c_int32)]
         L.or_cells.argtypes = [C.POINTER(Prior), C.c_int64] + [DP] * 6 + [C.POINTER(C.c_int32)]
         L.or_prior_means.argtypes = [C.POINTER(Prior), C.c_int64] + [DP] * 10
         L.or_integrals.argtypes = [C.POINTER(Prior), C.c_int64] + [DP] * 10
@@ -322,6 +323,16 @@ def kernel_entries(layout, z):
     K = (C.c_double * 12)()
     n = lib().or_kernel(C.byref(Lc), *[float(v) for v in z], jj, K)
     return [(jj[e], K[e]) for e in range(n)]
+
+
+def bins(layout, pos):
+    """Bin of every position (pos: [3, N]) in every binning, [nbin, N] int32, -1 outside."""
+    keep = []
+    Lc = make_layout(layout, keep)
+    x, y, z = (_f64(pos[k]) for k in range(3))
+    out = np.empty((Lc.nbin, x.size), dtype=np.int32)
+    lib().or_bins(C.byref(Lc), x.size, _dp(x), _dp(y), _dp(z), out.ctypes.data_as(C.POINTER(C.c_int32)))
+    return out
 
 
 def circular_L(pot, E):

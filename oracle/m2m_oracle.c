@@ -199,28 +199,33 @@ static int edge_bin(const double *e, int ne, double r) {
     return k;
 }
 
+/* Bin of the position (x, y, z) in binning b, -1 outside (section 2: each
+ * observable is the weighted count, or LOS moment, of the particles in one bin
+ * of a binning of the projected or spatial coordinates).  Shells bin the
+ * radius r, annuli the projected radius, grids the sky plane (x, y cos i -
+ * z sin i) into nx * ny pixels numbered iy * nx + ix. */
+static int bin_of(const or_layout *L, int b, double ci, double si, double x, double y, double z) {
+    double X = x, Ys = y * ci - z * si;
+    if (L->kind[b] == OR_BIN_SHELL)
+        return edge_bin(L->edge[b], L->nedge[b], sqrt(x * x + y * y + z * z));
+    if (L->kind[b] == OR_BIN_ANNULUS)
+        return edge_bin(L->edge[b], L->nedge[b], sqrt(X * X + Ys * Ys));
+    double fx = floor((X - L->x0[b]) / (L->x1[b] - L->x0[b]) * L->nx[b]);
+    double fy = floor((Ys - L->y0[b]) / (L->y1[b] - L->y0[b]) * L->ny[b]);
+    if (fx >= 0 && fx < L->nx[b] && fy >= 0 && fy < L->ny[b])
+        return (int)fy * L->nx[b] + (int)fx;
+    return -1;
+}
+
 int or_kernel(const or_layout *L, double x, double y, double z,
               double vx, double vy, double vz, int32_t *jidx, double *Kval) {
     (void)vx;
     double ci = cos(L->incl), si = sin(L->incl);
-    double X = x, Ys = y * ci - z * si;
     double vl = vy * si + vz * ci;
     int cnt = 0, off = 0;
     for (int b = 0; b < L->nbin; ++b) {
-        int nb, k = -1;
-        if (L->kind[b] == OR_BIN_SHELL) {
-            nb = L->nedge[b] - 1;
-            k = edge_bin(L->edge[b], L->nedge[b], sqrt(x * x + y * y + z * z));
-        } else if (L->kind[b] == OR_BIN_ANNULUS) {
-            nb = L->nedge[b] - 1;
-            k = edge_bin(L->edge[b], L->nedge[b], sqrt(X * X + Ys * Ys));
-        } else {
-            nb = L->nx[b] * L->ny[b];
-            double fx = floor((X - L->x0[b]) / (L->x1[b] - L->x0[b]) * L->nx[b]);
-            double fy = floor((Ys - L->y0[b]) / (L->y1[b] - L->y0[b]) * L->ny[b]);
-            if (fx >= 0 && fx < L->nx[b] && fy >= 0 && fy < L->ny[b])
-                k = (int)fy * L->nx[b] + (int)fx;
-        }
+        int nb = L->kind[b] == OR_BIN_GRID ? L->nx[b] * L->ny[b] : L->nedge[b] - 1;
+        int k = bin_of(L, b, ci, si, x, y, z);
         for (int m = 0; m < L->nmom[b]; ++m) {
             if (k >= 0) {
                 int mo = L->mom[b][m];
@@ -232,6 +237,15 @@ int or_kernel(const or_layout *L, double x, double y, double z,
         off += L->nmom[b] * nb;
     }
     return cnt;
+}
+
+/* Bin of every particle in every binning: bin[b * N + i], -1 outside. */
+void or_bins(const or_layout *L, int64_t N, const double *x, const double *y, const double *z, int32_t *bin) {
+    double ci = cos(L->incl), si = sin(L->incl);
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < N; ++i)
+        for (int b = 0; b < L->nbin; ++b)
+            bin[(int64_t)b * N + i] = bin_of(L, b, ci, si, x[i], y[i], z[i]);
 }
 
 /* ------------------------------------------------------------------- priors

@@ -103,6 +103,7 @@ def lib():
         L.m2m_weights.argtypes = [CTX, VP, C.c_int32]
         L.m2m_priors.argtypes = [CTX, VP, C.POINTER(C.c_double), C.c_int32]
         L.m2m_particles.argtypes = [CTX, VP, C.c_int32]
+        L.m2m_tags.argtypes = [CTX, VP, C.c_int32]
         L.m2m_history.argtypes = [CTX, C.POINTER(m2m_step_stats), C.c_int64, C.POINTER(C.c_int64)]
         L.m2m_multipole_tables.argtypes = [CTX, C.POINTER(C.c_double), C.POINTER(C.c_double)]
         L.m2m_mlp_state.argtypes = [CTX, C.POINTER(C.c_float), C.POINTER(C.c_double), C.POINTER(C.c_int32),
@@ -207,8 +208,9 @@ def pack_prior(pr, n_models, keep, Erange=None, ref=None):
 class Context:
     """Handle of one m2m_ctx plus the host copies the call needed to stay alive."""
 
-    def __init__(self, ptr, n, J, n_models, dtype, ncell):
+    def __init__(self, ptr, n, J, n_models, dtype, ncell, nbin):
         self.ptr = ptr
+        self.nbin = nbin
         self.N = n
         self.J = J
         self.n_models = n_models
@@ -288,7 +290,7 @@ def m2m_create(cfg, xv, w, Y, sigma, Erange=None, device_ptrs=False, stream=None
         raise M2MError(st, m2m_last_error(None))
     pr = cfg["prior"]
     ncell = 0 if pr["kind"] == "flat" else int(np.prod(pr["shape"]))
-    return Context(out, n, t.J, M, dt, ncell)
+    return Context(out, n, t.J, M, dt, ncell, lay.nbin)
 
 
 def _stats_dict(s):
@@ -337,6 +339,17 @@ def m2m_particles(ctx, out=None):
     xv = np.zeros((6, ctx.N), dtype=ctx.dtype)
     _check(lib().m2m_particles(ctx.ptr, C.c_void_p(xv.ctypes.data), 0), ctx)
     return xv
+
+
+def m2m_tags(ctx, out=None):
+    """Stored bin (rows 0..nbin-1, 0xFFFF outside) and prior-cell (row nbin)
+    decisions of the current state, [nbin + 1, N] uint16."""
+    if out is not None:
+        _check(lib().m2m_tags(ctx.ptr, C.c_void_p(int(out.data_ptr())), 1), ctx)
+        return out
+    t = np.zeros((ctx.nbin + 1, ctx.N), dtype=np.uint16)
+    _check(lib().m2m_tags(ctx.ptr, C.c_void_p(t.ctypes.data), 0), ctx)
+    return t
 
 
 def m2m_history(ctx, max_rows=None):

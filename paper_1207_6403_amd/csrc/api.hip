@@ -649,7 +649,7 @@ static m2m_status derive_erange_T(m2m_ctx* c, std::vector<double>& er) {
     a.tile_cnt = p.tile_cnt;
     a.block_tile0 = p.block_tile0;
     a.block_slot0 = p.block_slot0;
-    a.pots = (const Pot<T>*)c->pots_d;
+    a.pots = (const Pot<double>*)c->pots64;
     a.out = p.erange_out;
     HIPCHK(c, launch_erange<T>(a, c->pot_kind, p.nblock, c->stream));
     std::vector<double> h((size_t)p.nslot * 2);
@@ -736,6 +736,10 @@ static Layout<T> layout_of(const m2m_ctx* c) {
             B.sx = (T)(d.nx / (d.x1 - d.x0));
             B.y0 = (T)d.y0;
             B.sy = (T)(d.ny / (d.y1 - d.y0));
+            const double u = std::ldexp(1.0, -24), sx = d.nx / (d.x1 - d.x0), sy = d.ny / (d.y1 - d.y0);
+            B.gx0 = (T)(2.0 * u * sx * std::fabs(d.x0));
+            B.gy0 = (T)(2.0 * u * sy * std::fabs(d.y0));
+            B.gys = (T)(6.0 * u * sy);
         } else {
             B.nb = d.nedge - 1;
             e0 += d.nedge;
@@ -1011,7 +1015,7 @@ static m2m_status create_T(m2m_ctx* c, const m2m_target* tg, const void* xv, con
     if ((s = make_plan(c, c->launch.threads, c->launch.ilp, c->launch.blocks_per_cu))) return s;
     std::vector<double> er(2 * (size_t)c->M, 0.0);
     if (c->prior.kind != M2M_PRIOR_FLAT) {
-        if (c->prior.Erange) for (size_t k = 0; k < er.size(); ++k) er[k] = c->prior.Erange[k];
+        if (!c->erange_user.empty()) er = c->erange_user;
         else if ((s = derive_erange_T<T>(c, er))) return s;
     }
     c->erange_host = er;
@@ -1080,6 +1084,7 @@ extern "C" m2m_status m2m_create(const m2m_config* cfg, const m2m_obs_layout* la
     }
     c->pot_kind = c->pots[0].kind;
     c->prior = cfg->prior;
+    if (cfg->prior.Erange) c->erange_user.assign(cfg->prior.Erange, cfg->prior.Erange + 2 * (size_t)c->M);
     c->prior.Erange = nullptr;
     if (cfg->prior.kind == M2M_PRIOR_MLP) c->mlp_init_host.assign(cfg->prior.mlp_init, cfg->prior.mlp_init + M2M_MLP_NPARAM);
     c->prior.mlp_init = nullptr;
@@ -1309,6 +1314,16 @@ extern "C" m2m_status m2m_weights(m2m_ctx* c, void* w_out, int32_t device_ptr) {
 extern "C" m2m_status m2m_particles(m2m_ctx* c, void* xv_out, int32_t device_ptr) {
     if (!c || !xv_out) return fail(c, M2M_ERR_INVALID, "null argument");
     return copy_rows(c, xv_out, 0, 6, device_ptr);
+}
+
+extern "C" m2m_status m2m_tags(m2m_ctx* c, uint16_t* out, int32_t device_ptr) {
+    if (!c || !out) return fail(c, M2M_ERR_INVALID, "null argument");
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    const uint16_t* src = tags(c, (int)(c->step & 1));
+    for (int k = 0; k <= c->lay.nbin; ++k)
+        HIPCHK(c, hipMemcpy(out + (size_t)k * c->N, src + (size_t)k * c->stride, sizeof(uint16_t) * c->N,
+                            device_ptr ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost));
+    return M2M_OK;
 }
 
 template <typename T>

@@ -22,8 +22,13 @@ constexpr int kMaxBin = 4;
 constexpr int kMaxEntries = 3 * kMaxBin;   // kernel entries K_j per particle (fixed slots)
 constexpr int kLcTab = 256;                // circular-orbit energies per model (FP64 path)
 constexpr int kLcE = 2048;                 // uniform-E Lc(E) table per model (FP32 path)
-constexpr float kGuardBin = 1e-4f;         // guard band, in bins, of the FP32 bin coordinates
 constexpr float kGuardCell = 1e-4f;        // guard band, in cells, of the FP32 prior coordinates
+// Guard bands of the FP32 bin decisions: twice a bound on the difference between
+// the FP32 coordinate and the FP64 one computed from the same FP32 particle (u =
+// 2^-24, the FP32 unit roundoff), plus a floor that keeps a coordinate exactly
+// on an edge open.
+constexpr float kU32 = 5.9604645e-8f;
+constexpr float kGuardBinFloor = 1e-6f;    // bins
 
 // Potential parameters with derived constants.
 template <typename T>
@@ -56,6 +61,10 @@ struct BinDesc {
     int32_t kind, nmom, mom, off;   // off: first observable index of the binning
     int32_t nb, edge0, nx, ny;      // nb: bins per moment
     T x0, sx, y0, sy;
+    // FP32 grid guard terms (bins): gx0 = 2u sx |x0|, gy0 = 2u sy |y0| (the
+    // rounded origins), gys = 6u sy (the rounded projection, per unit of
+    // |y cos i| + |z sin i|)
+    T gx0, gy0, gys;
 };
 
 template <typename T>
@@ -423,20 +432,29 @@ __device__ __forceinline__ int bin_f64(int kind, double cosd, double sind, doubl
 
 // Bin of binning b (kind `kind`) in FP32, -1 outside; sure = false when the
 // coordinate lies within the guard band of an edge (the caller re-decides with
-// bin_f64).
+// bin_f64).  Ys = y cos i - z sin i in FP32 and aYs = |y cos i| + |z sin i|.
+// Guards (twice the bound, u = 2^-24):
+//   grid x: fx = (x - x0) sx carries the rounding of x0 (u |x0| sx) and three
+//     relative roundings (the difference, sx, the product): 2(u sx |x0| + 3u |fx|);
+//   grid y: the same plus the projection, two roundings per product (cos i or
+//     sin i, the product) and one of the difference, <= 3u aYs, times sy;
+//   radius: the sum of squares (3u, halved by the root), the root (2u) and the
+//     rounded edge (u) stay below 12u r; the projected radius adds 6u aYs.
 __device__ __forceinline__ int bin_fast(const BinDesc<float>& d, int kind, const float* __restrict__ ef, float x,
-                                        float y, float z, float Ys, bool& sure) {
+                                        float y, float z, float Ys, float aYs, bool& sure) {
     if (kind == 3) {
         const float fx = (x - d.x0) * d.sx;
         const float fy = (Ys - d.y0) * d.sy;
-        sure = !near_cell_edge(fx, d.nx, kGuardBin) && !near_cell_edge(fy, d.ny, kGuardBin);
+        const float gx = d.gx0 + 6.0f * kU32 * fabsf(fx) + kGuardBinFloor;
+        const float gy = d.gy0 + d.gys * aYs + 6.0f * kU32 * fabsf(fy) + kGuardBinFloor;
+        sure = !near_cell_edge(fx, d.nx, gx) && !near_cell_edge(fy, d.ny, gy);
         if (fx >= 0.0f && fx < float(d.nx) && fy >= 0.0f && fy < float(d.ny)) return int(fy) * d.nx + int(fx);
         return -1;
     }
     const float rad = kind == 1 ? __builtin_sqrtf(x * x + y * y + z * z) : __builtin_sqrtf(x * x + Ys * Ys);
     const float* e = ef + d.edge0;
     const int ne = d.nb + 1;
-    const float g = kGuardBin * rad;
+    const float g = 12.0f * kU32 * rad + (kind == 1 ? 0.0f : 6.0f * kU32 * aYs);
     const int k = edge_bin(e, ne, rad);
     if (k >= 0) sure = !(rad - e[k] < g) && !(e[k + 1] - rad < g);
     else sure = !(fabsf(rad - e[0]) < g) && !(fabsf(rad - e[ne - 1]) < g) && rad == rad;

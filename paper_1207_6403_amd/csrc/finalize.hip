@@ -123,11 +123,25 @@ __global__ void __launch_bounds__(256) finalize_kernel(FinArgs<T, PT> a) {
         x2 += chi_prev[2 * k];
         x2i += chi_prev[2 * k + 1];
     }
-    for (int q = q0 * kStatWaves + tid; q < q1 * kStatWaves; q += 256) {   // per-wave rows of the slots
-        S += a.seg_stats[4 * q];
-        W += a.seg_stats[4 * q + 1];
-        W2 += a.seg_stats[4 * q + 2];
-        mn = fmin(mn, a.seg_stats[4 * q + 3]);
+    // per-wave rows of the slots, kStatRows per thread in flight before the first
+    // wait (one dependent round trip per 256 * kStatRows rows, not per 256)
+    constexpr int kStatRows = 16;
+    const double2* rows = reinterpret_cast<const double2*>(a.seg_stats);
+    for (int r0 = q0 * kStatWaves, r1 = q1 * kStatWaves; r0 < r1; r0 += 256 * kStatRows) {
+        double2 v0[kStatRows], v1[kStatRows];
+        #pragma unroll
+        for (int u = 0; u < kStatRows; ++u) {
+            const int q = r0 + u * 256 + tid;
+            v0[u] = q < r1 ? rows[2 * q] : make_double2(0.0, 0.0);
+            v1[u] = q < r1 ? rows[2 * q + 1] : make_double2(0.0, INFINITY);
+        }
+        #pragma unroll
+        for (int u = 0; u < kStatRows; ++u) {
+            S += v0[u].x;
+            W += v0[u].y;
+            W2 += v1[u].x;
+            mn = fmin(mn, v1[u].y);
+        }
     }
     x2 = fwave_sum(x2); x2i = fwave_sum(x2i); S = fwave_sum(S); W = fwave_sum(W); W2 = fwave_sum(W2);
     #pragma unroll

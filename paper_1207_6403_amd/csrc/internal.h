@@ -39,6 +39,7 @@ struct m2m_ctx {
     m2m_obs_layout lay{};
     std::vector<double> edges_host[M2M_MAX_BINNINGS];
     std::vector<double> erange_host;
+    std::vector<double> erange_user;   // the caller's (Emin, Emax) per model, if given
     std::vector<float> lce_host;   // per model: origin and inverse spacing of the uniform-E tables
     int64_t N = 0, stride = 0;
     int J = 0, JP = 0, NC = 0, pcols = 0, nedge = 0;

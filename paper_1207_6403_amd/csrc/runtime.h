@@ -113,7 +113,7 @@ struct ErangeArgs {
     const int32_t* tile_cnt;
     const int32_t* block_tile0;
     const int32_t* block_slot0;
-    const Pot<T>* pots;
+    const Pot<double>* pots;      // FP64: E(0) of the particles as stored, in FP64
     double* out;   // 2 * nslot
 };
 

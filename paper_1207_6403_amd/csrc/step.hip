@@ -62,7 +62,8 @@ __device__ __forceinline__ unsigned particle_step(const StepArgs<T, PT>& a, cons
     // bins and cell of the new state
     unsigned open = 0;
     const T vl = vy * L.sini + vz * L.cosi;
-    const float Ys = float(y * L.cosi - z * L.sini);
+    const float yc = float(y * L.cosi), zs = float(z * L.sini);
+    const float Ys = yc - zs, aYs = fabsf(yc) + fabsf(zs);
     // (no branches: a decision left open stores a provisional tag, which the
     // fix-up overwrites, and scatters to the lane's trash slot, as does a
     // particle outside the binning)
@@ -74,7 +75,7 @@ __device__ __forceinline__ unsigned particle_step(const StepArgs<T, PT>& a, cons
         bool take;
         if constexpr (sizeof(T) == 4) {
             bool sure;
-            k = bin_fast(L.b[b], V.kind(b), B.ed, x, y, z, Ys, sure);
+            k = bin_fast(L.b[b], V.kind(b), B.ed, x, y, z, Ys, aYs, sure);
             open |= sure ? 0u : 1u << b;
             take = sure && k >= 0;
         } else {
@@ -307,13 +308,15 @@ __global__ void __launch_bounds__(sizeof(T) == 8 ? 256 : 1024) step_kernel(StepA
 }
 
 // ---------------------------------------------------- energy range (at create)
+// Min and max of E(0) over each model's particles, in FP64 from the stored
+// values (the range the prior's energy axis spans when the caller gives none).
 template <typename T, int POT>
 __global__ void __launch_bounds__(256) erange_kernel(ErangeArgs<T> a) {
     __shared__ double rmin[4], rmax[4];
     const int t0 = a.block_tile0[blockIdx.x], t1 = a.block_tile0[blockIdx.x + 1];
     int slot = a.block_slot0[blockIdx.x] - 1, cur = -1;
     double lo = INFINITY, hi = -INFINITY;
-    Pot<T> pot;
+    Pot<double> pot;
     for (int t = t0; t <= t1; ++t) {
         const int m = t < t1 ? a.tile_model[t] : -2;
         if (m != cur) {
@@ -342,9 +345,9 @@ __global__ void __launch_bounds__(256) erange_kernel(ErangeArgs<T> a) {
             const int64_t p = p0 + i;
             T x = a.in[p], y = a.in[a.stride + p], z = a.in[2 * a.stride + p];
             T vx = a.in[3 * a.stride + p], vy = a.in[4 * a.stride + p], vz = a.in[5 * a.stride + p];
-            T phi, ax, ay, az;
-            potential<POT, T>(pot, x, y, z, phi, ax, ay, az);
-            const double E = double(T(0.5) * (vx * vx + vy * vy + vz * vz) + phi);
+            double phi, ax, ay, az;
+            potential<POT, double>(pot, double(x), double(y), double(z), phi, ax, ay, az);
+            const double E = 0.5 * (double(vx) * vx + double(vy) * vy + double(vz) * vz) + phi;
             lo = fmin(lo, E);
             hi = fmax(hi, E);
         }
