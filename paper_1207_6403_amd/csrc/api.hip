@@ -195,7 +195,7 @@ static m2m_status validate(const m2m_config* cfg, const m2m_obs_layout* lay, con
 static void free_plan(m2m_ctx* c) {
     Plan& p = c->plan;
     for (void* q : {(void*)p.tile_model, (void*)p.tile_p0, (void*)p.tile_cnt, (void*)p.block_tile0,
-                    (void*)p.block_slot0, (void*)p.model_slot, (void*)p.part, (void*)p.seg_stats,
+                    (void*)p.block_slot0, (void*)p.block_desc, (void*)p.model_slot, (void*)p.part, (void*)p.seg_stats,
                     (void*)p.erange_out, (void*)p.chunk_desc, (void*)p.slot_base, (void*)p.slot_stride})
         dfree(c, q);
     p = Plan();
@@ -243,13 +243,26 @@ static m2m_status make_plan(m2m_ctx* c, int threads, int ilp, int bpc) {
         }
     }
     mslot[c->M] = nslot;
+    std::vector<BlockDesc> bdesc(B);
+    for (int64_t b = 0; b < B; ++b) {
+        BlockDesc& d = bdesc[b];
+        d = BlockDesc{};
+        d.t0 = bt0[b];
+        d.t1 = bt0[b + 1];
+        d.slot0 = bs0[b];
+        if (d.t0 < d.t1) {
+            d.m0 = tm[d.t0];
+            d.p0 = tp[d.t0];
+            d.cnt0 = tc[d.t0];
+        }
+    }
     p.ntile = T;
     p.nblock = (int)B;
     p.nslot = nslot;
     m2m_status s;
     if ((s = upload(c, &p.tile_model, tm)) || (s = upload(c, &p.tile_p0, tp)) || (s = upload(c, &p.tile_cnt, tc)) ||
         (s = upload(c, &p.block_tile0, bt0)) || (s = upload(c, &p.block_slot0, bs0)) ||
-        (s = upload(c, &p.model_slot, mslot)))
+        (s = upload(c, &p.block_desc, bdesc)) || (s = upload(c, &p.model_slot, mslot)))
         return s;
     // partial slots, chunk-major: for model m, chunk k (kFinCols columns) of all
     // the model's slots is one contiguous block, so each finalise block reads
@@ -368,6 +381,7 @@ static void fill_step_args(m2m_ctx* c, StepArgs<T, T>& a, int parity, int mode, 
     a.tile_cnt = p.tile_cnt;
     a.block_tile0 = p.block_tile0;
     a.block_slot0 = p.block_slot0;
+    a.block_desc = p.block_desc;
     a.pots = (const Pot<T>*)c->pots_d;
     a.lctab = (const T*)c->lctab;
     a.lcetab = (const float*)c->lcetab;
@@ -380,6 +394,7 @@ static void fill_step_args(m2m_ctx* c, StepArgs<T, T>& a, int parity, int mode, 
     a.slot_stride = p.slot_stride;
     a.seg_stats = p.seg_stats;
     a.edges = (const T*)c->edges;
+    a.edges64 = c->edges64;
     a.nedge = c->nedge;
     a.pcols = c->pcols;
     a.jpad = c->JP;

@@ -66,7 +66,7 @@ __global__ void __launch_bounds__(1024) cells_kernel(StepArgs<float, float> a) {
             potential<POT, float>(pot, x, y, z, phi, ax, ay, az);
             const float E = 0.5f * (vx * vx + vy * vy + vz * vz) + phi;
             int cell;
-            if (!cell_fast<POT>(pot, et, a.cells, Emin, sE, E, x, y, z, vx, vy, vz, cell)) {
+            if (cell_fast<POT>(pot, et, a.cells, Emin, sE, E, x, y, z, vx, vy, vz, cell) != 0u) {
                 const Exact* ex = a.ex;
                 const Pot<double>& pd = ex->pots[m];
                 cell = prior_cell_seeded<POT>(pd, ex->lctab + pd.lc_off, ex->rce + (size_t)m * kLcE, double(pot.lcE0),

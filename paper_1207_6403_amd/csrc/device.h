@@ -274,15 +274,19 @@ __device__ __forceinline__ bool near_cell_edge(float f, int n, float g) {
 // uniform over [Emin, Emax], then L/Lc in [0, 1] or Lz/Lc in [-1, 1], then
 // optionally Lz/L in [-1, 1]; coordinates outside a range take the edge cell.
 // Lc < 0 marks an unbound energy (infinite Lc), Lc = 0 a degenerate one.
+__device__ __forceinline__ int cell_axis_E(const Cells& c, double Emin, double Emax, double E) {
+    return clamp_cell((E - Emin) / (Emax - Emin) * c.n0, c.n0);
+}
+__device__ __forceinline__ int cell_axis_2(const Cells& c, double L, double Lz, double Lc) {
+    if (c.ax2 == 0) return clamp_cell((Lc > 0 ? L / Lc : (Lc < 0 ? 0.0 : 1e300)) * c.n1, c.n1);
+    return clamp_cell(((Lc > 0 ? Lz / Lc : (Lc < 0 ? 0.0 : (Lz > 0 ? 1e300 : -1e300))) + 1.0) * 0.5 * c.n1, c.n1);
+}
+__device__ __forceinline__ int cell_axis_3(const Cells& c, double L, double Lz) {
+    return c.n2 > 1 ? clamp_cell(((L > 0 ? Lz / L : 0.0) + 1.0) * 0.5 * c.n2, c.n2) : 0;
+}
 __device__ __forceinline__ int cell_index(const Cells& c, double Emin, double Emax, double E, double L, double Lz,
                                           double Lc) {
-    const int iE = clamp_cell((E - Emin) / (Emax - Emin) * c.n0, c.n0);
-    int i2;
-    if (c.ax2 == 0) i2 = clamp_cell((Lc > 0 ? L / Lc : (Lc < 0 ? 0.0 : 1e300)) * c.n1, c.n1);
-    else i2 = clamp_cell(((Lc > 0 ? Lz / Lc : (Lc < 0 ? 0.0 : (Lz > 0 ? 1e300 : -1e300))) + 1.0) * 0.5 * c.n1, c.n1);
-    int i3 = 0;
-    if (c.n2 > 1) i3 = clamp_cell(((L > 0 ? Lz / L : 0.0) + 1.0) * 0.5 * c.n2, c.n2);
-    return (iE * c.n1 + i2) * c.n2 + i3;
+    return (cell_axis_E(c, Emin, Emax, E) * c.n1 + cell_axis_2(c, L, Lz, Lc)) * c.n2 + cell_axis_3(c, L, Lz);
 }
 
 // Cell of the moving prior in FP64, Lc(E) from the circular-orbit table.
@@ -304,32 +308,43 @@ __device__ __forceinline__ int prior_cell_f64(const Pot<double>& p, const double
 // three steps reach FP64 precision), the Hernquist closed form, or the
 // circular-orbit table (gtab, device memory) outside the seed table.
 template <int POT>
+__device__ __forceinline__ double energy64(const Pot<double>& p, double x, double y, double z, double vx, double vy,
+                                          double vz) {
+    double phi, ax, ay, az;
+    potential<POT, double>(p, x, y, z, phi, ax, ay, az);
+    return 0.5 * (vx * vx + vy * vy + vz * vz) + phi;
+}
+__device__ __forceinline__ void angmom64(double x, double y, double z, double vx, double vy, double vz, double& L,
+                                         double& Lz) {
+    const double Lx = y * vz - z * vy, Ly = z * vx - x * vz;
+    Lz = x * vy - y * vx;
+    L = sqrt(Lx * Lx + Ly * Ly + Lz * Lz);
+}
+template <int POT>
+__device__ __forceinline__ double lc_seeded(const Pot<double>& p, const double* __restrict__ gtab,
+                                           const float* __restrict__ rce, double E0, double invh, double E) {
+    const double t = (E - E0) * invh;
+    if (POT == 0 || !(t >= 0.0) || !(t < double(kLcE - 1))) return circular_L<POT, double, 5>(p, gtab, E);
+    const int k = int(t);
+    double r = exp(double(rce[k]) + (t - k) * double(rce[k + 1] - rce[k]));
+    #pragma unroll
+    for (int it = 0; it < 3; ++it) {
+        double ph, d1, d2;
+        radial_derivs<POT, double>(p, r, ph, d1, d2);
+        r = r - (ph + 0.5 * r * d1 - E) / (0.5 * (3.0 * d1 + r * d2));
+    }
+    double ph, d1, d2;
+    radial_derivs<POT, double>(p, r, ph, d1, d2);
+    return r * sqrt(r * d1);
+}
+template <int POT>
 __device__ __forceinline__ void integrals_seeded(const Pot<double>& p, const double* __restrict__ gtab,
                                                  const float* __restrict__ rce, double E0, double invh, double x,
                                                  double y, double z, double vx, double vy, double vz, double& E,
                                                  double& L, double& Lz, double& Lc) {
-    double phi, ax, ay, az;
-    potential<POT, double>(p, x, y, z, phi, ax, ay, az);
-    E = 0.5 * (vx * vx + vy * vy + vz * vz) + phi;
-    const double Lx = y * vz - z * vy, Ly = z * vx - x * vz;
-    Lz = x * vy - y * vx;
-    L = sqrt(Lx * Lx + Ly * Ly + Lz * Lz);
-    const double t = (E - E0) * invh;
-    if (POT == 0 || !(t >= 0.0) || !(t < double(kLcE - 1))) {
-        Lc = circular_L<POT, double, 5>(p, gtab, E);
-    } else {
-        const int k = int(t);
-        double r = exp(double(rce[k]) + (t - k) * double(rce[k + 1] - rce[k]));
-        #pragma unroll
-        for (int it = 0; it < 3; ++it) {
-            double ph, d1, d2;
-            radial_derivs<POT, double>(p, r, ph, d1, d2);
-            r = r - (ph + 0.5 * r * d1 - E) / (0.5 * (3.0 * d1 + r * d2));
-        }
-        double ph, d1, d2;
-        radial_derivs<POT, double>(p, r, ph, d1, d2);
-        Lc = r * sqrt(r * d1);
-    }
+    E = energy64<POT>(p, x, y, z, vx, vy, vz);
+    angmom64(x, y, z, vx, vy, vz, L, Lz);
+    Lc = lc_seeded<POT>(p, gtab, rce, E0, invh, E);
 }
 
 // Cell of the moving prior in FP64 for a decision the FP32 path left open.
@@ -360,13 +375,15 @@ __device__ __forceinline__ bool lc_from_table(const float2* __restrict__ et, flo
     return true;
 }
 
-// Cell of the moving prior from FP32 values, or false when a coordinate lies
-// within the guard band of a cell edge (or outside the Lc table): the caller
-// then re-decides in FP64 with prior_cell_f64.
+// Cell of the moving prior from FP32 values.  Returns the axes whose FP32
+// coordinate lies within the guard band of a cell edge (bit 0: E, bit 1: L/Lc
+// or Lz/Lc, also when Lc(E) is not in the table or not positive, bit 2: Lz/L);
+// the caller re-decides those in FP64.  cell is the index from the clamped FP32
+// coordinates of every axis (exact on the axes not returned).
 template <int POT>
-__device__ __forceinline__ bool cell_fast(const Pot<float>& p, const float2* __restrict__ et, const Cells& c,
-                                          float Emin, float sE, float E, float x, float y, float z, float vx, float vy,
-                                          float vz, int& cell) {
+__device__ __forceinline__ unsigned cell_fast(const Pot<float>& p, const float2* __restrict__ et, const Cells& c,
+                                              float Emin, float sE, float E, float x, float y, float z, float vx,
+                                              float vy, float vz, int& cell) {
     const int n0 = opaque(c.n0), n1 = opaque(c.n1), n2 = opaque(c.n2), ax2 = opaque(c.ax2);
     const float Lz = x * vy - y * vx;
     float L = 0.0f;
@@ -374,19 +391,19 @@ __device__ __forceinline__ bool cell_fast(const Pot<float>& p, const float2* __r
         const float Lx = y * vz - z * vy, Ly = z * vx - x * vz;
         L = sqrtf(Lx * Lx + Ly * Ly + Lz * Lz);
     }
-    float Lc, err = 2e-6f;
+    float Lc = 1.0f, err = 2e-6f;
+    bool have = true;
     if (POT == 0) {
         // Hernquist closed form (see circular_L)
-        if (!(E < 0.0f)) return false;
         const float D = p.GM * p.GM - 8.0f * E * p.GM * p.a;
         const float rc = 4.0f * p.a * (p.GM + E * p.a) / (sqrtf(D) - p.GM - 4.0f * E * p.a);
-        if (!(rc > 0.0f)) return false;
+        have = E < 0.0f && rc > 0.0f;
         Lc = rc * sqrtf(p.GM * rc) / (rc + p.a);
         err = 1e-5f;
-    } else if (!lc_from_table(et, p.lcE0, p.lcEinv, E, Lc, err)) {
-        return false;
+    } else {
+        have = lc_from_table(et, p.lcE0, p.lcEinv, E, Lc, err);
     }
-    if (!(Lc > 0.0f)) return false;
+    have = have && Lc > 0.0f;
     const float fE = (E - Emin) * sE;
     const float iLc = qdiv(1.0f, Lc);
     const float f2 = ax2 == 0 ? L * iLc * float(n1) : (Lz * iLc + 1.0f) * 0.5f * float(n1);
@@ -394,11 +411,11 @@ __device__ __forceinline__ bool cell_fast(const Pot<float>& p, const float2* __r
     // a relative error err of Lc moves f2 by at most |f2| err (L/Lc axis) or
     // |f2 - n1/2| err (Lz/Lc axis)
     const float g2 = kGuardCell + (ax2 == 0 ? fabsf(f2) : fabsf(f2 - 0.5f * float(n1))) * err;
-    if (near_cell_edge(fE, n0, kGuardCell) || near_cell_edge(f2, n1, g2) ||
-        (n2 > 1 && near_cell_edge(f3, n2, kGuardCell)))
-        return false;
-    cell = (clamp_cell(fE, n0) * n1 + clamp_cell(f2, n1)) * n2 + (n2 > 1 ? clamp_cell(f3, n2) : 0);
-    return true;
+    unsigned open = near_cell_edge(fE, n0, kGuardCell) ? 1u : 0u;
+    open |= (!have || near_cell_edge(f2, n1, g2)) ? 2u : 0u;
+    open |= (n2 > 1 && near_cell_edge(f3, n2, kGuardCell)) ? 4u : 0u;
+    cell = (clamp_cell(fE, n0) * n1 + (have ? clamp_cell(f2, n1) : 0)) * n2 + (n2 > 1 ? clamp_cell(f3, n2) : 0);
+    return open;
 }
 
 // ---------------------------------------------------------------- observables

@@ -19,6 +19,7 @@ struct Plan {
     int32_t* tile_cnt = nullptr;
     int32_t* block_tile0 = nullptr;
     int32_t* block_slot0 = nullptr;
+    m2m::BlockDesc* block_desc = nullptr;
     int32_t* model_slot = nullptr;
     int32_t* chunk_desc = nullptr;   // 8 per finalise chunk: model, col0, ncol, slot0, nslot, base
     int64_t* slot_base = nullptr;    // per slot: index of its first column in `part`

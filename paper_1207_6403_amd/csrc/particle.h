@@ -73,6 +73,23 @@ __device__ __forceinline__ X ro(const X* p, int64_t i) {
     }
 }
 
+// Pull every 64-byte line of the kernel's argument block into the scalar cache
+// in one round trip (one word per line, all loads issued before the first
+// wait): the compiler places each argument load next to its first use, and
+// those loads then hit the cache instead of waiting on memory one after the
+// other.
+template <int BYTES>
+__device__ __forceinline__ void warm_kernargs() {
+    using cU32 = const __attribute__((address_space(4))) uint32_t;
+    cU32* k = (cU32*)__builtin_amdgcn_kernarg_segment_ptr();
+    constexpr int kLines = (BYTES + 63) / 64;
+    uint32_t v[kLines];
+    #pragma unroll
+    for (int i = 0; i < kLines; ++i) v[i] = k[16 * i];
+    #pragma unroll
+    for (int i = 0; i < kLines; ++i) asm volatile("" ::"s"(v[i]));
+}
+
 // Value at byte offset off from base.  Every row of a state buffer (values,
 // then tags) is addressed from the buffer's base with a 32-bit byte offset
 // (state buffers are smaller than 4 GiB), so one scalar base serves all rows.

@@ -21,6 +21,15 @@ constexpr int kSlotsPerSplit = 32;   // partial slots in flight per finalise thr
 constexpr int kFinCols = 32;         // columns per finalise block
 constexpr int kFinGroups = 8;        // slot groups per column (256 threads)
 
+// Where a block of the fused kernel starts, in one load: its tiles [t0, t1),
+// its first partial slot, the model of its first tile and that tile's first
+// particle and count (the rest of the tiles come from the tile tables).
+struct BlockDesc {
+    int32_t t0, t1, slot0, m0;
+    int64_t p0;
+    int32_t cnt0, reserved;
+};
+
 struct StatRow {
     double chi2, chi2_inst, S, F, sum_w, min_w, sum_w2, n_eff;
     long long step;
@@ -41,6 +50,7 @@ struct StepArgs {
     const int32_t* tile_cnt;
     const int32_t* block_tile0;   // nblocks + 1
     const int32_t* block_slot0;   // first partial slot of each block
+    const BlockDesc* block_desc;  // nblocks
     const Pot<T>* pots;           // per model
     const T* lctab;               // kLcTab circular-orbit energies per model
     const float* lcetab;          // kLcE (Lc, error bound) pairs per model (FP32 path)
@@ -53,6 +63,7 @@ struct StepArgs {
     const int32_t* slot_stride;   //   slot_stride[q] + j % kFinCols]
     double* seg_stats;            // nslot * 4
     const T* edges;
+    const double* edges64;        // the same edges in FP64
     int32_t nedge;
     int32_t pcols, jpad;
     Layout<T> lay;

@@ -23,12 +23,19 @@ namespace m2m {
 // scatter into the histograms.  With kObserve the particle is neither updated
 // nor moved: its current bins and cell are decided and stored.
 // FP32 kernels decide in FP32; a decision inside its guard band is left open
-// and flagged in the returned mask (bit b: binning b, bit NB: the cell), to be
-// re-taken in FP64 by fixup(); FP64 kernels decide in FP64 and return 0.
+// and flagged in the returned mask (bit b: binning b, bits NB..NB+2: the cell's
+// axes), to be re-taken in FP64 by fixup() from the new state kept in `kp`;
+// FP64 kernels decide in FP64 and return 0.
+template <typename T>
+struct Keep {
+    T x, y, z, vx, vy, vz, w, vl;
+    int cell;   // from the FP32 coordinates (exact on the axes not left open)
+};
+
 template <int POT, int NB, uint64_t SIG, typename T, typename PT>
 __device__ __forceinline__ unsigned particle_step(const StepArgs<T, PT>& a, const Blk<T>& B, Acc& acc, int64_t p,
                                                   T x, T y, T z, T vx, T vy, T vz, T w, T what_p,
-                                                  const uint16_t (&tg)[kMaxBin + 1]) {
+                                                  const uint16_t (&tg)[kMaxBin + 1], Keep<T>& kp) {
     const Layout<T>& L = a.lay;
     const LayoutView<SIG, T> V{L};
     const uint32_t fl = opaque(a.flags);
@@ -88,51 +95,50 @@ __device__ __forceinline__ unsigned particle_step(const StepArgs<T, PT>& a, cons
         st_at<uint16_t>(a.out, ot + b * (rb / uint32_t(sizeof(T)) * 2u), k < 0 ? kNoBin : (uint16_t)k);
         scatter_bin(V, B.hist, b, k, take, a.jpad + lane, wn, vl);
     }
+    int cell = 0;
     if (fl & kAccum) {
         if (!have_phi) {
             T ax, ay, az;
             potential<POT, T>(B.pot, x, y, z, phi, ax, ay, az);
         }
-        int cell = 0;
-        bool sure = true;
+        unsigned am = 0;
         if constexpr (sizeof(T) == 4) {
             const float E = 0.5f * (vx * vx + vy * vy + vz * vz) + phi;
-            sure = cell_fast<POT>(B.pot, B.et, a.cells, B.Emin, B.sE, E, x, y, z, vx, vy, vz, cell);
-            open |= sure ? 0u : 1u << NB;
-            if (!sure) cell = 0;
+            am = cell_fast<POT>(B.pot, B.et, a.cells, B.Emin, B.sE, E, x, y, z, vx, vy, vz, cell);
+            open |= am << NB;
         } else {
             cell = prior_cell_f64<POT>(B.pot, B.lct, a.cells, a.ex->erange[2 * B.m], a.ex->erange[2 * B.m + 1], x, y, z,
                                        vx, vy, vz);
         }
         st_at<uint16_t>(a.out, ot + a.cellrow * (rb / uint32_t(sizeof(T)) * 2u), (uint16_t)cell);
-        const int ci = sure ? cell : a.cells.ncell + lane;
+        const int ci = am == 0 ? cell : a.cells.ncell + lane;
         atomicAdd(&B.csum[ci], double(wn));
         atomicAdd(&B.ccnt[ci], 1u);
     }
+    kp.x = x; kp.y = y; kp.z = z; kp.vx = vx; kp.vy = vy; kp.vz = vz; kp.w = wn; kp.vl = vl;
+    kp.cell = cell;
     return open;
 }
 
 // Address-space-qualified pointers for the out-of-line fix-up: its arguments
 // keep their memory kinds, so neither side falls back to flat addressing.
 using cExact = const __attribute__((address_space(4))) Exact;
-using gF32 = const __attribute__((address_space(1))) float;
 using gU16 = __attribute__((address_space(1))) uint16_t;
 using lF64 = __attribute__((address_space(3))) double;
 using lU32 = __attribute__((address_space(3))) unsigned;
 
 // The decisions particle_step left open (mask `open`), taken in FP64 from the
-// FP32 coordinates of the new state (read back from the particle's own stores,
-// or from the input when observing only), then stored and scattered.  Out of
-// line: it runs for a few particles in ten thousand, and inlined its FP64
-// working set would raise the register use of the whole kernel.
+// FP32 coordinates of the new state (kept in registers: x..vz, the weight wn,
+// v_los vl and the FP32 cell), then stored and scattered.  Only the open axes
+// of the cell are re-taken: E needs one FP64 potential, L/Lc or Lz/Lc the
+// circular-orbit Lc(E) as well, Lz/L neither.  Out of line: it runs for about
+// one particle in a thousand, and inlined its FP64 working set would raise the
+// register use of the whole kernel.
 template <int POT, int NB>
 __device__ __noinline__ void fixup(cExact* ex, int m, unsigned open, int64_t p, int64_t stride, int cellrow,
-                                   gF32* src, gU16* tout, lF64* hist, lF64* csum, lU32* ccnt, float lcE0,
+                                   float x, float y, float z, float vx, float vy, float vz, float wn, float vl,
+                                   int cell, gU16* tout, lF64* hist, lF64* csum, lU32* ccnt, float lcE0,
                                    float lcEinv) {
-    const float x = src[p], y = src[stride + p], z = src[2 * stride + p];
-    const float vx = src[3 * stride + p], vy = src[4 * stride + p], vz = src[5 * stride + p];
-    const float wn = src[6 * stride + p];
-    const float vl = vy * ex->lay.sini + vz * ex->lay.cosi;
     #pragma unroll
     for (int b = 0; b < NB; ++b) {
         if (!(open & (1u << b))) continue;
@@ -146,29 +152,54 @@ __device__ __noinline__ void fixup(cExact* ex, int m, unsigned open, int64_t p, 
             __hip_atomic_fetch_add(&hist[base + mm * nb], double(wn * moment_value<float>((mom >> (2 * mm)) & 3, vl)),
                                    __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     }
-    if (open & (1u << NB)) {
-        const Pot<double> pd = ex->pots[m];
+    const unsigned am = (open >> NB) & 7u;
+    if (am) {
         Cells cells;
         cells.n0 = ex->cells.n0;
         cells.n1 = ex->cells.n1;
         cells.n2 = ex->cells.n2;
         cells.ax2 = ex->cells.ax2;
         cells.ncell = ex->cells.ncell;
-        const int cell = prior_cell_seeded<POT>(pd, ex->lctab + pd.lc_off, ex->rce + (size_t)m * kLcE, double(lcE0),
-                                                double(lcEinv), cells, ex->erange[2 * m], ex->erange[2 * m + 1],
-                                                double(x), double(y), double(z), double(vx), double(vy), double(vz));
-        tout[cellrow * stride + p] = (uint16_t)cell;
-        __hip_atomic_fetch_add(&csum[cell], double(wn), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-        __hip_atomic_fetch_add(&ccnt[cell], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        const int n1 = cells.n1, n2 = cells.n2;
+        int iE = cell / (n1 * n2), i2 = (cell / n2) % n1, i3 = cell % n2;
+        const double X = x, Y = y, Z = z, VX = vx, VY = vy, VZ = vz;
+        if (am & 3u) {
+            const Pot<double> pd = ex->pots[m];
+            const double E = energy64<POT>(pd, X, Y, Z, VX, VY, VZ);
+            if (am & 1u) iE = cell_axis_E(cells, ex->erange[2 * m], ex->erange[2 * m + 1], E);
+            if (am & 2u) {
+                double L, Lz;
+                angmom64(X, Y, Z, VX, VY, VZ, L, Lz);
+                const double Lc = lc_seeded<POT>(pd, ex->lctab + pd.lc_off, ex->rce + (size_t)m * kLcE,
+                                                 double(lcE0), double(lcEinv), E);
+                i2 = cell_axis_2(cells, L, Lz, Lc);
+            }
+        }
+        if (am & 4u) {
+            double L, Lz;
+            angmom64(X, Y, Z, VX, VY, VZ, L, Lz);
+            i3 = cell_axis_3(cells, L, Lz);
+        }
+        const int c = (iE * n1 + i2) * n2 + i3;
+        tout[cellrow * stride + p] = (uint16_t)c;
+        __hip_atomic_fetch_add(&csum[c], double(wn), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        __hip_atomic_fetch_add(&ccnt[c], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     }
 }
 
 template <typename T, typename PT, int POT, int NB, uint64_t SIG, int ILP>
 __global__ void __launch_bounds__(sizeof(T) == 8 ? 256 : 1024) step_kernel(StepArgs<T, PT> a) {
     extern __shared__ __align__(16) unsigned char smem[];
-    // an earlier step failed: the whole step is a no-op (the flag is checked
-    // before the first store; the table loads need not wait for it)
-    const int failed = *a.flag;
+    warm_kernargs<sizeof(StepArgs<T, PT>)>();
+    // an earlier step failed: the whole step is a no-op (the flag, as it stood
+    // when the kernel started, is read through the scalar cache and checked
+    // after the first model's tables are in LDS and before the first store, so
+    // that no load of the prologue waits for it)
+    const int failed = ro(a.flag, 0);
+    // the block's start in one load; everything the prologue loads next (model
+    // tables, the update table, cell means, the first tile's particles) depends
+    // on it alone
+    const BlockDesc bd = ro(a.block_desc, blockIdx.x);
 
     constexpr bool F32 = sizeof(T) == 4;
     const int J = a.lay.J, NC = a.cells.ncell, JP = a.jpad, NE = (a.nedge + 1) & ~1;
@@ -183,21 +214,20 @@ __global__ void __launch_bounds__(sizeof(T) == 8 ? 256 : 1024) step_kernel(StepA
     T* ed = cm + ((NC + 1) & ~1);                                    // edges in T
     T* lct = ed + NE;                                                // circular-orbit energies (FP64)
 
-    for (int i = tid; i < a.nedge; i += nt) { ed[i] = a.edges[i]; ed64[i] = a.ex->edges[i]; }
+    for (int i = tid; i < a.nedge; i += nt) { ed[i] = a.edges[i]; ed64[i] = a.edges64[i]; }
 
-    const int t0 = ro(a.block_tile0, blockIdx.x), t1 = ro(a.block_tile0, blockIdx.x + 1);
+    const int t0 = bd.t0, t1 = bd.t1;
     const uint32_t fl = a.flags;
     const uint32_t wm = (fl >> kWhatShift) & 3u;
     const bool want_cm = wm == 1 || wm == 2;
     const bool accum = fl & kAccum;
     const bool stepping = !(fl & kObserve);
-    int slot = ro(a.block_slot0, blockIdx.x) - 1;
+    int slot = bd.slot0 - 1;
     int cur = -1;
     Blk<T> B;
     B.hist = hist; B.csum = csum; B.ccnt = ccnt; B.cl = cl; B.cm = cm; B.ed = ed; B.ed64 = ed64;
     B.lct = lct;
     Acc acc;
-    if (failed) return;
 
     // the particles of a tile (values and the tags of the current state); the
     // next tile's are loaded while this one is processed
@@ -205,9 +235,7 @@ __global__ void __launch_bounds__(sizeof(T) == 8 ? 256 : 1024) step_kernel(StepA
         T x[ILP], y[ILP], z[ILP], vx[ILP], vy[ILP], vz[ILP], w[ILP], wh[ILP];
         uint16_t tg[ILP][kMaxBin + 1];
     };
-    auto load_tile = [&](int t, Regs& R) {
-        const int64_t p0 = ro(a.tile_p0, t);
-        const int cnt = ro(a.tile_cnt, t);
+    auto load_tile = [&](int64_t p0, int cnt, Regs& R) {
         #pragma unroll
         for (int k = 0; k < ILP; ++k) {
             const int i = k * nt + tid;
@@ -232,8 +260,11 @@ __global__ void __launch_bounds__(sizeof(T) == 8 ? 256 : 1024) step_kernel(StepA
         }
     };
     Regs next_r;
-    if (t0 < t1) load_tile(t0, next_r);
+    int64_t next_p0 = bd.p0;
+    int next_cnt = bd.cnt0;
+    if (t0 < t1) load_tile(next_p0, next_cnt, next_r);
     unsigned open[ILP];   // decisions left open in the previous tile
+    Keep<T> kp[ILP];      // and its particles' new state
     int64_t p_open = 0;   // its first particle
     #pragma unroll
     for (int k = 0; k < ILP; ++k) open[k] = 0u;
@@ -246,11 +277,12 @@ __global__ void __launch_bounds__(sizeof(T) == 8 ? 256 : 1024) step_kernel(StepA
             #pragma unroll
             for (int k = 0; k < ILP; ++k)
                 if (open[k])
-                    fixup<POT, NB>((cExact*)a.ex, B.m, open[k], p_open + k * nt + tid, a.stride, a.cellrow,
-                                   (gF32*)a.out, (gU16*)((char*)a.out + 7 * a.stride * sizeof(T)), (lF64*)hist,
-                                   (lF64*)csum, (lU32*)ccnt, B.pot.lcE0, B.pot.lcEinv);
+                    fixup<POT, NB>((cExact*)a.ex, B.m, open[k], p_open + k * nt + tid, a.stride, a.cellrow, kp[k].x,
+                                   kp[k].y, kp[k].z, kp[k].vx, kp[k].vy, kp[k].vz, kp[k].w, kp[k].vl, kp[k].cell,
+                                   (gU16*)((char*)a.out + 7 * a.stride * sizeof(T)), (lF64*)hist, (lF64*)csum,
+                                   (lU32*)ccnt, B.pot.lcE0, B.pot.lcEinv);
         }
-        const int m = t < t1 ? ro(a.tile_model, t) : -2;
+        const int m = t < t1 ? (t == t0 ? bd.m0 : ro(a.tile_model, t)) : -2;
         if (m != cur) {
             if (cur >= 0) {
                 // flush the finished model's histograms to its partial slot
@@ -284,19 +316,24 @@ __global__ void __launch_bounds__(sizeof(T) == 8 ? 256 : 1024) step_kernel(StepA
             // in LDS it would leave room for one block per CU only
             B.et = reinterpret_cast<const float2*>(a.lcetab) + (size_t)m * kLcE;
             __syncthreads();
+            if (failed) return;   // (uniform: every thread leaves here, before any store)
         }
         // this tile's particles (their loads were issued one tile ago), then the
         // next tile's loads
         const Regs cur_r = next_r;
-        if (t + 1 < t1) load_tile(t + 1, next_r);
-        const int64_t p0 = ro(a.tile_p0, t);
-        const int cnt = ro(a.tile_cnt, t);
+        const int64_t p0 = next_p0;
+        const int cnt = next_cnt;
+        if (t + 1 < t1) {
+            next_p0 = ro(a.tile_p0, t + 1);
+            next_cnt = ro(a.tile_cnt, t + 1);
+            load_tile(next_p0, next_cnt, next_r);
+        }
         #pragma unroll
         for (int k = 0; k < ILP; ++k) {
             const int i = k * nt + tid;
             open[k] = i < cnt ? particle_step<POT, NB, SIG>(a, B, acc, p0 + i, cur_r.x[k], cur_r.y[k], cur_r.z[k],
                                                         cur_r.vx[k], cur_r.vy[k], cur_r.vz[k], cur_r.w[k], cur_r.wh[k],
-                                                        cur_r.tg[k])
+                                                        cur_r.tg[k], kp[k])
                               : 0u;
         }
         p_open = p0;
