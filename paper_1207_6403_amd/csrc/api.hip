@@ -852,7 +852,6 @@ static m2m_status build_lc_etab(m2m_ctx* c, const std::vector<double>& er) {
         if (q.kind != M2M_POT_LOG && hi >= 0.0) hi = -1e-3 * std::fabs(er[2 * m]);
         if (!(hi > lo)) hi = lo + 1e-6;
         const double h = (hi - lo) / (kLcE - 1);
-        const double eE = 8e-7 * std::max(2.0, std::max(std::fabs(lo), std::fabs(hi)));
         std::vector<double> L(kLcE);
         for (int k = 0; k < kLcE; ++k) {
             double rc;
@@ -869,9 +868,9 @@ static m2m_status build_lc_etab(m2m_ctx* c, const std::vector<double>& er) {
                     if (!(ex > 0)) { dev = 1.0; break; }
                     dev = std::max(dev, std::fabs(std::exp(l0 + f * (l1 - l0)) - ex) / ex);
                 }
-                // FP32 index error: ulp(E - E0) * invh + ulp(t) < 1e-4 of an interval;
-                // FP32 energy error: eE (a few ulp of the largest |E|) times d ln Lc / dE
-                err = std::min(1.0, 4.0 * dev + 2e-4 * std::fabs(l1 - l0) + eE * std::fabs(l1 - l0) / h + 1e-6);
+                // (the FP32 index, energy and evaluation errors are bounded per
+                // particle by the kernel)
+                err = std::min(1.0, 4.0 * dev + 1e-7);
             }
             tab[2 * ((size_t)m * kLcE + k)] = L[k] > 0 ? (float)std::log(L[k]) : -1e30f;
             tab[2 * ((size_t)m * kLcE + k) + 1] = (float)err;

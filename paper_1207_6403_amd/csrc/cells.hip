@@ -24,6 +24,7 @@ __global__ void __launch_bounds__(1024) cells_kernel(StepArgs<float, float> a) {
     int slot = ro(a.block_slot0, blockIdx.x) - 1, cur = -1;
     Pot<float> pot{};
     float Emin = 0.0f, sE = 0.0f;
+    CellGuard cg{};
     if (failed) return;
     const uint32_t rb = uint32_t(a.stride * sizeof(float));
     uint16_t* tags = reinterpret_cast<uint16_t*>(reinterpret_cast<char*>(a.out) + 7 * (size_t)rb) +
@@ -48,6 +49,7 @@ __global__ void __launch_bounds__(1024) cells_kernel(StepArgs<float, float> a) {
             pot = ro(a.pots, m);
             Emin = ro(a.erange, 2 * m);
             sE = float(a.cells.n0) / (ro(a.erange, 2 * m + 1) - Emin);
+            cg = cell_guard(Emin, ro(a.erange, 2 * m + 1), sE);
             __syncthreads();
             for (int c = tid; c < NC; c += nt) { csum[c] = 0.0; ccnt[c] = 0u; }
             for (int i = tid; i < kLcE; i += nt)
@@ -64,9 +66,9 @@ __global__ void __launch_bounds__(1024) cells_kernel(StepArgs<float, float> a) {
             const float vz = ld_at<float>(a.out, o + 5 * rb), w = ld_at<float>(a.out, o + 6 * rb);
             float phi, ax, ay, az;
             potential<POT, float>(pot, x, y, z, phi, ax, ay, az);
-            const float E = 0.5f * (vx * vx + vy * vy + vz * vz) + phi;
+            const float KE = 0.5f * (vx * vx + vy * vy + vz * vz);
             int cell;
-            if (cell_fast<POT>(pot, et, a.cells, Emin, sE, E, x, y, z, vx, vy, vz, cell) != 0u) {
+            if (cell_fast<POT>(pot, et, a.cells, Emin, sE, cg, KE, phi, x, y, z, vx, vy, vz, cell) != 0u) {
                 const Exact* ex = a.ex;
                 const Pot<double>& pd = ex->pots[m];
                 cell = prior_cell_seeded<POT>(pd, ex->lctab + pd.lc_off, ex->rce + (size_t)m * kLcE, double(pot.lcE0),

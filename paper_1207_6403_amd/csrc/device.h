@@ -358,60 +358,89 @@ __device__ __forceinline__ int prior_cell_seeded(const Pot<double>& p, const dou
     return cell_index(c, Emin, Emax, E, L, Lz, Lc);
 }
 
-// Lc(E) of an FP32 kernel from the model's uniform-E table in LDS: pairs
-// (ln Lc(E_k), bound) at E_k = E0 + k / invh, k < kLcE; ln Lc is interpolated
-// linearly and bound is the relative error of the resulting Lc on [E_k, E_k+1]
-// (measured on the host in FP64, with a safety factor).  Returns false outside
-// the table.
-__device__ __forceinline__ bool lc_from_table(const float2* __restrict__ et, float E0, float invh, float E, float& Lc,
-                                              float& err) {
-    const float t = (E - E0) * invh;
+// Lc(E) of an FP32 kernel from the model's uniform-E table: pairs (ln Lc(E_k),
+// bound) at E_k = E0 + k / invh, k < kLcE; ln Lc is interpolated linearly and
+// bound is the relative interpolation error on [E_k, E_k+1] (measured on the
+// host in FP64, with a safety factor).  dl receives a bound on the relative
+// error of the FP32 result: the interpolation bound; the energy error eE, the
+// rounding of E0 and of the table index (3u |E - E0|) through the slope of
+// ln Lc; the rounding of the interpolated logarithm and of the hardware exp.
+// Returns false outside the table.
+__device__ __forceinline__ bool lc_from_table(const float2* __restrict__ et, float E0, float invh, float E, float eE,
+                                              float& Lc, float& dl) {
+    const float d = E - E0;
+    const float t = d * invh;
     if (!(t >= 0.0f) || !(t < float(kLcE - 1))) return false;
     const int k = int(t);
     const float f = t - float(k);
     const float2 a = et[k], b = et[k + 1];
-    Lc = __expf(a.x + f * (b.x - a.x));
-    err = a.y;
+    const float l = a.x + f * (b.x - a.x);
+    Lc = __expf(l);
+    dl = a.y + fabsf(b.x - a.x) * invh * (eE + kU32 * (fabsf(E0) + 3.0f * fabsf(d))) +
+         kU32 * (4.0f * fabsf(l) + 3.0f);
     return true;
 }
 
-// Cell of the moving prior from FP32 values.  Returns the axes whose FP32
+// Guard of the energy axis of the prior cells, per model: the FP32 coordinate
+// fE = (E - Emin) sE differs from the exact one by at most
+//   sE (eE + u |Emin|) + |fE| (4u + u (|Emin| + |Emax|) / (Emax - Emin))
+// (eE: the energy error; the rounded Emin; the difference, the product and
+// the rounded sE, itself n0 over the difference of the rounded range); the
+// guard is twice that, plus a floor.
+struct CellGuard {
+    float e0, e1, e2;   // gE = e0 + e1 eE + e2 |fE|
+};
+__device__ __forceinline__ CellGuard cell_guard(float Emin, float Emax, float sE) {
+    CellGuard g;
+    g.e0 = 2.0f * sE * kU32 * fabsf(Emin) + kGuardBinFloor;
+    g.e1 = 2.0f * sE;
+    g.e2 = 2.0f * kU32 * (4.0f + (fabsf(Emin) + fabsf(Emax)) / (Emax - Emin));
+    return g;
+}
+
+// Cell of the moving prior from FP32 values: kinetic energy KE and potential
+// phi (E = KE + phi), position and velocity.  Returns the axes whose FP32
 // coordinate lies within the guard band of a cell edge (bit 0: E, bit 1: L/Lc
 // or Lz/Lc, also when Lc(E) is not in the table or not positive, bit 2: Lz/L);
 // the caller re-decides those in FP64.  cell is the index from the clamped FP32
 // coordinates of every axis (exact on the axes not returned).
+// Guards, twice a bound on the FP32 error (u = 2^-24):
+//   E: |E32 - E| <= u (4 KE + 17 |phi| + 3 v0^2): the kinetic sum, the
+//      potential (at most 16u |phi| for the analytic potentials with the
+//      hardware reciprocal, logarithm and square root, plus 3u v0^2 from the
+//      argument of the logarithmic potential's log) and the sum; see cell_guard;
+//   L/Lc or Lz/Lc: the rounding of L (2u per product pair, 3u L) or Lz
+//      (2u (|x vy| + |y vx|)) over Lc, and the relative error of Lc (dl, plus
+//      3u for the reciprocal and the product) times the coordinate's distance
+//      from the axis origin, plus 2u |f2|;
+//   Lz/L: 1e-4 cells.
 template <int POT>
 __device__ __forceinline__ unsigned cell_fast(const Pot<float>& p, const float2* __restrict__ et, const Cells& c,
-                                              float Emin, float sE, float E, float x, float y, float z, float vx,
-                                              float vy, float vz, int& cell) {
+                                              float Emin, float sE, const CellGuard& G, float KE, float phi, float x,
+                                              float y, float z, float vx, float vy, float vz, int& cell) {
     const int n0 = opaque(c.n0), n1 = opaque(c.n1), n2 = opaque(c.n2), ax2 = opaque(c.ax2);
-    const float Lz = x * vy - y * vx;
-    float L = 0.0f;
+    const float E = KE + phi;
+    const float eE = kU32 * (4.0f * KE + 17.0f * fabsf(phi) + 3.0f * p.v2);
+    const float xvy = x * vy, yvx = y * vx;
+    const float Lz = xvy - yvx;
+    float L = 0.0f, dL = 2.0f * kU32 * (fabsf(xvy) + fabsf(yvx));
     if (ax2 == 0 || n2 > 1) {   // |L| only for the L/Lc and Lz/L axes
-        const float Lx = y * vz - z * vy, Ly = z * vx - x * vz;
+        const float yvz = y * vz, zvy = z * vy, zvx = z * vx, xvz = x * vz;
+        const float Lx = yvz - zvy, Ly = zvx - xvz;
         L = sqrtf(Lx * Lx + Ly * Ly + Lz * Lz);
+        if (ax2 == 0) dL += 2.0f * kU32 * (fabsf(yvz) + fabsf(zvy) + fabsf(zvx) + fabsf(xvz)) + 3.0f * kU32 * L;
     }
-    float Lc = 1.0f, err = 2e-6f;
-    bool have = true;
-    if (POT == 0) {
-        // Hernquist closed form (see circular_L)
-        const float D = p.GM * p.GM - 8.0f * E * p.GM * p.a;
-        const float rc = 4.0f * p.a * (p.GM + E * p.a) / (sqrtf(D) - p.GM - 4.0f * E * p.a);
-        have = E < 0.0f && rc > 0.0f;
-        Lc = rc * sqrtf(p.GM * rc) / (rc + p.a);
-        err = 1e-5f;
-    } else {
-        have = lc_from_table(et, p.lcE0, p.lcEinv, E, Lc, err);
-    }
-    have = have && Lc > 0.0f;
+    float Lc = 1.0f, dl = 1.0f;
+    const bool have = lc_from_table(et, p.lcE0, p.lcEinv, E, eE, Lc, dl) && Lc > 0.0f;
     const float fE = (E - Emin) * sE;
     const float iLc = qdiv(1.0f, Lc);
-    const float f2 = ax2 == 0 ? L * iLc * float(n1) : (Lz * iLc + 1.0f) * 0.5f * float(n1);
+    const float s2 = ax2 == 0 ? float(n1) : 0.5f * float(n1);
+    const float f2 = ax2 == 0 ? L * iLc * float(n1) : (Lz * iLc + 1.0f) * s2;
     const float f3 = n2 > 1 ? ((L > 0.0f ? qdiv(Lz, L) : 0.0f) + 1.0f) * 0.5f * float(n2) : 0.5f;
-    // a relative error err of Lc moves f2 by at most |f2| err (L/Lc axis) or
-    // |f2 - n1/2| err (Lz/Lc axis)
-    const float g2 = kGuardCell + (ax2 == 0 ? fabsf(f2) : fabsf(f2 - 0.5f * float(n1))) * err;
-    unsigned open = near_cell_edge(fE, n0, kGuardCell) ? 1u : 0u;
+    const float gE = G.e0 + G.e1 * eE + G.e2 * fabsf(fE);
+    const float g2 = 2.0f * (s2 * dL * iLc + fabsf(f2 - (ax2 == 0 ? 0.0f : s2)) * (dl + 3.0f * kU32) +
+                             2.0f * kU32 * fabsf(f2)) + kGuardBinFloor;
+    unsigned open = near_cell_edge(fE, n0, gE) ? 1u : 0u;
     open |= (!have || near_cell_edge(f2, n1, g2)) ? 2u : 0u;
     open |= (n2 > 1 && near_cell_edge(f3, n2, kGuardCell)) ? 4u : 0u;
     cell = (clamp_cell(fE, n0) * n1 + (have ? clamp_cell(f2, n1) : 0)) * n2 + (n2 > 1 ? clamp_cell(f3, n2) : 0);

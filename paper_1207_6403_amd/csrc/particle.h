@@ -45,6 +45,7 @@ struct Blk {
     const T* lct;       // circular-orbit energies (FP64 kernels)
     Pot<T> pot;
     T Emin, sE, wflat;
+    CellGuard cg;       // energy-axis guard of the prior cells (FP32 kernels)
     int m;
 };
 

@@ -103,8 +103,8 @@ __device__ __forceinline__ unsigned particle_step(const StepArgs<T, PT>& a, cons
         }
         unsigned am = 0;
         if constexpr (sizeof(T) == 4) {
-            const float E = 0.5f * (vx * vx + vy * vy + vz * vz) + phi;
-            am = cell_fast<POT>(B.pot, B.et, a.cells, B.Emin, B.sE, E, x, y, z, vx, vy, vz, cell);
+            const float KE = 0.5f * (vx * vx + vy * vy + vz * vz);
+            am = cell_fast<POT>(B.pot, B.et, a.cells, B.Emin, B.sE, B.cg, KE, phi, x, y, z, vx, vy, vz, cell);
             open |= am << NB;
         } else {
             cell = prior_cell_f64<POT>(B.pot, B.lct, a.cells, a.ex->erange[2 * B.m], a.ex->erange[2 * B.m + 1], x, y, z,
@@ -305,6 +305,7 @@ __global__ void __launch_bounds__(sizeof(T) == 8 ? 256 : 1024) step_kernel(StepA
             B.pot = ro(a.pots, m);
             B.Emin = ro(a.erange, 2 * m);
             B.sE = T(a.cells.n0) / (ro(a.erange, 2 * m + 1) - ro(a.erange, 2 * m));
+            if constexpr (F32) B.cg = cell_guard(B.Emin, ro(a.erange, 2 * m + 1), B.sE);
             B.wflat = ro(a.flatw, m);
             __syncthreads();
             for (int j = tid; j < J; j += nt) { hist[j] = 0.0; cl[j] = a.cvec[(size_t)m * J + j]; }

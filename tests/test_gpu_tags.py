@@ -106,6 +106,25 @@ def test_tags_separate_cell_kernel():
     check_tags(cfg, ctx, inp, er)
 
 
+@pytest.mark.parametrize("pot", ["hernquist", "hernquist_nfw"])
+def test_tags_fp32_spherical_potentials(pot):
+    """FP32 shells and annuli with an (E, L/Lc) prior in a Hernquist or
+    Hernquist + NFW potential: Lc(E) from the closed form or the table."""
+    cfg = configs.cfg1(N=1 << 18)
+    cfg["precision"] = "f32"
+    if pot == "hernquist_nfw":
+        cfg["potential"] = {"kind": "hernquist_nfw", "G": 1.0, "M": 1.0, "a": 1.0, "Mh": 5.0, "rs": 4.0}
+    # the rate of this model, derived as for the full-size workloads
+    cfg["eps"] = 0.1 / (cfg["dt"] * derive_eps.max_abs_G(cfg))
+    inp = H.inputs(cfg)
+    er = H.erange(cfg, inp)
+    H.flush("case cfg1 FP32 %s N=%d" % (pot, cfg["N"]))
+    ctx = m2m.m2m_create(cfg, inp["ics"], inp["w"], inp["Y"], inp["sigma"], Erange=er)
+    check_tags(cfg, ctx, inp, er)
+    m2m.m2m_step(ctx, 3)
+    check_tags(cfg, ctx, inp, er)
+
+
 def test_tags_fp64_shells_and_annuli():
     cfg = configs.cfg1(N=20000)
     inp = H.inputs(cfg)
