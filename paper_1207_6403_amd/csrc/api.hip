@@ -253,7 +253,12 @@ static m2m_status make_plan(m2m_ctx* c, int threads, int ilp, int bpc) {
         if (d.t0 < d.t1) {
             d.m0 = tm[d.t0];
             d.p0 = tp[d.t0];
-            d.cnt0 = tc[d.t0];
+            int32_t te = d.t0;
+            while (te < d.t1 && tm[te] == d.m0) ++te;
+            d.n0 = (int32_t)(tp[te - 1] + tc[te - 1] - tp[d.t0]);
+            d.tseg1 = te;
+        } else {
+            d.tseg1 = d.t1;
         }
     }
     p.ntile = T;
@@ -309,7 +314,7 @@ static m2m_status make_plan(m2m_ctx* c, int threads, int ilp, int bpc) {
     const size_t ts = tsize(c);
     const int NCk = c->cells_apart ? 0 : c->NC;   // cells the fused kernel holds
     const int NCe = (NCk + 1) & ~1, NE = (c->nedge + 1) & ~1;
-    p.lds = 8 * ((size_t)c->JP + kTrash + NCk + kTrash + NE + 64) + 4 * ((size_t)NCe + kTrash) +
+    p.lds = 8 * ((size_t)c->JP + kTrash + NCk + kTrash + NE + 2) + 4 * ((size_t)NCe + kTrash) +
             ts * ((size_t)c->JP + 2 + NCe + NE + kLcTab);
     p.lds = (p.lds + 15) & ~(size_t)15;
     if (p.lds > (size_t)c->max_lds)
@@ -1139,7 +1144,7 @@ extern "C" m2m_status m2m_create(const m2m_config* cfg, const m2m_obs_layout* la
     {
         // LDS of the fused kernel with the prior cells (as make_plan computes it)
         const int NCe = (c->NC + 1) & ~1, NE = (c->nedge + 1) & ~1;
-        const size_t fused = 8 * ((size_t)c->JP + kTrash + c->NC + kTrash + NE + 64) +
+        const size_t fused = 8 * ((size_t)c->JP + kTrash + c->NC + kTrash + NE + 2) +
                              4 * ((size_t)NCe + kTrash) + 4 * ((size_t)c->JP + 2 + NCe + NE + kLcTab);
         // the learned prior's judge grid, and FP32 histogram priors too large for
         // the fused kernel, are accumulated by the cell kernel

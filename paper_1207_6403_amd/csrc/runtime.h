@@ -22,12 +22,13 @@ constexpr int kFinCols = 32;         // columns per finalise block
 constexpr int kFinGroups = 8;        // slot groups per column (256 threads)
 
 // Where a block of the fused kernel starts, in one load: its tiles [t0, t1),
-// its first partial slot, the model of its first tile and that tile's first
-// particle and count (the rest of the tiles come from the tile tables).
+// its first partial slot, and its first segment (the run of tiles of one
+// model): the model, the first particle, the particle count and the tile after
+// the segment (later segments, rare, come from the tile tables).
 struct BlockDesc {
     int32_t t0, t1, slot0, m0;
     int64_t p0;
-    int32_t cnt0, reserved;
+    int32_t n0, tseg1;
 };
 
 struct StatRow {

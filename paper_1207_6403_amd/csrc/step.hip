@@ -35,11 +35,11 @@ struct Keep {
 template <int POT, int NB, uint64_t SIG, typename T, typename PT>
 __device__ __forceinline__ unsigned particle_step(const StepArgs<T, PT>& a, const Blk<T>& B, Acc& acc, int64_t p,
                                                   T x, T y, T z, T vx, T vy, T vz, T w, T what_p,
-                                                  const uint16_t (&tg)[kMaxBin + 1], Keep<T>& kp) {
+                                                  const uint16_t (&tg)[kMaxBin + 1], Keep<T>& kp, uint32_t fl,
+                                                  uint32_t rb) {
+    // fl: the step flags; rb: bytes per value row
     const Layout<T>& L = a.lay;
     const LayoutView<SIG, T> V{L};
-    const uint32_t fl = opaque(a.flags);
-    const uint32_t rb = opaque(uint32_t(a.stride * sizeof(T)));   // bytes per value row
     const uint32_t o = uint32_t(p) * uint32_t(sizeof(T));
     const uint32_t ot = 7 * rb + uint32_t(p) * 2u;                 // tag of row 0
     const int nbin = V.nbin();
@@ -207,8 +207,8 @@ __global__ void __launch_bounds__(sizeof(T) == 8 ? 256 : 1024) step_kernel(StepA
     double* hist = reinterpret_cast<double*>(smem);                 // J (padded to JP), then kTrash
     double* csum = hist + JP + kTrash;                               // NC, then kTrash
     double* ed64 = csum + NC + kTrash;                               // edges, FP64
-    double* red = ed64 + NE;                                         // 4 * 16
-    unsigned* ccnt = reinterpret_cast<unsigned*>(red + 64);          // NC (padded to even), then kTrash
+    unsigned* ctr = reinterpret_cast<unsigned*>(ed64 + NE);         // work counter (2 doubles' room)
+    unsigned* ccnt = reinterpret_cast<unsigned*>(ed64 + NE + 2);     // NC (padded to even), then kTrash
     T* cl = reinterpret_cast<T*>(ccnt + ((NC + 1) & ~1) + kTrash);   // J : Dt_j / sigma_j, zero to JP + 2
     T* cm = cl + JP + 2;                                             // NC: cell means
     T* ed = cm + ((NC + 1) & ~1);                                    // edges in T
@@ -216,32 +216,37 @@ __global__ void __launch_bounds__(sizeof(T) == 8 ? 256 : 1024) step_kernel(StepA
 
     for (int i = tid; i < a.nedge; i += nt) { ed[i] = a.edges[i]; ed64[i] = a.edges64[i]; }
 
-    const int t0 = bd.t0, t1 = bd.t1;
     const uint32_t fl = a.flags;
     const uint32_t wm = (fl >> kWhatShift) & 3u;
     const bool want_cm = wm == 1 || wm == 2;
     const bool accum = fl & kAccum;
     const bool stepping = !(fl & kObserve);
-    int slot = bd.slot0 - 1;
-    int cur = -1;
     Blk<T> B;
     B.hist = hist; B.csum = csum; B.ccnt = ccnt; B.cl = cl; B.cm = cm; B.ed = ed; B.ed64 = ed64;
     B.lct = lct;
     Acc acc;
 
-    // the particles of a tile (values and the tags of the current state); the
-    // next tile's are loaded while this one is processed
+    // Work is handed out per wave in chunks of CH = 64 ILP particles of the
+    // current segment (the block's run of tiles of one model): wave w starts
+    // with chunk w and then takes the next unclaimed chunk from a counter in
+    // LDS, so that waves slowed by a fix-up or by the issue order simply take
+    // fewer chunks and the block's waves finish together.  The next chunk's
+    // particles are loaded while the current one is processed.
+    constexpr int CH = 64 * ILP;
+    const int nw = nt >> 6, wid = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
     struct Regs {
         T x[ILP], y[ILP], z[ILP], vx[ILP], vy[ILP], vz[ILP], w[ILP], wh[ILP];
         uint16_t tg[ILP][kMaxBin + 1];
     };
-    auto load_tile = [&](int64_t p0, int cnt, Regs& R) {
+    // the particles of chunk c of the segment [P0, P0 + n) (values and the tags
+    // of the current state)
+    auto load_chunk = [&](int64_t P0, int n, int c, Regs& R) {
+        const uint32_t rb = opaque(uint32_t(a.stride * sizeof(T))), tr = uint32_t(a.stride * 2);
         #pragma unroll
         for (int k = 0; k < ILP; ++k) {
-            const int i = k * nt + tid;
-            if (i < cnt) {
-                const int64_t p = p0 + i;
-                const uint32_t rb = opaque(uint32_t(a.stride * sizeof(T))), tr = uint32_t(a.stride * 2);
+            const int i = c * CH + k * 64 + lane;
+            if (i < n) {
+                const int64_t p = P0 + i;
                 const uint32_t o = uint32_t(p) * uint32_t(sizeof(T)), ot = 7 * rb + uint32_t(p) * 2u;
                 R.x[k] = ld_at<T>(a.in, o);
                 R.y[k] = ld_at<T>(a.in, o + rb);
@@ -260,84 +265,97 @@ __global__ void __launch_bounds__(sizeof(T) == 8 ? 256 : 1024) step_kernel(StepA
         }
     };
     Regs next_r;
-    int64_t next_p0 = bd.p0;
-    int next_cnt = bd.cnt0;
-    if (t0 < t1) load_tile(next_p0, next_cnt, next_r);
-    unsigned open[ILP];   // decisions left open in the previous tile
+    // the first segment (its first chunk's loads go out before the tables')
+    int m = bd.m0, n = bd.n0, slot = bd.slot0, te = bd.tseg1;
+    int64_t P0 = bd.p0;
+    int ts = bd.t0;
+    if (ts < bd.t1 && wid * CH < n) load_chunk(P0, n, wid, next_r);
+    unsigned open[ILP];   // decisions left open in the previous chunk
     Keep<T> kp[ILP];      // and its particles' new state
     int64_t p_open = 0;   // its first particle
     #pragma unroll
     for (int k = 0; k < ILP; ++k) open[k] = 0u;
 
-    for (int t = t0; t <= t1; ++t) {
-        if constexpr (F32) {
-            // the previous tile's open decisions (out of line, and before this
-            // tile's loads are issued, so that waiting for those loads never
-            // waits for the unknown memory operations of a call)
-            #pragma unroll
-            for (int k = 0; k < ILP; ++k)
-                if (open[k])
-                    fixup<POT, NB>((cExact*)a.ex, B.m, open[k], p_open + k * nt + tid, a.stride, a.cellrow, kp[k].x,
-                                   kp[k].y, kp[k].z, kp[k].vx, kp[k].vy, kp[k].vz, kp[k].w, kp[k].vl, kp[k].cell,
-                                   (gU16*)((char*)a.out + 7 * a.stride * sizeof(T)), (lF64*)hist, (lF64*)csum,
-                                   (lU32*)ccnt, B.pot.lcE0, B.pot.lcEinv);
-        }
-        const int m = t < t1 ? (t == t0 ? bd.m0 : ro(a.tile_model, t)) : -2;
-        if (m != cur) {
-            if (cur >= 0) {
-                // flush the finished model's histograms to its partial slot
-                __syncthreads();
-                PT* dst = a.part + ro(a.slot_base, slot);
-                const int64_t cs = ro(a.slot_stride, slot);
-                auto at = [&](int j) -> PT& { return dst[(j / kFinCols) * cs + j % kFinCols]; };
-                for (int j = tid; j < J; j += nt) at(j) = PT(hist[j]);
-                if (accum)
-                    for (int c = tid; c < NC; c += nt) { at(JP + 2 * c) = PT(csum[c]); at(JP + 2 * c + 1) = PT(ccnt[c]); }
-                // (observing only, the statistics belong to the kernel that updated the weights)
-                if (stepping) wave_stats(acc.S, acc.W, acc.W2, acc.mn, a.seg_stats + 4 * kStatWaves * (size_t)slot);
-                acc.S = acc.W = acc.W2 = 0;
-                acc.mn = INFINITY;
+    while (ts < bd.t1) {
+        // the segment's model: tables, histograms and the work counter
+        B.m = m;
+        B.pot = ro(a.pots, m);
+        B.Emin = ro(a.erange, 2 * m);
+        B.sE = T(a.cells.n0) / (ro(a.erange, 2 * m + 1) - ro(a.erange, 2 * m));
+        if constexpr (F32) B.cg = cell_guard(B.Emin, ro(a.erange, 2 * m + 1), B.sE);
+        B.wflat = ro(a.flatw, m);
+        for (int j = tid; j < J; j += nt) { hist[j] = 0.0; cl[j] = a.cvec[(size_t)m * J + j]; }
+        if (tid < JP + 2 - J) cl[J + tid] = T(0);   // the entries bins without a particle read
+        if (accum) for (int c = tid; c < NC; c += nt) { csum[c] = 0.0; ccnt[c] = 0u; }
+        if (want_cm) for (int c = tid; c < NC; c += nt) cm[c] = a.cellmean[(size_t)m * NC + c];
+        if (NC && !F32) for (int i = tid; i < kLcTab; i += nt) lct[i] = a.lctab[(size_t)B.pot.lc_off + i];
+        if (tid == 0) *ctr = 0u;
+        // the uniform-E Lc table of the model, read from global memory (L1/L2)
+        B.et = reinterpret_cast<const float2*>(a.lcetab) + (size_t)m * kLcE;
+        __syncthreads();
+        if (failed) return;   // (uniform: every thread leaves here, before any store)
+
+        const int nch = (n + CH - 1) / CH;
+        int c = wid;
+        while (true) {
+            if constexpr (F32) {
+                // the previous chunk's open decisions (out of line, and before the
+                // next chunk's loads are issued, so that waiting for those loads
+                // never waits for the unknown memory operations of a call)
+                #pragma unroll
+                for (int k = 0; k < ILP; ++k)
+                    if (open[k])
+                        fixup<POT, NB>((cExact*)a.ex, B.m, open[k], p_open + k * 64 + lane, a.stride, a.cellrow,
+                                       kp[k].x, kp[k].y, kp[k].z, kp[k].vx, kp[k].vy, kp[k].vz, kp[k].w, kp[k].vl,
+                                       kp[k].cell, (gU16*)((char*)a.out + 7 * a.stride * sizeof(T)), (lF64*)hist,
+                                       (lF64*)csum, (lU32*)ccnt, B.pot.lcE0, B.pot.lcEinv);
+                #pragma unroll
+                for (int k = 0; k < ILP; ++k) open[k] = 0u;
             }
-            if (m < 0) break;
-            cur = m;
-            ++slot;
-            B.m = m;
-            B.pot = ro(a.pots, m);
-            B.Emin = ro(a.erange, 2 * m);
-            B.sE = T(a.cells.n0) / (ro(a.erange, 2 * m + 1) - ro(a.erange, 2 * m));
-            if constexpr (F32) B.cg = cell_guard(B.Emin, ro(a.erange, 2 * m + 1), B.sE);
-            B.wflat = ro(a.flatw, m);
-            __syncthreads();
-            for (int j = tid; j < J; j += nt) { hist[j] = 0.0; cl[j] = a.cvec[(size_t)m * J + j]; }
-            if (tid < JP + 2 - J) cl[J + tid] = T(0);   // the entries bins without a particle read
-            if (accum) for (int c = tid; c < NC; c += nt) { csum[c] = 0.0; ccnt[c] = 0u; }
-            if (want_cm) for (int c = tid; c < NC; c += nt) cm[c] = a.cellmean[(size_t)m * NC + c];
-            if (NC && !F32) for (int i = tid; i < kLcTab; i += nt) lct[i] = a.lctab[(size_t)B.pot.lc_off + i];
-            // the uniform-E Lc table of the model, read from global memory (L1/L2):
-            // in LDS it would leave room for one block per CU only
-            B.et = reinterpret_cast<const float2*>(a.lcetab) + (size_t)m * kLcE;
-            __syncthreads();
-            if (failed) return;   // (uniform: every thread leaves here, before any store)
+            if (c >= nch) break;
+            // this chunk's particles (loaded one chunk ago), then the next chunk's loads
+            const Regs cur_r = next_r;
+            unsigned got = 0;
+            if (lane == 0) got = __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            const int cn = nw + (int)__builtin_amdgcn_readfirstlane(got);
+            if (cn < nch) load_chunk(P0, n, cn, next_r);
+            const uint32_t flo = opaque(a.flags), rbo = opaque(uint32_t(a.stride * sizeof(T)));
+            #pragma unroll
+            for (int k = 0; k < ILP; ++k) {
+                const int i = c * CH + k * 64 + lane;
+                open[k] = i < n ? particle_step<POT, NB, SIG>(a, B, acc, P0 + i, cur_r.x[k], cur_r.y[k], cur_r.z[k],
+                                                              cur_r.vx[k], cur_r.vy[k], cur_r.vz[k], cur_r.w[k],
+                                                              cur_r.wh[k], cur_r.tg[k], kp[k], flo, rbo)
+                                : 0u;
+            }
+            p_open = P0 + (int64_t)c * CH;
+            c = cn;
         }
-        // this tile's particles (their loads were issued one tile ago), then the
-        // next tile's loads
-        const Regs cur_r = next_r;
-        const int64_t p0 = next_p0;
-        const int cnt = next_cnt;
-        if (t + 1 < t1) {
-            next_p0 = ro(a.tile_p0, t + 1);
-            next_cnt = ro(a.tile_cnt, t + 1);
-            load_tile(next_p0, next_cnt, next_r);
-        }
-        #pragma unroll
-        for (int k = 0; k < ILP; ++k) {
-            const int i = k * nt + tid;
-            open[k] = i < cnt ? particle_step<POT, NB, SIG>(a, B, acc, p0 + i, cur_r.x[k], cur_r.y[k], cur_r.z[k],
-                                                        cur_r.vx[k], cur_r.vy[k], cur_r.vz[k], cur_r.w[k], cur_r.wh[k],
-                                                        cur_r.tg[k], kp[k])
-                              : 0u;
-        }
-        p_open = p0;
+
+        // flush the segment's histograms to its partial slot
+        __syncthreads();
+        PT* dst = a.part + ro(a.slot_base, slot);
+        const int64_t cs = ro(a.slot_stride, slot);
+        auto at = [&](int j) -> PT& { return dst[(j / kFinCols) * cs + j % kFinCols]; };
+        for (int j = tid; j < J; j += nt) at(j) = PT(hist[j]);
+        if (accum)
+            for (int c2 = tid; c2 < NC; c2 += nt) { at(JP + 2 * c2) = PT(csum[c2]); at(JP + 2 * c2 + 1) = PT(ccnt[c2]); }
+        // (observing only, the statistics belong to the kernel that updated the weights)
+        if (stepping) wave_stats(acc.S, acc.W, acc.W2, acc.mn, a.seg_stats + 4 * kStatWaves * (size_t)slot);
+        acc.S = acc.W = acc.W2 = 0;
+        acc.mn = INFINITY;
+
+        // the next segment, if any (a block spanning models)
+        ts = te;
+        if (ts >= bd.t1) break;
+        m = ro(a.tile_model, ts);
+        P0 = ro(a.tile_p0, ts);
+        te = ts;
+        while (te < bd.t1 && ro(a.tile_model, te) == m) ++te;
+        n = (int)(ro(a.tile_p0, te - 1) + ro(a.tile_cnt, te - 1) - P0);
+        ++slot;
+        __syncthreads();   // every thread has read the LDS of the flushed segment
+        if (wid * CH < n) load_chunk(P0, n, wid, next_r);
     }
     if (acc.bad) {
         __hip_atomic_fetch_or(a.flag, (int)acc.bad, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
