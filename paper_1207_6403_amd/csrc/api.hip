@@ -303,8 +303,8 @@ static m2m_status make_plan(m2m_ctx* c, int threads, int ilp, int bpc) {
         (s = upload(c, &p.slot_stride, sstride)))
         return s;
     // per-wave statistics rows, the identity where no wave writes
-    std::vector<double> st0((size_t)nslot * kStatWaves * 4, 0.0);
-    for (size_t r = 0; r < (size_t)nslot * kStatWaves; ++r) st0[4 * r + 3] = INFINITY;
+    std::vector<double> st0((size_t)nslot * 4, 0.0);
+    for (size_t r = 0; r < (size_t)nslot; ++r) st0[4 * r + 3] = INFINITY;
     if ((s = dalloc(c, (char**)&p.part, npart * tsize(c))) || (s = upload(c, &p.seg_stats, st0)) ||
         (s = dalloc(c, &p.erange_out, (size_t)nslot * 2)))
         return s;
@@ -314,7 +314,7 @@ static m2m_status make_plan(m2m_ctx* c, int threads, int ilp, int bpc) {
     const size_t ts = tsize(c);
     const int NCk = c->cells_apart ? 0 : c->NC;   // cells the fused kernel holds
     const int NCe = (NCk + 1) & ~1, NE = (c->nedge + 1) & ~1;
-    p.lds = 8 * ((size_t)c->JP + kTrash + NCk + kTrash + NE + 2) + 4 * ((size_t)NCe + kTrash) +
+    p.lds = 8 * ((size_t)c->JP + kTrash + NCk + kTrash + NE + 2 + 64) + 4 * ((size_t)NCe + kTrash) +
             ts * ((size_t)c->JP + 2 + NCe + NE + kLcTab);
     p.lds = (p.lds + 15) & ~(size_t)15;
     if (p.lds > (size_t)c->max_lds)
@@ -1144,7 +1144,7 @@ extern "C" m2m_status m2m_create(const m2m_config* cfg, const m2m_obs_layout* la
     {
         // LDS of the fused kernel with the prior cells (as make_plan computes it)
         const int NCe = (c->NC + 1) & ~1, NE = (c->nedge + 1) & ~1;
-        const size_t fused = 8 * ((size_t)c->JP + kTrash + c->NC + kTrash + NE + 2) +
+        const size_t fused = 8 * ((size_t)c->JP + kTrash + c->NC + kTrash + NE + 2 + 64) +
                              4 * ((size_t)NCe + kTrash) + 4 * ((size_t)c->JP + 2 + NCe + NE + kLcTab);
         // the learned prior's judge grid, and FP32 histogram priors too large for
         // the fused kernel, are accumulated by the cell kernel

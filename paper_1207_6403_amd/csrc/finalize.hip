@@ -123,11 +123,10 @@ __global__ void __launch_bounds__(256) finalize_kernel(FinArgs<T, PT> a) {
         x2 += chi_prev[2 * k];
         x2i += chi_prev[2 * k + 1];
     }
-    // per-wave rows of the slots, kStatRows per thread in flight before the first
-    // wait (one dependent round trip per 256 * kStatRows rows, not per 256)
-    constexpr int kStatRows = 16;
+    // the slots' rows, kStatRows per thread in flight before the first wait
+    constexpr int kStatRows = 4;
     const double2* rows = reinterpret_cast<const double2*>(a.seg_stats);
-    for (int r0 = q0 * kStatWaves, r1 = q1 * kStatWaves; r0 < r1; r0 += 256 * kStatRows) {
+    for (int r0 = q0, r1 = q1; r0 < r1; r0 += 256 * kStatRows) {
         double2 v0[kStatRows], v1[kStatRows];
         #pragma unroll
         for (int u = 0; u < kStatRows; ++u) {

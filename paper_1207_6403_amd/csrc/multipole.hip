@@ -245,7 +245,9 @@ __global__ void __launch_bounds__(sizeof(T) == 8 ? 256 : 1024) mp_kick_drift_ker
         const int m = t < t1 ? ro(a.tile_model, t) : -2;
         if (m != cur) {
             if (cur >= 0) {
-                wave_stats(acc.S, acc.W, acc.W2, acc.mn, a.seg_stats + 4 * kStatWaves * (size_t)slot);
+                wave_stats(acc.S, acc.W, acc.W2, acc.mn, red);
+                __syncthreads();
+                if (tid == 0) block_stats_write(red, nt >> 6, a.seg_stats + 4 * (size_t)slot);
                 acc.S = acc.W = acc.W2 = 0;
                 acc.mn = INFINITY;
             }

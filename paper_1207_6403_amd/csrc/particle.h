@@ -23,12 +23,26 @@ __device__ __forceinline__ T wave_min(T v) {
 
 // Wave sum / min of four per-thread statistics into the wave's row of out
 // (out[4 w .. 4 w + 3] for wave w of the block): no block barrier.
-__device__ __forceinline__ void wave_stats(double s, double w, double w2, double mn, double* out) {
+// Weight statistics of a block, (S, sum w, sum w^2, min w): each wave reduces
+// its lanes and leaves its four values in lds[4 * wave ..] before a block
+// barrier the caller already has; after it, one thread adds the waves in order
+// and writes the block's row (deterministic, no extra barrier).
+__device__ __forceinline__ void wave_stats(double s, double w, double w2, double mn, double* lds) {
     s = wave_sum(s); w = wave_sum(w); w2 = wave_sum(w2); mn = wave_min(mn);
     if ((threadIdx.x & 63) == 0) {
-        double* o = out + 4 * (threadIdx.x >> 6);
+        double* o = lds + 4 * (threadIdx.x >> 6);
         o[0] = s; o[1] = w; o[2] = w2; o[3] = mn;
     }
+}
+__device__ __forceinline__ void block_stats_write(const double* lds, int nwave, double* out) {
+    double s = 0.0, w = 0.0, w2 = 0.0, mn = INFINITY;
+    for (int k = 0; k < nwave; ++k) {
+        s += lds[4 * k];
+        w += lds[4 * k + 1];
+        w2 += lds[4 * k + 2];
+        mn = fmin(mn, lds[4 * k + 3]);
+    }
+    out[0] = s; out[1] = w; out[2] = w2; out[3] = mn;
 }
 
 // Per-block working set of one model (LDS tables and model constants).

@@ -13,10 +13,6 @@ constexpr int kRing = 4096;          // statistics rows kept per model
 // scatters of particles outside every bin, or whose decision the FP64 fix-up
 // takes later, land there instead of branching around the atomic.
 constexpr int kTrash = 64;
-// Weight statistics are written per wave: kStatWaves rows of (S, sum w, sum w^2,
-// min w) per partial slot (a block has at most 16 waves; rows of absent waves
-// hold the identity).
-constexpr int kStatWaves = 16;
 constexpr int kSlotsPerSplit = 32;   // partial slots in flight per finalise thread
 constexpr int kFinCols = 32;         // columns per finalise block
 constexpr int kFinGroups = 8;        // slot groups per column (256 threads)
@@ -62,7 +58,7 @@ struct StepArgs {
     PT* part;                     // partial slots, chunk-major per model
     const int64_t* slot_base;     // column j of slot q: part[slot_base[q] + (j / kFinCols) *
     const int32_t* slot_stride;   //   slot_stride[q] + j % kFinCols]
-    double* seg_stats;            // nslot * 4
+    double* seg_stats;            // nslot * 4: (S, sum w, sum w^2, min w) per partial slot
     const T* edges;
     const double* edges64;        // the same edges in FP64
     int32_t nedge;

@@ -208,7 +208,8 @@ __global__ void __launch_bounds__(sizeof(T) == 8 ? 256 : 1024) step_kernel(StepA
     double* csum = hist + JP + kTrash;                               // NC, then kTrash
     double* ed64 = csum + NC + kTrash;                               // edges, FP64
     unsigned* ctr = reinterpret_cast<unsigned*>(ed64 + NE);         // work counter (2 doubles' room)
-    unsigned* ccnt = reinterpret_cast<unsigned*>(ed64 + NE + 2);     // NC (padded to even), then kTrash
+    double* wst = ed64 + NE + 2;                                     // 4 per wave: weight statistics
+    unsigned* ccnt = reinterpret_cast<unsigned*>(wst + 64);          // NC (padded to even), then kTrash
     T* cl = reinterpret_cast<T*>(ccnt + ((NC + 1) & ~1) + kTrash);   // J : Dt_j / sigma_j, zero to JP + 2
     T* cm = cl + JP + 2;                                             // NC: cell means
     T* ed = cm + ((NC + 1) & ~1);                                    // edges in T
@@ -332,16 +333,18 @@ __global__ void __launch_bounds__(sizeof(T) == 8 ? 256 : 1024) step_kernel(StepA
             c = cn;
         }
 
-        // flush the segment's histograms to its partial slot
+        // flush the segment's histograms to its partial slot, and its weight
+        // statistics (observing only, they belong to the kernel that updated
+        // the weights)
+        if (stepping) wave_stats(acc.S, acc.W, acc.W2, acc.mn, wst);
         __syncthreads();
+        if (stepping && tid == 0) block_stats_write(wst, nw, a.seg_stats + 4 * (size_t)slot);
         PT* dst = a.part + ro(a.slot_base, slot);
         const int64_t cs = ro(a.slot_stride, slot);
         auto at = [&](int j) -> PT& { return dst[(j / kFinCols) * cs + j % kFinCols]; };
         for (int j = tid; j < J; j += nt) at(j) = PT(hist[j]);
         if (accum)
             for (int c2 = tid; c2 < NC; c2 += nt) { at(JP + 2 * c2) = PT(csum[c2]); at(JP + 2 * c2 + 1) = PT(ccnt[c2]); }
-        // (observing only, the statistics belong to the kernel that updated the weights)
-        if (stepping) wave_stats(acc.S, acc.W, acc.W2, acc.mn, a.seg_stats + 4 * kStatWaves * (size_t)slot);
         acc.S = acc.W = acc.W2 = 0;
         acc.mn = INFINITY;
 
