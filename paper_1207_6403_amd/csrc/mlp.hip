@@ -114,6 +114,21 @@ constexpr int kThB2 = kThW2 + kMlpH * kW2Row;
 constexpr int kThW3 = kThB2 + kMlpH, kThB3 = kThW3 + kMlpH, kThN = kThB3 + 4;
 constexpr int kActRow = kMlpH + 1;
 
+// Copy the parameters into a block's LDS with all of a thread's loads issued
+// before the first wait (a load-then-store loop waits once per element).
+template <int NT, typename Put>
+__device__ __forceinline__ void load_theta(const float* __restrict__ theta, Put&& put) {
+    constexpr int kPer = (kMlpNP + NT - 1) / NT;
+    float v[kPer];
+    #pragma unroll
+    for (int u = 0; u < kPer; ++u) v[u] = theta[min(int(threadIdx.x) + u * NT, kMlpNP - 1)];
+    #pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+        const int i = int(threadIdx.x) + u * NT;
+        if (i < kMlpNP) put(i, v[u]);
+    }
+}
+
 __global__ void __launch_bounds__(kMlpTrainThreads) mlp_train_kernel(MlpArgs a, int b) {
     __shared__ __align__(16) float th[kThN];
     __shared__ float H1[kMlpSamples][kActRow], H2[kMlpSamples][kActRow];
@@ -122,15 +137,15 @@ __global__ void __launch_bounds__(kMlpTrainThreads) mlp_train_kernel(MlpArgs a, 
     if (*a.flag) return;
     const int tid = threadIdx.x, s = tid / kMlpTPS, q = tid % kMlpTPS;
     constexpr int UPT = kMlpH / kMlpTPS;   // units per thread
-    for (int i = tid; i < kMlpNP; i += kMlpTrainThreads) {
-        const float v = a.theta[i];
+    // the sample first: its load is then in flight with the parameters'
+    const float4 smp = a.sub[(size_t)b * a.batch + (size_t)blockIdx.x * kMlpSamples + s];
+    load_theta<kMlpTrainThreads>(a.theta, [&](int i, float v) {
         int d;
         if (i < kMlpW2) d = i;
         else if (i < kMlpB2) d = kThW2 + ((i - kMlpW2) / kMlpH) * kW2Row + (i - kMlpW2) % kMlpH;
         else d = kThB2 + (i - kMlpB2);
         th[d] = v;
-    }
-    const float4 smp = a.sub[(size_t)b * a.batch + (size_t)blockIdx.x * kMlpSamples + s];
+    });
     __syncthreads();
     // layer 1
     #pragma unroll
@@ -229,27 +244,38 @@ __global__ void __launch_bounds__(kMlpTrainThreads) mlp_train_kernel(MlpArgs a, 
     }
 }
 
-// One Adam step on the minibatch gradient; c1 = 1 - beta1^t, c2 = 1 - beta2^t.
-// Block: 64 parameters (lanes); wave w adds the blocks' partial rows w, w + 4, ...
-// in order (FP64), then the four wave sums are added in wave order.
-__global__ void __launch_bounds__(256) mlp_adam_kernel(MlpArgs a, int nblk, float c1, float c2) {
-    __shared__ double part[4][64];
-    if (*a.flag) return;
+// Sum of the training blocks' partial rows for parameter j = 64 blockIdx.x +
+// lane, in a fixed order (FP64): wave w of the 16 adds rows w, w + 16, ...
+// (16 rows in flight per round), then the wave sums are added in wave order.
+constexpr int kSumWaves = 16;
+__device__ __forceinline__ bool grad_row_sum(const MlpArgs& a, int nblk, double* part, float& g) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int j = blockIdx.x * 64 + lane;
     const int jj = min(j, kMlpNP - 1);
     double gs = 0.0;
-    for (int k0 = w; k0 < nblk; k0 += 4 * 8) {
-        float v[8];
+    for (int k0 = w; k0 < nblk; k0 += kSumWaves * 16) {
+        float v[16];
         #pragma unroll
-        for (int u = 0; u < 8; ++u) v[u] = a.gpart[(size_t)min(k0 + 4 * u, nblk - 1) * kMlpNP + jj];
+        for (int u = 0; u < 16; ++u) v[u] = a.gpart[(size_t)min(k0 + kSumWaves * u, nblk - 1) * kMlpNP + jj];
         #pragma unroll
-        for (int u = 0; u < 8; ++u) gs += k0 + 4 * u < nblk ? double(v[u]) : 0.0;
+        for (int u = 0; u < 16; ++u) gs += k0 + kSumWaves * u < nblk ? double(v[u]) : 0.0;
     }
-    part[w][lane] = gs;
+    part[w * 64 + lane] = gs;
     __syncthreads();
-    if (w != 0 || j >= kMlpNP) return;
-    const float g = float(((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane]);
+    if (w != 0 || j >= kMlpNP) return false;
+    double t = part[lane];
+    for (int k = 1; k < kSumWaves; ++k) t += part[k * 64 + lane];
+    g = float(t);
+    return true;
+}
+
+// One Adam step on the minibatch gradient; c1 = 1 - beta1^t, c2 = 1 - beta2^t.
+__global__ void __launch_bounds__(64 * kSumWaves) mlp_adam_kernel(MlpArgs a, int nblk, float c1, float c2) {
+    __shared__ double part[kSumWaves * 64];
+    if (*a.flag) return;
+    float g;
+    if (!grad_row_sum(a, nblk, part, g)) return;
+    const int j = blockIdx.x * 64 + (threadIdx.x & 63);
     const float m = a.beta1 * a.adam_m[j] + (1.0f - a.beta1) * g;
     const float v = a.beta2 * a.adam_v[j] + (1.0f - a.beta2) * g * g;
     a.adam_m[j] = m;
@@ -258,22 +284,10 @@ __global__ void __launch_bounds__(256) mlp_adam_kernel(MlpArgs a, int nblk, floa
 }
 
 // The minibatch gradient alone (the blocks' rows added as in mlp_adam_kernel).
-__global__ void __launch_bounds__(256) mlp_grad_sum_kernel(MlpArgs a, int nblk, float* grad) {
-    __shared__ double part[4][64];
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int j = blockIdx.x * 64 + lane;
-    const int jj = min(j, kMlpNP - 1);
-    double gs = 0.0;
-    for (int k0 = w; k0 < nblk; k0 += 4 * 8) {
-        float v[8];
-        #pragma unroll
-        for (int u = 0; u < 8; ++u) v[u] = a.gpart[(size_t)min(k0 + 4 * u, nblk - 1) * kMlpNP + jj];
-        #pragma unroll
-        for (int u = 0; u < 8; ++u) gs += k0 + 4 * u < nblk ? double(v[u]) : 0.0;
-    }
-    part[w][lane] = gs;
-    __syncthreads();
-    if (w == 0 && j < kMlpNP) grad[j] = float(((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane]);
+__global__ void __launch_bounds__(64 * kSumWaves) mlp_grad_sum_kernel(MlpArgs a, int nblk, float* grad) {
+    __shared__ double part[kSumWaves * 64];
+    float g;
+    if (grad_row_sum(a, nblk, part, g)) grad[blockIdx.x * 64 + (threadIdx.x & 63)] = g;
 }
 
 // Block partials of the inference passes: thread values reduced in a fixed tree.
@@ -298,7 +312,7 @@ __global__ void __launch_bounds__(kMlpInferThreads, 2) mlp_infer_kernel(MlpArgs 
     __shared__ double sh[kMlpInferThreads / 64];
     if (*a.flag) return;
     const int tid = threadIdx.x;
-    for (int i = tid; i < kMlpNP; i += blockDim.x) th[i] = a.theta[i];
+    load_theta<kMlpInferThreads>(a.theta, [&](int i, float v) { th[i] = v; });
     __syncthreads();
     double gmax = -INFINITY;
     for (int64_t p = (int64_t)blockIdx.x * blockDim.x + tid; p < a.n; p += (int64_t)gridDim.x * blockDim.x) {
@@ -408,7 +422,7 @@ static hipError_t refresh_pot(const MlpArgs& a, int t0, hipStream_t s) {
         const int t = t0 + b + 1;
         const float c1 = float(1.0 - std::pow(double(a.beta1), t)), c2 = float(1.0 - std::pow(double(a.beta2), t));
         hipLaunchKernelGGL(mlp_train_kernel, dim3(nblk), dim3(kMlpTrainThreads), 0, s, a, b);
-        hipLaunchKernelGGL(mlp_adam_kernel, dim3((kMlpNP + 63) / 64), dim3(256), 0, s, a, nblk, c1, c2);
+        hipLaunchKernelGGL(mlp_adam_kernel, dim3((kMlpNP + 63) / 64), dim3(64 * kSumWaves), 0, s, a, nblk, c1, c2);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     hipLaunchKernelGGL((mlp_infer_kernel<POT>), dim3(a.nblk), dim3(kMlpInferThreads), 0, s, a);
@@ -424,7 +438,7 @@ static hipError_t refresh_pot(const MlpArgs& a, int t0, hipStream_t s) {
 hipError_t launch_mlp_grad(const MlpArgs& a, float* grad, hipStream_t s) {
     const int nblk = a.batch / kMlpSamples;
     hipLaunchKernelGGL(mlp_train_kernel, dim3(nblk), dim3(kMlpTrainThreads), 0, s, a, 0);
-    hipLaunchKernelGGL(mlp_grad_sum_kernel, dim3((kMlpNP + 63) / 64), dim3(256), 0, s, a, nblk, grad);
+    hipLaunchKernelGGL(mlp_grad_sum_kernel, dim3((kMlpNP + 63) / 64), dim3(64 * kSumWaves), 0, s, a, nblk, grad);
     return hipGetLastError();
 }
 
