@@ -84,6 +84,24 @@ __device__ __forceinline__ T mpk_b(int l, int m) { if constexpr (sizeof(T) == 4)
 template <typename T>
 __device__ __forceinline__ T mpk_c(int l, int m) { if constexpr (sizeof(T) == 4) return kMpC.c[l][m]; else return kMpC.cd[l][m]; }
 
+// Copy of the FP32 node table (n float4 entries) into LDS by the block's nt
+// threads: each thread issues its kMpCopyRounds loads before the first LDS
+// write, so that the copy costs one memory round trip, not one per entry (the
+// largest table that fits LDS needs ten rounds of 1024 threads).
+constexpr int kMpCopyRounds = 10;
+__device__ __forceinline__ void mp_table_to_lds(float4* __restrict__ dst, const float4* __restrict__ src, int n,
+                                                int tid, int nt) {
+    for (int i0 = tid; i0 < n; i0 += kMpCopyRounds * nt) {
+        float4 v[kMpCopyRounds];
+        // indexes past the end re-read the last entry and write it back to its
+        // place (unconditional writes: no write waits in a branch of its own)
+        #pragma unroll
+        for (int k = 0; k < kMpCopyRounds; ++k) v[k] = src[min(i0 + k * nt, n - 1)];
+        #pragma unroll
+        for (int k = 0; k < kMpCopyRounds; ++k) dst[min(i0 + k * nt, n - 1)] = v[k];
+    }
+}
+
 // Potential and acceleration at (x, y, z) from a node table tab (FP64: nn nodes
 // of kMpW values, A then B; FP32: nn nodes of kMpRowF values, 16-byte (A cos,
 // B cos, A sin, B sin) entries by (l, m); the terms above the model's lmax are
@@ -233,8 +251,7 @@ __global__ void __launch_bounds__(sizeof(T) == 8 ? 256 : 1024) mp_kick_drift_ker
     const uint32_t wm = (fl >> kWhatShift) & 3u;
     const bool want_cm = wm == 1 || wm == 2;
     if constexpr (F32)
-        for (int i = tid; i < NT / 4; i += nt)
-            reinterpret_cast<float4*>(tabl)[i] = reinterpret_cast<const float4*>(mp.tab)[i];
+        mp_table_to_lds(reinterpret_cast<float4*>(tabl), reinterpret_cast<const float4*>(mp.tab), NT / 4, tid, nt);
     int slot = ro(a.block_slot0, blockIdx.x) - 1, cur = -1;
     Blk<T> B{};
     Acc acc;
@@ -644,8 +661,7 @@ __global__ void __launch_bounds__(sizeof(T) == 8 ? 256 : 1024) mp_kick_kernel(Mp
     float* tabl = reinterpret_cast<float*>(smem);
     const int NT = F32 ? mp.nn * kMpRowF : 0;
     if constexpr (F32)
-        for (int i = tid; i < NT / 4; i += nt)
-            reinterpret_cast<float4*>(tabl)[i] = reinterpret_cast<const float4*>(mp.tab)[i];
+        mp_table_to_lds(reinterpret_cast<float4*>(tabl), reinterpret_cast<const float4*>(mp.tab), NT / 4, tid, nt);
     __syncthreads();
     if (failed) return;
     const int t0 = ro(mp.block_tile0, blockIdx.x), t1 = ro(mp.block_tile0, blockIdx.x + 1);
