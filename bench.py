@@ -41,13 +41,14 @@ FP32_PEAK_TFLOPS = 157.3           # MI355X vector FP32 (published; packed FP32 
 def mp_flops_per_particle(lmax=8):
     """Algorithmic FP32 operations (an FMA counts 2) of the multipole
     update/kick/drift kernel per particle: per (l, m >= 0) term 12 to interpolate
-    the four node coefficients (a + t (b - a) each), 11 for the potential, 45 for
-    the gradient (6 for the two radial combinations, 12 for the solid-harmonic
-    derivatives, 15 to accumulate three components, 12 for the radial term) and 8
-    for the harmonic recurrence; per degree l 4 for the radial powers; 50 for the
-    set-up of the expansion point, the weight update, the kick and the drift."""
+    the four node coefficients (a + t (b - a) each), 12 for the potential (the two
+    normalised radial combinations P and their sum against Y_lm), 28 for the
+    gradient (9 each for the doubled x and y ladder sums, 5 for z, 5 for the radial
+    term) and 8 for the harmonic recurrence; per degree l 5 for the radial powers
+    and the radial sum; 60 for the set-up of the expansion point, the final
+    scaling of the gradient, the weight update, the kick and the drift."""
     terms = (lmax + 1) * (lmax + 2) // 2
-    return terms * (12 + 11 + 45 + 8) + (lmax + 1) * 4 + 50
+    return terms * (12 + 12 + 28 + 8) + (lmax + 1) * 5 + 60
 
 
 def kernel_sources_sha256():

@@ -58,11 +58,14 @@ __device__ __forceinline__ void mp_harmonics(T ux, T uy, T uz, T (&Yr)[kMpTri], 
 }
 
 // Recurrence and expansion constants by (l, m) for a loop over l that is not
-// unrolled (its index is uniform, so these are scalar loads): (2l-1)/(l-m),
-// (l+m-1)/(l-m) and c_lm = (2 - d_m0)(l-m)!/(l+m)!.
+// fully unrolled (its index is uniform, so these are scalar loads rather than
+// conversions): (2l-1)/(l-m), (l+m-1)/(l-m), c_lm = (2 - d_m0)(l-m)!/(l+m)!, l+m
+// and -(l+m)(l+m-1) (the derivative factors), and by l: 2l-1 and 2l+1.
 struct MpConst {
     float a[kMpL + 1][kMpL + 1], b[kMpL + 1][kMpL + 1], c[kMpL + 1][kMpL + 1];
+    float s[kMpL + 1][kMpL + 1], d[kMpL + 1][kMpL + 1], o[kMpL + 1], p[kMpL + 1];
     double ad[kMpL + 1][kMpL + 1], bd[kMpL + 1][kMpL + 1], cd[kMpL + 1][kMpL + 1];
+    double sd[kMpL + 1][kMpL + 1], dd[kMpL + 1][kMpL + 1], od[kMpL + 1], pd[kMpL + 1];
 };
 constexpr MpConst make_mp_const() {
     MpConst k{};
@@ -72,7 +75,13 @@ constexpr MpConst make_mp_const() {
             const double b = l - m >= 2 ? double(l + m - 1) / (l - m) : 0.0;
             k.a[l][m] = float(a); k.b[l][m] = float(b); k.c[l][m] = float(mp_c(l, m));
             k.ad[l][m] = a; k.bd[l][m] = b; k.cd[l][m] = mp_c(l, m);
+            k.s[l][m] = float(l + m); k.sd[l][m] = l + m;
+            k.d[l][m] = -float((l + m) * (l + m - 1)); k.dd[l][m] = -double((l + m) * (l + m - 1));
         }
+    for (int l = 0; l <= kMpL; ++l) {
+        k.o[l] = float(2 * l - 1); k.od[l] = 2 * l - 1;
+        k.p[l] = float(2 * l + 1); k.pd[l] = 2 * l + 1;
+    }
     return k;
 }
 __constant__ MpConst kMpC = make_mp_const();
@@ -83,6 +92,14 @@ template <typename T>
 __device__ __forceinline__ T mpk_b(int l, int m) { if constexpr (sizeof(T) == 4) return kMpC.b[l][m]; else return kMpC.bd[l][m]; }
 template <typename T>
 __device__ __forceinline__ T mpk_c(int l, int m) { if constexpr (sizeof(T) == 4) return kMpC.c[l][m]; else return kMpC.cd[l][m]; }
+template <typename T>
+__device__ __forceinline__ T mpk_s(int l, int m) { if constexpr (sizeof(T) == 4) return kMpC.s[l][m]; else return kMpC.sd[l][m]; }
+template <typename T>
+__device__ __forceinline__ T mpk_d(int l, int m) { if constexpr (sizeof(T) == 4) return kMpC.d[l][m]; else return kMpC.dd[l][m]; }
+template <typename T>
+__device__ __forceinline__ T mpk_o(int l) { if constexpr (sizeof(T) == 4) return kMpC.o[l]; else return kMpC.od[l]; }
+template <typename T>
+__device__ __forceinline__ T mpk_p(int l) { if constexpr (sizeof(T) == 4) return kMpC.p[l]; else return kMpC.pd[l]; }
 
 // Copy of the FP32 node table (n float4 entries) into LDS by the block's nt
 // threads: each thread issues its kMpCopyRounds loads before the first LDS
@@ -131,12 +148,21 @@ __device__ __forceinline__ void mp_field(const MpArgs<T>& mp, const TabT* __rest
     const TabT* t0 = tab + (size_t)k * (F4 ? kMpRowF : kMpW);
     const TabT* t1 = t0 + (F4 ? kMpRowF : kMpW);
     const T irc = T(1) / rc;
-    T U = T(0), gx = T(0), gy = T(0), gz = T(0);
+    // Every gradient contribution carries the factor 1/rc, applied once at the
+    // end: with P = A rc^-(l+1) + B rc^l (the term's radial factor in the
+    // potential), the derivative factors A rc^-(l+2) + B rc^(l-1) are P/rc, and the
+    // radial term of A r^-(l+1) is -(2l+1) A rc^-(l+2) Y_lm r^.  GX and GY hold
+    // twice the x and y sums (the ladder combinations carry a factor 1/2), R the
+    // radial sum.
+    T U = T(0), GX = T(0), GY = T(0), GZ = T(0), R = T(0);
     T rl = T(1), rn = irc;   // rc^l, rc^-(l+1)
     T Yr[kMpL + 1], Yi[kMpL + 1], Y1r[kMpL + 1], Y1i[kMpL + 1], Y2r[kMpL + 1], Y2i[kMpL + 1];
     #pragma unroll
     for (int m = 0; m <= kMpL; ++m) { Y1r[m] = Y1i[m] = Y2r[m] = Y2i[m] = T(0); }
-    #pragma unroll 1
+    // FP32: three degrees per pass, so that the three rows rotate through
+    // registers instead of being copied (FP64 keeps one: its registers are full)
+    constexpr int kLUnroll = sizeof(T) == 4 ? 3 : 1;
+    #pragma unroll kLUnroll
     for (int l = 0; l <= kMpL; ++l) {
         // row l of Y from rows l-1 and l-2
         #pragma unroll
@@ -146,13 +172,13 @@ __device__ __forceinline__ void mp_field(const MpArgs<T>& mp, const TabT* __rest
                 if (l == 0) {
                     yr = T(1);
                 } else {
-                    const T f = -T(2 * l - 1);
+                    const T f = -mpk_o<T>(l);
                     yr = f * (ux * Y1r[m > 0 ? m - 1 : 0] - uy * Y1i[m > 0 ? m - 1 : 0]);
                     yi = f * (ux * Y1i[m > 0 ? m - 1 : 0] + uy * Y1r[m > 0 ? m - 1 : 0]);
                 }
             } else if (m + 1 == l) {
-                yr = T(2 * l - 1) * uz * Y1r[m];
-                yi = T(2 * l - 1) * uz * Y1i[m];
+                yr = mpk_o<T>(l) * uz * Y1r[m];
+                yi = mpk_o<T>(l) * uz * Y1i[m];
             } else if (m + 2 <= l) {
                 const T fa = mpk_a<T>(l, m), fb = mpk_b<T>(l, m);
                 yr = fa * uz * Y1r[m] - fb * Y2r[m];
@@ -161,8 +187,7 @@ __device__ __forceinline__ void mp_field(const MpArgs<T>& mp, const TabT* __rest
             Yr[m] = yr;
             Yi[m] = yi;
         }
-        const T cA = rn * irc, cB = rl * irc;   // rc^-(l+2), rc^(l-1)
-        const int l2 = l * l;
+        T Rl = T(0);
         #pragma unroll
         for (int m = 0; m <= kMpL; ++m) {
             if (m > l) break;
@@ -178,7 +203,7 @@ __device__ __forceinline__ void mp_field(const MpArgs<T>& mp, const TabT* __rest
                 As = u.z + t * (v.z - u.z);
                 Bs = u.w + t * (v.w - u.w);
             } else {
-                const int jc = m == 0 ? l2 : l2 + 2 * m - 1;
+                const int jc = m == 0 ? (l * l) : (l * l) + 2 * m - 1;
                 Ac = T(t0[jc]) + t * (T(t1[jc]) - T(t0[jc]));
                 Bc = T(t0[nlm + jc]) + t * (T(t1[nlm + jc]) - T(t0[nlm + jc]));
                 if (m > 0) {
@@ -188,36 +213,35 @@ __device__ __forceinline__ void mp_field(const MpArgs<T>& mp, const TabT* __rest
                 }
             }
             const T yr = Yr[m], yi = Yi[m];
-            U += c * (yr * (Ac * rn + Bc * rl) + yi * (As * rn + Bs * rl));
-            const T gc = Ac * cA + Bc * cB, gs = As * cA + Bs * cB;
-            // gradient of R_lm over r^(l-1), from row l-1 (zero for l = 0)
+            const T Pc = c * (Ac * rn + Bc * rl), Ps = c * (As * rn + Bs * rl);
+            U += yr * Pc + yi * Ps;
+            // gradient of R_lm over r^(l-1), from row l-1 (zero for l = 0): x and y
+            // from the raising and lowering combinations, z from d/dz R_lm
             const T upr = m + 1 <= kMpL ? Y1r[m + 1 <= kMpL ? m + 1 : 0] : T(0);
             const T upi = m + 1 <= kMpL ? Y1i[m + 1 <= kMpL ? m + 1 : 0] : T(0);
-            T dxr, dxi, dyr, dyi;
             if (m == 0) {
-                dxr = upr; dxi = T(0); dyr = upi; dyi = T(0);
+                GX += T(2) * (upr * Pc);
+                GY += T(2) * (upi * Pc);
             } else {
-                const T f = -T((l + m) * (l + m - 1));
-                const T dnr = f * Y1r[m > 0 ? m - 1 : 0], dni = f * Y1i[m > 0 ? m - 1 : 0];
-                dxr = T(0.5) * (upr + dnr); dxi = T(0.5) * (upi + dni);
-                dyr = T(0.5) * (upi - dni); dyi = -T(0.5) * (upr - dnr);
+                const T f = mpk_d<T>(l, m);
+                const T dr = Y1r[m > 0 ? m - 1 : 0], di = Y1i[m > 0 ? m - 1 : 0];
+                GX += (upr * Pc + upi * Ps) + f * (dr * Pc + di * Ps);
+                GY += (upi * Pc - upr * Ps) - f * (di * Pc - dr * Ps);
             }
-            const T dzr = T(l + m) * Y1r[m], dzi = T(l + m) * Y1i[m];
-            gx += c * (dxr * gc + dxi * gs);
-            gy += c * (dyr * gc + dyi * gs);
-            gz += c * (dzr * gc + dzi * gs);
-            const T rad = c * T(2 * l + 1) * cA * (yr * Ac + yi * As);
-            gx -= rad * ux; gy -= rad * uy; gz -= rad * uz;
+            GZ += mpk_s<T>(l, m) * (Y1r[m] * Pc + Y1i[m] * Ps);
+            Rl += c * (yr * Ac + yi * As);
         }
+        R += mpk_p<T>(l) * rn * Rl;
         #pragma unroll
         for (int m = 0; m <= kMpL; ++m) { Y2r[m] = Y1r[m]; Y2i[m] = Y1i[m]; Y1r[m] = Yr[m]; Y1i[m] = Yi[m]; }
         rl *= rc;
         rn *= irc;
     }
     phi = -mp.G * U;
-    ax = mp.G * gx;
-    ay = mp.G * gy;
-    az = mp.G * gz;
+    const T gi = mp.G * irc;
+    ax = gi * (T(0.5) * GX - R * ux);
+    ay = gi * (T(0.5) * GY - R * uy);
+    az = gi * (GZ - R * uz);
 }
 
 // Interval of radius r: -1 below rmin, else k with r_k <= r < r_k+1 (k = nn-1 at

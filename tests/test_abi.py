@@ -78,6 +78,25 @@ def test_invalid_arguments_rejected_without_device(mutate, msg):
     assert msg in str(e.value)
 
 
+def test_empty_inputs_rejected_without_device():
+    """No particles at all, and a batch with one empty model: both are invalid
+    (every model's observables are sums over its own particles, section 2)."""
+    cfg, inp = _small()
+    cfg["N"] = 0
+    with pytest.raises(b.M2MError) as e:
+        b.m2m_create(cfg, inp["ics"][:, :0].copy(), inp["w"][:0].copy(), inp["Y"], inp["sigma"],
+                     Erange=np.array([-1.0, 0.0]))
+    assert e.value.status == 1 and "at least one particle" in str(e.value)
+    cfg = configs.cfg4(n_models=3, nmin=10, nmax=20)
+    cfg["model_sizes"] = np.array([12, 0, 15], dtype=np.int64)
+    cfg["N"] = 27
+    inp = configs.make_inputs(configs.cfg4(n_models=3, nmin=10, nmax=20))
+    with pytest.raises(b.M2MError) as e:
+        b.m2m_create(cfg, inp["ics"][:, :27].copy(), inp["w"][:27].copy(), inp["Y"], inp["sigma"],
+                     Erange=np.tile([-1.0, 0.0], 3))
+    assert e.value.status == 1 and "at least one particle" in str(e.value)
+
+
 def test_target_size_mismatch_rejected():
     cfg, inp = _small()
     with pytest.raises(b.M2MError) as e:
