@@ -595,14 +595,32 @@ __global__ void __launch_bounds__(256) mp_accum_kernel(MpArgs<float> mp) {
             rn *= ir;
         }
     }
+    // Wave sums of the kMpW values, reduced and scattered at once: padded to 3 x
+    // 64 values, each level pairs lanes L and L ^ o; a lane keeps the half of its
+    // values that its bit o selects, sends the other half to its partner and adds
+    // what it receives.  After the six levels lane L holds the sums of values
+    // 3L, 3L + 1 and 3L + 2 (189 independent exchanges instead of 6 dependent
+    // ones per value).
+    constexpr int kRs = 3 * 64;
+    static_assert(kMpW <= kRs, "reduce-scatter holds 3 values per lane");
+    float a[kRs];
+    #pragma unroll
+    for (int v = 0; v < kRs; ++v) a[v] = v < kMpW ? acc[v] : 0.0f;
+    #pragma unroll
+    for (int lv = 0; lv < 6; ++lv) {
+        const int o = 32 >> lv, h = (kRs / 2) >> lv;
+        const bool up = (lane & o) != 0;
+        #pragma unroll
+        for (int i = 0; i < h; ++i) {
+            const float keep = up ? a[i + h] : a[i];
+            const float send = up ? a[i] : a[i + h];
+            a[i] = keep + __shfl_xor(send, o, 64);
+        }
+    }
     float* dst = mp.part + (size_t)c * kMpW;
     #pragma unroll
-    for (int v = 0; v < kMpW; ++v) {
-        float t = acc[v];
-        #pragma unroll
-        for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o, 64);
-        if (lane == (v & 63)) dst[v] = t;
-    }
+    for (int j = 0; j < 3; ++j)
+        if (3 * lane + j < kMpW) dst[3 * lane + j] = a[j];
 }
 
 // Interval sums of key k (interval k - 1, row k of S): the key's chunks added in
