@@ -66,7 +66,7 @@ constexpr int kMlpNP = kMlpH * 3 + kMlpH + kMlpH * kMlpH + kMlpH + kMlpH + 1;   
 constexpr int kMlpW1 = 0, kMlpB1 = kMlpW1 + kMlpH * 3, kMlpW2 = kMlpB1 + kMlpH, kMlpB2 = kMlpW2 + kMlpH * kMlpH,
               kMlpW3 = kMlpB2 + kMlpH, kMlpB3 = kMlpW3 + kMlpH;
 constexpr int kMlpSamples = 32;        // samples per training block
-constexpr int kMlpTPS = 8;             // threads per sample
+constexpr int kMlpTPS = 16;            // threads per sample
 constexpr int kMlpTrainThreads = kMlpSamples * kMlpTPS;
 constexpr int kMlpInferThreads = 256;
 constexpr int kMlpMaxInferBlocks = 2048;

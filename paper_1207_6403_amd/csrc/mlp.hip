@@ -103,7 +103,7 @@ __device__ __forceinline__ float mlp_forward(const float* th, float u0, float u1
 
 // Minibatch b, block of kMlpSamples samples (b*batch + blockIdx.x*kMlpSamples on),
 // kMlpTPS threads per sample: thread t takes sample s = t / kMlpTPS and the units
-// q*8 .. q*8+7 (q = t % kMlpTPS) of each layer; activations and deltas are shared
+// q*UPT .. q*UPT+UPT-1 (q = t % kMlpTPS, UPT = 64 / kMlpTPS) of each layer; activations and deltas are shared
 // in LDS.  Loss (g - t)^2 averaged over the minibatch.  The block's gradient sums
 // over its samples (in sample order) go to its partial row.  W2 is held in LDS
 // with rows padded to kW2Row floats, so that the eight rows a wave reads at once
@@ -202,21 +202,24 @@ __global__ void __launch_bounds__(kMlpTrainThreads) mlp_train_kernel(MlpArgs a, 
         D1[s][i] = d1[k] * (1.0f - h * h);
     }
     __syncthreads();
-    // sums over the block's samples: thread t takes W2 row o = t / 4, columns
-    // 16 (t % 4) .. +15; threads t < 64 also row t of b2, W3, b1, W1, thread 0 b3
+    // sums over the block's samples: kTPR threads per W2 row, thread t takes row
+    // o = t / kTPR, columns kCols (t % kTPR) .. +kCols-1; threads t < 64 also row
+    // t of b2, W3, b1, W1, thread 0 b3
     float* dst = a.gpart + (size_t)blockIdx.x * kMlpNP;
     {
-        const int o = tid >> 2, i0 = 16 * (tid & 3);
-        float gw[16];
+        constexpr int kTPR = kMlpTrainThreads / kMlpH, kCols = kMlpH / kTPR;
+        static_assert(kTPR * kMlpH == kMlpTrainThreads && kCols * kTPR == kMlpH, "W2 rows split evenly");
+        const int o = tid / kTPR, i0 = kCols * (tid % kTPR);
+        float gw[kCols];
         #pragma unroll
-        for (int j = 0; j < 16; ++j) gw[j] = 0.0f;
+        for (int j = 0; j < kCols; ++j) gw[j] = 0.0f;
         for (int ss = 0; ss < kMlpSamples; ++ss) {
             const float d2 = D2[ss][o];
             #pragma unroll
-            for (int j = 0; j < 16; ++j) gw[j] += d2 * H1[ss][i0 + j];
+            for (int j = 0; j < kCols; ++j) gw[j] += d2 * H1[ss][i0 + j];
         }
         #pragma unroll
-        for (int j = 0; j < 16; ++j) dst[kMlpW2 + kMlpH * o + i0 + j] = gw[j];
+        for (int j = 0; j < kCols; ++j) dst[kMlpW2 + kMlpH * o + i0 + j] = gw[j];
     }
     if (tid < kMlpH) {
         const int o = tid;
