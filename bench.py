@@ -148,7 +148,8 @@ WORKLOADS = {
             "steps on a 2^20 sample (128 Adam minibatches of 8192), judged against a 32x32x8 (E, L/Lc, Lz/L) "
             "histogram prior, J=4896, dt=0.005"),
 }
-DEFAULT_CPU_STEPS = {"logpot": 24, "batched": 24, "multipole": 2, "mlp": 2}
+# oracle steps of the CPU sample: about 10-15 s on 16 host threads
+DEFAULT_CPU_STEPS = {"logpot": 96, "batched": 96, "multipole": 6, "mlp": 8}
 
 
 def main():

@@ -418,6 +418,8 @@ __device__ __forceinline__ uint32_t wave_excl_scan(uint32_t v, uint32_t* total) 
 }
 
 // Block b's particles [b R, (b + 1) R): interval keys and per-interval counts.
+constexpr int kMpSortRun = 8;   // particles per thread per round of the sort kernels
+
 __global__ void __launch_bounds__(kMpSortThreads) mp_interval_kernel(MpArgs<float> mp) {
     __shared__ uint32_t cnt[kMpMaxNodes + 1];
     if (*mp.flag) return;
@@ -426,12 +428,25 @@ __global__ void __launch_bounds__(kMpSortThreads) mp_interval_kernel(MpArgs<floa
     __syncthreads();
     const int64_t p0 = (int64_t)b * mp.R, p1 = min(mp.n, p0 + mp.R);
     const uint32_t rb = uint32_t(mp.stride * 4);
-    for (int64_t p = p0 + tid; p < p1; p += nt) {
-        const uint32_t o = uint32_t(p) * 4u;
-        const int k1 = mp_interval_f32(mp, ld_at<float>(mp.src, o), ld_at<float>(mp.src, o + rb),
-                                       ld_at<float>(mp.src, o + 2 * rb)) + 1;
-        mp.key[p] = (uint16_t)k1;
-        atomicAdd(&cnt[k1], 1u);
+    // kMpSortRun particles per thread per round, all loaded before the first is
+    // decided (indexes past the end re-read the last particle, rewrite its key
+    // and count nothing)
+    for (int64_t pb = p0 + tid; pb < p1; pb += (int64_t)kMpSortRun * nt) {
+        float x[kMpSortRun], y[kMpSortRun], z[kMpSortRun];
+        #pragma unroll
+        for (int u = 0; u < kMpSortRun; ++u) {
+            const uint32_t o = uint32_t(min(pb + (int64_t)u * nt, p1 - 1)) * 4u;
+            x[u] = ld_at<float>(mp.src, o);
+            y[u] = ld_at<float>(mp.src, o + rb);
+            z[u] = ld_at<float>(mp.src, o + 2 * rb);
+        }
+        #pragma unroll
+        for (int u = 0; u < kMpSortRun; ++u) {
+            const int64_t p = pb + (int64_t)u * nt;
+            const int k1 = mp_interval_f32(mp, x[u], y[u], z[u]) + 1;
+            mp.key[min(p, p1 - 1)] = (uint16_t)k1;
+            atomicAdd(&cnt[k1], p < p1 ? 1u : 0u);
+        }
     }
     __syncthreads();
     for (int i = tid; i <= nn; i += nt) mp.counts[(size_t)i * mp.G_sort + b] = cnt[i];
@@ -486,12 +501,27 @@ __global__ void __launch_bounds__(kMpSortThreads) mp_scatter_kernel(MpArgs<float
     __syncthreads();
     const int64_t p0 = (int64_t)b * mp.R, p1 = min(mp.n, p0 + mp.R);
     const uint32_t rb = uint32_t(mp.stride * 4);
-    for (int64_t p = p0 + tid; p < p1; p += nt) {
-        const uint32_t o = uint32_t(p) * 4u;
-        const float x = ld_at<float>(mp.src, o), y = ld_at<float>(mp.src, o + rb), z = ld_at<float>(mp.src, o + 2 * rb);
-        const float w = ld_at<float>(mp.src, o + 6 * rb);
-        const uint32_t pos = atomicAdd(&off[mp.key[p]], 1u);
-        mp.sorted[pos] = make_float4(x, y, z, w);
+    // kMpSortRun particles per thread per round, all loaded before the first
+    // position is claimed (indexes past the end re-read the last particle and
+    // claim nothing)
+    for (int64_t pb = p0 + tid; pb < p1; pb += (int64_t)kMpSortRun * nt) {
+        float4 v[kMpSortRun];
+        uint32_t key[kMpSortRun];
+        #pragma unroll
+        for (int u = 0; u < kMpSortRun; ++u) {
+            const int64_t p = min(pb + (int64_t)u * nt, p1 - 1);
+            const uint32_t o = uint32_t(p) * 4u;
+            v[u] = make_float4(ld_at<float>(mp.src, o), ld_at<float>(mp.src, o + rb), ld_at<float>(mp.src, o + 2 * rb),
+                               ld_at<float>(mp.src, o + 6 * rb));
+            key[u] = mp.key[p];
+        }
+        #pragma unroll
+        for (int u = 0; u < kMpSortRun; ++u) {
+            if (pb + (int64_t)u * nt < p1) {
+                const uint32_t pos = atomicAdd(&off[key[u]], 1u);
+                mp.sorted[pos] = v[u];
+            }
+        }
     }
 }
 
