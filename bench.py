@@ -149,7 +149,7 @@ WORKLOADS = {
             "histogram prior, J=4896, dt=0.005"),
 }
 # oracle steps of the CPU sample: about 10-15 s on 16 host threads
-DEFAULT_CPU_STEPS = {"logpot": 96, "batched": 96, "multipole": 6, "mlp": 8}
+DEFAULT_CPU_STEPS = {"logpot": 96, "batched": 220, "multipole": 6, "mlp": 150}
 
 
 def main():
