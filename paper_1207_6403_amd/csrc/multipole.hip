@@ -665,12 +665,14 @@ __global__ void __launch_bounds__(256) mp_chunksum_kernel(MpArgs<float> mp) {
     const int j0 = (int)c0[k], j1 = (int)c0[k + 1];
     const float* src = mp.part + v;
     double acc = 0.0;
-    for (int j = j0; j < j1; j += 8) {
-        float u[8];
+    // 32 chunk rows in flight per round, added in chunk order
+    constexpr int kRun = 32;
+    for (int j = j0; j < j1; j += kRun) {
+        float u[kRun];
         #pragma unroll
-        for (int q = 0; q < 8; ++q) u[q] = src[(size_t)min(j + q, j1 - 1) * kMpW];
+        for (int q = 0; q < kRun; ++q) u[q] = src[(size_t)min(j + q, j1 - 1) * kMpW];
         #pragma unroll
-        for (int q = 0; q < 8; ++q) acc += j + q < j1 ? double(u[q]) : 0.0;
+        for (int q = 0; q < kRun; ++q) acc += j + q < j1 ? double(u[q]) : 0.0;
     }
     const int jj = v < kMpNlm ? v : v - kMpNlm;
     int l = 0;
@@ -700,19 +702,39 @@ __global__ void __launch_bounds__(128) mp_scan_kernel(MpArgs<T> mp) {
     const int e = 2 * l * (l + 1) + 4 * m + 2 * sn;
     constexpr bool F4 = sizeof(T) == 4;
     const int rowlen = F4 ? kMpRowF : W, ea = F4 ? e : v, eb = F4 ? e + 1 : kMpNlm + v;
-    if (tid == 0) {
-        double acc = 0.0;
-        for (int k = 0; k < nn; ++k) {
-            acc += colA[k];
-            if (v < nlm) mp.A64[(size_t)k * nlm + v] = acc;
-            mp.tab_out[(size_t)k * rowlen + ea] = T(acc);
+    // wave 0: A at node k = colA[0] + ... + colA[k]; wave 1: B at node k =
+    // colB[nn] + ... + colB[k + 1], i.e. the same scan along i = nn - 1 - k.
+    // Each lane adds a run of kRun consecutive terms in order; the runs' totals
+    // are scanned across the wave, and each lane adds the total before its run
+    // to its own partial sums (a fixed order).
+    const int lane = tid & 63, wv = tid >> 6;
+    if (wv < 2) {
+        constexpr int kRun = (kMpMaxNodes + 63) / 64;
+        const int i0 = lane * kRun;
+        double part[kRun], run = 0.0;
+        #pragma unroll
+        for (int q = 0; q < kRun; ++q) {
+            const int i = i0 + q;
+            run += i < nn ? (wv == 0 ? colA[i] : colB[nn - i]) : 0.0;
+            part[q] = run;
         }
-    } else if (tid == 64) {
-        double acc = 0.0;
-        for (int k = nn - 1; k >= 0; --k) {
-            acc += colB[k + 1];
-            if (v < nlm) mp.B64[(size_t)k * nlm + v] = acc;
-            mp.tab_out[(size_t)k * rowlen + eb] = T(acc);
+        double inc = run;
+        #pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const double u = __shfl_up(inc, d, 64);
+            if (lane >= d) inc += u;
+        }
+        double before = __shfl_up(inc, 1, 64);
+        if (lane == 0) before = 0.0;
+        #pragma unroll
+        for (int q = 0; q < kRun; ++q) {
+            const int i = i0 + q;
+            if (i < nn) {
+                const double val = before + part[q];
+                const int k = wv == 0 ? i : nn - 1 - i;
+                if (v < nlm) (wv == 0 ? mp.A64 : mp.B64)[(size_t)k * nlm + v] = val;
+                mp.tab_out[(size_t)k * rowlen + (wv == 0 ? ea : eb)] = T(val);
+            }
         }
     }
     if constexpr (sizeof(T) == 8) {
