@@ -83,9 +83,10 @@ constexpr uint64_t layout_sig(int nbin, uint64_t c0, uint64_t c1 = 0, uint64_t c
     return uint64_t(nbin) | c0 << 4 | c1 << 14 | c2 << 24 | c3 << 34;
 }
 // The layouts with compiled kernels: sky pixels (mass) with a kinematic grid
-// (first and second LOS moments); 3D shells (mass) with projected annuli
-// (second LOS moment).
+// (first and second LOS moments), alone or followed by 3D shells (mass); 3D
+// shells (mass) with projected annuli (second LOS moment).
 constexpr uint64_t kSigPixKin = layout_sig(2, bin_code(3, 1, 0), bin_code(3, 2, 1 | 2 << 2));
+constexpr uint64_t kSigPixKinShell = layout_sig(3, bin_code(3, 1, 0), bin_code(3, 2, 1 | 2 << 2), bin_code(1, 1, 0));
 constexpr uint64_t kSigShellAnn = layout_sig(2, bin_code(1, 1, 0), bin_code(2, 1, 2));
 
 // Structure of the layout seen by a kernel compiled for signature SIG.

@@ -456,8 +456,10 @@ static hipError_t launch_k(const StepArgs<T, PT>& a, int ilp, int blocks, int th
 template <typename T, typename PT, int POT>
 static hipError_t launch_step_pot(const StepArgs<T, PT>& a, uint64_t sig, int nbin, int ilp, int blocks, int threads,
                                   size_t lds, hipStream_t s) {
-    if constexpr (sizeof(T) == 4 && POT == 1)
+    if constexpr (sizeof(T) == 4 && POT == 1) {
         if (sig == kSigPixKin) return launch_k<T, PT, POT, 2, kSigPixKin>(a, ilp, blocks, threads, lds, s);
+        if (sig == kSigPixKinShell) return launch_k<T, PT, POT, 4, kSigPixKinShell>(a, ilp, blocks, threads, lds, s);
+    }
     if constexpr (sizeof(T) == 4 && POT != 1)
         if (sig == kSigShellAnn) return launch_k<T, PT, POT, 2, kSigShellAnn>(a, ilp, blocks, threads, lds, s);
     if (nbin <= 2) return launch_k<T, PT, POT, 2, 0>(a, ilp, blocks, threads, lds, s);
@@ -487,8 +489,10 @@ template <typename T, typename PT, int POT>
 static hipError_t set_lds_pot(size_t lds) {
     hipError_t e = set_lds_k<T, PT, POT, 2, 0>(lds);
     if (e == hipSuccess) e = set_lds_k<T, PT, POT, 4, 0>(lds);
-    if constexpr (sizeof(T) == 4 && POT == 1)
+    if constexpr (sizeof(T) == 4 && POT == 1) {
         if (e == hipSuccess) e = set_lds_k<T, PT, POT, 2, kSigPixKin>(lds);
+        if (e == hipSuccess) e = set_lds_k<T, PT, POT, 4, kSigPixKinShell>(lds);
+    }
     if constexpr (sizeof(T) == 4 && POT != 1)
         if (e == hipSuccess) e = set_lds_k<T, PT, POT, 2, kSigShellAnn>(lds);
     return e;
