@@ -788,7 +788,10 @@ static hipError_t launch_kd(const StepArgs<T, PT>& a, const MpArgs<T>& mp, int b
 template <typename T, typename PT>
 hipError_t launch_mp_step(const StepArgs<T, PT>& a, const MpArgs<T>& mp, uint64_t sig, int nbin, int blocks,
                           const MpLds& lds, hipStream_t s) {
-    (void)sig;
+    // the sky pixels + kinematics + shells layout has a kernel of its own (kinds
+    // and moments fixed at compile time), as in the fused step kernel
+    if constexpr (sizeof(T) == 4)
+        if (sig == kSigPixKinShell) return launch_kd<T, PT, 4, kSigPixKinShell>(a, mp, blocks, lds.kick_drift, s);
     if (nbin <= 2) return launch_kd<T, PT, 2, 0>(a, mp, blocks, lds.kick_drift, s);
     return launch_kd<T, PT, 4, 0>(a, mp, blocks, lds.kick_drift, s);
 }
@@ -819,6 +822,9 @@ hipError_t set_mp_lds_limit(size_t lds) {
         hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
+    if constexpr (sizeof(T) == 4)
+        return hipFuncSetAttribute((const void*)mp_kick_drift_kernel<T, PT, 4, kSigPixKinShell>,
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     return hipSuccess;
 }
 
