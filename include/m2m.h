@@ -287,6 +287,27 @@ m2m_status m2m_mlp_state(m2m_ctx *ctx, float *theta, double *judge, int32_t *use
 m2m_status m2m_mlp_loss_grad(m2m_ctx *ctx, const float *theta, const float *samples, int32_t n, float *grad,
                              double *loss);
 
+/* The loss and gradient of m2m_mlp_loss_grad, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc): this call allocates nothing.  Its working memory (the
+ * training blocks' partial gradient rows and the per-sample loss terms) is a
+ * static array of the library, one copy per device, sized for at most
+ * M2M_MLP_NOALLOC_MAX samples (4.6 MB), held from the first m2m_create on that
+ * device until the process ends.  theta (M2M_MLP_NPARAM FP32), samples (n rows
+ * of (u0, u1, u2, t) FP32, 16-byte aligned), grad (M2M_MLP_NPARAM FP32) and loss
+ * (one FP64, nullable: the sum of the per-sample terms, i.e. the mean) are
+ * device pointers on the context's device, owned by the caller.  The work is
+ * enqueued on the context's stream and the call returns without waiting:
+ * results are valid once that stream has been synchronised.  The kernels are
+ * those of m2m_mlp_loss_grad (bitwise the same gradient).  Every call on a
+ * device shares that device's array: calls that overlap on one device (other
+ * contexts, other streams) race.  INVALID for a null argument, a context
+ * without a learned prior, n not a positive multiple of 32 or above
+ * M2M_MLP_NOALLOC_MAX, or misaligned samples. */
+#define M2M_MLP_NOALLOC_MAX 8192
+m2m_status m2m_mlp_loss_grad_noalloc(m2m_ctx *ctx, const float *theta, const float *samples, int32_t n,
+                                     float *grad, double *loss);
+
 /* Time candidate launch shapes (threads x ilp x blocks_per_cu) on trial_steps
  * steps each, restore the state, keep the fastest; chosen may be NULL.  The
  * choice is cached in the JSON file named by $M2M_AUTOTUNE_CACHE if set. */

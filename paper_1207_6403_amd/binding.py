@@ -110,6 +110,7 @@ def lib():
                                     C.POINTER(C.c_int64)]
         L.m2m_mlp_loss_grad.argtypes = [CTX, C.POINTER(C.c_float), C.POINTER(C.c_float), C.c_int32,
                                         C.POINTER(C.c_float), C.POINTER(C.c_double)]
+        L.m2m_mlp_loss_grad_noalloc.argtypes = [CTX, VP, VP, C.c_int32, VP, VP]
         L.m2m_autotune.argtypes = [CTX, C.c_int32, C.POINTER(m2m_launch)]
         L.m2m_get_launch.argtypes = [CTX, C.POINTER(m2m_launch)]
         L.m2m_set_launch.argtypes = [CTX, C.POINTER(m2m_launch)]
@@ -119,7 +120,7 @@ def lib():
         L.m2m_last_error.argtypes = [CTX]
         L.m2m_last_error.restype = C.c_char_p
         for f in ("m2m_create", "m2m_step", "m2m_observables", "m2m_weights", "m2m_priors", "m2m_particles",
-                  "m2m_history", "m2m_multipole_tables", "m2m_mlp_state", "m2m_mlp_loss_grad", "m2m_autotune", "m2m_get_launch", "m2m_set_launch", "m2m_kernel_time"):
+                  "m2m_history", "m2m_multipole_tables", "m2m_mlp_state", "m2m_mlp_loss_grad", "m2m_mlp_loss_grad_noalloc", "m2m_autotune", "m2m_get_launch", "m2m_set_launch", "m2m_kernel_time"):
             getattr(L, f).restype = C.c_int
         if L.m2m_abi_version() != ABI_VERSION:
             raise ImportError("libm2m_hip.so ABI %d, binding expects %d" % (L.m2m_abi_version(), ABI_VERSION))
@@ -393,6 +394,21 @@ def m2m_mlp_loss_grad(ctx, theta, samples):
     _check(lib().m2m_mlp_loss_grad(ctx.ptr, th.ctypes.data_as(fp), sm.ctypes.data_as(fp), sm.shape[0],
                                    g.ctypes.data_as(fp), C.byref(loss)), ctx)
     return loss.value, g
+
+
+MLP_NOALLOC_MAX = 8192
+
+
+def m2m_mlp_loss_grad_noalloc(ctx, theta, samples, grad, loss=None):
+    """The same loss and gradient with no device allocation: theta (float32 [4481]),
+    samples (float32 [n, 4]), grad (float32 [4481]) and loss (float64 [1] or None)
+    are device tensors (torch, on the context's device).  Enqueued on the context's
+    stream; synchronise before reading grad and loss."""
+    n = int(samples.shape[0])
+    _check(lib().m2m_mlp_loss_grad_noalloc(ctx.ptr, C.c_void_p(int(theta.data_ptr())),
+                                           C.c_void_p(int(samples.data_ptr())), n,
+                                           C.c_void_p(int(grad.data_ptr())),
+                                           C.c_void_p(int(loss.data_ptr())) if loss is not None else None), ctx)
 
 
 def _launch_dict(L):

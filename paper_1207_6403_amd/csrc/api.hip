@@ -1125,6 +1125,17 @@ extern "C" m2m_status m2m_create(const m2m_config* cfg, const m2m_obs_layout* la
     hipError_t e = hipGetDevice(&c->device);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&c->numCU, hipDeviceAttributeMultiprocessorCount, c->device);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&c->max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device);
+    if (e == hipSuccess) {
+        // the static scratch of the allocation-free entry point: its device
+        // address, looked up once per device (with the device current); a failed
+        // lookup disables that entry point only
+        const hipError_t es = mlp_noalloc_scratch(c->device, &c->noalloc_scratch);
+        if (es != hipSuccess) {
+            (void)hipGetLastError();
+            c->noalloc_scratch = nullptr;
+            c->noalloc_error = std::string("hipGetSymbolAddress of the scratch array: ") + hipGetErrorString(es);
+        }
+    }
     if (e == hipSuccess && !c->stream) {
         // the legacy default stream cannot be captured into graphs: run on a
         // stream of our own (default priority) unless the caller names one
@@ -1455,6 +1466,27 @@ extern "C" m2m_status m2m_mlp_loss_grad(m2m_ctx* c, const float* theta, const fl
         for (float v : hl) t += v;
         *loss = t;
     }
+    return M2M_OK;
+}
+
+extern "C" m2m_status m2m_mlp_loss_grad_noalloc(m2m_ctx* c, const float* theta, const float* samples, int32_t n,
+                                                float* grad, double* loss) {
+    if (!c) return fail(nullptr, M2M_ERR_INVALID, "ctx is NULL");
+    if (c->prior.kind != M2M_PRIOR_MLP) return fail(c, M2M_ERR_INVALID, "the context has no learned prior");
+    if (!theta || !samples || !grad) return fail(c, M2M_ERR_INVALID, "null argument");
+    if (n < kMlpSamples || n % kMlpSamples) return fail(c, M2M_ERR_INVALID, "n must be a positive multiple of 32");
+    if (n > kMlpNoAllocMax)
+        return fail(c, M2M_ERR_INVALID, "n must be at most " + std::to_string(kMlpNoAllocMax) +
+                                            " samples (the size of the static scratch)");
+    if (((uintptr_t)samples & 15) != 0) return fail(c, M2M_ERR_INVALID, "samples must be 16-byte aligned");
+    if (m2m_status s = sticky(c)) return s;
+    if (!c->noalloc_scratch) return fail(c, M2M_ERR_DEVICE, c->noalloc_error);
+    MlpArgs a{};
+    fill_mlp_args(c, a, c->step);
+    a.theta = const_cast<float*>(theta);
+    a.sub = reinterpret_cast<float4*>(const_cast<float*>(samples));
+    a.batch = n;
+    HIPCHK(c, launch_mlp_grad_noalloc(a, c->noalloc_scratch, grad, loss, c->stream));
     return M2M_OK;
 }
 

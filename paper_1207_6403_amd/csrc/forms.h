@@ -108,6 +108,18 @@ hipError_t launch_mlp_refresh(const MlpArgs& a, int pot_kind, int t0, hipStream_
 // a.sub at the parameters a.theta (the training kernels of a refresh, without
 // the Adam step): grad gets kMlpNP values.
 hipError_t launch_mlp_grad(const MlpArgs& a, float* grad, hipStream_t s);
+// The same with no allocation: the partial rows and loss terms of at most
+// kMlpNoAllocMax samples live in the library's static scratch array of the
+// device (scratch_ptr, from mlp_noalloc_scratch); a.theta, a.sub and grad are
+// the caller's device buffers; loss (device, nullable) gets the sum of the loss
+// terms.  Calls that overlap on one device share the scratch and race.
+constexpr int kMlpNoAllocMax = 8192;
+constexpr size_t kMlpNoAllocFloats = (size_t)(kMlpNoAllocMax / kMlpSamples) * kMlpNP + kMlpNoAllocMax;
+constexpr int kMaxDevices = 64;
+hipError_t launch_mlp_grad_noalloc(MlpArgs a, float* scratch_ptr, float* grad, double* loss, hipStream_t s);
+// Device address of that scratch array on `device` (which must be current),
+// looked up once per device and kept.
+hipError_t mlp_noalloc_scratch(int device, float** out);
 
 // Weight update, first kick and drift of a multipole step (the coefficients of
 // the new state and the second kick follow with launch_mp_build).

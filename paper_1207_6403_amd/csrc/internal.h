@@ -77,6 +77,8 @@ struct m2m_ctx {
     double* mlp_red = nullptr;
     double* mlp_stats = nullptr;
     int mlp_nblk = 0;
+    float* noalloc_scratch = nullptr;   // the device's static scratch (m2m_mlp_loss_grad_noalloc)
+    std::string noalloc_error;          // why it is null, if it is
     int64_t mlp_t = 0;
     // prior cells accumulated by a kernel of their own (the fused kernel then
     // observes without them): its LDS bytes

@@ -18,6 +18,8 @@
 //                 the fallback threshold
 // with single-block reductions of the per-block partials in between, in block
 // order (deterministic).
+#include <mutex>
+
 #include "forms.h"
 
 namespace m2m {
@@ -442,6 +444,59 @@ hipError_t launch_mlp_grad(const MlpArgs& a, float* grad, hipStream_t s) {
     const int nblk = a.batch / kMlpSamples;
     hipLaunchKernelGGL(mlp_train_kernel, dim3(nblk), dim3(kMlpTrainThreads), 0, s, a, 0);
     hipLaunchKernelGGL(mlp_grad_sum_kernel, dim3((kMlpNP + 63) / 64), dim3(64 * kSumWaves), 0, s, a, nblk, grad);
+    return hipGetLastError();
+}
+
+// ------------------------------------------- loss and gradient without allocation
+// The working memory of launch_mlp_grad_noalloc: the training blocks' partial
+// gradient rows, then the per-sample loss terms, for at most kMlpNoAllocMax
+// samples.  Each device that runs the library holds one copy until the process
+// ends.  Host code never uses this name as an address: the device address comes
+// from hipGetSymbolAddress (mlp_noalloc_scratch).
+static __device__ __align__(256) float scratch[kMlpNoAllocFloats];
+
+namespace {
+std::mutex g_scratch_mu;
+float* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+hipError_t mlp_noalloc_scratch(int device, float** out) {
+    *out = nullptr;
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        // (the caller has made `device` current)
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[device] = static_cast<float*>(p);
+    }
+    *out = g_scratch_ptr[device];
+    return hipSuccess;
+}
+
+// Sum of the n per-sample loss terms in FP64: thread t adds terms t, t + 256, ...
+// in order, then a fixed tree.
+__global__ void __launch_bounds__(256) mlp_loss_sum_kernel(const float* terms, int n, double* out) {
+    __shared__ double sh[256];
+    const int tid = threadIdx.x;
+    double v = 0.0;
+    for (int k = tid; k < n; k += 256) v += double(terms[k]);
+    sh[tid] = v;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (tid < o) sh[tid] += sh[tid + o];
+        __syncthreads();
+    }
+    if (tid == 0) *out = sh[0];
+}
+
+hipError_t launch_mlp_grad_noalloc(MlpArgs a, float* scratch_ptr, float* grad, double* loss, hipStream_t s) {
+    a.gpart = scratch_ptr;
+    a.loss = scratch_ptr + (size_t)(kMlpNoAllocMax / kMlpSamples) * kMlpNP;
+    const hipError_t e = launch_mlp_grad(a, grad, s);
+    if (e != hipSuccess || !loss) return e;
+    hipLaunchKernelGGL(mlp_loss_sum_kernel, dim3(1), dim3(256), 0, s, a.loss, a.batch, loss);
     return hipGetLastError();
 }
 
