@@ -82,30 +82,91 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(cfg, inp, er, nsteps):
-    """The FP64 oracle, as it is, on the host cores: a bounded sample of the workload
-    (the learned prior through the oracle's refresh schedule)."""
+def host_cpu():
+    """Model name of the host CPU and the cores this process may run on."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return model, len(os.sched_getaffinity(0))
+
+
+def _oracle_model(cfg, inp, er, sl=None, model=0):
+    import oracle
+    ics = inp["ics"].astype(np.float64)
+    w = inp["w"].astype(np.float64)
+    if sl is not None:
+        ics, w = ics[:, sl].copy(), w[sl].copy()
+    return oracle.Model(cfg, ics, w, inp["Y"], inp["sigma"], Erange=tuple(er), model=model)
+
+
+def _oracle_run(cfg, m, nsteps):
     import oracle
     from oracle import mlp
-    m = oracle.Model(cfg, inp["ics"].astype(np.float64), inp["w"].astype(np.float64), inp["Y"], inp["sigma"],
-                     Erange=tuple(er))
-    t0 = time.perf_counter()
     if cfg["prior"]["kind"] == "mlp":
         pr = cfg["prior"]
         lp = mlp.LearnedPrior(pr["mlp_init"], pr["lr"], pr["beta1"], pr["beta2"], pr["adam_eps"], pr["seed"],
                               pr["subset"], pr["batch"], pr["fallback"])
-        st = mlp.run(m, lp, pr, nsteps, oracle.subset)
-    else:
-        st = m.run(nsteps)
+        return mlp.run(m, lp, pr, nsteps, oracle.subset)
+    return m.run(nsteps)
+
+
+def cpu_baseline(cfg, inp, er, nsteps, steps_1core, sl=None, model=0):
+    """The FP64 oracle, as it is, on the host cores: a bounded sample of the workload
+    on all of them, and a shorter one on one core.  Returns the baseline record, the
+    oracle's statistics rows and its model after the all-core sample."""
+    import oracle
+    cpu_model, ncores = host_cpu()
+    n = cfg["N"] if sl is None else sl.stop - sl.start
+    m1 = _oracle_model(cfg, inp, er, sl, model)
+    oracle.set_threads(1)
+    t0 = time.perf_counter()
+    _oracle_run(cfg, m1, steps_1core)
+    dt1 = time.perf_counter() - t0
+    oracle.set_threads(ncores)
+    m = _oracle_model(cfg, inp, er, sl, model)
+    t0 = time.perf_counter()
+    st = _oracle_run(cfg, m, nsteps)
     dt = time.perf_counter() - t0
-    return {"value": cfg["N"] * nsteps / dt, "unit": "particle-steps/s", "cores": oracle.threads(),
-            "kind": "oracle", "sample": "N=%d particles x %d steps of the same workload (%.1f s)" % (cfg["N"], nsteps, dt)}, st
+    what = "N=%d particles" % n if sl is None else "model %d alone (N=%d)" % (model, n)
+    rec = {"value": n * nsteps / dt, "unit": "particle-steps/s", "cores": oracle.threads(), "kind": "oracle",
+           "sample": "%s x %d steps of the same workload (%.1f s)" % (what, nsteps, dt),
+           "value_1core": n * steps_1core / dt1,
+           "sample_1core": "%s x %d steps on one core (%.1f s)" % (what, steps_1core, dt1),
+           "cpu_model": cpu_model}
+    return rec, st, m
 
 
-def batched_checks(m2m, cfg, inp, xv, w, launch, cpu_steps, sample=(0, 31, 63)):
-    """Batched workload: chi^2 of sampled models after two steps of the full 64-model run
-    against the oracle run on each of those models alone, and the oracle's rate on the
-    first sampled model (a bounded sample of the workload)."""
+def obs_rel_err(cfg, ys_gpu, ys_or):
+    """Largest error of the smoothed observables relative to the largest value of
+    the same binning and moment."""
+    err, j = 0.0, 0
+    for b in cfg["layout"]["binnings"]:
+        nb = b["nx"] * b["ny"] if b["kind"] == "grid" else len(b["edges"]) - 1
+        for _ in b["moments"]:
+            o, g = ys_or[j:j + nb], ys_gpu[j:j + nb]
+            err = max(err, float(np.max(np.abs(g - o)) / max(np.max(np.abs(o)), 1e-300)))
+            j += nb
+    return err
+
+
+def smoothed_next(cfg, om):
+    """The oracle's smoothed observables of its current state (those a context holds
+    after the same number of steps)."""
+    g = cfg["dt"] / cfg["tau"]
+    ys = om.arr["ys"]
+    return ys + g * (om.observe() - ys)
+
+
+def batched_checks(m2m, cfg, inp, xv, w, launch, cpu_steps, steps_1core, sample=(0, 31, 63)):
+    """Batched workload: the full 64-model run for cpu_steps steps against the oracle
+    run on sampled models alone -- the first sampled model for all cpu_steps steps
+    (also the oracle's rate), the others for two -- and the chi^2 errors."""
     import oracle
     offs = np.concatenate([[0], np.cumsum(cfg["model_sizes"])])
     ics64 = inp["ics"].astype(np.float64)
@@ -114,25 +175,22 @@ def batched_checks(m2m, cfg, inp, xv, w, launch, cpu_steps, sample=(0, 31, 63)):
         er += list(oracle.energy_range(cfg, ics64, slice(offs[m], offs[m + 1]), model=m))
     ctx2 = m2m.m2m_create(cfg, xv, w, inp["Y"], inp["sigma"], Erange=np.array(er), device_ptrs=True)
     m2m.m2m_set_launch(ctx2, threads=launch["threads"], ilp=launch["ilp"], blocks_per_cu=launch["blocks_per_cu"])
-    m2m.m2m_step(ctx2, 2)
+    m2m.m2m_step(ctx2, cpu_steps)
     hist = m2m.m2m_history(ctx2)
     m2m.m2m_destroy(ctx2)
     errs, cpu = [], None
     for m in sample:
-        sl = slice(offs[m], offs[m + 1])
-        om = oracle.Model(cfg, ics64[:, sl].copy(), inp["w"][sl].astype(np.float64), inp["Y"], inp["sigma"],
-                          Erange=tuple(er[2 * m:2 * m + 2]), model=m)
-        t0 = time.perf_counter()
-        rows = om.run(cpu_steps if cpu is None else 2)
-        dt = time.perf_counter() - t0
+        sl = slice(int(offs[m]), int(offs[m + 1]))
         if cpu is None:
-            cpu = {"value": (offs[m + 1] - offs[m]) * cpu_steps / dt, "unit": "particle-steps/s",
-                   "cores": oracle.threads(), "kind": "oracle",
-                   "sample": "model %d alone (N=%d) x %d steps (%.1f s)" % (m, offs[m + 1] - offs[m], cpu_steps, dt)}
-        g = [r for r in hist if r["model"] == m and r["step"] == 1][0]
-        errs.append(abs(g["chi2"] - rows[1][0]) / rows[1][0])
-        log("model %d: chi2 step 1 GPU %.10g oracle %.10g" % (m, g["chi2"], rows[1][0]))
-    return cpu, max(errs)
+            cpu, rows, _ = cpu_baseline(cfg, inp, er[2 * m:2 * m + 2], cpu_steps, steps_1core, sl=sl, model=m)
+            n = cpu_steps - 1
+        else:
+            rows = _oracle_model(cfg, inp, er[2 * m:2 * m + 2], sl, m).run(2)
+            n = 1
+        g = [r for r in hist if r["model"] == m and r["step"] == n][0]
+        errs.append(abs(g["chi2"] - rows[n][0]) / rows[n][0])
+        log("model %d: chi2 step %d GPU %.10g oracle %.10g" % (m, n, g["chi2"], rows[n][0]))
+    return cpu, errs
 
 
 WORKLOADS = {
@@ -211,7 +269,9 @@ def main():
     # timed region 1 (the throughput): K steps as the library runs them, from
     # HIP graphs of G steps each where the step sequence allows (both step
     # parities' graphs built beforehand)
-    G = args.graph_steps
+    # (graphs hold an even number of steps, at most K, so that K steps replay whole
+    # graphs where K allows)
+    G = min(args.graph_steps, args.steps - args.steps % 2) if args.steps >= 2 else 0
     m2m.m2m_set_launch(ctx, timing=0, graph_steps=G)
     if G:
         m2m.m2m_step(ctx, 2 * G)
@@ -250,21 +310,33 @@ def main():
     log("throughput: %.2f us/step (%.3g particle-steps/s); one by one: %.2f us/step, dominant kernel %.2f us (%d launches)"
         % (wall / args.steps * 1e6, value, wall_ev / args.steps * 1e6, k_ms * 1e3, k_n))
 
-    # chi^2 relative error against the oracle after two steps from the initial state
+    # chi^2 (and the smoothed observables) against the oracle at the end of the
+    # oracle's CPU sample: a second context from the same initial state runs the
+    # same number of steps
     chi2_err = None
+    parity = None
     cpu = None
+    steps_1core = max(1, cpu_steps // 16)
     if batched and not args.no_cpu_baseline:
-        cpu, chi2_err = batched_checks(m2m, cfg, inp, xv, w, launch, cpu_steps)
+        cpu, errs = batched_checks(m2m, cfg, inp, xv, w, launch, cpu_steps, steps_1core)
+        chi2_err = errs[0]
+        parity = {"chi2_rel_err_model0_end_of_sample": errs[0], "chi2_rel_err_sampled_models_step1": errs[1:],
+                  "steps": cpu_steps}
     elif not args.no_cpu_baseline:
         import oracle
         er = oracle.energy_range(cfg, inp["ics"].astype(np.float64))
         ctx2 = m2m.m2m_create(cfg, xv, w, inp["Y"], inp["sigma"], Erange=np.array(er), device_ptrs=True)
         m2m.m2m_set_launch(ctx2, threads=launch["threads"], ilp=launch["ilp"], blocks_per_cu=launch["blocks_per_cu"])
-        g1 = m2m.m2m_step(ctx2, 2)[0]
+        g_last = m2m.m2m_step(ctx2, cpu_steps)[0]
+        ys_gpu = m2m.m2m_observables(ctx2, 0)["y_smooth"]
         m2m.m2m_destroy(ctx2)
-        log("cpu baseline: %d oracle steps of N=%d" % (max(cpu_steps, 2), cfg["N"]))
-        cpu, ost = cpu_baseline(cfg, inp, er, max(cpu_steps, 2))
-        chi2_err = abs(g1["chi2"] - ost[1][0]) / ost[1][0]
+        log("cpu baseline: %d oracle steps of N=%d (and %d on one core)" % (cpu_steps, cfg["N"], steps_1core))
+        cpu, ost, om = cpu_baseline(cfg, inp, er, cpu_steps, steps_1core)
+        chi2_err = abs(g_last["chi2"] - ost[-1][0]) / ost[-1][0]
+        parity = {"steps": cpu_steps, "chi2_rel_err": chi2_err,
+                  "obs_max_rel_err": obs_rel_err(cfg, ys_gpu, smoothed_next(cfg, om))}
+        log("parity after %d steps: chi2 %.3g, smoothed observables %.3g" % (
+            cpu_steps, chi2_err, parity["obs_max_rel_err"]))
 
     config = {"workload": WORKLOADS[wl] % cfg["N"], "N": cfg["N"], "launch": launch}
     if batched:
@@ -273,6 +345,7 @@ def main():
         config.update(J=4946 if wl == "multipole" else 4896,
                       prior_cells=8192 if wl == "mlp" else 1024)
     graphs = G and (cfg["prior"]["kind"] == "flat" or cfg["prior"].get("period", 1) == 1)
+    replayed = (args.steps // G) * G if graphs else 0
     out = {
         "metric": "particle-steps/sec at 1M particles (push+observe+update); chi2 rel. err vs oracle",
         "value": value,
@@ -288,11 +361,13 @@ def main():
         "data": "synthetic",
         "config": config,
         "roofline": roof,
-        "timing": {"value": ("%d steps replayed from HIP graphs of %d steps" % (args.steps, G)) if graphs
+        "timing": {"value": ("%d steps: %d replayed from HIP graphs of %d steps, %d launched one by one"
+                             % (args.steps, replayed, G, args.steps - replayed)) if graphs
                    else "%d steps launched one by one (the step sequence changes between refreshes)" % args.steps,
                    "one_by_one_value": cfg["N"] * args.steps / wall_ev,
                    "one_by_one_ms_per_step": wall_ev / args.steps * 1e3},
         "chi2_rel_err_vs_oracle": chi2_err,
+        "parity_vs_oracle": parity,
         "chi2_final": last["chi2"],
         "cpu_baseline": cpu,
     }

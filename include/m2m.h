@@ -200,7 +200,10 @@ typedef struct m2m_ctx m2m_ctx;
 
 int32_t m2m_abi_version(void);
 
-/* Create a context: validate, copy the particles (xv: 6 * N values, SoA
+/* Paper section 2 (the problem: an N-body particle model evolved in a given or
+ * self-consistent potential whose weights are fitted to target observables with
+ * errors) and section 2.1 (initial weights 1/N, flat or moving priors).
+ * Create a context: validate, copy the particles (xv: 6 * N values, SoA
  * x[N] y[N] z[N] vx[N] vy[N] vz[N]; w: N values > 0, both in cfg precision),
  * observe the initial state (y(0), smoothed y = y(0), priors at step 0).
  * Errors: INVALID (w <= 0 or non-finite, J or model offsets inconsistent,
@@ -210,30 +213,47 @@ m2m_status m2m_create(const m2m_config *cfg, const m2m_obs_layout *layout,
                       const m2m_target *target, const void *xv, const void *w,
                       int32_t device_ptrs, m2m_ctx **out);
 
-/* Advance n_steps >= 0 steps.  last (nullable) receives n_models rows: the
+/* Paper section 2: the weights are adapted, by maximising F of eq. 1 with the
+ * entropy of eq. 2, while the particles are evolved; section 2.1: the moving
+ * priors are recomputed from the weight distribution as the run proceeds.
+ * Advance n_steps >= 0 steps.  last (nullable) receives n_models rows: the
  * statistics of the final step taken.  On NONPOSITIVE_WEIGHT / NONFINITE the
  * context stays at the start of the failing step (whose index is in the
  * message and in m2m_step_index); later calls return the same error. */
 m2m_status m2m_step(m2m_ctx *ctx, int64_t n_steps, m2m_step_stats *last);
 
-/* Steps taken so far (host mirror of the device counter). */
+/* Steps taken so far (host mirror of the device counter); -1 for a NULL ctx. */
 int64_t m2m_step_index(const m2m_ctx *ctx);
 
-/* Observables of model m at the current state: y (last observe), y_smooth,
- * delta = (y_smooth - Y)/sigma (J values each, host, nullable) and chi2
- * (nullable). */
+/* Paper section 2: the model observables compared with the target data, their
+ * deviations and chi^2 (the first term of eq. 1).
+ * Observables of model m at the current state: y (last observe), y_smooth,
+ * delta = (y_smooth - Y)/sigma (J values each, host, nullable, caller-owned)
+ * and chi2 (nullable).  Synchronises the context's stream.  INVALID for a
+ * model outside [0, n_models). */
 m2m_status m2m_observables(m2m_ctx *ctx, int32_t model, double *y, double *y_smooth,
                            double *delta, double *chi2);
 
-/* Current weights, N values in cfg precision. */
+/* Paper section 2 (eq. 1 and 2): the particle weights w_i that the fit adapts.
+ * Current weights, N values in cfg precision, into w_out (host, or device when
+ * device_ptr = 1; caller-owned); synchronises the context's stream.  INVALID for
+ * a null argument. */
 m2m_status m2m_weights(m2m_ctx *ctx, void *w_out, int32_t device_ptr);
 
-/* Priors what_i the next step will use (N values, cfg precision, nullable;
- * MLP: those of the last refresh) and the cell table (n_models * ncell FP64
- * cell means, host, nullable; HIST and MLP only). */
+/* Paper section 2.1 (and eq. 2): the priors what_i of the entropy, flat or moving
+ * (the mean weight over a cell of the integrals of motion, or the learned form).
+ * Priors what_i the next step will use (N values, cfg precision, nullable;
+ * MLP: those of the last refresh; host, or device when device_ptr = 1) and the
+ * cell table (n_models * ncell FP64 cell means, host, nullable; HIST and MLP
+ * only), both caller-owned.  Synchronises the context's stream.  INVALID when a
+ * cell table is asked of a flat prior. */
 m2m_status m2m_priors(m2m_ctx *ctx, void *what_out, double *cell_mean, int32_t device_ptr);
 
-/* Current particles, 6 * N values SoA (same layout as m2m_create). */
+/* Paper section 2: the phase-space coordinates of the evolved particles (the
+ * state a run can be restarted from with m2m_create, together with the weights).
+ * Current particles, 6 * N values SoA (same layout as m2m_create), into xv_out
+ * (host, or device when device_ptr = 1; caller-owned); synchronises the stream.
+ * INVALID for a null argument. */
 m2m_status m2m_particles(m2m_ctx *ctx, void *xv_out, int32_t device_ptr);
 
 /* Decisions stored with the current state (section 2: the observables are
@@ -323,10 +343,14 @@ m2m_status m2m_set_launch(m2m_ctx *ctx, const m2m_launch *in);
  * or took no steps); *launches gets the launch count. */
 m2m_status m2m_kernel_time(const m2m_ctx *ctx, double *ms_per_launch, int64_t *launches);
 
-/* Free every device buffer of the context (NULL is ignored). */
+/* End of the run of section 2: free every device buffer of the context (NULL is
+ * ignored); waits for the context's stream first. */
 void m2m_destroy(m2m_ctx *ctx);
 
-/* Message of the last error on ctx ("" if none; static text if ctx is NULL). */
+/* Error reporting of this boundary (no paper passage: status codes only cross
+ * it).  Message of the last error on ctx ("" if none); with ctx NULL, the message
+ * of the last failed m2m_create on this thread.  The string is owned by the
+ * library and valid until the next call on the same context. */
 const char *m2m_last_error(const m2m_ctx *ctx);
 
 #ifdef __cplusplus

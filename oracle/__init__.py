@@ -108,6 +108,7 @@ def lib():
         L.or_philox4x32.argtypes = [C.POINTER(C.c_uint32), C.POINTER(C.c_uint32), C.POINTER(C.c_uint32)]
         L.or_subset.argtypes = [C.c_uint32, C.c_uint32, C.c_int64, C.c_uint32, C.POINTER(C.c_int64)]
         L.or_threads.restype = C.c_int
+        L.or_set_threads.argtypes = [C.c_int]
         _lib = L
     return _lib
 
@@ -408,3 +409,8 @@ def subset(seed, refresh, count, N):
 
 def threads():
     return lib().or_threads()
+
+
+def set_threads(n):
+    """Threads of the oracle's parallel loops from now on."""
+    lib().or_set_threads(int(n))

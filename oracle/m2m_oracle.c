@@ -110,6 +110,16 @@ static int nthreads(void) {
 
 int or_threads(void) { return nthreads(); }
 
+/* Threads of the parallel loops from now on (the CPU-baseline timing runs the
+ * oracle on one core as well as on all of them). */
+void or_set_threads(int n) {
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 /* ------------------------------------------------------------------ potentials
  * Section 2: the potential is fixed and known a priori, or self-consistent.
  * Analytic forms: Hernquist Phi = -GM/(r+a); logarithmic
