@@ -315,7 +315,8 @@ static m2m_status make_plan(m2m_ctx* c, int threads, int ilp, int bpc) {
     const int NCk = c->cells_apart ? 0 : c->NC;   // cells the fused kernel holds
     const int NCe = (NCk + 1) & ~1, NE = (c->nedge + 1) & ~1;
     p.lds = 8 * ((size_t)c->JP + kTrash + NCk + kTrash + NE + 2 + 64) + 4 * ((size_t)NCe + kTrash) +
-            ts * ((size_t)c->JP + 2 + NCe + NE + kLcTab);
+            ts * ((size_t)c->JP + 2 + NCe + NE + kLcTab) + (ts == 4 && NCk > 0 ? 8 * (size_t)kLcE : 0) +
+            (ts == 4 ? 8 * (size_t)kFixQ * (threads / 64) : 0);
     p.lds = (p.lds + 15) & ~(size_t)15;
     if (p.lds > (size_t)c->max_lds)
         return fail(c, M2M_ERR_UNSUPPORTED, "layout needs " + std::to_string(p.lds) + " bytes of LDS per block (max " +
@@ -374,12 +375,15 @@ static uint16_t* tags(const m2m_ctx* c, int k) {
     return (uint16_t*)((char*)c->state[k] + (size_t)7 * c->stride * tsize(c));
 }
 
+static size_t state_bytes(const m2m_ctx* c);
+
 template <typename T>
 static void fill_step_args(m2m_ctx* c, StepArgs<T, T>& a, int parity, int mode, int what_mode, int accum) {
     const Plan& p = c->plan;
     a.in = (const T*)c->state[parity];
     a.out = (T*)c->state[parity ^ 1];
     a.stride = c->stride;
+    a.state_bytes = (uint32_t)state_bytes(c);
     a.what = (T*)c->what;
     a.tile_model = p.tile_model;
     a.tile_p0 = p.tile_p0;
@@ -1156,7 +1160,8 @@ extern "C" m2m_status m2m_create(const m2m_config* cfg, const m2m_obs_layout* la
         // LDS of the fused kernel with the prior cells (as make_plan computes it)
         const int NCe = (c->NC + 1) & ~1, NE = (c->nedge + 1) & ~1;
         const size_t fused = 8 * ((size_t)c->JP + kTrash + c->NC + kTrash + NE + 2 + 64) +
-                             4 * ((size_t)NCe + kTrash) + 4 * ((size_t)c->JP + 2 + NCe + NE + kLcTab);
+                             4 * ((size_t)NCe + kTrash) + 4 * ((size_t)c->JP + 2 + NCe + NE + kLcTab) +
+                             (c->NC > 0 ? 8 * (size_t)kLcE : 0) + 8 * (size_t)kFixQ * 16;
         // the learned prior's judge grid, and FP32 histogram priors too large for
         // the fused kernel, are accumulated by the cell kernel
         c->cells_apart = c->prec == M2M_F32 && (c->prior.kind == M2M_PRIOR_MLP ||

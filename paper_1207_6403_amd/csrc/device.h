@@ -146,6 +146,10 @@ __device__ __forceinline__ double qdiv(double a, double b) { return a / b; }
 __device__ __forceinline__ float qlog(float v) { return __logf(v); }
 __device__ __forceinline__ double qlog(double v) { return log(v); }
 __device__ __forceinline__ float qexp(float v) { return __expf(v); }
+// ln of a weight ratio for the update (not a decision input): the hardware base-2
+// logarithm times ln 2 (the ratio is a normal number)
+__device__ __forceinline__ float qlog_ratio(float v) { return __builtin_amdgcn_logf(v) * 0.693147180559945309f; }
+__device__ __forceinline__ double qlog_ratio(double v) { return log(v); }
 __device__ __forceinline__ double qexp(double v) { return exp(v); }
 
 // Phi(x) and a = -grad Phi.  POT is the compile-time potential kind.
@@ -260,15 +264,17 @@ __device__ __forceinline__ int clamp_cell(double f, int n) {
     return int(f);
 }
 __device__ __forceinline__ int clamp_cell(float f, int n) {
-    if (!(f >= 0.0f)) return 0;
-    if (f >= float(n)) return n - 1;
-    return int(f);
+    // (branch free: max(NaN, 0) is 0, and the conversion saturates large values)
+    return min(int(fmaxf(f, 0.0f)), n - 1);
 }
 // Is the clamped FP32 coordinate f within g of a cell edge it could cross?
+// (Branch free: every term is evaluated and combined with selects, so that the
+// test costs a few VALU operations and no exec-mask branches.)
 __device__ __forceinline__ bool near_cell_edge(float f, int n, float g) {
-    if (!(f > -g) || !(f < float(n) + g)) return !(f == f);   // far outside: clamped either way
     const float fr = f - floorf(f);
-    return fr < g || fr > 1.0f - g;
+    const bool inside = (f > -g) & (f < float(n) + g);   // (false for NaN)
+    const bool edge = (fr < g) | (fr > 1.0f - g);
+    return inside ? edge : (f != f);                      // far outside: clamped either way
 }
 
 // Cell index from E, L, Lz and Lc(E) in FP64 (the defining arithmetic): E
@@ -415,11 +421,25 @@ __device__ __forceinline__ CellGuard cell_guard(float Emin, float Emax, float sE
 //      3u for the reciprocal and the product) times the coordinate's distance
 //      from the axis origin, plus 2u |f2|;
 //   Lz/L: 1e-4 cells.
-template <int POT>
+// Cell-axis configurations a kernel can be compiled for (CAX): the second axis
+// and the presence of the third taken from the Cells at run time (0), or fixed:
+// Lz/Lc with no third axis (1), L/Lc with no third axis (2).
+constexpr int kCaxRuntime = 0, kCaxLzNo3 = 1, kCaxLNo3 = 2;
+
+// The compiled configuration matching a prior's cells (kCaxRuntime if none).
+__host__ __device__ inline int cax_of(const Cells& c) {
+    if (c.n2 == 1 && c.ax2 == 1) return kCaxLzNo3;
+    if (c.n2 == 1 && c.ax2 == 0) return kCaxLNo3;
+    return kCaxRuntime;
+}
+
+template <int POT, int CAX = kCaxRuntime>
 __device__ __forceinline__ unsigned cell_fast(const Pot<float>& p, const float2* __restrict__ et, const Cells& c,
                                               float Emin, float sE, const CellGuard& G, float KE, float phi, float x,
                                               float y, float z, float vx, float vy, float vz, int& cell) {
-    const int n0 = opaque(c.n0), n1 = opaque(c.n1), n2 = opaque(c.n2), ax2 = opaque(c.ax2);
+    const int n0 = opaque(c.n0), n1 = opaque(c.n1);
+    const int n2 = CAX == kCaxRuntime ? opaque(c.n2) : 1;
+    const int ax2 = CAX == kCaxRuntime ? opaque(c.ax2) : (CAX == kCaxLzNo3 ? 1 : 0);
     const float E = KE + phi;
     const float eE = kU32 * (4.0f * KE + 17.0f * fabsf(phi) + 3.0f * p.v2);
     const float xvy = x * vy, yvx = y * vx;
@@ -494,9 +514,10 @@ __device__ __forceinline__ int bin_fast(const BinDesc<float>& d, int kind, const
         const float fy = (Ys - d.y0) * d.sy;
         const float gx = d.gx0 + 6.0f * kU32 * fabsf(fx) + kGuardBinFloor;
         const float gy = d.gy0 + d.gys * aYs + 6.0f * kU32 * fabsf(fy) + kGuardBinFloor;
-        sure = !near_cell_edge(fx, d.nx, gx) && !near_cell_edge(fy, d.ny, gy);
-        if (fx >= 0.0f && fx < float(d.nx) && fy >= 0.0f && fy < float(d.ny)) return int(fy) * d.nx + int(fx);
-        return -1;
+        sure = !(near_cell_edge(fx, d.nx, gx) | near_cell_edge(fy, d.ny, gy));
+        const bool in = (fx >= 0.0f) & (fx < float(d.nx)) & (fy >= 0.0f) & (fy < float(d.ny));
+        // (the conversions of out-of-range values are not used)
+        return in ? int(fy) * d.nx + int(fx) : -1;
     }
     const float rad = kind == 1 ? __builtin_sqrtf(x * x + y * y + z * z) : __builtin_sqrtf(x * x + Ys * Ys);
     const float* e = ef + d.edge0;
@@ -506,6 +527,15 @@ __device__ __forceinline__ int bin_fast(const BinDesc<float>& d, int kind, const
     if (k >= 0) sure = !(rad - e[k] < g) && !(e[k + 1] - rad < g);
     else sure = !(fabsf(rad - e[0]) < g) && !(fabsf(rad - e[ne - 1]) < g) && rad == rad;
     return k;
+}
+
+// Line-of-sight velocity v_los = vy sin i + vz cos i (one fused form everywhere,
+// so that every path of a kernel computes the same value).
+__device__ __forceinline__ float line_of_sight(float vy, float vz, float sini, float cosi) {
+    return fmaf(vy, sini, vz * cosi);
+}
+__device__ __forceinline__ double line_of_sight(double vy, double vz, double sini, double cosi) {
+    return vy * sini + vz * cosi;
 }
 
 // Kernel value of moment code mo (0: 1, 1: v_los, 2: v_los^2).

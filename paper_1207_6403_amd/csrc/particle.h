@@ -144,7 +144,7 @@ __device__ __forceinline__ T weight_update(const StepArgs<T, PT>& a, const Blk<T
     const Layout<T>& L = a.lay;
     const LayoutView<SIG, T> V{L};
     const int nbin = V.nbin();
-    const T vl = vy * L.sini + vz * L.cosi;
+    const T vl = line_of_sight(vy, vz, L.sini, L.cosi);
     T chi = T(0);
     #pragma unroll
     for (int b = 0; b < NB; ++b) {
@@ -166,7 +166,7 @@ __device__ __forceinline__ T weight_update(const StepArgs<T, PT>& a, const Blk<T
     const T wh = wm == 0 ? B.wflat : (wm == 3 ? what_p : B.cm[tg[kMaxBin]]);
     // (FP32: the hardware log, exp and reciprocal, a few ulp each; the FP64
     // kernels use the exact forms)
-    const T lr = qlog(qdiv(w, wh));
+    const T lr = qlog_ratio(qdiv(w, wh));
     const T G = -chi - a.mu * (lr + T(1));
     const T edt = a.eps * a.dt;
     const T wn = (fl & kExpLaw) ? w * qexp(edt * G) : w * (T(1) + edt * G);

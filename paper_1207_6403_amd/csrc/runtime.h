@@ -13,6 +13,9 @@ constexpr int kRing = 4096;          // statistics rows kept per model
 // scatters of particles outside every bin, or whose decision the FP64 fix-up
 // takes later, land there instead of branching around the atomic.
 constexpr int kTrash = 64;
+// Open decisions (particle, mask) a wave of the FP32 fused kernel queues in LDS
+// before re-taking them in FP64 (one chunk of ILP = 2).
+constexpr int kFixQ = 128;
 constexpr int kSlotsPerSplit = 32;   // partial slots in flight per finalise thread
 constexpr int kFinCols = 32;         // columns per finalise block
 constexpr int kFinGroups = 8;        // slot groups per column (256 threads)
@@ -41,6 +44,7 @@ struct StepArgs {
     const T* in;            // state at step n
     T* out;                 // state at step n+1 (the state at step n when observing only)
     int64_t stride;
+    uint32_t state_bytes;   // bytes of a state buffer (value and tag rows)
     T* what;                // per-particle priors (stored modes)
     const int32_t* tile_model;
     const int64_t* tile_p0;

@@ -24,24 +24,19 @@ namespace m2m {
 // nor moved: its current bins and cell are decided and stored.
 // FP32 kernels decide in FP32; a decision inside its guard band is left open
 // and flagged in the returned mask (bit b: binning b, bits NB..NB+2: the cell's
-// axes), to be re-taken in FP64 by fixup() from the new state kept in `kp`;
-// FP64 kernels decide in FP64 and return 0.
-template <typename T>
-struct Keep {
-    T x, y, z, vx, vy, vz, w, vl;
-    int cell;   // from the FP32 coordinates (exact on the axes not left open)
-};
+// axes), to be re-taken in FP64 by fix_one() from the stored new state; FP64
+// kernels decide in FP64 and return 0.
 
-template <int POT, int NB, uint64_t SIG, typename T, typename PT>
+template <int POT, int NB, uint64_t SIG, int CAX, typename T, typename PT>
 __device__ __forceinline__ unsigned particle_step(const StepArgs<T, PT>& a, const Blk<T>& B, Acc& acc, int64_t p,
                                                   T x, T y, T z, T vx, T vy, T vz, T w, T what_p,
-                                                  const uint16_t (&tg)[kMaxBin + 1], Keep<T>& kp, uint32_t fl,
-                                                  uint32_t rb) {
+                                                  const uint16_t (&tg)[kMaxBin + 1], uint32_t fl, uint32_t rb) {
     // fl: the step flags; rb: bytes per value row
     const Layout<T>& L = a.lay;
     const LayoutView<SIG, T> V{L};
     const uint32_t o = uint32_t(p) * uint32_t(sizeof(T));
     const uint32_t ot = 7 * rb + uint32_t(p) * 2u;                 // tag of row 0
+
     const int nbin = V.nbin();
     T wn = w, phi = T(0);
     bool have_phi = false;
@@ -68,7 +63,7 @@ __device__ __forceinline__ unsigned particle_step(const StepArgs<T, PT>& a, cons
     }
     // bins and cell of the new state
     unsigned open = 0;
-    const T vl = vy * L.sini + vz * L.cosi;
+    const T vl = line_of_sight(vy, vz, L.sini, L.cosi);
     const float yc = float(y * L.cosi), zs = float(z * L.sini);
     const float Ys = yc - zs, aYs = fabsf(yc) + fabsf(zs);
     // (no branches: a decision left open stores a provisional tag, which the
@@ -104,7 +99,7 @@ __device__ __forceinline__ unsigned particle_step(const StepArgs<T, PT>& a, cons
         unsigned am = 0;
         if constexpr (sizeof(T) == 4) {
             const float KE = 0.5f * (vx * vx + vy * vy + vz * vz);
-            am = cell_fast<POT>(B.pot, B.et, a.cells, B.Emin, B.sE, B.cg, KE, phi, x, y, z, vx, vy, vz, cell);
+            am = cell_fast<POT, CAX>(B.pot, B.et, a.cells, B.Emin, B.sE, B.cg, KE, phi, x, y, z, vx, vy, vz, cell);
             open |= am << NB;
         } else {
             cell = prior_cell_f64<POT>(B.pot, B.lct, a.cells, a.ex->erange[2 * B.m], a.ex->erange[2 * B.m + 1], x, y, z,
@@ -115,37 +110,39 @@ __device__ __forceinline__ unsigned particle_step(const StepArgs<T, PT>& a, cons
         atomicAdd(&B.csum[ci], double(wn));
         atomicAdd(&B.ccnt[ci], 1u);
     }
-    kp.x = x; kp.y = y; kp.z = z; kp.vx = vx; kp.vy = vy; kp.vz = vz; kp.w = wn; kp.vl = vl;
-    kp.cell = cell;
     return open;
 }
 
-// Address-space-qualified pointers for the out-of-line fix-up: its arguments
-// keep their memory kinds, so neither side falls back to flat addressing.
+// The decisions particle_step left open for particle p (mask `open`), taken in
+// FP64 from the FP32 coordinates of its new state, read back from the output
+// buffer where this wave stored them (with the provisional FP32 cell tag, exact
+// on the axes not left open), then stored and scattered.  Only the open axes of
+// the cell are re-taken: E needs one FP64 potential, L/Lc or Lz/Lc the
+// circular-orbit Lc(E) as well, Lz/L neither.
+// Out of line (its FP64 working set would otherwise raise the register use of
+// the whole kernel), with address-space-qualified pointers so that neither side
+// falls back to flat addressing; called from the queue drain only.
 using cExact = const __attribute__((address_space(4))) Exact;
-using gU16 = __attribute__((address_space(1))) uint16_t;
+using gF32 = __attribute__((address_space(1))) float;
 using lF64 = __attribute__((address_space(3))) double;
 using lU32 = __attribute__((address_space(3))) unsigned;
-
-// The decisions particle_step left open (mask `open`), taken in FP64 from the
-// FP32 coordinates of the new state (kept in registers: x..vz, the weight wn,
-// v_los vl and the FP32 cell), then stored and scattered.  Only the open axes
-// of the cell are re-taken: E needs one FP64 potential, L/Lc or Lz/Lc the
-// circular-orbit Lc(E) as well, Lz/L neither.  Out of line: it runs for about
-// one particle in a thousand, and inlined its FP64 working set would raise the
-// register use of the whole kernel.
 template <int POT, int NB>
-__device__ __noinline__ void fixup(cExact* ex, int m, unsigned open, int64_t p, int64_t stride, int cellrow,
-                                   float x, float y, float z, float vx, float vy, float vz, float wn, float vl,
-                                   int cell, gU16* tout, lF64* hist, lF64* csum, lU32* ccnt, float lcE0,
-                                   float lcEinv) {
+__device__ __noinline__ void fix_one(cExact* ex, int m, unsigned open, int64_t p, int64_t stride, int cellrow,
+                                     gF32* out, lF64* hist, lF64* csum, lU32* ccnt, float lcE0, float lcEinv, float sini,
+                                     float cosi) {
+    const float x = out[p], y = out[stride + p], z = out[2 * stride + p];
+    const float vx = out[3 * stride + p], vy = out[4 * stride + p], vz = out[5 * stride + p];
+    const float wn = out[6 * stride + p];
+    __attribute__((address_space(1))) uint16_t* tags =
+        reinterpret_cast<__attribute__((address_space(1))) uint16_t*>(out + 7 * stride);
+    const float vl = line_of_sight(vy, vz, sini, cosi);
     #pragma unroll
     for (int b = 0; b < NB; ++b) {
         if (!(open & (1u << b))) continue;
         const int kind = ex->lay.b[b].kind, nx = ex->lay.b[b].nx, ny = ex->lay.b[b].ny, nb = ex->lay.b[b].nb;
         const int k = bin_f64(kind, ex->cosd, ex->sind, ex->x0d[b], ex->wxd[b], nx, ex->y0d[b], ex->wyd[b], ny,
                               ex->edges + ex->lay.b[b].edge0, nb + 1, double(x), double(y), double(z));
-        tout[b * stride + p] = k < 0 ? kNoBin : (uint16_t)k;
+        tags[b * stride + p] = k < 0 ? kNoBin : (uint16_t)k;
         if (k < 0) continue;
         const int base = ex->lay.b[b].off + k, mom = ex->lay.b[b].mom;
         for (int mm = 0; mm < ex->lay.b[b].nmom; ++mm)
@@ -161,6 +158,7 @@ __device__ __noinline__ void fixup(cExact* ex, int m, unsigned open, int64_t p, 
         cells.ax2 = ex->cells.ax2;
         cells.ncell = ex->cells.ncell;
         const int n1 = cells.n1, n2 = cells.n2;
+        const int cell = tags[cellrow * stride + p];
         int iE = cell / (n1 * n2), i2 = (cell / n2) % n1, i3 = cell % n2;
         const double X = x, Y = y, Z = z, VX = vx, VY = vy, VZ = vz;
         if (am & 3u) {
@@ -181,13 +179,19 @@ __device__ __noinline__ void fixup(cExact* ex, int m, unsigned open, int64_t p, 
             i3 = cell_axis_3(cells, L, Lz);
         }
         const int c = (iE * n1 + i2) * n2 + i3;
-        tout[cellrow * stride + p] = (uint16_t)c;
+        tags[cellrow * stride + p] = (uint16_t)c;
         __hip_atomic_fetch_add(&csum[c], double(wn), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         __hip_atomic_fetch_add(&ccnt[c], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     }
 }
 
-template <typename T, typename PT, int POT, int NB, uint64_t SIG, int ILP>
+// MODE: the step flags at run time (0), or compiled in: a stepping kernel of a
+// histogram prior refreshed every step with the exponential law (1), or an
+// observe-only pass that takes the prior cells (2).
+constexpr uint32_t kHotFlags = kExpLaw | (1u << kWhatShift) | kAccum;
+constexpr uint32_t kObsCells = kObserve | kAccum;
+
+template <typename T, typename PT, int POT, int NB, uint64_t SIG, int CAX, int MODE, int ILP>
 __global__ void __launch_bounds__(sizeof(T) == 8 ? 256 : 1024) step_kernel(StepArgs<T, PT> a) {
     extern __shared__ __align__(16) unsigned char smem[];
     warm_kernargs<sizeof(StepArgs<T, PT>)>();
@@ -214,10 +218,12 @@ __global__ void __launch_bounds__(sizeof(T) == 8 ? 256 : 1024) step_kernel(StepA
     T* cm = cl + JP + 2;                                             // NC: cell means
     T* ed = cm + ((NC + 1) & ~1);                                    // edges in T
     T* lct = ed + NE;                                                // circular-orbit energies (FP64)
+    float2* etl = reinterpret_cast<float2*>(lct + kLcTab);           // uniform-E Lc table (FP32, with cells)
+    uint2* fq = reinterpret_cast<uint2*>(etl + (F32 && NC ? kLcE : 0));  // per wave: kFixQ open decisions (FP32)
 
     for (int i = tid; i < a.nedge; i += nt) { ed[i] = a.edges[i]; ed64[i] = a.edges64[i]; }
 
-    const uint32_t fl = a.flags;
+    const uint32_t fl = MODE == 1 ? kHotFlags : (MODE == 2 ? kObsCells : a.flags);
     const uint32_t wm = (fl >> kWhatShift) & 3u;
     const bool want_cm = wm == 1 || wm == 2;
     const bool accum = fl & kAccum;
@@ -256,26 +262,28 @@ __global__ void __launch_bounds__(sizeof(T) == 8 ? 256 : 1024) step_kernel(StepA
                 R.vy[k] = ld_at<T>(a.in, o + 4 * rb);
                 R.vz[k] = ld_at<T>(a.in, o + 5 * rb);
                 R.w[k] = ld_at<T>(a.in, o + 6 * rb);
-                R.wh[k] = (stepping && wm == 3) ? a.what[p] : T(1);
                 #pragma unroll
                 for (int b = 0; b < kMaxBin; ++b)
-                    R.tg[k][b] = (stepping && b < NB && b < LayoutView<SIG, T>{a.lay}.nbin()) ? ld_at<uint16_t>(a.in, ot + b * tr)
-                                                                                   : kNoBin;
+                    R.tg[k][b] = (stepping && b < NB && b < LayoutView<SIG, T>{a.lay}.nbin())
+                                     ? ld_at<uint16_t>(a.in, ot + b * tr) : kNoBin;
                 R.tg[k][kMaxBin] = (stepping && want_cm) ? ld_at<uint16_t>(a.in, ot + a.cellrow * tr) : 0;
+                R.wh[k] = (stepping && wm == 3) ? a.what[p] : T(1);
             }
         }
     };
-    Regs next_r;
+    // two register sets, used in turn: the chunk being processed and the next
+    // one being loaded (no copy between them)
+    Regs R0;
     // the first segment (its first chunk's loads go out before the tables')
     int m = bd.m0, n = bd.n0, slot = bd.slot0, te = bd.tseg1;
     int64_t P0 = bd.p0;
     int ts = bd.t0;
-    if (ts < bd.t1 && wid * CH < n) load_chunk(P0, n, wid, next_r);
-    unsigned open[ILP];   // decisions left open in the previous chunk
-    Keep<T> kp[ILP];      // and its particles' new state
-    int64_t p_open = 0;   // its first particle
-    #pragma unroll
-    for (int k = 0; k < ILP; ++k) open[k] = 0u;
+    if (ts < bd.t1 && wid * CH < n) load_chunk(P0, n, wid, R0);
+    // FP32: the decisions this wave left open, (particle, mask) pairs queued in
+    // LDS and re-taken in FP64 all lanes at a time when the queue fills up or the
+    // segment ends (qn is wave-uniform)
+    uint2* myq = fq + wid * kFixQ;
+    int qn = 0;
 
     while (ts < bd.t1) {
         // the segment's model: tables, histograms and the work counter
@@ -290,9 +298,19 @@ __global__ void __launch_bounds__(sizeof(T) == 8 ? 256 : 1024) step_kernel(StepA
         if (accum) for (int c = tid; c < NC; c += nt) { csum[c] = 0.0; ccnt[c] = 0u; }
         if (want_cm) for (int c = tid; c < NC; c += nt) cm[c] = a.cellmean[(size_t)m * NC + c];
         if (NC && !F32) for (int i = tid; i < kLcTab; i += nt) lct[i] = a.lctab[(size_t)B.pot.lc_off + i];
+        if (F32 && accum) {
+            // the model's uniform-E Lc table into LDS (a global gather in the
+            // particle loop would wait behind the chunk's stores and the next
+            // chunk's loads)
+            const float4* src = reinterpret_cast<const float4*>(a.lcetab + 2 * (size_t)m * kLcE);
+            for (int i = tid; i < kLcE / 2; i += nt) {
+                const float4 v = src[i];
+                etl[2 * i] = make_float2(v.x, v.y);
+                etl[2 * i + 1] = make_float2(v.z, v.w);
+            }
+        }
         if (tid == 0) *ctr = 0u;
-        // the uniform-E Lc table of the model, read from global memory (L1/L2)
-        B.et = reinterpret_cast<const float2*>(a.lcetab) + (size_t)m * kLcE;
+        B.et = etl;
         __syncthreads();
         if (failed) return;   // (uniform: every thread leaves here, before any store)
 
@@ -300,36 +318,47 @@ __global__ void __launch_bounds__(sizeof(T) == 8 ? 256 : 1024) step_kernel(StepA
         int c = wid;
         while (true) {
             if constexpr (F32) {
-                // the previous chunk's open decisions (out of line, and before the
-                // next chunk's loads are issued, so that waiting for those loads
-                // never waits for the unknown memory operations of a call)
-                #pragma unroll
-                for (int k = 0; k < ILP; ++k)
-                    if (open[k])
-                        fixup<POT, NB>((cExact*)a.ex, B.m, open[k], p_open + k * 64 + lane, a.stride, a.cellrow,
-                                       kp[k].x, kp[k].y, kp[k].z, kp[k].vx, kp[k].vy, kp[k].vz, kp[k].w, kp[k].vl,
-                                       kp[k].cell, (gU16*)((char*)a.out + 7 * a.stride * sizeof(T)), (lF64*)hist,
-                                       (lF64*)csum, (lU32*)ccnt, B.pot.lcE0, B.pot.lcEinv);
-                #pragma unroll
-                for (int k = 0; k < ILP; ++k) open[k] = 0u;
+                // re-take the queued open decisions when another chunk might not
+                // fit, and at the end of the segment (before the next chunk's loads
+                // are issued, so that waiting for those never waits on these)
+                if (qn > kFixQ - CH || (c >= nch && qn > 0)) {
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");   // this wave's stores are complete
+                    for (int i = lane; i < qn; i += 64) {
+                        const uint2 e = myq[i];
+                        fix_one<POT, NB>((cExact*)a.ex, B.m, e.y, (int64_t)e.x, a.stride, a.cellrow, (gF32*)a.out,
+                                         (lF64*)hist, (lF64*)csum, (lU32*)ccnt, B.pot.lcE0, B.pot.lcEinv, a.lay.sini,
+                                         a.lay.cosi);
+                    }
+                    qn = 0;
+                }
             }
             if (c >= nch) break;
             // this chunk's particles (loaded one chunk ago), then the next chunk's loads
-            const Regs cur_r = next_r;
+            const Regs cur_r = R0;
             unsigned got = 0;
             if (lane == 0) got = __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
             const int cn = nw + (int)__builtin_amdgcn_readfirstlane(got);
-            if (cn < nch) load_chunk(P0, n, cn, next_r);
-            const uint32_t flo = opaque(a.flags), rbo = opaque(uint32_t(a.stride * sizeof(T)));
+            if (cn < nch) load_chunk(P0, n, cn, R0);
+            const uint32_t flo = MODE ? fl : opaque(a.flags), rbo = opaque(uint32_t(a.stride * sizeof(T)));
             #pragma unroll
             for (int k = 0; k < ILP; ++k) {
                 const int i = c * CH + k * 64 + lane;
-                open[k] = i < n ? particle_step<POT, NB, SIG>(a, B, acc, P0 + i, cur_r.x[k], cur_r.y[k], cur_r.z[k],
-                                                              cur_r.vx[k], cur_r.vy[k], cur_r.vz[k], cur_r.w[k],
-                                                              cur_r.wh[k], cur_r.tg[k], kp[k], flo, rbo)
-                                : 0u;
+                const unsigned o = i < n ? particle_step<POT, NB, SIG, CAX>(a, B, acc, P0 + i, cur_r.x[k], cur_r.y[k],
+                                                                           cur_r.z[k], cur_r.vx[k], cur_r.vy[k],
+                                                                           cur_r.vz[k], cur_r.w[k], cur_r.wh[k],
+                                                                           cur_r.tg[k], flo, rbo)
+                                         : 0u;
+                if constexpr (F32) {
+                    // queue the open decisions of this 64-particle group
+                    const unsigned long long bm = __ballot(o != 0u);
+                    if (bm) {
+                        const int pos = qn + (int)__builtin_amdgcn_mbcnt_hi(
+                                                 uint32_t(bm >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(bm), 0u));
+                        if (o) myq[pos] = make_uint2(uint32_t(P0 + i), o);
+                        qn += __popcll(bm);
+                    }
+                }
             }
-            p_open = P0 + (int64_t)c * CH;
             c = cn;
         }
 
@@ -358,7 +387,7 @@ __global__ void __launch_bounds__(sizeof(T) == 8 ? 256 : 1024) step_kernel(StepA
         n = (int)(ro(a.tile_p0, te - 1) + ro(a.tile_cnt, te - 1) - P0);
         ++slot;
         __syncthreads();   // every thread has read the LDS of the flushed segment
-        if (wid * CH < n) load_chunk(P0, n, wid, next_r);
+        if (wid * CH < n) load_chunk(P0, n, wid, R0);
     }
     if (acc.bad) {
         __hip_atomic_fetch_or(a.flag, (int)acc.bad, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -444,26 +473,44 @@ hipError_t launch_gather(const GatherArgs<T>& a, int pot_kind, int blocks, hipSt
 template hipError_t launch_gather<float>(const GatherArgs<float>&, int, int, hipStream_t);
 template hipError_t launch_gather<double>(const GatherArgs<double>&, int, int, hipStream_t);
 
-template <typename T, typename PT, int POT, int NB, uint64_t SIG>
+template <typename T, typename PT, int POT, int NB, uint64_t SIG, int CAX, int MODE>
 static hipError_t launch_k(const StepArgs<T, PT>& a, int ilp, int blocks, int threads, size_t lds, hipStream_t s) {
-    if (ilp == 1) hipLaunchKernelGGL((step_kernel<T, PT, POT, NB, SIG, 1>), dim3(blocks), dim3(threads), lds, s, a);
-    else hipLaunchKernelGGL((step_kernel<T, PT, POT, NB, SIG, 2>), dim3(blocks), dim3(threads), lds, s, a);
+    if (ilp == 1)
+        hipLaunchKernelGGL((step_kernel<T, PT, POT, NB, SIG, CAX, MODE, 1>), dim3(blocks), dim3(threads), lds, s, a);
+    else
+        hipLaunchKernelGGL((step_kernel<T, PT, POT, NB, SIG, CAX, MODE, 2>), dim3(blocks), dim3(threads), lds, s, a);
     return hipGetLastError();
 }
 
-// FP32 layouts with a compiled signature get their own kernels; every other
-// layout runs the kernels compiled for at most NB = 2 or 4 binnings.
+// A signature kernel with the prior's cell axes and the step's flags compiled in
+// when they are the common ones (CAX1; the stepping or observing flags of a
+// histogram prior refreshed every step), else with both at run time.
+template <typename T, typename PT, int POT, int NB, uint64_t SIG, int CAX1>
+static hipError_t launch_cax(const StepArgs<T, PT>& a, int ilp, int blocks, int threads, size_t lds, hipStream_t s) {
+    if (a.cells.ncell > 0 && cax_of(a.cells) == CAX1) {
+        if (a.flags == kHotFlags) return launch_k<T, PT, POT, NB, SIG, CAX1, 1>(a, ilp, blocks, threads, lds, s);
+        if ((a.flags & ~(3u << kWhatShift)) == kObsCells)
+            return launch_k<T, PT, POT, NB, SIG, CAX1, 2>(a, ilp, blocks, threads, lds, s);
+    }
+    return launch_k<T, PT, POT, NB, SIG, kCaxRuntime, 0>(a, ilp, blocks, threads, lds, s);
+}
+
+// FP32 layouts with a compiled signature get their own kernels (for the log
+// potential's (E, Lz/Lc) priors and the spherical potentials' (E, L/Lc) priors
+// with the cell axes compiled in as well); every other layout runs the kernels
+// compiled for at most NB = 2 or 4 binnings.
 template <typename T, typename PT, int POT>
 static hipError_t launch_step_pot(const StepArgs<T, PT>& a, uint64_t sig, int nbin, int ilp, int blocks, int threads,
                                   size_t lds, hipStream_t s) {
     if constexpr (sizeof(T) == 4 && POT == 1) {
-        if (sig == kSigPixKin) return launch_k<T, PT, POT, 2, kSigPixKin>(a, ilp, blocks, threads, lds, s);
-        if (sig == kSigPixKinShell) return launch_k<T, PT, POT, 4, kSigPixKinShell>(a, ilp, blocks, threads, lds, s);
+        if (sig == kSigPixKin) return launch_cax<T, PT, POT, 2, kSigPixKin, kCaxLzNo3>(a, ilp, blocks, threads, lds, s);
+        if (sig == kSigPixKinShell)
+            return launch_cax<T, PT, POT, 4, kSigPixKinShell, kCaxLzNo3>(a, ilp, blocks, threads, lds, s);
     }
     if constexpr (sizeof(T) == 4 && POT != 1)
-        if (sig == kSigShellAnn) return launch_k<T, PT, POT, 2, kSigShellAnn>(a, ilp, blocks, threads, lds, s);
-    if (nbin <= 2) return launch_k<T, PT, POT, 2, 0>(a, ilp, blocks, threads, lds, s);
-    return launch_k<T, PT, POT, 4, 0>(a, ilp, blocks, threads, lds, s);
+        if (sig == kSigShellAnn) return launch_cax<T, PT, POT, 2, kSigShellAnn, kCaxLNo3>(a, ilp, blocks, threads, lds, s);
+    if (nbin <= 2) return launch_k<T, PT, POT, 2, 0, kCaxRuntime, 0>(a, ilp, blocks, threads, lds, s);
+    return launch_k<T, PT, POT, 4, 0, kCaxRuntime, 0>(a, ilp, blocks, threads, lds, s);
 }
 
 template <typename T, typename PT>
@@ -476,25 +523,34 @@ hipError_t launch_step(const StepArgs<T, PT>& a, int pot_kind, uint64_t sig, int
     }
 }
 
-template <typename T, typename PT, int POT, int NB, uint64_t SIG>
+template <typename T, typename PT, int POT, int NB, uint64_t SIG, int CAX, int MODE>
 static hipError_t set_lds_k(size_t lds) {
-    for (const void* f : {(const void*)step_kernel<T, PT, POT, NB, SIG, 1>, (const void*)step_kernel<T, PT, POT, NB, SIG, 2>}) {
+    for (const void* f : {(const void*)step_kernel<T, PT, POT, NB, SIG, CAX, MODE, 1>,
+                          (const void*)step_kernel<T, PT, POT, NB, SIG, CAX, MODE, 2>}) {
         hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
 }
 
+template <typename T, typename PT, int POT, int NB, uint64_t SIG, int CAX1>
+static hipError_t set_lds_sig(size_t lds) {
+    hipError_t e = set_lds_k<T, PT, POT, NB, SIG, kCaxRuntime, 0>(lds);
+    if (e == hipSuccess) e = set_lds_k<T, PT, POT, NB, SIG, CAX1, 1>(lds);
+    if (e == hipSuccess) e = set_lds_k<T, PT, POT, NB, SIG, CAX1, 2>(lds);
+    return e;
+}
+
 template <typename T, typename PT, int POT>
 static hipError_t set_lds_pot(size_t lds) {
-    hipError_t e = set_lds_k<T, PT, POT, 2, 0>(lds);
-    if (e == hipSuccess) e = set_lds_k<T, PT, POT, 4, 0>(lds);
+    hipError_t e = set_lds_k<T, PT, POT, 2, 0, kCaxRuntime, 0>(lds);
+    if (e == hipSuccess) e = set_lds_k<T, PT, POT, 4, 0, kCaxRuntime, 0>(lds);
     if constexpr (sizeof(T) == 4 && POT == 1) {
-        if (e == hipSuccess) e = set_lds_k<T, PT, POT, 2, kSigPixKin>(lds);
-        if (e == hipSuccess) e = set_lds_k<T, PT, POT, 4, kSigPixKinShell>(lds);
+        if (e == hipSuccess) e = set_lds_sig<T, PT, POT, 2, kSigPixKin, kCaxLzNo3>(lds);
+        if (e == hipSuccess) e = set_lds_sig<T, PT, POT, 4, kSigPixKinShell, kCaxLzNo3>(lds);
     }
     if constexpr (sizeof(T) == 4 && POT != 1)
-        if (e == hipSuccess) e = set_lds_k<T, PT, POT, 2, kSigShellAnn>(lds);
+        if (e == hipSuccess) e = set_lds_sig<T, PT, POT, 2, kSigShellAnn, kCaxLNo3>(lds);
     return e;
 }
 
