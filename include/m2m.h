@@ -273,6 +273,14 @@ m2m_status m2m_tags(m2m_ctx *ctx, uint16_t *out, int32_t device_ptr);
  * 4096 steps per model).  out holds max_rows rows; *n_rows gets the count. */
 m2m_status m2m_history(m2m_ctx *ctx, m2m_step_stats *out, int64_t max_rows, int64_t *n_rows);
 
+/* Paper section 4: the data are fitted in a sequence of gravitational potentials
+ * (here the n_models models of one context, each with its own potential) and
+ * the fits are compared.  For the statistics of the last step taken: chi2
+ * (n_models values, the smoothed chi^2 of each model), delta (n_models values,
+ * chi2 - min over models) and *best (the model of least chi^2; the first on a
+ * tie).  Host outputs, each nullable.  INVALID when no step has been taken. */
+m2m_status m2m_delta_chi2(m2m_ctx *ctx, double *chi2, double *delta, int32_t *best);
+
 /* Node coefficients of a MULTIPOLE model (sections 1 and 2: the potential
  * computed from the particles), as used by the first kick of the next step:
  * A and B, nnode * (lmax+1)^2 FP64 values each (host; node k at k*(lmax+1)^2,

@@ -106,6 +106,7 @@ def lib():
         L.m2m_tags.argtypes = [CTX, VP, C.c_int32]
         L.m2m_history.argtypes = [CTX, C.POINTER(m2m_step_stats), C.c_int64, C.POINTER(C.c_int64)]
         L.m2m_multipole_tables.argtypes = [CTX, C.POINTER(C.c_double), C.POINTER(C.c_double)]
+        L.m2m_delta_chi2.argtypes = [CTX, C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_int32)]
         L.m2m_mlp_state.argtypes = [CTX, C.POINTER(C.c_float), C.POINTER(C.c_double), C.POINTER(C.c_int32),
                                     C.POINTER(C.c_int64)]
         L.m2m_mlp_loss_grad.argtypes = [CTX, C.POINTER(C.c_float), C.POINTER(C.c_float), C.c_int32,
@@ -120,7 +121,7 @@ def lib():
         L.m2m_last_error.argtypes = [CTX]
         L.m2m_last_error.restype = C.c_char_p
         for f in ("m2m_create", "m2m_step", "m2m_observables", "m2m_weights", "m2m_priors", "m2m_particles",
-                  "m2m_history", "m2m_multipole_tables", "m2m_mlp_state", "m2m_mlp_loss_grad", "m2m_mlp_loss_grad_noalloc", "m2m_autotune", "m2m_get_launch", "m2m_set_launch", "m2m_kernel_time"):
+                  "m2m_history", "m2m_multipole_tables", "m2m_delta_chi2", "m2m_mlp_state", "m2m_mlp_loss_grad", "m2m_mlp_loss_grad_noalloc", "m2m_autotune", "m2m_get_launch", "m2m_set_launch", "m2m_kernel_time"):
             getattr(L, f).restype = C.c_int
         if L.m2m_abi_version() != ABI_VERSION:
             raise ImportError("libm2m_hip.so ABI %d, binding expects %d" % (L.m2m_abi_version(), ABI_VERSION))
@@ -359,6 +360,15 @@ def m2m_history(ctx, max_rows=None):
     n = C.c_int64()
     _check(lib().m2m_history(ctx.ptr, rows, max_rows, C.byref(n)), ctx)
     return [_stats_dict(rows[k]) for k in range(n.value)]
+
+
+def m2m_delta_chi2(ctx):
+    """Per-model chi^2 of the last step, chi^2 - min, and the best model's index."""
+    chi2 = np.zeros(ctx.n_models)
+    delta = np.zeros(ctx.n_models)
+    best = C.c_int32()
+    _check(lib().m2m_delta_chi2(ctx.ptr, _dp(chi2), _dp(delta), C.byref(best)), ctx)
+    return chi2, delta, best.value
 
 
 def m2m_multipole_tables(ctx, nnode, lmax):

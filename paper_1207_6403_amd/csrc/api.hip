@@ -1404,6 +1404,29 @@ extern "C" m2m_status m2m_history(m2m_ctx* c, m2m_step_stats* out, int64_t max_r
     return M2M_OK;
 }
 
+// ------------------------------------------------------ potential sequence
+extern "C" m2m_status m2m_delta_chi2(m2m_ctx* c, double* chi2, double* delta, int32_t* best) {
+    if (!c) return fail(nullptr, M2M_ERR_INVALID, "ctx is NULL");
+    if (c->step < 1) return fail(c, M2M_ERR_INVALID, "no step taken yet");
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    const int64_t row = (c->step - 1) % kRing;
+    std::vector<double> x(c->M);
+    for (int m = 0; m < c->M; ++m) {
+        StatRow r;
+        HIPCHK(c, hipMemcpy(&r, c->ring + (size_t)m * kRing + row, sizeof(r), hipMemcpyDeviceToHost));
+        x[m] = r.chi2;
+    }
+    int b = 0;
+    for (int m = 1; m < c->M; ++m)
+        if (x[m] < x[b]) b = m;
+    for (int m = 0; m < c->M; ++m) {
+        if (chi2) chi2[m] = x[m];
+        if (delta) delta[m] = x[m] - x[b];
+    }
+    if (best) *best = b;
+    return M2M_OK;
+}
+
 // --------------------------------------------------------- multipole tables
 extern "C" m2m_status m2m_multipole_tables(m2m_ctx* c, double* A, double* B) {
     if (!c || !A || !B) return fail(c, M2M_ERR_INVALID, "null argument");

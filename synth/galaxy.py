@@ -96,6 +96,163 @@ def hernquist_isotropic_ics(n, seed, G=1.0, M=1.0, a=1.0):
     return np.stack([x, y, z, speed * ex, speed * ey, speed * ez])
 
 
+# ------------------------------------------------- anisotropic Hernquist models
+# Initial models of the convergence experiment (paper section 3), G = M = a = 1, in
+# terms of the relative potential Psi = -Phi = 1/(1 + r) (r = (1 - Psi)/Psi) and
+# the binding energy eps = Psi - v^2/2.
+#
+# Osipkov-Merritt (anisotropy radius ra): f = f(Q), Q = eps - L^2/(2 ra^2), from the
+# Eddington inversion of rho_Q = (1 + r^2/ra^2) rho, which for the Hernquist
+# sphere is rho_Q(Psi) = [Psi^4/(1 - Psi) + (Psi^2 - Psi^3)/ra^2] / (2 pi):
+#   f(Q) = 1/(sqrt(8) pi^2) int_0^Q rho_Q''(Psi) dPsi / sqrt(Q - Psi)
+# (d rho_Q/d Psi vanishes at Psi = 0); beta(r) = r^2/(r^2 + ra^2).
+#
+# Tangential, constant beta = -1/2: f = L g(eps).  Then rho/r = 2 pi^2
+# int_0^Psi (Psi - e) g(e) de, so g = (rho/r)''/(2 pi^2) with
+# rho/r = Psi^5/(2 pi (1 - Psi)^2).
+
+def om_rhoq_pp(psi, ra):
+    """Second derivative of rho_Q(Psi) of the Osipkov-Merritt Hernquist model."""
+    u = 1.0 - psi
+    app = 12.0 * psi ** 2 / u + 2.0 * psi ** 3 * (4.0 - 3.0 * psi) / u ** 3
+    bpp = (2.0 - 6.0 * psi) / (ra * ra)
+    return (app + bpp) / (2.0 * np.pi)
+
+
+def om_df_table(ra, n=1200):
+    """f(Q) of the Osipkov-Merritt Hernquist model on Q in (0, 1): the Eddington
+    integral with Psi = Q - u^2 (dPsi / sqrt(Q - Psi) = 2 du), by adaptive
+    quadrature.  Returns (Q, f) for interpolation in ln(1 - Q)."""
+    lq = np.linspace(np.log(1e-7), np.log(1.0 - 1e-7), n)   # ln(1 - Q) grid, both ends
+    Q = 1.0 - np.exp(lq[::-1])
+    Q = np.concatenate([np.geomspace(1e-7, Q[0], 200, endpoint=False), Q])
+    f = np.empty(Q.size)
+    for k, q in enumerate(Q):
+        f[k] = integrate.quad(lambda u: 2.0 * om_rhoq_pp(q - u * u, ra), 0.0, np.sqrt(q),
+                              epsabs=0.0, epsrel=1e-10, limit=400)[0]
+    return Q, f / (np.sqrt(8.0) * np.pi ** 2)
+
+
+class OMDF:
+    """Interpolated f(Q) of the Osipkov-Merritt Hernquist model (0 for Q <= 0)."""
+
+    def __init__(self, ra):
+        self.ra = ra
+        Q, f = om_df_table(ra)
+        if np.any(f < 0):
+            raise ValueError("Osipkov-Merritt Hernquist model with ra=%g is unphysical (f < 0)" % ra)
+        self._x = np.log(Q)
+        self._y = np.log(np.maximum(f, 1e-300))
+
+    def __call__(self, Q):
+        Q = np.asarray(Q, dtype=np.float64)
+        out = np.zeros(Q.shape)
+        ok = (Q > 0) & (Q < 1)
+        out[ok] = np.exp(np.interp(np.log(Q[ok]), self._x, self._y))
+        return out
+
+
+def tangential_g(eps):
+    """g(eps) of the beta = -1/2 Hernquist model f = L g(eps): (rho/r)''/(2 pi^2)."""
+    eps = np.asarray(eps, dtype=np.float64)
+    u = 1.0 - eps
+    cpp = 20.0 * eps ** 3 / u ** 2 + 20.0 * eps ** 4 / u ** 3 + 6.0 * eps ** 5 / u ** 4
+    return np.where((eps > 0) & (eps < 1), cpp / (4.0 * np.pi ** 3), 0.0)
+
+
+def _rejection(rng, n, bound, sample, density):
+    """Rejection sampling of n values with per-item envelopes `bound` (proposal
+    sample(idx) on the item's support, unnormalised density(values, idx))."""
+    out = np.empty(n)
+    todo = np.arange(n)
+    worst = 0.0
+    while todo.size:
+        v = sample(todo)
+        p = density(v, todo)
+        worst = max(worst, float(np.max(p / bound[todo])))
+        acc = rng.uniform(0.0, 1.0, todo.size) * bound[todo] < p
+        out[todo[acc]] = v[acc]
+        todo = todo[~acc]
+    if worst > 1.0:
+        raise RuntimeError("rejection envelope too low (%.3f)" % worst)
+    return out
+
+
+def _envelope(n, dens_on_grid):
+    s = np.linspace(0.0, 1.0, 257)[1:-1]
+    b = np.zeros(n)
+    for k in range(0, n, 32768):
+        sl = slice(k, k + 32768)
+        b[sl] = 1.5 * dens_on_grid(s, sl).max(axis=1)
+    return b
+
+
+def _tangential_frame(x, y, z, rng):
+    """Unit vectors r_hat and two tangential directions per particle."""
+    r = np.sqrt(x * x + y * y + z * z)
+    er = np.stack([x, y, z]) / r
+    a = rng.normal(0.0, 1.0, (3, x.size))
+    e1 = a - er * (a * er).sum(axis=0)
+    e1 /= np.linalg.norm(e1, axis=0)
+    e2 = np.cross(er.T, e1.T).T
+    return r, er, e1, e2
+
+
+def hernquist_om_ics(n, seed, ra):
+    """Osipkov-Merritt Hernquist initial model: positions from M(r); velocities with
+    w = (v_r, v_t sqrt(1 + r^2/ra^2)) isotropic and |w| drawn from w^2 f(Psi - w^2/2)."""
+    rng = np.random.default_rng(seed)
+    df = OMDF(ra)
+    x, y, z = hernquist_positions(rng, n)
+    r, er, e1, e2 = _tangential_frame(x, y, z, rng)
+    psi = 1.0 / (1.0 + r)
+    wmax = np.sqrt(2.0 * psi)
+    dens = lambda w, idx: w * w * df(psi[idx] - 0.5 * w * w)
+    bound = _envelope(n, lambda s, sl: (wmax[sl, None] * s) ** 2 * df(psi[sl, None] * (1.0 - s * s)))
+    w = _rejection(rng, n, bound, lambda idx: rng.uniform(0.0, 1.0, idx.size) * wmax[idx], dens)
+    ct = rng.uniform(-1.0, 1.0, n)
+    st = np.sqrt(1.0 - ct * ct)
+    ph = rng.uniform(0.0, 2.0 * np.pi, n)
+    vr = w * ct
+    vt = w * st / np.sqrt(1.0 + (r / ra) ** 2)
+    v = er * vr + (e1 * np.cos(ph) + e2 * np.sin(ph)) * vt
+    return np.concatenate([np.stack([x, y, z]), v])
+
+
+def hernquist_tangential_ics(n, seed):
+    """beta = -1/2 Hernquist initial model f = L g(eps): positions from M(r); speed
+    from v^3 g(Psi - v^2/2), angle eta to r_hat from sin^2(eta)."""
+    rng = np.random.default_rng(seed)
+    x, y, z = hernquist_positions(rng, n)
+    r, er, e1, e2 = _tangential_frame(x, y, z, rng)
+    psi = 1.0 / (1.0 + r)
+    vmax = np.sqrt(2.0 * psi)
+    dens = lambda v, idx: v ** 3 * tangential_g(psi[idx] - 0.5 * v * v)
+    bound = _envelope(n, lambda s, sl: (vmax[sl, None] * s) ** 3 * tangential_g(psi[sl, None] * (1.0 - s * s)))
+    v = _rejection(rng, n, bound, lambda idx: rng.uniform(0.0, 1.0, idx.size) * vmax[idx], dens)
+    eta = _rejection(rng, n, np.ones(n), lambda idx: rng.uniform(0.0, np.pi, idx.size),
+                     lambda e, idx: np.sin(e) ** 2)
+    ph = rng.uniform(0.0, 2.0 * np.pi, n)
+    vel = er * (v * np.cos(eta)) + (e1 * np.cos(ph) + e2 * np.sin(ph)) * (v * np.sin(eta))
+    return np.concatenate([np.stack([x, y, z]), vel])
+
+
+def anisotropy_profile(ics, w, edges):
+    """beta(r) = 1 - (sigma_theta^2 + sigma_phi^2)/(2 sigma_r^2) of a weighted
+    particle model in radial shells (second moments about zero: the models are
+    non-rotating)."""
+    x, y, z, vx, vy, vz = ics
+    r = np.sqrt(x * x + y * y + z * z)
+    vr = (x * vx + y * vy + z * vz) / r
+    v2 = vx * vx + vy * vy + vz * vz
+    k = np.digitize(r, edges) - 1
+    ok = (k >= 0) & (k < len(edges) - 1)
+    nb = len(edges) - 1
+    sr = np.bincount(k[ok], weights=(w * vr * vr)[ok], minlength=nb)
+    st = np.bincount(k[ok], weights=(w * (v2 - vr * vr))[ok], minlength=nb)
+    return 1.0 - st / (2.0 * sr)
+
+
 # ---------------------------------------------------------- logarithmic potential
 def log_density(R2, z2, v0=1.0, Rc=0.1, q=0.8, G=1.0):
     """Poisson density of Phi = v0^2/2 ln(Rc^2 + R^2 + z^2/q^2)."""

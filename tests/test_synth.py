@@ -103,3 +103,47 @@ def test_noise_is_seeded_and_sized():
     np.testing.assert_allclose(s1[:30], 0.05 * Yt[:30])
     np.testing.assert_allclose(s1[30:], 0.1 * Yt[30:])
     assert np.all(s1 > 0)
+
+
+# ------------------------------------------- anisotropic initial models (NEXT-1)
+def test_om_df_reduces_to_isotropic_closed_form():
+    """Osipkov-Merritt inversion with ra -> infinity is the isotropic Hernquist DF."""
+    df = galaxy.OMDF(1e6)
+    E = -np.array([0.05, 0.2, 0.5, 0.8, 0.95])
+    np.testing.assert_allclose(df(-E), galaxy.hernquist_df(E), rtol=1e-3)
+
+
+@pytest.mark.parametrize("ra", [1.0, 0.6])
+def test_om_df_reproduces_density(ra):
+    """4 pi / (1 + r^2/ra^2) int w^2 f(Psi - w^2/2) dw = rho(r) (the OM velocity
+    integral with w = (v_r, v_t sqrt(1 + r^2/ra^2)))."""
+    from scipy import integrate
+    df = galaxy.OMDF(ra)
+    for r in (0.1, 1.0, 4.0):
+        psi = 1.0 / (1.0 + r)
+        I = integrate.quad(lambda w: w * w * df(psi - 0.5 * w * w), 0.0, np.sqrt(2 * psi), limit=400)[0]
+        rho = 4.0 * np.pi * I / (1.0 + r * r / (ra * ra))
+        assert rho == pytest.approx(galaxy.hernquist_density(r), rel=2e-3)
+
+
+def test_tangential_df_reproduces_density():
+    """2 pi^2 r int_0^Psi (Psi - e) g(e) de = rho(r) for f = L g(e)."""
+    from scipy import integrate
+    for r in (0.1, 1.0, 4.0):
+        psi = 1.0 / (1.0 + r)
+        I = integrate.quad(lambda e: (psi - e) * galaxy.tangential_g(e), 0.0, psi, limit=200)[0]
+        assert 2 * np.pi ** 2 * r * I == pytest.approx(galaxy.hernquist_density(r), rel=1e-10)
+
+
+def test_sampled_anisotropy_profiles():
+    """Sampled models carry the anisotropy they are built with: OM beta(r) =
+    r^2/(r^2 + ra^2) (shell averages), beta = -1/2, and 0 for the isotropic DF."""
+    edges = np.array([0.5, 1.0, 2.0, 4.0])
+    n = 100000
+    rm = np.sqrt(edges[1:] * edges[:-1])
+    om = galaxy.hernquist_om_ics(n, 11, 0.6)
+    np.testing.assert_allclose(galaxy.anisotropy_profile(om, np.ones(n), edges), rm ** 2 / (rm ** 2 + 0.36), atol=0.04)
+    tg = galaxy.hernquist_tangential_ics(n, 12)
+    np.testing.assert_allclose(galaxy.anisotropy_profile(tg, np.ones(n), edges), -0.5, atol=0.04)
+    iso = galaxy.hernquist_isotropic_ics(n, 13)
+    np.testing.assert_allclose(galaxy.anisotropy_profile(iso, np.ones(n), edges), 0.0, atol=0.04)
