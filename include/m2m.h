@@ -45,7 +45,7 @@
 extern "C" {
 #endif
 
-#define M2M_ABI_VERSION 1
+#define M2M_ABI_VERSION 2
 #define M2M_MAX_BINNINGS 4
 #define M2M_MAX_EDGES 256
 #define M2M_MLP_NPARAM 4481
@@ -63,6 +63,16 @@ typedef enum {
 enum { M2M_F32 = 0, M2M_F64 = 1 };
 enum { M2M_POT_HERNQUIST = 0, M2M_POT_LOG = 1, M2M_POT_HERNQUIST_NFW = 2, M2M_POT_MULTIPOLE = 3 };
 enum { M2M_BIN_SHELL = 1, M2M_BIN_ANNULUS = 2, M2M_BIN_GRID = 3 };
+/* Moment codes of a binning: mass, first and second line-of-sight moments, and
+ * the Gauss-Hermite moments h1..h4 (section 1: absorption-line kinematics from
+ * long-slit and integral-field spectra) of each bin's line-of-sight velocity
+ * distribution expanded about the Gaussian (V_b, sigma_b) given with the data
+ * (van der Marel & Franx 1993): kernel 2 sqrt(pi) alpha(nu) H_m(nu),
+ * nu = (v_los - V_b)/sigma_b, alpha(nu) = exp(-nu^2/2)/sqrt(2 pi), H_m the
+ * normalised Hermite polynomials; its mass-weighted sum over the particles of a
+ * bin is the bin's mass times h_m. */
+enum { M2M_MOM_MASS = 0, M2M_MOM_V = 1, M2M_MOM_V2 = 2, M2M_MOM_H1 = 3, M2M_MOM_H2 = 4, M2M_MOM_H3 = 5,
+       M2M_MOM_H4 = 6 };
 enum { M2M_PRIOR_FLAT = 0, M2M_PRIOR_HIST = 1, M2M_PRIOR_MLP = 2 };
 enum { M2M_UPDATE_EULER = 0, M2M_UPDATE_EXP = 1 };
 
@@ -92,7 +102,10 @@ typedef struct {
  * projected radius R = |(X, Y)| against nedge strictly increasing edges (bins
  * are [e_k, e_k+1)); GRID bins the sky plane into nx * ny pixels over
  * [x0, x1) x [y0, y1), pixel k = iy * nx + ix.  mom[0..nmom-1] lists the
- * moments fitted in these bins: 0 = mass, 1 = sum w v_los, 2 = sum w v_los^2. */
+ * moment codes fitted in these bins (M2M_MOM_*: 0 = mass, 1 = sum w v_los,
+ * 2 = sum w v_los^2, 3..6 = Gauss-Hermite h1..h4); a binning that lists a
+ * Gauss-Hermite code gives gh, 2 * nb values (host, copied at creation): V_b of
+ * every bin, then sigma_b > 0 of every bin. */
 typedef struct {
     int32_t kind;
     int32_t nmom;
@@ -101,6 +114,7 @@ typedef struct {
     const double *edges;     /* host, nedge values (SHELL, ANNULUS)     */
     int32_t nx, ny;
     double x0, x1, y0, y1;   /* GRID extent                             */
+    const double *gh;        /* host, Gauss-Hermite V_b[nb], sigma_b[nb] */
 } m2m_binning;
 
 /* Observation layout.  Sky coordinates for inclination incl (radians):

@@ -52,7 +52,8 @@ class Layout(C.Structure):
                 ("edge", C.POINTER(C.c_double) * MAXBIN),
                 ("nx", C.c_int32 * MAXBIN), ("ny", C.c_int32 * MAXBIN),
                 ("x0", C.c_double * MAXBIN), ("x1", C.c_double * MAXBIN),
-                ("y0", C.c_double * MAXBIN), ("y1", C.c_double * MAXBIN)]
+                ("y0", C.c_double * MAXBIN), ("y1", C.c_double * MAXBIN),
+                ("gh", C.POINTER(C.c_double) * MAXBIN)]
 
 
 class Prior(C.Structure):
@@ -146,6 +147,10 @@ def make_layout(lay, keep):
         s.nmom[b] = len(d["moments"])
         for m, mo in enumerate(d["moments"]):
             s.mom[b][m] = int(mo)
+        if any(int(mo) >= 3 for mo in d["moments"]):
+            gh = _f64(np.asarray(d["gh"], dtype=np.float64).ravel())   # V_b then sigma_b
+            keep.append(gh)
+            s.gh[b] = _dp(gh)
         if d["kind"] in ("shell", "annulus"):
             e = _f64(d["edges"])
             keep.append(e)

@@ -30,6 +30,7 @@
  *               dt as w_i <- w_i exp(eps dt G_i) (default) or w_i (1 + eps dt G_i)
  *   7 push      kick-drift-kick leapfrog over dt
  */
+#define _DEFAULT_SOURCE
 #include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
@@ -63,6 +64,7 @@ typedef struct {
     const double *edge[OR_MAXBIN];
     int32_t nx[OR_MAXBIN], ny[OR_MAXBIN];
     double x0[OR_MAXBIN], x1[OR_MAXBIN], y0[OR_MAXBIN], y1[OR_MAXBIN];
+    const double *gh[OR_MAXBIN];   /* Gauss-Hermite moments: V_b[nb] then sigma_b[nb] */
 } or_layout;
 
 typedef struct {
@@ -199,6 +201,8 @@ double or_circular_L(const or_pot *p, double E) {
  *   shell   K = 1[e_k <= r < e_k+1]               (3D density)
  *   annulus K = 1[e_k <= R < e_k+1] * v_los^m      (projected radius R)
  *   grid    K = 1[(X, Y) in pixel k] * v_los^m     (sky plane)
+ * (m = 0, 1, 2; the Gauss-Hermite kernels of gh_kernel replace v_los^m for
+ * moment codes 3..6)
  * Sky coordinates for inclination i: X = x, Y = y cos i - z sin i,
  * v_los = vy sin i + vz cos i.  Bins are half-open; a particle outside every bin
  * contributes nothing.  Returns the number of non-zero entries. */
@@ -227,6 +231,37 @@ static int bin_of(const or_layout *L, int b, double ci, double si, double x, dou
     return -1;
 }
 
+/* Gauss-Hermite line-of-sight kinematics (section 1: absorption-line
+ * kinematics from long-slit and integral-field spectra).  Reading: the LOSVD of
+ * bin b is expanded about the Gaussian of mean V_b and dispersion sigma_b given
+ * with the data (van der Marel & Franx 1993); moment code 2 + m (m = 1..4) is the
+ * kernel K = 2 sqrt(pi) alpha(nu) H_m(nu), nu = (v_los - V_b)/sigma_b,
+ * alpha(nu) = exp(-nu^2/2)/sqrt(2 pi), whose mass-weighted expectation under a
+ * Gauss-Hermite LOSVD is h_m.  H_m = Hp_m / sqrt(2^m m!) with the physicists'
+ * Hermite polynomials Hp_0 = 1, Hp_1 = 2 nu, Hp_(m+1) = 2 nu Hp_m - 2 m Hp_(m-1). */
+static double gh_kernel(int m, double nu) {
+    double hm1 = 1.0, h = 2.0 * nu, norm = 2.0;   /* Hp_0, Hp_1, 2^1 1! */
+    if (m == 0) { h = 1.0; norm = 1.0; }
+    for (int k = 1; k < m; ++k) {
+        double hn = 2.0 * nu * h - 2.0 * k * hm1;
+        hm1 = h;
+        h = hn;
+        norm *= 2.0 * (k + 1);
+    }
+    return 2.0 * sqrt(M_PI) * exp(-0.5 * nu * nu) / sqrt(2.0 * M_PI) * h / sqrt(norm);
+}
+
+/* Kernel value of moment code mo of a particle in bin k of binning b:
+ * 0 mass, 1 v_los, 2 v_los^2, 3..6 Gauss-Hermite h1..h4. */
+static double moment_kernel(const or_layout *L, int b, int k, int mo, double vl) {
+    if (mo == 0) return 1.0;
+    if (mo == 1) return vl;
+    if (mo == 2) return vl * vl;
+    int nb = L->kind[b] == OR_BIN_GRID ? L->nx[b] * L->ny[b] : L->nedge[b] - 1;
+    double nu = (vl - L->gh[b][k]) / L->gh[b][nb + k];
+    return gh_kernel(mo - 2, nu);
+}
+
 int or_kernel(const or_layout *L, double x, double y, double z,
               double vx, double vy, double vz, int32_t *jidx, double *Kval) {
     (void)vx;
@@ -238,9 +273,8 @@ int or_kernel(const or_layout *L, double x, double y, double z,
         int k = bin_of(L, b, ci, si, x, y, z);
         for (int m = 0; m < L->nmom[b]; ++m) {
             if (k >= 0) {
-                int mo = L->mom[b][m];
                 jidx[cnt] = off + m * nb + k;
-                Kval[cnt] = mo == 0 ? 1.0 : (mo == 1 ? vl : vl * vl);
+                Kval[cnt] = moment_kernel(L, b, k, L->mom[b][m], vl);
                 ++cnt;
             }
         }

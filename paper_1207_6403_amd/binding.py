@@ -13,7 +13,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB = os.path.join(HERE, "libm2m_hip.so")
 
-ABI_VERSION = 1
+ABI_VERSION = 2
 MAX_BINNINGS = 4
 MLP_NPARAM = 4481
 F32, F64 = 0, 1
@@ -41,7 +41,8 @@ class m2m_potential(C.Structure):
 class m2m_binning(C.Structure):
     _fields_ = [("kind", C.c_int32), ("nmom", C.c_int32), ("mom", C.c_int32 * 3), ("nedge", C.c_int32),
                 ("edges", C.POINTER(C.c_double)), ("nx", C.c_int32), ("ny", C.c_int32),
-                ("x0", C.c_double), ("x1", C.c_double), ("y0", C.c_double), ("y1", C.c_double)]
+                ("x0", C.c_double), ("x1", C.c_double), ("y0", C.c_double), ("y1", C.c_double),
+                ("gh", C.POINTER(C.c_double))]
 
 
 class m2m_obs_layout(C.Structure):
@@ -172,6 +173,10 @@ def pack_layout(lay, keep):
             keep.append(e)
             bb.nedge = e.size
             bb.edges = _dp(e)
+        if any(int(m) >= 3 for m in d["moments"]):
+            g = np.ascontiguousarray(np.asarray(d["gh"], dtype=np.float64).ravel())   # V_b then sigma_b
+            keep.append(g)
+            bb.gh = _dp(g)
     return s
 
 

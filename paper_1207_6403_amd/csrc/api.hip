@@ -119,8 +119,12 @@ static m2m_status validate(const m2m_config* cfg, const m2m_obs_layout* lay, con
     for (int b = 0; b < lay->nbin; ++b) {
         const m2m_binning& d = lay->bin[b];
         if (d.nmom < 1 || d.nmom > 3) return fail(nullptr, M2M_ERR_INVALID, "nmom must be 1..3");
-        for (int k = 0; k < d.nmom; ++k)
-            if (d.mom[k] < 0 || d.mom[k] > 2) return fail(nullptr, M2M_ERR_INVALID, "moments are 0, 1 or 2");
+        bool gh = false;
+        for (int k = 0; k < d.nmom; ++k) {
+            if (d.mom[k] < M2M_MOM_MASS || d.mom[k] > M2M_MOM_H4)
+                return fail(nullptr, M2M_ERR_INVALID, "moment codes are 0..6");
+            gh |= d.mom[k] >= M2M_MOM_H1;
+        }
         int nb;
         if (d.kind == M2M_BIN_SHELL || d.kind == M2M_BIN_ANNULUS) {
             if (d.nedge < 2 || !d.edges) return fail(nullptr, M2M_ERR_INVALID, "need >= 2 edges");
@@ -139,6 +143,12 @@ static m2m_status validate(const m2m_config* cfg, const m2m_obs_layout* lay, con
             return fail(nullptr, M2M_ERR_INVALID, "unknown binning kind");
         }
         if (nb > 65534) return fail(nullptr, M2M_ERR_UNSUPPORTED, "at most 65534 bins per binning");
+        if (gh) {
+            if (!d.gh) return fail(nullptr, M2M_ERR_INVALID, "Gauss-Hermite moments need the bins' (V, sigma)");
+            for (int k = 0; k < nb; ++k)
+                if (!is_fin(d.gh[k]) || !(d.gh[nb + k] > 0) || !is_fin(d.gh[nb + k]))
+                    return fail(nullptr, M2M_ERR_INVALID, "Gauss-Hermite V must be finite and sigma > 0");
+        }
         J += d.nmom * nb;
     }
     if (ne > M2M_MAX_EDGES) return fail(nullptr, M2M_ERR_INVALID, "too many edges (max 256)");
@@ -316,7 +326,7 @@ static m2m_status make_plan(m2m_ctx* c, int threads, int ilp, int bpc) {
     const int NCe = (NCk + 1) & ~1, NE = (c->nedge + 1) & ~1;
     p.lds = 8 * ((size_t)c->JP + kTrash + NCk + kTrash + NE + 2 + 64) + 4 * ((size_t)NCe + kTrash) +
             ts * ((size_t)c->JP + 2 + NCe + NE + kLcTab) + (ts == 4 && NCk > 0 ? 8 * (size_t)kLcE : 0) +
-            (ts == 4 ? 8 * (size_t)kFixQ * (threads / 64) : 0);
+            (ts == 4 ? 8 * (size_t)kFixQ * (threads / 64) : 0) + ts * 2 * (size_t)c->ngh;
     p.lds = (p.lds + 15) & ~(size_t)15;
     if (p.lds > (size_t)c->max_lds)
         return fail(c, M2M_ERR_UNSUPPORTED, "layout needs " + std::to_string(p.lds) + " bytes of LDS per block (max " +
@@ -353,6 +363,7 @@ static m2m_status upload_exact(m2m_ctx* c) {
     e.erange = c->erange64;
     e.edges = c->edges64;
     e.rce = (const float*)c->rcetab;
+    e.gh = (const float*)c->ghtab32;
     e.lay = layout_of<float>(c);
     e.cells = c->cells;
     e.cosd = std::cos(c->lay.incl);
@@ -404,6 +415,7 @@ static void fill_step_args(m2m_ctx* c, StepArgs<T, T>& a, int parity, int mode, 
     a.seg_stats = p.seg_stats;
     a.edges = (const T*)c->edges;
     a.edges64 = c->edges64;
+    a.ghtab = (const T*)c->ghtab;
     a.nedge = c->nedge;
     a.pcols = c->pcols;
     a.jpad = c->JP;
@@ -749,9 +761,14 @@ static Layout<T> layout_of(const m2m_ctx* c) {
         B.kind = d.kind;
         B.nmom = d.nmom;
         B.mom = 0;
-        for (int k = 0; k < d.nmom; ++k) B.mom |= d.mom[k] << (2 * k);
+        for (int k = 0; k < d.nmom; ++k) B.mom |= d.mom[k] << (kMomBits * k);
         B.off = off;
         B.edge0 = e0;
+        B.gh0 = L.ngh;
+        if (!c->gh_host[b].empty()) {
+            L.has_gh = 1;
+            L.ngh += (int)(c->gh_host[b].size() / 2);
+        }
         if (d.kind == M2M_BIN_GRID) {
             B.nb = d.nx * d.ny;
             B.nx = d.nx;
@@ -779,7 +796,7 @@ static uint64_t signature_of(const m2m_ctx* c) {
     for (int b = 0; b < c->lay.nbin; ++b) {
         const m2m_binning& d = c->lay.bin[b];
         int mom = 0;
-        for (int k = 0; k < d.nmom; ++k) mom |= d.mom[k] << (2 * k);
+        for (int k = 0; k < d.nmom; ++k) mom |= d.mom[k] << (kMomBits * k);
         code[b] = bin_code(d.kind, d.nmom, mom);
     }
     return layout_sig(c->lay.nbin, code[0], code[1], code[2], code[3]);
@@ -958,6 +975,24 @@ static m2m_status create_T(m2m_ctx* c, const m2m_target* tg, const void* xv, con
             for (double v : c->edges_host[b]) { ed.push_back((T)v); ed64.push_back(v); }
     if (ed.empty()) { ed.push_back(T(0)); ed64.push_back(0.0); }
     if ((s = upload(c, (T**)&c->edges, ed)) || (s = upload(c, &c->edges64, ed64))) return s;
+    {
+        // Gauss-Hermite (V, 1/sigma) pairs of the GH binnings, in layout order, in
+        // the particle precision and in FP32 (the FP32 kernels' exact path)
+        std::vector<T> gt;
+        std::vector<float> gf;
+        for (int b = 0; b < c->lay.nbin; ++b) {
+            const std::vector<double>& g = c->gh_host[b];
+            const size_t nb = g.size() / 2;
+            for (size_t k = 0; k < nb; ++k) {
+                gt.push_back((T)g[k]);
+                gt.push_back((T)(1.0 / g[nb + k]));
+                gf.push_back((float)g[k]);
+                gf.push_back((float)(1.0 / g[nb + k]));
+            }
+        }
+        if (gt.empty()) { gt.assign(2, T(0)); gf.assign(2, 0.0f); }
+        if ((s = upload(c, (T**)&c->ghtab, gt)) || (s = upload(c, (float**)&c->ghtab32, gf))) return s;
+    }
     std::vector<T> fw(c->M);
     for (int m = 0; m < c->M; ++m)
         fw[m] = (T)(c->prior.flat_value > 0 ? c->prior.flat_value : 1.0 / (double)(c->off[m + 1] - c->off[m]));
@@ -1113,12 +1148,23 @@ extern "C" m2m_status m2m_create(const m2m_config* cfg, const m2m_obs_layout* la
     c->prior.mlp_init = nullptr;
     c->lay = *layout;
     for (int b = 0; b < layout->nbin; ++b) {
-        if (layout->bin[b].kind != M2M_BIN_GRID)
-            c->edges_host[b].assign(layout->bin[b].edges, layout->bin[b].edges + layout->bin[b].nedge);
+        const m2m_binning& d = layout->bin[b];
+        if (d.kind != M2M_BIN_GRID) c->edges_host[b].assign(d.edges, d.edges + d.nedge);
         c->lay.bin[b].edges = nullptr;
+        bool gh = false;
+        for (int k = 0; k < d.nmom; ++k) gh |= d.mom[k] >= M2M_MOM_H1;
+        if (gh) {
+            const int nb = d.kind == M2M_BIN_GRID ? d.nx * d.ny : d.nedge - 1;
+            c->gh_host[b].assign(d.gh, d.gh + 2 * (size_t)nb);
+        }
+        c->lay.bin[b].gh = nullptr;
     }
     c->nedge = 0;
-    for (int b = 0; b < layout->nbin; ++b) c->nedge += (int)c->edges_host[b].size();
+    c->ngh = 0;
+    for (int b = 0; b < layout->nbin; ++b) {
+        c->nedge += (int)c->edges_host[b].size();
+        c->ngh += (int)(c->gh_host[b].size() / 2);
+    }
     c->N = N;
     c->stride = (N + 63) / 64 * 64;
     c->J = J;
@@ -1161,7 +1207,7 @@ extern "C" m2m_status m2m_create(const m2m_config* cfg, const m2m_obs_layout* la
         const int NCe = (c->NC + 1) & ~1, NE = (c->nedge + 1) & ~1;
         const size_t fused = 8 * ((size_t)c->JP + kTrash + c->NC + kTrash + NE + 2 + 64) +
                              4 * ((size_t)NCe + kTrash) + 4 * ((size_t)c->JP + 2 + NCe + NE + kLcTab) +
-                             (c->NC > 0 ? 8 * (size_t)kLcE : 0) + 8 * (size_t)kFixQ * 16;
+                             (c->NC > 0 ? 8 * (size_t)kLcE : 0) + 8 * (size_t)kFixQ * 16 + 8 * (size_t)c->ngh;
         // the learned prior's judge grid, and FP32 histogram priors too large for
         // the fused kernel, are accumulated by the cell kernel
         c->cells_apart = c->prec == M2M_F32 && (c->prior.kind == M2M_PRIOR_MLP ||

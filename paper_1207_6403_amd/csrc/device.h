@@ -54,12 +54,16 @@ __device__ __forceinline__ X opaque(X x) {
 // One binning of the observation layout.  Grids: sx, sy = n / width give the
 // fast FP32 bin coordinate (the FP64 decision uses the defining form
 // (v - x0) / width * n with the constants in Exact); shells and annuli: nb + 1
-// edges from edge0 of the edge tables.  mom packs the listed moments in 2-bit
-// fields: moment m is (mom >> 2m) & 3.
+// edges from edge0 of the edge tables.  mom packs the listed moment codes in
+// 3-bit fields: code m is (mom >> 3m) & 7 (0 mass, 1 v_los, 2 v_los^2, 3..6
+// Gauss-Hermite h1..h4, whose bins' (V, 1/sigma) pairs start at pair gh0 of the
+// Gauss-Hermite table).
+constexpr int kMomBits = 3;
 template <typename T>
 struct BinDesc {
     int32_t kind, nmom, mom, off;   // off: first observable index of the binning
     int32_t nb, edge0, nx, ny;      // nb: bins per moment
+    int32_t gh0, pad;
     T x0, sx, y0, sy;
     // FP32 grid guard terms (bins): gx0 = 2u sx |x0|, gy0 = 2u sy |y0| (the
     // rounded origins), gys = 6u sy (the rounded projection, per unit of
@@ -72,22 +76,26 @@ struct Layout {
     T cosi, sini;
     int32_t nbin;
     int32_t J;
+    int32_t has_gh, ngh;   // Gauss-Hermite moments listed; pairs in the table
     BinDesc<T> b[kMaxBin];
 };
 
 // Compile-time signature of a layout's structure: nbin in the low 4 bits, then
-// 10 bits per binning (kind, nmom, mom).  Kernels compiled for a signature
+// 13 bits per binning (kind 2, nmom 2, mom 9).  Kernels compiled for a signature
 // take these from the signature instead of the layout (0: from the layout).
+constexpr int kCodeBits = 13;
 constexpr uint64_t bin_code(int kind, int nmom, int mom) { return uint64_t(kind | nmom << 2 | mom << 4); }
 constexpr uint64_t layout_sig(int nbin, uint64_t c0, uint64_t c1 = 0, uint64_t c2 = 0, uint64_t c3 = 0) {
-    return uint64_t(nbin) | c0 << 4 | c1 << 14 | c2 << 24 | c3 << 34;
+    return uint64_t(nbin) | c0 << 4 | c1 << (4 + kCodeBits) | c2 << (4 + 2 * kCodeBits) | c3 << (4 + 3 * kCodeBits);
 }
+constexpr int moms(int m0, int m1 = 0, int m2 = 0) { return m0 | m1 << kMomBits | m2 << (2 * kMomBits); }
 // The layouts with compiled kernels: sky pixels (mass) with a kinematic grid
 // (first and second LOS moments), alone or followed by 3D shells (mass); 3D
 // shells (mass) with projected annuli (second LOS moment).
-constexpr uint64_t kSigPixKin = layout_sig(2, bin_code(3, 1, 0), bin_code(3, 2, 1 | 2 << 2));
-constexpr uint64_t kSigPixKinShell = layout_sig(3, bin_code(3, 1, 0), bin_code(3, 2, 1 | 2 << 2), bin_code(1, 1, 0));
-constexpr uint64_t kSigShellAnn = layout_sig(2, bin_code(1, 1, 0), bin_code(2, 1, 2));
+constexpr uint64_t kSigPixKin = layout_sig(2, bin_code(3, 1, moms(0)), bin_code(3, 2, moms(1, 2)));
+constexpr uint64_t kSigPixKinShell =
+    layout_sig(3, bin_code(3, 1, moms(0)), bin_code(3, 2, moms(1, 2)), bin_code(1, 1, moms(0)));
+constexpr uint64_t kSigShellAnn = layout_sig(2, bin_code(1, 1, moms(0)), bin_code(2, 1, moms(2)));
 
 // Structure of the layout seen by a kernel compiled for signature SIG.
 template <uint64_t SIG, typename T>
@@ -98,16 +106,21 @@ struct LayoutView {
         else return opaque(L.nbin);
     }
     __device__ __forceinline__ int kind(int b) const {
-        if constexpr (SIG != 0) return int((SIG >> (4 + 10 * b)) & 3);
+        if constexpr (SIG != 0) return int((SIG >> (4 + kCodeBits * b)) & 3);
         else return opaque(L.b[b].kind);
     }
     __device__ __forceinline__ int nmom(int b) const {
-        if constexpr (SIG != 0) return int((SIG >> (6 + 10 * b)) & 3);
+        if constexpr (SIG != 0) return int((SIG >> (6 + kCodeBits * b)) & 3);
         else return opaque(L.b[b].nmom);
     }
     __device__ __forceinline__ int mom(int b) const {
-        if constexpr (SIG != 0) return int((SIG >> (8 + 10 * b)) & 63);
+        if constexpr (SIG != 0) return int((SIG >> (8 + kCodeBits * b)) & 511);
         else return opaque(L.b[b].mom);
+    }
+    // does any binning list a Gauss-Hermite moment (code >= 3)?
+    __device__ __forceinline__ bool has_gh() const {
+        if constexpr (SIG != 0) return false;   // (the compiled signatures list none)
+        else return opaque(L.has_gh) != 0;
     }
 };
 
@@ -128,6 +141,7 @@ struct Exact {
     const double* erange;     // Emin, Emax per model
     const double* edges;      // edge values
     const float* rce;         // kLcE values ln r_c(E_k) per model: Newton seeds (FP32 path)
+    const float* gh;          // Gauss-Hermite table: (V, 1/sigma) per bin of each GH binning (FP32)
     double cosd, sind;
     double x0d[kMaxBin], wxd[kMaxBin], y0d[kMaxBin], wyd[kMaxBin];
 };
@@ -542,6 +556,33 @@ __device__ __forceinline__ double line_of_sight(double vy, double vz, double sin
 template <typename T>
 __device__ __forceinline__ T moment_value(int mo, T vl) {
     return mo == 0 ? T(1) : (mo == 1 ? vl : vl * vl);
+}
+
+// Gauss-Hermite kernel (section 1: absorption-line kinematics; the LOSVD of a
+// bin expanded about its Gaussian (V, sigma) as in van der Marel & Franx 1993):
+// 2 sqrt(pi) alpha(nu) H_m(nu) = sqrt(2) exp(-nu^2/2) H_m(nu), nu = (v - V)/sigma,
+// for m = code - 2 = 1..4, with the normalised Hermite polynomials written out:
+//   m = 1: 2 nu,  m = 2: 2 nu^2 - 1,  m = 3: sqrt(2/3) (2 nu^3 - 3 nu),
+//   m = 4: (4 nu^4 - 12 nu^2 + 3) / sqrt(12)   (each times exp(-nu^2/2)).
+// gv: the bin's (V, 1/sigma).
+template <typename T>
+__device__ __forceinline__ T gh_value(int code, T vl, T V, T isig) {
+    const T nu = (vl - V) * isig, n2 = nu * nu;
+    const T e = qexp(T(-0.5) * n2);
+    T p;
+    if (code == 3) p = T(2) * nu;
+    else if (code == 4) p = T(2) * n2 - T(1);
+    else if (code == 5) p = T(0.816496580927726033) * nu * (T(2) * n2 - T(3));
+    else p = T(0.288675134594812882) * (n2 * (T(4) * n2 - T(12)) + T(3));
+    return p * e;
+}
+
+// Kernel value of any moment code; (V, 1/sigma) of the bin from gv (read only
+// for the Gauss-Hermite codes).
+template <typename T>
+__device__ __forceinline__ T kernel_value(int code, T vl, const T* gv) {
+    if (code <= 2) return moment_value<T>(code, vl);
+    return gh_value<T>(code, vl, gv[0], gv[1]);
 }
 
 }  // namespace m2m

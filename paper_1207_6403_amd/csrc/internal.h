@@ -39,6 +39,8 @@ struct m2m_ctx {
     m2m_prior prior{};
     m2m_obs_layout lay{};
     std::vector<double> edges_host[M2M_MAX_BINNINGS];
+    std::vector<double> gh_host[M2M_MAX_BINNINGS];   // Gauss-Hermite V_b then sigma_b (GH binnings)
+    int ngh = 0;                                      // GH bins over all binnings
     std::vector<double> erange_host;
     std::vector<double> erange_user;   // the caller's (Emin, Emax) per model, if given
     std::vector<float> lce_host;   // per model: origin and inverse spacing of the uniform-E tables
@@ -105,6 +107,8 @@ struct m2m_ctx {
     void* cvec = nullptr;
     void* cellmean = nullptr;
     void* edges = nullptr;
+    void* ghtab = nullptr;     // (V, 1/sigma) pairs, particle precision
+    void* ghtab32 = nullptr;   // the same in FP32
     void* scratch_n = nullptr;
     double *Y = nullptr, *sigma = nullptr, *y = nullptr, *ys = nullptr, *delta = nullptr;
     double* cellmean64 = nullptr;

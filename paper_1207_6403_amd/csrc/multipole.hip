@@ -299,6 +299,7 @@ __global__ void __launch_bounds__(sizeof(T) == 8 ? 256 : 1024) mp_kick_drift_ker
             B.wflat = ro(a.flatw, m);
             B.cl = a.cvec + (size_t)m * J;
             B.cm = a.cellmean + (size_t)m * NC;
+            B.gh = a.ghtab;
             __syncthreads();   // (the first: the node table is in place)
         }
         const int64_t p0 = ro(a.tile_p0, t);

@@ -57,6 +57,7 @@ struct Blk {
     const double* ed64; // edges in FP64
     const float2* et;   // uniform-E Lc table (FP32 kernels)
     const T* lct;       // circular-orbit energies (FP64 kernels)
+    const T* gh;        // Gauss-Hermite (V, 1/sigma) pairs of the layout's GH bins
     Pot<T> pot;
     T Emin, sE, wflat;
     CellGuard cg;       // energy-axis guard of the prior cells (FP32 kernels)
@@ -119,16 +120,21 @@ __device__ __forceinline__ void st_at(void* base, uint32_t off, X v) {
 
 // Scatter w * K_j of one particle's bin k of binning b (moments of v_los = vl);
 // when take is false the terms go to the lane's trash slot instead.
+// (Gauss-Hermite moments read the bin's (V, 1/sigma) pair from gh; a particle
+// outside the binning reads pair 0 for a value that goes to the trash slot.)
 template <uint64_t SIG, typename T>
 __device__ __forceinline__ void scatter_bin(const LayoutView<SIG, T>& V, double* hist, int b, int k, bool take,
-                                            int trash, T wn, T vl) {
+                                            int trash, T wn, T vl, const T* gh) {
     const BinDesc<T>& d = V.L.b[b];
     const int base = d.off + k;
     const int nmom = V.nmom(b), mom = V.mom(b);
+    const T* gv = gh + 2 * (d.gh0 + (k < 0 ? 0 : k));
     #pragma unroll
     for (int mm = 0; mm < 3; ++mm) {
         if (mm >= nmom) break;
-        atomicAdd(&hist[take ? base + mm * d.nb : trash], double(wn * moment_value<T>((mom >> (2 * mm)) & 3, vl)));
+        const int code = (mom >> (kMomBits * mm)) & 7;
+        const T kv = V.has_gh() ? kernel_value<T>(code, vl, gv) : moment_value<T>(code, vl);
+        atomicAdd(&hist[take ? base + mm * d.nb : trash], double(wn * kv));
     }
 }
 
@@ -155,11 +161,14 @@ __device__ __forceinline__ T weight_update(const StepArgs<T, PT>& a, const Blk<T
         }
         const int base = L.b[b].off + k;
         const int nmom = V.nmom(b), mom = V.mom(b);
+        const T* gv = B.gh + 2 * (L.b[b].gh0 + (k == kNoBin ? 0 : k));
         #pragma unroll
         for (int mm = 0; mm < 3; ++mm) {
             if (mm >= nmom) break;
             const int j = (ZSLOT >= 0 && k == kNoBin) ? zslot : base + mm * L.b[b].nb;
-            chi += moment_value<T>((mom >> (2 * mm)) & 3, vl) * B.cl[j];
+            const int code = (mom >> (kMomBits * mm)) & 7;
+            const T kv = V.has_gh() ? kernel_value<T>(code, vl, gv) : moment_value<T>(code, vl);
+            chi += kv * B.cl[j];
         }
     }
     const uint32_t wm = (fl >> kWhatShift) & 3u;

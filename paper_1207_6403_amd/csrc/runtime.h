@@ -65,6 +65,7 @@ struct StepArgs {
     double* seg_stats;            // nslot * 4: (S, sum w, sum w^2, min w) per partial slot
     const T* edges;
     const double* edges64;        // the same edges in FP64
+    const T* ghtab;               // Gauss-Hermite (V, 1/sigma) pairs (lay.ngh of them)
     int32_t nedge;
     int32_t pcols, jpad;
     Layout<T> lay;

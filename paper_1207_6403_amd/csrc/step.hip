@@ -88,7 +88,7 @@ __device__ __forceinline__ unsigned particle_step(const StepArgs<T, PT>& a, cons
             take = k >= 0;
         }
         st_at<uint16_t>(a.out, ot + b * (rb / uint32_t(sizeof(T)) * 2u), k < 0 ? kNoBin : (uint16_t)k);
-        scatter_bin(V, B.hist, b, k, take, a.jpad + lane, wn, vl);
+        scatter_bin(V, B.hist, b, k, take, a.jpad + lane, wn, vl, B.gh);
     }
     int cell = 0;
     if (fl & kAccum) {
@@ -145,8 +145,10 @@ __device__ __noinline__ void fix_one(cExact* ex, int m, unsigned open, int64_t p
         tags[b * stride + p] = k < 0 ? kNoBin : (uint16_t)k;
         if (k < 0) continue;
         const int base = ex->lay.b[b].off + k, mom = ex->lay.b[b].mom;
+        const float* gv = ex->gh + 2 * (ex->lay.b[b].gh0 + k);
         for (int mm = 0; mm < ex->lay.b[b].nmom; ++mm)
-            __hip_atomic_fetch_add(&hist[base + mm * nb], double(wn * moment_value<float>((mom >> (2 * mm)) & 3, vl)),
+            __hip_atomic_fetch_add(&hist[base + mm * nb],
+                                   double(wn * kernel_value<float>((mom >> (kMomBits * mm)) & 7, vl, gv)),
                                    __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     }
     const unsigned am = (open >> NB) & 7u;
@@ -220,8 +222,10 @@ __global__ void __launch_bounds__(sizeof(T) == 8 ? 256 : 1024) step_kernel(StepA
     T* lct = ed + NE;                                                // circular-orbit energies (FP64)
     float2* etl = reinterpret_cast<float2*>(lct + kLcTab);           // uniform-E Lc table (FP32, with cells)
     uint2* fq = reinterpret_cast<uint2*>(etl + (F32 && NC ? kLcE : 0));  // per wave: kFixQ open decisions (FP32)
+    T* ghl = reinterpret_cast<T*>(fq + (F32 ? kFixQ * (blockDim.x >> 6) : 0));   // Gauss-Hermite (V, 1/sigma) pairs
 
     for (int i = tid; i < a.nedge; i += nt) { ed[i] = a.edges[i]; ed64[i] = a.edges64[i]; }
+    for (int i = tid; i < 2 * a.lay.ngh; i += nt) ghl[i] = a.ghtab[i];
 
     const uint32_t fl = MODE == 1 ? kHotFlags : (MODE == 2 ? kObsCells : a.flags);
     const uint32_t wm = (fl >> kWhatShift) & 3u;
@@ -231,6 +235,7 @@ __global__ void __launch_bounds__(sizeof(T) == 8 ? 256 : 1024) step_kernel(StepA
     Blk<T> B;
     B.hist = hist; B.csum = csum; B.ccnt = ccnt; B.cl = cl; B.cm = cm; B.ed = ed; B.ed64 = ed64;
     B.lct = lct;
+    B.gh = ghl;
     Acc acc;
 
     // Work is handed out per wave in chunks of CH = 64 ILP particles of the

@@ -96,6 +96,49 @@ def cfg4(n_models=64, nmin=100_000, nmax=2_000_000, steps=3000):
             "target": {"kind": "hernquist_om", "ra": 1.0, "noise": 0.05, "seed_cfg": 1}}
 
 
+def layout_cfg2_gh():
+    """The cfg 2 layout plus the kinematic grid again with the Gauss-Hermite moments
+    h3 and h4 (integral-field kinematics); the bins' Gaussians (V_b, sigma_b) come
+    from the target (filled in by make_inputs)."""
+    lay = layout_cfg2()
+    kin = dict(lay["binnings"][1])
+    kin.update(moments=(5, 6), gh=None)
+    lay["binnings"].append(kin)
+    return lay
+
+
+def cfg2gh(N=1 << 20, steps=5000, target_n=1 << 23):
+    """Log-potential model fitted to surface density, v, v^2 and Gauss-Hermite h3,
+    h4 of a rotating target (errors 3% on density and velocities, 0.01 on h_m)."""
+    c = cfg2(N, steps, target_n)
+    c.update({"name": "log_gh_fp32_N%d" % N, "index": 6, "layout": layout_cfg2_gh()})
+    c["target"] = dict(c["target"], noise_gh=0.01, seed_cfg=2)
+    return c
+
+
+def layout_fig1():
+    """The cfg 1 shells, and the annuli with the second moment and the
+    Gauss-Hermite h3, h4 about the target's own dispersion (V_b = 0: non-rotating)."""
+    lay = layout_cfg1()
+    lay["binnings"][1] = dict(lay["binnings"][1], moments=(2, 5, 6), gh=None, gh_zero_mean=True)
+    return lay
+
+
+def cfg_fig1(N=20000, steps=2000, ics="isotropic", target_n=1 << 22, precision="f64"):
+    """The convergence experiment of the paper's Fig. 1: the cfg 1 model (Hernquist
+    potential, moving (E, L/Lc) priors) fitted to idealised line-of-sight data of
+    an Osipkov-Merritt r_a = 1 target -- shell masses, and per annulus v^2, h3 and
+    h4 -- from a realisation of target_n particles with errors of 1% (masses,
+    dispersions) and 0.005 (h_m), no noise drawn; initial particle models
+    'isotropic', 'radial' (Osipkov-Merritt r_a = 0.6) or 'tangential' (beta = -1/2)."""
+    c = cfg1(N, steps)
+    c.update({"name": "fig1_%s_N%d" % (ics, N), "index": 7, "layout": layout_fig1(), "precision": precision,
+              "ics": ics})
+    c["target"] = {"kind": "hernquist_om_realisation", "ra": 1.0, "n": target_n, "noise": 0.01,
+                   "noise_gh": 0.005, "draw": False}
+    return c
+
+
 def mlp_init(seed):
     """Initial parameters of the 3-64-64-1 prior network (FP32): weights normal
     with variance 1/fan-in, biases zero; W1[64,3], b1, W2[64,64], b2, W3[1,64], b3."""
@@ -132,12 +175,22 @@ LOG_MASS_R10 = 9.999142073415042
 _TARGET_CACHE = {}
 
 
+def _layout_key(lay):
+    return repr({"incl": lay["incl"], "binnings": [{k: v for k, v in b.items() if k != "gh"}
+                                                   for b in lay["binnings"]]})
+
+
 def cached_target(cfg):
-    """make_target(cfg), memoised on the target recipe and the layout."""
-    key = (cfg["index"], repr(cfg["target"]), repr(cfg["layout"]))
+    """make_target(cfg), memoised on the target recipe and the layout (with the
+    Gauss-Hermite parameters it fills into the layout)."""
+    key = (cfg["index"], repr(cfg["target"]), _layout_key(cfg["layout"]))
     if key not in _TARGET_CACHE:
         _TARGET_CACHE[key] = make_target(cfg)
-    return _TARGET_CACHE[key]
+    Y, sigma, gh = _TARGET_CACHE[key]
+    for b, g in zip(cfg["layout"]["binnings"], gh):
+        if g is not None:
+            b["gh"] = g
+    return Y, sigma
 
 
 def make_inputs(cfg, dtype=np.float64, cache_target=True):
@@ -154,25 +207,53 @@ def make_inputs(cfg, dtype=np.float64, cache_target=True):
         ics = np.concatenate(parts, axis=1)
         w = np.concatenate(ws)
     elif pot["kind"] == "hernquist":
-        ics = galaxy.hernquist_isotropic_ics(cfg["N"], seed, pot["G"], pot["M"], pot["a"])
+        kind = cfg.get("ics", "isotropic")
+        if kind == "isotropic":
+            ics = galaxy.hernquist_isotropic_ics(cfg["N"], seed, pot["G"], pot["M"], pot["a"])
+        elif kind == "radial":
+            ics = galaxy.hernquist_om_ics(cfg["N"], seed + 3, 0.6)
+        elif kind == "tangential":
+            ics = galaxy.hernquist_tangential_ics(cfg["N"], seed + 4)
+        else:
+            raise ValueError("unknown initial model %r" % kind)
         w = np.full(cfg["N"], 1.0 / cfg["N"])
     else:
         lp = LOG_POT
         ics = galaxy.log_isotropic_ics(cfg["N"], seed, lp["v0"], lp["Rc"], lp["q"])
         w = np.full(cfg["N"], 1.0 / cfg["N"])
-    Y, sigma = cached_target(cfg) if cache_target else make_target(cfg)
+    if cache_target:
+        Y, sigma = cached_target(cfg)
+    else:
+        Y, sigma, gh = make_target(cfg)
+        for b, g in zip(cfg["layout"]["binnings"], gh):
+            if g is not None:
+                b["gh"] = g
     return {"ics": ics.astype(dtype), "w": w.astype(dtype), "Y": Y.copy(), "sigma": sigma.copy()}
 
 
 def make_target(cfg):
+    """(Y, sigma, gh): the noisy target and, per binning, the Gauss-Hermite
+    parameters (V_b, sigma_b) measured from the target (None for binnings without
+    Gauss-Hermite moments)."""
     t = cfg["target"]
     lay = cfg["layout"]
     sidx = t.get("seed_cfg", cfg["index"])
+    gh = [None] * len(lay["binnings"])
     if t["kind"] == "hernquist_om":
         Yt, Mb = targets.hernquist_om_target(lay, ra=t["ra"])
     else:
-        lp = LOG_POT
-        real = galaxy.log_isotropic_ics(t["n"], seed_for(sidx, 5), lp["v0"], lp["Rc"], lp["q"])
-        real = galaxy.make_rotating(real, t["rot_frac"], seed_for(sidx, 6))
+        if t["kind"] == "hernquist_om_realisation":
+            real = galaxy.hernquist_om_ics(t["n"], seed_for(sidx, 5), t["ra"])
+        else:
+            lp = LOG_POT
+            real = galaxy.log_isotropic_ics(t["n"], seed_for(sidx, 5), lp["v0"], lp["Rc"], lp["q"])
+            real = galaxy.make_rotating(real, t["rot_frac"], seed_for(sidx, 6))
+        for ib, b in enumerate(lay["binnings"]):
+            if any(m >= 3 for m in b["moments"]):
+                gh[ib] = targets.gh_parameters(b, real, lay["incl"], zero_mean=b.get("gh_zero_mean", False))
+                b["gh"] = gh[ib]
         Yt, Mb = targets.observe_realisation(lay, real, 1.0 / t["n"])
-    return targets.add_noise(lay, Yt, Mb, t["noise"], seed_for(sidx, 1))
+    Y, sigma = targets.add_noise(lay, Yt, Mb, t["noise"], seed_for(sidx, 1), f_gh=t.get("noise_gh"))
+    if not t.get("draw", True):
+        Y = Yt   # idealised data: the errors are given, no noise is drawn
+    return Y, sigma, gh

@@ -14,8 +14,12 @@ and then perturbed once by Gaussian noise of relative size f.
 A "layout" is a dict: ``incl`` (radians) and a list ``binnings``; each binning is
 one of ``{"kind": "shell", "edges": ...}``, ``{"kind": "annulus", "edges": ...}`` or
 ``{"kind": "grid", "nx", "ny", "x0", "x1", "y0", "y1"}`` and carries ``moments``, a
-tuple drawn from (0, 1, 2): mass, sum of w*v_los, sum of w*v_los^2.  Observable j
-runs over binnings in order, then over the listed moments, then over bins.
+tuple drawn from (0, 1, 2): mass, sum of w*v_los, sum of w*v_los^2, and 3..6: the
+Gauss-Hermite moments h1..h4 of the line-of-sight velocity distribution about the
+Gaussian (V_b, sigma_b) of each bin, which such a binning carries as ``gh``
+(array [2, nb]: V_b, sigma_b; measured from the target, as an observer's
+Gaussian fit would be).  Observable j runs over binnings in order, then over the
+listed moments, then over bins.
 """
 import numpy as np
 
@@ -137,6 +141,46 @@ def hernquist_om_target(layout, ra=1.0, G=1.0, M=1.0, a=1.0):
 
 
 # ----------------------------------------------------------------- realisations
+def _bin_index(b, ics, inc):
+    """Bin of every particle of a realisation in binning b (-1 outside) and nb."""
+    x, y, z = ics[0], ics[1], ics[2]
+    X = x
+    Ysky = y * np.cos(inc) - z * np.sin(inc)
+    if b["kind"] == "grid":
+        ix = np.floor((X - b["x0"]) / (b["x1"] - b["x0"]) * b["nx"]).astype(np.int64)
+        iy = np.floor((Ysky - b["y0"]) / (b["y1"] - b["y0"]) * b["ny"]).astype(np.int64)
+        ok = (ix >= 0) & (ix < b["nx"]) & (iy >= 0) & (iy < b["ny"])
+        return np.where(ok, iy * b["nx"] + ix, -1), b["nx"] * b["ny"]
+    rad = np.sqrt(x * x + y * y + z * z) if b["kind"] == "shell" else np.sqrt(X * X + Ysky * Ysky)
+    e = np.asarray(b["edges"])
+    k = np.searchsorted(e, rad, side="right") - 1
+    return np.where((k >= 0) & (k < len(e) - 1), k, -1), len(e) - 1
+
+
+def gh_parameters(b, ics, inc, zero_mean=False):
+    """The Gaussian each bin's line-of-sight velocities are expanded about: the
+    mass-weighted mean V_b (0 when zero_mean) and dispersion sigma_b of the
+    realisation's v_los in the bin; [2, nb]."""
+    vlos = ics[4] * np.sin(inc) + ics[5] * np.cos(inc)
+    k, nb = _bin_index(b, ics, inc)
+    ok = k >= 0
+    n = np.maximum(np.bincount(k[ok], minlength=nb), 1)
+    m1 = np.bincount(k[ok], weights=vlos[ok], minlength=nb) / n
+    m2 = np.bincount(k[ok], weights=vlos[ok] ** 2, minlength=nb) / n
+    V = np.zeros(nb) if zero_mean else m1
+    sig = np.sqrt(np.maximum(m2 - V * V, 1e-12))
+    return np.stack([V, sig])
+
+
+def gauss_hermite_kernel(m, nu):
+    """2 sqrt(pi) alpha(nu) H_m(nu) of the van der Marel & Franx expansion, m = 1..4
+    (alpha = exp(-nu^2/2)/sqrt(2 pi); H_1 = sqrt(2) nu, H_2 = (2 nu^2 - 1)/sqrt(2),
+    H_3 = (2 nu^3 - 3 nu)/sqrt(3), H_4 = (4 nu^4 - 12 nu^2 + 3)/sqrt(24))."""
+    h = {1: np.sqrt(2.0) * nu, 2: (2 * nu ** 2 - 1) / np.sqrt(2.0), 3: (2 * nu ** 3 - 3 * nu) / np.sqrt(3.0),
+         4: (4 * nu ** 4 - 12 * nu ** 2 + 3) / np.sqrt(24.0)}[m]
+    return np.sqrt(2.0) * np.exp(-0.5 * nu * nu) * h
+
+
 def observe_realisation(layout, ics, mass):
     """Observe a particle realisation of the target galaxy (equal masses) on the
     layout's bins.  Returns (Y_true, M_b) where M_b is the binned mass that goes with
@@ -164,18 +208,24 @@ def observe_realisation(layout, ics, mass):
         vv = vlos[ok]
         mass_b = np.bincount(idx, minlength=nb) * mass
         for m in b["moments"]:
-            w = mass * vv ** m
+            if m <= 2:
+                w = mass * vv ** m
+            else:
+                gh = np.asarray(b["gh"])
+                w = mass * gauss_hermite_kernel(m - 2, (vv - gh[0][idx]) / gh[1][idx])
             out.append(np.bincount(idx, weights=w, minlength=nb))
             mb.append(mass_b)
     return np.concatenate(out), np.concatenate(mb)
 
 
 # ------------------------------------------------------------------------ noise
-def add_noise(layout, Y_true, M_b, f, seed):
+def add_noise(layout, Y_true, M_b, f, seed, f_gh=None):
     """One fixed Gaussian noise draw.  Mass-type observables: sigma = f |Y|;
     first moments: sigma = f sqrt(M_b Y2) (f on the rms LOS velocity);
-    second moments: sigma = 2 f Y2 (f on the dispersion).  Zero errors (empty bins)
-    are raised to the smallest positive error of the same group."""
+    second moments: sigma = 2 f Y2 (f on the dispersion); Gauss-Hermite moments:
+    sigma = f_gh M_b (an error f_gh on h_m; f_gh = f when not given).  Zero errors
+    (empty bins) are raised to the smallest positive error of the same group."""
+    f_gh = f if f_gh is None else f_gh
     rng = np.random.default_rng(seed)
     kinds = observable_kinds(layout)
     moment = np.array([k[0] for k in kinds])
@@ -196,8 +246,10 @@ def add_noise(layout, Y_true, M_b, f, seed):
                 if y2 is None:
                     raise ValueError("first moment needs the second moment in the same binning")
                 sigma[sl] = f * np.sqrt(np.maximum(M_b[sl] * y2, 0.0))
-            else:
+            elif m == 2:
                 sigma[sl] = 2.0 * f * np.abs(Y_true[sl])
+            else:
+                sigma[sl] = f_gh * M_b[sl]
             s = sigma[sl]
             pos = s[s > 0]
             floor = pos.min() if pos.size else 1.0

@@ -111,7 +111,8 @@ def moment_scale(cfg, ics, w):
         nb = len(b["edges"]) - 1 if b["kind"] != "grid" else b["nx"] * b["ny"]
         mom = list(b["moments"])
         # mass of the binning (moment 0 needs to be computed even if not fitted)
-        lay1 = {"incl": layout["incl"], "binnings": [dict(b, moments=(0, 2))]}
+        lay1 = {"incl": layout["incl"], "binnings": [{k: v for k, v in dict(b, moments=(0, 2)).items()
+                                                      if k not in ("gh", "gh_zero_mean")}]}
         c1 = dict(cfg, layout=lay1, prior={"kind": "flat"})
         mm = oracle.Model(c1, ics.astype(np.float64), np.abs(w).astype(np.float64), np.zeros(2 * nb), np.ones(2 * nb))
         y = mm.observe()
@@ -119,5 +120,8 @@ def moment_scale(cfg, ics, w):
         for k, mo in enumerate(mom):
             if mo == 1:
                 out[start + k * nb:start + (k + 1) * nb] = np.sqrt(M_b * Y2)
+            elif mo >= 3:
+                # Gauss-Hermite kernels: |sqrt(2) exp(-nu^2/2) H_m(nu)| < 1.5
+                out[start + k * nb:start + (k + 1) * nb] = 1.5 * M_b
         start += len(mom) * nb
     return out

@@ -34,7 +34,7 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_abi_version():
-    assert b.m2m_abi_version() == 1
+    assert b.m2m_abi_version() == 2
 
 
 def test_struct_layouts_match_header(tmp_path):
