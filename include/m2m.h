@@ -295,6 +295,21 @@ m2m_status m2m_history(m2m_ctx *ctx, m2m_step_stats *out, int64_t max_rows, int6
  * tie).  Host outputs, each nullable.  INVALID when no step has been taken. */
 m2m_status m2m_delta_chi2(m2m_ctx *ctx, double *chi2, double *delta, int32_t *best);
 
+/* Paper section 3, Fig. 1: the anisotropy profile a fit recovers for a
+ * spherical target.  Velocity second moments of model `model`'s weighted
+ * particles in the current state, in spherical shells [edges[k], edges[k+1])
+ * of r = |x| about the origin: out (host, 4 * nshell FP64 values, row-major)
+ * gets, per shell, sum w, sum w v_r^2, sum w v_theta^2 and sum w v_phi^2
+ * (spherical components about the z axis; v_phi = 0 on the axis).  Particles
+ * outside every shell add nothing.  Then beta(r) = 1 - (row 2 + row 3) /
+ * (2 row 1).  edges: nshell + 1 strictly increasing finite radii, edges[0] > 0
+ * (host, copied); 1 <= nshell <= M2M_SHELL_MAX.  Sums in FP64 on the GPU, in
+ * a fixed block order (the order of additions inside a block varies, so the
+ * last bits may differ between calls).  Synchronises the context's stream.
+ * INVALID for a bad model index, edges or nshell. */
+#define M2M_SHELL_MAX 256
+m2m_status m2m_shell_moments(m2m_ctx *ctx, int32_t model, const double *edges, int32_t nshell, double *out);
+
 /* Node coefficients of a MULTIPOLE model (sections 1 and 2: the potential
  * computed from the particles), as used by the first kick of the next step:
  * A and B, nnode * (lmax+1)^2 FP64 values each (host; node k at k*(lmax+1)^2,

@@ -360,6 +360,40 @@ def leapfrog(pot, ics, nsteps, dt):
     return np.stack(a)
 
 
+def shell_moments(ics, w, edges):
+    """Section 3, Fig. 1: the anisotropy recovered for a spherical target.  Per
+    spherical shell [edges[k], edges[k+1]) of r = |x|: sum w, and sum w v_c^2 for
+    the spherical velocity components c = r, theta, phi (unit vectors e_r = x/r,
+    e_phi = z_hat x e_r / |z_hat x e_r|, e_theta = e_phi x e_r; v_phi = 0 and
+    v_theta^2 = |v|^2 - v_r^2 on the z axis).  Returns [4, nshell]."""
+    ics = np.asarray(ics, dtype=np.float64)
+    w = np.asarray(w, dtype=np.float64)
+    edges = np.asarray(edges, dtype=np.float64)
+    ns = edges.size - 1
+    out = np.zeros((4, ns))
+    for i in range(ics.shape[1]):
+        x = ics[:3, i]
+        v = ics[3:, i]
+        r = np.linalg.norm(x)
+        k = int(np.searchsorted(edges, r, side="right")) - 1
+        if k < 0 or k >= ns:
+            continue
+        er = x / r
+        ephi = np.cross([0.0, 0.0, 1.0], er)
+        n = np.linalg.norm(ephi)
+        vr = v @ er
+        if n > 0.0:
+            ephi /= n
+            vphi = v @ ephi
+            vth = v @ np.cross(ephi, er)
+            vth2 = vth * vth
+        else:
+            vphi = 0.0
+            vth2 = v @ v - vr * vr
+        out[:, k] += w[i] * np.array([1.0, vr * vr, vth2, vphi * vphi])
+    return out
+
+
 def legendre(lmax, x):
     P = np.zeros((lmax + 1) * (lmax + 1))
     lib().or_legendre(lmax, float(x), _dp(P))

@@ -108,6 +108,7 @@ def lib():
         L.m2m_history.argtypes = [CTX, C.POINTER(m2m_step_stats), C.c_int64, C.POINTER(C.c_int64)]
         L.m2m_multipole_tables.argtypes = [CTX, C.POINTER(C.c_double), C.POINTER(C.c_double)]
         L.m2m_delta_chi2.argtypes = [CTX, C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_int32)]
+        L.m2m_shell_moments.argtypes = [CTX, C.c_int32, C.POINTER(C.c_double), C.c_int32, C.POINTER(C.c_double)]
         L.m2m_mlp_state.argtypes = [CTX, C.POINTER(C.c_float), C.POINTER(C.c_double), C.POINTER(C.c_int32),
                                     C.POINTER(C.c_int64)]
         L.m2m_mlp_loss_grad.argtypes = [CTX, C.POINTER(C.c_float), C.POINTER(C.c_float), C.c_int32,
@@ -122,7 +123,7 @@ def lib():
         L.m2m_last_error.argtypes = [CTX]
         L.m2m_last_error.restype = C.c_char_p
         for f in ("m2m_create", "m2m_step", "m2m_observables", "m2m_weights", "m2m_priors", "m2m_particles",
-                  "m2m_history", "m2m_multipole_tables", "m2m_delta_chi2", "m2m_mlp_state", "m2m_mlp_loss_grad", "m2m_mlp_loss_grad_noalloc", "m2m_autotune", "m2m_get_launch", "m2m_set_launch", "m2m_kernel_time"):
+                  "m2m_history", "m2m_multipole_tables", "m2m_delta_chi2", "m2m_shell_moments", "m2m_mlp_state", "m2m_mlp_loss_grad", "m2m_mlp_loss_grad_noalloc", "m2m_autotune", "m2m_get_launch", "m2m_set_launch", "m2m_kernel_time"):
             getattr(L, f).restype = C.c_int
         if L.m2m_abi_version() != ABI_VERSION:
             raise ImportError("libm2m_hip.so ABI %d, binding expects %d" % (L.m2m_abi_version(), ABI_VERSION))
@@ -374,6 +375,23 @@ def m2m_delta_chi2(ctx):
     best = C.c_int32()
     _check(lib().m2m_delta_chi2(ctx.ptr, _dp(chi2), _dp(delta), C.byref(best)), ctx)
     return chi2, delta, best.value
+
+
+def m2m_shell_moments(ctx, edges, model=0):
+    """Velocity second moments of a model's weighted particles in spherical shells
+    [edges[k], edges[k+1]): array [4, nshell] of sum w, sum w v_r^2,
+    sum w v_theta^2, sum w v_phi^2."""
+    e = np.ascontiguousarray(edges, dtype=np.float64)
+    ns = e.size - 1
+    out = np.zeros(4 * max(ns, 0))
+    _check(lib().m2m_shell_moments(ctx.ptr, int(model), _dp(e), int(ns), _dp(out)), ctx)
+    return out.reshape(4, ns)
+
+
+def anisotropy(moments):
+    """beta = 1 - (sum w v_theta^2 + sum w v_phi^2) / (2 sum w v_r^2) per shell, from
+    m2m_shell_moments (second moments about zero: a non-rotating model)."""
+    return 1.0 - (moments[2] + moments[3]) / (2.0 * moments[1])
 
 
 def m2m_multipole_tables(ctx, nnode, lmax):

@@ -1473,6 +1473,36 @@ extern "C" m2m_status m2m_delta_chi2(m2m_ctx* c, double* chi2, double* delta, in
     return M2M_OK;
 }
 
+// ------------------------------------------------------------ shell moments
+extern "C" m2m_status m2m_shell_moments(m2m_ctx* c, int32_t model, const double* edges, int32_t nshell, double* out) {
+    if (!c) return fail(nullptr, M2M_ERR_INVALID, "ctx is NULL");
+    if (!edges || !out) return fail(c, M2M_ERR_INVALID, "null argument");
+    if (model < 0 || model >= c->M) return fail(c, M2M_ERR_INVALID, "model index out of range");
+    if (nshell < 1 || nshell > kShellMax) return fail(c, M2M_ERR_INVALID, "nshell must be in [1, 256]");
+    if (!(edges[0] > 0.0) || !is_fin(edges[nshell])) return fail(c, M2M_ERR_INVALID, "edges must be finite and > 0");
+    for (int k = 0; k < nshell; ++k)
+        if (!(edges[k + 1] > edges[k])) return fail(c, M2M_ERR_INVALID, "edges must increase strictly");
+    if (c->status == M2M_ERR_DEVICE) return c->status;
+    const size_t npart = (size_t)kShellBlocks * 4 * kShellMax;
+    if (!c->shell_buf)
+        if (m2m_status s = dalloc(c, &c->shell_buf, npart + (kShellMax + 1) + 4 * kShellMax)) return s;
+    double* d_edges = c->shell_buf + npart;
+    double* d_out = d_edges + (kShellMax + 1);
+    HIPCHK(c, hipMemcpyAsync(d_edges, edges, sizeof(double) * (nshell + 1), hipMemcpyHostToDevice, c->stream));
+    const int64_t p0 = c->off[model], p1 = c->off[model + 1];
+    const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(kShellBlocks, (p1 - p0 + kShellThreads - 1) / kShellThreads));
+    if (c->prec == M2M_F64) {
+        ShellArgs<double> a{(const double*)c->state[c->step & 1], c->stride, p0, p1, d_edges, nshell, c->shell_buf};
+        HIPCHK(c, launch_shell_moments<double>(a, blocks, d_out, c->stream));
+    } else {
+        ShellArgs<float> a{(const float*)c->state[c->step & 1], c->stride, p0, p1, d_edges, nshell, c->shell_buf};
+        HIPCHK(c, launch_shell_moments<float>(a, blocks, d_out, c->stream));
+    }
+    HIPCHK(c, hipMemcpyAsync(out, d_out, sizeof(double) * 4 * nshell, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return M2M_OK;
+}
+
 // --------------------------------------------------------- multipole tables
 extern "C" m2m_status m2m_multipole_tables(m2m_ctx* c, double* A, double* B) {
     if (!c || !A || !B) return fail(c, M2M_ERR_INVALID, "null argument");

@@ -132,4 +132,22 @@ hipError_t launch_mp_build(const MpArgs<T>& mp, int blocks, const MpLds& lds, hi
 template <typename T, typename PT>
 hipError_t set_mp_lds_limit(size_t lds);
 
+// Velocity second moments in spherical shells of the particles [p0, p1) of a
+// state buffer (moments.hip): per block, nshell sums each of w, w v_r^2,
+// w v_theta^2 and w v_phi^2 into its row of `part` (blocks x 4 nshell), then
+// their sum in block order into `out` (device, 4 x nshell).
+constexpr int kShellThreads = 256;
+constexpr int kShellMax = 256;
+constexpr int kShellBlocks = 512;
+template <typename T>
+struct ShellArgs {
+    const T* state;
+    int64_t stride, p0, p1;
+    const double* edges;   // nshell + 1 increasing radii
+    int32_t nshell;
+    double* part;
+};
+template <typename T>
+hipError_t launch_shell_moments(const ShellArgs<T>& a, int blocks, double* out, hipStream_t s);
+
 }  // namespace m2m

@@ -110,6 +110,7 @@ struct m2m_ctx {
     void* ghtab = nullptr;     // (V, 1/sigma) pairs, particle precision
     void* ghtab32 = nullptr;   // the same in FP32
     void* scratch_n = nullptr;
+    double* shell_buf = nullptr;   // shell moments: block partials, edges, sums (allocated at first use)
     double *Y = nullptr, *sigma = nullptr, *y = nullptr, *ys = nullptr, *delta = nullptr;
     double* cellmean64 = nullptr;
     // finalise column chunks (launch-shape independent) and chi^2 shares

@@ -124,18 +124,35 @@ def layout_fig1():
     return lay
 
 
-def cfg_fig1(N=20000, steps=2000, ics="isotropic", target_n=1 << 22, precision="f64"):
+def cfg_fig1(N=20000, steps=2000, ics="isotropic", target_n=None, precision="f64", noise=0.01, noise_gh=0.005):
     """The convergence experiment of the paper's Fig. 1: the cfg 1 model (Hernquist
     potential, moving (E, L/Lc) priors) fitted to idealised line-of-sight data of
     an Osipkov-Merritt r_a = 1 target -- shell masses, and per annulus v^2, h3 and
-    h4 -- from a realisation of target_n particles with errors of 1% (masses,
-    dispersions) and 0.005 (h_m), no noise drawn; initial particle models
-    'isotropic', 'radial' (Osipkov-Merritt r_a = 0.6) or 'tangential' (beta = -1/2)."""
+    h4 -- with errors `noise` (masses, dispersions) and `noise_gh` (h_m), no noise
+    drawn.  The data are the model's exact moments (target_n None) or those of a
+    realisation of target_n particles.  Initial particle models 'isotropic',
+    'radial' (Osipkov-Merritt r_a = 0.6) or 'tangential' (beta = -1/2)."""
     c = cfg1(N, steps)
     c.update({"name": "fig1_%s_N%d" % (ics, N), "index": 7, "layout": layout_fig1(), "precision": precision,
               "ics": ics})
-    c["target"] = {"kind": "hernquist_om_realisation", "ra": 1.0, "n": target_n, "noise": 0.01,
-                   "noise_gh": 0.005, "draw": False}
+    if target_n is None:
+        c["target"] = {"kind": "hernquist_om_exact", "ra": 1.0, "noise": noise, "noise_gh": noise_gh, "draw": False}
+    else:
+        c["target"] = {"kind": "hernquist_om_realisation", "ra": 1.0, "n": target_n, "noise": noise,
+                       "noise_gh": noise_gh, "draw": False}
+    return c
+
+
+def cfg_fig1_run(ics, prior="moving", eps=None):
+    """One fit of the Fig. 1 experiment as run on the GPU: 2^21 particles (FP32) of
+    the initial model `ics`, exact target data with errors 0.3% (masses,
+    dispersions) and 0.0015 (h_m), entropy weight mu = 1e3 with the moving (E,
+    L/Lc) prior or constant priors (prior="flat"), 150,000 steps; eps from
+    EPS_FIG1 (eps dt max|G(0)| = 3) unless given."""
+    c = cfg_fig1(N=1 << 21, steps=150_000, ics=ics, precision="f32", noise=0.003, noise_gh=0.0015)
+    c.update({"name": "fig1_%s_%s" % (ics, prior), "mu": 1e3, "eps": EPS_FIG1[ics] if eps is None else eps})
+    if prior == "flat":
+        c["prior"] = {"kind": "flat"}
     return c
 
 
@@ -167,6 +184,8 @@ EPS_CFG3 = 1.85e-6
 # The 64-model batch shares one rate: the maximum of |G(0)| over its models at
 # their full sizes (1.1e8, from the halo-heavy models' outer shells).
 EPS_CFG4 = 8.98e-8
+# The Fig. 1 runs (cfg_fig1_run), one rate per initial model.
+EPS_FIG1 = {"isotropic": 7.448e-06, "radial": 2.764e-05, "tangential": 6.088e-06}
 # Mass of the truncated (r <= 10) logarithmic-potential density: the self-consistent
 # form weights its particles by w_i * Mtot (galaxy.log_mass_within_sphere()).
 LOG_MASS_R10 = 9.999142073415042
@@ -241,6 +260,8 @@ def make_target(cfg):
     gh = [None] * len(lay["binnings"])
     if t["kind"] == "hernquist_om":
         Yt, Mb = targets.hernquist_om_target(lay, ra=t["ra"])
+    elif t["kind"] == "hernquist_om_exact":
+        Yt, Mb, gh = targets.hernquist_om_exact_target(lay, ra=t["ra"])
     else:
         if t["kind"] == "hernquist_om_realisation":
             real = galaxy.hernquist_om_ics(t["n"], seed_for(sidx, 5), t["ra"])

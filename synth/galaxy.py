@@ -122,10 +122,9 @@ def om_rhoq_pp(psi, ra):
 def om_df_table(ra, n=1200):
     """f(Q) of the Osipkov-Merritt Hernquist model on Q in (0, 1): the Eddington
     integral with Psi = Q - u^2 (dPsi / sqrt(Q - Psi) = 2 du), by adaptive
-    quadrature.  Returns (Q, f) for interpolation in ln(1 - Q)."""
-    lq = np.linspace(np.log(1e-7), np.log(1.0 - 1e-7), n)   # ln(1 - Q) grid, both ends
-    Q = 1.0 - np.exp(lq[::-1])
-    Q = np.concatenate([np.geomspace(1e-7, Q[0], 200, endpoint=False), Q])
+    quadrature.  Returns (Q, f); galaxy.OMDF interpolates ln f in ln Q."""
+    # geometric in Q towards 0 and in 1 - Q towards 1
+    Q = np.concatenate([np.geomspace(1e-7, 0.5, n // 2, endpoint=False), 1.0 - np.geomspace(0.5, 1e-7, n // 2)])
     f = np.empty(Q.size)
     for k, q in enumerate(Q):
         f[k] = integrate.quad(lambda u: 2.0 * om_rhoq_pp(q - u * u, ra), 0.0, np.sqrt(q),

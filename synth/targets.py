@@ -112,6 +112,103 @@ def hernquist_om_annulus_moment2(edges, ra, G=1.0, M=1.0, a=1.0, per_bin=161):
     return out
 
 
+class OMLineOfSight:
+    """Exact line-of-sight kinematics of the Osipkov-Merritt Hernquist model
+    (G = M = a = 1), line of sight along z.
+
+    At a point at radius r the DF is f_Q(Psi - v_r^2/2 - s^2 v_t^2/2) with
+    s^2 = 1 + r^2/r_a^2; in u = (v_r, s v_t) it is isotropic, so the velocity
+    along a unit vector n has the density (1/(s^2 k)) G(Psi - v^2/(2 k^2)), where
+    k^2 = n_r^2 + n_t^2/s^2 and G(q) = 2 pi int_0^q f_Q (the one-dimensional
+    marginal of an isotropic distribution).  By Eddington's formula
+    int_0^q f_Q = (1/(sqrt(8) pi^2)) int_0^q rho_Q'(Psi) dPsi / sqrt(q - Psi), so
+    G(q) = (sqrt(2)/pi) sqrt(q) int_0^1 rho_Q'(q (1 - s^2)) ds needs no f_Q.  An
+    annulus's sum of K(v_los) is the integral over R (Gauss-Legendre in ln R),
+    z = R tan(theta) and t = sqrt(2 Psi) sin(phi) of (1/s^2) K(k t) G(Psi - t^2/2)."""
+
+    def __init__(self, ra, nR=24, ntheta=96, nphi=64, qmax=0.95, ntab=40001):
+        self.ra = ra
+        xs, ws = np.polynomial.legendre.leggauss(64)
+        s = 0.5 * (xs + 1.0)
+        self._q = np.linspace(0.0, qmax, ntab)
+        psi = self._q[:, None] * (1.0 - s[None, :] ** 2)
+        self._G = np.sqrt(2.0) / np.pi * np.sqrt(self._q) * (0.5 * ws[None, :] * self.rhoq_p(psi)).sum(axis=1)
+        self._gl = [np.polynomial.legendre.leggauss(n) for n in (nR, ntheta, nphi)]
+
+    def rhoq_p(self, psi):
+        """d rho_Q / d Psi, rho_Q = [Psi^4/(1 - Psi) + (Psi^2 - Psi^3)/r_a^2] / (2 pi)."""
+        u = 1.0 - psi
+        return ((4.0 * psi ** 3 * u + psi ** 4) / (u * u) + (2.0 * psi - 3.0 * psi ** 2) / self.ra ** 2) / (2.0 * np.pi)
+
+    def G(self, q):
+        return np.interp(q, self._q, self._G)
+
+    def annulus_sums(self, R1, R2, kernels):
+        """[len(kernels)] sums of K(v_los) over the annulus R1 <= R < R2, each kernel
+        a function of v_los (vectorised)."""
+        (xr, wr), (xt, wt), (xp, wp) = self._gl
+        lR = 0.5 * (np.log(R2) - np.log(R1)) * xr + 0.5 * (np.log(R2) + np.log(R1))
+        R = np.exp(lR)[:, None, None]
+        wR = (0.5 * (np.log(R2) - np.log(R1)) * wr * 2.0 * np.pi * np.exp(2 * lR))[:, None, None]
+        th = (0.25 * np.pi * (xt + 1.0))[None, :, None]
+        wth = (0.25 * np.pi * wt)[None, :, None]
+        ph = (0.5 * np.pi * xp)[None, None, :]
+        wph = (0.5 * np.pi * wp)[None, None, :]
+        z = R * np.tan(th)
+        dz = R / np.cos(th) ** 2
+        r = np.sqrt(R * R + z * z)
+        psi = 1.0 / (1.0 + r)
+        s2 = 1.0 + r * r / (self.ra * self.ra)
+        nr2 = (z / r) ** 2
+        k = np.sqrt(nr2 + (1.0 - nr2) / s2)
+        t = np.sqrt(2.0 * psi) * np.sin(ph)
+        base = 2.0 * wR * wth * dz * wph * np.sqrt(2.0 * psi) * np.cos(ph) * self.G(psi * np.cos(ph) ** 2) / s2
+        return np.array([np.sum(base * K(k * t)) for K in kernels])
+
+
+def hernquist_om_exact_target(layout, ra=1.0):
+    """Idealised data of the Osipkov-Merritt Hernquist target (G = M = a = 1, line
+    of sight z): exact shell and annulus masses (closed forms) and, per annulus,
+    the exact sums of v_los, v_los^2 and the Gauss-Hermite kernels about
+    V_b = 0 and sigma_b = the annulus's exact dispersion.  Returns (Y, M_b, gh)
+    with gh per binning ([2, nb] or None); fills b["gh"] of the layout."""
+    los = OMLineOfSight(ra)
+    Y, Mb_list, gh = [], [], []
+    for b in layout["binnings"]:
+        e = np.asarray(b["edges"], dtype=float)
+        nb = len(e) - 1
+        if b["kind"] == "shell":
+            mass = np.diff(galaxy.hernquist_mass(e, 1.0, 1.0))
+            if any(m != 0 for m in b["moments"]):
+                raise ValueError("shells carry masses only")
+            Y += [mass] * len(b["moments"])
+            Mb_list += [mass] * len(b["moments"])
+            gh.append(None)
+            continue
+        if b["kind"] != "annulus":
+            raise ValueError("exact target supports shells and annuli only")
+        mass = np.diff(hernquist_projected_mass(e, 1.0, 1.0))
+        v2 = np.array([los.annulus_sums(e[i], e[i + 1], [lambda v: v * v])[0] for i in range(nb)])
+        sig = np.sqrt(v2 / mass)
+        g = np.stack([np.zeros(nb), sig]) if any(m >= 3 for m in b["moments"]) else None
+        if g is not None:
+            b["gh"] = g
+        gh.append(g)
+        for m in b["moments"]:
+            if m == 0:
+                Y.append(mass)
+            elif m == 1:
+                Y.append(np.zeros(nb))
+            elif m == 2:
+                Y.append(v2)
+            else:
+                Y.append(np.array([los.annulus_sums(e[i], e[i + 1],
+                                                    [lambda v, i=i: gauss_hermite_kernel(m - 2, v / sig[i])])[0]
+                                   for i in range(nb)]))
+            Mb_list.append(mass)
+    return np.concatenate(Y), np.concatenate(Mb_list), gh
+
+
 def hernquist_om_target(layout, ra=1.0, G=1.0, M=1.0, a=1.0):
     """True (noise-free) observables of the OM Hernquist target for a layout made of
     shells (moment 0) and annuli (moment 0 or 2; the mean LOS velocity is zero)."""

@@ -5,7 +5,8 @@ eps * dt * max_i |G_i(0)| = 0.1, where G_i = dF/dw_i with the priors held fixed.
 G_i(0) is read off one oracle step with a negligible rate (w1 = w0 exp(e dt G)).
 The batched workload shares one rate over its 64 models: the maximum is taken over
 all of them at their full sizes.  Calls only the oracle and the input generators;
-prints the values recorded in synth/configs.py (EPS_CFG2, EPS_CFG3, EPS_CFG4).
+prints the values recorded in synth/configs.py (EPS_CFG2, EPS_CFG3, EPS_CFG4, and
+EPS_FIG1 of the Fig. 1 experiment, whose runs take eps dt max|G(0)| = 3).
 
     python tests/golden/derive_eps.py
 """
@@ -44,7 +45,14 @@ def max_abs_G_batched(cfg):
 
 
 if __name__ == "__main__":
-    which = sys.argv[1:] or ["EPS_CFG2", "EPS_CFG3", "EPS_CFG4"]
+    which = sys.argv[1:] or ["EPS_CFG2", "EPS_CFG3", "EPS_CFG4", "EPS_FIG1"]
+    if "EPS_FIG1" in which:
+        which.remove("EPS_FIG1")
+        # the Fig. 1 runs adapt 30 times faster: eps dt max|G(0)| = 3, per initial model
+        for ics in ("isotropic", "radial", "tangential"):
+            c = configs.cfg_fig1_run(ics, eps=1.0)
+            g = max_abs_G(c)
+            print("EPS_FIG1[%r] = %.4e   # max|G(0)| = %.4e" % (ics, float("%.3e" % (3.0 / (c["dt"] * g))), g))
     cases = {"EPS_CFG2": lambda: max_abs_G(configs.cfg2(N=1 << 20)),
              "EPS_CFG3": lambda: max_abs_G(configs.cfg3(N=1 << 20)),
              "EPS_CFG4": lambda: max_abs_G_batched(configs.cfg4())}

@@ -147,3 +147,28 @@ def test_sampled_anisotropy_profiles():
     np.testing.assert_allclose(galaxy.anisotropy_profile(tg, np.ones(n), edges), -0.5, atol=0.04)
     iso = galaxy.hernquist_isotropic_ics(n, 13)
     np.testing.assert_allclose(galaxy.anisotropy_profile(iso, np.ones(n), edges), 0.0, atol=0.04)
+
+
+def test_om_exact_target():
+    """The exact Osipkov-Merritt line-of-sight sums: annulus masses against the
+    closed-form projected mass, annulus v_los^2 against the Jeans quadrature,
+    h3 = 0 by symmetry, and h4 against a 2^20-particle realisation of the DF
+    within 4 standard errors of its shot noise."""
+    los = targets.OMLineOfSight(1.0)
+    e = configs.layout_cfg1()["binnings"][1]["edges"]
+    sums = np.array([los.annulus_sums(e[i], e[i + 1], [lambda v: 1.0 + 0.0 * v, lambda v: v * v])
+                     for i in range(len(e) - 1)])
+    np.testing.assert_allclose(sums[:, 0], np.diff(targets.hernquist_projected_mass(e, 1.0, 1.0)), rtol=1e-5)
+    np.testing.assert_allclose(sums[:, 1], targets.hernquist_om_annulus_moment2(e, 1.0), rtol=2e-5)
+    lay = configs.layout_fig1()
+    Y, Mb, gh = targets.hernquist_om_exact_target(lay, 1.0)
+    nb = len(e) - 1
+    assert np.all(np.abs(Y[30 + nb:30 + 2 * nb]) <= 1e-10 * Mb[30 + nb:30 + 2 * nb])
+    n = 1 << 20
+    real = galaxy.hernquist_om_ics(n, 21, 1.0)
+    k, _ = targets._bin_index(lay["binnings"][1], real, 0.0)
+    ok = k >= 0
+    K = targets.gauss_hermite_kernel(4, real[5, ok] / gh[1][1][k[ok]])
+    h4 = np.bincount(k[ok], weights=K, minlength=nb) / n
+    se = np.sqrt(np.bincount(k[ok], weights=K * K, minlength=nb)) / n
+    assert np.all(np.abs(h4 - Y[30 + 2 * nb:]) <= 4.0 * se + 1e-12), (h4 - Y[30 + 2 * nb:]) / se
