@@ -64,7 +64,7 @@ def measured_traffic(n):
     """HBM bytes per launch of the fused kernel from the committed counter summary
     (FETCH_SIZE + WRITE_SIZE, scaled by the same counters on a plain copy), or None
     when the kernel sources have changed since the counters were taken."""
-    path = os.path.join(ROOT, "profiles", "step_kernel_logpot_N1M_traffic.txt")
+    path = os.path.join(ROOT, "profiles", "step_kernel_logpot_N1M_counters.txt")
     if n != 1 << 20 or not os.path.exists(path):
         return None
     kv = {}
@@ -223,9 +223,11 @@ def main():
     ap.add_argument("--autotune", action="store_true",
                     help="time the candidate launch shapes first (the default shape is the tuned one)")
     ap.add_argument("--graph-steps", type=int, default=100)
+    ap.add_argument("--inputs-cache", default="", metavar="DIR",
+                    help="keep the generated inputs in DIR and reuse them (repeated profiler runs)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
-                    help="only copy MIB MiB device to device 10 times (the reference for the "
-                         "FETCH_SIZE / WRITE_SIZE counters) and exit")
+                    help="only copy MIB MiB device to device 60 times (the reference for the "
+                         "FETCH_SIZE / WRITE_SIZE counters, and its bandwidth at that footprint) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -240,8 +242,15 @@ def main():
         dst = torch.empty_like(src)
         for _ in range(10):
             dst.copy_(src)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(50):
+            dst.copy_(src)
+        e1.record()
         torch.cuda.synchronize()
-        print(json.dumps({"copy_bytes_per_launch": 4 * n, "launches": 10}))
+        ms = e0.elapsed_time(e1) / 50
+        print(json.dumps({"copy_bytes_per_launch": 4 * n, "launches": 60, "ms_per_copy": ms,
+                          "read_plus_write_GBps": 2 * 4 * n / (ms * 1e-3) / 1e9}))
         return
 
     import paper_1207_6403_amd as m2m
@@ -252,8 +261,17 @@ def main():
     cfg = {"logpot": lambda: configs.cfg2(N=args.n), "batched": configs.cfg4, "multipole": configs.cfg3,
            "mlp": configs.cfg5}[wl]()
     cpu_steps = args.cpu_steps or DEFAULT_CPU_STEPS[wl]
-    log("generating inputs (N=%d)" % cfg["N"])
-    inp = configs.make_inputs(cfg, dtype=np.float32)
+    cache = os.path.join(args.inputs_cache, "%s_%d.npz" % (wl, cfg["N"])) if args.inputs_cache else None
+    if cache and os.path.exists(cache):
+        log("loading inputs (N=%d) from %s" % (cfg["N"], cache))
+        with np.load(cache) as z:
+            inp = {k: z[k] for k in ("ics", "w", "Y", "sigma")}
+    else:
+        log("generating inputs (N=%d)" % cfg["N"])
+        inp = configs.make_inputs(cfg, dtype=np.float32)
+        if cache:
+            os.makedirs(args.inputs_cache, exist_ok=True)
+            np.savez(cache, **inp)
     dev = torch.device("cuda:0")
     xv = torch.from_numpy(np.ascontiguousarray(inp["ics"])).to(dev)
     w = torch.from_numpy(np.ascontiguousarray(inp["w"])).to(dev)

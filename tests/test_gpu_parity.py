@@ -1,12 +1,17 @@
 """GPU parity of the fused M2M step (C ABI, HIP path) against the FP64 oracle.
 
-Bars (derived in the design doc):
+Bars:
   FP64 path: every output within 1e-11 relative of the oracle after one step and
              within 1e-8 after 50 steps (rounding order only).
   FP32 path: one step -- weights and coordinates within 1e-6 relative (coordinates
              absolute 1e-6 * scale), observables within 1e-6 of sum |w K| except bins
              explained by particles within 1e-5 of a bin edge, chi^2 within 1e-6
-             relative; end of run -- chi^2 and the binned observables within 1e-3.
+             relative; end of run -- chi^2 within 1e-3, every bin within
+             max(1e-3, 3 x the spread of an oracle run started one FP32 ulp away).
+  Batched FP32 path: weights within max(2e-6, 6e-7 L), L the largest total change
+             of a log-weight over the run (sum over steps of |ln w_n+1 / w_n|): the
+             FP32 update exponent carries a relative error of a few ulp, so each
+             step's error in ln w is ~6e-8 times a small multiple of its change.
 """
 import numpy as np
 import pytest
@@ -14,6 +19,7 @@ import pytest
 import oracle
 from synth import configs
 from tests import helpers as H
+from tests.golden import derive_eps
 
 pytestmark = pytest.mark.gpu
 
@@ -107,26 +113,80 @@ def smoothed_next(cfg, om):
     return ys + g * (om.observe() - ys)
 
 
-def test_cfg2_fp32_end_of_run():
-    """200 steps of N = 2e4: chi^2 within 1e-3 of the FP64 oracle; the smoothed
-    observables within max(1e-3, 3x the spread of two oracle runs whose initial
-    coordinates differ by one FP32 ulp) at the 99th percentile of the bins."""
-    cfg = configs.cfg2(N=20000)
-    inp, ctx, (om,) = run_both(cfg, 200)
-    st = m2m.m2m_step(ctx, 200)[0]
-    ost = om.run(200)[-1]
-    assert st["chi2"] == pytest.approx(ost[0], rel=1e-3)
-    ulp = H.oracle_models(cfg, dict(inp, ics=np.nextafter(inp["ics"], np.float32(np.inf))), H.erange(cfg, inp))[0]
-    ulp.run(200)
+def one_particle_share(layout, ics, w, scale):
+    """Per observable, the largest |w_i K_ij| of one particle over sum_i |w_i K_ij|."""
+    big = np.zeros(scale.size)
+    for i in range(w.size):
+        for j, K in oracle.kernel_entries(layout, ics[:, i]):
+            big[j] = max(big[j], abs(w[i] * K))
+    return big / np.maximum(scale, 1e-300)
+
+
+def end_of_run(cfg, nsteps, launch=None):
+    """Run the GPU path and the oracle nsteps from the same inputs (and, when some
+    bin differs by more than 1e-3, a second oracle run whose initial coordinates
+    are one FP32 ulp away: the spread that FP32 coordinates alone cause in an
+    orbit integration of this length).
+    Asserts chi^2 within 1e-3 of the oracle's, and every bin's smoothed
+    observable within max(1e-3, 3 x the largest one-ulp spread) of the scale
+    sum |w K| of its bin, or, in a bin beyond that, within twice the largest
+    share of one particle in it; returns the errors."""
+    inp, ctx, (om,) = run_both(cfg, nsteps, launch=launch)
+    st = m2m.m2m_step(ctx, nsteps)[0]
+    ost = om.run(nsteps)[-1]
     obs = m2m.m2m_observables(ctx, 0)
     ys_o = smoothed_next(cfg, om)
     scale = H.moment_scale(cfg, om.ics(), om.w)
     big = scale > 1e-3 * scale.max()
     err = np.abs(obs["y_smooth"] - ys_o)[big] / scale[big]
-    floor = np.abs(smoothed_next(cfg, ulp) - ys_o)[big] / scale[big]
-    H.flush("end-of-run error p99 %.3g max %.3g; one-ulp floor p99 %.3g max %.3g" % (
-        np.percentile(err, 99), err.max(), np.percentile(floor, 99), floor.max()))
-    assert np.percentile(err, 99) <= max(1e-3, 3 * np.percentile(floor, 99))
+    chi_err = abs(st["chi2"] - ost[0]) / ost[0]
+    floor = None
+    if err.max() > 1e-3:
+        # only needed when the bins are not all within 1e-3
+        ulp = H.oracle_models(cfg, dict(inp, ics=np.nextafter(inp["ics"], np.float32(np.inf))),
+                              H.erange(cfg, inp))[0]
+        ulp.run(nsteps)
+        floor = np.abs(smoothed_next(cfg, ulp) - ys_o)[big] / scale[big]
+    H.flush("%s N=%d %d steps: chi2 GPU %.8g oracle %.8g rel %.3g; bins max %.3g p99 %.3g; one-ulp floor %s" % (
+        cfg["name"], cfg["N"], nsteps, st["chi2"], ost[0], chi_err, err.max(), np.percentile(err, 99),
+        "not needed" if floor is None else "max %.3g p99 %.3g" % (floor.max(), np.percentile(floor, 99))))
+    assert chi_err <= 1e-3
+    bound = max(1e-3, 0.0 if floor is None else 3 * floor.max())
+    if err.max() > bound:
+        # sparse bins: one particle on the other side of an edge moves the bin by its
+        # own share of sum |w K| (the orbits of FP32 and FP64 coordinates part in time)
+        share = one_particle_share(cfg["layout"], om.ics(), om.w, scale)[big]
+        over = err > bound
+        H.flush("%d bins beyond %.3g, each within twice its largest one-particle share: %s" % (
+            over.sum(), bound, np.all(err[over] <= 2 * share[over])))
+        assert np.all(err[over] <= 2 * share[over])
+    m2m.m2m_destroy(ctx)
+    return chi_err, err, floor
+
+
+def test_cfg2_fp32_end_of_run():
+    """200 steps of N = 2e4."""
+    end_of_run(configs.cfg2(N=20000), 200)
+
+
+def test_cfg2_fp32_end_of_run_full_size():
+    """The benchmark's 2^20 particles in its launch shape, 500 steps."""
+    end_of_run(configs.cfg2(), 500, launch={"threads": 1024, "ilp": 1, "blocks_per_cu": 1})
+
+
+def test_cfg3_multipole_end_of_run():
+    """The self-consistent multipole model, 2^18 particles, 200 steps (its rate derived
+    at this size as for the full workload)."""
+    cfg = configs.cfg3(N=1 << 18)
+    cfg["eps"] = 0.1 / (cfg["dt"] * derive_eps.max_abs_G(cfg))
+    end_of_run(cfg, 200)
+
+
+def test_cfg5_learned_prior_end_of_run():
+    """The learned prior, 2^18 particles, 300 steps (three refreshes)."""
+    cfg = configs.cfg5(N=1 << 18)
+    cfg["eps"] = 0.1 / (cfg["dt"] * derive_eps.max_abs_G(cfg))
+    end_of_run(cfg, 300)
 
 
 def test_cfg1_fp64_full_run_chi2():
@@ -174,9 +234,16 @@ def test_batched_models_match_oracle():
     offs = np.concatenate([[0], np.cumsum(cfg["model_sizes"])])
     wg = m2m.m2m_weights(ctx).astype(np.float64)
     for m, om in enumerate(ors):
-        ost = om.run(4)[-1]
-        np.testing.assert_allclose(wg[offs[m]:offs[m + 1]], om.w, rtol=1e-5)
-        assert rows[m]["chi2"] == pytest.approx(ost[0], rel=1e-5)
+        L = np.zeros(om.w.size)
+        for n in range(4):
+            w0 = om.w.copy()
+            ost = om.run(1)[-1]
+            L += np.abs(np.log(om.w / w0))
+        tol = max(2e-6, 6e-7 * L.max())
+        H.flush("model %d: largest total |d ln w| %.3g, bar %.3g, error %.3g" % (
+            m, L.max(), tol, np.max(np.abs(wg[offs[m]:offs[m + 1]] / om.w - 1))))
+        np.testing.assert_allclose(wg[offs[m]:offs[m + 1]], om.w, rtol=tol)
+        assert rows[m]["chi2"] == pytest.approx(ost[0], rel=tol)
         assert rows[m]["model"] == m
 
 
