@@ -784,6 +784,20 @@ static Layout<T> layout_of(const m2m_ctx* c) {
         } else {
             B.nb = d.nedge - 1;
             e0 += d.nedge;
+            // log-spaced edges (as FP32 values): the kernels estimate the bin from
+            // ln r when every edge lies within a quarter bin of its place
+            if (sizeof(T) == 4 && d.nedge >= 3) {
+                std::vector<double> lf(d.nedge);
+                for (int k = 0; k < d.nedge; ++k) lf[k] = std::log((double)(float)c->edges_host[b][k]);
+                const double x0 = (double)(float)lf[0], sx = (double)(float)((d.nedge - 1) / (lf[d.nedge - 1] - lf[0]));
+                bool geo = std::isfinite(x0) && std::isfinite(sx) && sx > 0;
+                for (int k = 0; geo && k < d.nedge; ++k) geo = std::fabs((lf[k] - x0) * sx - k) <= 0.25;
+                if (geo) {
+                    B.geo = 1;
+                    B.x0 = (T)x0;
+                    B.sx = (T)sx;
+                }
+            }
         }
         off += d.nmom * B.nb;
     }

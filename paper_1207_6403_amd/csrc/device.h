@@ -63,7 +63,7 @@ template <typename T>
 struct BinDesc {
     int32_t kind, nmom, mom, off;   // off: first observable index of the binning
     int32_t nb, edge0, nx, ny;      // nb: bins per moment
-    int32_t gh0, pad;
+    int32_t gh0, geo;   // geo: shells/annuli with log-spaced edges, ln e_k = x0 + k / sx
     T x0, sx, y0, sy;
     // FP32 grid guard terms (bins): gx0 = 2u sx |x0|, gy0 = 2u sy |y0| (the
     // rounded origins), gys = 6u sy (the rounded projection, per unit of
@@ -186,16 +186,29 @@ __device__ __forceinline__ void potential(const Pot<T>& p, T x, T y, T z, T& phi
     if (POT == 2 && p.GMh > T(0)) {
         const T xx = r * p.irs;
         const T l1 = dlog1p(xx);
-        ph += r > T(0) ? -p.GMh * l1 / r : -p.GMh * p.irs;
         // dPhi_NFW/dr = G Mh/rs^2 f(x), f = ln(1+x)/x^2 - 1/(x(1+x)); the two terms
         // cancel near x = 0, where the Taylor series is used instead.
         T f;
-        if (xx < T(0.05)) {
-            f = T(0.5) + xx * (T(-2.0 / 3.0) + xx * (T(0.75) + xx * (T(-0.8) + xx * (T(5.0 / 6.0) - xx * T(6.0 / 7.0)))));
+        if constexpr (sizeof(T) == 4) {
+            // one hardware reciprocal of r serves every division (1/x = rs/r)
+            const T ir = r > T(0) ? qdiv(T(1), r) : T(0);
+            ph += r > T(0) ? -p.GMh * l1 * ir : -p.GMh * p.irs;
+            if (xx < T(0.05)) {
+                f = T(0.5) + xx * (T(-2.0 / 3.0) + xx * (T(0.75) + xx * (T(-0.8) + xx * (T(5.0 / 6.0) - xx * T(6.0 / 7.0)))));
+            } else {
+                const T ix = p.rs * ir;
+                f = ix * (l1 * ix - qdiv(T(1), T(1) + xx));
+            }
+            g_over_r += p.GMh * p.irs * p.irs * f * ir;
         } else {
-            f = l1 / (xx * xx) - T(1) / (xx * (T(1) + xx));
+            ph += r > T(0) ? -p.GMh * l1 / r : -p.GMh * p.irs;
+            if (xx < T(0.05)) {
+                f = T(0.5) + xx * (T(-2.0 / 3.0) + xx * (T(0.75) + xx * (T(-0.8) + xx * (T(5.0 / 6.0) - xx * T(6.0 / 7.0)))));
+            } else {
+                f = l1 / (xx * xx) - T(1) / (xx * (T(1) + xx));
+            }
+            g_over_r += r > T(0) ? p.GMh * p.irs * p.irs * f / r : T(0);
         }
-        g_over_r += r > T(0) ? p.GMh * p.irs * p.irs * f / r : T(0);
     }
     phi = ph;
     ax = -g_over_r * x;
@@ -537,7 +550,19 @@ __device__ __forceinline__ int bin_fast(const BinDesc<float>& d, int kind, const
     const float* e = ef + d.edge0;
     const int ne = d.nb + 1;
     const float g = 12.0f * kU32 * rad + (kind == 1 ? 0.0f : 6.0f * kU32 * aYs);
-    const int k = edge_bin(e, ne, rad);
+    int k;
+    if (d.geo) {
+        // log-spaced edges: the bin from ln r (within one bin of the right one, as
+        // the host checked), then one step down and one up by comparing with the
+        // edges themselves, so that k is the edge interval a search would find
+        const bool in = (rad >= e[0]) & (rad < e[ne - 1]);
+        int j = int(fminf(fmaxf((qlog(rad) - d.x0) * d.sx, 0.0f), float(d.nb - 1)));
+        j -= int(rad < e[j]);
+        j += int(rad >= e[j + 1]);
+        k = in ? j : -1;
+    } else {
+        k = edge_bin(e, ne, rad);
+    }
     if (k >= 0) sure = !(rad - e[k] < g) && !(e[k + 1] - rad < g);
     else sure = !(fabsf(rad - e[0]) < g) && !(fabsf(rad - e[ne - 1]) < g) && rad == rad;
     return k;

@@ -96,7 +96,9 @@ def pot32(pot, x, y, z, hw, fused):
     if k == "hernquist_nfw":
         GMh, irs = F32(pot.get("G", 1.0) * pot["Mh"]), F32(1.0 / pot["rs"])
         l1 = hw.log1p((r * irs).astype(F32))
-        ph = (ph + (-(GMh * l1).astype(F32) / r).astype(F32)).astype(F32)
+        t = (-GMh * l1).astype(F32)
+        ir = hw.rcp(r)          # one hardware reciprocal of r
+        ph = fma(t, ir, ph) if fused else (ph + (t * ir).astype(F32)).astype(F32)
     return ph
 
 
