@@ -315,7 +315,8 @@ def main():
         achieved = flops / (k_ms * 1e-3) / 1e12
         roof = {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": achieved / FP32_PEAK_TFLOPS, "traffic": None,
-                "kernel": "mp_kick_drift_kernel (weight update, first kick from the node tables in LDS, drift)",
+                "kernel": "mp_kick_kernel (second kick: the l <= 8 field from the node tables in LDS, stored for "
+                          "the next step's first kick)",
                 "kernel_us": k_ms * 1e3, "flops_per_launch": flops}
     else:
         bpp = BYTES_PER_PARTICLE_STEP + (4 if wl == "mlp" else 0)   # the learned prior is read per particle

@@ -199,7 +199,7 @@ typedef struct {
 
 /* Launch shape of the fused step kernel (see m2m_autotune).  timing = 1 makes
  * m2m_step launch without graphs and bracket every fused step kernel (MULTIPOLE
- * models: the update/first-kick/drift kernel) with HIP events on the context's
+ * models: the second-kick kernel, which evaluates the field) with HIP events on the context's
  * stream (read with m2m_kernel_time). */
 typedef struct {
     int32_t threads;        /* 64..1024, multiple of 64 (FP64: at most 256) */

@@ -332,12 +332,12 @@ static m2m_status make_plan(m2m_ctx* c, int threads, int ilp, int bpc) {
         return fail(c, M2M_ERR_UNSUPPORTED, "layout needs " + std::to_string(p.lds) + " bytes of LDS per block (max " +
                                                 std::to_string(c->max_lds) + ")");
     if (c->mp) {
-        // multipole kernels: FP32 kernels keep the node table in LDS (update and
-        // drift, second kick)
+        // multipole kernels: the FP32 second kick keeps the node table in LDS (the
+        // first kick reads the stored field and needs no table)
         const int nn = c->mp_pot.nnode;
         const bool f32 = ts == 4;
         MpLds& L = c->mp_lds;
-        L.kick_drift = 512 + (f32 ? 4 * (size_t)nn * kMpRowF : 0);
+        L.kick_drift = 512;
         L.coeff = 0;
         L.kick = f32 ? 4 * (size_t)nn * kMpRowF : 0;
         const size_t need = std::max(L.kick_drift, L.kick);
@@ -483,7 +483,7 @@ static void prior_modes(const m2m_ctx* c, int64_t n, int* what_mode, int* accum)
 // Multipole kernel arguments; src is the state buffer the coefficient and
 // second-kick kernels work on.
 template <typename T>
-static void fill_mp_args(const m2m_ctx* c, MpArgs<T>& mp, const void* src) {
+static void fill_mp_args(const m2m_ctx* c, MpArgs<T>& mp, const void* src, int parity, int kick) {
     const m2m_potential& q = c->mp_pot;
     const Plan& p = c->plan;
     const double lr0 = std::log(q.rmin), dl = (std::log(q.rmax) - lr0) / (q.nnode - 1);
@@ -518,6 +518,9 @@ static void fill_mp_args(const m2m_ctx* c, MpArgs<T>& mp, const void* src) {
     mp.B64 = c->mp_B64;
     mp.src = (const T*)src;
     mp.stride = c->stride;
+    mp.acc_in = (const T*)c->mp_acc[parity];
+    mp.acc_out = (T*)c->mp_acc[parity ^ 1];
+    mp.kick = kick;
     mp.block_tile0 = p.block_tile0;
     mp.tile_p0 = p.tile_p0;
     mp.tile_cnt = p.tile_cnt;
@@ -625,18 +628,16 @@ static hipError_t launch_one_T(m2m_ctx* c, int64_t n, hipEvent_t e0, hipEvent_t 
             c->mlp_t += c->prior.mlp_subset / c->prior.mlp_batch;
         }
     }
-    if (e0) (void)hipEventRecord(e0, c->stream);
     hipError_t e;
     if (c->mp) {
         // self-consistent model: update, kicks and drift with the coefficient
         // rebuild between them, then the fused kernel observes the new state
-        // (the timing events bracket the update/kick/drift kernel)
+        // (the timing events bracket the second kick, which evaluates the field)
         MpArgs<T> mp;
-        fill_mp_args<T>(c, mp, a.out);
+        fill_mp_args<T>(c, mp, a.out, (int)(n & 1), 1);
         e = launch_mp_step<T, T>(a, mp, c->sig, c->lay.nbin, p.nblock, c->mp_lds, c->stream);
-        if (e1) (void)hipEventRecord(e1, c->stream);
-        e1 = nullptr;
-        if (e == hipSuccess && !c->frozen) e = launch_mp_build<T>(mp, p.nblock, c->mp_lds, c->stream, true);
+        if (e == hipSuccess && !c->frozen) e = launch_mp_build<T>(mp, p.nblock, c->mp_lds, c->stream, e0, e1);
+        e0 = e1 = nullptr;
         if (e == hipSuccess) {
             StepArgs<T, T> o;
             fill_step_args<T>(c, o, (int)((n + 1) & 1), 1, 0, acc);
@@ -644,6 +645,7 @@ static hipError_t launch_one_T(m2m_ctx* c, int64_t n, hipEvent_t e0, hipEvent_t 
             e = launch_step<T, T>(o, c->pot_kind, c->sig, c->lay.nbin, p.ilp, p.nblock, p.threads, p.lds, c->stream);
         }
     } else {
+        if (e0) (void)hipEventRecord(e0, c->stream);
         e = launch_step<T, T>(a, c->pot_kind, c->sig, c->lay.nbin, p.ilp, p.nblock, p.threads, p.lds, c->stream);
     }
     if (e1) (void)hipEventRecord(e1, c->stream);
@@ -1066,7 +1068,8 @@ static m2m_status create_T(m2m_ctx* c, const m2m_target* tg, const void* xv, con
         const size_t ntab = (size_t)nn * (sizeof(T) == 4 ? kMpRowF : kMpW);
         if ((s = upload(c, &c->mp_rk, rk)) || (s = dalloc(c, (T**)&c->mp_tab, ntab)) ||
             (s = dalloc(c, &c->mp_S, (size_t)(nn + 1) * kMpW)) || (s = dalloc(c, &c->mp_A64, (size_t)nn * nlm)) ||
-            (s = dalloc(c, &c->mp_B64, (size_t)nn * nlm)))
+            (s = dalloc(c, &c->mp_B64, (size_t)nn * nlm)) || (s = dalloc(c, (T**)&c->mp_acc[0], 3 * (size_t)c->stride)) ||
+            (s = dalloc(c, (T**)&c->mp_acc[1], 3 * (size_t)c->stride)))
             return s;
         HIPCHK(c, hipMemset(c->mp_tab, 0, sizeof(T) * ntab));
         HIPCHK(c, hipMemset(c->mp_S, 0, sizeof(double) * (nn + 1) * kMpW));
@@ -1096,10 +1099,10 @@ static m2m_status create_T(m2m_ctx* c, const m2m_target* tg, const void* xv, con
     if ((s = upload(c, (T**)&c->erange, erT)) || (s = upload(c, &c->erange64, er))) return s;
     if ((s = build_lc_etab<T>(c, er)) || (s = upload_exact(c))) return s;
     if (c->mp) {
-        // coefficients of the initial state (used by the first kick of step 0)
+        // coefficients of the initial state and its field (the first kick of step 0)
         MpArgs<T> mp;
-        fill_mp_args<T>(c, mp, c->state[0]);
-        HIPCHK(c, launch_mp_build<T>(mp, c->plan.nblock, c->mp_lds, c->stream, false));
+        fill_mp_args<T>(c, mp, c->state[0], 1, 2);
+        HIPCHK(c, launch_mp_build<T>(mp, c->plan.nblock, c->mp_lds, c->stream));
     }
     HIPCHK(c, launch_prologue_T<T>(c));
     HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -1681,6 +1684,7 @@ static m2m_status snapshot(m2m_ctx* c, Snapshot& s, bool restore) {
         items.push_back({c->mp_tab, nn * (ts == 4 ? kMpRowF : kMpW) * ts});
         items.push_back({c->mp_A64, nn * nlm * 8});
         items.push_back({c->mp_B64, nn * nlm * 8});
+        items.push_back({c->mp_acc[c->step & 1], 3 * (size_t)c->stride * ts});
     }
     if (!restore) {
         for (auto& it : items) {

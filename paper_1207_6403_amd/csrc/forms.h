@@ -49,6 +49,12 @@ struct MpArgs {
     double* B64;                     // nn x nlm
     const T* src;                    // state buffer the coefficient and kick kernels work on
     int64_t stride;
+    // accelerations (3 rows of `stride`) of the state the step starts from, read
+    // by its first kick, and of the state it makes, written by the second kick
+    // (the same field at the same points with the same node table)
+    const T* acc_in;
+    T* acc_out;
+    int32_t kick;                    // launch_mp_build: 0 no kick, 1 kick and store, 2 store only
     const int32_t* block_tile0;
     const int64_t* tile_p0;
     const int32_t* tile_cnt;
@@ -126,9 +132,13 @@ hipError_t mlp_noalloc_scratch(int device, float** out);
 template <typename T, typename PT>
 hipError_t launch_mp_step(const StepArgs<T, PT>& a, const MpArgs<T>& mp, uint64_t sig, int nbin, int blocks,
                           const MpLds& lds, hipStream_t s);
-// Coefficients of the particles in mp.src (and, with kick, the second kick).
+// Coefficients of the particles in mp.src, then per mp.kick: nothing (0), the
+// second kick with its accelerations stored in mp.acc_out (1), or only the
+// accelerations (2: the initial state's, for the first step's first kick).
+// ek0/ek1 (nullable): events recorded around the kick kernel.
 template <typename T>
-hipError_t launch_mp_build(const MpArgs<T>& mp, int blocks, const MpLds& lds, hipStream_t s, bool kick);
+hipError_t launch_mp_build(const MpArgs<T>& mp, int blocks, const MpLds& lds, hipStream_t s,
+                           hipEvent_t ek0 = nullptr, hipEvent_t ek1 = nullptr);
 template <typename T, typename PT>
 hipError_t set_mp_lds_limit(size_t lds);
 

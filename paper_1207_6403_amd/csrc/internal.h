@@ -53,6 +53,7 @@ struct m2m_ctx {
     bool mp = false;
     m2m_potential mp_pot{};
     void* mp_tab = nullptr;
+    void* mp_acc[2] = {nullptr, nullptr};   // accelerations of the state in state[k] (3 rows each)
     double* mp_rk = nullptr;
     double* mp_S = nullptr;
     double* mp_A64 = nullptr;

@@ -10,12 +10,13 @@
 // radii outside [rmin, rmax] are evaluated at the clamped radius.
 //
 // One step of a multipole model runs
-//   mp_kick_drift   weight update, first half kick (coefficients of step n), drift
+//   mp_kick_drift   weight update, first half kick (the field at x_n, stored by the
+//                   previous step's second kick), drift
 //   per-interval sums of the drifted particles with the new weights: FP32
 //                   mp_interval, mp_offsets, mp_scatter (counting sort by
 //                   interval), mp_accum, mp_chunksum; FP64 mp_coeff_atomic
 //   mp_scan         node coefficients of step n+1
-//   mp_kick         second half kick
+//   mp_kick         second half kick; stores the field at x_n+1 for the next step
 // then the fused step kernel observing the new state, and the finalise kernel.
 #include "particle.h"
 #include "forms.h"
@@ -261,21 +262,16 @@ template <typename T, typename PT, int NB, uint64_t SIG>
 __global__ void __launch_bounds__(sizeof(T) == 8 ? 256 : 1024) mp_kick_drift_kernel(StepArgs<T, PT> a, MpArgs<T> mp) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int failed = *a.flag;
-    constexpr bool F32 = sizeof(T) == 4;
     const int J = a.lay.J, NC = a.cells.ncell;
     const int nt = blockDim.x, tid = threadIdx.x;
-    // LDS: reduction scratch, then the FP32 node table; the update table and the
-    // cell means are read from global memory (they leave the table the room)
+    // LDS: reduction scratch; the update table and the cell means are read from
+    // global memory
     double* red = reinterpret_cast<double*>(smem);                        // 64
-    float* tabl = reinterpret_cast<float*>(red + 64);                      // FP32: nn x kMpRowF
-    const int NT = F32 ? mp.nn * kMpRowF : 0;
 
     const int t0 = ro(a.block_tile0, blockIdx.x), t1 = ro(a.block_tile0, blockIdx.x + 1);
     const uint32_t fl = a.flags;
     const uint32_t wm = (fl >> kWhatShift) & 3u;
     const bool want_cm = wm == 1 || wm == 2;
-    if constexpr (F32)
-        mp_table_to_lds(reinterpret_cast<float4*>(tabl), reinterpret_cast<const float4*>(mp.tab), NT / 4, tid, nt);
     int slot = ro(a.block_slot0, blockIdx.x) - 1, cur = -1;
     Blk<T> B{};
     Acc acc;
@@ -300,7 +296,7 @@ __global__ void __launch_bounds__(sizeof(T) == 8 ? 256 : 1024) mp_kick_drift_ker
             B.cl = a.cvec + (size_t)m * J;
             B.cm = a.cellmean + (size_t)m * NC;
             B.gh = a.ghtab;
-            __syncthreads();   // (the first: the node table is in place)
+            __syncthreads();
         }
         const int64_t p0 = ro(a.tile_p0, t);
         const int cnt = ro(a.tile_cnt, t);
@@ -318,9 +314,8 @@ __global__ void __launch_bounds__(sizeof(T) == 8 ? 256 : 1024) mp_kick_drift_ker
             const T what_p = wm == 3 ? a.what[p] : T(1);
             const T wn = weight_update<NB, SIG>(a, B, acc, p, vy, vz, w, what_p, tg, fl);
             if (!(fl & kFrozen)) {
-                T phi, ax, ay, az;
-                if constexpr (F32) mp_field<T, float>(mp, tabl, x, y, z, phi, ax, ay, az);
-                else mp_field<T, T>(mp, mp.tab, x, y, z, phi, ax, ay, az);
+                // the field at x_n: stored by the previous step's second kick (or at creation)
+                const T ax = ld_at<T>(mp.acc_in, o), ay = ld_at<T>(mp.acc_in, o + rb), az = ld_at<T>(mp.acc_in, o + 2 * rb);
                 vx += hdt * ax; vy += hdt * ay; vz += hdt * az;
                 x += a.dt * vx; y += a.dt * vy; z += a.dt * vz;
             }
@@ -771,9 +766,14 @@ __global__ void __launch_bounds__(sizeof(T) == 8 ? 256 : 1024) mp_kick_kernel(Mp
             T phi, ax, ay, az;
             if constexpr (F32) mp_field<T, float>(mp, tabl, x, y, z, phi, ax, ay, az);
             else mp_field<T, T>(mp, mp.tab, x, y, z, phi, ax, ay, az);
-            st_at(dst, o + 3 * rb, ld_at<T>(mp.src, o + 3 * rb) + mp.hdt * ax);
-            st_at(dst, o + 4 * rb, ld_at<T>(mp.src, o + 4 * rb) + mp.hdt * ay);
-            st_at(dst, o + 5 * rb, ld_at<T>(mp.src, o + 5 * rb) + mp.hdt * az);
+            st_at(mp.acc_out, o, ax);
+            st_at(mp.acc_out, o + rb, ay);
+            st_at(mp.acc_out, o + 2 * rb, az);
+            if (mp.kick == 1) {
+                st_at(dst, o + 3 * rb, ld_at<T>(mp.src, o + 3 * rb) + mp.hdt * ax);
+                st_at(dst, o + 4 * rb, ld_at<T>(mp.src, o + 4 * rb) + mp.hdt * ay);
+                st_at(dst, o + 5 * rb, ld_at<T>(mp.src, o + 5 * rb) + mp.hdt * az);
+            }
         }
     }
 }
@@ -798,7 +798,8 @@ hipError_t launch_mp_step(const StepArgs<T, PT>& a, const MpArgs<T>& mp, uint64_
 }
 
 template <typename T>
-hipError_t launch_mp_build(const MpArgs<T>& mp, int blocks, const MpLds& lds, hipStream_t s, bool kick) {
+hipError_t launch_mp_build(const MpArgs<T>& mp, int blocks, const MpLds& lds, hipStream_t s, hipEvent_t ek0,
+                           hipEvent_t ek1) {
     hipError_t e;
     if constexpr (sizeof(T) == 4) {
         hipLaunchKernelGGL(mp_interval_kernel, dim3(mp.G_sort), dim3(kMpSortThreads), 0, s, mp);
@@ -811,8 +812,10 @@ hipError_t launch_mp_build(const MpArgs<T>& mp, int blocks, const MpLds& lds, hi
     }
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL((mp_scan_kernel<T>), dim3(kMpNlm), dim3(128), 0, s, mp);
-    if ((e = hipGetLastError()) != hipSuccess || !kick) return e;
+    if ((e = hipGetLastError()) != hipSuccess || !mp.kick) return e;
+    if (ek0) (void)hipEventRecord(ek0, s);
     hipLaunchKernelGGL((mp_kick_kernel<T>), dim3(blocks), dim3(sizeof(T) == 8 ? 256 : 1024), lds.kick, s, mp);
+    if (ek1) (void)hipEventRecord(ek1, s);
     return hipGetLastError();
 }
 
@@ -833,8 +836,10 @@ template hipError_t launch_mp_step<float, float>(const StepArgs<float, float>&, 
                                                  const MpLds&, hipStream_t);
 template hipError_t launch_mp_step<double, double>(const StepArgs<double, double>&, const MpArgs<double>&, uint64_t,
                                                    int, int, const MpLds&, hipStream_t);
-template hipError_t launch_mp_build<float>(const MpArgs<float>&, int, const MpLds&, hipStream_t, bool);
-template hipError_t launch_mp_build<double>(const MpArgs<double>&, int, const MpLds&, hipStream_t, bool);
+template hipError_t launch_mp_build<float>(const MpArgs<float>&, int, const MpLds&, hipStream_t, hipEvent_t,
+                                          hipEvent_t);
+template hipError_t launch_mp_build<double>(const MpArgs<double>&, int, const MpLds&, hipStream_t, hipEvent_t,
+                                           hipEvent_t);
 template hipError_t set_mp_lds_limit<float, float>(size_t);
 template hipError_t set_mp_lds_limit<double, double>(size_t);
 

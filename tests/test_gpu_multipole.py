@@ -5,7 +5,11 @@ Bars:
   node tables -- each coefficient within rtol * scale, scale = sum over the same
     particles of m_i r_i^l (or r_i^-(l+1)) times max |P_l^m| (so that coefficients
     that cancel to ~0 are judged against the size of their terms): rtol 1e-12 for
-    FP64 (summation order only), 2e-5 for FP32 (FP32 terms, FP32 per-block sums);
+    FP64 (summation order only); FP32, same coordinates on both sides (the initial
+    state): 2e-6 (FP32 terms, per-lane FP32 sums of 16 particles and a 64-lane
+    butterfly, FP64 above: each under 2e-7 of the scale in a numpy restatement,
+    3.4e-7 measured); FP32 after steps: 2e-5 (the two sides' coordinates then
+    differ by the FP32 rounding of the orbit integration, which dominates);
   FP64 steps -- weights, coordinates and statistics within 1e-10 relative after a
     few steps (FP64 atomics make the summation order, and so the last bits of the
     coefficients, vary);
@@ -134,7 +138,7 @@ def start(cfg, launch=None):
     return inp, ctx, om
 
 
-@pytest.mark.parametrize("precision,rtol", [("f64", 1e-12), ("f32", 2e-5)])
+@pytest.mark.parametrize("precision,rtol", [("f64", 1e-12), ("f32", 2e-6)])
 def test_tables_of_the_initial_state(precision, rtol):
     cfg = small(30011, precision)
     inp, ctx, om = start(cfg)

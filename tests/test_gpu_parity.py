@@ -73,6 +73,30 @@ def test_cfg1_fp64_matches_oracle(nsteps):
     assert m2m.m2m_step_index(ctx) == nsteps
 
 
+def test_fp32_bin_reduction_bound():
+    """The FP32 path's observables of the initial state (no step: the same FP32
+    coordinates on both sides, every bin decision exact) at the benchmark size and
+    launch shape.  Each block sums its particles' w K in FP64 in LDS and rounds the
+    sum to FP32 once in its partial slot; the slots are added in FP64.  So a mass
+    bin (K = 1, w exact) is off by at most 2^-24 of sum |w K|, and a moment bin
+    adds the FP32 rounding of K itself (v_los from one fused multiply-add, then
+    its square: a few units of 2^-24)."""
+    from synth import targets
+    cfg = configs.cfg2()
+    inp, ctx, (om,) = run_both(cfg, 0, launch={"threads": 1024, "ilp": 1, "blocks_per_cu": 1})
+    y = m2m.m2m_observables(ctx, 0)["y"]
+    yo = om.observe()
+    scale = H.moment_scale(cfg, om.ics(), om.w)
+    mom = np.array([k[0] for k in targets.observable_kinds(cfg["layout"])])
+    err = np.abs(y - yo) / np.maximum(scale, 1e-300)
+    H.flush("initial-state observables, error / sum |w K|: mass %.3g, v %.3g, v^2 %.3g" % (
+        err[mom == 0].max(), err[mom == 1].max(), err[mom == 2].max()))
+    u = 2.0 ** -24
+    assert err[mom == 0].max() <= 1.0 * u
+    assert err[mom == 1].max() <= 3.0 * u
+    assert err[mom == 2].max() <= 5.0 * u
+
+
 def test_cfg2_fp32_single_step():
     cfg = configs.cfg2(N=50000)
     inp, ctx, (om,) = run_both(cfg, 1)
