@@ -61,11 +61,16 @@ class Prior(C.Structure):
                 ("Emin", C.c_double), ("Emax", C.c_double), ("flat_value", C.c_double), ("ref", Pot)]
 
 
+class Tracers(C.Structure):
+    _fields_ = [("binning", C.c_int32), ("n", C.c_int32), ("bin", C.POINTER(C.c_int32)),
+                ("v", C.POINTER(C.c_double)), ("s", C.POINTER(C.c_double)), ("lam", C.c_double)]
+
+
 class Cfg(C.Structure):
     _fields_ = [("N", C.c_int64), ("J", C.c_int32), ("update", C.c_int16), ("frozen", C.c_int16),
                 ("dt", C.c_double), ("eps", C.c_double), ("mu", C.c_double), ("tau", C.c_double),
                 ("pot", Pot), ("lay", Layout), ("prior", Prior),
-                ("Y", C.POINTER(C.c_double)), ("sigma", C.POINTER(C.c_double))]
+                ("Y", C.POINTER(C.c_double)), ("sigma", C.POINTER(C.c_double)), ("trc", Tracers)]
 
 
 class State(C.Structure):
@@ -73,7 +78,29 @@ class State(C.Structure):
                 ("x", "y", "z", "vx", "vy", "vz", "w", "what", "ys", "yobs", "delta", "mpA", "mpB")] + \
                [("n", C.c_int64)] + [(n, C.c_double) for n in
                                      ("chi2", "chi2_inst", "S", "F", "sumw", "minw", "sumw2")] + \
-               [("status", C.c_int32), ("pad", C.c_int32), ("bad_step", C.c_int64)]
+               [("status", C.c_int32), ("pad", C.c_int32), ("bad_step", C.c_int64)] + \
+               [(n, C.POINTER(C.c_double)) for n in ("tL", "tM", "tLobs", "tMobs")] + [("loglike", C.c_double)]
+
+
+def tracer_widths(tr):
+    """Kernel width of each tracer: sqrt(error^2 + h^2)."""
+    return np.sqrt(np.asarray(tr["dv"], dtype=np.float64) ** 2 + float(tr["h"]) ** 2)
+
+
+def make_tracers(tr, keep):
+    """Tracers struct from {"binning", "bin", "v", "dv", "h", "lambda"} (or None)."""
+    t = Tracers()
+    t.binning, t.n, t.lam = -1, 0, 0.0
+    if not tr:
+        return t
+    b = np.ascontiguousarray(tr["bin"], dtype=np.int32)
+    v = _f64(tr["v"])
+    sw = tracer_widths(tr)
+    keep += [b, v, sw]
+    t.binning, t.n, t.lam = int(tr["binning"]), b.size, float(tr["lambda"])
+    t.bin = b.ctypes.data_as(C.POINTER(C.c_int32))
+    t.v, t.s = _dp(v), _dp(sw)
+    return t
 
 
 _lib = None
@@ -102,6 +129,7 @@ def lib():
         L.or_mp_exact.argtypes = [C.POINTER(Pot), C.c_int64, DP, DP, DP, DP,
                                   C.c_double, C.c_double, C.c_double, DP, DP, DP, DP]
         L.or_observe.argtypes = [C.POINTER(Cfg), C.c_int64] + [DP] * 8
+        L.or_tracer_observe.argtypes = [C.POINTER(Cfg), C.c_int64] + [DP] * 9
         L.or_leapfrog.argtypes = [C.POINTER(Pot), C.c_int64, C.c_int64, C.c_double] + [DP] * 6
         L.or_field_many.argtypes = [C.POINTER(Pot), DP, DP, C.c_int64] + [DP] * 7
         L.or_step.argtypes = [C.POINTER(Cfg), C.POINTER(State)]
@@ -244,6 +272,7 @@ class Model:
         self.Erange = Erange
         c.prior = make_prior(cfg["prior"], pot, N, Erange)
         c.Y, c.sigma = _dp(self.Y), _dp(self.sigma)
+        c.trc = make_tracers(cfg.get("tracers"), self.keep)
         self.c = c
         self.arr = {}
         for k, name in enumerate(("x", "y", "z", "vx", "vy", "vz")):
@@ -256,6 +285,12 @@ class Model:
         nn = max(c.pot.nnode, 1)
         self.arr["mpA"] = np.zeros(nn * nlm)
         self.arr["mpB"] = np.zeros(nn * nlm)
+        tr = cfg.get("tracers")
+        ntb = tracer_bins(cfg["layout"], tr["binning"]) if tr else 1
+        self.arr["tL"] = np.zeros(max(c.trc.n, 1))
+        self.arr["tLobs"] = np.zeros(max(c.trc.n, 1))
+        self.arr["tM"] = np.zeros(ntb)
+        self.arr["tMobs"] = np.zeros(ntb)
         s = State()
         for name, a in self.arr.items():
             setattr(s, name, _dp(a))
@@ -284,6 +319,20 @@ class Model:
         rc = lib().or_run(C.byref(self.c), C.byref(self.s), nsteps, _dp(st))
         self.status = rc
         return st[:nsteps]
+
+    @property
+    def loglike(self):
+        """Tracer log-likelihood sum_t ln(Ls_t / Ms_b(t)) of the last step's smoothed sums."""
+        return float(self.s.loglike)
+
+    def tracer_observe(self):
+        """(L_t, M_b) of the current state (no smoothing)."""
+        a = self.arr
+        L = np.zeros(max(self.c.trc.n, 1))
+        M = np.zeros(a["tM"].size)
+        lib().or_tracer_observe(C.byref(self.c), self.c.N, _dp(a["x"]), _dp(a["y"]), _dp(a["z"]),
+                                _dp(a["vx"]), _dp(a["vy"]), _dp(a["vz"]), _dp(a["w"]), _dp(L), _dp(M))
+        return L[:self.c.trc.n], M
 
     def observe(self):
         y = np.zeros(self.J)
@@ -319,6 +368,11 @@ class Model:
 
     def set_what(self, what):
         self.arr["what"][:] = what
+
+
+def tracer_bins(layout, ib):
+    b = layout["binnings"][ib]
+    return b["nx"] * b["ny"] if b["kind"] == "grid" else len(b["edges"]) - 1
 
 
 def kernel_entries(layout, z):

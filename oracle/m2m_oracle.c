@@ -29,6 +29,14 @@
  *               (dw_i/dt = eps w_i dF/dw_i with the priors held fixed), integrated over
  *               dt as w_i <- w_i exp(eps dt G_i) (default) or w_i (1 + eps dt G_i)
  *   7 push      kick-drift-kick leapfrog over dt
+ * With discrete tracer velocities (section 1 lists PNe velocities among the
+ * data; reading: the likelihood term of NMAGIC's discrete-velocity fits), steps
+ * 1-3 also observe, smooth (as y) and score the tracers:
+ *   L_t(n) = sum_i w_i [b(z_i) = b_t] phi(v_los,i; V_t, s_t),  M_b(n) = sum_i w_i [b(z_i) = b]
+ *   loglike = sum_t ln(Ls_t / Ms_(b_t))  (each tracer's model LOSVD density at V_t)
+ * and the update gains lambda d(loglike)/dw_i with the smoothed values held:
+ *   G_i += lambda (sum_{t in b(z_i)} phi(v_los,i; V_t, s_t) / Ls_t - n_(b(z_i)) / Ms_(b(z_i)))
+ * (phi the normal density, s_t^2 = error^2 + smoothing^2, n_b the tracers in bin b).
  */
 #define _DEFAULT_SOURCE
 #include <math.h>
@@ -77,6 +85,16 @@ typedef struct {
     or_pot ref;        /* potential in which E and Lc(E) are measured  */
 } or_prior;
 
+/* Discrete tracers: per tracer its bin in layout binning `binning`, its
+ * line-of-sight velocity and kernel width s_t (sqrt(error^2 + h^2)). */
+typedef struct {
+    int32_t binning;   /* -1: no tracers */
+    int32_t n;
+    const int32_t *bin;
+    const double *v, *s;
+    double lambda;
+} or_tracers;
+
 typedef struct {
     int64_t N;
     int32_t J;
@@ -87,6 +105,7 @@ typedef struct {
     or_layout lay;
     or_prior prior;
     const double *Y, *sigma;
+    or_tracers trc;
 } or_cfg;
 
 typedef struct {
@@ -100,6 +119,9 @@ typedef struct {
     double chi2, chi2_inst, S, F, sumw, minw, sumw2;
     int32_t status, pad;
     int64_t bad_step;
+    double *tL, *tM;       /* tracers: smoothed L_t (n) and bin masses M_b (nb)  */
+    double *tLobs, *tMobs; /* the same from the last observe                     */
+    double loglike;
 } or_state;
 
 static int nthreads(void) {
@@ -629,6 +651,54 @@ void or_observe(const or_cfg *c, int64_t N, const double *x, const double *y, co
     free(part);
 }
 
+/* ------------------------------------------------------------------ tracers */
+static int binning_nbins(const or_layout *L, int b) {
+    return L->kind[b] == OR_BIN_GRID ? L->nx[b] * L->ny[b] : L->nedge[b] - 1;
+}
+
+static double normal_density(double v, double mean, double s) {
+    double d = (v - mean) / s;
+    return exp(-0.5 * d * d) / (sqrt(2.0 * M_PI) * s);
+}
+
+/* Tracers grouped by bin: first[b] .. first[b+1] index into order[]. */
+static void tracer_lists(const or_cfg *c, int nb, int32_t *first, int32_t *order) {
+    const or_tracers *T = &c->trc;
+    for (int b = 0; b <= nb; ++b) first[b] = 0;
+    for (int t = 0; t < T->n; ++t) first[T->bin[t] + 1] += 1;
+    for (int b = 0; b < nb; ++b) first[b + 1] += first[b];
+    int32_t *fill = (int32_t *)malloc(sizeof(int32_t) * (size_t)(nb + 1));
+    memcpy(fill, first, sizeof(int32_t) * (size_t)(nb + 1));
+    for (int t = 0; t < T->n; ++t) order[fill[T->bin[t]]++] = t;
+    free(fill);
+}
+
+/* L_t and M_b of the particles (see the header). */
+void or_tracer_observe(const or_cfg *c, int64_t N, const double *x, const double *y, const double *z,
+                       const double *vx, const double *vy, const double *vz, const double *w,
+                       double *L, double *M) {
+    const or_tracers *T = &c->trc;
+    const or_layout *Ly = &c->lay;
+    int nb = binning_nbins(Ly, T->binning);
+    int32_t *first = (int32_t *)malloc(sizeof(int32_t) * (size_t)(nb + 1));
+    int32_t *order = (int32_t *)malloc(sizeof(int32_t) * (size_t)(T->n > 0 ? T->n : 1));
+    tracer_lists(c, nb, first, order);
+    double ci = cos(Ly->incl), si = sin(Ly->incl);
+    for (int t = 0; t < T->n; ++t) L[t] = 0.0;
+    for (int b = 0; b < nb; ++b) M[b] = 0.0;
+    for (int64_t i = 0; i < N; ++i) {
+        int b = bin_of(Ly, T->binning, ci, si, x[i], y[i], z[i]);
+        if (b < 0) continue;
+        double vl = vy[i] * si + vz[i] * ci;
+        M[b] += w[i];
+        for (int e = first[b]; e < first[b + 1]; ++e) {
+            int t = order[e];
+            L[t] += w[i] * normal_density(vl, T->v[t], T->s[t]);
+        }
+    }
+    free(first); free(order);
+}
+
 /* Leapfrog kick-drift-kick over dt (reading of "evolved in the potential"). */
 static void push(const or_pot *p, const double *A, const double *B, double dt,
                  double *x, double *y, double *z, double *vx, double *vy, double *vz) {
@@ -677,6 +747,23 @@ int or_step(const or_cfg *c, or_state *s) {
         chi2i += di * di;
     }
     s->chi2 = chi2; s->chi2_inst = chi2i;
+    /* 1-3 for the tracers */
+    const or_tracers *T = &c->trc;
+    int tnb = T->n > 0 ? binning_nbins(&c->lay, T->binning) : 0;
+    int32_t *tfirst = NULL, *torder = NULL;
+    if (T->n > 0) {
+        or_tracer_observe(c, N, s->x, s->y, s->z, s->vx, s->vy, s->vz, s->w, s->tLobs, s->tMobs);
+        for (int t = 0; t < T->n; ++t)
+            s->tL[t] = s->n == 0 ? s->tLobs[t] : s->tL[t] + g * (s->tLobs[t] - s->tL[t]);
+        for (int b = 0; b < tnb; ++b)
+            s->tM[b] = s->n == 0 ? s->tMobs[b] : s->tM[b] + g * (s->tMobs[b] - s->tM[b]);
+        double ll = 0.0;
+        for (int t = 0; t < T->n; ++t) ll += log(s->tL[t] / s->tM[T->bin[t]]);
+        s->loglike = ll;
+        tfirst = (int32_t *)malloc(sizeof(int32_t) * (size_t)(tnb + 1));
+        torder = (int32_t *)malloc(sizeof(int32_t) * (size_t)T->n);
+        tracer_lists(c, tnb, tfirst, torder);
+    }
     /* 4 prior */
     if (P->kind == OR_PRIOR_FLAT) {
         for (int64_t i = 0; i < N; ++i) s->what[i] = P->flat_value;
@@ -706,12 +793,25 @@ int or_step(const or_cfg *c, or_state *s) {
         double chi_term = 0.0;
         for (int e = 0; e < n; ++e) chi_term += K[e] * s->delta[jj[e]] / c->sigma[jj[e]];
         double G = -chi_term - c->mu * (log(s->w[i] / s->what[i]) + 1.0);
+        if (T->n > 0) {
+            int b = bin_of(&c->lay, T->binning, cos(c->lay.incl), sin(c->lay.incl), s->x[i], s->y[i], s->z[i]);
+            if (b >= 0) {
+                double vl = s->vy[i] * sin(c->lay.incl) + s->vz[i] * cos(c->lay.incl);
+                double lt = 0.0;
+                for (int e = tfirst[b]; e < tfirst[b + 1]; ++e) {
+                    int t = torder[e];
+                    lt += normal_density(vl, T->v[t], T->s[t]) / s->tL[t];
+                }
+                G += T->lambda * (lt - (tfirst[b + 1] - tfirst[b]) / s->tM[b]);
+            }
+        }
         double wn = c->update == 1 ? s->w[i] * exp(c->eps * c->dt * G)
                                    : s->w[i] * (1.0 + c->eps * c->dt * G);
         if (!isfinite(wn)) bad |= 2;
         else if (wn <= 0.0) bad |= 1;
         s->w[i] = wn;
     }
+    free(tfirst); free(torder);
     if (bad) {
         s->status = (bad & 2) ? OR_NONFINITE : OR_NONPOSITIVE;
         s->bad_step = s->n;

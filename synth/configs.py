@@ -156,6 +156,32 @@ def cfg_fig1_run(ics, prior="moving", eps=None):
     return c
 
 
+_PNE_CACHE = {}
+
+
+def _pne_tracers(n, dv):
+    """(bin, v) of n tracers drawn from the 2^20-particle Osipkov-Merritt
+    realisation (memoised: the realisation takes seconds)."""
+    if (n, dv) not in _PNE_CACHE:
+        if "real" not in _PNE_CACHE:
+            _PNE_CACHE["real"] = galaxy.hernquist_om_ics(1 << 20, seed_for(1, 8), 1.0)
+        _PNE_CACHE[(n, dv)] = targets.discrete_tracers(layout_cfg1(), 1, _PNE_CACHE["real"], n, dv, seed_for(1, 9))
+    return _PNE_CACHE[(n, dv)]
+
+
+def cfg_pne(N=20000, steps=2000, n_tracers=2000, precision="f64", lam=1.0, dv=0.05, h=0.05):
+    """Discrete line-of-sight velocities (planetary-nebula-like tracers) added to
+    the cfg 1 model: n_tracers drawn from a 2^20-particle realisation of its
+    Osipkov-Merritt target, each binned in the annuli (binning 1) with a velocity
+    error dv; kernel width sqrt(dv^2 + h^2); weight lam of the log-likelihood in
+    the merit function."""
+    c = cfg1(N, steps)
+    c.update({"name": "pne_%s_N%d_T%d" % (precision, N, n_tracers), "precision": precision})
+    b, v = _pne_tracers(n_tracers, dv)
+    c["tracers"] = {"binning": 1, "bin": b, "v": v, "dv": np.full(b.size, dv), "h": h, "lambda": lam}
+    return c
+
+
 def mlp_init(seed):
     """Initial parameters of the 3-64-64-1 prior network (FP32): weights normal
     with variance 1/fan-in, biases zero; W1[64,3], b1, W2[64,64], b2, W3[1,64], b3."""

@@ -355,3 +355,18 @@ def add_noise(layout, Y_true, M_b, f, seed, f_gh=None):
     g = rng.normal(0.0, 1.0, Y_true.size)
     del moment
     return Y_true + sigma * g, sigma
+
+
+def discrete_tracers(layout, ib, ics, n, dv, seed):
+    """Discrete tracers (planetary-nebula-like) drawn from a target realisation:
+    n of its particles at random, each with its bin in binning ib (those outside
+    the binning are skipped) and its line-of-sight velocity plus a Gaussian error
+    of dispersion dv.  Returns (bin, v) of the kept tracers."""
+    rng = np.random.default_rng(seed)
+    idx = rng.choice(ics.shape[1], size=n, replace=False)
+    sub = ics[:, idx]
+    k, _ = _bin_index(layout["binnings"][ib], sub, layout["incl"])
+    inc = layout["incl"]
+    vlos = sub[4] * np.sin(inc) + sub[5] * np.cos(inc)
+    ok = k >= 0
+    return k[ok].astype(np.int32), vlos[ok] + dv * rng.standard_normal(int(ok.sum()))
