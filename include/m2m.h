@@ -310,6 +310,40 @@ m2m_status m2m_delta_chi2(m2m_ctx *ctx, double *chi2, double *delta, int32_t *be
 #define M2M_SHELL_MAX 256
 m2m_status m2m_shell_moments(m2m_ctx *ctx, int32_t model, const double *edges, int32_t nshell, double *out);
 
+/* Paper section 1 lists PNe velocities among the data: discrete tracers, each
+ * with a sky position and one line-of-sight velocity.  Reading (the likelihood
+ * term of NMAGIC's discrete-velocity fits): tracer t lies in bin b_t of one
+ * layout binning (an annulus or sky-grid binning); its likelihood is the
+ * model's line-of-sight velocity density at V_t in that bin,
+ *   L_t = sum_i w_i [bin(z_i) = b_t] phi(v_los,i; V_t, s_t),  M_b = sum_i w_i [bin(z_i) = b],
+ * both smoothed over time like the observables, and lambda sum_t ln(L_t / M_(b_t))
+ * joins the merit function; the weight update gains its gradient
+ *   lambda (sum_{t in b(z_i)} phi(v_los,i; V_t, s_t) / L_t - n_(b(z_i)) / M_(b(z_i)))
+ * (phi the normal density of width s_t, n_b the tracers in bin b). */
+typedef struct {
+    int32_t binning;        /* index of the layout binning the tracers are binned in */
+    int32_t n;              /* tracers, 1 .. M2M_TRACERS_MAX                          */
+    const int32_t *bin;     /* n: the tracer's bin within that binning               */
+    const double *v;        /* n: its line-of-sight velocity                         */
+    const double *width;    /* n: kernel width s_t > 0 (velocity error and smoothing) */
+    double lambda;          /* weight of the log-likelihood in the merit function    */
+} m2m_tracers;
+#define M2M_TRACERS_MAX 8192
+
+/* Attach discrete tracers to a single-model context before its first step (a
+ * fixed analytic potential; not with the learned prior).  Host arrays, copied.
+ * Observes the tracers in the initial state (their smoothed sums start there).
+ * INVALID for a bad binning index or bin, n outside [1, M2M_TRACERS_MAX], a
+ * width <= 0, a non-finite value, a step already taken or tracers already set;
+ * UNSUPPORTED for batched, multipole or learned-prior contexts. */
+m2m_status m2m_set_tracers(m2m_ctx *ctx, const m2m_tracers *tracers);
+
+/* The tracers' smoothed sums of the current state and their log-likelihood
+ * sum_t ln(L_t / M_(b_t)): loglike (host scalar), L (n values, in the order the
+ * tracers were given), M (the binning's bins); each nullable.  Synchronises the
+ * context's stream.  INVALID without tracers. */
+m2m_status m2m_tracer_state(m2m_ctx *ctx, double *loglike, double *L, double *M);
+
 /* Node coefficients of a MULTIPOLE model (sections 1 and 2: the potential
  * computed from the particles), as used by the first kick of the next step:
  * A and B, nnode * (lmax+1)^2 FP64 values each (host; node k at k*(lmax+1)^2,

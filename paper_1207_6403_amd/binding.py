@@ -45,6 +45,11 @@ class m2m_binning(C.Structure):
                 ("gh", C.POINTER(C.c_double))]
 
 
+class m2m_tracers(C.Structure):
+    _fields_ = [("binning", C.c_int32), ("n", C.c_int32), ("bin", C.POINTER(C.c_int32)),
+                ("v", C.POINTER(C.c_double)), ("width", C.POINTER(C.c_double)), ("lam", C.c_double)]
+
+
 class m2m_obs_layout(C.Structure):
     _fields_ = [("incl", C.c_double), ("nbin", C.c_int32), ("reserved", C.c_int32),
                 ("bin", m2m_binning * MAX_BINNINGS)]
@@ -109,6 +114,8 @@ def lib():
         L.m2m_multipole_tables.argtypes = [CTX, C.POINTER(C.c_double), C.POINTER(C.c_double)]
         L.m2m_delta_chi2.argtypes = [CTX, C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_int32)]
         L.m2m_shell_moments.argtypes = [CTX, C.c_int32, C.POINTER(C.c_double), C.c_int32, C.POINTER(C.c_double)]
+        L.m2m_set_tracers.argtypes = [CTX, C.POINTER(m2m_tracers)]
+        L.m2m_tracer_state.argtypes = [CTX] + [C.POINTER(C.c_double)] * 3
         L.m2m_mlp_state.argtypes = [CTX, C.POINTER(C.c_float), C.POINTER(C.c_double), C.POINTER(C.c_int32),
                                     C.POINTER(C.c_int64)]
         L.m2m_mlp_loss_grad.argtypes = [CTX, C.POINTER(C.c_float), C.POINTER(C.c_float), C.c_int32,
@@ -123,7 +130,7 @@ def lib():
         L.m2m_last_error.argtypes = [CTX]
         L.m2m_last_error.restype = C.c_char_p
         for f in ("m2m_create", "m2m_step", "m2m_observables", "m2m_weights", "m2m_priors", "m2m_particles",
-                  "m2m_history", "m2m_multipole_tables", "m2m_delta_chi2", "m2m_shell_moments", "m2m_mlp_state", "m2m_mlp_loss_grad", "m2m_mlp_loss_grad_noalloc", "m2m_autotune", "m2m_get_launch", "m2m_set_launch", "m2m_kernel_time"):
+                  "m2m_history", "m2m_multipole_tables", "m2m_delta_chi2", "m2m_shell_moments", "m2m_set_tracers", "m2m_tracer_state", "m2m_mlp_state", "m2m_mlp_loss_grad", "m2m_mlp_loss_grad_noalloc", "m2m_autotune", "m2m_get_launch", "m2m_set_launch", "m2m_kernel_time"):
             getattr(L, f).restype = C.c_int
         if L.m2m_abi_version() != ABI_VERSION:
             raise ImportError("libm2m_hip.so ABI %d, binding expects %d" % (L.m2m_abi_version(), ABI_VERSION))
@@ -298,7 +305,34 @@ def m2m_create(cfg, xv, w, Y, sigma, Erange=None, device_ptrs=False, stream=None
         raise M2MError(st, m2m_last_error(None))
     pr = cfg["prior"]
     ncell = 0 if pr["kind"] == "flat" else int(np.prod(pr["shape"]))
-    return Context(out, n, t.J, M, dt, ncell, lay.nbin)
+    ctx = Context(out, n, t.J, M, dt, ncell, lay.nbin)
+    if cfg.get("tracers"):
+        m2m_set_tracers(ctx, cfg["tracers"])
+    return ctx
+
+
+def m2m_set_tracers(ctx, tr):
+    """Attach discrete tracers {"binning", "bin", "v", "dv", "h", "lambda"}: kernel
+    widths sqrt(dv^2 + h^2)."""
+    b = np.ascontiguousarray(tr["bin"], dtype=np.int32)
+    v = np.ascontiguousarray(tr["v"], dtype=np.float64)
+    wd = np.ascontiguousarray(np.sqrt(np.asarray(tr["dv"], dtype=np.float64) ** 2 + float(tr["h"]) ** 2))
+    t = m2m_tracers()
+    t.binning, t.n, t.lam = int(tr["binning"]), b.size, float(tr["lambda"])
+    t.bin = b.ctypes.data_as(C.POINTER(C.c_int32))
+    t.v, t.width = _dp(v), _dp(wd)
+    _check(lib().m2m_set_tracers(ctx.ptr, C.byref(t)), ctx)
+    ctx.n_tracers = b.size
+
+
+def m2m_tracer_state(ctx, nb):
+    """(log-likelihood, smoothed L per tracer, smoothed M per bin of the tracers'
+    binning (nb bins)) of the current state."""
+    ll = C.c_double()
+    L = np.zeros(ctx.n_tracers)
+    M = np.zeros(nb)
+    _check(lib().m2m_tracer_state(ctx.ptr, C.byref(ll), _dp(L), _dp(M)), ctx)
+    return ll.value, L, M
 
 
 def _stats_dict(s):

@@ -17,7 +17,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libm2m_hip.so")
 BUILD = os.path.join(ROOT, "_build")
 
-SOURCES = ["step.hip", "cells.hip", "multipole.hip", "mlp.hip", "finalize.hip", "moments.hip", "api.hip"]
+SOURCES = ["step.hip", "cells.hip", "multipole.hip", "mlp.hip", "finalize.hip", "moments.hip", "tracers.hip", "api.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -416,6 +416,7 @@ static void fill_step_args(m2m_ctx* c, StepArgs<T, T>& a, int parity, int mode, 
     a.edges = (const T*)c->edges;
     a.edges64 = c->edges64;
     a.ghtab = (const T*)c->ghtab;
+    a.extra = nullptr;
     a.nedge = c->nedge;
     a.pcols = c->pcols;
     a.jpad = c->JP;
@@ -603,6 +604,40 @@ static GatherArgs<T> gather_args(m2m_ctx* c, int k, int what_mode, T* out) {
     return a;
 }
 
+// Tracer kernels' arguments for the state in buffer k.
+template <typename T>
+static TracerArgs<T> tracer_args(const m2m_ctx* c, int k, int first_obs) {
+    TracerArgs<T> a{};
+    a.state = (const T*)c->state[k];
+    a.stride = c->stride;
+    a.n = c->N;
+    a.tagrow = c->trc_binning;
+    a.ntr = c->trc_n;
+    a.nb = c->trc_nb;
+    a.sini = (T)std::sin(c->lay.incl);
+    a.cosi = (T)std::cos(c->lay.incl);
+    a.first = c->trc_first;
+    a.V = (const T*)c->trc_V;
+    a.is = (const T*)c->trc_is;
+    a.nf = (const T*)c->trc_nf;
+    a.cL = (const T*)c->trc_cL;
+    a.cM = (const T*)c->trc_cM;
+    a.extra = (T*)c->trc_extra;
+    a.part = c->trc_part;
+    a.nblk = c->trc_nblk;
+    a.Ls = c->trc_Ls;
+    a.Ms = c->trc_Ms;
+    a.cL_out = (T*)c->trc_cL;
+    a.cM_out = (T*)c->trc_cM;
+    a.loglike = c->trc_ll;
+    a.tbin = c->trc_tbin;
+    a.g = c->dt / c->tau;
+    a.lambda = c->trc_lambda;
+    a.first_obs = first_obs;
+    a.flag = c->flag;
+    return a;
+}
+
 template <typename T>
 static hipError_t launch_one_T(m2m_ctx* c, int64_t n, hipEvent_t e0, hipEvent_t e1) {
     int wm, acc;
@@ -645,12 +680,20 @@ static hipError_t launch_one_T(m2m_ctx* c, int64_t n, hipEvent_t e0, hipEvent_t 
             e = launch_step<T, T>(o, c->pot_kind, c->sig, c->lay.nbin, p.ilp, p.nblock, p.threads, p.lds, c->stream);
         }
     } else {
+        if (c->trc_n) {
+            // the tracers' term of G for every particle of state n
+            if ((e = launch_tracer_grad<T>(tracer_args<T>(c, (int)(n & 1), 0), c->stream)) != hipSuccess) return e;
+            a.flags |= kTracers;
+            a.extra = (const T*)c->trc_extra;
+        }
         if (e0) (void)hipEventRecord(e0, c->stream);
         e = launch_step<T, T>(a, c->pot_kind, c->sig, c->lay.nbin, p.ilp, p.nblock, p.threads, p.lds, c->stream);
     }
     if (e1) (void)hipEventRecord(e1, c->stream);
     if (e != hipSuccess) return e;
     if (c->cells_apart && acc && (e = launch_cells_after<T>(c, (int)((n + 1) & 1))) != hipSuccess) return e;
+    if (c->trc_n && (e = launch_tracer_observe<T>(tracer_args<T>(c, (int)((n + 1) & 1), 0), c->stream)) != hipSuccess)
+        return e;
     FinArgs<T, T> f;
     fill_fin_args<T>(c, f, 0, acc, (int)(n & 1));
     return launch_finalize<T, T>(f, c->stream);
@@ -1490,6 +1533,91 @@ extern "C" m2m_status m2m_delta_chi2(m2m_ctx* c, double* chi2, double* delta, in
     return M2M_OK;
 }
 
+// ------------------------------------------------------------------ tracers
+template <typename T>
+static m2m_status set_tracers_T(m2m_ctx* c, const m2m_tracers* t) {
+    const int n = t->n, nb = c->trc_nb;
+    // CSR by bin (stable), the caller's order kept in perm
+    std::vector<int32_t> first(nb + 1, 0), order(n), tbin(n);
+    for (int k = 0; k < n; ++k) first[t->bin[k] + 1] += 1;
+    for (int b = 0; b < nb; ++b) first[b + 1] += first[b];
+    std::vector<int32_t> fill(first.begin(), first.end() - 1);
+    c->trc_perm.assign(n, 0);
+    for (int k = 0; k < n; ++k) {
+        const int pos = fill[t->bin[k]]++;
+        order[pos] = k;
+        c->trc_perm[k] = pos;
+    }
+    std::vector<T> V(n), is(n), nf(n);
+    for (int q = 0; q < n; ++q) {
+        const int k = order[q];
+        tbin[q] = t->bin[k];
+        V[q] = (T)t->v[k];
+        is[q] = (T)(1.0 / t->width[k]);
+        nf[q] = (T)(1.0 / (std::sqrt(2.0 * M_PI) * t->width[k]));
+    }
+    c->trc_nblk = (int)std::max<int64_t>(1, std::min<int64_t>(kTrcBlocks, (c->N + 1023) / 1024));
+    m2m_status s;
+    if ((s = upload(c, &c->trc_first, first)) || (s = upload(c, &c->trc_tbin, tbin)) ||
+        (s = upload(c, (T**)&c->trc_V, V)) || (s = upload(c, (T**)&c->trc_is, is)) ||
+        (s = upload(c, (T**)&c->trc_nf, nf)) || (s = dalloc(c, (T**)&c->trc_cL, (size_t)n)) ||
+        (s = dalloc(c, (T**)&c->trc_cM, (size_t)nb)) || (s = dalloc(c, (T**)&c->trc_extra, (size_t)c->stride)) ||
+        (s = dalloc(c, &c->trc_part, (size_t)c->trc_nblk * (n + nb))) || (s = dalloc(c, &c->trc_Ls, (size_t)n)) ||
+        (s = dalloc(c, &c->trc_Ms, (size_t)nb)) || (s = dalloc(c, &c->trc_ll, 1)))
+        return s;
+    c->trc_lambda = t->lambda;
+    c->trc_n = n;
+    const TracerArgs<T> a = tracer_args<T>(c, 0, 1);
+    const size_t lds = tracer_lds<T>(a);
+    if (lds > (size_t)c->max_lds) {
+        c->trc_n = 0;
+        return fail(c, M2M_ERR_UNSUPPORTED, "tracers need " + std::to_string(lds) + " bytes of LDS per block");
+    }
+    HIPCHK(c, set_tracer_lds_limit<T>(lds));
+    // the initial state's sums start the smoothing
+    HIPCHK(c, launch_tracer_observe<T>(a, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return M2M_OK;
+}
+
+extern "C" m2m_status m2m_set_tracers(m2m_ctx* c, const m2m_tracers* t) {
+    if (!c) return fail(nullptr, M2M_ERR_INVALID, "ctx is NULL");
+    if (!t || !t->bin || !t->v || !t->width) return fail(c, M2M_ERR_INVALID, "null argument");
+    if (c->M != 1 || c->mp || c->prior.kind == M2M_PRIOR_MLP)
+        return fail(c, M2M_ERR_UNSUPPORTED, "tracers need a single-model context with an analytic potential "
+                                            "and no learned prior");
+    if (c->trc_n) return fail(c, M2M_ERR_INVALID, "tracers are already set");
+    if (c->step != 0) return fail(c, M2M_ERR_INVALID, "tracers must be set before the first step");
+    if (t->binning < 0 || t->binning >= c->lay.nbin) return fail(c, M2M_ERR_INVALID, "binning index out of range");
+    if (t->n < 1 || t->n > M2M_TRACERS_MAX) return fail(c, M2M_ERR_INVALID, "n must be in [1, 4096]");
+    if (!is_fin(t->lambda)) return fail(c, M2M_ERR_INVALID, "lambda must be finite");
+    const m2m_binning& d = c->lay.bin[t->binning];
+    const int nb = d.kind == M2M_BIN_GRID ? d.nx * d.ny : d.nedge - 1;
+    for (int k = 0; k < t->n; ++k) {
+        if (t->bin[k] < 0 || t->bin[k] >= nb) return fail(c, M2M_ERR_INVALID, "tracer bin out of range");
+        if (!is_fin(t->v[k])) return fail(c, M2M_ERR_INVALID, "tracer velocities must be finite");
+        if (!(t->width[k] > 0.0) || !is_fin(t->width[k])) return fail(c, M2M_ERR_INVALID, "widths must be > 0");
+    }
+    if (c->status == M2M_ERR_DEVICE) return c->status;
+    c->trc_binning = t->binning;
+    c->trc_nb = nb;
+    return c->prec == M2M_F64 ? set_tracers_T<double>(c, t) : set_tracers_T<float>(c, t);
+}
+
+extern "C" m2m_status m2m_tracer_state(m2m_ctx* c, double* loglike, double* L, double* M) {
+    if (!c) return fail(nullptr, M2M_ERR_INVALID, "ctx is NULL");
+    if (!c->trc_n) return fail(c, M2M_ERR_INVALID, "the context has no tracers");
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (loglike) HIPCHK(c, hipMemcpy(loglike, c->trc_ll, sizeof(double), hipMemcpyDeviceToHost));
+    if (L) {
+        std::vector<double> Ls(c->trc_n);
+        HIPCHK(c, hipMemcpy(Ls.data(), c->trc_Ls, sizeof(double) * c->trc_n, hipMemcpyDeviceToHost));
+        for (int k = 0; k < c->trc_n; ++k) L[k] = Ls[c->trc_perm[k]];
+    }
+    if (M) HIPCHK(c, hipMemcpy(M, c->trc_Ms, sizeof(double) * c->trc_nb, hipMemcpyDeviceToHost));
+    return M2M_OK;
+}
+
 // ------------------------------------------------------------ shell moments
 extern "C" m2m_status m2m_shell_moments(m2m_ctx* c, int32_t model, const double* edges, int32_t nshell, double* out) {
     if (!c) return fail(nullptr, M2M_ERR_INVALID, "ctx is NULL");
@@ -1673,6 +1801,13 @@ static m2m_status snapshot(m2m_ctx* c, Snapshot& s, bool restore) {
                                {c->cellmean, MC * ts}, {c->cellmean64, MC * 8}, {c->chunk_chi, 4 * (size_t)c->nchunk * 8},
                                {c->ring, sizeof(StatRow) * (size_t)c->M * kRing}, {c->d_step, 16}};
     if (c->what) items.push_back({c->what, (size_t)c->stride * ts});
+    if (c->trc_n) {
+        items.push_back({c->trc_Ls, (size_t)c->trc_n * 8});
+        items.push_back({c->trc_Ms, (size_t)c->trc_nb * 8});
+        items.push_back({c->trc_cL, (size_t)c->trc_n * ts});
+        items.push_back({c->trc_cM, (size_t)c->trc_nb * ts});
+        items.push_back({c->trc_ll, 8});
+    }
     if (c->mlp_theta) {
         items.push_back({c->mlp_theta, sizeof(float) * kMlpNP});
         items.push_back({c->mlp_m, sizeof(float) * kMlpNP});

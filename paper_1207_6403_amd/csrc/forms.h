@@ -160,4 +160,50 @@ struct ShellArgs {
 template <typename T>
 hipError_t launch_shell_moments(const ShellArgs<T>& a, int blocks, double* out, hipStream_t s);
 
+// Discrete tracers (tracers.hip): tracers grouped by bin (first[b] .. first[b+1]),
+// each with its velocity V, inverse width is = 1/s and density factor
+// nf = 1/(sqrt(2 pi) s); per tracer the smoothed sum Ls and the update factor
+// cL = lambda / Ls, per bin the smoothed mass Ms and cM = -lambda n_b / Ms.
+constexpr int kTrcThreads = 256;
+constexpr int kTrcBlocks = 512;
+template <typename T>
+struct TracerArgs {
+    const T* state;          // state buffer (value rows, then tag rows)
+    int64_t stride, n;
+    int32_t tagrow;          // tag row of the tracers' binning
+    int32_t ntr, nb;
+    T sini, cosi;
+    const int32_t* first;    // nb + 1
+    const T* V;
+    const T* is;
+    const T* nf;
+    const T* cL;             // ntr
+    const T* cM;             // nb
+    T* extra;                // n: the likelihood's term of G (tracer_grad)
+    double* part;            // blocks x (ntr + nb) partial sums (tracer_observe)
+    int32_t nblk;            // blocks of tracer_observe
+    double* Ls;              // ntr smoothed sums
+    double* Ms;              // nb smoothed masses
+    T* cL_out;
+    T* cM_out;
+    double* loglike;
+    const int32_t* tbin;     // ntr: bin of each tracer (CSR order)
+    double g;                // dt / tau
+    double lambda;
+    int32_t first_obs;       // 1: the smoothed sums start at this observation
+    const int* flag;
+};
+// Sums L_t, M_b of the state (per-block partials), then their smoothing, the
+// log-likelihood and the update factors (one block).
+template <typename T>
+hipError_t launch_tracer_observe(const TracerArgs<T>& a, hipStream_t s);
+// extra[p] of every particle of the state.
+template <typename T>
+hipError_t launch_tracer_grad(const TracerArgs<T>& a, hipStream_t s);
+// Dynamic LDS the tracer kernels need, and the attribute that allows it.
+template <typename T>
+size_t tracer_lds(const TracerArgs<T>& a);
+template <typename T>
+hipError_t set_tracer_lds_limit(size_t lds);
+
 }  // namespace m2m

@@ -88,6 +88,17 @@ struct m2m_ctx {
     bool cells_apart = false;
     size_t cells_lds = 0;
     m2m::Cells cells{};
+    // discrete tracers: CSR by bin (first, bin of each), per tracer V, 1/s,
+    // 1/(sqrt(2 pi) s), update factors, smoothed sums, the likelihood's term of
+    // G per particle, block partials; perm: CSR position of the caller's tracer k
+    int trc_n = 0, trc_binning = -1, trc_nb = 0, trc_nblk = 0;
+    double trc_lambda = 0;
+    std::vector<int32_t> trc_perm;
+    int32_t* trc_first = nullptr;
+    int32_t* trc_tbin = nullptr;
+    void *trc_V = nullptr, *trc_is = nullptr, *trc_nf = nullptr, *trc_cL = nullptr, *trc_cM = nullptr;
+    void* trc_extra = nullptr;
+    double *trc_part = nullptr, *trc_Ls = nullptr, *trc_Ms = nullptr, *trc_ll = nullptr;
     // device
     hipStream_t stream = nullptr;
     bool own_stream = false;

@@ -176,7 +176,7 @@ __device__ __forceinline__ T weight_update(const StepArgs<T, PT>& a, const Blk<T
     // (FP32: the hardware log, exp and reciprocal, a few ulp each; the FP64
     // kernels use the exact forms)
     const T lr = qlog_ratio(qdiv(w, wh));
-    const T G = -chi - a.mu * (lr + T(1));
+    const T G = -chi - a.mu * (lr + T(1)) + ((fl & kTracers) ? a.extra[p] : T(0));
     const T edt = a.eps * a.dt;
     const T wn = (fl & kExpLaw) ? w * qexp(edt * G) : w * (T(1) + edt * G);
     acc.S -= double(w) * double(lr);

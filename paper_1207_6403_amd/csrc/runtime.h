@@ -66,13 +66,14 @@ struct StepArgs {
     const T* edges;
     const double* edges64;        // the same edges in FP64
     const T* ghtab;               // Gauss-Hermite (V, 1/sigma) pairs (lay.ngh of them)
+    const T* extra;               // kTracers: per particle, the tracer likelihood's term of G
     int32_t nedge;
     int32_t pcols, jpad;
     Layout<T> lay;
     Cells cells;
     const Exact* ex;              // FP64 constants and tables (device memory)
     T dt, eps, mu;
-    uint32_t flags;               // kObserve | kWhat* | kAccum | kExpLaw | kFrozen
+    uint32_t flags;               // kObserve | kWhat* | kAccum | kExpLaw | kFrozen | kTracers
     int32_t cellrow;              // tag row of the prior cell
     int* flag;
     long long* bad_step;
@@ -86,6 +87,7 @@ constexpr uint32_t kWhatShift = 1u;   // 2 bits
 constexpr uint32_t kAccum = 8u;       // decide (and store) the prior cell of the new state
 constexpr uint32_t kExpLaw = 16u;     // w <- w exp(eps dt G), else w (1 + eps dt G)
 constexpr uint32_t kFrozen = 32u;     // particles do not move
+constexpr uint32_t kTracers = 64u;    // G gains extra[p] (discrete tracers' likelihood)
 
 // Tags: per particle and binning, the bin the particle fell in (kNoBin when
 // none), and its prior cell; rows of `stride` uint16 after the 7 value rows.

@@ -1,0 +1,235 @@
+// tracers.hip -- discrete line-of-sight velocities (section 1 lists PNe
+// velocities among the data).  Reading: tracer t in bin b_t of one binning has
+// the likelihood of the model's line-of-sight velocity density at its velocity,
+//   L_t = sum_i w_i [bin(z_i) = b_t] phi(v_los,i; V_t, s_t),  M_b = sum_i w_i [bin(z_i) = b],
+// both smoothed like the observables; lambda sum_t ln(Ls_t / Ms_(b_t)) joins the
+// merit function, and the weight update gains
+//   lambda (sum_{t in b(z_i)} phi(v_los,i; V_t, s_t) / Ls_t - n_(b(z_i)) / Ms_(b(z_i))).
+//
+//   tracer_observe    per block, chunks of particles counting-sorted by bin in
+//                     LDS; each thread owns some tracers and sums w phi over its
+//                     tracers' bins (no atomics on the sums), threads over bins
+//                     sum the masses; per-block partial rows
+//   tracer_finalize   one block: the rows in block order (FP64), smoothing, the
+//                     log-likelihood and the update factors
+//   tracer_grad       per particle: its term of G from the factors of its bin,
+//                     with the bin's tracers in LDS
+// The bin of a particle is its stored tag, so the decisions are the step
+// kernel's (exact at edges).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "forms.h"
+#include "device.h"
+
+namespace m2m {
+
+constexpr int kTrcChunk = 1024;   // particles per chunk of tracer_observe
+
+__device__ __forceinline__ float trc_exp(float v) { return __expf(v); }
+__device__ __forceinline__ double trc_exp(double v) { return exp(v); }
+
+// Exclusive prefix sum of cnt[0..n) in place (cnt[n] gets the total), by all
+// threads of the block: contiguous runs per thread, then a scan of the run sums.
+__device__ void block_exclusive_scan(uint32_t* cnt, int n, uint32_t* wsum) {
+    const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63, wv = tid >> 6;
+    const int per = (n + nt - 1) / nt;
+    const int b0 = min(n, tid * per), b1 = min(n, b0 + per);
+    uint32_t s = 0;
+    for (int b = b0; b < b1; ++b) s += cnt[b];
+    // inclusive scan of the run sums within the wave
+    uint32_t incl = s;
+    #pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t u = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += u;
+    }
+    if (lane == 63) wsum[wv] = incl;
+    __syncthreads();
+    uint32_t before = 0;
+    for (int k = 0; k < wv; ++k) before += wsum[k];
+    uint32_t run = before + incl - s;
+    for (int b = b0; b < b1; ++b) {
+        const uint32_t c = cnt[b];
+        cnt[b] = run;
+        run += c;
+    }
+    if (tid == nt - 1) cnt[n] = run;
+    __syncthreads();
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kTrcThreads) tracer_observe_kernel(TracerArgs<T> a) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int ntr = a.ntr, nb = a.nb, tid = threadIdx.x, nt = blockDim.x;
+    double* acc = reinterpret_cast<double*>(smem);            // ntr, each owned by one thread
+    double* mass = acc + ntr;                                  // nb
+    T* svl = reinterpret_cast<T*>(mass + nb);                  // kTrcChunk, sorted by bin
+    T* sw = svl + kTrcChunk;                                   // kTrcChunk
+    uint32_t* cnt = reinterpret_cast<uint32_t*>(sw + kTrcChunk);   // nb + 1: counts, then starts
+    uint32_t* wsum = cnt + nb + 1;                             // 16
+    if (*a.flag) return;
+    for (int k = tid; k < ntr + nb; k += nt) acc[k] = 0.0;     // (mass follows acc)
+    const uint16_t* tag = reinterpret_cast<const uint16_t*>(a.state + 7 * a.stride) + (size_t)a.tagrow * a.stride;
+    const T* S = a.state;
+    const int64_t st = a.stride;
+    constexpr int kPer = kTrcChunk / kTrcThreads;
+    for (int64_t c0 = (int64_t)blockIdx.x * kTrcChunk; c0 < a.n; c0 += (int64_t)gridDim.x * kTrcChunk) {
+        for (int b = tid; b <= nb; b += nt) cnt[b] = 0u;
+        __syncthreads();
+        int bq[kPer];
+        uint32_t slot[kPer];
+        T vq[kPer], wq[kPer];
+        #pragma unroll
+        for (int q = 0; q < kPer; ++q) {
+            const int64_t p = c0 + tid + q * kTrcThreads;
+            bq[q] = -1;
+            if (p < a.n) {
+                const int b = tag[p];
+                if (b != kNoBin) {
+                    bq[q] = b;
+                    vq[q] = line_of_sight(S[4 * st + p], S[5 * st + p], a.sini, a.cosi);
+                    wq[q] = S[6 * st + p];
+                    slot[q] = atomicAdd(&cnt[b], 1u);
+                }
+            }
+        }
+        __syncthreads();
+        block_exclusive_scan(cnt, nb, wsum);
+        #pragma unroll
+        for (int q = 0; q < kPer; ++q)
+            if (bq[q] >= 0) {
+                const uint32_t pos = cnt[bq[q]] + slot[q];
+                svl[pos] = vq[q];
+                sw[pos] = wq[q];
+            }
+        __syncthreads();
+        for (int b = tid; b < nb; b += nt) {
+            double m = 0.0;
+            for (uint32_t i = cnt[b]; i < cnt[b + 1]; ++i) m += double(sw[i]);
+            mass[b] += m;
+        }
+        for (int t = tid; t < ntr; t += nt) {
+            const int b = a.tbin[t];
+            const T V = a.V[t], is = a.is[t], nf = a.nf[t];
+            double s = 0.0;
+            for (uint32_t i = cnt[b]; i < cnt[b + 1]; ++i) {
+                const T d = (svl[i] - V) * is;
+                s += double(sw[i] * nf * trc_exp(T(-0.5) * d * d));
+            }
+            acc[t] += s;
+        }
+        __syncthreads();
+    }
+    double* dst = a.part + (size_t)blockIdx.x * (ntr + nb);
+    for (int k = tid; k < ntr + nb; k += nt) dst[k] = acc[k];
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) tracer_finalize_kernel(TracerArgs<T> a) {
+    __shared__ double red[256];
+    if (*a.flag) return;
+    const int ntr = a.ntr, nb = a.nb, W = ntr + nb, tid = threadIdx.x;
+    for (int k = tid; k < W; k += 256) {
+        double v = 0.0;
+        for (int q = 0; q < a.nblk; ++q) v += a.part[(size_t)q * W + k];
+        double* sm = k < ntr ? a.Ls + k : a.Ms + (k - ntr);
+        *sm = a.first_obs ? v : *sm + a.g * (v - *sm);
+    }
+    __syncthreads();
+    double ll = 0.0;
+    for (int t = tid; t < ntr; t += 256) {
+        const double Ls = a.Ls[t], Ms = a.Ms[a.tbin[t]];
+        ll += log(Ls / Ms);
+        a.cL_out[t] = T(a.lambda / Ls);
+    }
+    for (int b = tid; b < nb; b += 256) {
+        const int nbt = a.first[b + 1] - a.first[b];
+        a.cM_out[b] = nbt ? T(-a.lambda * nbt / a.Ms[b]) : T(0);
+    }
+    red[tid] = ll;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (tid < o) red[tid] += red[tid + o];
+        __syncthreads();
+    }
+    if (tid == 0) *a.loglike = red[0];
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kTrcThreads) tracer_grad_kernel(TracerArgs<T> a) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int ntr = a.ntr, tid = threadIdx.x, nt = blockDim.x;
+    T* tV = reinterpret_cast<T*>(smem);        // ntr
+    T* tis = tV + ntr;                          // ntr
+    T* tc = tis + ntr;                          // ntr: cL nf
+    if (*a.flag) return;
+    for (int t = tid; t < ntr; t += nt) {
+        tV[t] = a.V[t];
+        tis[t] = a.is[t];
+        tc[t] = a.cL[t] * a.nf[t];
+    }
+    __syncthreads();
+    const uint16_t* tag = reinterpret_cast<const uint16_t*>(a.state + 7 * a.stride) + (size_t)a.tagrow * a.stride;
+    const T* S = a.state;
+    const int64_t st = a.stride;
+    for (int64_t p = (int64_t)blockIdx.x * nt + tid; p < a.n; p += (int64_t)gridDim.x * nt) {
+        const int b = tag[p];
+        T x = T(0);
+        if (b != kNoBin) {
+            const T vl = line_of_sight(S[4 * st + p], S[5 * st + p], a.sini, a.cosi);
+            x = a.cM[b];
+            for (int t = a.first[b]; t < a.first[b + 1]; ++t) {
+                const T d = (vl - tV[t]) * tis[t];
+                x += tc[t] * trc_exp(T(-0.5) * d * d);
+            }
+        }
+        a.extra[p] = x;
+    }
+}
+
+template <typename T>
+static size_t observe_lds(const TracerArgs<T>& a) {
+    return sizeof(double) * (size_t)(a.ntr + a.nb) + 2 * sizeof(T) * kTrcChunk + sizeof(uint32_t) * (a.nb + 1 + 16);
+}
+
+template <typename T>
+hipError_t launch_tracer_observe(const TracerArgs<T>& a, hipStream_t s) {
+    hipLaunchKernelGGL(tracer_observe_kernel<T>, dim3(a.nblk), dim3(kTrcThreads), observe_lds(a), s, a);
+    hipLaunchKernelGGL(tracer_finalize_kernel<T>, dim3(1), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_tracer_grad(const TracerArgs<T>& a, hipStream_t s) {
+    const int blocks = (int)std::min<int64_t>(kTrcBlocks * 4, (a.n + kTrcThreads - 1) / kTrcThreads);
+    hipLaunchKernelGGL(tracer_grad_kernel<T>, dim3(std::max(blocks, 1)), dim3(kTrcThreads),
+                       3 * sizeof(T) * (size_t)a.ntr, s, a);
+    return hipGetLastError();
+}
+
+template <typename T>
+size_t tracer_lds(const TracerArgs<T>& a) {
+    return std::max(observe_lds(a), 3 * sizeof(T) * (size_t)a.ntr);
+}
+
+template <typename T>
+hipError_t set_tracer_lds_limit(size_t lds) {
+    hipError_t e = hipFuncSetAttribute((const void*)tracer_observe_kernel<T>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    return hipFuncSetAttribute((const void*)tracer_grad_kernel<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)lds);
+}
+
+template hipError_t launch_tracer_observe<float>(const TracerArgs<float>&, hipStream_t);
+template hipError_t launch_tracer_observe<double>(const TracerArgs<double>&, hipStream_t);
+template hipError_t launch_tracer_grad<float>(const TracerArgs<float>&, hipStream_t);
+template hipError_t launch_tracer_grad<double>(const TracerArgs<double>&, hipStream_t);
+template size_t tracer_lds<float>(const TracerArgs<float>&);
+template size_t tracer_lds<double>(const TracerArgs<double>&);
+template hipError_t set_tracer_lds_limit<float>(size_t);
+template hipError_t set_tracer_lds_limit<double>(size_t);
+
+}  // namespace m2m

@@ -40,15 +40,16 @@ def test_abi_version():
 def test_struct_layouts_match_header(tmp_path):
     src = tmp_path / "sz.c"
     src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "m2m.h"\n'
-                   'int main(){printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(m2m_config), '
+                   'int main(){printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(m2m_config), '
                    'sizeof(m2m_prior), sizeof(m2m_obs_layout), sizeof(m2m_potential), sizeof(m2m_step_stats), '
-                   'sizeof(m2m_launch), sizeof(m2m_target), offsetof(m2m_config, stream), offsetof(m2m_prior, mlp_init));}\n')
+                   'sizeof(m2m_launch), sizeof(m2m_target), offsetof(m2m_config, stream), offsetof(m2m_prior, mlp_init), '
+                   'sizeof(m2m_tracers), offsetof(m2m_tracers, lambda));}\n')
     exe = tmp_path / "sz"
     subprocess.check_call(["gcc", "-I" + os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
     got = [int(v) for v in subprocess.check_output([str(exe)]).split()]
     want = [C.sizeof(b.m2m_config), C.sizeof(b.m2m_prior), C.sizeof(b.m2m_obs_layout), C.sizeof(b.m2m_potential),
             C.sizeof(b.m2m_step_stats), C.sizeof(b.m2m_launch), C.sizeof(b.m2m_target),
-            b.m2m_config.stream.offset, b.m2m_prior.mlp_init.offset]
+            b.m2m_config.stream.offset, b.m2m_prior.mlp_init.offset, C.sizeof(b.m2m_tracers), b.m2m_tracers.lam.offset]
     assert got == want
 
 
