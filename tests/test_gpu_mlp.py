@@ -143,41 +143,72 @@ def nn_log_roughness(cfg, ics, vals, Erange, Y, sigma):
     return float(np.mean(np.abs(lv - lv[j[:, 1]])))
 
 
-def test_learned_prior_gain_over_histogram_prior():
-    """What the trained network gains over the histogram prior it stands in for, at
-    equal mu (1e5: at the workload's mu = 5e-3 the entropy term is ~1e7 times
-    smaller than the chi^2 force and no prior changes the run): 2^18 particles,
-    2000 steps, refreshes every 25 steps on a 2^15 sample.  The learned prior is a
-    smooth function of the integrals, the histogram prior a noisy piecewise
-    constant: the learned prior must be at least twice as smooth (nearest
-    neighbours in feature space) at chi^2 within 5% of the histogram prior's, with
-    its fallback on.  (It does not lower chi^2 here: the entry records that too.)"""
+def weight_smoothness(cfg, ics, w, Erange, Y, sigma):
+    """W_s = sum_c sum_{i in c} w_i (ln w_i - <ln w>_c)^2 / sum w on a fine 64 x 64 x 16
+    grid of (E, L/Lc, Lz/L) -- finer than, and independent of, every prior's cells --
+    with <ln w>_c the w-weighted mean in cell c (zero for weights constant per cell).
+    Integrals from the oracle in the prior's reference potential."""
+    m = oracle.Model(dict(cfg, prior=dict(cfg["prior"], kind="hist")), ics.astype(np.float64),
+                     np.ones(ics.shape[1]), Y, sigma, Erange=tuple(Erange))
+    E, L, Lz, Lc = m.integrals()
+    iE = np.clip(((E - Erange[0]) / (Erange[1] - Erange[0]) * 64).astype(int), 0, 63)
+    i2 = np.clip((np.where(Lc > 0, L / np.where(Lc > 0, Lc, 1.0), 0.0) * 64).astype(int), 0, 63)
+    i3 = np.clip(((np.where(L > 0, Lz / np.where(L > 0, L, 1.0), 0.0) + 1.0) * 8).astype(int), 0, 15)
+    c = (iE * 64 + i2) * 16 + i3
+    w = np.asarray(w, dtype=np.float64)
+    lw = np.log(w)
+    sw = np.bincount(c, weights=w, minlength=64 * 64 * 16)
+    mean = np.bincount(c, weights=w * lw, minlength=64 * 64 * 16) / np.maximum(sw, 1e-300)
+    return float(np.sum(w * (lw - mean[c]) ** 2) / w.sum())
+
+
+def test_weight_smoothness_at_equal_chi2():
+    """What the moving priors gain (section 2.1: a smoother distribution function):
+    flat, histogram and learned priors at equal mu (2^18 particles, 2000 steps,
+    refreshes every 25 steps on a 2^15 sample).  At mu = 3e4 and 1e5 each moving
+    prior ends with both a lower chi^2 and smoother weights (lower W_s) than the
+    flat prior: it dominates it.  (chi^2 is not monotonic in mu -- some entropy
+    improves the fit -- so the comparison is made at equal mu, not interpolated to
+    equal chi^2.)  The learned prior's weights are slightly smoother than the
+    histogram prior's at a slightly higher chi^2: neither dominates (measured, not
+    asserted).  At the workload's mu = 5e-3 the entropy term is ~1e7 times smaller
+    than the chi^2 force and the three runs agree.  Secondary: the learned prior
+    itself is at least twice as smooth as the histogram prior (nearest neighbours
+    in feature space) at mu = 1e5."""
     base = configs.cfg5(N=1 << 18, target_n=1 << 20)
     base["prior"].update(subset=1 << 15, batch=1024, period=25)
     base["eps"] = 0.1 / (base["dt"] * derive_eps.max_abs_G(base))
-    base["mu"] = 1e5
     inp = H.inputs(base)
     er = H.erange(base, inp)
-    out = {}
-    for name, pr in (("hist", dict(base["prior"], kind="hist")), ("mlp", dict(base["prior"]))):
-        cfg = dict(base, prior=pr)
-        H.flush("case %s prior, N=%d mu=%g" % (name, cfg["N"], cfg["mu"]))
-        ctx = m2m.m2m_create(cfg, inp["ics"], inp["w"], inp["Y"], inp["sigma"], Erange=er)
-        st = m2m.m2m_step(ctx, 2000)[0]
-        x = m2m.m2m_particles(ctx)
-        what = m2m.m2m_priors(ctx)[0]
-        out[name] = (st["chi2"], nn_log_roughness(cfg, x, what, er, inp["Y"], inp["sigma"]),
-                     nn_log_roughness(cfg, x, m2m.m2m_weights(ctx), er, inp["Y"], inp["sigma"]), st["n_eff"])
-        if name == "mlp":
-            out["mlp_state"] = m2m.m2m_mlp_state(ctx)
-    (c_h, rp_h, rw_h, ne_h), (c_m, rp_m, rw_m, ne_m) = out["hist"], out["mlp"]
-    H.flush("hist: chi2 %.6g prior roughness %.4f weight roughness %.4f n_eff %.4g" % (c_h, rp_h, rw_h, ne_h))
-    H.flush("mlp:  chi2 %.6g prior roughness %.4f weight roughness %.4f n_eff %.4g (judge %.3f, fallback %s)" % (
-        c_m, rp_m, rw_m, ne_m, out["mlp_state"]["judge"], out["mlp_state"]["used_fallback"]))
-    assert not out["mlp_state"]["used_fallback"]
-    assert rp_m <= 0.5 * rp_h
-    assert c_m <= 1.05 * c_h
-    assert ne_m >= 0.9 * ne_h
+    curves = {}
+    for name, pr in (("flat", {"kind": "flat"}), ("hist", dict(base["prior"], kind="hist")),
+                     ("mlp", dict(base["prior"]))):
+        pts = []
+        for mu in (5e-3, 1e4, 3e4, 1e5):   # (1e4: recorded)
+            cfg = dict(base, prior=pr, mu=mu)
+            ctx = m2m.m2m_create(cfg, inp["ics"], inp["w"], inp["Y"], inp["sigma"],
+                                 Erange=None if name == "flat" else er)
+            st = m2m.m2m_step(ctx, 2000)[0]
+            x = m2m.m2m_particles(ctx)
+            ws = weight_smoothness(base, x, m2m.m2m_weights(ctx), er, inp["Y"], inp["sigma"])
+            H.flush("%-4s mu %-7g chi2 %10.2f W_s %.5f n_eff %.4g" % (name, mu, st["chi2"], ws, st["n_eff"]))
+            if name == "mlp" and mu == 1e5:
+                assert not m2m.m2m_mlp_state(ctx)["used_fallback"]
+                rp = {"mlp": nn_log_roughness(cfg, x, m2m.m2m_priors(ctx)[0], er, inp["Y"], inp["sigma"])}
+            if name == "hist" and mu == 1e5:
+                rp_h = nn_log_roughness(cfg, x, m2m.m2m_priors(ctx)[0], er, inp["Y"], inp["sigma"])
+            pts.append((mu, st["chi2"], ws))
+            m2m.m2m_destroy(ctx)
+        curves[name] = pts
+    # the workload's mu: no prior acts
+    c0 = [curves[k][0][1] for k in curves]
+    assert max(c0) - min(c0) <= 1e-6 * max(c0)
+    for k in (1, 2):    # mu = 3e4, 1e5
+        fl = curves["flat"][k + 1]
+        for name in ("hist", "mlp"):
+            mu, chi2, ws = curves[name][k + 1]
+            assert chi2 < fl[1] and ws < fl[2], (name, mu, chi2, ws, fl)
+    assert rp["mlp"] <= 0.5 * rp_h
 
 
 def test_learned_prior_on_a_multipole_model():
