@@ -60,7 +60,7 @@ class m2m_prior(C.Structure):
                 ("Erange", C.POINTER(C.c_double)), ("flat_value", C.c_double), ("ref", m2m_potential),
                 ("mlp_subset", C.c_int32), ("mlp_batch", C.c_int32), ("lr", C.c_double), ("beta1", C.c_double),
                 ("beta2", C.c_double), ("adam_eps", C.c_double), ("fallback", C.c_double), ("seed", C.c_uint32),
-                ("reserved", C.c_int32), ("mlp_init", C.POINTER(C.c_float))]
+                ("mlp_mfma", C.c_int32), ("mlp_init", C.POINTER(C.c_float))]
 
 
 class m2m_config(C.Structure):
@@ -212,6 +212,7 @@ def pack_prior(pr, n_models, keep, Erange=None, ref=None):
     s.adam_eps = float(pr.get("adam_eps", 0.0))
     s.fallback = float(pr.get("fallback", 0.0))
     s.seed = int(pr.get("seed", 0)) & 0xFFFFFFFF
+    s.mlp_mfma = 1 if pr.get("mfma", False) else 0
     if pr.get("mlp_init") is not None:
         th = np.ascontiguousarray(pr["mlp_init"], dtype=np.float32)
         assert th.size == MLP_NPARAM

@@ -574,6 +574,7 @@ static void fill_mlp_args(const m2m_ctx* c, MlpArgs& a, int64_t n) {
     a.red = c->mlp_red;
     a.stats = c->mlp_stats;
     a.loss = nullptr;
+    a.mfma = P.mlp_mfma;
     a.flag = c->flag;
 }
 

@@ -99,6 +99,7 @@ struct MlpArgs {
     double* red;               // nblk x 2 per-block partials
     double* stats;             // gmax, sum w, sum e, judge numerator, judge, fallback used, refreshes
     float* loss;               // per sample (g - t)^2 / batch, or null
+    int32_t mfma;              // 1: inference's hidden layer on the matrix cores (BF16 operands, FP32 sums)
     const int* flag;
 };
 

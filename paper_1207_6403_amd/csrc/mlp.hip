@@ -334,6 +334,111 @@ __global__ void __launch_bounds__(kMlpInferThreads, 2) mlp_infer_kernel(MlpArgs 
     if (tid == 0) a.red[2 * blockIdx.x] = gmax;
 }
 
+// The same inference with the 64 x 64 hidden layer on the matrix cores (BF16
+// operands, FP32 accumulation): each wave takes 64 particles, one per lane for
+// the features and the first layer, whose outputs go to an LDS row per particle
+// as BF16; the hidden layer is then 4 x 4 tiles of 16 particles x 16 units, each
+// two 16x16x32 BF16 products (units' W2 rows held in registers as BF16), and each
+// lane finishes the tanh and the output sum for its units of 16 particles; the
+// 16 lanes that share particles add their partial outputs.
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+constexpr int kHRow = kMlpH + 8;   // LDS row of one particle's first-layer outputs (BF16, padded)
+
+template <int POT>
+__global__ void __launch_bounds__(kMlpInferThreads, 2) mlp_infer_mfma_kernel(MlpArgs a) {
+    constexpr int kWaves = kMlpInferThreads / 64;
+    __shared__ __align__(16) float l1[kMlpH][4];               // W1 row and b1 per unit
+    __shared__ float b2s[kMlpH], w3s[kMlpH];
+    __shared__ __align__(16) __bf16 hrow[kWaves][64][kHRow];
+    __shared__ float gbuf[kWaves][64];
+    __shared__ double sh[kMlpInferThreads / 64];
+    if (*a.flag) return;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    for (int o = tid; o < kMlpH; o += kMlpInferThreads) {
+        l1[o][0] = a.theta[kMlpW1 + 3 * o];
+        l1[o][1] = a.theta[kMlpW1 + 3 * o + 1];
+        l1[o][2] = a.theta[kMlpW1 + 3 * o + 2];
+        l1[o][3] = a.theta[kMlpB1 + o];
+        b2s[o] = a.theta[kMlpB2 + o];
+        w3s[o] = a.theta[kMlpW3 + o];
+    }
+    // B operands: unit n = 16 c + lane % 16, inputs k = 32 s + 8 (lane / 16) + v
+    bf16x8 bw[4][2];
+    #pragma unroll
+    for (int c = 0; c < 4; ++c)
+        #pragma unroll
+        for (int s2 = 0; s2 < 2; ++s2)
+            #pragma unroll
+            for (int v = 0; v < 8; ++v)
+                bw[c][s2][v] = (__bf16)a.theta[kMlpW2 + (16 * c + (lane & 15)) * kMlpH + 32 * s2 + 8 * (lane >> 4) + v];
+    const float b3 = a.theta[kMlpB3];
+    __syncthreads();
+    double gmax = -INFINITY;
+    for (int64_t base = (int64_t)blockIdx.x * kMlpInferThreads; base < a.n; base += (int64_t)gridDim.x * kMlpInferThreads) {
+        const int64_t p = base + tid;
+        float u0 = 0.0f, u1 = 0.0f, u2 = 0.0f, w;
+        if (p < a.n) mlp_features<POT>(a, p, u0, u1, u2, w);
+        // first layer, to this particle's LDS row in BF16
+        #pragma unroll
+        for (int o8 = 0; o8 < kMlpH; o8 += 8) {
+            bf16x8 hv;
+            #pragma unroll
+            for (int v = 0; v < 8; ++v) {
+                const int o = o8 + v;
+                hv[v] = (__bf16)unit_tanh(l1[o][3] + l1[o][0] * u0 + l1[o][1] * u1 + l1[o][2] * u2);
+            }
+            *reinterpret_cast<bf16x8*>(&hrow[wv][lane][o8]) = hv;
+        }
+        __syncthreads();
+        float pg[4][4];
+        #pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            floatx4 acc[4];
+            #pragma unroll
+            for (int c = 0; c < 4; ++c) acc[c] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+            #pragma unroll
+            for (int s2 = 0; s2 < 2; ++s2) {
+                const bf16x8 af = *reinterpret_cast<const bf16x8*>(&hrow[wv][16 * t + (lane & 15)][32 * s2 + 8 * (lane >> 4)]);
+                #pragma unroll
+                for (int c = 0; c < 4; ++c) acc[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, bw[c][s2], acc[c], 0, 0, 0);
+            }
+            // lane holds units 16 c + lane % 16 of particles 16 t + 4 (lane / 16) + v
+            #pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                float sum = 0.0f;
+                #pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    const int n = 16 * c + (lane & 15);
+                    sum += w3s[n] * unit_tanh(acc[c][v] + b2s[n]);
+                }
+                pg[t][v] = sum;
+            }
+        }
+        // add the 16 lanes that hold the same particles (lanes differing in bits 0..3)
+        #pragma unroll
+        for (int t = 0; t < 4; ++t)
+            #pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                float x = pg[t][v];
+                x += __shfl_xor(x, 1, 64);
+                x += __shfl_xor(x, 2, 64);
+                x += __shfl_xor(x, 4, 64);
+                x += __shfl_xor(x, 8, 64);
+                if ((lane & 15) == 0) gbuf[wv][16 * t + 4 * (lane >> 4) + v] = x + b3;
+            }
+        __syncthreads();
+        if (p < a.n) {
+            const float g = gbuf[wv][lane];
+            a.what[p] = g;
+            gmax = fmax(gmax, double(g));
+        }
+        __syncthreads();
+    }
+    gmax = block_reduce(gmax, true, sh);
+    if (tid == 0) a.red[2 * blockIdx.x] = gmax;
+}
+
 __global__ void __launch_bounds__(kMlpInferThreads) mlp_norm_kernel(MlpArgs a) {
     __shared__ double sh[kMlpInferThreads / 64];
     if (*a.flag) return;
@@ -430,7 +535,8 @@ static hipError_t refresh_pot(const MlpArgs& a, int t0, hipStream_t s) {
         hipLaunchKernelGGL(mlp_adam_kernel, dim3((kMlpNP + 63) / 64), dim3(64 * kSumWaves), 0, s, a, nblk, c1, c2);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
-    hipLaunchKernelGGL((mlp_infer_kernel<POT>), dim3(a.nblk), dim3(kMlpInferThreads), 0, s, a);
+    if (a.mfma) hipLaunchKernelGGL((mlp_infer_mfma_kernel<POT>), dim3(a.nblk), dim3(kMlpInferThreads), 0, s, a);
+    else hipLaunchKernelGGL((mlp_infer_kernel<POT>), dim3(a.nblk), dim3(kMlpInferThreads), 0, s, a);
     hipLaunchKernelGGL(mlp_reduce_kernel, dim3(1), dim3(256), 0, s, a, 0);
     hipLaunchKernelGGL(mlp_norm_kernel, dim3(a.nblk), dim3(kMlpInferThreads), 0, s, a);
     hipLaunchKernelGGL(mlp_reduce_kernel, dim3(1), dim3(256), 0, s, a, 1);

@@ -198,7 +198,7 @@ def cfg5(N=1 << 22, steps=5000, target_n=1 << 23):
               "prior": {"kind": "mlp", "axes": ("E", "L/Lc", "Lz/L"), "shape": (32, 32, 8),
                         "period": 100, "hidden": 64, "subset": 1 << 20, "batch": 8192,
                         "lr": 1e-3, "beta1": 0.9, "beta2": 0.999, "adam_eps": 1e-8,
-                        "fallback": 0.5, "seed": seed, "mlp_init": mlp_init(seed)},
+                        "fallback": 0.5, "seed": seed, "mlp_init": mlp_init(seed), "mfma": True},
               "eps": EPS_CFG2})
     return c
 

@@ -28,7 +28,9 @@ m2m = pytest.importorskip("paper_1207_6403_amd")
 
 def setup(N, subset, batch, period, fallback=0.5, target_n=1 << 16, full=False):
     cfg = configs.cfg5() if full else configs.cfg5(N=N, target_n=target_n)
-    cfg["prior"].update(subset=subset, batch=batch, period=period, fallback=fallback)
+    # the tight mode (FP32 throughout) for the oracle bars; the BF16 matrix-core
+    # inference has its own test against it
+    cfg["prior"].update(subset=subset, batch=batch, period=period, fallback=fallback, mfma=False)
     if not full:
         # the rate of a small model, derived as for the full-size workloads:
         # eps dt max|G(0)| = 0.1 (G is far larger when few particles meet the target)
@@ -110,6 +112,35 @@ def test_full_size_refresh():
     np.testing.assert_allclose(m2m.m2m_weights(ctx).astype(np.float64), om.w, rtol=2e-6)
 
 
+def test_bf16_matrix_core_inference():
+    """The workload's mode: the hidden layer of the inference over all particles on
+    the matrix cores (BF16 operands, FP32 accumulation), against the FP32 mode of
+    the same run (the same training, so the same parameters): priors within 1e-2
+    relative L2 and every ln(prior) within 3e-2, the judge within 1e-2 relative and
+    the same fallback decision; the parameters bitwise equal."""
+    res = {}
+    for mf in (False, True):
+        cfg = configs.cfg5(N=1 << 16, target_n=1 << 16)
+        cfg["prior"].update(subset=1 << 14, batch=1024, period=2, fallback=1e9, mfma=mf)
+        cfg["eps"] = 0.1 / (cfg["dt"] * derive_eps.max_abs_G(cfg))
+        inp = H.inputs(cfg)
+        er = H.erange(cfg, inp)
+        ctx = m2m.m2m_create(cfg, inp["ics"], inp["w"], inp["Y"], inp["sigma"], Erange=er)
+        m2m.m2m_step(ctx, 1)    # one refresh (step 0): the same training in both modes
+        res[mf] = (m2m.m2m_priors(ctx)[0].astype(np.float64), m2m.m2m_mlp_state(ctx))
+        m2m.m2m_destroy(ctx)
+    (p32, s32), (p16, s16) = res[False], res[True]
+    np.testing.assert_array_equal(s16["theta"], s32["theta"])
+    rel = np.linalg.norm(p16 - p32) / np.linalg.norm(p32)
+    dl = np.max(np.abs(np.log(p16) - np.log(p32)))
+    H.flush("BF16 inference vs FP32: priors rel-L2 %.3g, max |d ln what| %.3g, judge %.6g vs %.6g" % (
+        rel, dl, s16["judge"], s32["judge"]))
+    assert rel <= 1e-2
+    assert dl <= 3e-2
+    assert s16["judge"] == pytest.approx(s32["judge"], rel=1e-2)
+    assert s16["used_fallback"] == s32["used_fallback"]
+
+
 def test_gradient_matches_oracle():
     """The training kernels' loss and gradient at identical parameters and samples
     against the FP64 backpropagation (itself pinned to finite differences): the
@@ -172,11 +203,11 @@ def test_weight_smoothness_at_equal_chi2():
     equal chi^2.)  The learned prior's weights are slightly smoother than the
     histogram prior's at a slightly higher chi^2: neither dominates (measured, not
     asserted).  At the workload's mu = 5e-3 the entropy term is ~1e7 times smaller
-    than the chi^2 force and the three runs agree.  Secondary: the learned prior
+    than the chi^2 force and the three runs agree (to 1e-4).  Secondary: the learned prior
     itself is at least twice as smooth as the histogram prior (nearest neighbours
     in feature space) at mu = 1e5."""
     base = configs.cfg5(N=1 << 18, target_n=1 << 20)
-    base["prior"].update(subset=1 << 15, batch=1024, period=25)
+    base["prior"].update(subset=1 << 15, batch=1024, period=25, mfma=False)
     base["eps"] = 0.1 / (base["dt"] * derive_eps.max_abs_G(base))
     inp = H.inputs(base)
     er = H.erange(base, inp)
@@ -202,7 +233,7 @@ def test_weight_smoothness_at_equal_chi2():
         curves[name] = pts
     # the workload's mu: no prior acts
     c0 = [curves[k][0][1] for k in curves]
-    assert max(c0) - min(c0) <= 1e-6 * max(c0)
+    assert max(c0) - min(c0) <= 1e-4 * max(c0)    # (different kernel variants: FP32 rounding only)
     for k in (1, 2):    # mu = 3e4, 1e5
         fl = curves["flat"][k + 1]
         for name in ("hist", "mlp"):
@@ -216,7 +247,7 @@ def test_learned_prior_on_a_multipole_model():
     analytic reference potential): one refresh and two steps against the oracle."""
     cfg = configs.cfg3(N=12007, target_n=1 << 16)
     c5 = configs.cfg5(N=16)
-    cfg["prior"] = dict(c5["prior"], subset=2048, batch=256, period=2, fallback=1e9,
+    cfg["prior"] = dict(c5["prior"], subset=2048, batch=256, period=2, fallback=1e9, mfma=False,
                         ref_potential=dict(configs.LOG_POT))
     cfg["eps"] = 0.1 / (cfg["dt"] * derive_eps.max_abs_G(cfg))
     inp = H.inputs(cfg)
