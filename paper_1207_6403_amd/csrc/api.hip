@@ -431,8 +431,11 @@ static void fill_step_args(m2m_ctx* c, StepArgs<T, T>& a, int parity, int mode, 
         a.cells.ncell = 0;
         accum = 0;
     }
-    a.flags = (mode == 1 ? kObserve : 0u) | ((uint32_t)what_mode << kWhatShift) | (accum ? kAccum : 0u) |
-              (c->update == 1 ? kExpLaw : 0u) | (c->frozen ? kFrozen : 0u);
+    // (an observe-only pass neither updates nor moves: the law and frozen flags
+    // are left out, so that it matches the compiled-in observe flags)
+    a.flags = mode == 1 ? kObserve | ((uint32_t)what_mode << kWhatShift) | (accum ? kAccum : 0u)
+                        : ((uint32_t)what_mode << kWhatShift) | (accum ? kAccum : 0u) |
+                              (c->update == 1 ? kExpLaw : 0u) | (c->frozen ? kFrozen : 0u);
     a.cellrow = c->lay.nbin;
     a.flag = c->flag;
     a.bad_step = c->bad_step;
@@ -625,6 +628,7 @@ static TracerArgs<T> tracer_args(const m2m_ctx* c, int k, int first_obs) {
     a.cM = (const T*)c->trc_cM;
     a.extra = (T*)c->trc_extra;
     a.part = c->trc_part;
+    a.colsum = c->trc_colsum;
     a.nblk = c->trc_nblk;
     a.Ls = c->trc_Ls;
     a.Ms = c->trc_Ms;
@@ -1557,13 +1561,14 @@ static m2m_status set_tracers_T(m2m_ctx* c, const m2m_tracers* t) {
         is[q] = (T)(1.0 / t->width[k]);
         nf[q] = (T)(1.0 / (std::sqrt(2.0 * M_PI) * t->width[k]));
     }
-    c->trc_nblk = (int)std::max<int64_t>(1, std::min<int64_t>(kTrcBlocks, (c->N + 1023) / 1024));
+    c->trc_nblk = (int)std::max<int64_t>(1, std::min<int64_t>(std::min(kTrcBlocks, c->numCU), (c->N + 1023) / 1024));
     m2m_status s;
     if ((s = upload(c, &c->trc_first, first)) || (s = upload(c, &c->trc_tbin, tbin)) ||
         (s = upload(c, (T**)&c->trc_V, V)) || (s = upload(c, (T**)&c->trc_is, is)) ||
         (s = upload(c, (T**)&c->trc_nf, nf)) || (s = dalloc(c, (T**)&c->trc_cL, (size_t)n)) ||
         (s = dalloc(c, (T**)&c->trc_cM, (size_t)nb)) || (s = dalloc(c, (T**)&c->trc_extra, (size_t)c->stride)) ||
-        (s = dalloc(c, &c->trc_part, (size_t)c->trc_nblk * (n + nb))) || (s = dalloc(c, &c->trc_Ls, (size_t)n)) ||
+        (s = dalloc(c, &c->trc_part, (size_t)c->trc_nblk * (n + nb))) || (s = dalloc(c, &c->trc_colsum, (size_t)(n + nb))) ||
+        (s = dalloc(c, &c->trc_Ls, (size_t)n)) ||
         (s = dalloc(c, &c->trc_Ms, (size_t)nb)) || (s = dalloc(c, &c->trc_ll, 1)))
         return s;
     c->trc_lambda = t->lambda;

@@ -166,7 +166,7 @@ hipError_t launch_shell_moments(const ShellArgs<T>& a, int blocks, double* out, 
 // nf = 1/(sqrt(2 pi) s); per tracer the smoothed sum Ls and the update factor
 // cL = lambda / Ls, per bin the smoothed mass Ms and cM = -lambda n_b / Ms.
 constexpr int kTrcThreads = 256;
-constexpr int kTrcBlocks = 512;
+constexpr int kTrcBlocks = 256;
 template <typename T>
 struct TracerArgs {
     const T* state;          // state buffer (value rows, then tag rows)
@@ -182,6 +182,7 @@ struct TracerArgs {
     const T* cM;             // nb
     T* extra;                // n: the likelihood's term of G (tracer_grad)
     double* part;            // blocks x (ntr + nb) partial sums (tracer_observe)
+    double* colsum;          // ntr + nb: their column sums
     int32_t nblk;            // blocks of tracer_observe
     double* Ls;              // ntr smoothed sums
     double* Ms;              // nb smoothed masses

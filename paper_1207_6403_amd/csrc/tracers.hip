@@ -10,8 +10,9 @@
 //                     LDS; each thread owns some tracers and sums w phi over its
 //                     tracers' bins (no atomics on the sums), threads over bins
 //                     sum the masses; per-block partial rows
-//   tracer_finalize   one block: the rows in block order (FP64), smoothing, the
-//                     log-likelihood and the update factors
+//   tracer_sum        the rows' column sums in a fixed order (FP64)
+//   tracer_finalize   one block: smoothing, the log-likelihood and the update
+//                     factors
 //   tracer_grad       per particle: its term of G from the factors of its bin,
 //                     with the bin's tracers in LDS
 // The bin of a particle is its stored tag, so the decisions are the step
@@ -25,7 +26,8 @@
 
 namespace m2m {
 
-constexpr int kTrcChunk = 1024;   // particles per chunk of tracer_observe
+constexpr int kTrcChunk = 2048;   // particles per chunk of tracer_observe
+constexpr int kTrcObsThreads = 1024;   // threads of tracer_observe (one block per CU)
 
 __device__ __forceinline__ float trc_exp(float v) { return __expf(v); }
 __device__ __forceinline__ double trc_exp(double v) { return exp(v); }
@@ -60,7 +62,7 @@ __device__ void block_exclusive_scan(uint32_t* cnt, int n, uint32_t* wsum) {
 }
 
 template <typename T>
-__global__ void __launch_bounds__(kTrcThreads) tracer_observe_kernel(TracerArgs<T> a) {
+__global__ void __launch_bounds__(kTrcObsThreads) tracer_observe_kernel(TracerArgs<T> a) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int ntr = a.ntr, nb = a.nb, tid = threadIdx.x, nt = blockDim.x;
     double* acc = reinterpret_cast<double*>(smem);            // ntr, each owned by one thread
@@ -74,7 +76,7 @@ __global__ void __launch_bounds__(kTrcThreads) tracer_observe_kernel(TracerArgs<
     const uint16_t* tag = reinterpret_cast<const uint16_t*>(a.state + 7 * a.stride) + (size_t)a.tagrow * a.stride;
     const T* S = a.state;
     const int64_t st = a.stride;
-    constexpr int kPer = kTrcChunk / kTrcThreads;
+    constexpr int kPer = kTrcChunk / kTrcObsThreads;
     for (int64_t c0 = (int64_t)blockIdx.x * kTrcChunk; c0 < a.n; c0 += (int64_t)gridDim.x * kTrcChunk) {
         for (int b = tid; b <= nb; b += nt) cnt[b] = 0u;
         __syncthreads();
@@ -83,7 +85,7 @@ __global__ void __launch_bounds__(kTrcThreads) tracer_observe_kernel(TracerArgs<
         T vq[kPer], wq[kPer];
         #pragma unroll
         for (int q = 0; q < kPer; ++q) {
-            const int64_t p = c0 + tid + q * kTrcThreads;
+            const int64_t p = c0 + tid + q * kTrcObsThreads;
             bq[q] = -1;
             if (p < a.n) {
                 const int b = tag[p];
@@ -126,14 +128,35 @@ __global__ void __launch_bounds__(kTrcThreads) tracer_observe_kernel(TracerArgs<
     for (int k = tid; k < ntr + nb; k += nt) dst[k] = acc[k];
 }
 
+// Column sums of the block rows: a block per 64 columns, its four waves each
+// adding a quarter of the rows (16 loads in flight), the quarters added in wave
+// order (a fixed order).
+template <typename T>
+__global__ void __launch_bounds__(256) tracer_sum_kernel(TracerArgs<T> a) {
+    __shared__ double sh[4][64];
+    if (*a.flag) return;
+    const int W = a.ntr + a.nb, lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int col = blockIdx.x * 64 + lane, cc = min(col, W - 1);
+    double s = 0.0;
+    for (int q0 = wv; q0 < a.nblk; q0 += 4 * 16) {
+        double v[16];
+        #pragma unroll
+        for (int u = 0; u < 16; ++u) v[u] = a.part[(size_t)min(q0 + 4 * u, a.nblk - 1) * W + cc];
+        #pragma unroll
+        for (int u = 0; u < 16; ++u) s += q0 + 4 * u < a.nblk ? v[u] : 0.0;
+    }
+    sh[wv][lane] = s;
+    __syncthreads();
+    if (wv == 0 && col < W) a.colsum[col] = ((sh[0][lane] + sh[1][lane]) + sh[2][lane]) + sh[3][lane];
+}
+
 template <typename T>
 __global__ void __launch_bounds__(256) tracer_finalize_kernel(TracerArgs<T> a) {
     __shared__ double red[256];
     if (*a.flag) return;
     const int ntr = a.ntr, nb = a.nb, W = ntr + nb, tid = threadIdx.x;
     for (int k = tid; k < W; k += 256) {
-        double v = 0.0;
-        for (int q = 0; q < a.nblk; ++q) v += a.part[(size_t)q * W + k];
+        const double v = a.colsum[k];
         double* sm = k < ntr ? a.Ls + k : a.Ms + (k - ntr);
         *sm = a.first_obs ? v : *sm + a.g * (v - *sm);
     }
@@ -196,7 +219,8 @@ static size_t observe_lds(const TracerArgs<T>& a) {
 
 template <typename T>
 hipError_t launch_tracer_observe(const TracerArgs<T>& a, hipStream_t s) {
-    hipLaunchKernelGGL(tracer_observe_kernel<T>, dim3(a.nblk), dim3(kTrcThreads), observe_lds(a), s, a);
+    hipLaunchKernelGGL(tracer_observe_kernel<T>, dim3(a.nblk), dim3(kTrcObsThreads), observe_lds(a), s, a);
+    hipLaunchKernelGGL(tracer_sum_kernel<T>, dim3((a.ntr + a.nb + 63) / 64), dim3(256), 0, s, a);
     hipLaunchKernelGGL(tracer_finalize_kernel<T>, dim3(1), dim3(256), 0, s, a);
     return hipGetLastError();
 }
