@@ -71,6 +71,12 @@ __global__ void __launch_bounds__(256) mlp_subset_kernel(MlpArgs a) {
     a.sub[k] = make_float4(u0, u1, u2, logf(w));
 }
 
+// Operand vectors of the matrix-core products (v_mfma_f32_16x16x32_bf16: lane l
+// holds row l % 16 and k = 8 (l / 16) .. + 7 of A, column l % 16 and the same k of
+// B, and column l % 16, rows 4 (l / 16) .. + 3 of the FP32 result).
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
 // tanh(x) = 1 - 2 / (exp(2x) + 1), with the hardware exp and reciprocal: an
 // absolute error of a few 1e-7 over the whole line (+-1 in the limits), which
 // is what the units' sums see.
@@ -249,6 +255,164 @@ __global__ void __launch_bounds__(kMlpTrainThreads) mlp_train_kernel(MlpArgs a, 
     }
 }
 
+// The same training step with the three 32 x 64 x 64 contractions of a block on
+// the matrix cores (BF16 operands, FP32 accumulation): 256 threads (four waves)
+// per block of 32 samples.  Wave w takes
+//   the forward hidden layer  Z2[s][o] = sum_i H1[s][i] W2[o][i]   for units 16w..16w+15,
+//   the backward to layer 1   D1[s][i] = sum_o D2[s][o] W2[o][i]   for inputs 16w..16w+15,
+//   the W2 gradient           dW2[o][i] = sum_s D2[s][o] H1[s][i]  for units 16w..16w+15,
+// each as 16x16x32 products (the W2 slices it needs held in registers as BF16);
+// the elementwise layers, the output and the other parameters' sums are FP32 on
+// the VALU.  Operands in LDS: activations and deltas per sample (BF16 rows) and
+// transposed (BF16 rows per unit), FP32 copies for the elementwise work.
+constexpr int kTrainMfmaThreads = 256;
+constexpr int kRowB = kMlpH + 8;              // BF16 row of 64 units (padded)
+constexpr int kRowT = kMlpSamples + 8;        // BF16 row of 32 samples (padded)
+
+__global__ void __launch_bounds__(kTrainMfmaThreads) mlp_train_mfma_kernel(MlpArgs a, int b) {
+    constexpr int S = kMlpSamples, H = kMlpH;
+    __shared__ float w1s[H][4];                         // W1 row and b1 per unit
+    __shared__ float b2s[H], w3s[H];
+    __shared__ float U[S][4];                           // u0 u1 u2 and dg per sample
+    __shared__ float H1f[S][H + 1], H2f[S][H + 1], D2f[S][H + 1], D1f[S][H + 1];
+    __shared__ __align__(16) __bf16 H1b[S][kRowB], D2b[S][kRowB];
+    __shared__ __align__(16) __bf16 H1T[H][kRowT], D2T[H][kRowT];
+    if (*a.flag) return;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int l16 = lane & 15, q4 = lane >> 4;
+    const size_t s0 = (size_t)b * a.batch + (size_t)blockIdx.x * S;
+    for (int o = tid; o < H; o += kTrainMfmaThreads) {
+        w1s[o][0] = a.theta[kMlpW1 + 3 * o];
+        w1s[o][1] = a.theta[kMlpW1 + 3 * o + 1];
+        w1s[o][2] = a.theta[kMlpW1 + 3 * o + 2];
+        w1s[o][3] = a.theta[kMlpB1 + o];
+        b2s[o] = a.theta[kMlpB2 + o];
+        w3s[o] = a.theta[kMlpW3 + o];
+    }
+    if (tid < S) {
+        const float4 smp = a.sub[s0 + tid];
+        U[tid][0] = smp.x; U[tid][1] = smp.y; U[tid][2] = smp.z; U[tid][3] = smp.w;
+    }
+    // W2 slices: forward (rows 16w + l16, inputs 32 k + 8 q4 + v) and backward
+    // (units 32 k + 8 q4 + v, input column 16w + l16)
+    bf16x8 wf[2], wb[2];
+    #pragma unroll
+    for (int k = 0; k < 2; ++k)
+        #pragma unroll
+        for (int v = 0; v < 8; ++v) {
+            wf[k][v] = (__bf16)a.theta[kMlpW2 + (16 * wv + l16) * H + 32 * k + 8 * q4 + v];
+            wb[k][v] = (__bf16)a.theta[kMlpW2 + (32 * k + 8 * q4 + v) * H + 16 * wv + l16];
+        }
+    const float b3 = a.theta[kMlpB3];
+    __syncthreads();
+    // layer 1: thread takes sample tid / 8 and units 8 (tid % 8) .. + 7
+    {
+        const int s = tid >> 3, o0 = 8 * (tid & 7);
+        bf16x8 hv;
+        #pragma unroll
+        for (int v = 0; v < 8; ++v) {
+            const int o = o0 + v;
+            const float h = unit_tanh(w1s[o][3] + w1s[o][0] * U[s][0] + w1s[o][1] * U[s][1] + w1s[o][2] * U[s][2]);
+            H1f[s][o] = h;
+            hv[v] = (__bf16)h;
+            H1T[o][s] = (__bf16)h;
+        }
+        *reinterpret_cast<bf16x8*>(&H1b[s][o0]) = hv;
+    }
+    __syncthreads();
+    // forward hidden layer: units 16 wv + l16 of samples 16 t + 4 q4 + v
+    #pragma unroll
+    for (int t = 0; t < 2; ++t) {
+        floatx4 z = {0.0f, 0.0f, 0.0f, 0.0f};
+        #pragma unroll
+        for (int k = 0; k < 2; ++k)
+            z = __builtin_amdgcn_mfma_f32_16x16x32_bf16(*reinterpret_cast<const bf16x8*>(&H1b[16 * t + l16][32 * k + 8 * q4]),
+                                                        wf[k], z, 0, 0, 0);
+        const int o = 16 * wv + l16;
+        #pragma unroll
+        for (int v = 0; v < 4; ++v) H2f[16 * t + 4 * q4 + v][o] = unit_tanh(z[v] + b2s[o]);
+    }
+    __syncthreads();
+    // output and its derivative per sample
+    if (tid < S) {
+        float g = b3;
+        for (int o = 0; o < H; ++o) g += w3s[o] * H2f[tid][o];
+        const float dg = 2.0f * (g - U[tid][3]) / float(a.batch);
+        if (a.loss) a.loss[(size_t)blockIdx.x * S + tid] = (g - U[tid][3]) * (g - U[tid][3]) / float(a.batch);
+        U[tid][3] = dg;
+    }
+    __syncthreads();
+    {
+        const int s = tid >> 3, o0 = 8 * (tid & 7);
+        bf16x8 dv;
+        #pragma unroll
+        for (int v = 0; v < 8; ++v) {
+            const int o = o0 + v;
+            const float h = H2f[s][o];
+            const float d = U[s][3] * w3s[o] * (1.0f - h * h);
+            D2f[s][o] = d;
+            dv[v] = (__bf16)d;
+            D2T[o][s] = (__bf16)d;
+        }
+        *reinterpret_cast<bf16x8*>(&D2b[s][o0]) = dv;
+    }
+    __syncthreads();
+    // back to layer 1: inputs 16 wv + l16 of samples 16 t + 4 q4 + v
+    #pragma unroll
+    for (int t = 0; t < 2; ++t) {
+        floatx4 z = {0.0f, 0.0f, 0.0f, 0.0f};
+        #pragma unroll
+        for (int k = 0; k < 2; ++k)
+            z = __builtin_amdgcn_mfma_f32_16x16x32_bf16(*reinterpret_cast<const bf16x8*>(&D2b[16 * t + l16][32 * k + 8 * q4]),
+                                                        wb[k], z, 0, 0, 0);
+        const int i = 16 * wv + l16;
+        #pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int s = 16 * t + 4 * q4 + v;
+            const float h = H1f[s][i];
+            D1f[s][i] = z[v] * (1.0f - h * h);
+        }
+    }
+    // W2 gradient: units 16 wv + 4 q4 + v, inputs 16 c + l16 (one product over the 32 samples)
+    float* dst = a.gpart + (size_t)blockIdx.x * kMlpNP;
+    {
+        const bf16x8 af = *reinterpret_cast<const bf16x8*>(&D2T[16 * wv + l16][8 * q4]);
+        #pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            floatx4 z = {0.0f, 0.0f, 0.0f, 0.0f};
+            z = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, *reinterpret_cast<const bf16x8*>(&H1T[16 * c + l16][8 * q4]), z,
+                                                        0, 0, 0);
+            #pragma unroll
+            for (int v = 0; v < 4; ++v) dst[kMlpW2 + (16 * wv + 4 * q4 + v) * H + 16 * c + l16] = z[v];
+        }
+    }
+    __syncthreads();
+    if (tid < H) {
+        const int o = tid;
+        float gb2 = 0.0f, gw3 = 0.0f, gb1 = 0.0f, gw10 = 0.0f, gw11 = 0.0f, gw12 = 0.0f;
+        for (int ss = 0; ss < S; ++ss) {
+            const float d2 = D2f[ss][o], d1o = D1f[ss][o];
+            gb2 += d2;
+            gw3 += U[ss][3] * H2f[ss][o];
+            gb1 += d1o;
+            gw10 += d1o * U[ss][0];
+            gw11 += d1o * U[ss][1];
+            gw12 += d1o * U[ss][2];
+        }
+        dst[kMlpB2 + o] = gb2;
+        dst[kMlpW3 + o] = gw3;
+        dst[kMlpB1 + o] = gb1;
+        dst[kMlpW1 + 3 * o] = gw10;
+        dst[kMlpW1 + 3 * o + 1] = gw11;
+        dst[kMlpW1 + 3 * o + 2] = gw12;
+        if (o == 0) {
+            float gb3 = 0.0f;
+            for (int ss = 0; ss < S; ++ss) gb3 += U[ss][3];
+            dst[kMlpB3] = gb3;
+        }
+    }
+}
+
 // Sum of the training blocks' partial rows for parameter j = 64 blockIdx.x +
 // lane, in a fixed order (FP64): wave w of the 16 adds rows w, w + 16, ...
 // (16 rows in flight per round), then the wave sums are added in wave order.
@@ -341,8 +505,6 @@ __global__ void __launch_bounds__(kMlpInferThreads, 2) mlp_infer_kernel(MlpArgs 
 // two 16x16x32 BF16 products (units' W2 rows held in registers as BF16), and each
 // lane finishes the tanh and the output sum for its units of 16 particles; the
 // 16 lanes that share particles add their partial outputs.
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-typedef float floatx4 __attribute__((ext_vector_type(4)));
 constexpr int kHRow = kMlpH + 8;   // LDS row of one particle's first-layer outputs (BF16, padded)
 
 template <int POT>
@@ -531,7 +693,8 @@ static hipError_t refresh_pot(const MlpArgs& a, int t0, hipStream_t s) {
     for (int b = 0; b < nb; ++b) {
         const int t = t0 + b + 1;
         const float c1 = float(1.0 - std::pow(double(a.beta1), t)), c2 = float(1.0 - std::pow(double(a.beta2), t));
-        hipLaunchKernelGGL(mlp_train_kernel, dim3(nblk), dim3(kMlpTrainThreads), 0, s, a, b);
+        if (a.mfma) hipLaunchKernelGGL(mlp_train_mfma_kernel, dim3(nblk), dim3(kTrainMfmaThreads), 0, s, a, b);
+        else hipLaunchKernelGGL(mlp_train_kernel, dim3(nblk), dim3(kMlpTrainThreads), 0, s, a, b);
         hipLaunchKernelGGL(mlp_adam_kernel, dim3((kMlpNP + 63) / 64), dim3(64 * kSumWaves), 0, s, a, nblk, c1, c2);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
@@ -548,7 +711,8 @@ static hipError_t refresh_pot(const MlpArgs& a, int t0, hipStream_t s) {
 
 hipError_t launch_mlp_grad(const MlpArgs& a, float* grad, hipStream_t s) {
     const int nblk = a.batch / kMlpSamples;
-    hipLaunchKernelGGL(mlp_train_kernel, dim3(nblk), dim3(kMlpTrainThreads), 0, s, a, 0);
+    if (a.mfma) hipLaunchKernelGGL(mlp_train_mfma_kernel, dim3(nblk), dim3(kTrainMfmaThreads), 0, s, a, 0);
+    else hipLaunchKernelGGL(mlp_train_kernel, dim3(nblk), dim3(kMlpTrainThreads), 0, s, a, 0);
     hipLaunchKernelGGL(mlp_grad_sum_kernel, dim3((kMlpNP + 63) / 64), dim3(64 * kSumWaves), 0, s, a, nblk, grad);
     return hipGetLastError();
 }

@@ -26,11 +26,11 @@ pytestmark = pytest.mark.gpu
 m2m = pytest.importorskip("paper_1207_6403_amd")
 
 
-def setup(N, subset, batch, period, fallback=0.5, target_n=1 << 16, full=False):
+def setup(N, subset, batch, period, fallback=0.5, target_n=1 << 16, full=False, mfma=False):
     cfg = configs.cfg5() if full else configs.cfg5(N=N, target_n=target_n)
     # the tight mode (FP32 throughout) for the oracle bars; the BF16 matrix-core
     # inference has its own test against it
-    cfg["prior"].update(subset=subset, batch=batch, period=period, fallback=fallback, mfma=False)
+    cfg["prior"].update(subset=subset, batch=batch, period=period, fallback=fallback, mfma=mfma)
     if not full:
         # the rate of a small model, derived as for the full-size workloads:
         # eps dt max|G(0)| = 0.1 (G is far larger when few particles meet the target)
@@ -112,40 +112,44 @@ def test_full_size_refresh():
     np.testing.assert_allclose(m2m.m2m_weights(ctx).astype(np.float64), om.w, rtol=2e-6)
 
 
-def test_bf16_matrix_core_inference():
-    """The workload's mode: the hidden layer of the inference over all particles on
-    the matrix cores (BF16 operands, FP32 accumulation), against the FP32 mode of
-    the same run (the same training, so the same parameters): priors within 1e-2
-    relative L2 and every ln(prior) within 3e-2, the judge within 1e-2 relative and
-    the same fallback decision; the parameters bitwise equal."""
+def test_bf16_matrix_core_mode():
+    """The workload's mode -- the hidden-layer contractions of the training and of
+    the inference over all particles on the matrix cores (BF16 operands, FP32
+    accumulation) -- against the FP32 mode of the same run after one refresh
+    (128 Adam steps on BF16 gradients against FP32 ones): priors within 1e-2
+    relative L2 and every ln(prior) within 5e-2, the judge within 1e-2 relative and
+    the same fallback decision."""
     res = {}
     for mf in (False, True):
         cfg = configs.cfg5(N=1 << 16, target_n=1 << 16)
-        cfg["prior"].update(subset=1 << 14, batch=1024, period=2, fallback=1e9, mfma=mf)
+        cfg["prior"].update(subset=1 << 17, batch=1024, period=2, fallback=1e9, mfma=mf)
         cfg["eps"] = 0.1 / (cfg["dt"] * derive_eps.max_abs_G(cfg))
         inp = H.inputs(cfg)
         er = H.erange(cfg, inp)
         ctx = m2m.m2m_create(cfg, inp["ics"], inp["w"], inp["Y"], inp["sigma"], Erange=er)
-        m2m.m2m_step(ctx, 1)    # one refresh (step 0): the same training in both modes
+        m2m.m2m_step(ctx, 1)    # one refresh (step 0)
         res[mf] = (m2m.m2m_priors(ctx)[0].astype(np.float64), m2m.m2m_mlp_state(ctx))
         m2m.m2m_destroy(ctx)
     (p32, s32), (p16, s16) = res[False], res[True]
-    np.testing.assert_array_equal(s16["theta"], s32["theta"])
     rel = np.linalg.norm(p16 - p32) / np.linalg.norm(p32)
     dl = np.max(np.abs(np.log(p16) - np.log(p32)))
-    H.flush("BF16 inference vs FP32: priors rel-L2 %.3g, max |d ln what| %.3g, judge %.6g vs %.6g" % (
-        rel, dl, s16["judge"], s32["judge"]))
+    dth = np.max(np.abs(s16["theta"] - s32["theta"]))
+    H.flush("BF16 mode vs FP32: priors rel-L2 %.3g, max |d ln what| %.3g, judge %.6g vs %.6g, max |d theta| %.3g" % (
+        rel, dl, s16["judge"], s32["judge"], dth))
     assert rel <= 1e-2
-    assert dl <= 3e-2
+    assert dl <= 5e-2
     assert s16["judge"] == pytest.approx(s32["judge"], rel=1e-2)
     assert s16["used_fallback"] == s32["used_fallback"]
 
 
-def test_gradient_matches_oracle():
+@pytest.mark.parametrize("mfma", [False, True])
+def test_gradient_matches_oracle(mfma):
     """The training kernels' loss and gradient at identical parameters and samples
-    against the FP64 backpropagation (itself pinned to finite differences): the
-    gradient within 1e-5 relative L2 (FP32), the loss within 1e-6."""
-    cfg, ctx, om, lp = setup(4096, 512, 128, 4)
+    against the FP64 backpropagation (itself pinned to finite differences): FP32,
+    the gradient within 1e-5 relative L2 and the loss within 1e-6; BF16 matrix
+    cores (the workload's mode; the three hidden-layer contractions in BF16 with
+    FP32 sums), the gradient within 1e-2 relative L2 and the loss within 1e-5."""
+    cfg, ctx, om, lp = setup(4096, 512, 128, 4, mfma=mfma)
     rng = np.random.default_rng(11)
     n = 4096
     u = rng.uniform(-1.0, 1.0, (n, 3))
@@ -156,9 +160,9 @@ def test_gradient_matches_oracle():
     loss_o, grad_o = mlp.loss_grad(theta.astype(np.float64), samples[:, :3].astype(np.float64),
                                    samples[:, 3].astype(np.float64))
     rel = np.linalg.norm(grad_g - grad_o) / np.linalg.norm(grad_o)
-    H.flush("gradient: rel L2 %.3g, loss GPU %.10g oracle %.10g" % (rel, loss_g, loss_o))
-    assert rel <= 1e-5
-    assert loss_g == pytest.approx(loss_o, rel=1e-6)
+    H.flush("gradient (%s): rel L2 %.3g, loss GPU %.10g oracle %.10g" % ("BF16" if mfma else "FP32", rel, loss_g, loss_o))
+    assert rel <= (1e-2 if mfma else 1e-5)
+    assert loss_g == pytest.approx(loss_o, rel=1e-5 if mfma else 1e-6)
 
 
 def nn_log_roughness(cfg, ics, vals, Erange, Y, sigma):
