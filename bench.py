@@ -230,8 +230,9 @@ def main():
                          "FETCH_SIZE / WRITE_SIZE counters, and its bandwidth at that footprint) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(the sharding design is described in DESIGN.md); run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
+              "(each model's particles would shard over GPUs with an all-reduce of the partial "
+              "histograms per step); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -578,6 +578,8 @@ static void fill_mlp_args(const m2m_ctx* c, MlpArgs& a, int64_t n) {
     a.stats = c->mlp_stats;
     a.loss = nullptr;
     a.mfma = P.mlp_mfma;
+    a.pot32 = P.mlp_mfma && !c->mp ? (const Pot<float>*)c->pots_d : nullptr;
+    a.lcetab = (const float2*)c->lcetab;
     a.flag = c->flag;
 }
 

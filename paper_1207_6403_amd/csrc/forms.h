@@ -99,7 +99,11 @@ struct MlpArgs {
     double* red;               // nblk x 2 per-block partials
     double* stats;             // gmax, sum w, sum e, judge numerator, judge, fallback used, refreshes
     float* loss;               // per sample (g - t)^2 / batch, or null
-    int32_t mfma;              // 1: inference's hidden layer on the matrix cores (BF16 operands, FP32 sums)
+    int32_t mfma;              // 1: hidden-layer contractions on the matrix cores (BF16 operands, FP32 sums)
+    // with mfma, for an analytic potential: the inference's features in FP32
+    // (FP32 potential and the uniform-E Lc table), else from FP64 integrals
+    const Pot<float>* pot32;   // null: FP64 features
+    const float2* lcetab;      // kLcE (ln Lc, bound) pairs
     const int* flag;
 };
 

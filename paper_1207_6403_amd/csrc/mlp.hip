@@ -57,6 +57,33 @@ __device__ __forceinline__ void mlp_features(const MlpArgs& a, int64_t p, float&
     u2 = float(L > 0.0 ? Lz / L : 0.0);
 }
 
+// The same features in FP32 for the BF16 inference (whose network rounds its
+// activations to 8 bits, so FP32 integrals lose nothing): the FP32 potential,
+// L and Lz, and Lc(E) from the uniform-E table; an energy outside the table
+// takes the FP64 route.
+template <int POT>
+__device__ __forceinline__ void mlp_features32(const MlpArgs& a, int64_t p, float& u0, float& u1, float& u2,
+                                               float& w) {
+    const float* s = a.state;
+    const int64_t S = a.stride;
+    const float x = s[p], y = s[S + p], z = s[2 * S + p], vx = s[3 * S + p], vy = s[4 * S + p], vz = s[5 * S + p];
+    w = s[6 * S + p];
+    const Pot<float> pt = *a.pot32;
+    float phi, ax, ay, az;
+    potential<POT, float>(pt, x, y, z, phi, ax, ay, az);
+    const float E = 0.5f * (vx * vx + vy * vy + vz * vz) + phi;
+    const float lx = y * vz - z * vy, ly = z * vx - x * vz, lz = x * vy - y * vx;
+    const float L = sqrtf(lx * lx + ly * ly + lz * lz);
+    float Lc, dl;
+    if (!lc_from_table(a.lcetab, pt.lcE0, pt.lcEinv, E, 0.0f, Lc, dl)) {
+        mlp_features<POT>(a, p, u0, u1, u2, w);
+        return;
+    }
+    u0 = float(2.0 * (double(E) - a.Emin) / (a.Emax - a.Emin) - 1.0);
+    u1 = Lc > 0.0f ? 2.0f * L / Lc - 1.0f : -1.0f;
+    u2 = L > 0.0f ? lz / L : 0.0f;
+}
+
 template <int POT>
 __global__ void __launch_bounds__(256) mlp_subset_kernel(MlpArgs a) {
     if (*a.flag) return;
@@ -540,7 +567,10 @@ __global__ void __launch_bounds__(kMlpInferThreads, 2) mlp_infer_mfma_kernel(Mlp
     for (int64_t base = (int64_t)blockIdx.x * kMlpInferThreads; base < a.n; base += (int64_t)gridDim.x * kMlpInferThreads) {
         const int64_t p = base + tid;
         float u0 = 0.0f, u1 = 0.0f, u2 = 0.0f, w;
-        if (p < a.n) mlp_features<POT>(a, p, u0, u1, u2, w);
+        if (p < a.n) {
+            if (a.pot32) mlp_features32<POT>(a, p, u0, u1, u2, w);
+            else mlp_features<POT>(a, p, u0, u1, u2, w);
+        }
         // first layer, to this particle's LDS row in BF16
         #pragma unroll
         for (int o8 = 0; o8 < kMlpH; o8 += 8) {
