@@ -165,6 +165,22 @@ __device__ __forceinline__ float qexp(float v) { return __expf(v); }
 __device__ __forceinline__ float qlog_ratio(float v) { return __builtin_amdgcn_logf(v) * 0.693147180559945309f; }
 __device__ __forceinline__ double qlog_ratio(double v) { return log(v); }
 __device__ __forceinline__ double qexp(double v) { return exp(v); }
+// Square root and ln(1 + x) of the FP32 potentials: the hardware square root
+// (at most 1.6u relative error, u = 2^-24, measured on gfx950 over every float in
+// [2^-30, 2^30)), and ln(1 + x) = x ln(w) / (w - 1) with w = 1 + x rounded
+// (Goldberg 1991, "What every computer scientist should know about
+// floating-point arithmetic", Theorem 4), ln(w) from the hardware base-2
+// logarithm (at most 6u relative error over the same floats).  The FP64 kernels
+// use the library forms.
+__device__ __forceinline__ float psqrt(float v) { return __builtin_amdgcn_sqrtf(v); }
+__device__ __forceinline__ double psqrt(double v) { return sqrt(v); }
+__device__ __forceinline__ float plog1p(float v) {
+    const float w = 1.0f + v;
+    const float d = w - 1.0f;
+    const float l = __builtin_amdgcn_logf(w) * 0.693147180559945309f;
+    return d == 0.0f ? v : v * (l * __builtin_amdgcn_rcpf(d));
+}
+__device__ __forceinline__ double plog1p(double v) { return log1p(v); }
 
 // Phi(x) and a = -grad Phi.  POT is the compile-time potential kind.
 template <int POT, typename T>
@@ -179,13 +195,13 @@ __device__ __forceinline__ void potential(const Pot<T>& p, T x, T y, T z, T& phi
         return;
     }
     const T r2 = x * x + y * y + z * z;
-    const T r = dsqrt(r2);
+    const T r = psqrt(r2);
     const T u = r + p.a;
     T ph = -qdiv(p.GM, u);
     T g_over_r = r > T(0) ? qdiv(p.GM, u * u * r) : T(0);   // (dPhi/dr)/r
     if (POT == 2 && p.GMh > T(0)) {
         const T xx = r * p.irs;
-        const T l1 = dlog1p(xx);
+        const T l1 = plog1p(xx);
         // dPhi_NFW/dr = G Mh/rs^2 f(x), f = ln(1+x)/x^2 - 1/(x(1+x)); the two terms
         // cancel near x = 0, where the Taylor series is used instead.
         T f;
@@ -439,11 +455,15 @@ __device__ __forceinline__ CellGuard cell_guard(float Emin, float Emax, float sE
 // the caller re-decides those in FP64.  cell is the index from the clamped FP32
 // coordinates of every axis (exact on the axes not returned).
 // Guards, twice a bound on the FP32 error (u = 2^-24):
-//   E: |E32 - E| <= u (4 KE + 17 |phi| + 3 v0^2): the kinetic sum, the
-//      potential (at most 16u |phi| for the analytic potentials with the
-//      hardware reciprocal, logarithm and square root, plus 3u v0^2 from the
-//      argument of the logarithmic potential's log) and the sum; see cell_guard;
-//   L/Lc or Lz/Lc: the rounding of L (2u per product pair, 3u L) or Lz
+//   E: |E32 - E| <= u (4 KE + 25 |phi| + 3 v0^2): the kinetic sum, the
+//      potential (at most 24u |phi| for the analytic potentials with the
+//      hardware reciprocal, logarithm and square root: the Hernquist+NFW sum is
+//      the largest, r 3.1u, x = r/rs 5.1u, ln(1+x) 11.1u, 1/r 4.6u, the NFW
+//      term 18.7u, the Hernquist term 8.6u, the sum 19.7u; plus 3u v0^2 from
+//      the argument of the logarithmic potential's log) and the sum; see
+//      cell_guard;
+//   L/Lc or Lz/Lc: the rounding of L (2u per product pair; the sum of squares
+//      and the hardware root 4u L) or Lz
 //      (2u (|x vy| + |y vx|)) over Lc, and the relative error of Lc (dl, plus
 //      3u for the reciprocal and the product) times the coordinate's distance
 //      from the axis origin, plus 2u |f2|;
@@ -468,15 +488,15 @@ __device__ __forceinline__ unsigned cell_fast(const Pot<float>& p, const float2*
     const int n2 = CAX == kCaxRuntime ? opaque(c.n2) : 1;
     const int ax2 = CAX == kCaxRuntime ? opaque(c.ax2) : (CAX == kCaxLzNo3 ? 1 : 0);
     const float E = KE + phi;
-    const float eE = kU32 * (4.0f * KE + 17.0f * fabsf(phi) + 3.0f * p.v2);
+    const float eE = kU32 * (4.0f * KE + 25.0f * fabsf(phi) + 3.0f * p.v2);
     const float xvy = x * vy, yvx = y * vx;
     const float Lz = xvy - yvx;
     float L = 0.0f, dL = 2.0f * kU32 * (fabsf(xvy) + fabsf(yvx));
     if (ax2 == 0 || n2 > 1) {   // |L| only for the L/Lc and Lz/L axes
         const float yvz = y * vz, zvy = z * vy, zvx = z * vx, xvz = x * vz;
         const float Lx = yvz - zvy, Ly = zvx - xvz;
-        L = sqrtf(Lx * Lx + Ly * Ly + Lz * Lz);
-        if (ax2 == 0) dL += 2.0f * kU32 * (fabsf(yvz) + fabsf(zvy) + fabsf(zvx) + fabsf(xvz)) + 3.0f * kU32 * L;
+        L = __builtin_amdgcn_sqrtf(Lx * Lx + Ly * Ly + Lz * Lz);
+        if (ax2 == 0) dL += 2.0f * kU32 * (fabsf(yvz) + fabsf(zvy) + fabsf(zvx) + fabsf(xvz)) + 4.0f * kU32 * L;
     }
     float Lc = 1.0f, dl = 1.0f;
     const bool have = lc_from_table(et, p.lcE0, p.lcEinv, E, eE, Lc, dl) && Lc > 0.0f;
@@ -532,8 +552,9 @@ __device__ __forceinline__ int bin_f64(int kind, double cosd, double sind, doubl
 //     relative roundings (the difference, sx, the product): 2(u sx |x0| + 3u |fx|);
 //   grid y: the same plus the projection, two roundings per product (cos i or
 //     sin i, the product) and one of the difference, <= 3u aYs, times sy;
-//   radius: the sum of squares (3u, halved by the root), the root (2u) and the
-//     rounded edge (u) stay below 12u r; the projected radius adds 6u aYs.
+//   radius: the sum of squares (3u, halved by the root), the hardware root
+//     (at most 1.6u, counted as 2u) and the rounded edge (u) stay below 12u r;
+//     the projected radius adds 6u aYs.
 __device__ __forceinline__ int bin_fast(const BinDesc<float>& d, int kind, const float* __restrict__ ef, float x,
                                         float y, float z, float Ys, float aYs, bool& sure) {
     if (kind == 3) {
@@ -546,7 +567,7 @@ __device__ __forceinline__ int bin_fast(const BinDesc<float>& d, int kind, const
         // (the conversions of out-of-range values are not used)
         return in ? int(fy) * d.nx + int(fx) : -1;
     }
-    const float rad = kind == 1 ? __builtin_sqrtf(x * x + y * y + z * z) : __builtin_sqrtf(x * x + Ys * Ys);
+    const float rad = kind == 1 ? psqrt(x * x + y * y + z * z) : psqrt(x * x + Ys * Ys);
     const float* e = ef + d.edge0;
     const int ne = d.nb + 1;
     const float g = 12.0f * kU32 * rad + (kind == 1 ? 0.0f : 6.0f * kU32 * aYs);

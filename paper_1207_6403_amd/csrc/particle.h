@@ -151,7 +151,7 @@ __device__ __forceinline__ T weight_update(const StepArgs<T, PT>& a, const Blk<T
     const LayoutView<SIG, T> V{L};
     const int nbin = V.nbin();
     const T vl = line_of_sight(vy, vz, L.sini, L.cosi);
-    T chi = T(0);
+    T chi = T(-0.0);   // (adding -0 is exact for every value, so the first sum folds away)
     #pragma unroll
     for (int b = 0; b < NB; ++b) {
         if (b >= nbin) break;
@@ -176,7 +176,7 @@ __device__ __forceinline__ T weight_update(const StepArgs<T, PT>& a, const Blk<T
     // (FP32: the hardware log, exp and reciprocal, a few ulp each; the FP64
     // kernels use the exact forms)
     const T lr = qlog_ratio(qdiv(w, wh));
-    const T G = -chi - a.mu * (lr + T(1)) + ((fl & kTracers) ? a.extra[p] : T(0));
+    const T G = -chi - a.mu * (lr + T(1)) + ((fl & kTracers) ? a.extra[p] : T(-0.0));
     const T edt = a.eps * a.dt;
     const T wn = (fl & kExpLaw) ? w * qexp(edt * G) : w * (T(1) + edt * G);
     acc.S -= double(w) * double(lr);

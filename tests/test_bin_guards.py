@@ -13,7 +13,8 @@ coordinate lies within a guard band of an edge.  The guard is twice a bound on
   radius:  12u r, plus 6u (|y cos i| + |z sin i|) for the projected radius
 (plus a floor of 1e-6 bins).  These tests restate that FP32 arithmetic with numpy
 float32 (IEEE round-to-nearest, like the GPU's add, multiply and fused
-multiply-add), with and without contraction of the projection into an FMA, on
+multiply-add; the hardware square root as the rounded root moved by up to two
+ulp), with and without contraction of the projection into an FMA, on
 particles packed within a few 1e-5 bins of the edges, and check against the
 oracle's FP64 bins of the same FP32 particles that no decision the guard calls
 sure is wrong -- and that a guard ten times narrower would be wrong somewhere
@@ -107,6 +108,20 @@ def grid_fp32(d, incl, x, y, z, fused, scale=1.0):
     return k, sure
 
 
+_WIG = np.random.default_rng(11)
+
+
+def _hw_sqrt(s):
+    """The hardware square root: the correctly rounded root moved at random by up
+    to two ulp (its measured bound on gfx950 is 1.6u relative)."""
+    r = np.sqrt(s.astype(np.float64)).astype(F32)
+    k = _WIG.integers(-2, 3, r.shape)
+    for step in (1, 2):
+        r = np.where(k >= step, np.nextafter(r, F32(np.inf)), r)
+        r = np.where(k <= -step, np.nextafter(r, F32(-np.inf)), r)
+    return r.astype(F32)
+
+
 def radial_fp32(d, incl, x, y, z, fused, scale=1.0):
     e = np.asarray(d["edges"]).astype(F32)
     if d["kind"] == "shell":
@@ -123,7 +138,7 @@ def radial_fp32(d, incl, x, y, z, fused, scale=1.0):
     else:
         s = ((a * a).astype(F32) + (b * b).astype(F32)).astype(F32)
         s = (s + (c * c).astype(F32)).astype(F32)
-    rad = np.sqrt(s).astype(F32)
+    rad = _hw_sqrt(s)
     g = F32(scale) * (F32(12 * U) * rad + extra)
     k = np.searchsorted(e, rad, side="right") - 1
     inside = (rad >= e[0]) & (rad < e[-1])

@@ -4,7 +4,7 @@ averages over cells of the integrals of motion E and L/Lc(E) or Lz/Lc(E)).
 The fused kernel computes each particle's cell coordinates in FP32 and
 re-decides an axis in FP64 when its coordinate lies within the guard band of
 an edge.  The guards are twice per-particle bounds on the FP32 error (u = 2^-24):
-  energy: |E32 - E| <= u (4 KE + 17 |phi| + 3 v0^2), carried into
+  energy: |E32 - E| <= u (4 KE + 25 |phi| + 3 v0^2), carried into
       fE = (E - Emin) sE with the rounded Emin and sE;
   L/Lc or Lz/Lc: the rounding of L or Lz over Lc, plus the relative error of
       the tabulated Lc(E) (the table's interpolation bound, the energy error and
@@ -12,8 +12,10 @@ an edge.  The guards are twice per-particle bounds on the FP32 error (u = 2^-24)
       interpolation and of exp) times the distance from the axis origin.
 These tests restate that FP32 arithmetic with numpy float32, with and without
 contraction into fused multiply-adds, modelling each hardware transcendental
-(log, exp, reciprocal, square root, log1p) as the correctly rounded result
-moved by up to one ulp (two for log1p) at random.  On particles placed within
+(log, exp, reciprocal, square root, and ln(1 + x) in Goldberg's form from the
+hardware log) as the correctly rounded result moved at random by up to one ulp
+(two for the square root, six for ln(1 + x): their measured bounds on gfx950
+are 1.6u and 6u relative).  On particles placed within
 a few 1e-5 cells of both an energy edge and an edge of the second axis, in the
 three analytic potentials, no decision the guard calls sure may differ from
 the oracle's FP64 cell of the same FP32 particle, and a guard ten (for
@@ -61,10 +63,10 @@ class Hw:
         return self._wiggle((1.0 / v.astype(np.float64)).astype(F32), 1)
 
     def sqrt(self, v):
-        return self._wiggle(np.sqrt(v.astype(np.float64)).astype(F32), 1)
+        return self._wiggle(np.sqrt(v.astype(np.float64)).astype(F32), 2)
 
     def log1p(self, v):
-        return self._wiggle(np.log1p(v.astype(np.float64)).astype(F32), 2)
+        return self._wiggle(np.log1p(v.astype(np.float64)).astype(F32), 6)
 
 
 def fma(a, b, c):
@@ -133,7 +135,7 @@ def cell_fp32(pot, prior, Erange, tab, E0, invh, xv, hw, fused, scale=1.0):
     KE = (F32(0.5) * sumsq(vx, vy, vz, fused)).astype(F32)
     E = (KE + phi).astype(F32)
     v2 = F32(pot.get("v0", 0.0) ** 2)
-    eE = (F32(U) * (F32(4) * KE + F32(17) * np.abs(phi) + F32(3) * v2)).astype(F32)
+    eE = (F32(U) * (F32(4) * KE + F32(25) * np.abs(phi) + F32(3) * v2)).astype(F32)
     xvy, yvx = (x * vy).astype(F32), (y * vx).astype(F32)
     Lz = fma(x, vy, -yvx) if fused else (xvy - yvx).astype(F32)
     dL = (F32(2 * U) * (np.abs(xvy) + np.abs(yvx))).astype(F32)
@@ -143,7 +145,7 @@ def cell_fp32(pot, prior, Erange, tab, E0, invh, xv, hw, fused, scale=1.0):
         Lx = fma(y, vz, -zvy) if fused else (yvz - zvy).astype(F32)
         Ly = fma(z, vx, -xvz) if fused else (zvx - xvz).astype(F32)
         L = hw.sqrt(sumsq(Lx, Ly, Lz, fused))
-        dL = (dL + F32(2 * U) * (np.abs(yvz) + np.abs(zvy) + np.abs(zvx) + np.abs(xvz)) + F32(3 * U) * L).astype(F32)
+        dL = (dL + F32(2 * U) * (np.abs(yvz) + np.abs(zvy) + np.abs(zvx) + np.abs(xvz)) + F32(4 * U) * L).astype(F32)
     # the table
     d = (E - E0).astype(F32)
     t = (d * invh).astype(F32)
