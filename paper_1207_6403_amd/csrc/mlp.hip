@@ -57,6 +57,15 @@ __device__ __forceinline__ void mlp_features(const MlpArgs& a, int64_t p, float&
     u2 = float(L > 0.0 ? Lz / L : 0.0);
 }
 
+// The FP64 features out of line (the rare FP64 route of the FP32 features below,
+// kept out of the register allocation of the kernels that call it).
+template <int POT>
+__device__ __noinline__ float4 mlp_features_ool(const MlpArgs& a, int64_t p) {
+    float4 f;
+    mlp_features<POT>(a, p, f.x, f.y, f.z, f.w);
+    return f;
+}
+
 // The same features in FP32 for the BF16 inference (whose network rounds its
 // activations to 8 bits, so FP32 integrals lose nothing): the FP32 potential,
 // L and Lz, and Lc(E) from the uniform-E table; an energy outside the table
@@ -76,7 +85,8 @@ __device__ __forceinline__ void mlp_features32(const MlpArgs& a, int64_t p, floa
     const float L = sqrtf(lx * lx + ly * ly + lz * lz);
     float Lc, dl;
     if (!lc_from_table(a.lcetab, pt.lcE0, pt.lcEinv, E, 0.0f, Lc, dl)) {
-        mlp_features<POT>(a, p, u0, u1, u2, w);
+        const float4 f = mlp_features_ool<POT>(a, p);
+        u0 = f.x; u1 = f.y; u2 = f.z; w = f.w;
         return;
     }
     u0 = float(2.0 * (double(E) - a.Emin) / (a.Emax - a.Emin) - 1.0);
@@ -110,6 +120,11 @@ typedef float floatx4 __attribute__((ext_vector_type(4)));
 __device__ __forceinline__ float unit_tanh(float x) {
     return 1.0f - 2.0f * __builtin_amdgcn_rcpf(__expf(2.0f * x) + 1.0f);
 }
+// The BF16 inference's form: its weights and biases come pre-multiplied by
+// 2 log2(e), so that y = 2 log2(e) x and 1 / (exp(2x) + 1) is one hardware base-2
+// exponential, an add and a reciprocal (tanh(x) = 1 - 2 r).
+constexpr float kTwoLog2e = 2.88539008177792681f;
+__device__ __forceinline__ float unit_r(float y) { return __builtin_amdgcn_rcpf(__builtin_amdgcn_exp2f(y) + 1.0f); }
 
 // Forward pass of one sample with the parameters th in LDS: the first hidden
 // layer h1 (registers), the second layer's units one by one (to h2, an LDS row,
@@ -534,8 +549,23 @@ __global__ void __launch_bounds__(kMlpInferThreads, 2) mlp_infer_kernel(MlpArgs 
 // 16 lanes that share particles add their partial outputs.
 constexpr int kHRow = kMlpH + 8;   // LDS row of one particle's first-layer outputs (BF16, padded)
 
-template <int POT>
-__global__ void __launch_bounds__(kMlpInferThreads, 2) mlp_infer_mfma_kernel(MlpArgs a) {
+// Sum over the 16 lanes of a row (lanes 16 r .. 16 r + 15), the same in every
+// lane of the row: with data-parallel-primitive moves, the pairs and the quads
+// (quad permutations 1 0 3 2 and 2 3 0 1), then the halves of the row (the
+// half-row mirror takes lane i of eight from lane 7 - i) and the row (the row
+// mirror: lane 15 - i).
+__device__ __forceinline__ float row_sum16(float x) {
+    x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0xB1, 0xF, 0xF, false));
+    x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x4E, 0xF, 0xF, false));
+    x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x141, 0xF, 0xF, false));
+    x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x140, 0xF, 0xF, false));
+    return x;
+}
+
+// P32: the features in FP32 (four waves per SIMD: the FP64 route is out of
+// line), else in FP64 (two).
+template <int POT, bool P32>
+__global__ void __launch_bounds__(kMlpInferThreads, P32 ? 4 : 2) mlp_infer_mfma_kernel(MlpArgs a) {
     constexpr int kWaves = kMlpInferThreads / 64;
     __shared__ __align__(16) float l1[kMlpH][4];               // W1 row and b1 per unit
     __shared__ float b2s[kMlpH], w3s[kMlpH];
@@ -544,13 +574,15 @@ __global__ void __launch_bounds__(kMlpInferThreads, 2) mlp_infer_mfma_kernel(Mlp
     __shared__ double sh[kMlpInferThreads / 64];
     if (*a.flag) return;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    // the hidden layers' weights and biases times 2 log2(e) (unit_r), and -2 w3:
+    // a unit's output term w3 tanh(x) = w3 - 2 w3 r
     for (int o = tid; o < kMlpH; o += kMlpInferThreads) {
-        l1[o][0] = a.theta[kMlpW1 + 3 * o];
-        l1[o][1] = a.theta[kMlpW1 + 3 * o + 1];
-        l1[o][2] = a.theta[kMlpW1 + 3 * o + 2];
-        l1[o][3] = a.theta[kMlpB1 + o];
-        b2s[o] = a.theta[kMlpB2 + o];
-        w3s[o] = a.theta[kMlpW3 + o];
+        l1[o][0] = kTwoLog2e * a.theta[kMlpW1 + 3 * o];
+        l1[o][1] = kTwoLog2e * a.theta[kMlpW1 + 3 * o + 1];
+        l1[o][2] = kTwoLog2e * a.theta[kMlpW1 + 3 * o + 2];
+        l1[o][3] = kTwoLog2e * a.theta[kMlpB1 + o];
+        b2s[o] = kTwoLog2e * a.theta[kMlpB2 + o];
+        w3s[o] = -2.0f * a.theta[kMlpW3 + o];
     }
     // B operands: unit n = 16 c + lane % 16, inputs k = 32 s + 8 (lane / 16) + v
     bf16x8 bw[4][2];
@@ -560,15 +592,20 @@ __global__ void __launch_bounds__(kMlpInferThreads, 2) mlp_infer_mfma_kernel(Mlp
         for (int s2 = 0; s2 < 2; ++s2)
             #pragma unroll
             for (int v = 0; v < 8; ++v)
-                bw[c][s2][v] = (__bf16)a.theta[kMlpW2 + (16 * c + (lane & 15)) * kMlpH + 32 * s2 + 8 * (lane >> 4) + v];
+                bw[c][s2][v] =
+                    (__bf16)(kTwoLog2e * a.theta[kMlpW2 + (16 * c + (lane & 15)) * kMlpH + 32 * s2 + 8 * (lane >> 4) + v]);
     const float b3 = a.theta[kMlpB3];
+    // the sum of w3 over this lane's four units (their w3 terms, added once)
+    float w3l = 0.0f;
+    #pragma unroll
+    for (int c = 0; c < 4; ++c) w3l += a.theta[kMlpW3 + 16 * c + (lane & 15)];
     __syncthreads();
     double gmax = -INFINITY;
     for (int64_t base = (int64_t)blockIdx.x * kMlpInferThreads; base < a.n; base += (int64_t)gridDim.x * kMlpInferThreads) {
         const int64_t p = base + tid;
         float u0 = 0.0f, u1 = 0.0f, u2 = 0.0f, w;
         if (p < a.n) {
-            if (a.pot32) mlp_features32<POT>(a, p, u0, u1, u2, w);
+            if constexpr (P32) mlp_features32<POT>(a, p, u0, u1, u2, w);
             else mlp_features<POT>(a, p, u0, u1, u2, w);
         }
         // first layer, to this particle's LDS row in BF16
@@ -578,47 +615,41 @@ __global__ void __launch_bounds__(kMlpInferThreads, 2) mlp_infer_mfma_kernel(Mlp
             #pragma unroll
             for (int v = 0; v < 8; ++v) {
                 const int o = o8 + v;
-                hv[v] = (__bf16)unit_tanh(l1[o][3] + l1[o][0] * u0 + l1[o][1] * u1 + l1[o][2] * u2);
+                hv[v] = (__bf16)fmaf(-2.0f, unit_r(l1[o][3] + l1[o][0] * u0 + l1[o][1] * u1 + l1[o][2] * u2), 1.0f);
             }
             *reinterpret_cast<bf16x8*>(&hrow[wv][lane][o8]) = hv;
         }
         __syncthreads();
-        float pg[4][4];
         #pragma unroll
         for (int t = 0; t < 4; ++t) {
+            // (the products accumulate onto the units' biases: every element a lane
+            // holds belongs to its unit 16 c + lane % 16)
             floatx4 acc[4];
             #pragma unroll
-            for (int c = 0; c < 4; ++c) acc[c] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+            for (int c = 0; c < 4; ++c) {
+                const float b = b2s[16 * c + (lane & 15)];
+                acc[c] = floatx4{b, b, b, b};
+            }
             #pragma unroll
             for (int s2 = 0; s2 < 2; ++s2) {
                 const bf16x8 af = *reinterpret_cast<const bf16x8*>(&hrow[wv][16 * t + (lane & 15)][32 * s2 + 8 * (lane >> 4)]);
                 #pragma unroll
                 for (int c = 0; c < 4; ++c) acc[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, bw[c][s2], acc[c], 0, 0, 0);
             }
-            // lane holds units 16 c + lane % 16 of particles 16 t + 4 (lane / 16) + v
+            // lane holds units 16 c + lane % 16 of particles 16 t + 4 (lane / 16) + v;
+            // the 16 lanes that hold the same particles (one row) add their sums
             #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                float sum = 0.0f;
+                float x = w3l;
                 #pragma unroll
                 for (int c = 0; c < 4; ++c) {
                     const int n = 16 * c + (lane & 15);
-                    sum += w3s[n] * unit_tanh(acc[c][v] + b2s[n]);
+                    x = fmaf(w3s[n], unit_r(acc[c][v]), x);
                 }
-                pg[t][v] = sum;
-            }
-        }
-        // add the 16 lanes that hold the same particles (lanes differing in bits 0..3)
-        #pragma unroll
-        for (int t = 0; t < 4; ++t)
-            #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                float x = pg[t][v];
-                x += __shfl_xor(x, 1, 64);
-                x += __shfl_xor(x, 2, 64);
-                x += __shfl_xor(x, 4, 64);
-                x += __shfl_xor(x, 8, 64);
+                x = row_sum16(x);
                 if ((lane & 15) == 0) gbuf[wv][16 * t + 4 * (lane >> 4) + v] = x + b3;
             }
+        }
         __syncthreads();
         if (p < a.n) {
             const float g = gbuf[wv][lane];
@@ -728,7 +759,8 @@ static hipError_t refresh_pot(const MlpArgs& a, int t0, hipStream_t s) {
         hipLaunchKernelGGL(mlp_adam_kernel, dim3((kMlpNP + 63) / 64), dim3(64 * kSumWaves), 0, s, a, nblk, c1, c2);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
-    if (a.mfma) hipLaunchKernelGGL((mlp_infer_mfma_kernel<POT>), dim3(a.nblk), dim3(kMlpInferThreads), 0, s, a);
+    if (a.mfma && a.pot32) hipLaunchKernelGGL((mlp_infer_mfma_kernel<POT, true>), dim3(a.nblk), dim3(kMlpInferThreads), 0, s, a);
+    else if (a.mfma) hipLaunchKernelGGL((mlp_infer_mfma_kernel<POT, false>), dim3(a.nblk), dim3(kMlpInferThreads), 0, s, a);
     else hipLaunchKernelGGL((mlp_infer_kernel<POT>), dim3(a.nblk), dim3(kMlpInferThreads), 0, s, a);
     hipLaunchKernelGGL(mlp_reduce_kernel, dim3(1), dim3(256), 0, s, a, 0);
     hipLaunchKernelGGL(mlp_norm_kernel, dim3(a.nblk), dim3(kMlpInferThreads), 0, s, a);
