@@ -29,8 +29,13 @@ namespace m2m {
 constexpr int kTrcChunk = 2048;   // particles per chunk of tracer_observe
 constexpr int kTrcObsThreads = 1024;   // threads of tracer_observe (one block per CU)
 
-__device__ __forceinline__ float trc_exp(float v) { return __expf(v); }
-__device__ __forceinline__ double trc_exp(double v) { return exp(v); }
+// exp(-d^2 / 2) of a tracer's Gaussian at d = (v - V) / s, from d' = (v - V) q / s:
+// FP32 with q = sqrt(log2(e) / 2), so that it is one hardware base-2
+// exponential of -d'^2; FP64 with q = 1 and the library exp.
+__device__ __forceinline__ float trc_q(float) { return 0.849321800288019136f; }
+__device__ __forceinline__ double trc_q(double) { return 1.0; }
+__device__ __forceinline__ float trc_gauss(float dq) { return __builtin_amdgcn_exp2f(-(dq * dq)); }
+__device__ __forceinline__ double trc_gauss(double dq) { return exp(-0.5 * dq * dq); }
 
 // Exclusive prefix sum of cnt[0..n) in place (cnt[n] gets the total), by all
 // threads of the block: contiguous runs per thread, then a scan of the run sums.
@@ -114,13 +119,22 @@ __global__ void __launch_bounds__(kTrcObsThreads) tracer_observe_kernel(TracerAr
         }
         for (int t = tid; t < ntr; t += nt) {
             const int b = a.tbin[t];
-            const T V = a.V[t], is = a.is[t], nf = a.nf[t];
-            double s = 0.0;
-            for (uint32_t i = cnt[b]; i < cnt[b + 1]; ++i) {
-                const T d = (svl[i] - V) * is;
-                s += double(sw[i] * nf * trc_exp(T(-0.5) * d * d));
+            const T V = a.V[t], isq = a.is[t] * trc_q(T(0));
+            // four particles per round, their LDS reads issued together, into two sums
+            double s0 = 0.0, s1 = 0.0;
+            uint32_t i = cnt[b];
+            const uint32_t e = cnt[b + 1];
+            for (; i + 4 <= e; i += 4) {
+                T v[4], w[4];
+                #pragma unroll
+                for (int u = 0; u < 4; ++u) { v[u] = svl[i + u]; w[u] = sw[i + u]; }
+                s0 += double(w[0] * trc_gauss((v[0] - V) * isq));
+                s1 += double(w[1] * trc_gauss((v[1] - V) * isq));
+                s0 += double(w[2] * trc_gauss((v[2] - V) * isq));
+                s1 += double(w[3] * trc_gauss((v[3] - V) * isq));
             }
-            acc[t] += s;
+            for (; i < e; ++i) s0 += double(sw[i] * trc_gauss((svl[i] - V) * isq));
+            acc[t] += double(a.nf[t]) * (s0 + s1);   // (the tracer's normalisation, once per chunk)
         }
         __syncthreads();
     }
@@ -190,7 +204,7 @@ __global__ void __launch_bounds__(kTrcThreads) tracer_grad_kernel(TracerArgs<T> 
     if (*a.flag) return;
     for (int t = tid; t < ntr; t += nt) {
         tV[t] = a.V[t];
-        tis[t] = a.is[t];
+        tis[t] = a.is[t] * trc_q(T(0));
         tc[t] = a.cL[t] * a.nf[t];
     }
     __syncthreads();
@@ -203,10 +217,21 @@ __global__ void __launch_bounds__(kTrcThreads) tracer_grad_kernel(TracerArgs<T> 
         if (b != kNoBin) {
             const T vl = line_of_sight(S[4 * st + p], S[5 * st + p], a.sini, a.cosi);
             x = a.cM[b];
-            for (int t = a.first[b]; t < a.first[b + 1]; ++t) {
-                const T d = (vl - tV[t]) * tis[t];
-                x += tc[t] * trc_exp(T(-0.5) * d * d);
+            // four tracers per round, their LDS reads issued together, into two sums
+            T x1 = T(0);
+            int t = a.first[b];
+            const int te = a.first[b + 1];
+            for (; t + 4 <= te; t += 4) {
+                T V[4], q[4], c[4];
+                #pragma unroll
+                for (int u = 0; u < 4; ++u) { V[u] = tV[t + u]; q[u] = tis[t + u]; c[u] = tc[t + u]; }
+                x += c[0] * trc_gauss((vl - V[0]) * q[0]);
+                x1 += c[1] * trc_gauss((vl - V[1]) * q[1]);
+                x += c[2] * trc_gauss((vl - V[2]) * q[2]);
+                x1 += c[3] * trc_gauss((vl - V[3]) * q[3]);
             }
+            for (; t < te; ++t) x += tc[t] * trc_gauss((vl - tV[t]) * tis[t]);
+            x += x1;
         }
         a.extra[p] = x;
     }
