@@ -10,7 +10,9 @@ Workloads (--workload):
   multipole  2^23 particles in their own multipole potential (lmax 8, 200 nodes),
              the logpot observables plus 50 density shells;
   mlp        2^22 particles with the learned prior (refreshed every 100 steps on a
-             2^20 sample, judged against a 32x32x8 histogram prior).
+             2^20 sample, judged against a 32x32x8 histogram prior);
+  pne        2^20 Hernquist-potential particles with 833 discrete line-of-sight
+             velocities (their log-likelihood in the merit function).
 One step = weight update + push + observe + smoothing, deviations, chi^2 and
 prior, all on the GPU.
 
@@ -205,9 +207,12 @@ WORKLOADS = {
     "mlp": ("learned prior: N=%d FP32 particles in the log potential, 3-64-64-1 network retrained every 100 "
             "steps on a 2^20 sample (128 Adam minibatches of 8192), judged against a 32x32x8 (E, L/Lc, Lz/L) "
             "histogram prior, J=4896, dt=0.005"),
+    "pne": ("discrete-velocity likelihood: N=%d FP32 particles in the Hernquist potential, 30 shells + 20 "
+            "annuli (LOS second moment), the line-of-sight velocities of the 833 of 1000 drawn tracers that "
+            "fall in the annuli (lambda=1, kernel width 0.071), (E, L/Lc) 20x20 moving prior every step, dt=0.01"),
 }
 # oracle steps of the CPU sample: about 10-15 s on 16 host threads
-DEFAULT_CPU_STEPS = {"logpot": 96, "batched": 220, "multipole": 6, "mlp": 150}
+DEFAULT_CPU_STEPS = {"logpot": 96, "batched": 220, "multipole": 6, "mlp": 150, "pne": 20}
 
 
 def main():
@@ -217,7 +222,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--n", type=int, default=1 << 20, help="particles of the logpot workload")
     ap.add_argument("--workload", choices=sorted(WORKLOADS), default="logpot",
-                    help="logpot (the headline), batched, multipole or mlp")
+                    help="logpot (the headline), batched, multipole, mlp or pne (discrete velocities)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=0, help="oracle steps of the CPU baseline (0: per workload)")
     ap.add_argument("--autotune", action="store_true",
@@ -260,7 +265,8 @@ def main():
     wl = args.workload
     batched = wl == "batched"
     cfg = {"logpot": lambda: configs.cfg2(N=args.n), "batched": configs.cfg4, "multipole": configs.cfg3,
-           "mlp": configs.cfg5}[wl]()
+           "mlp": configs.cfg5,
+           "pne": lambda: dict(configs.cfg_pne(N=args.n, n_tracers=1000, precision="f32"), eps=configs.EPS_PNE)}[wl]()
     cpu_steps = args.cpu_steps or DEFAULT_CPU_STEPS[wl]
     cache = os.path.join(args.inputs_cache, "%s_%d.npz" % (wl, cfg["N"])) if args.inputs_cache else None
     if cache and os.path.exists(cache):
@@ -320,7 +326,8 @@ def main():
                           "the next step's first kick)",
                 "kernel_us": k_ms * 1e3, "flops_per_launch": flops}
     else:
-        bpp = BYTES_PER_PARTICLE_STEP + (4 if wl == "mlp" else 0)   # the learned prior is read per particle
+        # (the learned prior, or the tracers' term of G, is read per particle)
+        bpp = BYTES_PER_PARTICLE_STEP + (4 if wl in ("mlp", "pne") else 0)
         achieved = bpp * cfg["N"] / (k_ms * 1e-3) / 1e9
         roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(cfg["N"]) if wl == "logpot" else None,
@@ -349,18 +356,32 @@ def main():
         m2m.m2m_set_launch(ctx2, threads=launch["threads"], ilp=launch["ilp"], blocks_per_cu=launch["blocks_per_cu"])
         g_last = m2m.m2m_step(ctx2, cpu_steps)[0]
         ys_gpu = m2m.m2m_observables(ctx2, 0)["y_smooth"]
+        trc = cfg.get("tracers")
+        if trc:
+            nb = len(cfg["layout"]["binnings"][trc["binning"]]["edges"]) - 1
+            ll_gpu = m2m.m2m_tracer_state(ctx2, nb)[0]
         m2m.m2m_destroy(ctx2)
         log("cpu baseline: %d oracle steps of N=%d (and %d on one core)" % (cpu_steps, cfg["N"], steps_1core))
         cpu, ost, om = cpu_baseline(cfg, inp, er, cpu_steps, steps_1core)
         chi2_err = abs(g_last["chi2"] - ost[-1][0]) / ost[-1][0]
         parity = {"steps": cpu_steps, "chi2_rel_err": chi2_err,
                   "obs_max_rel_err": obs_rel_err(cfg, ys_gpu, smoothed_next(cfg, om))}
+        if trc:
+            # the oracle's tracer log-likelihood of its current state (smoothed sums)
+            g = cfg["dt"] / cfg["tau"]
+            L, M = om.tracer_observe()
+            L = om.arr["tL"][:L.size] + g * (L - om.arr["tL"][:L.size])
+            M = om.arr["tM"] + g * (M - om.arr["tM"])
+            ll = float(np.sum(np.log(L / M[trc["bin"]])))
+            parity["loglike_rel_err"] = abs(ll_gpu - ll) / abs(ll)
         log("parity after %d steps: chi2 %.3g, smoothed observables %.3g" % (
             cpu_steps, chi2_err, parity["obs_max_rel_err"]))
 
     config = {"workload": WORKLOADS[wl] % cfg["N"], "N": cfg["N"], "launch": launch}
     if batched:
         config.update(models=len(cfg["model_sizes"]), J=50, prior_cells=400)
+    elif wl == "pne":
+        config.update(J=50, prior_cells=400, tracers=len(cfg["tracers"]["v"]))
     else:
         config.update(J=4946 if wl == "multipole" else 4896,
                       prior_cells=8192 if wl == "mlp" else 1024)

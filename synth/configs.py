@@ -210,6 +210,8 @@ EPS_CFG3 = 1.85e-6
 # The 64-model batch shares one rate: the maximum of |G(0)| over its models at
 # their full sizes (1.1e8, from the halo-heavy models' outer shells).
 EPS_CFG4 = 8.98e-8
+# The discrete-velocity workload (cfg_pne at 2^20 particles, 1000 tracers, FP32).
+EPS_PNE = 7.04e-05
 # The Fig. 1 runs (cfg_fig1_run), one rate per initial model.
 EPS_FIG1 = {"isotropic": 7.448e-06, "radial": 2.764e-05, "tangential": 6.088e-06}
 # Mass of the truncated (r <= 10) logarithmic-potential density: the self-consistent

@@ -5,8 +5,9 @@ eps * dt * max_i |G_i(0)| = 0.1, where G_i = dF/dw_i with the priors held fixed.
 G_i(0) is read off one oracle step with a negligible rate (w1 = w0 exp(e dt G)).
 The batched workload shares one rate over its 64 models: the maximum is taken over
 all of them at their full sizes.  Calls only the oracle and the input generators;
-prints the values recorded in synth/configs.py (EPS_CFG2, EPS_CFG3, EPS_CFG4, and
-EPS_FIG1 of the Fig. 1 experiment, whose runs take eps dt max|G(0)| = 3).
+prints the values recorded in synth/configs.py (EPS_CFG2, EPS_CFG3, EPS_CFG4,
+EPS_PNE of the discrete-velocity workload, and EPS_FIG1 of the Fig. 1 experiment,
+whose runs take eps dt max|G(0)| = 3).
 
     python tests/golden/derive_eps.py
 """
@@ -45,7 +46,7 @@ def max_abs_G_batched(cfg):
 
 
 if __name__ == "__main__":
-    which = sys.argv[1:] or ["EPS_CFG2", "EPS_CFG3", "EPS_CFG4", "EPS_FIG1"]
+    which = sys.argv[1:] or ["EPS_CFG2", "EPS_CFG3", "EPS_CFG4", "EPS_PNE", "EPS_FIG1"]
     if "EPS_FIG1" in which:
         which.remove("EPS_FIG1")
         # the Fig. 1 runs adapt 30 times faster: eps dt max|G(0)| = 3, per initial model
@@ -55,8 +56,10 @@ if __name__ == "__main__":
             print("EPS_FIG1[%r] = %.4e   # max|G(0)| = %.4e" % (ics, float("%.3e" % (3.0 / (c["dt"] * g))), g))
     cases = {"EPS_CFG2": lambda: max_abs_G(configs.cfg2(N=1 << 20)),
              "EPS_CFG3": lambda: max_abs_G(configs.cfg3(N=1 << 20)),
-             "EPS_CFG4": lambda: max_abs_G_batched(configs.cfg4())}
-    dts = {"EPS_CFG2": configs.cfg2(N=16)["dt"], "EPS_CFG3": configs.cfg3(N=16)["dt"], "EPS_CFG4": 0.01}
+             "EPS_CFG4": lambda: max_abs_G_batched(configs.cfg4()),
+             "EPS_PNE": lambda: max_abs_G(configs.cfg_pne(N=1 << 20, n_tracers=1000, precision="f32"))}
+    dts = {"EPS_CFG2": configs.cfg2(N=16)["dt"], "EPS_CFG3": configs.cfg3(N=16)["dt"], "EPS_CFG4": 0.01,
+           "EPS_PNE": configs.cfg_pne(N=16, n_tracers=16)["dt"]}
     for name in which:
         g = cases[name]()
         cfg = {"dt": dts[name]}
