@@ -169,7 +169,6 @@ hipError_t launch_shell_moments(const ShellArgs<T>& a, int blocks, double* out, 
 // each with its velocity V, inverse width is = 1/s and density factor
 // nf = 1/(sqrt(2 pi) s); per tracer the smoothed sum Ls and the update factor
 // cL = lambda / Ls, per bin the smoothed mass Ms and cM = -lambda n_b / Ms.
-constexpr int kTrcThreads = 256;
 constexpr int kTrcBlocks = 256;
 template <typename T>
 struct TracerArgs {

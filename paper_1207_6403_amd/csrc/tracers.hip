@@ -13,8 +13,9 @@
 //   tracer_sum        the rows' column sums in a fixed order (FP64)
 //   tracer_finalize   one block: smoothing, the log-likelihood and the update
 //                     factors
-//   tracer_grad       per particle: its term of G from the factors of its bin,
-//                     with the bin's tracers in LDS
+//   tracer_grad       per chunk of particles counting-sorted by bin in LDS:
+//                     each particle's term of G from the factors of its bin,
+//                     with the tracers in LDS
 // The bin of a particle is its stored tag, so the decisions are the step
 // kernel's (exact at edges).
 #include <hip/hip_runtime.h>
@@ -194,31 +195,71 @@ __global__ void __launch_bounds__(256) tracer_finalize_kernel(TracerArgs<T> a) {
     if (tid == 0) *a.loglike = red[0];
 }
 
+// Per chunk of particles, counting-sorted by bin in LDS as in tracer_observe, so
+// that the 64 lanes of a wave take consecutive particles of (mostly) one bin:
+// their loops over the bin's tracers then have one length and read the same
+// tracer at once.  Each particle's term goes back to its own place; particles in
+// no bin get 0.
 template <typename T>
-__global__ void __launch_bounds__(kTrcThreads) tracer_grad_kernel(TracerArgs<T> a) {
+__global__ void __launch_bounds__(kTrcObsThreads) tracer_grad_kernel(TracerArgs<T> a) {
     extern __shared__ __align__(16) unsigned char smem[];
-    const int ntr = a.ntr, tid = threadIdx.x, nt = blockDim.x;
-    T* tV = reinterpret_cast<T*>(smem);        // ntr
-    T* tis = tV + ntr;                          // ntr
-    T* tc = tis + ntr;                          // ntr: cL nf
+    const int ntr = a.ntr, nb = a.nb, tid = threadIdx.x, nt = blockDim.x;
+    T* tV = reinterpret_cast<T*>(smem);                          // ntr
+    T* tis = tV + ntr;                                            // ntr
+    T* tc = tis + ntr;                                            // ntr: cL nf
+    T* svl = tc + ntr;                                            // kTrcChunk, sorted by bin
+    uint16_t* sidx = reinterpret_cast<uint16_t*>(svl + kTrcChunk);   // kTrcChunk: index in the chunk
+    uint16_t* sbin = sidx + kTrcChunk;                            // kTrcChunk: bin
+    uint32_t* cnt = reinterpret_cast<uint32_t*>(sbin + kTrcChunk);   // nb + 1: counts, then starts
+    uint32_t* wsum = cnt + nb + 1;                                // 16
     if (*a.flag) return;
     for (int t = tid; t < ntr; t += nt) {
         tV[t] = a.V[t];
         tis[t] = a.is[t] * trc_q(T(0));
         tc[t] = a.cL[t] * a.nf[t];
     }
-    __syncthreads();
     const uint16_t* tag = reinterpret_cast<const uint16_t*>(a.state + 7 * a.stride) + (size_t)a.tagrow * a.stride;
     const T* S = a.state;
     const int64_t st = a.stride;
-    for (int64_t p = (int64_t)blockIdx.x * nt + tid; p < a.n; p += (int64_t)gridDim.x * nt) {
-        const int b = tag[p];
-        T x = T(0);
-        if (b != kNoBin) {
-            const T vl = line_of_sight(S[4 * st + p], S[5 * st + p], a.sini, a.cosi);
-            x = a.cM[b];
+    constexpr int kPer = kTrcChunk / kTrcObsThreads;
+    for (int64_t c0 = (int64_t)blockIdx.x * kTrcChunk; c0 < a.n; c0 += (int64_t)gridDim.x * kTrcChunk) {
+        for (int b = tid; b <= nb; b += nt) cnt[b] = 0u;
+        __syncthreads();
+        int bq[kPer];
+        uint32_t slot[kPer];
+        T vq[kPer];
+        #pragma unroll
+        for (int q = 0; q < kPer; ++q) {
+            const int64_t p = c0 + tid + q * kTrcObsThreads;
+            bq[q] = -1;
+            if (p < a.n) {
+                const int b = tag[p];
+                if (b != kNoBin) {
+                    bq[q] = b;
+                    vq[q] = line_of_sight(S[4 * st + p], S[5 * st + p], a.sini, a.cosi);
+                    slot[q] = atomicAdd(&cnt[b], 1u);
+                } else {
+                    a.extra[p] = T(0);
+                }
+            }
+        }
+        __syncthreads();
+        block_exclusive_scan(cnt, nb, wsum);
+        #pragma unroll
+        for (int q = 0; q < kPer; ++q)
+            if (bq[q] >= 0) {
+                const uint32_t pos = cnt[bq[q]] + slot[q];
+                svl[pos] = vq[q];
+                sidx[pos] = (uint16_t)(tid + q * kTrcObsThreads);
+                sbin[pos] = (uint16_t)bq[q];
+            }
+        __syncthreads();
+        const uint32_t total = cnt[nb];
+        for (uint32_t pos = tid; pos < total; pos += nt) {
+            const int b = sbin[pos];
+            const T vl = svl[pos];
+            T x = a.cM[b], x1 = T(0);
             // four tracers per round, their LDS reads issued together, into two sums
-            T x1 = T(0);
             int t = a.first[b];
             const int te = a.first[b + 1];
             for (; t + 4 <= te; t += 4) {
@@ -231,9 +272,9 @@ __global__ void __launch_bounds__(kTrcThreads) tracer_grad_kernel(TracerArgs<T> 
                 x1 += c[3] * trc_gauss((vl - V[3]) * q[3]);
             }
             for (; t < te; ++t) x += tc[t] * trc_gauss((vl - tV[t]) * tis[t]);
-            x += x1;
+            a.extra[c0 + sidx[pos]] = x + x1;
         }
-        a.extra[p] = x;
+        __syncthreads();   // (the next chunk reuses the LDS)
     }
 }
 
@@ -251,16 +292,19 @@ hipError_t launch_tracer_observe(const TracerArgs<T>& a, hipStream_t s) {
 }
 
 template <typename T>
+static size_t grad_lds(const TracerArgs<T>& a) {
+    return 3 * sizeof(T) * (size_t)a.ntr + (sizeof(T) + 4) * kTrcChunk + sizeof(uint32_t) * (a.nb + 1 + 16);
+}
+
+template <typename T>
 hipError_t launch_tracer_grad(const TracerArgs<T>& a, hipStream_t s) {
-    const int blocks = (int)std::min<int64_t>(kTrcBlocks * 4, (a.n + kTrcThreads - 1) / kTrcThreads);
-    hipLaunchKernelGGL(tracer_grad_kernel<T>, dim3(std::max(blocks, 1)), dim3(kTrcThreads),
-                       3 * sizeof(T) * (size_t)a.ntr, s, a);
+    hipLaunchKernelGGL(tracer_grad_kernel<T>, dim3(a.nblk), dim3(kTrcObsThreads), grad_lds(a), s, a);
     return hipGetLastError();
 }
 
 template <typename T>
 size_t tracer_lds(const TracerArgs<T>& a) {
-    return std::max(observe_lds(a), 3 * sizeof(T) * (size_t)a.ntr);
+    return std::max(observe_lds(a), grad_lds(a));
 }
 
 template <typename T>
