@@ -630,7 +630,6 @@ static TracerArgs<T> tracer_args(const m2m_ctx* c, int k, int first_obs) {
     a.cM = (const T*)c->trc_cM;
     a.extra = (T*)c->trc_extra;
     a.part = c->trc_part;
-    a.colsum = c->trc_colsum;
     a.nblk = c->trc_nblk;
     a.Ls = c->trc_Ls;
     a.Ms = c->trc_Ms;
@@ -1569,7 +1568,7 @@ static m2m_status set_tracers_T(m2m_ctx* c, const m2m_tracers* t) {
         (s = upload(c, (T**)&c->trc_V, V)) || (s = upload(c, (T**)&c->trc_is, is)) ||
         (s = upload(c, (T**)&c->trc_nf, nf)) || (s = dalloc(c, (T**)&c->trc_cL, (size_t)n)) ||
         (s = dalloc(c, (T**)&c->trc_cM, (size_t)nb)) || (s = dalloc(c, (T**)&c->trc_extra, (size_t)c->stride)) ||
-        (s = dalloc(c, &c->trc_part, (size_t)c->trc_nblk * (n + nb))) || (s = dalloc(c, &c->trc_colsum, (size_t)(n + nb))) ||
+        (s = dalloc(c, &c->trc_part, (size_t)c->trc_nblk * (n + nb))) ||
         (s = dalloc(c, &c->trc_Ls, (size_t)n)) ||
         (s = dalloc(c, &c->trc_Ms, (size_t)nb)) || (s = dalloc(c, &c->trc_ll, 1)))
         return s;
@@ -1615,6 +1614,11 @@ extern "C" m2m_status m2m_set_tracers(m2m_ctx* c, const m2m_tracers* t) {
 extern "C" m2m_status m2m_tracer_state(m2m_ctx* c, double* loglike, double* L, double* M) {
     if (!c) return fail(nullptr, M2M_ERR_INVALID, "ctx is NULL");
     if (!c->trc_n) return fail(c, M2M_ERR_INVALID, "the context has no tracers");
+    if (loglike) {
+        const hipError_t e = c->prec == M2M_F64 ? launch_tracer_loglike<double>(tracer_args<double>(c, 0, 0), c->stream)
+                                                : launch_tracer_loglike<float>(tracer_args<float>(c, 0, 0), c->stream);
+        HIPCHK(c, e);
+    }
     HIPCHK(c, hipStreamSynchronize(c->stream));
     if (loglike) HIPCHK(c, hipMemcpy(loglike, c->trc_ll, sizeof(double), hipMemcpyDeviceToHost));
     if (L) {

@@ -185,7 +185,6 @@ struct TracerArgs {
     const T* cM;             // nb
     T* extra;                // n: the likelihood's term of G (tracer_grad)
     double* part;            // blocks x (ntr + nb) partial sums (tracer_observe)
-    double* colsum;          // ntr + nb: their column sums
     int32_t nblk;            // blocks of tracer_observe
     double* Ls;              // ntr smoothed sums
     double* Ms;              // nb smoothed masses
@@ -198,10 +197,13 @@ struct TracerArgs {
     int32_t first_obs;       // 1: the smoothed sums start at this observation
     const int* flag;
 };
-// Sums L_t, M_b of the state (per-block partials), then their smoothing, the
-// log-likelihood and the update factors (one block).
+// Sums L_t, M_b of the state (per-block partials), then their smoothing and the
+// update factors.
 template <typename T>
 hipError_t launch_tracer_observe(const TracerArgs<T>& a, hipStream_t s);
+// The log-likelihood of the smoothed sums into *loglike.
+template <typename T>
+hipError_t launch_tracer_loglike(const TracerArgs<T>& a, hipStream_t s);
 // extra[p] of every particle of the state.
 template <typename T>
 hipError_t launch_tracer_grad(const TracerArgs<T>& a, hipStream_t s);

@@ -98,7 +98,7 @@ struct m2m_ctx {
     int32_t* trc_tbin = nullptr;
     void *trc_V = nullptr, *trc_is = nullptr, *trc_nf = nullptr, *trc_cL = nullptr, *trc_cM = nullptr;
     void* trc_extra = nullptr;
-    double *trc_part = nullptr, *trc_colsum = nullptr, *trc_Ls = nullptr, *trc_Ms = nullptr, *trc_ll = nullptr;
+    double *trc_part = nullptr, *trc_Ls = nullptr, *trc_Ms = nullptr, *trc_ll = nullptr;
     // device
     hipStream_t stream = nullptr;
     bool own_stream = false;

@@ -10,9 +10,9 @@
 //                     LDS; each thread owns some tracers and sums w phi over its
 //                     tracers' bins (no atomics on the sums), threads over bins
 //                     sum the masses; per-block partial rows
-//   tracer_sum        the rows' column sums in a fixed order (FP64)
-//   tracer_finalize   one block: smoothing, the log-likelihood and the update
-//                     factors
+//   tracer_sum        the rows' column sums in a fixed order (FP64), and per
+//                     column its smoothing and update factor
+//   tracer_loglike    one block, when the log-likelihood is read
 //   tracer_grad       per chunk of particles counting-sorted by bin in LDS:
 //                     each particle's term of G from the factors of its bin,
 //                     with the tracers in LDS
@@ -27,7 +27,7 @@
 
 namespace m2m {
 
-constexpr int kTrcChunk = 2048;   // particles per chunk of tracer_observe
+constexpr int kTrcChunk = 4096;   // particles per chunk of tracer_observe and tracer_grad
 constexpr int kTrcObsThreads = 1024;   // threads of tracer_observe (one block per CU)
 
 // exp(-d^2 / 2) of a tracer's Gaussian at d = (v - V) / s, from d' = (v - V) q / s:
@@ -162,30 +162,31 @@ __global__ void __launch_bounds__(256) tracer_sum_kernel(TracerArgs<T> a) {
     }
     sh[wv][lane] = s;
     __syncthreads();
-    if (wv == 0 && col < W) a.colsum[col] = ((sh[0][lane] + sh[1][lane]) + sh[2][lane]) + sh[3][lane];
+    if (wv == 0 && col < W) {
+        // the column's smoothing and update factor (each column is one tracer's
+        // sum or one bin's mass: no other column is needed)
+        const double v = ((sh[0][lane] + sh[1][lane]) + sh[2][lane]) + sh[3][lane];
+        if (col < a.ntr) {
+            const double ls = a.first_obs ? v : a.Ls[col] + a.g * (v - a.Ls[col]);
+            a.Ls[col] = ls;
+            a.cL_out[col] = T(a.lambda / ls);
+        } else {
+            const int b = col - a.ntr, nbt = a.first[b + 1] - a.first[b];
+            const double ms = a.first_obs ? v : a.Ms[b] + a.g * (v - a.Ms[b]);
+            a.Ms[b] = ms;
+            a.cM_out[b] = nbt ? T(-a.lambda * nbt / ms) : T(0);
+        }
+    }
 }
 
+// The log-likelihood sum_t ln(Ls_t / Ms_(b_t)) of the smoothed sums as they
+// stand (one block; launched when it is read).
 template <typename T>
-__global__ void __launch_bounds__(256) tracer_finalize_kernel(TracerArgs<T> a) {
+__global__ void __launch_bounds__(256) tracer_loglike_kernel(TracerArgs<T> a) {
     __shared__ double red[256];
-    if (*a.flag) return;
-    const int ntr = a.ntr, nb = a.nb, W = ntr + nb, tid = threadIdx.x;
-    for (int k = tid; k < W; k += 256) {
-        const double v = a.colsum[k];
-        double* sm = k < ntr ? a.Ls + k : a.Ms + (k - ntr);
-        *sm = a.first_obs ? v : *sm + a.g * (v - *sm);
-    }
-    __syncthreads();
+    const int tid = threadIdx.x;
     double ll = 0.0;
-    for (int t = tid; t < ntr; t += 256) {
-        const double Ls = a.Ls[t], Ms = a.Ms[a.tbin[t]];
-        ll += log(Ls / Ms);
-        a.cL_out[t] = T(a.lambda / Ls);
-    }
-    for (int b = tid; b < nb; b += 256) {
-        const int nbt = a.first[b + 1] - a.first[b];
-        a.cM_out[b] = nbt ? T(-a.lambda * nbt / a.Ms[b]) : T(0);
-    }
+    for (int t = tid; t < a.ntr; t += 256) ll += log(a.Ls[t] / a.Ms[a.tbin[t]]);
     red[tid] = ll;
     __syncthreads();
     for (int o = 128; o > 0; o >>= 1) {
@@ -287,7 +288,12 @@ template <typename T>
 hipError_t launch_tracer_observe(const TracerArgs<T>& a, hipStream_t s) {
     hipLaunchKernelGGL(tracer_observe_kernel<T>, dim3(a.nblk), dim3(kTrcObsThreads), observe_lds(a), s, a);
     hipLaunchKernelGGL(tracer_sum_kernel<T>, dim3((a.ntr + a.nb + 63) / 64), dim3(256), 0, s, a);
-    hipLaunchKernelGGL(tracer_finalize_kernel<T>, dim3(1), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_tracer_loglike(const TracerArgs<T>& a, hipStream_t s) {
+    hipLaunchKernelGGL(tracer_loglike_kernel<T>, dim3(1), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
@@ -318,6 +324,8 @@ hipError_t set_tracer_lds_limit(size_t lds) {
 
 template hipError_t launch_tracer_observe<float>(const TracerArgs<float>&, hipStream_t);
 template hipError_t launch_tracer_observe<double>(const TracerArgs<double>&, hipStream_t);
+template hipError_t launch_tracer_loglike<float>(const TracerArgs<float>&, hipStream_t);
+template hipError_t launch_tracer_loglike<double>(const TracerArgs<double>&, hipStream_t);
 template hipError_t launch_tracer_grad<float>(const TracerArgs<float>&, hipStream_t);
 template hipError_t launch_tracer_grad<double>(const TracerArgs<double>&, hipStream_t);
 template size_t tracer_lds<float>(const TracerArgs<float>&);
