@@ -121,21 +121,21 @@ __global__ void __launch_bounds__(kTrcObsThreads) tracer_observe_kernel(TracerAr
         for (int t = tid; t < ntr; t += nt) {
             const int b = a.tbin[t];
             const T V = a.V[t], isq = a.is[t] * trc_q(T(0));
-            // four particles per round, their LDS reads issued together, into two sums
-            double s0 = 0.0, s1 = 0.0;
+            // four particles per round, their LDS reads issued together and their
+            // terms added in pairs before the FP64 sum
+            double s0 = 0.0;
             uint32_t i = cnt[b];
             const uint32_t e = cnt[b + 1];
             for (; i + 4 <= e; i += 4) {
                 T v[4], w[4];
                 #pragma unroll
                 for (int u = 0; u < 4; ++u) { v[u] = svl[i + u]; w[u] = sw[i + u]; }
-                s0 += double(w[0] * trc_gauss((v[0] - V) * isq));
-                s1 += double(w[1] * trc_gauss((v[1] - V) * isq));
-                s0 += double(w[2] * trc_gauss((v[2] - V) * isq));
-                s1 += double(w[3] * trc_gauss((v[3] - V) * isq));
+                const T g0 = w[0] * trc_gauss((v[0] - V) * isq), g1 = w[1] * trc_gauss((v[1] - V) * isq);
+                const T g2 = w[2] * trc_gauss((v[2] - V) * isq), g3 = w[3] * trc_gauss((v[3] - V) * isq);
+                s0 += double((g0 + g1) + (g2 + g3));
             }
             for (; i < e; ++i) s0 += double(sw[i] * trc_gauss((svl[i] - V) * isq));
-            acc[t] += double(a.nf[t]) * (s0 + s1);   // (the tracer's normalisation, once per chunk)
+            acc[t] += double(a.nf[t]) * s0;   // (the tracer's normalisation, once per chunk)
         }
         __syncthreads();
     }
