@@ -89,19 +89,20 @@ __global__ void __launch_bounds__(kTrcObsThreads) tracer_observe_kernel(TracerAr
         int bq[kPer];
         uint32_t slot[kPer];
         T vq[kPer], wq[kPer];
+        // (the velocities and weight are loaded with the tag, not after it: a
+        // particle in no bin leaves them unused)
         #pragma unroll
         for (int q = 0; q < kPer; ++q) {
-            const int64_t p = c0 + tid + q * kTrcObsThreads;
-            bq[q] = -1;
-            if (p < a.n) {
-                const int b = tag[p];
-                if (b != kNoBin) {
-                    bq[q] = b;
-                    vq[q] = line_of_sight(S[4 * st + p], S[5 * st + p], a.sini, a.cosi);
-                    wq[q] = S[6 * st + p];
-                    slot[q] = atomicAdd(&cnt[b], 1u);
-                }
-            }
+            const int64_t p = min(c0 + tid + q * kTrcObsThreads, a.n - 1);
+            bq[q] = tag[p];
+            vq[q] = line_of_sight(S[4 * st + p], S[5 * st + p], a.sini, a.cosi);
+            wq[q] = S[6 * st + p];
+        }
+        #pragma unroll
+        for (int q = 0; q < kPer; ++q) {
+            const bool in = c0 + tid + q * kTrcObsThreads < a.n && bq[q] != kNoBin;
+            if (in) slot[q] = atomicAdd(&cnt[bq[q]], 1u);
+            else bq[q] = -1;
         }
         __syncthreads();
         block_exclusive_scan(cnt, nb, wsum);
@@ -229,19 +230,21 @@ __global__ void __launch_bounds__(kTrcObsThreads) tracer_grad_kernel(TracerArgs<
         int bq[kPer];
         uint32_t slot[kPer];
         T vq[kPer];
+        // (the velocities are loaded with the tag, not after it)
+        #pragma unroll
+        for (int q = 0; q < kPer; ++q) {
+            const int64_t p = min(c0 + tid + q * kTrcObsThreads, a.n - 1);
+            bq[q] = tag[p];
+            vq[q] = line_of_sight(S[4 * st + p], S[5 * st + p], a.sini, a.cosi);
+        }
         #pragma unroll
         for (int q = 0; q < kPer; ++q) {
             const int64_t p = c0 + tid + q * kTrcObsThreads;
-            bq[q] = -1;
-            if (p < a.n) {
-                const int b = tag[p];
-                if (b != kNoBin) {
-                    bq[q] = b;
-                    vq[q] = line_of_sight(S[4 * st + p], S[5 * st + p], a.sini, a.cosi);
-                    slot[q] = atomicAdd(&cnt[b], 1u);
-                } else {
-                    a.extra[p] = T(0);
-                }
+            if (p < a.n && bq[q] != kNoBin) {
+                slot[q] = atomicAdd(&cnt[bq[q]], 1u);
+            } else {
+                if (p < a.n) a.extra[p] = T(0);
+                bq[q] = -1;
             }
         }
         __syncthreads();
