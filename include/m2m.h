@@ -155,9 +155,11 @@ typedef struct {
     int32_t mlp_subset, mlp_batch;
     double lr, beta1, beta2, adam_eps, fallback;
     uint32_t seed;
-    int32_t mlp_mfma;        /* MLP: 1 = the hidden layer of the inference over all
-                                particles on the matrix cores (BF16 operands, FP32
-                                accumulation); 0 = FP32 throughout (the tight mode) */
+    int32_t mlp_mfma;        /* MLP: 1 = the hidden-layer contractions of the training
+                                and of the inference over all particles on the matrix
+                                cores (BF16 operands, FP32 accumulation; the inference
+                                takes its features from FP32 integrals); 0 = FP32
+                                throughout with FP64 features (the tight mode) */
     const float *mlp_init;   /* host, M2M_MLP_NPARAM initial parameters (MLP only) */
 } m2m_prior;
 
