@@ -189,12 +189,14 @@ __device__ __noinline__ void fix_one(cExact* ex, int m, unsigned open, int64_t p
 
 // MODE: the step flags at run time (0), or compiled in: a stepping kernel of a
 // histogram prior refreshed every step with the exponential law (1), an
-// observe-only pass that takes the prior cells (2), or a stepping kernel with
+// observe-only pass that takes the prior cells (2), a stepping kernel with
 // stored per-particle priors and no cells (3: the learned prior between
-// refreshes, a periodic prior's steps that take no cells).
+// refreshes, a periodic prior's steps that take no cells), or mode 1 with the
+// discrete tracers' term of G (4).
 constexpr uint32_t kHotFlags = kExpLaw | (1u << kWhatShift) | kAccum;
 constexpr uint32_t kObsCells = kObserve | kAccum;
 constexpr uint32_t kHotStored = kExpLaw | (3u << kWhatShift);
+constexpr uint32_t kHotTracers = kHotFlags | kTracers;
 
 template <typename T, typename PT, int POT, int NB, uint64_t SIG, int CAX, int MODE, int ILP>
 __global__ void __launch_bounds__(sizeof(T) == 8 ? 256 : 1024) step_kernel(StepArgs<T, PT> a) {
@@ -230,7 +232,11 @@ __global__ void __launch_bounds__(sizeof(T) == 8 ? 256 : 1024) step_kernel(StepA
     for (int i = tid; i < a.nedge; i += nt) { ed[i] = a.edges[i]; ed64[i] = a.edges64[i]; }
     for (int i = tid; i < 2 * a.lay.ngh; i += nt) ghl[i] = a.ghtab[i];
 
-    const uint32_t fl = MODE == 1 ? kHotFlags : (MODE == 2 ? kObsCells : (MODE == 3 ? kHotStored : a.flags));
+    const uint32_t fl = MODE == 1   ? kHotFlags
+                        : MODE == 2 ? kObsCells
+                        : MODE == 3 ? kHotStored
+                        : MODE == 4 ? kHotTracers
+                                    : a.flags;
     const uint32_t wm = (fl >> kWhatShift) & 3u;
     const bool want_cm = wm == 1 || wm == 2;
     const bool accum = fl & kAccum;
@@ -498,6 +504,7 @@ static hipError_t launch_cax(const StepArgs<T, PT>& a, int ilp, int blocks, int 
     if (a.flags == kHotStored) return launch_k<T, PT, POT, NB, SIG, kCaxRuntime, 3>(a, ilp, blocks, threads, lds, s);
     if (a.cells.ncell > 0 && cax_of(a.cells) == CAX1) {
         if (a.flags == kHotFlags) return launch_k<T, PT, POT, NB, SIG, CAX1, 1>(a, ilp, blocks, threads, lds, s);
+        if (a.flags == kHotTracers) return launch_k<T, PT, POT, NB, SIG, CAX1, 4>(a, ilp, blocks, threads, lds, s);
         if ((a.flags & ~(3u << kWhatShift)) == kObsCells)
             return launch_k<T, PT, POT, NB, SIG, CAX1, 2>(a, ilp, blocks, threads, lds, s);
     }
@@ -548,6 +555,7 @@ static hipError_t set_lds_sig(size_t lds) {
     if (e == hipSuccess) e = set_lds_k<T, PT, POT, NB, SIG, CAX1, 1>(lds);
     if (e == hipSuccess) e = set_lds_k<T, PT, POT, NB, SIG, CAX1, 2>(lds);
     if (e == hipSuccess) e = set_lds_k<T, PT, POT, NB, SIG, kCaxRuntime, 3>(lds);
+    if (e == hipSuccess) e = set_lds_k<T, PT, POT, NB, SIG, CAX1, 4>(lds);
     return e;
 }
 
