@@ -17,8 +17,9 @@ One step = weight update + push + observe + smoothing, deviations, chi^2 and
 prior, all on the GPU.
 
 Prints one JSON line.  The timed region starts with the particles resident in
-HBM; the dominant kernel is bracketed by HIP events on the context's stream in a
-second timed region, which gives the roofline figure.
+HBM; in a second timed region HIP events attached to the dominant kernel's
+launches (on the context's stream) take its own start and end times, which give
+the roofline figure.
 
     python bench.py [--workload W] [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
     python bench.py --copy-calibration MIB   # plain device copy, for HBM counter scaling
@@ -308,8 +309,8 @@ def main():
     wall = time.perf_counter() - t0
     value = cfg["N"] * args.steps / wall
 
-    # timed region 2 (the roofline): the same K steps launched one by one, the
-    # dominant kernel bracketed by HIP events on the context's stream
+    # timed region 2 (the roofline): the same K steps launched one by one, HIP
+    # events attached to the dominant kernel's launches on the context's stream
     m2m.m2m_set_launch(ctx, timing=1, graph_steps=0)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
@@ -333,7 +334,8 @@ def main():
                 "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(cfg["N"]) if wl == "logpot" else None,
                 "kernel": "step_kernel (fused update + push + observe + prior cells)",
                 "kernel_us": k_ms * 1e3, "bytes_per_launch": bpp * cfg["N"]}
-    roof["timing"] = "HIP events around each of %d one-by-one launches" % k_n
+    roof["timing"] = ("HIP events attached to each of %d one-by-one launches (the kernel's own start and end)"
+                      % k_n)
     log("throughput: %.2f us/step (%.3g particle-steps/s); one by one: %.2f us/step, dominant kernel %.2f us (%d launches)"
         % (wall / args.steps * 1e6, value, wall_ev / args.steps * 1e6, k_ms * 1e3, k_n))
 

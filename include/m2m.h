@@ -202,9 +202,10 @@ typedef struct {
 } m2m_step_stats;
 
 /* Launch shape of the fused step kernel (see m2m_autotune).  timing = 1 makes
- * m2m_step launch without graphs and bracket every fused step kernel (MULTIPOLE
- * models: the second-kick kernel, which evaluates the field) with HIP events on the context's
- * stream (read with m2m_kernel_time). */
+ * m2m_step launch without graphs and time every fused step kernel (MULTIPOLE
+ * models: the second-kick kernel, which evaluates the field) with HIP events
+ * attached to its launch, which take the kernel's own start and end times
+ * (read with m2m_kernel_time). */
 typedef struct {
     int32_t threads;        /* 64..1024, multiple of 64 (FP64: at most 256) */
     int32_t ilp;            /* particles per thread per tile: 1 or 2        */
@@ -413,9 +414,9 @@ m2m_status m2m_get_launch(const m2m_ctx *ctx, m2m_launch *out);
 m2m_status m2m_set_launch(m2m_ctx *ctx, const m2m_launch *in);
 
 /* Average duration in milliseconds of the fused step kernel (MULTIPOLE
- * models: of the update/first-kick/drift kernel) over the last m2m_step call,
- * measured with HIP events on the context's stream (0 if the call used graphs
- * or took no steps); *launches gets the launch count. */
+ * models: of the second-kick kernel) over the last m2m_step call, from the HIP
+ * events attached to its launches (0 if the call used graphs or took no steps);
+ * *launches gets the launch count. */
 m2m_status m2m_kernel_time(const m2m_ctx *ctx, double *ms_per_launch, int64_t *launches);
 
 /* End of the run of section 2: free every device buffer of the context (NULL is

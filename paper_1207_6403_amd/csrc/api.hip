@@ -692,10 +692,10 @@ static hipError_t launch_one_T(m2m_ctx* c, int64_t n, hipEvent_t e0, hipEvent_t 
             a.flags |= kTracers;
             a.extra = (const T*)c->trc_extra;
         }
-        if (e0) (void)hipEventRecord(e0, c->stream);
-        e = launch_step<T, T>(a, c->pot_kind, c->sig, c->lay.nbin, p.ilp, p.nblock, p.threads, p.lds, c->stream);
+        // (timing: the events take the step kernel's own start and end times)
+        e = launch_step<T, T>(a, c->pot_kind, c->sig, c->lay.nbin, p.ilp, p.nblock, p.threads, p.lds, c->stream, e0,
+                              e1);
     }
-    if (e1) (void)hipEventRecord(e1, c->stream);
     if (e != hipSuccess) return e;
     if (c->cells_apart && acc && (e = launch_cells_after<T>(c, (int)((n + 1) & 1))) != hipSuccess) return e;
     if (c->trc_n && (e = launch_tracer_observe<T>(tracer_args<T>(c, (int)((n + 1) & 1), 0), c->stream)) != hipSuccess)

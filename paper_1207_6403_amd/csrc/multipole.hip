@@ -18,6 +18,8 @@
 //   mp_scan         node coefficients of step n+1
 //   mp_kick         second half kick; stores the field at x_n+1 for the next step
 // then the fused step kernel observing the new state, and the finalise kernel.
+#include <hip/hip_ext.h>
+
 #include "particle.h"
 #include "forms.h"
 
@@ -813,9 +815,11 @@ hipError_t launch_mp_build(const MpArgs<T>& mp, int blocks, const MpLds& lds, hi
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL((mp_scan_kernel<T>), dim3(kMpNlm), dim3(128), 0, s, mp);
     if ((e = hipGetLastError()) != hipSuccess || !mp.kick) return e;
-    if (ek0) (void)hipEventRecord(ek0, s);
-    hipLaunchKernelGGL((mp_kick_kernel<T>), dim3(blocks), dim3(sizeof(T) == 8 ? 256 : 1024), lds.kick, s, mp);
-    if (ek1) (void)hipEventRecord(ek1, s);
+    if (ek0 || ek1)   // (timing: the events take the kick's own start and end times)
+        hipExtLaunchKernelGGL((mp_kick_kernel<T>), dim3(blocks), dim3(sizeof(T) == 8 ? 256 : 1024),
+                              (uint32_t)lds.kick, s, ek0, ek1, 0u, mp);
+    else
+        hipLaunchKernelGGL((mp_kick_kernel<T>), dim3(blocks), dim3(sizeof(T) == 8 ? 256 : 1024), lds.kick, s, mp);
     return hipGetLastError();
 }
 

@@ -156,9 +156,10 @@ struct GatherArgs {
     int32_t cellrow;
 };
 
+// e0, e1 (timing): events that take the step kernel's own start and end times.
 template <typename T, typename PT>
 hipError_t launch_step(const StepArgs<T, PT>& a, int pot_kind, uint64_t sig, int nbin, int ilp, int blocks,
-                       int threads, size_t lds, hipStream_t s);
+                       int threads, size_t lds, hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 template <typename T, typename PT>
 hipError_t set_step_lds_limit(int pot_kind, size_t lds);
 template <typename T, typename PT>

@@ -14,6 +14,8 @@
 // When a block moves to another model (batched form) or finishes, it writes
 // its LDS histograms to its own partial slot (no atomics, deterministic
 // placement); finalize.hip sums the slots.
+#include <hip/hip_ext.h>
+
 #include "particle.h"
 
 namespace m2m {
@@ -488,11 +490,21 @@ template hipError_t launch_gather<float>(const GatherArgs<float>&, int, int, hip
 template hipError_t launch_gather<double>(const GatherArgs<double>&, int, int, hipStream_t);
 
 template <typename T, typename PT, int POT, int NB, uint64_t SIG, int CAX, int MODE>
-static hipError_t launch_k(const StepArgs<T, PT>& a, int ilp, int blocks, int threads, size_t lds, hipStream_t s) {
-    if (ilp == 1)
+static hipError_t launch_k(const StepArgs<T, PT>& a, int ilp, int blocks, int threads, size_t lds, hipStream_t s,
+                           hipEvent_t e0, hipEvent_t e1) {
+    if (e0 || e1) {
+        // (timing: the events take the kernel's own start and end times)
+        if (ilp == 1)
+            hipExtLaunchKernelGGL((step_kernel<T, PT, POT, NB, SIG, CAX, MODE, 1>), dim3(blocks), dim3(threads),
+                                  (uint32_t)lds, s, e0, e1, 0u, a);
+        else
+            hipExtLaunchKernelGGL((step_kernel<T, PT, POT, NB, SIG, CAX, MODE, 2>), dim3(blocks), dim3(threads),
+                                  (uint32_t)lds, s, e0, e1, 0u, a);
+    } else if (ilp == 1) {
         hipLaunchKernelGGL((step_kernel<T, PT, POT, NB, SIG, CAX, MODE, 1>), dim3(blocks), dim3(threads), lds, s, a);
-    else
+    } else {
         hipLaunchKernelGGL((step_kernel<T, PT, POT, NB, SIG, CAX, MODE, 2>), dim3(blocks), dim3(threads), lds, s, a);
+    }
     return hipGetLastError();
 }
 
@@ -500,15 +512,16 @@ static hipError_t launch_k(const StepArgs<T, PT>& a, int ilp, int blocks, int th
 // when they are the common ones (CAX1; the stepping or observing flags of a
 // histogram prior refreshed every step), else with both at run time.
 template <typename T, typename PT, int POT, int NB, uint64_t SIG, int CAX1>
-static hipError_t launch_cax(const StepArgs<T, PT>& a, int ilp, int blocks, int threads, size_t lds, hipStream_t s) {
-    if (a.flags == kHotStored) return launch_k<T, PT, POT, NB, SIG, kCaxRuntime, 3>(a, ilp, blocks, threads, lds, s);
+static hipError_t launch_cax(const StepArgs<T, PT>& a, int ilp, int blocks, int threads, size_t lds, hipStream_t s,
+                             hipEvent_t e0, hipEvent_t e1) {
+    if (a.flags == kHotStored) return launch_k<T, PT, POT, NB, SIG, kCaxRuntime, 3>(a, ilp, blocks, threads, lds, s, e0, e1);
     if (a.cells.ncell > 0 && cax_of(a.cells) == CAX1) {
-        if (a.flags == kHotFlags) return launch_k<T, PT, POT, NB, SIG, CAX1, 1>(a, ilp, blocks, threads, lds, s);
-        if (a.flags == kHotTracers) return launch_k<T, PT, POT, NB, SIG, CAX1, 4>(a, ilp, blocks, threads, lds, s);
+        if (a.flags == kHotFlags) return launch_k<T, PT, POT, NB, SIG, CAX1, 1>(a, ilp, blocks, threads, lds, s, e0, e1);
+        if (a.flags == kHotTracers) return launch_k<T, PT, POT, NB, SIG, CAX1, 4>(a, ilp, blocks, threads, lds, s, e0, e1);
         if ((a.flags & ~(3u << kWhatShift)) == kObsCells)
-            return launch_k<T, PT, POT, NB, SIG, CAX1, 2>(a, ilp, blocks, threads, lds, s);
+            return launch_k<T, PT, POT, NB, SIG, CAX1, 2>(a, ilp, blocks, threads, lds, s, e0, e1);
     }
-    return launch_k<T, PT, POT, NB, SIG, kCaxRuntime, 0>(a, ilp, blocks, threads, lds, s);
+    return launch_k<T, PT, POT, NB, SIG, kCaxRuntime, 0>(a, ilp, blocks, threads, lds, s, e0, e1);
 }
 
 // FP32 layouts with a compiled signature get their own kernels (for the log
@@ -517,25 +530,25 @@ static hipError_t launch_cax(const StepArgs<T, PT>& a, int ilp, int blocks, int 
 // compiled for at most NB = 2 or 4 binnings.
 template <typename T, typename PT, int POT>
 static hipError_t launch_step_pot(const StepArgs<T, PT>& a, uint64_t sig, int nbin, int ilp, int blocks, int threads,
-                                  size_t lds, hipStream_t s) {
+                                  size_t lds, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
     if constexpr (sizeof(T) == 4 && POT == 1) {
-        if (sig == kSigPixKin) return launch_cax<T, PT, POT, 2, kSigPixKin, kCaxLzNo3>(a, ilp, blocks, threads, lds, s);
+        if (sig == kSigPixKin) return launch_cax<T, PT, POT, 2, kSigPixKin, kCaxLzNo3>(a, ilp, blocks, threads, lds, s, e0, e1);
         if (sig == kSigPixKinShell)
-            return launch_cax<T, PT, POT, 4, kSigPixKinShell, kCaxLzNo3>(a, ilp, blocks, threads, lds, s);
+            return launch_cax<T, PT, POT, 4, kSigPixKinShell, kCaxLzNo3>(a, ilp, blocks, threads, lds, s, e0, e1);
     }
     if constexpr (sizeof(T) == 4 && POT != 1)
-        if (sig == kSigShellAnn) return launch_cax<T, PT, POT, 2, kSigShellAnn, kCaxLNo3>(a, ilp, blocks, threads, lds, s);
-    if (nbin <= 2) return launch_k<T, PT, POT, 2, 0, kCaxRuntime, 0>(a, ilp, blocks, threads, lds, s);
-    return launch_k<T, PT, POT, 4, 0, kCaxRuntime, 0>(a, ilp, blocks, threads, lds, s);
+        if (sig == kSigShellAnn) return launch_cax<T, PT, POT, 2, kSigShellAnn, kCaxLNo3>(a, ilp, blocks, threads, lds, s, e0, e1);
+    if (nbin <= 2) return launch_k<T, PT, POT, 2, 0, kCaxRuntime, 0>(a, ilp, blocks, threads, lds, s, e0, e1);
+    return launch_k<T, PT, POT, 4, 0, kCaxRuntime, 0>(a, ilp, blocks, threads, lds, s, e0, e1);
 }
 
 template <typename T, typename PT>
 hipError_t launch_step(const StepArgs<T, PT>& a, int pot_kind, uint64_t sig, int nbin, int ilp, int blocks,
-                       int threads, size_t lds, hipStream_t s) {
+                       int threads, size_t lds, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
     switch (pot_kind) {
-        case 0: return launch_step_pot<T, PT, 0>(a, sig, nbin, ilp, blocks, threads, lds, s);
-        case 1: return launch_step_pot<T, PT, 1>(a, sig, nbin, ilp, blocks, threads, lds, s);
-        default: return launch_step_pot<T, PT, 2>(a, sig, nbin, ilp, blocks, threads, lds, s);
+        case 0: return launch_step_pot<T, PT, 0>(a, sig, nbin, ilp, blocks, threads, lds, s, e0, e1);
+        case 1: return launch_step_pot<T, PT, 1>(a, sig, nbin, ilp, blocks, threads, lds, s, e0, e1);
+        default: return launch_step_pot<T, PT, 2>(a, sig, nbin, ilp, blocks, threads, lds, s, e0, e1);
     }
 }
 
@@ -592,9 +605,9 @@ hipError_t launch_erange(const ErangeArgs<T>& a, int pot_kind, int blocks, hipSt
 }
 
 template hipError_t launch_step<float, float>(const StepArgs<float, float>&, int, uint64_t, int, int, int, int, size_t,
-                                             hipStream_t);
+                                             hipStream_t, hipEvent_t, hipEvent_t);
 template hipError_t launch_step<double, double>(const StepArgs<double, double>&, int, uint64_t, int, int, int, int,
-                                               size_t, hipStream_t);
+                                               size_t, hipStream_t, hipEvent_t, hipEvent_t);
 template hipError_t set_step_lds_limit<float, float>(int, size_t);
 template hipError_t set_step_lds_limit<double, double>(int, size_t);
 template hipError_t launch_erange<float>(const ErangeArgs<float>&, int, int, hipStream_t);
