@@ -28,7 +28,7 @@
 namespace m2m {
 
 constexpr int kTrcChunk = 4096;   // particles per chunk of tracer_observe and tracer_grad
-constexpr int kTrcObsThreads = 1024;   // threads of tracer_observe (one block per CU)
+constexpr int kTrcObsThreads = 1024;   // threads of tracer_observe and tracer_grad (one block per CU)
 
 // exp(-d^2 / 2) of a tracer's Gaussian at d = (v - V) / s, from d' = (v - V) q / s:
 // FP32 with q = sqrt(log2(e) / 2), so that it is one hardware base-2
